@@ -1,0 +1,218 @@
+/*
+ * pat.h -- C ABI of the MI355X (gfx950) library for variational photoacoustic
+ * tomography (PAT) reconstruction with preconditioned PDHGM.
+ *
+ * Method: Boink et al., "A Framework for Directional and Higher-Order
+ * Reconstruction in Photoacoustic Tomography" (arXiv:1707.02245).
+ *
+ *   min_u 1/2 ||A u - f||^2 + R(u)                      (Sec. 2, eq. min_prob)
+ *
+ * with R = TV (eq. min_TV), TGV2 (eq. min_TGV), directional TV, or Tikhonov
+ * (LS-T, Sec. 2), solved in saddle-point form (Sec. 3.1) by the first-order
+ * primal-dual algorithm PDHGM (Algorithms 1 and 2) with diagonal or two-block
+ * step sizes (Sec. 3.3.2) and the primal-dual gap as stopping rule (Sec. 3.3.3).
+ *
+ * Conventions shared by every entry point:
+ *  - Data buffers are owned by the caller. Pointers named d_* are device
+ *    pointers (HIP global memory on the current device), borrowed for the
+ *    duration of the stream-ordered call; the library never frees them.
+ *  - Handles (pat_geometry, pat_precond_h, pat_unet) are owned by the
+ *    library and released only by their *_destroy function.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *    Calls are asynchronous with respect to the host unless documented.
+ *  - Images are row-major [ny][nx] with y increasing with the row index and
+ *    pixel (ix, iy) centred at (x_min + (ix+1/2) h, y_min + (iy+1/2) h).
+ *    Data are row-major [n_det][n_t] (bin b = d * n_t + k).
+ *  - Element type is fixed per geometry: float (PAT_F32) or double (PAT_F64).
+ *  - Return value < 0: error, outputs untouched, pat_last_error() explains.
+ *    Return value > 0: warning, outputs valid. Handles may be used by one
+ *    host thread at a time. No C++ exception crosses this boundary.
+ */
+#ifndef PAT_H
+#define PAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PAT_OK = 0,
+  PAT_NOT_CONVERGED = 1,      /* iteration cap reached before the gap target */
+  PAT_ERR_INVALID_ARG = -1,   /* rejected before any device work */
+  PAT_ERR_OOM = -2,           /* device allocation failed */
+  PAT_ERR_DEVICE = -3,        /* HIP runtime error (message in pat_last_error) */
+  PAT_ERR_NUMERIC = -4,       /* non-finite gap during iteration */
+  PAT_ERR_UNSUPPORTED = -5    /* valid request this build does not implement */
+} pat_status;
+
+typedef enum { PAT_F32 = 0, PAT_F64 = 1 } pat_dtype;
+
+typedef struct pat_geometry_s* pat_geometry;
+typedef struct pat_precond_s* pat_precond_h;
+
+/*
+ * Acquisition geometry (Sec. 3.3.1 discretisation; Sec. 4.1 eq. K_def).
+ *
+ * Point detectors sit on a circle arc of radius det_radius about
+ * (det_cx, det_cy): a closed circle (arc_span = 2 pi) places detector d at
+ * angle arc_center + 2 pi d / n_det; a shorter arc spaces them evenly from
+ * arc_center - arc_span/2 to arc_center + arc_span/2, both ends included.
+ * If det_xy is non-NULL it gives explicit host positions [n_det][2] instead.
+ *
+ * Time sample k measures the mean of the image over the circle of radius
+ * r_k = c (t0 + k dt) about the detector, sampled at M_k = max(1,
+ * ceil(2 pi r_k samples_per_pixel / h)) points at angles 2 pi (m + 1/2) / M_k,
+ * each read by bilinear interpolation with zero outside the grid:
+ *
+ *   A[(d,k), j] = (1/M_k) sum_m hat((X_dkm - x_j)/h) hat((Y_dkm - y_j)/h),
+ *   hat(t) = max(0, 1 - |t|).
+ *
+ * Validation (PAT_ERR_INVALID_ARG): nx, ny >= 2; non-square pixels; n_det < 1;
+ * n_t < 2; dt, c or samples_per_pixel <= 0; t0 < 0; any non-finite scalar;
+ * nx, ny > 16384 or n_det * n_t > 2^28.
+ */
+typedef struct {
+  int32_t nx, ny;
+  double x_min, x_max, y_min, y_max;
+  int32_t n_det;
+  double det_cx, det_cy, det_radius, arc_center, arc_span;
+  const double* det_xy;  /* optional host array [n_det][2]; NULL: use the arc */
+  int32_t n_t;
+  double t0, dt, c;
+  double samples_per_pixel;
+} pat_geometry_desc;
+
+typedef struct {
+  int32_t nx, ny, n_det, n_t;
+  int64_t n_pix, n_bins;
+  int64_t n_samples;      /* sum over bins of M_k (all arc samples) */
+  int64_t n_window;       /* arc samples inside the clip windows (work per apply) */
+  int32_t dtype;          /* pat_dtype */
+  int32_t fwd_lanes_log2, adj_tile, adj_det_group; /* launch parameters */
+} pat_geometry_info;
+
+/* Build the geometry tables on the device (FP64 host computation, rounded to
+ * the element type). Synchronous with respect to `stream` on return. */
+pat_status pat_geometry_create(const pat_geometry_desc* desc, pat_dtype dtype,
+                               void* stream, pat_geometry* out);
+pat_status pat_geometry_destroy(pat_geometry g);
+pat_status pat_geometry_get_info(pat_geometry g, pat_geometry_info* out);
+/* Launch parameters of the projector kernels (autotuner hook): forward lanes
+ * per bin (log2: 4, 5 or 6 for 16, 32 or 64 lanes), adjoint tile edge (16, 32
+ * or 64 pixels; FP64 uses 32 for 64) and detectors per adjoint workgroup
+ * (1..n_det). Invalid values: PAT_ERR_INVALID_ARG. */
+pat_status pat_geometry_set_launch(pat_geometry g, int32_t fwd_lanes_log2,
+                                   int32_t adj_tile, int32_t adj_det_group);
+
+/* f = A u (Sec. 4.1 eq. K_def, discretised as above).
+ * d_u: device [ny][nx]; d_f: device [n_det][n_t]; element type of g. */
+pat_status pat_forward(pat_geometry g, const void* d_u, void* d_f, void* stream);
+
+/* u = A^T f, the exact matrix transpose of pat_forward (Sec. 3.3.1 uses the
+ * transposed matrix, not a separately discretised adjoint). Deterministic.
+ * d_f: device [n_det][n_t]; d_u: device [ny][nx]. */
+pat_status pat_adjoint(pat_geometry g, const void* d_f, void* d_u, void* stream);
+
+/* Regulariser (Sec. 2.1, 2.2; Sec. 3.1 eqs. PD_TV, PD_TGV).
+ *  TV      : lambda ||grad u||_{2,1}
+ *  TGV     : lambda ||grad u - v||_{2,1} + tgv_alpha0 ||E v||_{F,1}
+ *            (lambda = alpha, tgv_alpha0 = alpha beta in the paper's notation)
+ *  DTV     : lambda ||D grad u||_{2,1}, D = I - (1 - dtv_eta) xi xi^T,
+ *            xi = (-sin theta, cos theta), theta = d_dtv_theta [ny][nx]
+ *            (device, element type of the geometry)
+ *  TIKHONOV: lambda/2 ||u||^2 (LS-T, a test problem with a closed form)
+ * grad uses unit-spacing forward differences with a zero last difference;
+ * E uses the backward differences -grad^T and counts the off-diagonal twice.
+ * Validation: lambda < 0 or non-finite, tgv_alpha0 < 0, dtv_eta not in
+ * (0, 1], DTV without d_dtv_theta -> PAT_ERR_INVALID_ARG. */
+typedef enum { PAT_REG_TV = 0, PAT_REG_TGV = 1, PAT_REG_DTV = 2, PAT_REG_TIKHONOV = 3 } pat_reg_kind;
+typedef struct {
+  int32_t kind;           /* pat_reg_kind */
+  double lambda;
+  double tgv_alpha0;
+  double dtv_eta;
+  const void* d_dtv_theta;
+} pat_regulariser;
+
+/* Step sizes (Sec. 3.3.2).
+ *  DIAG : sigma_i = 1 / sum_j |K_ij|, tau_j = 1 / sum_i |K_ij| over the
+ *         stacked operator K = [A; B] (TGV: [A 0; grad -I; 0 E]); the rows of
+ *         one pixel's dual vector share the smallest of their sigmas; rows
+ *         with no entries get sigma = 1.
+ *  BLOCK: scalar sigma1 (data), sigma2 (regulariser) and tau with
+ *         sigma_i tau L_i^2 = 0.99/4, tau = 1/(2 max(L1, L2)), L1 = ||A||,
+ *         L2 = ||B|| (TGV: the block [grad -I; 0 E]); norms by 1000 power
+ *         iterations times 1.05. */
+typedef enum { PAT_PRECOND_DIAG = 0, PAT_PRECOND_BLOCK = 1 } pat_precond_kind;
+
+/* Compute step sizes for (g, reg). The handle keeps device arrays and must
+ * be used with the same geometry and regulariser. Synchronous on return. */
+pat_status pat_precond(pat_geometry g, const pat_regulariser* reg, int32_t kind,
+                       void* stream, pat_precond_h* out);
+/* Export one step-size array to caller memory (device, element type of g):
+ * which = 0 sigma_q [n_bins], 1 sigma_r [N], 2 sigma_s [N] (TGV),
+ * 3 tau_u [N], 4 tau_v [2][N] (TGV). Missing arrays: PAT_ERR_INVALID_ARG. */
+pat_status pat_precond_get(pat_precond_h p, int32_t which, void* d_dst, void* stream);
+pat_status pat_precond_destroy(pat_precond_h p);
+
+/* Solver state for warm restarts and resume, in one device buffer of the
+ * geometry's element type, concatenated in this order:
+ *   u [N], ubar [N], q [n_bins], r [2][N] (not LS-T),
+ *   TGV only: v [2][N], vbar [2][N], s [3][N] (s_xx, s_xy, s_yy).
+ * pat_state_elems gives the length in elements. */
+pat_status pat_state_elems(pat_geometry g, int32_t reg_kind, int64_t* out);
+
+typedef struct {
+  int32_t max_iter;       /* iterations to run (cap); > 0 */
+  double gap_tol;         /* stop when rel_gap <= gap_tol; <= 0: run max_iter */
+  int32_t gap_every;      /* check interval in iterations (>= 1) */
+  int32_t graph_block;    /* iterations per captured HIP graph (>= 1; 0 = off) */
+  double theta;           /* extrapolation, 1.0 */
+  double gap_box;         /* C of the box-restricted gap; > 0 */
+  const void* d_u0;       /* optional warm start [ny][nx]; NULL = zero */
+  const void* d_state_in; /* optional full state to resume from; NULL = none */
+  void* d_state_out;      /* optional: receives the final state */
+  pat_precond_h precond;  /* NULL: DIAG computed for this call */
+} pat_solve_opts;
+
+typedef struct {
+  int32_t iters, converged, fallback;
+  double rel_gap, gap, primal, fstar, kty_l1, residual, seconds;
+} pat_solve_info;
+
+/* PDHGM (Algorithm 1 for TV/DTV/LS-T, Algorithm 2 for TGV) with theta
+ * extrapolation, from zero, from d_u0, or from d_state_in. The gap of
+ * Sec. 3.3.3 is taken with x restricted to the box ||x||_inf <= gap_box
+ * (the printed gap is infinite when G = 0):
+ *   gap = P(x) + 1/2||q||^2 + <q, f> + gap_box ||K^T y||_1, rel_gap = gap / P(x).
+ * A warm start that is non-finite or has P(u0) > P(0) = 1/2||f||^2 is
+ * replaced by zero (info->fallback = 1).
+ * d_f: device data [n_det][n_t]; d_u_out: device image [ny][nx].
+ * Returns PAT_OK when rel_gap <= gap_tol (or max_iter ran with gap_tol <= 0),
+ * PAT_NOT_CONVERGED at the cap, PAT_ERR_NUMERIC on a non-finite gap.
+ * Synchronous on return (info is filled). */
+pat_status pat_pdhg_solve(pat_geometry g, const void* d_f, const pat_regulariser* reg,
+                          const pat_solve_opts* opts, void* d_u_out,
+                          pat_solve_info* info, void* stream);
+
+/* n independent reconstructions advanced together: every kernel launch covers
+ * all active instances (FP32 geometries only), iterations run in captured
+ * HIP graphs of opts[0].graph_block iterations, and instances whose gap
+ * reaches their gap_tol retire at block ends. Arrays have n entries; per
+ * instance the arguments mean what they mean for pat_pdhg_solve. Returns
+ * PAT_OK if all converged, PAT_NOT_CONVERGED if any hit its cap. */
+pat_status pat_pdhg_solve_batched(int32_t n, const pat_geometry* g, const void* const* d_f,
+                                  const pat_regulariser* reg, const pat_solve_opts* opts,
+                                  void* const* d_u_out, pat_solve_info* info, void* stream);
+
+const char* pat_status_string(pat_status s);
+/* Message of the last error on the calling thread ("" if none). */
+const char* pat_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PAT_H */

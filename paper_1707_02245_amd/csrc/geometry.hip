@@ -1,0 +1,331 @@
+// Geometry tables of the circular-mean operator (arXiv:1707.02245, Sec. 3.3.1
+// discretisation of eq. K_def in Sec. 4.1) and the C-ABI entry points that
+// create and describe them.
+//
+// Every arc sample is addressed by (detector d, radius k, sample m). Its
+// position in continuous pixel-index units (pixel i has its centre at gx = i) is
+//
+//     gx = gdx_d + rho_k cos(phi_km),  gy = gdy_d + rho_k sin(phi_km),
+//     phi_km = 2 pi (m + 1/2) / M_k,   rho_k = r_k / h,
+//
+// evaluated in FP64 from FP64 tables by every kernel that touches samples, so
+// the forward and the adjoint see bit-identical positions and weights.
+// Per bin, the host computes up to four ranges of m whose samples can carry a
+// non-zero weight (the arc clipped to the grid's support box), so the forward
+// kernel skips the arc outside the image.
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+
+#include "pat_internal.hpp"
+
+namespace pat {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+struct Range {
+  int a, b;  // [a, b)
+};
+
+// Sample ranges of one circle (centre (cx, cy), radius rho, M samples) whose
+// samples may fall in the closed box [x0,x1]x[y0,y1] (grid index units).
+// Conservative: one extra sample on each side of every angular interval.
+int circle_box_ranges(double cx, double cy, double rho, int M, double x0, double x1,
+                      double y0, double y1, Range out[4]) {
+  const double eps = 1e-3;  // box growth, far above the FP64 position error
+  x0 -= eps; y0 -= eps; x1 += eps; y1 += eps;
+  auto inside = [&](double a) {
+    const double x = cx + rho * std::cos(a), y = cy + rho * std::sin(a);
+    return x >= x0 && x <= x1 && y >= y0 && y <= y1;
+  };
+  // distance bounds: skip circles that cannot meet the box
+  const double dx = std::max({x0 - cx, 0.0, cx - x1});
+  const double dy = std::max({y0 - cy, 0.0, cy - y1});
+  const double dmin = std::hypot(dx, dy);
+  double dmax = 0.0;
+  for (double sx : {x0, x1})
+    for (double sy : {y0, y1}) dmax = std::max(dmax, std::hypot(sx - cx, sy - cy));
+  if (rho < dmin - eps || rho > dmax + eps) return 0;
+  if (M == 1 || rho == 0.0) {
+    if (inside(0.5 * kTwoPi)) { out[0] = {0, M}; return 1; }
+    return 0;
+  }
+  // crossing angles with the four box lines
+  double cand[10];
+  int nc = 0;
+  cand[nc++] = 0.0;
+  for (double xv : {x0, x1}) {
+    const double t = (xv - cx) / rho;
+    if (t > -1.0 && t < 1.0) {
+      const double a = std::acos(t);
+      cand[nc++] = a;
+      cand[nc++] = kTwoPi - a;
+    }
+  }
+  for (double yh : {y0, y1}) {
+    const double t = (yh - cy) / rho;
+    if (t > -1.0 && t < 1.0) {
+      double a = std::asin(t);
+      if (a < 0) a += kTwoPi;
+      cand[nc++] = a;
+      double b = 0.5 * kTwoPi - std::asin(t);
+      if (b < 0) b += kTwoPi;
+      cand[nc++] = b;
+    }
+  }
+  std::sort(cand, cand + nc);
+  // sub-arcs between consecutive crossings are entirely inside or outside
+  Range raw[12];
+  int nr = 0;
+  for (int i = 0; i < nc; ++i) {
+    const double a = cand[i], b = (i + 1 < nc) ? cand[i + 1] : kTwoPi;
+    if (b - a <= 0.0) continue;
+    if (!inside(0.5 * (a + b))) continue;
+    // samples with phi in [a, b]: m + 1/2 in [a M / 2pi, b M / 2pi]
+    int lo = (int)std::floor(a * M / kTwoPi - 0.5) - 1;
+    int hi = (int)std::ceil(b * M / kTwoPi - 0.5) + 1;  // inclusive
+    if (hi - lo + 1 >= M) { out[0] = {0, M}; return 1; }
+    // split at the wrap so every range lies in [0, M)
+    if (lo < 0) {
+      raw[nr++] = {lo + M, M};
+      lo = 0;
+    }
+    if (hi >= M) {
+      raw[nr++] = {0, hi - M + 1};
+      hi = M - 1;
+    }
+    if (lo <= hi) raw[nr++] = {lo, hi + 1};
+  }
+  if (nr == 0) return 0;
+  std::sort(raw, raw + nr, [](const Range& p, const Range& q) { return p.a < q.a; });
+  // merge overlapping or touching ranges
+  Range mg[12];
+  int nm = 0;
+  for (int i = 0; i < nr; ++i) {
+    if (nm > 0 && raw[i].a <= mg[nm - 1].b) {
+      mg[nm - 1].b = std::max(mg[nm - 1].b, raw[i].b);
+    } else {
+      mg[nm++] = raw[i];
+    }
+  }
+  // at most four ranges: close the smallest gaps (still exact, more work)
+  while (nm > 4) {
+    int best = 0;
+    for (int i = 1; i + 1 < nm; ++i)
+      if (mg[i + 1].a - mg[i].b < mg[best + 1].a - mg[best].b) best = i;
+    mg[best].b = mg[best + 1].b;
+    for (int i = best + 1; i + 1 < nm; ++i) mg[i] = mg[i + 1];
+    --nm;
+  }
+  for (int i = 0; i < nm; ++i) out[i] = mg[i];
+  return nm;
+}
+
+static bool finite_all(std::initializer_list<double> xs) {
+  for (double x : xs)
+    if (!std::isfinite(x)) return false;
+  return true;
+}
+
+void validate_geometry_desc(const pat_geometry_desc* d) {
+  PAT_CHECK_ARG(d != nullptr, "desc is NULL");
+  PAT_CHECK_ARG(d->nx >= 2 && d->ny >= 2, "nx and ny must be >= 2");
+  PAT_CHECK_ARG(d->nx <= 16384 && d->ny <= 16384, "nx and ny must be <= 16384");
+  PAT_CHECK_ARG(d->n_det >= 1, "n_det must be >= 1");
+  PAT_CHECK_ARG(d->n_t >= 2, "n_t must be >= 2");
+  PAT_CHECK_ARG((int64_t)d->n_det * d->n_t <= (int64_t(1) << 28), "n_det * n_t too large");
+  PAT_CHECK_ARG(finite_all({d->x_min, d->x_max, d->y_min, d->y_max, d->det_cx, d->det_cy,
+                            d->det_radius, d->arc_center, d->arc_span, d->t0, d->dt, d->c,
+                            d->samples_per_pixel}),
+                "non-finite scalar in geometry");
+  PAT_CHECK_ARG(d->x_max > d->x_min && d->y_max > d->y_min, "empty image domain");
+  const double hx = (d->x_max - d->x_min) / d->nx, hy = (d->y_max - d->y_min) / d->ny;
+  PAT_CHECK_ARG(std::fabs(hx - hy) <= 1e-9 * std::max(hx, hy), "pixels must be square");
+  PAT_CHECK_ARG(d->dt > 0.0 && d->c > 0.0 && d->samples_per_pixel > 0.0,
+                "dt, c and samples_per_pixel must be > 0");
+  PAT_CHECK_ARG(d->t0 >= 0.0, "t0 must be >= 0");
+  if (d->det_xy) {
+    for (int i = 0; i < 2 * d->n_det; ++i)
+      PAT_CHECK_ARG(std::isfinite(d->det_xy[i]), "non-finite detector position");
+  } else {
+    PAT_CHECK_ARG(d->arc_span > 0.0 && d->arc_span <= kTwoPi + 1e-12,
+                  "arc_span must be in (0, 2 pi]");
+    PAT_CHECK_ARG(d->det_radius >= 0.0, "det_radius must be >= 0");
+  }
+  const double r_max = d->c * (d->t0 + d->dt * (d->n_t - 1));
+  const double m_max = std::ceil(kTwoPi * r_max * d->samples_per_pixel / hx);
+  PAT_CHECK_ARG(m_max < 4.0e6, "too many arc samples per circle");
+}
+
+}  // namespace pat
+
+using pat::Range;
+
+void pat_geometry_s::build_host() {
+  const pat_geometry_desc& d = desc;
+  using pat::kTwoPi;
+  nx = d.nx; ny = d.ny; n_det = d.n_det; n_t = d.n_t;
+  h = (d.x_max - d.x_min) / nx;
+  det_xy.resize(2 * (size_t)n_det);
+  if (d.det_xy) {
+    std::memcpy(det_xy.data(), d.det_xy, sizeof(double) * 2 * n_det);
+  } else {
+    const bool closed = std::fabs(d.arc_span - kTwoPi) < 1e-12;
+    for (int i = 0; i < n_det; ++i) {
+      double a;
+      if (closed) a = d.arc_center + kTwoPi * i / n_det;
+      else if (n_det == 1) a = d.arc_center;
+      else a = d.arc_center - 0.5 * d.arc_span + d.arc_span * i / (n_det - 1);
+      det_xy[2 * i] = d.det_cx + d.det_radius * std::cos(a);
+      det_xy[2 * i + 1] = d.det_cy + d.det_radius * std::sin(a);
+    }
+  }
+  M.resize(n_t);
+  off.resize(n_t);
+  radius.resize(n_t);
+  int64_t acc = 0;
+  for (int k = 0; k < n_t; ++k) {
+    const double r = d.c * (d.t0 + k * d.dt);
+    radius[k] = r;
+    const double m = std::ceil(kTwoPi * r * d.samples_per_pixel / h);
+    M[k] = std::max(1, (int)m);
+    off[k] = acc;
+    acc += M[k];
+  }
+  n_samples_per_det = acc;
+  PAT_CHECK_ARG(acc < (int64_t(1) << 31), "sample table too large");
+}
+
+void pat_geometry_s::upload(hipStream_t stream) {
+  using pat::kTwoPi;
+  using pat::DevBuf;
+  // detector positions and radii in grid index units
+  std::vector<double2> h_det(n_det), h_rad(n_t), h_cs(n_samples_per_det);
+  std::vector<int2> h_moff(n_t);
+  for (int i = 0; i < n_det; ++i) {
+    h_det[i].x = (det_xy[2 * i] - desc.x_min) / h - 0.5;
+    h_det[i].y = (det_xy[2 * i + 1] - desc.y_min) / h - 0.5;
+  }
+  for (int k = 0; k < n_t; ++k) {
+    h_rad[k].x = radius[k] / h;
+    h_rad[k].y = 1.0 / M[k];
+    h_moff[k] = make_int2(M[k], off[k]);
+    for (int m = 0; m < M[k]; ++m) {
+      const double phi = kTwoPi * (m + 0.5) / M[k];
+      h_cs[off[k] + m] = make_double2(std::cos(phi), std::sin(phi));
+    }
+  }
+  // clip windows: ranges of m whose samples can carry weight on the grid,
+  // i.e. lie in the box [-1, nx] x [-1, ny] of index space
+  const int64_t nb = (int64_t)n_det * n_t;
+  std::vector<int4> h_win(2 * nb);
+  n_window = 0;
+  for (int i = 0; i < n_det; ++i) {
+    for (int k = 0; k < n_t; ++k) {
+      Range rg[4];
+      const int n = pat::circle_box_ranges(h_det[i].x, h_det[i].y, h_rad[k].x, M[k], -1.0,
+                                      (double)nx, -1.0, (double)ny, rg);
+      int v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      for (int j = 0; j < n; ++j) {
+        v[2 * j] = rg[j].a;
+        v[2 * j + 1] = rg[j].b;
+        n_window += rg[j].b - rg[j].a;
+      }
+      const int64_t b = (int64_t)i * n_t + k;
+      h_win[2 * b] = make_int4(v[0], v[1], v[2], v[3]);
+      h_win[2 * b + 1] = make_int4(v[4], v[5], v[6], v[7]);
+    }
+  }
+  d_det.alloc(sizeof(double2) * n_det);
+  d_rad.alloc(sizeof(double2) * n_t);
+  d_moff.alloc(sizeof(int2) * n_t);
+  d_cs.alloc(sizeof(double2) * n_samples_per_det);
+  d_win.alloc(sizeof(int4) * 2 * nb);
+  PAT_HIP(hipMemcpyAsync(d_det.p, h_det.data(), d_det.bytes, hipMemcpyHostToDevice, stream));
+  PAT_HIP(hipMemcpyAsync(d_rad.p, h_rad.data(), d_rad.bytes, hipMemcpyHostToDevice, stream));
+  PAT_HIP(hipMemcpyAsync(d_moff.p, h_moff.data(), d_moff.bytes, hipMemcpyHostToDevice, stream));
+  PAT_HIP(hipMemcpyAsync(d_cs.p, h_cs.data(), d_cs.bytes, hipMemcpyHostToDevice, stream));
+  PAT_HIP(hipMemcpyAsync(d_win.p, h_win.data(), d_win.bytes, hipMemcpyHostToDevice, stream));
+  PAT_HIP(hipStreamSynchronize(stream));
+}
+
+void pat_geometry_s::set_launch(int lanes_log2_, int tile_, int det_group_) {
+  PAT_CHECK_ARG(lanes_log2_ >= 4 && lanes_log2_ <= 6, "forward lanes per bin must be 16, 32 or 64");
+  PAT_CHECK_ARG(tile_ == 16 || tile_ == 32 || tile_ == 64, "adjoint tile must be 16, 32 or 64");
+  PAT_CHECK_ARG(det_group_ >= 1 && det_group_ <= n_det, "adjoint detector group out of range");
+  lanes_log2 = lanes_log2_;
+  tile = tile_;
+  det_group = det_group_;
+}
+
+void pat_geometry_s::default_launch() {
+  // Enough adjoint workgroups to fill 256 CUs several times over.
+  tile = (nx >= 384 && ny >= 384) ? 32 : 32;
+  const int tiles = ((nx + tile - 1) / tile) * ((ny + tile - 1) / tile);
+  int groups = std::max(1, (2048 + tiles - 1) / tiles);
+  groups = std::min(groups, n_det);
+  det_group = (n_det + groups - 1) / groups;
+  lanes_log2 = 6;
+}
+
+using pat::guarded;
+
+extern "C" pat_status pat_geometry_create(const pat_geometry_desc* desc, pat_dtype dtype,
+                                          void* stream, pat_geometry* out) {
+  return guarded([&]() -> pat_status {
+    PAT_CHECK_ARG(out != nullptr, "out is NULL");
+    PAT_CHECK_ARG(dtype == PAT_F32 || dtype == PAT_F64, "dtype must be PAT_F32 or PAT_F64");
+    pat::validate_geometry_desc(desc);
+    std::unique_ptr<pat_geometry_s> g(new pat_geometry_s());
+    g->desc = *desc;
+    g->desc.det_xy = nullptr;  // the host copy lives in det_xy
+    if (desc->det_xy) {
+      g->det_xy.assign(desc->det_xy, desc->det_xy + 2 * (size_t)desc->n_det);
+      g->desc.det_xy = g->det_xy.data();
+    }
+    g->dtype = dtype;
+    g->build_host();
+    g->upload(static_cast<hipStream_t>(stream));
+    g->default_launch();
+    *out = g.release();
+    return PAT_OK;
+  });
+}
+
+extern "C" pat_status pat_geometry_destroy(pat_geometry g) {
+  return guarded([&]() -> pat_status {
+    delete g;
+    return PAT_OK;
+  });
+}
+
+extern "C" pat_status pat_geometry_get_info(pat_geometry g, pat_geometry_info* out) {
+  return guarded([&]() -> pat_status {
+    PAT_CHECK_ARG(g != nullptr && out != nullptr, "NULL argument");
+    out->nx = g->nx;
+    out->ny = g->ny;
+    out->n_det = g->n_det;
+    out->n_t = g->n_t;
+    out->n_pix = (int64_t)g->nx * g->ny;
+    out->n_bins = (int64_t)g->n_det * g->n_t;
+    out->n_samples = g->n_samples_per_det * g->n_det;
+    out->n_window = g->n_window;
+    out->dtype = g->dtype;
+    out->fwd_lanes_log2 = g->lanes_log2;
+    out->adj_tile = g->tile;
+    out->adj_det_group = g->det_group;
+    return PAT_OK;
+  });
+}
+
+extern "C" pat_status pat_geometry_set_launch(pat_geometry g, int32_t lanes_log2, int32_t tile,
+                                              int32_t det_group) {
+  return guarded([&]() -> pat_status {
+    PAT_CHECK_ARG(g != nullptr, "geometry is NULL");
+    g->set_launch(lanes_log2, tile, det_group);
+    return PAT_OK;
+  });
+}

@@ -1,0 +1,215 @@
+// Internal definitions shared by the translation units of libpat.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "pat.h"
+
+namespace pat {
+
+// ---------------------------------------------------------------- errors
+
+struct Error {
+  pat_status status;
+};
+
+void set_error(const char* fmt, ...);
+void clear_error();
+
+[[noreturn]] inline void fail(pat_status s, const char* msg) {
+  set_error("%s", msg);
+  throw Error{s};
+}
+
+#define PAT_CHECK_ARG(cond, msg)                                      \
+  do {                                                                \
+    if (!(cond)) {                                                    \
+      ::pat::set_error("invalid argument: %s", msg);                  \
+      throw ::pat::Error{PAT_ERR_INVALID_ARG};                        \
+    }                                                                 \
+  } while (0)
+
+#define PAT_HIP(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      ::pat::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                       __LINE__);                                                      \
+      throw ::pat::Error{e_ == hipErrorOutOfMemory ? PAT_ERR_OOM : PAT_ERR_DEVICE};    \
+    }                                                                                  \
+  } while (0)
+
+// Run a body and translate exceptions into a status (nothing crosses the ABI).
+template <class F>
+pat_status guarded(F&& body) {
+  try {
+    clear_error();
+    return body();
+  } catch (const Error& e) {
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return PAT_ERR_OOM;
+  } catch (...) {
+    set_error("unexpected internal error");
+    return PAT_ERR_DEVICE;
+  }
+}
+
+// ---------------------------------------------------------------- device memory
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t n) { alloc(n); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t n) {
+    release();
+    if (n == 0) return;
+    PAT_HIP(hipMalloc(&p, n));
+    bytes = n;
+  }
+  // grow-only reuse
+  void ensure(size_t n) { if (n > bytes) alloc(n); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+template <class T> inline T* ptr(const DevBuf& b) { return static_cast<T*>(b.p); }
+
+inline size_t dtype_size(int dt) { return dt == PAT_F64 ? sizeof(double) : sizeof(float); }
+
+// ---------------------------------------------------------------- device helpers
+
+template <class T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+template <class T> using vec2_t = typename Vec2<T>::type;
+
+// Sum over the lanes of a group of W consecutive lanes (W a power of two <= 64).
+template <int W, class T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
+  return v;
+}
+
+// Deterministic block reduction into one value per block (blockDim.x = NT).
+template <int NT, class T>
+__device__ __forceinline__ T block_sum(T v, T* lds) {
+  v = group_sum<64>(v);
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (lane == 0) lds[wave] = v;
+  __syncthreads();
+  T s = T(0);
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < NT / 64; ++w) s += lds[w];
+  }
+  __syncthreads();
+  return s;  // valid in thread 0
+}
+
+// ---------------------------------------------------------------- per-instance descriptor
+
+// Gap partial sums, one double per block and slot.
+enum GapSlot {
+  GAP_DATA = 0,     // 1/2 ||A u - f||^2
+  GAP_REG = 1,      // regulariser value at (u, v)
+  GAP_FSTAR = 2,    // 1/2 ||q||^2 + <q, f>
+  GAP_KTY = 3,      // ||K^T y||_1 (LS-T: ||A^T q||^2)
+  GAP_DU2 = 4,      // ||u+ - u||^2
+  GAP_U2 = 5,       // ||u||^2 before the update
+  GAP_NSLOTS = 6
+};
+
+// Geometry tables on the device plus launch parameters. Sample positions are
+// evaluated in FP64 for every element type.
+struct GeomDev {
+  int nx, ny, n_det, n_t;
+  int pitch;             // nx + 2 (padded image row length)
+  const double2* det;    // [n_det] detector position in pixel-index units
+  const double2* rad;    // [n_t] (r_k / h, 1 / M_k)
+  const int2* moff;      // [n_t] (M_k, offset of radius k in the table)
+  const double2* cs;     // [sum M_k] (cos, sin) of 2 pi (m + 1/2) / M_k
+  const int4* win;       // [n_bins][2]: four sample ranges [m0,m1) per bin
+  double kscale, koff;   // radius index of a radius rho in pixel units: rho*kscale - koff
+  int lanes_log2;        // forward: lanes per bin, log2 (4..6)
+  int tile;              // adjoint: tile edge in pixels
+  int tiles_x, tiles_y;
+  int det_group;         // adjoint: detectors per workgroup
+  int n_groups;          // ceil(n_det / det_group)
+};
+
+// Forward projection of one instance.
+template <class T>
+struct FwdArgs {
+  GeomDev g;
+  const T* upad;      // padded image [(ny+2)(nx+2)]
+  T* out;             // PLAIN: A u; DUAL: q (in/out); ROWSUM: sigma_q
+  const T* f;         // DUAL, GAP: data
+  const T* sigma;     // DUAL: sigma_q
+  const T* q;         // GAP: dual variable for F*
+  double* red;        // GAP: partial sums [GAP_NSLOTS][red_stride]
+  int red_stride;
+};
+
+// Adjoint projection of one instance into per-detector-group partial images.
+template <class T>
+struct AdjArgs {
+  GeomDev g;
+  const T* data;      // [n_det][n_t]
+  T* part;            // [n_groups][ny][nx]
+};
+
+// One PDHG instance as seen by the pixel kernels.
+template <class T>
+struct InstDev {
+  int nx, ny, n_groups, n_bins;
+  int kind;           // pat_reg_kind
+  T lam, alpha0;
+  T theta_ex;         // extrapolation parameter
+  const T* dmat;      // [3][N] (D11, D12, D22) of the directional gradient (DTV)
+  // state
+  T* u;               // [N]
+  T* ubar_pad;        // [(ny+2)(nx+2)], zero border
+  T* r;               // [2][N]
+  T* v;               // [2][N]  (TGV)
+  T* vbar;            // [2][N]  (TGV)
+  T* s;               // [3][N]  (TGV)
+  // step sizes
+  const T* sigma_r;   // [N]
+  const T* sigma_s;   // [N]
+  const T* tau_u;     // [N]
+  const T* tau_v;     // [N] (both components share one value)
+  const T* atq_part;  // [n_groups][N] partial A^T q per detector group
+  T* upad_gap;        // [(ny+2)(nx+2)] padded u+ written on check iterations
+  double* red;        // partial sums [GAP_NSLOTS][red_stride]
+  int red_stride;
+};
+
+// Ordered final sum of one instance's gap partials.
+struct GapFinishArgs {
+  const double* red;
+  int stride, n_fwd, n_pix;
+};
+
+}  // namespace pat

@@ -1,0 +1,115 @@
+// Host-side structures and launcher declarations of libpat.
+#pragma once
+
+#include "pat_common.hpp"
+
+// The opaque handle of pat.h.
+struct pat_geometry_s {
+  pat_geometry_desc desc{};
+  std::vector<double> det_xy;  // [n_det][2] world coordinates
+  int dtype = PAT_F32;
+  int nx = 0, ny = 0, n_det = 0, n_t = 0;
+  double h = 0.0;
+  std::vector<int> M, off;     // arc samples per radius and table offsets
+  std::vector<double> radius;  // r_k
+  int64_t n_samples_per_det = 0;
+  int64_t n_window = 0;        // samples inside the clip windows, all bins
+  pat::DevBuf d_det, d_rad, d_moff, d_cs, d_win;
+  // launch parameters
+  int lanes_log2 = 6, tile = 32, det_group = 16;
+  // scratch of the stand-alone applies
+  pat::DevBuf scratch_pad, scratch_part;
+
+  void build_host();
+  void upload(hipStream_t stream);
+  void set_launch(int lanes_log2, int tile, int det_group);
+  void default_launch();
+  pat::GeomDev dev() const;
+  int64_t n_bins() const { return (int64_t)n_det * n_t; }
+  int64_t n_pix() const { return (int64_t)nx * ny; }
+  int n_groups() const { return (n_det + det_group - 1) / det_group; }
+  int adj_blocks() const {
+    return ((nx + tile - 1) / tile) * ((ny + tile - 1) / tile) * n_groups();
+  }
+};
+
+// Step sizes of one (geometry, regulariser) pair.
+struct pat_precond_s {
+  pat_geometry g = nullptr;
+  int reg_kind = 0;
+  int kind = PAT_PRECOND_DIAG;
+  double L1 = 0.0, L2 = 0.0;  // BLOCK mode norms
+  pat::DevBuf sigma_q, sigma_r, sigma_s, tau_u, tau_v;
+};
+
+namespace pat {
+
+void validate_geometry_desc(const pat_geometry_desc* d);
+void validate_regulariser(const pat_geometry_s* g, const pat_regulariser* r);
+
+enum FwdMode { FWD_PLAIN = 0, FWD_DUAL = 1, FWD_GAP = 2, FWD_ROWSUM = 3 };
+
+constexpr int kThreads = 256;
+
+inline int fwd_blocks(const pat_geometry_s* g) {
+  const int bpb = kThreads >> g->lanes_log2;
+  return (int)((g->n_bins() + bpb - 1) / bpb);
+}
+inline int pix_blocks(int64_t n) { return (int)((n + kThreads - 1) / kThreads); }
+
+// Batched launch tables: args arrays and instance block offsets on the device.
+template <class T>
+struct Launch {
+  int n = 0;
+  DevBuf fwd, fwd_gap, adj, inst, gapfin;  // FwdArgs x2 / AdjArgs / InstDev / GapFinishArgs
+  DevBuf fwd_start, adj_start, pix_start;
+  int fwd_total = 0, adj_total = 0, pix_total = 0;
+  int lanes_log2 = 6;   // shared by every instance of one launch
+  int max_tile = 32;    // shared by every instance of one launch
+};
+
+// ---- launchers (projector.hip)
+template <class T>
+void launch_pad(const T* u, T* upad, int nx, int ny, hipStream_t s);
+template <class T>
+void launch_forward(int mode, const FwdArgs<T>& a, int lanes_log2, hipStream_t s);
+template <class T>
+void launch_forward_batched(int mode, const Launch<T>& L, int lanes_log2, hipStream_t s);
+template <class T>
+void launch_adjoint(const AdjArgs<T>& a, hipStream_t s);
+template <class T>
+void launch_adjoint_batched(const Launch<T>& L, hipStream_t s);
+template <class T>
+void launch_reduce_groups(const T* part, T* out, int n_groups, int64_t n, hipStream_t s);
+
+// ---- launchers (pdhg.hip)
+template <class T>
+void launch_reg_dual(const Launch<T>& L, hipStream_t s);
+template <class T>
+void launch_primal(const Launch<T>& L, bool check, hipStream_t s);
+template <class T>
+void launch_pattern(T* x, int64_t n, hipStream_t s);
+template <class T>
+void launch_gap_reg(const Launch<T>& L, hipStream_t s);
+// Sum the partial sums of every instance: out[inst][slot] (double).
+void launch_gap_finish(const GapFinishArgs* args, int n_inst, double* out, hipStream_t s);
+template <class T>
+void launch_precond_pix(int reg_kind, int nx, int ny, const T* colsum_a, const T* dmat,
+                        T* sigma_r, T* sigma_s, T* tau_u, T* tau_v, hipStream_t s);
+template <class T>
+void launch_dmat(const T* theta, T eta, T* dmat, int64_t n, hipStream_t s);
+template <class T>
+void launch_fill(T* p, T v, int64_t n, hipStream_t s);
+template <class T>
+void launch_reg_apply(int reg_kind, int nx, int ny, const T* dmat, const T* xu, const T* xv,
+                      T* z, hipStream_t s);
+template <class T>
+void launch_reg_apply_t(int reg_kind, int nx, int ny, const T* dmat, const T* z, T* yu, T* yv,
+                        hipStream_t s);
+template <class T>
+void launch_dot(const T* a, const T* b, int64_t n, double* partial, int n_part, double* out,
+                hipStream_t s);
+template <class T>
+void launch_scale_copy(T* y, const T* x, const double* denom, int64_t n, hipStream_t s);
+
+}  // namespace pat

@@ -1,0 +1,437 @@
+// Circular-mean projector A and its exact transpose on gfx950
+// (arXiv:1707.02245, Sec. 4.1 eq. K_def; Sec. 3.3.1: K applied as a matrix,
+// its transpose as the adjoint).
+//
+// Forward (bin-major gather): a group of 16..64 lanes owns one bin (d, k) and
+// walks the arc samples inside the bin's clip windows; each sample reads the
+// 2x2 neighbourhood of a zero-bordered copy of the image (L1/L2 resident)
+// and adds the bilinear weights times the values. The group sum times 1/M_k
+// is the bin's value; epilogues fuse the dual data step of PDHGM, the gap
+// terms or the row sums of the preconditioner.
+//
+// Adjoint (tile scatter): a workgroup owns a square pixel tile and a group of
+// detectors; each wave walks, for its detectors, the radii whose circles meet
+// the tile and the arc samples in the tile's angular window, and adds weight
+// times data into a private LDS accumulator (tile plus one-pixel halo). The
+// four waves' accumulators are summed in a fixed order and written as one
+// partial image per detector group; partials are summed in a fixed order by
+// the consumer. Positions and weights use the same FP64 formula as the
+// forward, so the two are transposes of the same matrix, and the result is
+// run-to-run deterministic (one wave per accumulator, no cross-wave atomics).
+
+#include "pat_internal.hpp"
+
+namespace pat {
+
+constexpr double kTwoPiD = 6.283185307179586476925286766559;
+
+__device__ __forceinline__ int find_inst(const int* __restrict__ starts, int n, int blk) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (starts[mid] <= blk) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Position of arc sample (d, k, m) in pixel-index units and its bilinear cell.
+struct Sample {
+  int ix, iy;
+  double tx, ty;
+};
+
+__device__ __forceinline__ Sample arc_sample(const double2 p, const double rho, const double2 cs) {
+  const double gx = fma(rho, cs.x, p.x);
+  const double gy = fma(rho, cs.y, p.y);
+  const double fx = floor(gx), fy = floor(gy);
+  Sample s;
+  s.ix = (int)fx;
+  s.iy = (int)fy;
+  s.tx = gx - fx;
+  s.ty = gy - fy;
+  return s;
+}
+
+// ------------------------------------------------------------------ padding
+
+template <class T>
+__global__ __launch_bounds__(256) void pad_kernel(const T* __restrict__ u, T* __restrict__ upad,
+                                                  int nx, int ny) {
+  const int P = nx + 2;
+  const int64_t n = (int64_t)P * (ny + 2);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(i % P) - 1, y = (int)(i / P) - 1;
+    upad[i] = (x >= 0 && x < nx && y >= 0 && y < ny) ? u[(int64_t)y * nx + x] : T(0);
+  }
+}
+
+template <class T>
+void launch_pad(const T* u, T* upad, int nx, int ny, hipStream_t s) {
+  const int64_t n = (int64_t)(nx + 2) * (ny + 2);
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(pad_kernel<T>, dim3(blocks), dim3(256), 0, s, u, upad, nx, ny);
+  PAT_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ forward
+
+template <class T, int MODE, int LANES>
+__global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T>* __restrict__ arr,
+                                                  const int* __restrict__ starts, int n_inst) {
+  int blk = blockIdx.x;
+  FwdArgs<T> a;
+  if (arr) {
+    const int i = find_inst(starts, n_inst, blk);
+    a = arr[i];
+    blk -= starts[i];
+  } else {
+    a = a0;
+  }
+  const GeomDev& g = a.g;
+  constexpr int BPB = 256 / LANES;
+  const int sub = threadIdx.x / LANES, lane = threadIdx.x % LANES;
+  const int n_bins = g.n_det * g.n_t;
+  const int b = blk * BPB + sub;
+  const bool valid = b < n_bins;
+  T acc = T(0);
+  double inv_m = 0.0;
+  if (valid) {
+    const int d = b / g.n_t, k = b - d * g.n_t;
+    const int4 w0 = g.win[2 * (int64_t)b], w1 = g.win[2 * (int64_t)b + 1];
+    const int l0 = w0.y - w0.x, l1 = w0.w - w0.z, l2 = w1.y - w1.x, l3 = w1.w - w1.z;
+    const int total = l0 + l1 + l2 + l3;
+    const double2 p = g.det[d];
+    const double2 rr = g.rad[k];
+    inv_m = rr.y;
+    const double2* __restrict__ cs = g.cs + g.moff[k].y;
+    const T* __restrict__ up = a.upad;
+    const int P = g.pitch;
+    for (int j = lane; j < total; j += LANES) {
+      int m;
+      if (j < l0) m = w0.x + j;
+      else if (j < l0 + l1) m = w0.z + (j - l0);
+      else if (j < l0 + l1 + l2) m = w1.x + (j - l0 - l1);
+      else m = w1.z + (j - l0 - l1 - l2);
+      const Sample s = arc_sample(p, rr.x, cs[m]);
+      if (s.ix >= -1 && s.ix < g.nx && s.iy >= -1 && s.iy < g.ny) {
+        const T tx = (T)s.tx, ty = (T)s.ty;
+        const T w00 = (T(1) - tx) * (T(1) - ty), w10 = tx * (T(1) - ty);
+        const T w01 = (T(1) - tx) * ty, w11 = tx * ty;
+        const T* q = up + (int64_t)(s.iy + 1) * P + (s.ix + 1);
+        acc += w00 * q[0] + w10 * q[1] + w01 * q[P] + w11 * q[P + 1];
+      }
+    }
+  }
+  acc = group_sum<LANES>(acc);
+  const T val = acc * (T)inv_m;
+  if (MODE == FWD_GAP) {
+    __shared__ double lds[8];
+    double d_data = 0.0, d_fs = 0.0;
+    if (valid && lane == 0) {
+      const double res = (double)val - (double)a.f[b];
+      const double qb = (double)a.q[b];
+      d_data = 0.5 * res * res;
+      d_fs = 0.5 * qb * qb + qb * (double)a.f[b];
+    }
+    const double s0 = block_sum<256>(d_data, lds);
+    const double s1 = block_sum<256>(d_fs, lds);
+    if (threadIdx.x == 0) {
+      a.red[GAP_DATA * (int64_t)a.red_stride + blk] = s0;
+      a.red[GAP_FSTAR * (int64_t)a.red_stride + blk] = s1;
+    }
+    return;
+  }
+  if (!valid || lane != 0) return;
+  if (MODE == FWD_PLAIN) {
+    a.out[b] = val;
+  } else if (MODE == FWD_DUAL) {
+    // q <- prox_{sigma F1*}(q + sigma A ubar) = (q + sigma (A ubar - f)) / (1 + sigma)
+    const T sg = a.sigma[b];
+    a.out[b] = (a.out[b] + sg * (val - a.f[b])) / (T(1) + sg);
+  } else if (MODE == FWD_ROWSUM) {
+    // A >= 0, so the absolute row sum is A 1; empty rows get sigma = 1
+    a.out[b] = val > T(0) ? T(1) / val : T(1);
+  }
+}
+
+template <class T, int MODE>
+static void fwd_dispatch(int lanes_log2, int blocks, const FwdArgs<T>& a0, const FwdArgs<T>* arr,
+                         const int* starts, int n, hipStream_t s) {
+  switch (lanes_log2) {
+    case 4: hipLaunchKernelGGL((fwd_kernel<T, MODE, 16>), dim3(blocks), dim3(256), 0, s, a0, arr, starts, n); break;
+    case 5: hipLaunchKernelGGL((fwd_kernel<T, MODE, 32>), dim3(blocks), dim3(256), 0, s, a0, arr, starts, n); break;
+    default: hipLaunchKernelGGL((fwd_kernel<T, MODE, 64>), dim3(blocks), dim3(256), 0, s, a0, arr, starts, n); break;
+  }
+}
+
+template <class T>
+static void fwd_mode_dispatch(int mode, int lanes_log2, int blocks, const FwdArgs<T>& a0,
+                              const FwdArgs<T>* arr, const int* starts, int n, hipStream_t s) {
+  if (blocks <= 0) return;
+  switch (mode) {
+    case FWD_PLAIN: fwd_dispatch<T, FWD_PLAIN>(lanes_log2, blocks, a0, arr, starts, n, s); break;
+    case FWD_DUAL: fwd_dispatch<T, FWD_DUAL>(lanes_log2, blocks, a0, arr, starts, n, s); break;
+    case FWD_GAP: fwd_dispatch<T, FWD_GAP>(lanes_log2, blocks, a0, arr, starts, n, s); break;
+    default: fwd_dispatch<T, FWD_ROWSUM>(lanes_log2, blocks, a0, arr, starts, n, s); break;
+  }
+  PAT_HIP(hipGetLastError());
+}
+
+template <class T>
+void launch_forward(int mode, const FwdArgs<T>& a, int lanes_log2, hipStream_t s) {
+  const int bpb = 256 >> lanes_log2;
+  const int blocks = (a.g.n_det * a.g.n_t + bpb - 1) / bpb;
+  fwd_mode_dispatch<T>(mode, lanes_log2, blocks, a, nullptr, nullptr, 1, s);
+}
+
+template <class T>
+void launch_forward_batched(int mode, const Launch<T>& L, int lanes_log2, hipStream_t s) {
+  FwdArgs<T> dummy{};
+  fwd_mode_dispatch<T>(mode, lanes_log2, L.fwd_total, dummy, ptr<FwdArgs<T>>(L.fwd),
+                       ptr<int>(L.fwd_start), L.n, s);
+}
+
+// ------------------------------------------------------------------ adjoint
+
+template <class T, int TILE>
+__global__ __launch_bounds__(256) void adj_kernel(AdjArgs<T> a0, const AdjArgs<T>* __restrict__ arr,
+                                                  const int* __restrict__ starts, int n_inst) {
+  constexpr int S = TILE + 2;  // tile plus a one-pixel halo on each side
+  __shared__ T acc[4 * S * S];
+  int blk = blockIdx.x;
+  AdjArgs<T> a;
+  if (arr) {
+    const int i = find_inst(starts, n_inst, blk);
+    a = arr[i];
+    blk -= starts[i];
+  } else {
+    a = a0;
+  }
+  const GeomDev& g = a.g;
+  const int n_tiles = g.tiles_x * g.tiles_y;
+  const int grp = blk / n_tiles, t = blk - grp * n_tiles;
+  const int I0 = (t % g.tiles_x) * TILE, J0 = (t / g.tiles_x) * TILE;
+  for (int i = threadIdx.x; i < 4 * S * S; i += 256) acc[i] = T(0);
+  __syncthreads();
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  T* __restrict__ my = acc + wave * S * S;
+  // samples whose cell (ix, iy) lies in [I0-1, I0+TILE-1] x [J0-1, J0+TILE-1]
+  // touch the tile; their positions lie in this closed box
+  const double bx0 = I0 - 1.0, bx1 = I0 + (double)TILE, by0 = J0 - 1.0, by1 = J0 + (double)TILE;
+  const int d_begin = grp * g.det_group;
+  const int d_end = min(g.n_det, d_begin + g.det_group);
+  for (int d = d_begin + wave; d < d_end; d += 4) {
+    const double2 p = g.det[d];
+    const double ex = fmax(fmax(bx0 - p.x, 0.0), p.x - bx1);
+    const double ey = fmax(fmax(by0 - p.y, 0.0), p.y - by1);
+    const double rmin = sqrt(ex * ex + ey * ey);
+    const double cx0 = bx0 - p.x, cx1 = bx1 - p.x, cy0 = by0 - p.y, cy1 = by1 - p.y;
+    const double rmax = sqrt(fmax(cx0 * cx0, cx1 * cx1) + fmax(cy0 * cy0, cy1 * cy1));
+    const int k0 = max(0, (int)floor(rmin * g.kscale - g.koff) - 1);
+    const int k1 = min(g.n_t - 1, (int)ceil(rmax * g.kscale - g.koff) + 1);
+    // angular window of the box seen from the detector; the whole circle when
+    // the detector is within two pixels of the box
+    const bool full = rmin < 2.0;
+    double a_lo = 0.0, a_hi = 0.0;
+    if (!full) {
+      const double pc = atan2(0.5 * (cy0 + cy1), 0.5 * (cx0 + cx1));
+      double dmin = 0.0, dmax = 0.0;
+      const double cxs[2] = {cx0, cx1}, cys[2] = {cy0, cy1};
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        double dd = atan2(cys[c >> 1], cxs[c & 1]) - pc;
+        dd -= kTwoPiD * rint(dd / kTwoPiD);
+        dmin = fmin(dmin, dd);
+        dmax = fmax(dmax, dd);
+      }
+      a_lo = pc + dmin - 1e-9;
+      a_hi = pc + dmax + 1e-9;
+    }
+    for (int k = k0; k <= k1; ++k) {
+      const T gk = a.data[(int64_t)d * g.n_t + k];
+      if (gk == T(0)) continue;
+      const int2 mo = g.moff[k];
+      const double2 rr = g.rad[k];
+      const int M = mo.x;
+      int mlo = 0, cnt = M;
+      if (!full) {
+        mlo = (int)floor(a_lo * M / kTwoPiD - 0.5) - 1;
+        const int mhi = (int)ceil(a_hi * M / kTwoPiD - 0.5) + 1;
+        cnt = min(M, mhi - mlo + 1);
+        mlo %= M;
+        if (mlo < 0) mlo += M;
+      }
+      const T gw = gk * (T)rr.y;
+      const double2* __restrict__ cs = g.cs + mo.y;
+      for (int j = lane; j < cnt; j += 64) {
+        int m = mlo + j;
+        if (m >= M) m -= M;
+        const Sample s = arc_sample(p, rr.x, cs[m]);
+        const int lx = s.ix - (I0 - 1), ly = s.iy - (J0 - 1);
+        if ((unsigned)lx <= (unsigned)TILE && (unsigned)ly <= (unsigned)TILE) {
+          const T tx = (T)s.tx, ty = (T)s.ty;
+          const T w00 = (T(1) - tx) * (T(1) - ty), w10 = tx * (T(1) - ty);
+          const T w01 = (T(1) - tx) * ty, w11 = tx * ty;
+          T* c = my + ly * S + lx;
+          atomicAdd(c, gw * w00);
+          atomicAdd(c + 1, gw * w10);
+          atomicAdd(c + S, gw * w01);
+          atomicAdd(c + S + 1, gw * w11);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const int64_t N = (int64_t)g.nx * g.ny;
+  T* __restrict__ out = a.part + grp * N;
+  for (int idx = threadIdx.x; idx < TILE * TILE; idx += 256) {
+    const int i = idx % TILE, j = idx / TILE;
+    const int X = I0 + i, Y = J0 + j;
+    if (X < g.nx && Y < g.ny) {
+      const int l = (j + 1) * S + (i + 1);
+      out[(int64_t)Y * g.nx + X] = ((acc[l] + acc[S * S + l]) + acc[2 * S * S + l]) + acc[3 * S * S + l];
+    }
+  }
+}
+
+template <class T>
+static void adj_dispatch(int tile, int blocks, const AdjArgs<T>& a0, const AdjArgs<T>* arr,
+                         const int* starts, int n, hipStream_t s) {
+  if (blocks <= 0) return;
+  switch (tile) {
+    case 16: hipLaunchKernelGGL((adj_kernel<T, 16>), dim3(blocks), dim3(256), 0, s, a0, arr, starts, n); break;
+    case 64:
+      if constexpr (sizeof(T) == 4) {
+        hipLaunchKernelGGL((adj_kernel<T, 64>), dim3(blocks), dim3(256), 0, s, a0, arr, starts, n);
+        break;
+      }
+      [[fallthrough]];
+    default: hipLaunchKernelGGL((adj_kernel<T, 32>), dim3(blocks), dim3(256), 0, s, a0, arr, starts, n); break;
+  }
+  PAT_HIP(hipGetLastError());
+}
+
+template <class T>
+void launch_adjoint(const AdjArgs<T>& a, hipStream_t s) {
+  const int blocks = a.g.tiles_x * a.g.tiles_y * a.g.n_groups;
+  adj_dispatch<T>(a.g.tile, blocks, a, nullptr, nullptr, 1, s);
+}
+
+template <class T>
+void launch_adjoint_batched(const Launch<T>& L, hipStream_t s) {
+  AdjArgs<T> dummy{};
+  adj_dispatch<T>(L.max_tile, L.adj_total, dummy, ptr<AdjArgs<T>>(L.adj),
+                  ptr<int>(L.adj_start), L.n, s);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void reduce_groups_kernel(const T* __restrict__ part,
+                                                            T* __restrict__ out, int n_groups,
+                                                            int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    T s = T(0);
+    for (int gi = 0; gi < n_groups; ++gi) s += part[gi * n + i];
+    out[i] = s;
+  }
+}
+
+template <class T>
+void launch_reduce_groups(const T* part, T* out, int n_groups, int64_t n, hipStream_t s) {
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(reduce_groups_kernel<T>, dim3(blocks), dim3(256), 0, s, part, out, n_groups, n);
+  PAT_HIP(hipGetLastError());
+}
+
+#define PAT_INST_PROJ(T)                                                                    \
+  template void launch_pad<T>(const T*, T*, int, int, hipStream_t);                         \
+  template void launch_forward<T>(int, const FwdArgs<T>&, int, hipStream_t);                \
+  template void launch_forward_batched<T>(int, const Launch<T>&, int, hipStream_t);        \
+  template void launch_adjoint<T>(const AdjArgs<T>&, hipStream_t);                          \
+  template void launch_adjoint_batched<T>(const Launch<T>&, hipStream_t);                   \
+  template void launch_reduce_groups<T>(const T*, T*, int, int64_t, hipStream_t);
+PAT_INST_PROJ(float)
+PAT_INST_PROJ(double)
+
+}  // namespace pat
+
+// ------------------------------------------------------------------ geometry view + C ABI
+
+pat::GeomDev pat_geometry_s::dev() const {
+  pat::GeomDev g{};
+  g.nx = nx;
+  g.ny = ny;
+  g.n_det = n_det;
+  g.n_t = n_t;
+  g.pitch = nx + 2;
+  g.det = pat::ptr<double2>(d_det);
+  g.rad = pat::ptr<double2>(d_rad);
+  g.moff = pat::ptr<int2>(d_moff);
+  g.cs = pat::ptr<double2>(d_cs);
+  g.win = pat::ptr<int4>(d_win);
+  g.kscale = h / (desc.c * desc.dt);
+  g.koff = desc.t0 / desc.dt;
+  g.lanes_log2 = lanes_log2;
+  g.tile = (dtype == PAT_F64 && tile == 64) ? 32 : tile;
+  g.tiles_x = (nx + g.tile - 1) / g.tile;
+  g.tiles_y = (ny + g.tile - 1) / g.tile;
+  g.det_group = det_group;
+  g.n_groups = n_groups();
+  return g;
+}
+
+namespace {
+
+template <class T>
+void forward_impl(pat_geometry g, const void* d_u, void* d_f, hipStream_t s) {
+  g->scratch_pad.ensure(sizeof(T) * (size_t)(g->nx + 2) * (g->ny + 2));
+  T* upad = pat::ptr<T>(g->scratch_pad);
+  pat::launch_pad<T>(static_cast<const T*>(d_u), upad, g->nx, g->ny, s);
+  pat::FwdArgs<T> a{};
+  a.g = g->dev();
+  a.upad = upad;
+  a.out = static_cast<T*>(d_f);
+  pat::launch_forward<T>(pat::FWD_PLAIN, a, g->lanes_log2, s);
+}
+
+template <class T>
+void adjoint_impl(pat_geometry g, const void* d_f, void* d_u, hipStream_t s) {
+  pat::AdjArgs<T> a{};
+  a.g = g->dev();
+  a.data = static_cast<const T*>(d_f);
+  const int ng = a.g.n_groups;
+  if (ng == 1) {
+    a.part = static_cast<T*>(d_u);
+    pat::launch_adjoint<T>(a, s);
+    return;
+  }
+  g->scratch_part.ensure(sizeof(T) * (size_t)ng * g->n_pix());
+  a.part = pat::ptr<T>(g->scratch_part);
+  pat::launch_adjoint<T>(a, s);
+  pat::launch_reduce_groups<T>(a.part, static_cast<T*>(d_u), ng, g->n_pix(), s);
+}
+
+}  // namespace
+
+extern "C" pat_status pat_forward(pat_geometry g, const void* d_u, void* d_f, void* stream) {
+  return pat::guarded([&]() -> pat_status {
+    PAT_CHECK_ARG(g != nullptr, "geometry is NULL");
+    PAT_CHECK_ARG(d_u != nullptr && d_f != nullptr, "NULL buffer");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (g->dtype == PAT_F64) forward_impl<double>(g, d_u, d_f, s);
+    else forward_impl<float>(g, d_u, d_f, s);
+    return PAT_OK;
+  });
+}
+
+extern "C" pat_status pat_adjoint(pat_geometry g, const void* d_f, void* d_u, void* stream) {
+  return pat::guarded([&]() -> pat_status {
+    PAT_CHECK_ARG(g != nullptr, "geometry is NULL");
+    PAT_CHECK_ARG(d_u != nullptr && d_f != nullptr, "NULL buffer");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (g->dtype == PAT_F64) adjoint_impl<double>(g, d_f, d_u, s);
+    else adjoint_impl<float>(g, d_f, d_u, s);
+    return PAT_OK;
+  });
+}

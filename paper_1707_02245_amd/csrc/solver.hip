@@ -1,0 +1,781 @@
+// Solve driver of preconditioned PDHGM (arXiv:1707.02245, Algorithms 1 and 2)
+// with the step-size rules of Sec. 3.3.2 and the gap stopping rule of
+// Sec. 3.3.3, for one instance or many instances sharing every launch.
+//
+// One iteration is four launches over all active instances:
+//   1. forward gather of ubar with the dual data step fused (q update)
+//   2. regulariser dual step (r, and s for TGV)
+//   3. adjoint scatter of q into per-detector-group partial images
+//   4. primal step (sums the partials, u and v updates, extrapolation)
+// and a check iteration adds: forward gather of u+ with the data and F* terms
+// reduced, the regulariser value reduced, and an ordered final sum per
+// instance. Blocks of iterations are captured once as a HIP graph and
+// replayed; the only device-to-host traffic is the gap sums per block.
+
+#include <chrono>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+
+#include "pat_internal.hpp"
+
+namespace pat {
+
+void validate_regulariser(const pat_geometry_s* g, const pat_regulariser* r) {
+  PAT_CHECK_ARG(r != nullptr, "regulariser is NULL");
+  PAT_CHECK_ARG(r->kind >= PAT_REG_TV && r->kind <= PAT_REG_TIKHONOV, "unknown regulariser kind");
+  PAT_CHECK_ARG(std::isfinite(r->lambda) && r->lambda >= 0.0, "lambda must be finite and >= 0");
+  if (r->kind == PAT_REG_TGV)
+    PAT_CHECK_ARG(std::isfinite(r->tgv_alpha0) && r->tgv_alpha0 >= 0.0,
+                  "tgv_alpha0 must be finite and >= 0");
+  if (r->kind == PAT_REG_DTV) {
+    PAT_CHECK_ARG(std::isfinite(r->dtv_eta) && r->dtv_eta > 0.0 && r->dtv_eta <= 1.0,
+                  "dtv_eta must be in (0, 1]");
+    PAT_CHECK_ARG(r->d_dtv_theta != nullptr, "DTV needs d_dtv_theta");
+  }
+  if (r->kind == PAT_REG_TIKHONOV) PAT_CHECK_ARG(r->lambda > 0.0, "Tikhonov lambda must be > 0");
+  (void)g;
+}
+
+static void validate_opts(const pat_solve_opts* o) {
+  PAT_CHECK_ARG(o != nullptr, "opts is NULL");
+  PAT_CHECK_ARG(o->max_iter > 0, "max_iter must be > 0");
+  PAT_CHECK_ARG(std::isfinite(o->gap_tol), "gap_tol must be finite");
+  PAT_CHECK_ARG(o->gap_every >= 1, "gap_every must be >= 1");
+  PAT_CHECK_ARG(o->graph_block >= 0, "graph_block must be >= 0");
+  PAT_CHECK_ARG(std::isfinite(o->theta) && o->theta >= 0.0 && o->theta <= 1.0,
+                "theta must be in [0, 1]");
+  PAT_CHECK_ARG(std::isfinite(o->gap_box) && o->gap_box > 0.0, "gap_box must be > 0");
+}
+
+// ------------------------------------------------------------------ step sizes
+
+template <class T>
+static void compute_dmat(pat_geometry g, const pat_regulariser* reg, DevBuf& dmat, hipStream_t s) {
+  if (reg->kind != PAT_REG_DTV) return;
+  dmat.ensure(sizeof(T) * 3 * g->n_pix());
+  launch_dmat<T>(static_cast<const T*>(reg->d_dtv_theta), (T)reg->dtv_eta, ptr<T>(dmat), g->n_pix(), s);
+}
+
+template <class T>
+static void apply_A(pat_geometry g, const T* x, T* y, DevBuf& pad, hipStream_t s) {
+  pad.ensure(sizeof(T) * (size_t)(g->nx + 2) * (g->ny + 2));
+  launch_pad<T>(x, ptr<T>(pad), g->nx, g->ny, s);
+  FwdArgs<T> a{};
+  a.g = g->dev();
+  a.upad = ptr<T>(pad);
+  a.out = y;
+  launch_forward<T>(FWD_PLAIN, a, g->lanes_log2, s);
+}
+
+template <class T>
+static void apply_At(pat_geometry g, const T* y, T* x, DevBuf& part, hipStream_t s) {
+  AdjArgs<T> a{};
+  a.g = g->dev();
+  a.data = y;
+  part.ensure(sizeof(T) * (size_t)a.g.n_groups * g->n_pix());
+  a.part = ptr<T>(part);
+  launch_adjoint<T>(a, s);
+  launch_reduce_groups<T>(a.part, x, a.g.n_groups, g->n_pix(), s);
+}
+
+template <class T>
+static void precond_diag(pat_precond_s* pc, const pat_regulariser* reg, const T* dmat, hipStream_t s) {
+  pat_geometry g = pc->g;
+  const int64_t N = g->n_pix(), nb = g->n_bins();
+  DevBuf ones(sizeof(T) * std::max<int64_t>(N, nb)), pad, part, colsum(sizeof(T) * N);
+  launch_fill<T>(ptr<T>(ones), T(1), std::max<int64_t>(N, nb), s);
+  // sigma_q = 1 / (A 1): A >= 0 so this is the absolute row sum
+  pad.ensure(sizeof(T) * (size_t)(g->nx + 2) * (g->ny + 2));
+  launch_pad<T>(ptr<T>(ones), ptr<T>(pad), g->nx, g->ny, s);
+  FwdArgs<T> a{};
+  a.g = g->dev();
+  a.upad = ptr<T>(pad);
+  a.out = ptr<T>(pc->sigma_q);
+  launch_forward<T>(FWD_ROWSUM, a, g->lanes_log2, s);
+  // column sums of A: A^T 1
+  apply_At<T>(g, ptr<T>(ones), ptr<T>(colsum), part, s);
+  launch_precond_pix<T>(reg->kind, g->nx, g->ny, ptr<T>(colsum), dmat, ptr<T>(pc->sigma_r),
+                        ptr<T>(pc->sigma_s), ptr<T>(pc->tau_u), ptr<T>(pc->tau_v), s);
+  PAT_HIP(hipStreamSynchronize(s));
+}
+
+constexpr int kPowerIters = 1000;
+constexpr double kPowerSafety = 1.05;
+
+// ||M|| by power iteration on M^T M from x_j = 1 + (j mod 5)/4 (normalised).
+template <class T, class Apply>
+static double power_norm(int64_t n, hipStream_t s, Apply&& normal_op) {
+  DevBuf x(sizeof(T) * n), y(sizeof(T) * n), part(sizeof(double) * 512), acc(sizeof(double));
+  launch_pattern<T>(ptr<T>(x), n, s);
+  launch_dot<T>(ptr<T>(x), ptr<T>(x), n, ptr<double>(part), 512, ptr<double>(acc), s);
+  launch_scale_copy<T>(ptr<T>(x), ptr<T>(x), ptr<double>(acc), n, s);
+  for (int it = 0; it < kPowerIters; ++it) {
+    normal_op(ptr<T>(x), ptr<T>(y));
+    launch_dot<T>(ptr<T>(y), ptr<T>(y), n, ptr<double>(part), 512, ptr<double>(acc), s);
+    launch_scale_copy<T>(ptr<T>(x), ptr<T>(y), ptr<double>(acc), n, s);
+  }
+  double lam2 = 0.0;
+  PAT_HIP(hipMemcpyAsync(&lam2, acc.p, sizeof(double), hipMemcpyDeviceToHost, s));
+  PAT_HIP(hipStreamSynchronize(s));
+  return std::sqrt(std::sqrt(lam2));  // ||M^T M x|| -> ||M||^2
+}
+
+template <class T>
+static void precond_block(pat_precond_s* pc, const pat_regulariser* reg, const T* dmat, hipStream_t s) {
+  pat_geometry g = pc->g;
+  const int64_t N = g->n_pix(), nb = g->n_bins();
+  DevBuf tmp_b(sizeof(T) * nb), pad, part;
+  const double L1 = kPowerSafety * power_norm<T>(N, s, [&](const T* x, T* y) {
+    apply_A<T>(g, x, ptr<T>(tmp_b), pad, s);
+    apply_At<T>(g, ptr<T>(tmp_b), y, part, s);
+  });
+  double L2 = 0.0;
+  if (reg->kind != PAT_REG_TIKHONOV) {
+    const bool tgv = reg->kind == PAT_REG_TGV;
+    const int64_t nx_ = tgv ? 3 * N : N;
+    DevBuf z(sizeof(T) * (tgv ? 5 : 2) * N);
+    L2 = kPowerSafety * power_norm<T>(nx_, s, [&](const T* x, T* y) {
+      launch_reg_apply<T>(reg->kind, g->nx, g->ny, dmat, x, tgv ? x + N : nullptr, ptr<T>(z), s);
+      launch_reg_apply_t<T>(reg->kind, g->nx, g->ny, dmat, ptr<T>(z), y, tgv ? y + N : nullptr, s);
+    });
+  }
+  pc->L1 = L1;
+  pc->L2 = L2;
+  const double tau = 1.0 / (2.0 * std::max(L1, L2));
+  const double s1 = 0.99 / (4.0 * tau * L1 * L1);
+  const double s2 = L2 > 0.0 ? 0.99 / (4.0 * tau * L2 * L2) : 1.0;
+  launch_fill<T>(ptr<T>(pc->sigma_q), (T)s1, nb, s);
+  launch_fill<T>(ptr<T>(pc->tau_u), (T)tau, N, s);
+  if (pc->sigma_r.p) launch_fill<T>(ptr<T>(pc->sigma_r), (T)s2, N, s);
+  if (pc->sigma_s.p) launch_fill<T>(ptr<T>(pc->sigma_s), (T)s2, N, s);
+  if (pc->tau_v.p) launch_fill<T>(ptr<T>(pc->tau_v), (T)tau, N, s);
+  PAT_HIP(hipStreamSynchronize(s));
+}
+
+static pat_precond_s* make_precond(pat_geometry g, const pat_regulariser* reg, int kind, hipStream_t s) {
+  std::unique_ptr<pat_precond_s> pc(new pat_precond_s());
+  pc->g = g;
+  pc->reg_kind = reg->kind;
+  pc->kind = kind;
+  const size_t es = dtype_size(g->dtype);
+  const int64_t N = g->n_pix();
+  pc->sigma_q.alloc(es * g->n_bins());
+  pc->tau_u.alloc(es * N);
+  if (reg->kind != PAT_REG_TIKHONOV) pc->sigma_r.alloc(es * N);
+  if (reg->kind == PAT_REG_TGV) {
+    pc->sigma_s.alloc(es * N);
+    pc->tau_v.alloc(es * N);
+  }
+  DevBuf dmat;
+  if (g->dtype == PAT_F64) {
+    compute_dmat<double>(g, reg, dmat, s);
+    if (kind == PAT_PRECOND_DIAG) precond_diag<double>(pc.get(), reg, ptr<double>(dmat), s);
+    else precond_block<double>(pc.get(), reg, ptr<double>(dmat), s);
+  } else {
+    compute_dmat<float>(g, reg, dmat, s);
+    if (kind == PAT_PRECOND_DIAG) precond_diag<float>(pc.get(), reg, ptr<float>(dmat), s);
+    else precond_block<float>(pc.get(), reg, ptr<float>(dmat), s);
+  }
+  return pc.release();
+}
+
+// ------------------------------------------------------------------ solver state
+
+int64_t state_elems(const pat_geometry_s* g, int kind) {
+  const int64_t N = g->n_pix(), nb = g->n_bins();
+  int64_t n = 2 * N + nb;
+  if (kind != PAT_REG_TIKHONOV) n += 2 * N;
+  if (kind == PAT_REG_TGV) n += 7 * N;
+  return n;
+}
+
+template <class T>
+struct Inst {
+  pat_geometry g = nullptr;
+  pat_regulariser reg{};
+  pat_solve_opts opts{};
+  const T* f = nullptr;
+  T* u_out = nullptr;
+  pat_solve_info* info = nullptr;
+  DevBuf u, ubar_pad, q, r, v, vbar, s, upad_gap, atq_part, red, dmat;
+  pat_precond_s* pc = nullptr;
+  std::unique_ptr<pat_precond_s> own_pc;
+  int n_fwd = 0, n_pix = 0, n_adj = 0, red_stride = 0;
+  int iters = 0;
+  bool active = true, converged = false;
+  int fallback = 0;
+  pat_status status = PAT_NOT_CONVERGED;
+  double last[GAP_NSLOTS] = {0, 0, 0, 0, 0, 0};
+  double rel_gap = INFINITY, gap = INFINITY, primal = 0, fstar = 0, kty = 0, residual = 0;
+
+  GeomDev gdev(int lanes_log2, int tile) const {
+    GeomDev d = g->dev();
+    d.lanes_log2 = lanes_log2;
+    d.tile = tile;
+    d.tiles_x = (g->nx + tile - 1) / tile;
+    d.tiles_y = (g->ny + tile - 1) / tile;
+    return d;
+  }
+};
+
+template <class T>
+class Solver {
+ public:
+  std::vector<std::unique_ptr<Inst<T>>> inst;
+  std::vector<int> act;  // indices of active instances
+  Launch<T> L;
+  hipStream_t s = nullptr;
+  int gap_every = 10, graph_block = 50;
+  int lanes_log2 = 6, tile = 32;
+  DevBuf results;        // [max_checks][n_active][GAP_NSLOTS]
+  double* h_results = nullptr;
+  int max_checks = 0;
+  std::map<std::string, hipGraphExec_t> graphs;
+
+  ~Solver() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    if (h_results) (void)hipHostFree(h_results);
+  }
+
+  void setup(hipStream_t stream) {
+    s = stream;
+    lanes_log2 = inst[0]->g->lanes_log2;
+    tile = inst[0]->g->tile;
+    if (sizeof(T) == 8 && tile == 64) tile = 32;
+    for (auto& ip : inst) alloc_instance(*ip);
+    act.clear();
+    for (size_t i = 0; i < inst.size(); ++i) act.push_back((int)i);
+    const int per_block = graph_block > 0 ? graph_block : 1;
+    max_checks = per_block / gap_every + 2;
+    results.alloc(sizeof(double) * max_checks * inst.size() * GAP_NSLOTS);
+    PAT_HIP(hipHostMalloc((void**)&h_results, sizeof(double) * max_checks * inst.size() * GAP_NSLOTS,
+                          hipHostMallocDefault));
+  }
+
+  void alloc_instance(Inst<T>& I) {
+    pat_geometry g = I.g;
+    const int64_t N = g->n_pix(), nb = g->n_bins();
+    const size_t P = (size_t)(g->nx + 2) * (g->ny + 2);
+    const int kind = I.reg.kind;
+    I.u.alloc(sizeof(T) * N);
+    I.ubar_pad.alloc(sizeof(T) * P);
+    I.upad_gap.alloc(sizeof(T) * P);
+    I.q.alloc(sizeof(T) * nb);
+    if (kind != PAT_REG_TIKHONOV) I.r.alloc(sizeof(T) * 2 * N);
+    if (kind == PAT_REG_TGV) {
+      I.v.alloc(sizeof(T) * 2 * N);
+      I.vbar.alloc(sizeof(T) * 2 * N);
+      I.s.alloc(sizeof(T) * 3 * N);
+    }
+    const GeomDev gd = I.gdev(lanes_log2, tile);
+    I.atq_part.alloc(sizeof(T) * gd.n_groups * N);
+    const int bpb = 256 >> lanes_log2;
+    I.n_fwd = (int)((nb + bpb - 1) / bpb);
+    I.n_pix = pix_blocks(N);
+    I.n_adj = gd.tiles_x * gd.tiles_y * gd.n_groups;
+    I.red_stride = std::max(I.n_fwd, I.n_pix);
+    I.red.alloc(sizeof(double) * GAP_NSLOTS * I.red_stride);
+    compute_dmat<T>(g, &I.reg, I.dmat, s);
+    if (I.opts.precond) {
+      PAT_CHECK_ARG(I.opts.precond->g == g && I.opts.precond->reg_kind == kind,
+                    "precond handle was made for another geometry or regulariser");
+      I.pc = I.opts.precond;
+    } else {
+      I.own_pc.reset(make_precond(g, &I.reg, PAT_PRECOND_DIAG, s));
+      I.pc = I.own_pc.get();
+    }
+  }
+
+  InstDev<T> inst_dev(const Inst<T>& I) const {
+    InstDev<T> d{};
+    const GeomDev gd = I.gdev(lanes_log2, tile);
+    d.nx = I.g->nx;
+    d.ny = I.g->ny;
+    d.n_groups = gd.n_groups;
+    d.n_bins = (int)I.g->n_bins();
+    d.kind = I.reg.kind;
+    d.lam = (T)I.reg.lambda;
+    d.alpha0 = (T)I.reg.tgv_alpha0;
+    d.theta_ex = (T)I.opts.theta;
+    d.dmat = ptr<T>(I.dmat);
+    d.u = ptr<T>(I.u);
+    d.ubar_pad = ptr<T>(I.ubar_pad);
+    d.r = ptr<T>(I.r);
+    d.v = ptr<T>(I.v);
+    d.vbar = ptr<T>(I.vbar);
+    d.s = ptr<T>(I.s);
+    d.sigma_r = ptr<T>(I.pc->sigma_r);
+    d.sigma_s = ptr<T>(I.pc->sigma_s);
+    d.tau_u = ptr<T>(I.pc->tau_u);
+    d.tau_v = ptr<T>(I.pc->tau_v);
+    d.atq_part = ptr<T>(I.atq_part);
+    d.upad_gap = ptr<T>(I.upad_gap);
+    d.red = ptr<double>(I.red);
+    d.red_stride = I.red_stride;
+    return d;
+  }
+
+  // Upload the launch tables of the active instances.
+  void build_launch() {
+    const int n = (int)act.size();
+    std::vector<FwdArgs<T>> fd(n), fg(n);
+    std::vector<AdjArgs<T>> ad(n);
+    std::vector<InstDev<T>> id(n);
+    std::vector<GapFinishArgs> gf(n);
+    std::vector<int> fs(n + 1), as(n + 1), ps(n + 1);
+    fs[0] = as[0] = ps[0] = 0;
+    for (int k = 0; k < n; ++k) {
+      const Inst<T>& I = *inst[act[k]];
+      const GeomDev gd = I.gdev(lanes_log2, tile);
+      fd[k] = FwdArgs<T>{};
+      fd[k].g = gd;
+      fd[k].upad = ptr<T>(I.ubar_pad);
+      fd[k].out = ptr<T>(I.q);
+      fd[k].f = I.f;
+      fd[k].sigma = ptr<T>(I.pc->sigma_q);
+      fg[k] = FwdArgs<T>{};
+      fg[k].g = gd;
+      fg[k].upad = ptr<T>(I.upad_gap);
+      fg[k].f = I.f;
+      fg[k].q = ptr<T>(I.q);
+      fg[k].red = ptr<double>(I.red);
+      fg[k].red_stride = I.red_stride;
+      ad[k] = AdjArgs<T>{};
+      ad[k].g = gd;
+      ad[k].data = ptr<T>(I.q);
+      ad[k].part = ptr<T>(I.atq_part);
+      id[k] = inst_dev(I);
+      gf[k] = GapFinishArgs{ptr<double>(I.red), I.red_stride, I.n_fwd, I.n_pix};
+      fs[k + 1] = fs[k] + I.n_fwd;
+      as[k + 1] = as[k] + I.n_adj;
+      ps[k + 1] = ps[k] + I.n_pix;
+    }
+    auto up = [&](DevBuf& b, const void* src, size_t bytes) {
+      b.ensure(bytes);
+      PAT_HIP(hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, s));
+    };
+    up(L.fwd, fd.data(), sizeof(FwdArgs<T>) * n);
+    up(L.fwd_gap, fg.data(), sizeof(FwdArgs<T>) * n);
+    up(L.adj, ad.data(), sizeof(AdjArgs<T>) * n);
+    up(L.inst, id.data(), sizeof(InstDev<T>) * n);
+    up(L.gapfin, gf.data(), sizeof(GapFinishArgs) * n);
+    up(L.fwd_start, fs.data(), sizeof(int) * (n + 1));
+    up(L.adj_start, as.data(), sizeof(int) * (n + 1));
+    up(L.pix_start, ps.data(), sizeof(int) * (n + 1));
+    PAT_HIP(hipStreamSynchronize(s));  // host vectors go out of scope
+    L.n = n;
+    L.fwd_total = fs[n];
+    L.adj_total = as[n];
+    L.pix_total = ps[n];
+    L.lanes_log2 = lanes_log2;
+    L.max_tile = tile;
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+  }
+
+  // gap evaluation at the current (u, v, q, r, s) into results slot c
+  void enqueue_gap(int c) {
+    // the gap forward uses the second FwdArgs table (input u+, gap epilogue)
+    std::swap(L.fwd, L.fwd_gap);
+    launch_forward_batched<T>(FWD_GAP, L, lanes_log2, s);
+    std::swap(L.fwd, L.fwd_gap);
+    launch_gap_reg<T>(L, s);
+    launch_gap_finish(ptr<GapFinishArgs>(L.gapfin), L.n,
+                      ptr<double>(results) + (size_t)c * L.n * GAP_NSLOTS, s);
+  }
+
+  void enqueue_iteration(bool check, int c) {
+    launch_forward_batched<T>(FWD_DUAL, L, lanes_log2, s);
+    launch_reg_dual<T>(L, s);
+    launch_adjoint_batched<T>(L, s);
+    launch_primal<T>(L, check, s);
+    if (check) enqueue_gap(c);
+  }
+
+  void init_state() {
+    for (int k : act) {
+      Inst<T>& I = *inst[k];
+      pat_geometry g = I.g;
+      const int64_t N = g->n_pix(), nb = g->n_bins();
+      const size_t P = (size_t)(g->nx + 2) * (g->ny + 2);
+      PAT_HIP(hipMemsetAsync(I.u.p, 0, sizeof(T) * N, s));
+      PAT_HIP(hipMemsetAsync(I.ubar_pad.p, 0, sizeof(T) * P, s));
+      PAT_HIP(hipMemsetAsync(I.upad_gap.p, 0, sizeof(T) * P, s));
+      PAT_HIP(hipMemsetAsync(I.q.p, 0, sizeof(T) * nb, s));
+      if (I.r.p) PAT_HIP(hipMemsetAsync(I.r.p, 0, I.r.bytes, s));
+      if (I.v.p) PAT_HIP(hipMemsetAsync(I.v.p, 0, I.v.bytes, s));
+      if (I.vbar.p) PAT_HIP(hipMemsetAsync(I.vbar.p, 0, I.vbar.bytes, s));
+      if (I.s.p) PAT_HIP(hipMemsetAsync(I.s.p, 0, I.s.bytes, s));
+      if (I.opts.d_state_in) {
+        const T* st = static_cast<const T*>(I.opts.d_state_in);
+        PAT_HIP(hipMemcpyAsync(I.u.p, st, sizeof(T) * N, hipMemcpyDeviceToDevice, s));
+        launch_pad<T>(st + N, ptr<T>(I.ubar_pad), g->nx, g->ny, s);
+        int64_t o = 2 * N;
+        PAT_HIP(hipMemcpyAsync(I.q.p, st + o, sizeof(T) * nb, hipMemcpyDeviceToDevice, s));
+        o += nb;
+        if (I.r.p) {
+          PAT_HIP(hipMemcpyAsync(I.r.p, st + o, sizeof(T) * 2 * N, hipMemcpyDeviceToDevice, s));
+          o += 2 * N;
+        }
+        if (I.reg.kind == PAT_REG_TGV) {
+          PAT_HIP(hipMemcpyAsync(I.v.p, st + o, sizeof(T) * 2 * N, hipMemcpyDeviceToDevice, s));
+          PAT_HIP(hipMemcpyAsync(I.vbar.p, st + o + 2 * N, sizeof(T) * 2 * N, hipMemcpyDeviceToDevice, s));
+          PAT_HIP(hipMemcpyAsync(I.s.p, st + o + 4 * N, sizeof(T) * 3 * N, hipMemcpyDeviceToDevice, s));
+        }
+      }
+    }
+    // warm starts: accept only finite u0 with P(u0) <= P(0) = 1/2 ||f||^2
+    bool any_u0 = false;
+    for (int k : act) any_u0 |= (inst[k]->opts.d_u0 != nullptr && !inst[k]->opts.d_state_in);
+    if (!any_u0) return;
+    for (int k : act) {
+      Inst<T>& I = *inst[k];
+      if (!I.opts.d_u0 || I.opts.d_state_in) continue;
+      PAT_HIP(hipMemcpyAsync(I.u.p, I.opts.d_u0, sizeof(T) * I.g->n_pix(), hipMemcpyDeviceToDevice, s));
+      launch_pad<T>(ptr<T>(I.u), ptr<T>(I.upad_gap), I.g->nx, I.g->ny, s);
+    }
+    enqueue_gap(0);
+    read_results(1);
+    DevBuf part(sizeof(double) * 512), acc(sizeof(double));
+    for (size_t a = 0; a < act.size(); ++a) {
+      Inst<T>& I = *inst[act[a]];
+      if (!I.opts.d_u0 || I.opts.d_state_in) continue;
+      const double* r = h_results + a * GAP_NSLOTS;
+      const double P0 = r[GAP_DATA] + r[GAP_REG];
+      launch_dot<T>(I.f, I.f, I.g->n_bins(), ptr<double>(part), 512, ptr<double>(acc), s);
+      double ff = 0.0;
+      PAT_HIP(hipMemcpyAsync(&ff, acc.p, sizeof(double), hipMemcpyDeviceToHost, s));
+      PAT_HIP(hipStreamSynchronize(s));
+      if (!std::isfinite(P0) || P0 > 0.5 * ff) {
+        I.fallback = 1;
+        PAT_HIP(hipMemsetAsync(I.u.p, 0, I.u.bytes, s));
+      } else {
+        launch_pad<T>(ptr<T>(I.u), ptr<T>(I.ubar_pad), I.g->nx, I.g->ny, s);
+      }
+    }
+    PAT_HIP(hipStreamSynchronize(s));
+  }
+
+  void read_results(int n_checks) {
+    const size_t bytes = sizeof(double) * (size_t)n_checks * L.n * GAP_NSLOTS;
+    PAT_HIP(hipMemcpyAsync(h_results, results.p, bytes, hipMemcpyDeviceToHost, s));
+    PAT_HIP(hipStreamSynchronize(s));
+  }
+
+  // Evaluate check c for the active instance at position a.
+  pat_status evaluate(int c, int a, int n_done) {
+    Inst<T>& I = *inst[act[a]];
+    const double* r = h_results + ((size_t)c * L.n + a) * GAP_NSLOTS;
+    const double P = r[GAP_DATA] + r[GAP_REG];
+    const double Fs = r[GAP_FSTAR];
+    double gap;
+    if (I.reg.kind == PAT_REG_TIKHONOV) gap = P + Fs + r[GAP_KTY] / (2.0 * I.reg.lambda);
+    else gap = P + Fs + I.opts.gap_box * r[GAP_KTY];
+    I.primal = P;
+    I.fstar = Fs;
+    I.kty = r[GAP_KTY];
+    I.gap = gap;
+    I.rel_gap = P > 0.0 ? gap / P : (gap == 0.0 ? 0.0 : INFINITY);
+    I.residual = r[GAP_U2] > 0.0 ? std::sqrt(r[GAP_DU2] / r[GAP_U2]) : INFINITY;
+    I.iters = n_done;
+    if (!std::isfinite(gap)) {
+      set_error("non-finite primal-dual gap at iteration %d", n_done);
+      return PAT_ERR_NUMERIC;
+    }
+    return PAT_OK;
+  }
+
+  hipGraphExec_t graph_for(int steps, const std::vector<int>& checks) {
+    std::string key = std::to_string(steps);
+    for (int c : checks) key += "," + std::to_string(c);
+    auto it = graphs.find(key);
+    if (it != graphs.end()) return it->second;
+    hipGraph_t graph;
+    PAT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    try {
+      run_direct(steps, checks);
+    } catch (...) {
+      hipGraph_t tmp;
+      (void)hipStreamEndCapture(s, &tmp);
+      if (tmp) (void)hipGraphDestroy(tmp);
+      throw;
+    }
+    PAT_HIP(hipStreamEndCapture(s, &graph));
+    hipGraphExec_t exec;
+    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    PAT_HIP(e);
+    graphs[key] = exec;
+    return exec;
+  }
+
+  void run_direct(int steps, const std::vector<int>& checks) {
+    size_t c = 0;
+    for (int t = 0; t < steps; ++t) {
+      const bool chk = c < checks.size() && checks[c] == t;
+      enqueue_iteration(chk, (int)c);
+      if (chk) ++c;
+    }
+  }
+
+  // Run all instances to convergence or their caps.
+  pat_status run(double* seconds) {
+    int n_done = 0;
+    hipEvent_t e0, e1;
+    PAT_HIP(hipEventCreate(&e0));
+    PAT_HIP(hipEventCreate(&e1));
+    PAT_HIP(hipEventRecord(e0, s));
+    pat_status worst = PAT_OK;
+    int max_cap = 0;
+    for (auto& ip : inst) max_cap = std::max(max_cap, ip->opts.max_iter);
+    while (!act.empty()) {
+      int cap = max_cap;
+      for (int k : act) cap = std::min(cap, inst[k]->opts.max_iter);
+      const int block = graph_block > 0 ? graph_block : gap_every;
+      const int steps = std::min(block, cap - n_done);
+      std::vector<int> checks;
+      for (int t = 0; t < steps; ++t) {
+        const int n = n_done + t + 1;
+        if (n % gap_every == 0 || n == cap || t == steps - 1) checks.push_back(t);
+      }
+      if (graph_block > 0) {
+        PAT_HIP(hipGraphLaunch(graph_for(steps, checks), s));
+      } else {
+        run_direct(steps, checks);
+      }
+      n_done += steps;
+      read_results((int)checks.size());
+      // decide on the last check of the block
+      const int c = (int)checks.size() - 1;
+      std::vector<int> keep;
+      for (size_t a = 0; a < act.size(); ++a) {
+        Inst<T>& I = *inst[act[a]];
+        const pat_status st = evaluate(c, (int)a, n_done);
+        if (st != PAT_OK) {
+          I.status = st;
+          I.active = false;
+          worst = st;
+          continue;
+        }
+        if (I.opts.gap_tol > 0.0 && I.rel_gap <= I.opts.gap_tol) {
+          I.converged = true;
+          I.status = PAT_OK;
+          I.active = false;
+        } else if (n_done >= I.opts.max_iter) {
+          I.status = I.opts.gap_tol > 0.0 ? PAT_NOT_CONVERGED : PAT_OK;
+          I.converged = false;
+          I.active = false;
+        } else {
+          keep.push_back(act[a]);
+        }
+        if (!I.active) finish_instance(I);
+      }
+      if (keep.size() != act.size()) {
+        act = keep;
+        if (!act.empty()) build_launch();
+      }
+    }
+    PAT_HIP(hipEventRecord(e1, s));
+    PAT_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    PAT_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *seconds = ms * 1e-3;
+    for (auto& ip : inst) {
+      if (ip->status < 0) return ip->status;
+      if (ip->status == PAT_NOT_CONVERGED) worst = worst == PAT_OK ? PAT_NOT_CONVERGED : worst;
+    }
+    return worst;
+  }
+
+  void finish_instance(Inst<T>& I) {
+    pat_geometry g = I.g;
+    const int64_t N = g->n_pix(), nb = g->n_bins();
+    if (I.status >= 0) {
+      PAT_HIP(hipMemcpyAsync(I.u_out, I.u.p, sizeof(T) * N, hipMemcpyDeviceToDevice, s));
+      if (I.opts.d_state_out) {
+        T* st = static_cast<T*>(I.opts.d_state_out);
+        PAT_HIP(hipMemcpyAsync(st, I.u.p, sizeof(T) * N, hipMemcpyDeviceToDevice, s));
+        const int P = g->nx + 2;
+        PAT_HIP(hipMemcpy2DAsync(st + N, sizeof(T) * g->nx, ptr<T>(I.ubar_pad) + P + 1, sizeof(T) * P,
+                                 sizeof(T) * g->nx, g->ny, hipMemcpyDeviceToDevice, s));
+        int64_t o = 2 * N;
+        PAT_HIP(hipMemcpyAsync(st + o, I.q.p, sizeof(T) * nb, hipMemcpyDeviceToDevice, s));
+        o += nb;
+        if (I.r.p) {
+          PAT_HIP(hipMemcpyAsync(st + o, I.r.p, sizeof(T) * 2 * N, hipMemcpyDeviceToDevice, s));
+          o += 2 * N;
+        }
+        if (I.reg.kind == PAT_REG_TGV) {
+          PAT_HIP(hipMemcpyAsync(st + o, I.v.p, sizeof(T) * 2 * N, hipMemcpyDeviceToDevice, s));
+          PAT_HIP(hipMemcpyAsync(st + o + 2 * N, I.vbar.p, sizeof(T) * 2 * N, hipMemcpyDeviceToDevice, s));
+          PAT_HIP(hipMemcpyAsync(st + o + 4 * N, I.s.p, sizeof(T) * 3 * N, hipMemcpyDeviceToDevice, s));
+        }
+      }
+    }
+    if (I.info) {
+      I.info->iters = I.iters;
+      I.info->converged = I.converged ? 1 : 0;
+      I.info->fallback = I.fallback;
+      I.info->rel_gap = I.rel_gap;
+      I.info->gap = I.gap;
+      I.info->primal = I.primal;
+      I.info->fstar = I.fstar;
+      I.info->kty_l1 = I.kty;
+      I.info->residual = I.residual;
+    }
+  }
+};
+
+// The library stream: a caller's NULL stream cannot be captured into a graph,
+// so solves on NULL run on a blocking stream of the library (ordered with NULL).
+static hipStream_t solve_stream(void* user, hipStream_t* owned) {
+  *owned = nullptr;
+  if (user) return static_cast<hipStream_t>(user);
+  PAT_HIP(hipStreamCreate(owned));
+  return *owned;
+}
+
+template <class T>
+static pat_status solve_impl(int n, const pat_geometry* g, const void* const* d_f,
+                             const pat_regulariser* reg, const pat_solve_opts* opts,
+                             void* const* d_u_out, pat_solve_info* info, void* stream) {
+  hipStream_t owned = nullptr;
+  hipStream_t s = solve_stream(stream, &owned);
+  struct StreamGuard {
+    hipStream_t h;
+    ~StreamGuard() {
+      if (h) { (void)hipStreamSynchronize(h); (void)hipStreamDestroy(h); }
+    }
+  } guard{owned};
+  Solver<T> S;
+  S.gap_every = opts[0].gap_every;
+  S.graph_block = opts[0].graph_block;
+  if (S.graph_block > 0 && S.graph_block % S.gap_every != 0)
+    S.graph_block = ((S.graph_block + S.gap_every - 1) / S.gap_every) * S.gap_every;
+  for (int i = 0; i < n; ++i) {
+    auto I = std::make_unique<Inst<T>>();
+    I->g = g[i];
+    I->reg = reg[i];
+    I->opts = opts[i];
+    I->f = static_cast<const T*>(d_f[i]);
+    I->u_out = static_cast<T*>(d_u_out[i]);
+    I->info = info ? &info[i] : nullptr;
+    S.inst.push_back(std::move(I));
+  }
+  S.setup(s);
+  S.build_launch();
+  S.init_state();
+  double secs = 0.0;
+  const pat_status st = S.run(&secs);
+  PAT_HIP(hipStreamSynchronize(s));
+  if (info)
+    for (int i = 0; i < n; ++i) info[i].seconds = secs;
+  return st;
+}
+
+static void validate_instance(pat_geometry g, const void* f, const pat_regulariser* reg,
+                              const pat_solve_opts* o, void* u) {
+  PAT_CHECK_ARG(g != nullptr, "geometry is NULL");
+  PAT_CHECK_ARG(f != nullptr && u != nullptr, "NULL data or output buffer");
+  validate_regulariser(g, reg);
+  validate_opts(o);
+  if (o->precond)
+    PAT_CHECK_ARG(o->precond->g == g && o->precond->reg_kind == reg->kind,
+                  "precond handle was made for another geometry or regulariser");
+}
+
+}  // namespace pat
+
+using pat::guarded;
+
+extern "C" pat_status pat_precond(pat_geometry g, const pat_regulariser* reg, int32_t kind,
+                                  void* stream, pat_precond_h* out) {
+  return guarded([&]() -> pat_status {
+    PAT_CHECK_ARG(g != nullptr && out != nullptr, "NULL argument");
+    pat::validate_regulariser(g, reg);
+    PAT_CHECK_ARG(kind == PAT_PRECOND_DIAG || kind == PAT_PRECOND_BLOCK, "unknown precond kind");
+    hipStream_t owned = nullptr;
+    hipStream_t s = pat::solve_stream(stream, &owned);
+    pat_status st = PAT_OK;
+    try {
+      *out = pat::make_precond(g, reg, kind, s);
+    } catch (...) {
+      if (owned) (void)hipStreamDestroy(owned);
+      throw;
+    }
+    if (owned) (void)hipStreamDestroy(owned);
+    return st;
+  });
+}
+
+extern "C" pat_status pat_precond_get(pat_precond_h p, int32_t which, void* d_dst, void* stream) {
+  return guarded([&]() -> pat_status {
+    PAT_CHECK_ARG(p != nullptr && d_dst != nullptr, "NULL argument");
+    const pat::DevBuf* b = nullptr;
+    switch (which) {
+      case 0: b = &p->sigma_q; break;
+      case 1: b = &p->sigma_r; break;
+      case 2: b = &p->sigma_s; break;
+      case 3: b = &p->tau_u; break;
+      case 4: b = &p->tau_v; break;
+      default: break;
+    }
+    PAT_CHECK_ARG(b != nullptr && b->p != nullptr, "step-size array not present for this regulariser");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (which == 4) {
+      // both components of v share one step size: export [2][N]
+      PAT_HIP(hipMemcpyAsync(d_dst, b->p, b->bytes, hipMemcpyDeviceToDevice, s));
+      PAT_HIP(hipMemcpyAsync(static_cast<char*>(d_dst) + b->bytes, b->p, b->bytes,
+                             hipMemcpyDeviceToDevice, s));
+    } else {
+      PAT_HIP(hipMemcpyAsync(d_dst, b->p, b->bytes, hipMemcpyDeviceToDevice, s));
+    }
+    return PAT_OK;
+  });
+}
+
+extern "C" pat_status pat_precond_destroy(pat_precond_h p) {
+  return guarded([&]() -> pat_status {
+    delete p;
+    return PAT_OK;
+  });
+}
+
+extern "C" pat_status pat_state_elems(pat_geometry g, int32_t reg_kind, int64_t* out) {
+  return guarded([&]() -> pat_status {
+    PAT_CHECK_ARG(g != nullptr && out != nullptr, "NULL argument");
+    PAT_CHECK_ARG(reg_kind >= PAT_REG_TV && reg_kind <= PAT_REG_TIKHONOV, "unknown regulariser kind");
+    *out = pat::state_elems(g, reg_kind);
+    return PAT_OK;
+  });
+}
+
+extern "C" pat_status pat_pdhg_solve(pat_geometry g, const void* d_f, const pat_regulariser* reg,
+                                     const pat_solve_opts* opts, void* d_u_out,
+                                     pat_solve_info* info, void* stream) {
+  return guarded([&]() -> pat_status {
+    pat::validate_instance(g, d_f, reg, opts, d_u_out);
+    if (g->dtype == PAT_F64)
+      return pat::solve_impl<double>(1, &g, &d_f, reg, opts, &d_u_out, info, stream);
+    return pat::solve_impl<float>(1, &g, &d_f, reg, opts, &d_u_out, info, stream);
+  });
+}
+
+extern "C" pat_status pat_pdhg_solve_batched(int32_t n, const pat_geometry* g, const void* const* d_f,
+                                             const pat_regulariser* reg, const pat_solve_opts* opts,
+                                             void* const* d_u_out, pat_solve_info* info,
+                                             void* stream) {
+  return guarded([&]() -> pat_status {
+    PAT_CHECK_ARG(n >= 1, "n must be >= 1");
+    PAT_CHECK_ARG(g && d_f && reg && opts && d_u_out, "NULL array");
+    for (int i = 0; i < n; ++i) {
+      pat::validate_instance(g[i], d_f[i], &reg[i], &opts[i], d_u_out[i]);
+      PAT_CHECK_ARG(g[i]->dtype == PAT_F32, "batched solves take FP32 geometries");
+    }
+    return pat::solve_impl<float>(n, g, d_f, reg, opts, d_u_out, info, stream);
+  });
+}

@@ -1,0 +1,251 @@
+"""Python binding of libpat (same names as the C ABI; marshalling only).
+
+Every step of the computation runs in the HIP kernels behind include/pat.h.
+PyTorch tensors serve only as device memory and as the source of the current
+HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+_DT = {torch.float32: L.PAT_F32, torch.float64: L.PAT_F64}
+_KIND = {"tv": L.PAT_REG_TV, "tgv": L.PAT_REG_TGV, "dtv": L.PAT_REG_DTV,
+         "tikhonov": L.PAT_REG_TIKHONOV, "lst": L.PAT_REG_TIKHONOV}
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _need(t, dtype, numel, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() != numel:
+        raise ValueError(f"{name}: expected contiguous {dtype} with {numel} elements, "
+                         f"got {t.dtype} {tuple(t.shape)}")
+
+
+def make_desc(nx, ny=None, x_min=-1.0, x_max=1.0, y_min=None, y_max=None, n_det=1,
+              det_cx=0.0, det_cy=0.0, det_radius=1.2, arc_center=0.0, arc_span=2 * math.pi,
+              det_xy=None, n_t=2, t0=0.0, dt=1.0, c=1.0, samples_per_pixel=1.0):
+    """pat_geometry_desc from keyword arguments (det_xy: host float64 [n_det][2])."""
+    ny = nx if ny is None else ny
+    y_min = x_min if y_min is None else y_min
+    y_max = x_max if y_max is None else y_max
+    d = L.GeometryDesc()
+    d.nx, d.ny = nx, ny
+    d.x_min, d.x_max, d.y_min, d.y_max = x_min, x_max, y_min, y_max
+    d.n_det = n_det
+    d.det_cx, d.det_cy, d.det_radius = det_cx, det_cy, det_radius
+    d.arc_center, d.arc_span = arc_center, arc_span
+    keep = None
+    if det_xy is not None:
+        import numpy as np
+        keep = np.ascontiguousarray(np.asarray(det_xy, dtype=np.float64).reshape(-1, 2))
+        d.n_det = keep.shape[0]
+        d.det_xy = keep.ctypes.data_as(C.POINTER(C.c_double))
+    d.n_t, d.t0, d.dt, d.c = n_t, t0, dt, c
+    d.samples_per_pixel = samples_per_pixel
+    return d, keep
+
+
+class Geometry:
+    """pat_geometry handle: acquisition geometry plus device tables."""
+
+    def __init__(self, dtype=torch.float32, **desc):
+        lib = L.load()
+        self.dtype = dtype
+        d, keep = make_desc(**desc)
+        self._desc = d
+        h = C.c_void_p()
+        L.check(lib.pat_geometry_create(C.byref(d), _DT[dtype], _stream(), C.byref(h)))
+        del keep
+        self._h = h
+        info = L.GeometryInfo()
+        L.check(lib.pat_geometry_get_info(h, C.byref(info)))
+        self.info = {k: getattr(info, k) for k, _ in info._fields_}
+        self.nx, self.ny = info.nx, info.ny
+        self.n_det, self.n_t = info.n_det, info.n_t
+
+    @property
+    def handle(self):
+        return self._h
+
+    def refresh_info(self):
+        info = L.GeometryInfo()
+        L.check(L.load().pat_geometry_get_info(self._h, C.byref(info)))
+        self.info = {k: getattr(info, k) for k, _ in info._fields_}
+        return self.info
+
+    def set_launch(self, lanes_log2, tile, det_group):
+        L.check(L.load().pat_geometry_set_launch(self._h, lanes_log2, tile, det_group))
+        return self.refresh_info()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.load().pat_geometry_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def image(self, fill=0.0):
+        return torch.full((self.ny, self.nx), fill, dtype=self.dtype, device="cuda")
+
+    def data(self, fill=0.0):
+        return torch.full((self.n_det, self.n_t), fill, dtype=self.dtype, device="cuda")
+
+    def forward(self, u, out=None):
+        """f = A u (pat_forward)."""
+        _need(u, self.dtype, self.nx * self.ny, "u")
+        out = self.data() if out is None else out
+        _need(out, self.dtype, self.n_det * self.n_t, "out")
+        L.check(L.load().pat_forward(self._h, _ptr(u), _ptr(out), _stream()))
+        return out
+
+    def adjoint(self, f, out=None):
+        """u = A^T f (pat_adjoint)."""
+        _need(f, self.dtype, self.n_det * self.n_t, "f")
+        out = self.image() if out is None else out
+        _need(out, self.dtype, self.nx * self.ny, "out")
+        L.check(L.load().pat_adjoint(self._h, _ptr(f), _ptr(out), _stream()))
+        return out
+
+    def state_elems(self, kind):
+        n = C.c_int64()
+        L.check(L.load().pat_state_elems(self._h, _KIND[kind], C.byref(n)))
+        return n.value
+
+
+@dataclass
+class Reg:
+    """Regulariser: kind in tv | tgv | dtv | tikhonov."""
+    kind: str
+    lam: float
+    alpha0: float = 0.0
+    eta: float = 1.0
+    theta: torch.Tensor | None = None
+
+    def c_struct(self):
+        r = L.Regulariser()
+        r.kind = _KIND[self.kind]
+        r.lam, r.tgv_alpha0, r.dtv_eta = self.lam, self.alpha0, self.eta
+        r.d_dtv_theta = self.theta.data_ptr() if self.theta is not None else None
+        return r
+
+
+class Precond:
+    """pat_precond_h: step sizes of one (geometry, regulariser) pair."""
+
+    def __init__(self, geom: Geometry, reg: Reg, kind="diag"):
+        self.geom = geom
+        self.reg = reg
+        r = reg.c_struct()
+        h = C.c_void_p()
+        k = L.PAT_PRECOND_DIAG if kind == "diag" else L.PAT_PRECOND_BLOCK
+        L.check(L.load().pat_precond(geom.handle, C.byref(r), k, _stream(), C.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def get(self, which):
+        """which: sigma_q | sigma_r | sigma_s | tau_u | tau_v."""
+        idx = ["sigma_q", "sigma_r", "sigma_s", "tau_u", "tau_v"].index(which)
+        g = self.geom
+        n = {0: g.n_det * g.n_t, 4: 2 * g.nx * g.ny}.get(idx, g.nx * g.ny)
+        out = torch.empty(n, dtype=g.dtype, device="cuda")
+        L.check(L.load().pat_precond_get(self._h, idx, _ptr(out), _stream()))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.load().pat_precond_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _opts(max_iter, gap_tol, gap_every, graph_block, theta, gap_box, u0, state_in,
+          state_out, precond):
+    o = L.SolveOpts()
+    o.max_iter, o.gap_tol, o.gap_every, o.graph_block = max_iter, gap_tol, gap_every, graph_block
+    o.theta, o.gap_box = theta, gap_box
+    o.d_u0 = u0.data_ptr() if u0 is not None else None
+    o.d_state_in = state_in.data_ptr() if state_in is not None else None
+    o.d_state_out = state_out.data_ptr() if state_out is not None else None
+    o.precond = precond.handle.value if precond is not None else None
+    return o
+
+
+def solve(geom: Geometry, f, reg: Reg, max_iter=2000, gap_tol=1e-4, gap_every=10,
+          graph_block=50, theta=1.0, gap_box=2.0, u0=None, state_in=None, state_out=None,
+          precond: Precond | None = None, out=None):
+    """pat_pdhg_solve. Returns (u, info dict, status)."""
+    _need(f, geom.dtype, geom.n_det * geom.n_t, "f")
+    out = geom.image() if out is None else out
+    n_state = None
+    for name, t in (("u0", u0),):
+        if t is not None:
+            _need(t, geom.dtype, geom.nx * geom.ny, name)
+    if state_in is not None or state_out is not None:
+        n_state = geom.state_elems(reg.kind)
+    if state_in is not None:
+        _need(state_in, geom.dtype, n_state, "state_in")
+    if state_out is not None:
+        _need(state_out, geom.dtype, n_state, "state_out")
+    if reg.theta is not None:
+        _need(reg.theta, geom.dtype, geom.nx * geom.ny, "theta")
+    r = reg.c_struct()
+    o = _opts(max_iter, gap_tol, gap_every, graph_block, theta, gap_box, u0, state_in,
+              state_out, precond)
+    info = L.SolveInfo()
+    st = L.check(L.load().pat_pdhg_solve(geom.handle, _ptr(f), C.byref(r), C.byref(o),
+                                         _ptr(out), C.byref(info), _stream()))
+    return out, info.as_dict(), st
+
+
+def solve_batched(problems, max_iter=2000, gap_tol=1e-4, gap_every=10, graph_block=50,
+                  theta=1.0, gap_box=2.0):
+    """pat_pdhg_solve_batched over a list of (geom, f, reg[, precond]) tuples.
+    Returns (list of u, list of info dicts, status)."""
+    n = len(problems)
+    geoms = (C.c_void_p * n)()
+    fs = (C.c_void_p * n)()
+    outs = (C.c_void_p * n)()
+    regs = (L.Regulariser * n)()
+    opts = (L.SolveOpts * n)()
+    infos = (L.SolveInfo * n)()
+    us = []
+    for i, p in enumerate(problems):
+        g, f, reg = p[0], p[1], p[2]
+        pc = p[3] if len(p) > 3 else None
+        _need(f, g.dtype, g.n_det * g.n_t, f"f[{i}]")
+        u = g.image()
+        us.append(u)
+        geoms[i] = g.handle.value
+        fs[i] = f.data_ptr()
+        outs[i] = u.data_ptr()
+        regs[i] = reg.c_struct()
+        opts[i] = _opts(max_iter, gap_tol, gap_every, graph_block, theta, gap_box, None, None,
+                        None, pc)
+    st = L.check(L.load().pat_pdhg_solve_batched(n, geoms, fs, regs, opts, outs, infos, _stream()))
+    return us, [infos[i].as_dict() for i in range(n)], st

@@ -1,0 +1,303 @@
+"""GPU parity of the HIP library (through the C ABI) against the FP64 oracle.
+
+Tolerances: FP64 element-wise to 1e-12 relative per apply (rounding order
+only); FP32 to 1e-5 relative L2 per apply and 1e-3 relative L2 on the image
+after a fixed iteration count (the workload targets).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import phantoms
+from oracle import geometry as OG
+from oracle import pdhg as OP
+
+from gpu_common import (DT, column_of_A, desc_for, host, oracle_problem, rel, split_state,
+                        synth_data, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+pat = pytest.importorskip("paper_1707_02245_amd.pat")
+
+TOL_APPLY = {"f64": 1e-12, "f32": 1e-5}
+
+CASES = {
+    # name: (desc kwargs, note)
+    "tv64": dict(n=64, n_det=32, n_t=128),                      # the 64^2 workload
+    "ragged": dict(n=37, n_det=7, n_t=53, ny=29, y_max=-1 + 29 * 2 / 37),
+    "arc90": dict(n=48, n_det=9, n_t=80, arc_span=math.pi / 2),
+    "inside": dict(n=40, n_det=3, n_t=30, det_xy=[[0.1, -0.2], [-0.93, 0.9], [0.5, 0.05]],
+                   dt=1.2 / 29),
+    "tiny": dict(n=2, n_det=2, n_t=5),
+    "onedet": dict(n=33, n_det=1, n_t=70),
+}
+
+
+def _desc(name):
+    kw = dict(CASES[name])
+    n = kw.pop("n")
+    d = desc_for(n, kw.pop("n_det"), kw.pop("n_t"))
+    if "ny" in kw:
+        d["ny"] = kw.pop("ny")
+    if "det_xy" in kw:
+        d["det_xy"] = np.array(kw.pop("det_xy"))
+        d["n_det"] = d["det_xy"].shape[0]
+    d.update(kw)
+    return d
+
+
+def _geoms(name, dt):
+    d = _desc(name)
+    og = OG.make_geometry(d)
+    gd = {k: v for k, v in d.items()}
+    g = pat.Geometry(dtype=DT[dt], **gd)
+    return d, og, g
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_forward_adjoint_elementwise(name, dt):
+    d, og, g = _geoms(name, dt)
+    A = OG.forward_matrix(og)
+    rng = np.random.default_rng(11)
+    u = rng.standard_normal(og.n_pix)
+    y = rng.standard_normal(og.n_bins)
+    print(f"case {name} {dt}: nx={og.nx} ny={og.ny} n_det={og.n_det} n_t={og.n_t}", flush=True)
+    fu = host(g.forward(to_dev(u.reshape(og.ny, og.nx), DT[dt])))
+    aty = host(g.adjoint(to_dev(y.reshape(og.n_det, og.n_t), DT[dt])))
+    assert rel(fu, A @ u) <= TOL_APPLY[dt]
+    assert rel(aty, A.T @ y) <= TOL_APPLY[dt]
+
+
+@pytest.mark.parametrize("launch", [(4, 16, 1), (5, 32, 3), (6, 64, 8)])
+def test_launch_shapes_agree_with_oracle(launch):
+    d, og, g = _geoms("ragged", "f32")
+    g.set_launch(*launch)
+    A = OG.forward_matrix(og)
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal(og.n_pix)
+    y = rng.standard_normal(og.n_bins)
+    fu = host(g.forward(to_dev(u.reshape(og.ny, og.nx), torch.float32)))
+    aty = host(g.adjoint(to_dev(y.reshape(og.n_det, og.n_t), torch.float32)))
+    assert rel(fu, A @ u) <= 1e-5 and rel(aty, A.T @ y) <= 1e-5
+
+
+def test_adjoint_is_deterministic():
+    d = desc_for(96, 40, 150)
+    g = pat.Geometry(dtype=torch.float32, **d)
+    y = to_dev(np.random.default_rng(2).standard_normal((40, 150)), torch.float32)
+    a = host(g.adjoint(y))
+    b = host(g.adjoint(y))
+    assert np.array_equal(a, b)
+
+
+FULL = {
+    "tgv256": (256, 256, 512, 2 * math.pi),
+    "dtv512": (512, 128, 1024, math.pi / 2),
+}
+
+
+@pytest.mark.parametrize("name", list(FULL))
+def test_full_size_sampled_rows_columns_and_dot(name):
+    """Workload sizes: sampled rows of A and columns of A (= rows of A^T)
+    from the oracle, plus the dot-product identity over the whole operator."""
+    n, n_det, n_t, span = FULL[name]
+    d = desc_for(n, n_det, n_t, arc_span=span)
+    og = OG.make_geometry(d)
+    g = pat.Geometry(dtype=torch.float32, **d)
+    rng = np.random.default_rng(21)
+    u = rng.standard_normal((n, n))
+    y = rng.standard_normal((n_det, n_t))
+    print(f"case {name}: forward/adjoint at {n}^2, {n_det}x{n_t}", flush=True)
+    fu = host(g.forward(to_dev(u, torch.float32))).ravel()
+    aty = host(g.adjoint(to_dev(y, torch.float32))).ravel()
+    bins = np.sort(rng.choice(og.n_bins, 96, replace=False))
+    ref_rows = OG.forward_rows(og, bins) @ u.ravel()
+    assert rel(fu[bins], ref_rows) <= 1e-5
+    pix = np.sort(rng.choice(og.n_pix, 12, replace=False))
+    ref_cols = np.array([column_of_A(og, j) @ y.ravel() for j in pix])
+    assert rel(aty[pix], ref_cols) <= 1e-5
+    lhs = float(fu @ y.ravel())
+    rhs = float(u.ravel() @ aty)
+    assert abs(lhs - rhs) <= 1e-5 * np.linalg.norm(fu) * np.linalg.norm(y)
+
+
+# ------------------------------------------------------------------ step sizes
+
+def _theta(n, ny=None, seed=3):
+    ny = n if ny is None else ny
+    return np.random.default_rng(seed).uniform(-1.5, 1.5, (ny, n))
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("kind", ["tv", "tgv", "dtv", "tikhonov"])
+def test_diag_preconditioner(kind, dt):
+    d, og, g = _geoms("ragged", dt)
+    A = OG.forward_matrix(og)
+    th = _theta(og.nx, og.ny)
+    p = oracle_problem(A, np.zeros(og.n_bins), og.nx, kind, 0.02, 0.04, 0.3, th, ny=og.ny)
+    ref = OP.precond_diag(p)
+    reg = pat.Reg(kind, 0.02, 0.04, 0.3, to_dev(th, DT[dt]) if kind == "dtv" else None)
+    pc = pat.Precond(g, reg, "diag")
+    tol = 1e-12 if dt == "f64" else 1e-6
+    assert rel(host(pc.get("sigma_q")), ref["sigma_q"]) <= tol
+    assert rel(host(pc.get("tau_u")), ref["tau_u"]) <= tol
+    if kind != "tikhonov":
+        assert rel(host(pc.get("sigma_r")), ref["sigma_r"]) <= tol
+    if kind == "tgv":
+        assert rel(host(pc.get("sigma_s")), ref["sigma_s"]) <= tol
+        assert rel(host(pc.get("tau_v")), ref["tau_v"].ravel()) <= tol
+
+
+@pytest.mark.parametrize("kind", ["tv", "tgv", "dtv"])
+def test_block_preconditioner(kind):
+    d, og, g = _geoms("arc90", "f64")
+    A = OG.forward_matrix(og)
+    th = _theta(og.nx)
+    p = oracle_problem(A, np.zeros(og.n_bins), og.nx, kind, 0.02, 0.04, 0.3, th)
+    ref = OP.precond_block(p)
+    reg = pat.Reg(kind, 0.02, 0.04, 0.3, to_dev(th, torch.float64) if kind == "dtv" else None)
+    pc = pat.Precond(g, reg, "block")
+    assert host(pc.get("tau_u"))[0] == pytest.approx(ref["tau_u"][0], rel=1e-9)
+    assert host(pc.get("sigma_q"))[0] == pytest.approx(ref["sigma_q"][0], rel=1e-9)
+    assert host(pc.get("sigma_r"))[0] == pytest.approx(ref["sigma_r"][0], rel=1e-9)
+
+
+# ------------------------------------------------------------------ PDHG iterations
+
+def _reg_pair(kind, og, dt, lam=0.02):
+    th = _theta(og.nx, og.ny)
+    reg = pat.Reg(kind, lam, 2 * lam, 0.1, to_dev(th, DT[dt]) if kind == "dtv" else None)
+    return reg, th
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("kind", ["tv", "tgv", "dtv", "tikhonov"])
+def test_fixed_iterations_full_state(kind, dt):
+    """State after 60 iterations (u, ubar, q, r, v, vbar, s) against Alg. 1/2."""
+    name = "arc90" if kind == "dtv" else "ragged"
+    d, og, g = _geoms(name, dt)
+    A = OG.forward_matrix(og)
+    fam = {"tv": "disc", "tgv": "vessel", "dtv": "segment", "tikhonov": "disc"}[kind]
+    rng = np.random.default_rng(4)
+    f = A @ np.clip(rng.uniform(-0.2, 1, og.n_pix), 0, None) + 0.01 * rng.standard_normal(og.n_bins)
+    reg, th = _reg_pair(kind, og, dt)
+    p = oracle_problem(A, f, og.nx, kind, reg.lam, reg.alpha0, reg.eta, th, ny=og.ny)
+    ref = OP.pdhg_solve(p, OP.precond_diag(p), iters=60)
+    st = torch.zeros(g.state_elems(kind), dtype=DT[dt], device="cuda")
+    u, info, status = pat.solve(g, to_dev(f, DT[dt]), reg, max_iter=60, gap_tol=0.0,
+                               gap_every=10, graph_block=20, state_out=st)
+    got = split_state(host(st), kind, og.n_pix, og.n_bins)
+    tol = 1e-10 if dt == "f64" else 1e-4
+    print(f"{kind} {dt}: rel u {rel(got['u'], ref['u']):.2e}", flush=True)
+    assert info["iters"] == 60
+    assert rel(host(u), ref["u"]) <= tol
+    for key in ("u", "ubar", "q", "r", "v", "vbar", "s"):
+        if key in got and key in ref:
+            assert rel(got[key], ref[key]) <= tol, key
+    g_ref = OP.gap_terms(p, ref, 2.0)
+    assert info["primal"] == pytest.approx(g_ref["P"], rel=1e-9 if dt == "f64" else 1e-4)
+    assert info["gap"] == pytest.approx(g_ref["gap"], rel=1e-8 if dt == "f64" else 1e-3)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_tv64_workload_200_iterations(dt):
+    """The 64^2 TV workload: lambda 0.05, DIAG, 200 iterations from zero, on
+    disc-phantom data synthesised on the 128^2 grid with 5% noise."""
+    d = desc_for(64, 32, 128)
+    og = OG.make_geometry(d)
+    A = OG.forward_matrix(og)
+    g = pat.Geometry(dtype=DT[dt], **d)
+    for seed in (0, 1):
+        f, _ = synth_data(d, "disc", seed)
+        p = oracle_problem(A, f, 64, "tv", 0.05)
+        ref = OP.pdhg_solve(p, OP.precond_diag(p), iters=200)
+        u, info, _ = pat.solve(g, to_dev(f, DT[dt]), pat.Reg("tv", 0.05), max_iter=200,
+                               gap_tol=0.0, gap_every=50, graph_block=50)
+        e = rel(host(u), ref["u"])
+        print(f"tv64 {dt} seed {seed}: rel L2 image {e:.3e}", flush=True)
+        assert e <= (1e-10 if dt == "f64" else 1e-3)
+
+
+def test_resume_is_bitwise():
+    d, og, g = _geoms("ragged", "f32")
+    A = OG.forward_matrix(og)
+    f = A @ np.random.default_rng(8).uniform(0, 1, og.n_pix)
+    reg = pat.Reg("tgv", 0.01, 0.02)
+    fd = to_dev(f, torch.float32)
+    n_st = g.state_elems("tgv")
+    full = torch.zeros(n_st, dtype=torch.float32, device="cuda")
+    half = torch.zeros(n_st, dtype=torch.float32, device="cuda")
+    again = torch.zeros(n_st, dtype=torch.float32, device="cuda")
+    pat.solve(g, fd, reg, max_iter=100, gap_tol=0.0, gap_every=10, graph_block=50, state_out=full)
+    pat.solve(g, fd, reg, max_iter=50, gap_tol=0.0, gap_every=10, graph_block=50, state_out=half)
+    pat.solve(g, fd, reg, max_iter=50, gap_tol=0.0, gap_every=10, graph_block=50,
+              state_in=half, state_out=again)
+    assert np.array_equal(host(full), host(again))
+
+
+def test_graph_and_direct_launches_agree():
+    d, og, g = _geoms("arc90", "f32")
+    A = OG.forward_matrix(og)
+    f = to_dev(A @ np.random.default_rng(9).uniform(0, 1, og.n_pix), torch.float32)
+    reg = pat.Reg("tv", 0.01)
+    a, ia, _ = pat.solve(g, f, reg, max_iter=80, gap_tol=0.0, gap_every=10, graph_block=40)
+    b, ib, _ = pat.solve(g, f, reg, max_iter=80, gap_tol=0.0, gap_every=10, graph_block=0)
+    assert np.array_equal(host(a), host(b))
+    assert ia["gap"] == ib["gap"]
+
+
+def test_warm_start_and_fallback():
+    d, og, g = _geoms("tv64", "f64")
+    A = OG.forward_matrix(og)
+    f, _ = synth_data(d, "disc", 3)
+    p = oracle_problem(A, f, 64, "tv", 0.05)
+    pc = OP.precond_diag(p)
+    fd = to_dev(f, torch.float64)
+    reg = pat.Reg("tv", 0.05)
+    good = OP.pdhg_solve(p, pc, iters=100)["u"]
+    ref = OP.pdhg_solve(p, pc, iters=40, u0=good)
+    u, info, _ = pat.solve(g, fd, reg, max_iter=40, gap_tol=0.0, gap_every=10, graph_block=20,
+                           u0=to_dev(good.reshape(64, 64), torch.float64))
+    assert info["fallback"] == 0 and rel(host(u), ref["u"]) <= 1e-10
+    zero = OP.pdhg_solve(p, pc, iters=40)["u"]
+    for bad in (np.full((64, 64), np.nan), np.full((64, 64), 1e3)):
+        assert OP.warm_start_rejected(p, bad.ravel())
+        u, info, _ = pat.solve(g, fd, reg, max_iter=40, gap_tol=0.0, gap_every=10,
+                               graph_block=20, u0=to_dev(bad, torch.float64))
+        assert info["fallback"] == 1 and rel(host(u), zero) <= 1e-10
+
+
+def test_converges_to_gap_and_matches_oracle_objective():
+    d = desc_for(48, 24, 96)
+    og = OG.make_geometry(d)
+    A = OG.forward_matrix(og)
+    f, _ = synth_data(d, "vessel", 5)
+    p = oracle_problem(A, f, 48, "tgv", 0.002, 0.004)
+    ref = OP.pdhg_solve(p, OP.precond_diag(p), tol=1e-4, max_iter=20000, gap_every=50)
+    g = pat.Geometry(dtype=torch.float32, **d)
+    u, info, st = pat.solve(g, to_dev(f, torch.float32), pat.Reg("tgv", 0.002, 0.004),
+                            max_iter=20000, gap_tol=1e-4, gap_every=50, graph_block=50)
+    assert st == 0 and info["converged"] == 1 and info["rel_gap"] <= 1e-4
+    assert info["iters"] == ref["history"][-1]["n"]
+    assert info["primal"] == pytest.approx(ref["history"][-1]["P"], rel=2e-4)
+
+
+def test_batched_matches_single_solves():
+    problems, singles = [], []
+    specs = [("ragged", "tv", 0.01), ("arc90", "tgv", 0.01), ("tv64", "dtv", 0.02),
+             ("ragged", "tgv", 0.005)]
+    for name, kind, lam in specs:
+        d, og, g = _geoms(name, "f32")
+        A = OG.forward_matrix(og)
+        f = to_dev(A @ np.random.default_rng(len(problems)).uniform(0, 1, og.n_pix), torch.float32)
+        reg, _ = _reg_pair(kind, og, "f32", lam)
+        problems.append((g, f, reg))
+    us, infos, st = pat.solve_batched(problems, max_iter=300, gap_tol=1e-3, gap_every=10,
+                                      graph_block=50)
+    for (g, f, reg), u, info in zip(problems, us, infos):
+        u1, i1, _ = pat.solve(g, f, reg, max_iter=300, gap_tol=1e-3, gap_every=10, graph_block=50)
+        assert info["iters"] == i1["iters"]
+        assert np.array_equal(host(u), host(u1))
