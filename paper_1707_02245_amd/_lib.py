@@ -42,6 +42,7 @@ class GeometryInfo(C.Structure):
         ("n_samples", C.c_int64), ("n_window", C.c_int64),
         ("dtype", C.c_int32),
         ("fwd_lanes_log2", C.c_int32), ("adj_tile", C.c_int32), ("adj_det_group", C.c_int32),
+        ("adj_mode", C.c_int32), ("csr_nnz", C.c_int64),
     ]
 
 
@@ -78,6 +79,7 @@ _SIGS = {
     "pat_geometry_destroy": ([C.c_void_p], C.c_int),
     "pat_geometry_get_info": ([C.c_void_p, C.POINTER(GeometryInfo)], C.c_int),
     "pat_geometry_set_launch": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32], C.c_int),
+    "pat_geometry_set_adjoint": ([C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
     "pat_forward": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "pat_adjoint": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "pat_precond": ([C.c_void_p, C.POINTER(Regulariser), C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),

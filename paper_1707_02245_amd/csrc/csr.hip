@@ -1,0 +1,196 @@
+// The stored transpose of the circular-mean operator: A^T as a CSR matrix
+// (rows = pixels, columns = bins, sorted), built once on the device and
+// applied by a sparse matrix-vector product (arXiv:1707.02245, Sec. 3.3.1:
+// compute the discretised matrix once and use its transpose as the adjoint).
+//
+// Build: one wave per pixel; lane d enumerates, for detector d, the radii
+// whose circles pass within sqrt(2) pixels of the pixel centre and the arc
+// samples in the pixel's angular window, computes each sample's position and
+// bilinear weights with exactly the arithmetic of the forward kernel, keeps
+// the weight that falls on this pixel and sums it per radius. Entries come
+// out in bin order (detector-major, then radius), so the build is
+// deterministic and needs no sort. A count pass and a fill pass share the
+// enumeration; the row offsets are a host prefix sum.
+
+#include <numeric>
+
+#include "pat_internal.hpp"
+
+namespace pat {
+
+constexpr double kTwoPiC = 6.283185307179586476925286766559;
+
+// Enumerate the non-zeros of row `pix` of A^T contributed by detector d.
+// With out_col == nullptr only counts; otherwise writes (bin, value) pairs.
+template <class T>
+__device__ int enum_pixel_detector(const GeomDev& g, int i, int j, int d, int* out_col, T* out_val) {
+  const double2 p = g.det[d];
+  const double dx = (double)i - p.x, dy = (double)j - p.y;
+  const double rho = sqrt(dx * dx + dy * dy);
+  const int k0 = max(0, (int)floor((rho - 1.5) * g.kscale - g.koff) - 1);
+  const int k1 = min(g.n_t - 1, (int)ceil((rho + 1.5) * g.kscale - g.koff) + 1);
+  const bool full = rho < 2.0;
+  double a_lo = 0.0, a_hi = 0.0;
+  if (!full) {
+    const double psi = atan2(dy, dx);
+    const double del = asin(fmin(1.0, 1.5 / rho)) + 1e-9;
+    a_lo = psi - del;
+    a_hi = psi + del;
+  }
+  int n = 0;
+  for (int k = k0; k <= k1; ++k) {
+    const int2 mo = g.moff[k];
+    const double2 rr = g.rad[k];
+    const int M = mo.x;
+    int mlo = 0, cnt = M;
+    if (!full) {
+      mlo = (int)floor(a_lo * M / kTwoPiC - 0.5) - 1;
+      const int mhi = (int)ceil(a_hi * M / kTwoPiC - 0.5) + 1;
+      cnt = min(M, mhi - mlo + 1);
+      mlo %= M;
+      if (mlo < 0) mlo += M;
+    }
+    T wsum = T(0);
+    for (int t = 0; t < cnt; ++t) {
+      int m = mlo + t;
+      if (m >= M) m -= M;
+      const double2 cs = g.cs[mo.y + m];
+      const double gx = fma(rr.x, cs.x, p.x);
+      const double gy = fma(rr.x, cs.y, p.y);
+      const double fx = floor(gx), fy = floor(gy);
+      const int ix = (int)fx, iy = (int)fy;
+      const int ox = i - ix, oy = j - iy;
+      if ((unsigned)ox <= 1u && (unsigned)oy <= 1u) {
+        const T tx = (T)(gx - fx), ty = (T)(gy - fy);
+        const T wx = ox ? tx : (T(1) - tx);
+        const T wy = oy ? ty : (T(1) - ty);
+        wsum += wx * wy;
+      }
+    }
+    if (wsum != T(0)) {
+      if (out_col) {
+        out_col[n] = d * g.n_t + k;
+        out_val[n] = wsum * (T)rr.y;
+      }
+      ++n;
+    }
+  }
+  return n;
+}
+
+__device__ __forceinline__ int wave_excl_scan(int v, int lane, int* total) {
+  int x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  *total = __shfl(x, 63, 64);
+  return x - v;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void csr_build_kernel(GeomDev g, int* __restrict__ row_cnt,
+                                                        const int64_t* __restrict__ row_ptr,
+                                                        int* __restrict__ col, T* __restrict__ val) {
+  const int64_t N = (int64_t)g.nx * g.ny;
+  const int64_t pix = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (pix >= N) return;  // whole wave
+  const int i = (int)(pix % g.nx), j = (int)(pix / g.nx);
+  int64_t pos = row_ptr ? row_ptr[pix] : 0;
+  int total = 0;
+  for (int d0 = 0; d0 < g.n_det; d0 += 64) {
+    const int d = d0 + lane;
+    const int c = d < g.n_det ? enum_pixel_detector<T>(g, i, j, d, nullptr, nullptr) : 0;
+    int sum;
+    const int excl = wave_excl_scan(c, lane, &sum);
+    if (row_ptr && c > 0) enum_pixel_detector<T>(g, i, j, d, col + pos + excl, val + pos + excl);
+    pos += sum;
+    total += sum;
+  }
+  if (!row_ptr && lane == 0) row_cnt[pix] = total;
+}
+
+template <class T>
+void build_csr_adjoint(pat_geometry_s* geo, hipStream_t s) {
+  const GeomDev g = geo->dev();
+  const int64_t N = geo->n_pix();
+  DevBuf cnt(sizeof(int) * N);
+  const int blocks = (int)((N + 3) / 4);
+  hipLaunchKernelGGL(csr_build_kernel<T>, dim3(blocks), dim3(256), 0, s, g, ptr<int>(cnt),
+                     (const int64_t*)nullptr, (int*)nullptr, (T*)nullptr);
+  PAT_HIP(hipGetLastError());
+  std::vector<int> h_cnt(N);
+  PAT_HIP(hipMemcpyAsync(h_cnt.data(), cnt.p, sizeof(int) * N, hipMemcpyDeviceToHost, s));
+  PAT_HIP(hipStreamSynchronize(s));
+  std::vector<int64_t> h_ptr(N + 1);
+  h_ptr[0] = 0;
+  for (int64_t r = 0; r < N; ++r) h_ptr[r + 1] = h_ptr[r] + h_cnt[r];
+  const int64_t nnz = h_ptr[N];
+  PAT_CHECK_ARG(nnz < (int64_t(1) << 31), "A^T has too many non-zeros for 32-bit columns");
+  geo->csr_ptr.alloc(sizeof(int64_t) * (N + 1));
+  geo->csr_col.alloc(sizeof(int) * std::max<int64_t>(nnz, 1));
+  geo->csr_val.alloc(sizeof(T) * std::max<int64_t>(nnz, 1));
+  PAT_HIP(hipMemcpyAsync(geo->csr_ptr.p, h_ptr.data(), sizeof(int64_t) * (N + 1),
+                         hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(csr_build_kernel<T>, dim3(blocks), dim3(256), 0, s, g, (int*)nullptr,
+                     ptr<int64_t>(geo->csr_ptr), ptr<int>(geo->csr_col), ptr<T>(geo->csr_val));
+  PAT_HIP(hipGetLastError());
+  PAT_HIP(hipStreamSynchronize(s));
+  geo->csr_nnz = nnz;
+}
+
+// y[row] = sum_e val[e] x[col[e]]: one wave per row, lanes stride the row.
+template <class T>
+__global__ __launch_bounds__(256) void csr_spmv_kernel(CsrArgs<T> a0, const CsrArgs<T>* __restrict__ arr,
+                                                       const int* __restrict__ starts, int n_inst) {
+  int blk = blockIdx.x;
+  CsrArgs<T> a;
+  if (arr) {
+    int lo = 0, hi = n_inst;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (starts[mid] <= blk) lo = mid; else hi = mid;
+    }
+    a = arr[lo];
+    blk -= starts[lo];
+  } else {
+    a = a0;
+  }
+  const int64_t row = (int64_t)blk * 4 + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (row >= a.n_rows) return;  // whole wave
+  const int64_t e0 = a.ptr[row], e1 = a.ptr[row + 1];
+  T acc = T(0);
+  for (int64_t e = e0 + lane; e < e1; e += 64) acc += a.val[e] * a.x[a.col[e]];
+  acc = group_sum<64>(acc);
+  if (lane == 0) a.y[row] = acc;
+}
+
+template <class T>
+void launch_csr_spmv(const CsrArgs<T>& a, hipStream_t s) {
+  const int blocks = (int)((a.n_rows + 3) / 4);
+  if (blocks <= 0) return;
+  hipLaunchKernelGGL(csr_spmv_kernel<T>, dim3(blocks), dim3(256), 0, s, a, (const CsrArgs<T>*)nullptr,
+                     (const int*)nullptr, 1);
+  PAT_HIP(hipGetLastError());
+}
+
+template <class T>
+void launch_csr_spmv_batched(const CsrArgs<T>* arr, const int* starts, int n_inst, int total_blocks,
+                             hipStream_t s) {
+  if (total_blocks <= 0) return;
+  CsrArgs<T> dummy{};
+  hipLaunchKernelGGL(csr_spmv_kernel<T>, dim3(total_blocks), dim3(256), 0, s, dummy, arr, starts, n_inst);
+  PAT_HIP(hipGetLastError());
+}
+
+template void build_csr_adjoint<float>(pat_geometry_s*, hipStream_t);
+template void build_csr_adjoint<double>(pat_geometry_s*, hipStream_t);
+template void launch_csr_spmv<float>(const CsrArgs<float>&, hipStream_t);
+template void launch_csr_spmv<double>(const CsrArgs<double>&, hipStream_t);
+template void launch_csr_spmv_batched<float>(const CsrArgs<float>*, const int*, int, int, hipStream_t);
+template void launch_csr_spmv_batched<double>(const CsrArgs<double>*, const int*, int, int, hipStream_t);
+
+}  // namespace pat

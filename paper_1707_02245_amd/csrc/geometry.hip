@@ -290,6 +290,7 @@ extern "C" pat_status pat_geometry_create(const pat_geometry_desc* desc, pat_dty
     g->build_host();
     g->upload(static_cast<hipStream_t>(stream));
     g->default_launch();
+    g->ensure_csr(static_cast<hipStream_t>(stream));
     *out = g.release();
     return PAT_OK;
   });
@@ -317,6 +318,8 @@ extern "C" pat_status pat_geometry_get_info(pat_geometry g, pat_geometry_info* o
     out->fwd_lanes_log2 = g->lanes_log2;
     out->adj_tile = g->tile;
     out->adj_det_group = g->det_group;
+    out->adj_mode = g->adj_mode;
+    out->csr_nnz = g->csr_nnz;
     return PAT_OK;
   });
 }
@@ -326,6 +329,16 @@ extern "C" pat_status pat_geometry_set_launch(pat_geometry g, int32_t lanes_log2
   return guarded([&]() -> pat_status {
     PAT_CHECK_ARG(g != nullptr, "geometry is NULL");
     g->set_launch(lanes_log2, tile, det_group);
+    return PAT_OK;
+  });
+}
+
+extern "C" pat_status pat_geometry_set_adjoint(pat_geometry g, int32_t mode, void* stream) {
+  return guarded([&]() -> pat_status {
+    PAT_CHECK_ARG(g != nullptr, "geometry is NULL");
+    PAT_CHECK_ARG(mode == 0 || mode == 1, "adjoint mode must be 0 (scatter) or 1 (CSR)");
+    if (mode == 1) g->ensure_csr(static_cast<hipStream_t>(stream));
+    g->adj_mode = mode;
     return PAT_OK;
   });
 }

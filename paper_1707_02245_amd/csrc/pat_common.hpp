@@ -206,6 +206,17 @@ struct InstDev {
   int red_stride;
 };
 
+// y = M x for a CSR matrix M (rows n_rows).
+template <class T>
+struct CsrArgs {
+  const int64_t* ptr;
+  const int* col;
+  const T* val;
+  const T* x;
+  T* y;
+  int64_t n_rows;
+};
+
 // Ordered final sum of one instance's gap partials.
 struct GapFinishArgs {
   const double* red;

@@ -17,6 +17,10 @@ struct pat_geometry_s {
   pat::DevBuf d_det, d_rad, d_moff, d_cs, d_win;
   // launch parameters
   int lanes_log2 = 6, tile = 32, det_group = 16;
+  // adjoint: 0 = tile scatter (matrix-free), 1 = stored CSR of A^T
+  int adj_mode = 1;
+  pat::DevBuf csr_ptr, csr_col, csr_val;
+  int64_t csr_nnz = -1;  // -1: not built
   // scratch of the stand-alone applies
   pat::DevBuf scratch_pad, scratch_part;
 
@@ -25,6 +29,7 @@ struct pat_geometry_s {
   void set_launch(int lanes_log2, int tile, int det_group);
   void default_launch();
   pat::GeomDev dev() const;
+  void ensure_csr(hipStream_t s);
   int64_t n_bins() const { return (int64_t)n_det * n_t; }
   int64_t n_pix() const { return (int64_t)nx * ny; }
   int n_groups() const { return (n_det + det_group - 1) / det_group; }
@@ -64,6 +69,9 @@ struct Launch {
   DevBuf fwd, fwd_gap, adj, inst, gapfin;  // FwdArgs x2 / AdjArgs / InstDev / GapFinishArgs
   DevBuf fwd_start, adj_start, pix_start;
   int fwd_total = 0, adj_total = 0, pix_total = 0;
+  // instances whose adjoint is the stored CSR of A^T
+  DevBuf csr, csr_start;
+  int n_adj = 0, n_csr = 0, csr_total = 0;
   int lanes_log2 = 6;   // shared by every instance of one launch
   int max_tile = 32;    // shared by every instance of one launch
 };
@@ -81,6 +89,21 @@ template <class T>
 void launch_adjoint_batched(const Launch<T>& L, hipStream_t s);
 template <class T>
 void launch_reduce_groups(const T* part, T* out, int n_groups, int64_t n, hipStream_t s);
+
+// Stand-alone applies (scratch owned by the geometry; adjoint by its mode).
+template <class T>
+void apply_forward(pat_geometry_s* g, const T* u, T* f, hipStream_t s);
+template <class T>
+void apply_adjoint(pat_geometry_s* g, const T* f, T* u, hipStream_t s);
+
+// ---- stored A^T (csr.hip)
+template <class T>
+void build_csr_adjoint(pat_geometry_s* geo, hipStream_t s);
+template <class T>
+void launch_csr_spmv(const CsrArgs<T>& a, hipStream_t s);
+template <class T>
+void launch_csr_spmv_batched(const CsrArgs<T>* arr, const int* starts, int n_inst, int total_blocks,
+                             hipStream_t s);
 
 // ---- launchers (pdhg.hip)
 template <class T>

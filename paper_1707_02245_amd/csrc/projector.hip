@@ -322,7 +322,7 @@ template <class T>
 void launch_adjoint_batched(const Launch<T>& L, hipStream_t s) {
   AdjArgs<T> dummy{};
   adj_dispatch<T>(L.max_tile, L.adj_total, dummy, ptr<AdjArgs<T>>(L.adj),
-                  ptr<int>(L.adj_start), L.n, s);
+                  ptr<int>(L.adj_start), L.n_adj, s);
 }
 
 template <class T>
@@ -381,6 +381,12 @@ pat::GeomDev pat_geometry_s::dev() const {
   return g;
 }
 
+void pat_geometry_s::ensure_csr(hipStream_t s) {
+  if (csr_nnz >= 0) return;
+  if (dtype == PAT_F64) pat::build_csr_adjoint<double>(this, s);
+  else pat::build_csr_adjoint<float>(this, s);
+}
+
 namespace {
 
 template <class T>
@@ -397,6 +403,18 @@ void forward_impl(pat_geometry g, const void* d_u, void* d_f, hipStream_t s) {
 
 template <class T>
 void adjoint_impl(pat_geometry g, const void* d_f, void* d_u, hipStream_t s) {
+  if (g->adj_mode == 1) {
+    g->ensure_csr(s);
+    pat::CsrArgs<T> c{};
+    c.ptr = pat::ptr<int64_t>(g->csr_ptr);
+    c.col = pat::ptr<int>(g->csr_col);
+    c.val = pat::ptr<T>(g->csr_val);
+    c.x = static_cast<const T*>(d_f);
+    c.y = static_cast<T*>(d_u);
+    c.n_rows = g->n_pix();
+    pat::launch_csr_spmv<T>(c, s);
+    return;
+  }
   pat::AdjArgs<T> a{};
   a.g = g->dev();
   a.data = static_cast<const T*>(d_f);
@@ -413,6 +431,17 @@ void adjoint_impl(pat_geometry g, const void* d_f, void* d_u, hipStream_t s) {
 }
 
 }  // namespace
+
+namespace pat {
+template <class T>
+void apply_forward(pat_geometry g, const T* u, T* f, hipStream_t s) { forward_impl<T>(g, u, f, s); }
+template <class T>
+void apply_adjoint(pat_geometry g, const T* f, T* u, hipStream_t s) { adjoint_impl<T>(g, f, u, s); }
+template void apply_forward<float>(pat_geometry, const float*, float*, hipStream_t);
+template void apply_forward<double>(pat_geometry, const double*, double*, hipStream_t);
+template void apply_adjoint<float>(pat_geometry, const float*, float*, hipStream_t);
+template void apply_adjoint<double>(pat_geometry, const double*, double*, hipStream_t);
+}  // namespace pat
 
 extern "C" pat_status pat_forward(pat_geometry g, const void* d_u, void* d_f, void* stream) {
   return pat::guarded([&]() -> pat_status {

@@ -59,32 +59,10 @@ static void compute_dmat(pat_geometry g, const pat_regulariser* reg, DevBuf& dma
 }
 
 template <class T>
-static void apply_A(pat_geometry g, const T* x, T* y, DevBuf& pad, hipStream_t s) {
-  pad.ensure(sizeof(T) * (size_t)(g->nx + 2) * (g->ny + 2));
-  launch_pad<T>(x, ptr<T>(pad), g->nx, g->ny, s);
-  FwdArgs<T> a{};
-  a.g = g->dev();
-  a.upad = ptr<T>(pad);
-  a.out = y;
-  launch_forward<T>(FWD_PLAIN, a, g->lanes_log2, s);
-}
-
-template <class T>
-static void apply_At(pat_geometry g, const T* y, T* x, DevBuf& part, hipStream_t s) {
-  AdjArgs<T> a{};
-  a.g = g->dev();
-  a.data = y;
-  part.ensure(sizeof(T) * (size_t)a.g.n_groups * g->n_pix());
-  a.part = ptr<T>(part);
-  launch_adjoint<T>(a, s);
-  launch_reduce_groups<T>(a.part, x, a.g.n_groups, g->n_pix(), s);
-}
-
-template <class T>
 static void precond_diag(pat_precond_s* pc, const pat_regulariser* reg, const T* dmat, hipStream_t s) {
   pat_geometry g = pc->g;
   const int64_t N = g->n_pix(), nb = g->n_bins();
-  DevBuf ones(sizeof(T) * std::max<int64_t>(N, nb)), pad, part, colsum(sizeof(T) * N);
+  DevBuf ones(sizeof(T) * std::max<int64_t>(N, nb)), pad, colsum(sizeof(T) * N);
   launch_fill<T>(ptr<T>(ones), T(1), std::max<int64_t>(N, nb), s);
   // sigma_q = 1 / (A 1): A >= 0 so this is the absolute row sum
   pad.ensure(sizeof(T) * (size_t)(g->nx + 2) * (g->ny + 2));
@@ -95,7 +73,7 @@ static void precond_diag(pat_precond_s* pc, const pat_regulariser* reg, const T*
   a.out = ptr<T>(pc->sigma_q);
   launch_forward<T>(FWD_ROWSUM, a, g->lanes_log2, s);
   // column sums of A: A^T 1
-  apply_At<T>(g, ptr<T>(ones), ptr<T>(colsum), part, s);
+  apply_adjoint<T>(g, ptr<T>(ones), ptr<T>(colsum), s);
   launch_precond_pix<T>(reg->kind, g->nx, g->ny, ptr<T>(colsum), dmat, ptr<T>(pc->sigma_r),
                         ptr<T>(pc->sigma_s), ptr<T>(pc->tau_u), ptr<T>(pc->tau_v), s);
   PAT_HIP(hipStreamSynchronize(s));
@@ -126,10 +104,10 @@ template <class T>
 static void precond_block(pat_precond_s* pc, const pat_regulariser* reg, const T* dmat, hipStream_t s) {
   pat_geometry g = pc->g;
   const int64_t N = g->n_pix(), nb = g->n_bins();
-  DevBuf tmp_b(sizeof(T) * nb), pad, part;
+  DevBuf tmp_b(sizeof(T) * nb);
   const double L1 = kPowerSafety * power_norm<T>(N, s, [&](const T* x, T* y) {
-    apply_A<T>(g, x, ptr<T>(tmp_b), pad, s);
-    apply_At<T>(g, ptr<T>(tmp_b), y, part, s);
+    apply_forward<T>(g, x, ptr<T>(tmp_b), s);
+    apply_adjoint<T>(g, ptr<T>(tmp_b), y, s);
   });
   double L2 = 0.0;
   if (reg->kind != PAT_REG_TIKHONOV) {
@@ -202,7 +180,8 @@ struct Inst {
   DevBuf u, ubar_pad, q, r, v, vbar, s, upad_gap, atq_part, red, dmat;
   pat_precond_s* pc = nullptr;
   std::unique_ptr<pat_precond_s> own_pc;
-  int n_fwd = 0, n_pix = 0, n_adj = 0, red_stride = 0;
+  int n_fwd = 0, n_pix = 0, n_adj = 0, n_csr = 0, red_stride = 0;
+  bool csr = false;  // adjoint by the stored CSR of A^T
   int iters = 0;
   bool active = true, converged = false;
   int fallback = 0;
@@ -270,11 +249,14 @@ class Solver {
       I.s.alloc(sizeof(T) * 3 * N);
     }
     const GeomDev gd = I.gdev(lanes_log2, tile);
-    I.atq_part.alloc(sizeof(T) * gd.n_groups * N);
+    I.csr = g->adj_mode == 1;
+    if (I.csr) g->ensure_csr(s);
+    I.atq_part.alloc(sizeof(T) * (I.csr ? 1 : gd.n_groups) * N);
     const int bpb = 256 >> lanes_log2;
     I.n_fwd = (int)((nb + bpb - 1) / bpb);
     I.n_pix = pix_blocks(N);
-    I.n_adj = gd.tiles_x * gd.tiles_y * gd.n_groups;
+    I.n_adj = I.csr ? 0 : gd.tiles_x * gd.tiles_y * gd.n_groups;
+    I.n_csr = I.csr ? (int)((N + 3) / 4) : 0;
     I.red_stride = std::max(I.n_fwd, I.n_pix);
     I.red.alloc(sizeof(double) * GAP_NSLOTS * I.red_stride);
     compute_dmat<T>(g, &I.reg, I.dmat, s);
@@ -293,7 +275,7 @@ class Solver {
     const GeomDev gd = I.gdev(lanes_log2, tile);
     d.nx = I.g->nx;
     d.ny = I.g->ny;
-    d.n_groups = gd.n_groups;
+    d.n_groups = I.csr ? 1 : gd.n_groups;
     d.n_bins = (int)I.g->n_bins();
     d.kind = I.reg.kind;
     d.lam = (T)I.reg.lambda;
@@ -321,11 +303,12 @@ class Solver {
   void build_launch() {
     const int n = (int)act.size();
     std::vector<FwdArgs<T>> fd(n), fg(n);
-    std::vector<AdjArgs<T>> ad(n);
+    std::vector<AdjArgs<T>> ad;
+    std::vector<CsrArgs<T>> cd;
     std::vector<InstDev<T>> id(n);
     std::vector<GapFinishArgs> gf(n);
-    std::vector<int> fs(n + 1), as(n + 1), ps(n + 1);
-    fs[0] = as[0] = ps[0] = 0;
+    std::vector<int> fs(n + 1), as(1, 0), cs(1, 0), ps(n + 1);
+    fs[0] = ps[0] = 0;
     for (int k = 0; k < n; ++k) {
       const Inst<T>& I = *inst[act[k]];
       const GeomDev gd = I.gdev(lanes_log2, tile);
@@ -342,14 +325,27 @@ class Solver {
       fg[k].q = ptr<T>(I.q);
       fg[k].red = ptr<double>(I.red);
       fg[k].red_stride = I.red_stride;
-      ad[k] = AdjArgs<T>{};
-      ad[k].g = gd;
-      ad[k].data = ptr<T>(I.q);
-      ad[k].part = ptr<T>(I.atq_part);
+      if (I.csr) {
+        CsrArgs<T> c{};
+        c.ptr = ptr<int64_t>(I.g->csr_ptr);
+        c.col = ptr<int>(I.g->csr_col);
+        c.val = ptr<T>(I.g->csr_val);
+        c.x = ptr<T>(I.q);
+        c.y = ptr<T>(I.atq_part);
+        c.n_rows = I.g->n_pix();
+        cd.push_back(c);
+        cs.push_back(cs.back() + I.n_csr);
+      } else {
+        AdjArgs<T> a{};
+        a.g = gd;
+        a.data = ptr<T>(I.q);
+        a.part = ptr<T>(I.atq_part);
+        ad.push_back(a);
+        as.push_back(as.back() + I.n_adj);
+      }
       id[k] = inst_dev(I);
       gf[k] = GapFinishArgs{ptr<double>(I.red), I.red_stride, I.n_fwd, I.n_pix};
       fs[k + 1] = fs[k] + I.n_fwd;
-      as[k + 1] = as[k] + I.n_adj;
       ps[k + 1] = ps[k] + I.n_pix;
     }
     auto up = [&](DevBuf& b, const void* src, size_t bytes) {
@@ -358,16 +354,21 @@ class Solver {
     };
     up(L.fwd, fd.data(), sizeof(FwdArgs<T>) * n);
     up(L.fwd_gap, fg.data(), sizeof(FwdArgs<T>) * n);
-    up(L.adj, ad.data(), sizeof(AdjArgs<T>) * n);
+    if (!ad.empty()) up(L.adj, ad.data(), sizeof(AdjArgs<T>) * ad.size());
+    if (!cd.empty()) up(L.csr, cd.data(), sizeof(CsrArgs<T>) * cd.size());
     up(L.inst, id.data(), sizeof(InstDev<T>) * n);
     up(L.gapfin, gf.data(), sizeof(GapFinishArgs) * n);
     up(L.fwd_start, fs.data(), sizeof(int) * (n + 1));
-    up(L.adj_start, as.data(), sizeof(int) * (n + 1));
+    up(L.adj_start, as.data(), sizeof(int) * as.size());
+    up(L.csr_start, cs.data(), sizeof(int) * cs.size());
     up(L.pix_start, ps.data(), sizeof(int) * (n + 1));
     PAT_HIP(hipStreamSynchronize(s));  // host vectors go out of scope
     L.n = n;
     L.fwd_total = fs[n];
-    L.adj_total = as[n];
+    L.adj_total = as.back();
+    L.n_adj = (int)ad.size();
+    L.n_csr = (int)cd.size();
+    L.csr_total = cs.back();
     L.pix_total = ps[n];
     L.lanes_log2 = lanes_log2;
     L.max_tile = tile;
@@ -389,7 +390,9 @@ class Solver {
   void enqueue_iteration(bool check, int c) {
     launch_forward_batched<T>(FWD_DUAL, L, lanes_log2, s);
     launch_reg_dual<T>(L, s);
-    launch_adjoint_batched<T>(L, s);
+    if (L.n_adj > 0) launch_adjoint_batched<T>(L, s);
+    if (L.n_csr > 0)
+      launch_csr_spmv_batched<T>(ptr<CsrArgs<T>>(L.csr), ptr<int>(L.csr_start), L.n_csr, L.csr_total, s);
     launch_primal<T>(L, check, s);
     if (check) enqueue_gap(c);
   }

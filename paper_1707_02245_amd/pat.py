@@ -91,6 +91,12 @@ class Geometry:
         L.check(L.load().pat_geometry_set_launch(self._h, lanes_log2, tile, det_group))
         return self.refresh_info()
 
+    def set_adjoint(self, mode):
+        """mode: "scatter" (matrix-free) or "csr" (stored A^T)."""
+        m = {"scatter": 0, "csr": 1}[mode]
+        L.check(L.load().pat_geometry_set_adjoint(self._h, m, _stream()))
+        return self.refresh_info()
+
     def close(self):
         if getattr(self, "_h", None):
             L.load().pat_geometry_destroy(self._h)
