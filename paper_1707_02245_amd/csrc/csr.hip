@@ -13,6 +13,7 @@
 // enumeration; the row offsets are a host prefix sum.
 
 #include <numeric>
+#include <type_traits>
 
 #include "pat_internal.hpp"
 
@@ -54,7 +55,7 @@ __device__ int enum_pixel_detector(const GeomDev& g, int i, int j, int d, int* o
     for (int t = 0; t < cnt; ++t) {
       int m = mlo + t;
       if (m >= M) m -= M;
-      const double2 cs = g.cs[mo.y + m];
+      const double2 cs = table_cs<T>(g, mo.y + m);
       const double gx = fma(rr.x, cs.x, p.x);
       const double gy = fma(rr.x, cs.y, p.y);
       const double fx = floor(gx), fy = floor(gy);
@@ -142,7 +143,10 @@ void build_csr_adjoint(pat_geometry_s* geo, hipStream_t s) {
 }
 
 // y[row] = sum_e val[e] x[col[e]]: one wave per row, lanes stride the row.
-template <class T>
+// The matrix streams through once per apply (non-temporal loads keep the
+// vectors and the solver state resident in the caches). WIDE accumulates in
+// FP64 into y64 (used for the gap's dual residual).
+template <class T, bool WIDE>
 __global__ __launch_bounds__(256) void csr_spmv_kernel(CsrArgs<T> a0, const CsrArgs<T>* __restrict__ arr,
                                                        const int* __restrict__ starts, int n_inst) {
   int blk = blockIdx.x;
@@ -162,27 +166,60 @@ __global__ __launch_bounds__(256) void csr_spmv_kernel(CsrArgs<T> a0, const CsrA
   const int lane = threadIdx.x % 64;
   if (row >= a.n_rows) return;  // whole wave
   const int64_t e0 = a.ptr[row], e1 = a.ptr[row + 1];
-  T acc = T(0);
-  for (int64_t e = e0 + lane; e < e1; e += 64) acc += a.val[e] * a.x[a.col[e]];
+  using Acc = typename std::conditional<WIDE, double, T>::type;
+  Acc acc0 = Acc(0), acc1 = Acc(0), acc2 = Acc(0), acc3 = Acc(0);
+  const T* __restrict__ val = a.val;
+  const int* __restrict__ col = a.col;
+  const T* __restrict__ x = a.x;
+  int64_t e = e0 + lane;
+  // four independent entries per lane in flight: the column loads of all four
+  // are issued before the dependent gathers of x
+  for (; e + 192 < e1; e += 256) {
+    const int c0 = __builtin_nontemporal_load(col + e);
+    const int c1 = __builtin_nontemporal_load(col + e + 64);
+    const int c2 = __builtin_nontemporal_load(col + e + 128);
+    const int c3 = __builtin_nontemporal_load(col + e + 192);
+    const T v0 = __builtin_nontemporal_load(val + e);
+    const T v1 = __builtin_nontemporal_load(val + e + 64);
+    const T v2 = __builtin_nontemporal_load(val + e + 128);
+    const T v3 = __builtin_nontemporal_load(val + e + 192);
+    acc0 += (Acc)v0 * (Acc)x[c0];
+    acc1 += (Acc)v1 * (Acc)x[c1];
+    acc2 += (Acc)v2 * (Acc)x[c2];
+    acc3 += (Acc)v3 * (Acc)x[c3];
+  }
+  for (; e < e1; e += 64) {
+    const int c = __builtin_nontemporal_load(col + e);
+    acc0 += (Acc)__builtin_nontemporal_load(val + e) * (Acc)x[c];
+  }
+  Acc acc = (acc0 + acc1) + (acc2 + acc3);
   acc = group_sum<64>(acc);
-  if (lane == 0) a.y[row] = acc;
+  if (lane == 0) {
+    if (WIDE) a.y64[row] = (double)acc;
+    else a.y[row] = (T)acc;
+  }
 }
 
 template <class T>
 void launch_csr_spmv(const CsrArgs<T>& a, hipStream_t s) {
   const int blocks = (int)((a.n_rows + 3) / 4);
   if (blocks <= 0) return;
-  hipLaunchKernelGGL(csr_spmv_kernel<T>, dim3(blocks), dim3(256), 0, s, a, (const CsrArgs<T>*)nullptr,
-                     (const int*)nullptr, 1);
+  hipLaunchKernelGGL((csr_spmv_kernel<T, false>), dim3(blocks), dim3(256), 0, s, a,
+                     (const CsrArgs<T>*)nullptr, (const int*)nullptr, 1);
   PAT_HIP(hipGetLastError());
 }
 
 template <class T>
 void launch_csr_spmv_batched(const CsrArgs<T>* arr, const int* starts, int n_inst, int total_blocks,
-                             hipStream_t s) {
+                             hipStream_t s, bool wide) {
   if (total_blocks <= 0) return;
   CsrArgs<T> dummy{};
-  hipLaunchKernelGGL(csr_spmv_kernel<T>, dim3(total_blocks), dim3(256), 0, s, dummy, arr, starts, n_inst);
+  if (wide)
+    hipLaunchKernelGGL((csr_spmv_kernel<T, true>), dim3(total_blocks), dim3(256), 0, s, dummy, arr,
+                       starts, n_inst);
+  else
+    hipLaunchKernelGGL((csr_spmv_kernel<T, false>), dim3(total_blocks), dim3(256), 0, s, dummy, arr,
+                       starts, n_inst);
   PAT_HIP(hipGetLastError());
 }
 
@@ -190,7 +227,7 @@ template void build_csr_adjoint<float>(pat_geometry_s*, hipStream_t);
 template void build_csr_adjoint<double>(pat_geometry_s*, hipStream_t);
 template void launch_csr_spmv<float>(const CsrArgs<float>&, hipStream_t);
 template void launch_csr_spmv<double>(const CsrArgs<double>&, hipStream_t);
-template void launch_csr_spmv_batched<float>(const CsrArgs<float>*, const int*, int, int, hipStream_t);
-template void launch_csr_spmv_batched<double>(const CsrArgs<double>*, const int*, int, int, hipStream_t);
+template void launch_csr_spmv_batched<float>(const CsrArgs<float>*, const int*, int, int, hipStream_t, bool);
+template void launch_csr_spmv_batched<double>(const CsrArgs<double>*, const int*, int, int, hipStream_t, bool);
 
 }  // namespace pat

@@ -242,12 +242,20 @@ void pat_geometry_s::upload(hipStream_t stream) {
   d_det.alloc(sizeof(double2) * n_det);
   d_rad.alloc(sizeof(double2) * n_t);
   d_moff.alloc(sizeof(int2) * n_t);
-  d_cs.alloc(sizeof(double2) * n_samples_per_det);
+  // the table is stored in the element type (positions are still FP64)
+  std::vector<float2> h_cs32;
+  if (dtype == PAT_F32) {
+    h_cs32.resize(n_samples_per_det);
+    for (int64_t i = 0; i < n_samples_per_det; ++i)
+      h_cs32[i] = make_float2((float)h_cs[i].x, (float)h_cs[i].y);
+  }
+  d_cs.alloc((dtype == PAT_F32 ? sizeof(float2) : sizeof(double2)) * n_samples_per_det);
   d_win.alloc(sizeof(int4) * 2 * nb);
   PAT_HIP(hipMemcpyAsync(d_det.p, h_det.data(), d_det.bytes, hipMemcpyHostToDevice, stream));
   PAT_HIP(hipMemcpyAsync(d_rad.p, h_rad.data(), d_rad.bytes, hipMemcpyHostToDevice, stream));
   PAT_HIP(hipMemcpyAsync(d_moff.p, h_moff.data(), d_moff.bytes, hipMemcpyHostToDevice, stream));
-  PAT_HIP(hipMemcpyAsync(d_cs.p, h_cs.data(), d_cs.bytes, hipMemcpyHostToDevice, stream));
+  PAT_HIP(hipMemcpyAsync(d_cs.p, dtype == PAT_F32 ? (const void*)h_cs32.data() : (const void*)h_cs.data(),
+                         d_cs.bytes, hipMemcpyHostToDevice, stream));
   PAT_HIP(hipMemcpyAsync(d_win.p, h_win.data(), d_win.bytes, hipMemcpyHostToDevice, stream));
   PAT_HIP(hipStreamSynchronize(stream));
 }

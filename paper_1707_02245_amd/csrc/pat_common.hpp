@@ -149,7 +149,7 @@ struct GeomDev {
   const double2* det;    // [n_det] detector position in pixel-index units
   const double2* rad;    // [n_t] (r_k / h, 1 / M_k)
   const int2* moff;      // [n_t] (M_k, offset of radius k in the table)
-  const double2* cs;     // [sum M_k] (cos, sin) of 2 pi (m + 1/2) / M_k
+  const void* cs;        // [sum M_k] (cos, sin) of 2 pi (m + 1/2) / M_k, element type
   const int4* win;       // [n_bins][2]: four sample ranges [m0,m1) per bin
   double kscale, koff;   // radius index of a radius rho in pixel units: rho*kscale - koff
   int lanes_log2;        // forward: lanes per bin, log2 (4..6)
@@ -158,6 +158,17 @@ struct GeomDev {
   int det_group;         // adjoint: detectors per workgroup
   int n_groups;          // ceil(n_det / det_group)
 };
+
+// (cos, sin) of an arc sample from the table of the element type, widened to FP64.
+template <class T>
+__device__ __forceinline__ double2 table_cs(const GeomDev& g, int idx) {
+  if constexpr (sizeof(T) == 8) {
+    return static_cast<const double2*>(g.cs)[idx];
+  } else {
+    const float2 c = static_cast<const float2*>(g.cs)[idx];
+    return make_double2((double)c.x, (double)c.y);
+  }
+}
 
 // Forward projection of one instance.
 template <class T>
@@ -201,6 +212,7 @@ struct InstDev {
   const T* tau_u;     // [N]
   const T* tau_v;     // [N] (both components share one value)
   const T* atq_part;  // [n_groups][N] partial A^T q per detector group
+  const double* atq64;  // [N] A^T q accumulated in FP64 (check iterations; may be null)
   T* upad_gap;        // [(ny+2)(nx+2)] padded u+ written on check iterations
   double* red;        // partial sums [GAP_NSLOTS][red_stride]
   int red_stride;
@@ -214,6 +226,7 @@ struct CsrArgs {
   const T* val;
   const T* x;
   T* y;
+  double* y64;        // wide variant: FP64 accumulation and output
   int64_t n_rows;
 };
 

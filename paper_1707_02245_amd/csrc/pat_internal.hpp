@@ -56,9 +56,10 @@ enum FwdMode { FWD_PLAIN = 0, FWD_DUAL = 1, FWD_GAP = 2, FWD_ROWSUM = 3 };
 
 constexpr int kThreads = 256;
 
-inline int fwd_blocks(const pat_geometry_s* g) {
-  const int bpb = kThreads >> g->lanes_log2;
-  return (int)((g->n_bins() + bpb - 1) / bpb);
+// Forward grid: radius-major, one block per (radius, group of 256/lanes detectors).
+inline int fwd_grid(int n_det, int n_t, int lanes_log2) {
+  const int bpb = kThreads >> lanes_log2;
+  return ((n_det + bpb - 1) / bpb) * n_t;
 }
 inline int pix_blocks(int64_t n) { return (int)((n + kThreads - 1) / kThreads); }
 
@@ -103,7 +104,7 @@ template <class T>
 void launch_csr_spmv(const CsrArgs<T>& a, hipStream_t s);
 template <class T>
 void launch_csr_spmv_batched(const CsrArgs<T>* arr, const int* starts, int n_inst, int total_blocks,
-                             hipStream_t s);
+                             hipStream_t s, bool wide = false);
 
 // ---- launchers (pdhg.hip)
 template <class T>

@@ -108,29 +108,30 @@ void launch_reg_dual(const Launch<T>& L, hipStream_t s) {
 
 // ------------------------------------------------------------------ primal step
 
-// (B^T r)_p for TV/TGV (B = grad) and DTV (B = D grad; D symmetric).
-template <class T>
-__device__ __forceinline__ T bt_r(const InstDev<T>& a, int64_t p, int i, int j, int64_t N) {
+// (B^T r)_p for TV/TGV (B = grad) and DTV (B = D grad; D symmetric), in
+// arithmetic type A (the element type, or FP64 for the gap's dual residual).
+template <class T, class A = T>
+__device__ __forceinline__ A bt_r(const InstDev<T>& a, int64_t p, int i, int j, int64_t N) {
   const int nx = a.nx, ny = a.ny;
   const bool ax = i < nx - 1, ay = j < ny - 1, bx = i >= 1, by = j >= 1;
   const T* __restrict__ rx = a.r;
   const T* __restrict__ ry = a.r + N;
   if (a.kind == PAT_REG_DTV) {
     const T* __restrict__ D = a.dmat;
-    auto w1 = [&](int64_t q) { return D[q] * rx[q] + D[N + q] * ry[q]; };
-    auto w2 = [&](int64_t q) { return D[N + q] * rx[q] + D[2 * N + q] * ry[q]; };
-    T t = T(0);
+    auto w1 = [&](int64_t q) { return (A)D[q] * (A)rx[q] + (A)D[N + q] * (A)ry[q]; };
+    auto w2 = [&](int64_t q) { return (A)D[N + q] * (A)rx[q] + (A)D[2 * N + q] * (A)ry[q]; };
+    A t = A(0);
     if (ax) t -= w1(p);
     if (bx) t += w1(p - 1);
     if (ay) t -= w2(p);
     if (by) t += w2(p - nx);
     return t;
   }
-  T t = T(0);
-  if (ax) t -= rx[p];
-  if (bx) t += rx[p - 1];
-  if (ay) t -= ry[p];
-  if (by) t += ry[p - nx];
+  A t = A(0);
+  if (ax) t -= (A)rx[p];
+  if (bx) t += (A)rx[p - 1];
+  if (ay) t -= (A)ry[p];
+  if (by) t += (A)ry[p - nx];
   return t;
 }
 
@@ -152,14 +153,16 @@ __global__ __launch_bounds__(256) void primal_kernel(const InstDev<T>* __restric
     const T u_old = a.u[p];
     const T tau = a.tau_u[p];
     T un;
+    // the gap's dual residual K^T y: FP64 A^T q when available
+    const double atq_d = (CHECK && a.atq64) ? a.atq64[p] : (double)atq;
     if (a.kind == PAT_REG_TIKHONOV) {
       // u <- prox_{tau G}(u - tau A^T q), G = lam/2 ||u||^2
       un = (u_old - tau * atq) / (T(1) + tau * a.lam);
-      if (CHECK) kty = (double)atq * (double)atq;
+      if (CHECK) kty = atq_d * atq_d;
     } else {
       const T gdir = atq + bt_r(a, p, i, j, N);
       un = u_old - tau * gdir;
-      if (CHECK) kty = fabs((double)gdir);
+      if (CHECK) kty = fabs(atq_d + bt_r<T, double>(a, p, i, j, N));
     }
     a.u[p] = un;
     const T ubar = un + a.theta_ex * (un - u_old);
@@ -190,7 +193,13 @@ __global__ __launch_bounds__(256) void primal_kernel(const InstDev<T>* __restric
       a.v[N + p] = vyn;
       a.vbar[p] = vxn + a.theta_ex * (vxn - vx);
       a.vbar[N + p] = vyn + a.theta_ex * (vyn - vy);
-      if (CHECK) kty += fabs((double)gvx) + fabs((double)gvy);
+      if (CHECK) {
+        const double ex = -((ax ? (double)sxx[p + 1] : (double)c_xx) - (double)c_xx) -
+                          ((ay ? (double)sxy[p + nx] : (double)c_xy) - (double)c_xy) - (double)a.r[p];
+        const double ey = -((ax ? (double)sxy[p + 1] : (double)c_xy) - (double)c_xy) -
+                          ((ay ? (double)syy[p + nx] : (double)c_yy) - (double)c_yy) - (double)a.r[N + p];
+        kty += fabs(ex) + fabs(ey);
+      }
     }
   }
   if (CHECK) {

@@ -91,36 +91,46 @@ __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T
   const GeomDev& g = a.g;
   constexpr int BPB = 256 / LANES;
   const int sub = threadIdx.x / LANES, lane = threadIdx.x % LANES;
-  const int n_bins = g.n_det * g.n_t;
-  const int b = blk * BPB + sub;
-  const bool valid = b < n_bins;
+  // radius-major order: consecutive blocks take the same radius for successive
+  // detector groups, so a radius' (cos, sin) table is reused from L2
+  const int n_dg = (g.n_det + BPB - 1) / BPB;
+  const int k = blk / n_dg;
+  const int d = (blk - k * n_dg) * BPB + sub;
+  const bool valid = d < g.n_det && k < g.n_t;
+  const int b = d * g.n_t + k;
   T acc = T(0);
   double inv_m = 0.0;
   if (valid) {
-    const int d = b / g.n_t, k = b - d * g.n_t;
     const int4 w0 = g.win[2 * (int64_t)b], w1 = g.win[2 * (int64_t)b + 1];
-    const int l0 = w0.y - w0.x, l1 = w0.w - w0.z, l2 = w1.y - w1.x, l3 = w1.w - w1.z;
-    const int total = l0 + l1 + l2 + l3;
     const double2 p = g.det[d];
     const double2 rr = g.rad[k];
     inv_m = rr.y;
-    const double2* __restrict__ cs = g.cs + g.moff[k].y;
+    const int toff = g.moff[k].y;
     const T* __restrict__ up = a.upad;
     const int P = g.pitch;
-    for (int j = lane; j < total; j += LANES) {
-      int m;
-      if (j < l0) m = w0.x + j;
-      else if (j < l0 + l1) m = w0.z + (j - l0);
-      else if (j < l0 + l1 + l2) m = w1.x + (j - l0 - l1);
-      else m = w1.z + (j - l0 - l1 - l2);
-      const Sample s = arc_sample(p, rr.x, cs[m]);
-      if (s.ix >= -1 && s.ix < g.nx && s.iy >= -1 && s.iy < g.ny) {
-        const T tx = (T)s.tx, ty = (T)s.ty;
-        const T w00 = (T(1) - tx) * (T(1) - ty), w10 = tx * (T(1) - ty);
-        const T w01 = (T(1) - tx) * ty, w11 = tx * ty;
-        const T* q = up + (int64_t)(s.iy + 1) * P + (s.ix + 1);
-        acc += w00 * q[0] + w10 * q[1] + w01 * q[P] + w11 * q[P + 1];
+    const int nx = g.nx, ny = g.ny;
+    // weighted 2x2 gather of one arc sample (zero outside the grid)
+    auto tap = [&](int m) -> T {
+      const Sample s = arc_sample(p, rr.x, table_cs<T>(g, toff + m));
+      if (s.ix < -1 || s.ix >= nx || s.iy < -1 || s.iy >= ny) return T(0);
+      const T tx = (T)s.tx, ty = (T)s.ty;
+      const T w00 = (T(1) - tx) * (T(1) - ty), w10 = tx * (T(1) - ty);
+      const T w01 = (T(1) - tx) * ty, w11 = tx * ty;
+      const T* q = up + (int64_t)(s.iy + 1) * P + (s.ix + 1);
+      return w00 * q[0] + w10 * q[1] + w01 * q[P] + w11 * q[P + 1];
+    };
+    const int rng[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m1 = rng[2 * r + 1];
+      int m = rng[2 * r] + lane;
+      // two samples per lane in flight
+      for (; m + LANES < m1; m += 2 * LANES) {
+        const T t0 = tap(m);
+        const T t1 = tap(m + LANES);
+        acc += t0 + t1;
       }
+      if (m < m1) acc += tap(m);
     }
   }
   acc = group_sum<LANES>(acc);
@@ -180,8 +190,7 @@ static void fwd_mode_dispatch(int mode, int lanes_log2, int blocks, const FwdArg
 
 template <class T>
 void launch_forward(int mode, const FwdArgs<T>& a, int lanes_log2, hipStream_t s) {
-  const int bpb = 256 >> lanes_log2;
-  const int blocks = (a.g.n_det * a.g.n_t + bpb - 1) / bpb;
+  const int blocks = fwd_grid(a.g.n_det, a.g.n_t, lanes_log2);
   fwd_mode_dispatch<T>(mode, lanes_log2, blocks, a, nullptr, nullptr, 1, s);
 }
 
@@ -263,11 +272,10 @@ __global__ __launch_bounds__(256) void adj_kernel(AdjArgs<T> a0, const AdjArgs<T
         if (mlo < 0) mlo += M;
       }
       const T gw = gk * (T)rr.y;
-      const double2* __restrict__ cs = g.cs + mo.y;
       for (int j = lane; j < cnt; j += 64) {
         int m = mlo + j;
         if (m >= M) m -= M;
-        const Sample s = arc_sample(p, rr.x, cs[m]);
+        const Sample s = arc_sample(p, rr.x, table_cs<T>(g, mo.y + m));
         const int lx = s.ix - (I0 - 1), ly = s.iy - (J0 - 1);
         if ((unsigned)lx <= (unsigned)TILE && (unsigned)ly <= (unsigned)TILE) {
           const T tx = (T)s.tx, ty = (T)s.ty;
@@ -368,7 +376,7 @@ pat::GeomDev pat_geometry_s::dev() const {
   g.det = pat::ptr<double2>(d_det);
   g.rad = pat::ptr<double2>(d_rad);
   g.moff = pat::ptr<int2>(d_moff);
-  g.cs = pat::ptr<double2>(d_cs);
+  g.cs = d_cs.p;
   g.win = pat::ptr<int4>(d_win);
   g.kscale = h / (desc.c * desc.dt);
   g.koff = desc.t0 / desc.dt;

@@ -177,7 +177,7 @@ struct Inst {
   const T* f = nullptr;
   T* u_out = nullptr;
   pat_solve_info* info = nullptr;
-  DevBuf u, ubar_pad, q, r, v, vbar, s, upad_gap, atq_part, red, dmat;
+  DevBuf u, ubar_pad, q, r, v, vbar, s, upad_gap, atq_part, atq64, red, dmat;
   pat_precond_s* pc = nullptr;
   std::unique_ptr<pat_precond_s> own_pc;
   int n_fwd = 0, n_pix = 0, n_adj = 0, n_csr = 0, red_stride = 0;
@@ -252,8 +252,8 @@ class Solver {
     I.csr = g->adj_mode == 1;
     if (I.csr) g->ensure_csr(s);
     I.atq_part.alloc(sizeof(T) * (I.csr ? 1 : gd.n_groups) * N);
-    const int bpb = 256 >> lanes_log2;
-    I.n_fwd = (int)((nb + bpb - 1) / bpb);
+    if (I.csr) I.atq64.alloc(sizeof(double) * N);
+    I.n_fwd = fwd_grid(g->n_det, g->n_t, lanes_log2);
     I.n_pix = pix_blocks(N);
     I.n_adj = I.csr ? 0 : gd.tiles_x * gd.tiles_y * gd.n_groups;
     I.n_csr = I.csr ? (int)((N + 3) / 4) : 0;
@@ -293,6 +293,7 @@ class Solver {
     d.tau_u = ptr<T>(I.pc->tau_u);
     d.tau_v = ptr<T>(I.pc->tau_v);
     d.atq_part = ptr<T>(I.atq_part);
+    d.atq64 = ptr<double>(I.atq64);
     d.upad_gap = ptr<T>(I.upad_gap);
     d.red = ptr<double>(I.red);
     d.red_stride = I.red_stride;
@@ -332,6 +333,7 @@ class Solver {
         c.val = ptr<T>(I.g->csr_val);
         c.x = ptr<T>(I.q);
         c.y = ptr<T>(I.atq_part);
+        c.y64 = ptr<double>(I.atq64);
         c.n_rows = I.g->n_pix();
         cd.push_back(c);
         cs.push_back(cs.back() + I.n_csr);
@@ -391,8 +393,13 @@ class Solver {
     launch_forward_batched<T>(FWD_DUAL, L, lanes_log2, s);
     launch_reg_dual<T>(L, s);
     if (L.n_adj > 0) launch_adjoint_batched<T>(L, s);
-    if (L.n_csr > 0)
+    if (L.n_csr > 0) {
       launch_csr_spmv_batched<T>(ptr<CsrArgs<T>>(L.csr), ptr<int>(L.csr_start), L.n_csr, L.csr_total, s);
+      // check iterations: A^T q once more with FP64 accumulation for the gap
+      if (check)
+        launch_csr_spmv_batched<T>(ptr<CsrArgs<T>>(L.csr), ptr<int>(L.csr_start), L.n_csr, L.csr_total,
+                                   s, true);
+    }
     launch_primal<T>(L, check, s);
     if (check) enqueue_gap(c);
   }

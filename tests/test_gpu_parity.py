@@ -69,8 +69,8 @@ def test_forward_adjoint_elementwise(name, dt, adj):
     print(f"case {name} {dt} {adj}: nx={og.nx} ny={og.ny} n_det={og.n_det} n_t={og.n_t}", flush=True)
     fu = host(g.forward(to_dev(u.reshape(og.ny, og.nx), DT[dt])))
     aty = host(g.adjoint(to_dev(y.reshape(og.n_det, og.n_t), DT[dt])))
-    assert rel(fu, A @ u) <= TOL_APPLY[dt]
-    assert rel(aty, A.T @ y) <= TOL_APPLY[dt]
+    ef, ea = rel(fu, A @ u), rel(aty, A.T @ y)
+    assert ef <= TOL_APPLY[dt] and ea <= TOL_APPLY[dt], (ef, ea)
 
 
 @pytest.mark.parametrize("launch", [(4, 16, 1), (5, 32, 3), (6, 64, 7)])
@@ -84,7 +84,8 @@ def test_launch_shapes_agree_with_oracle(launch):
     y = rng.standard_normal(og.n_bins)
     fu = host(g.forward(to_dev(u.reshape(og.ny, og.nx), torch.float32)))
     aty = host(g.adjoint(to_dev(y.reshape(og.n_det, og.n_t), torch.float32)))
-    assert rel(fu, A @ u) <= 1e-5 and rel(aty, A.T @ y) <= 1e-5
+    ef, ea = rel(fu, A @ u), rel(aty, A.T @ y)
+    assert ef <= 1e-5 and ea <= 1e-5, (ef, ea)
 
 
 @pytest.mark.parametrize("adj", ["csr", "scatter"])
@@ -130,10 +131,12 @@ def test_full_size_sampled_rows_columns_and_dot(name, adj):
     aty = host(g.adjoint(to_dev(y, torch.float32))).ravel()
     bins = np.sort(rng.choice(og.n_bins, 96, replace=False))
     ref_rows = OG.forward_rows(og, bins) @ u.ravel()
-    assert rel(fu[bins], ref_rows) <= 1e-5
+    er = rel(fu[bins], ref_rows)
+    assert er <= 1e-5, er
     pix = np.sort(rng.choice(og.n_pix, 12, replace=False))
     ref_cols = np.array([column_of_A(og, j) @ y.ravel() for j in pix])
-    assert rel(aty[pix], ref_cols) <= 1e-5
+    ec = rel(aty[pix], ref_cols)
+    assert ec <= 1e-5, ec
     lhs = float(fu @ y.ravel())
     rhs = float(u.ravel() @ aty)
     assert abs(lhs - rhs) <= 1e-5 * np.linalg.norm(fu) * np.linalg.norm(y)
@@ -156,14 +159,17 @@ def test_diag_preconditioner(kind, dt):
     ref = OP.precond_diag(p)
     reg = pat.Reg(kind, 0.02, 0.04, 0.3, to_dev(th, DT[dt]) if kind == "dtv" else None)
     pc = pat.Precond(g, reg, "diag")
-    tol = 1e-12 if dt == "f64" else 1e-6
-    assert rel(host(pc.get("sigma_q")), ref["sigma_q"]) <= tol
-    assert rel(host(pc.get("tau_u")), ref["tau_u"]) <= tol
+    # sigma_q = 1/(A 1): it carries the per-apply error of A (FP32 table of
+    # cos/sin with FP64 positions: a few 1e-6)
+    tol = 1e-12 if dt == "f64" else TOL_APPLY["f32"]
+    errs = {"sigma_q": rel(host(pc.get("sigma_q")), ref["sigma_q"]),
+            "tau_u": rel(host(pc.get("tau_u")), ref["tau_u"])}
     if kind != "tikhonov":
-        assert rel(host(pc.get("sigma_r")), ref["sigma_r"]) <= tol
+        errs["sigma_r"] = rel(host(pc.get("sigma_r")), ref["sigma_r"])
     if kind == "tgv":
-        assert rel(host(pc.get("sigma_s")), ref["sigma_s"]) <= tol
-        assert rel(host(pc.get("tau_v")), ref["tau_v"].ravel()) <= tol
+        errs["sigma_s"] = rel(host(pc.get("sigma_s")), ref["sigma_s"])
+        errs["tau_v"] = rel(host(pc.get("tau_v")), ref["tau_v"].ravel())
+    assert max(errs.values()) <= tol, errs
 
 
 @pytest.mark.parametrize("kind", ["tv", "tgv", "dtv"])
@@ -208,10 +214,12 @@ def test_fixed_iterations_full_state(kind, dt):
     tol = 1e-10 if dt == "f64" else 1e-4
     print(f"{kind} {dt}: rel u {rel(got['u'], ref['u']):.2e}", flush=True)
     assert info["iters"] == 60
-    assert rel(host(u), ref["u"]) <= tol
+    eu = rel(host(u), ref["u"])
+    assert eu <= tol, eu
     for key in ("u", "ubar", "q", "r", "v", "vbar", "s"):
         if key in got and key in ref:
-            assert rel(got[key], ref[key]) <= tol, key
+            e = rel(got[key], ref[key])
+            assert e <= tol, (key, e)
     g_ref = OP.gap_terms(p, ref, 2.0)
     assert info["primal"] == pytest.approx(g_ref["P"], rel=1e-9 if dt == "f64" else 1e-4)
     # near convergence the gap is a small difference of O(P) terms: compare on the scale of P
