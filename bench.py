@@ -11,7 +11,7 @@ forward / adjoint apply rates, the roofline of the dominant kernel, the
 batched and warm-start results when requested, and the FP64 CPU oracle timed
 on a bounded sample of the same workload.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--cap N] [--no-cpu]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--cap N] [--no-cpu] [--no-batched]
 """
 from __future__ import annotations
 
@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--steps", type=int, default=1)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--cap", type=int, default=100000,
                    help="iteration cap of one solve (the gap target decides the end)")
@@ -43,6 +43,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--apply-reps", type=int, default=50)
     p.add_argument("--dtype", default="f64", choices=["f64", "f32"])
+    p.add_argument("--no-batched", action="store_true", help="skip the batched leg")
     return p.parse_args()
 
 
@@ -63,7 +64,7 @@ def make_inputs(pat, torch, seed):
     fc = fc.cpu().numpy()
     gf.close()
     f = fc + wl.noise * np.linalg.norm(fc) / math.sqrt(fc.size) * case["noise"]
-    return wl, desc, case, f
+    return wl, desc, case, f, fc
 
 
 def time_apply(fn, reps, torch):
@@ -78,6 +79,40 @@ def time_apply(fn, reps, torch):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps * 1e-3
+
+
+def batched_leg(pat, torch, g, wl, fc, reg, pc, args, tdt, n_wl=4):
+    """Wavelengths of one phantom (amplitude x U(0.3, 1), independent noise)
+    share the geometry: one batched solve vs the same solves one by one."""
+    import phantoms
+    rng = np.random.default_rng([args.seed, 2])
+    amps = rng.uniform(0.3, 1.0, n_wl)
+    fs = []
+    for w in range(n_wl):
+        fw = amps[w] * fc
+        nz = phantoms.unit_noise(np.random.default_rng([args.seed, 3, w]), wl.n_det, wl.n_t)
+        fw = fw + wl.noise * np.linalg.norm(fw) / math.sqrt(fw.size) * nz
+        fs.append(torch.tensor(fw, dtype=tdt, device="cuda"))
+    kw = dict(max_iter=args.cap, gap_tol=wl.gap_tol, gap_every=args.gap_every,
+              graph_block=args.gap_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, infos_b, st_b = pat.solve_batched([(g, f, reg, pc) for f in fs], **kw)
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t0
+    t_seq, iters_seq = 0.0, []
+    for f in fs:
+        t0 = time.perf_counter()
+        _, info, _ = pat.solve(g, f, reg, precond=pc, **kw)
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - t0
+        iters_seq.append(info["iters"])
+    return dict(instances=n_wl, shared_geometry=True, batched_s=t_batched, sequential_s=t_seq,
+                per_reconstruction_batched_s=t_batched / n_wl,
+                per_reconstruction_sequential_s=t_seq / n_wl,
+                speedup=t_seq / t_batched, iters_batched=[i["iters"] for i in infos_b],
+                iters_sequential=iters_seq,
+                rel_gaps=[i["rel_gap"] for i in infos_b], status=st_b)
 
 
 def cpu_baseline(desc, f, wl, gpu_iters, budget_s=20.0):
@@ -133,7 +168,7 @@ def main():
     torch.cuda.init()
     dev = torch.cuda.get_device_properties(0)
     log(f"device {dev.name}")
-    wl, desc, case, f_np = make_inputs(pat, torch, args.seed)
+    wl, desc, case, f_np, fc_np = make_inputs(pat, torch, args.seed)
     tdt = torch.float64 if args.dtype == "f64" else torch.float32
     esz = 8 if args.dtype == "f64" else 4
     g = pat.Geometry(dtype=tdt, **desc)
@@ -220,6 +255,10 @@ def main():
         "apply": apply,
         "roofline": roofline,
     }
+    if not args.no_batched:
+        log("batched leg: 4 wavelengths sharing the geometry")
+        out["batched"] = batched_leg(pat, torch, g, wl, fc_np, reg, pc, args, tdt)
+        log(f"batched: {out['batched']}")
     if not args.no_cpu:
         log("cpu baseline (oracle, bounded sample)")
         out["cpu_baseline"] = cpu_baseline(desc, f_np, wl, iters)

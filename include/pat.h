@@ -210,11 +210,13 @@ pat_status pat_pdhg_solve(pat_geometry g, const void* d_f, const pat_regulariser
                           pat_solve_info* info, void* stream);
 
 /* n independent reconstructions advanced together: every kernel launch covers
- * all active instances (FP32 geometries only), iterations run in captured
- * HIP graphs of opts[0].graph_block iterations, and instances whose gap
- * reaches their gap_tol retire at block ends. Arrays have n entries; per
- * instance the arguments mean what they mean for pat_pdhg_solve. Returns
- * PAT_OK if all converged, PAT_NOT_CONVERGED if any hit its cap. */
+ * all active instances (one element type for the whole batch), instances
+ * that share a geometry share each pass over its stored A^T (up to 8 per
+ * pass), iterations run in captured HIP graphs of opts[0].graph_block
+ * iterations (gap every opts[0].gap_every), and instances whose gap reaches
+ * their gap_tol retire at block ends. Arrays have n entries; per instance the
+ * arguments mean what they mean for pat_pdhg_solve. Returns PAT_OK if all
+ * converged, PAT_NOT_CONVERGED if any hit its cap. Synchronous on return. */
 pat_status pat_pdhg_solve_batched(int32_t n, const pat_geometry* g, const void* const* d_f,
                                   const pat_regulariser* reg, const pat_solve_opts* opts,
                                   void* const* d_u_out, pat_solve_info* info, void* stream);

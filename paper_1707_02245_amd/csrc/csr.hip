@@ -200,6 +200,88 @@ __global__ __launch_bounds__(256) void csr_spmv_kernel(CsrArgs<T> a0, const CsrA
   }
 }
 
+// Multi-RHS variant: one wave per row; every (column, value) pair loaded once
+// serves all right-hand sides of the group.
+template <class T, bool WIDE, int R>
+__global__ __launch_bounds__(256) void csr_spmm_kernel(const CsrMultiArgs<T>* __restrict__ arr,
+                                                       const int* __restrict__ starts, int n_grp) {
+  int blk = blockIdx.x;
+  int lo = 0, hi = n_grp;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (starts[mid] <= blk) lo = mid; else hi = mid;
+  }
+  const CsrMultiArgs<T>& a = arr[lo];
+  blk -= starts[lo];
+  const int64_t row = (int64_t)blk * 4 + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (row >= a.n_rows) return;  // whole wave
+  const int nr = a.nrhs;
+  using Acc = typename std::conditional<WIDE, double, T>::type;
+  Acc acc[R];
+  const T* xs[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    acc[r] = Acc(0);
+    xs[r] = a.x[r];
+  }
+  const int64_t e0 = a.ptr[row], e1 = a.ptr[row + 1];
+  const T* __restrict__ val = a.val;
+  const int* __restrict__ col = a.col;
+  int64_t e = e0 + lane;
+  for (; e + 64 < e1; e += 128) {
+    const int c0 = __builtin_nontemporal_load(col + e);
+    const int c1 = __builtin_nontemporal_load(col + e + 64);
+    const T v0 = __builtin_nontemporal_load(val + e);
+    const T v1 = __builtin_nontemporal_load(val + e + 64);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (r < nr) acc[r] += (Acc)v0 * (Acc)xs[r][c0] + (Acc)v1 * (Acc)xs[r][c1];
+  }
+  if (e < e1) {
+    const int c0 = __builtin_nontemporal_load(col + e);
+    const T v0 = __builtin_nontemporal_load(val + e);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (r < nr) acc[r] += (Acc)v0 * (Acc)xs[r][c0];
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (r < nr) {
+      const Acc t = group_sum<64>(acc[r]);
+      if (lane == 0) {
+        if (WIDE) a.y64[r][row] = (double)t;
+        else a.y[r][row] = (T)t;
+      }
+    }
+  }
+}
+
+template <class T, bool WIDE>
+static void spmm_dispatch(int max_rhs, const CsrMultiArgs<T>* arr, const int* starts, int n_grp,
+                          int blocks, hipStream_t s) {
+  if (max_rhs <= 1)
+    hipLaunchKernelGGL((csr_spmm_kernel<T, WIDE, 1>), dim3(blocks), dim3(256), 0, s, arr, starts, n_grp);
+  else if (max_rhs <= 2)
+    hipLaunchKernelGGL((csr_spmm_kernel<T, WIDE, 2>), dim3(blocks), dim3(256), 0, s, arr, starts, n_grp);
+  else if (max_rhs <= 4)
+    hipLaunchKernelGGL((csr_spmm_kernel<T, WIDE, 4>), dim3(blocks), dim3(256), 0, s, arr, starts, n_grp);
+  else
+    hipLaunchKernelGGL((csr_spmm_kernel<T, WIDE, kMaxRhs>), dim3(blocks), dim3(256), 0, s, arr, starts, n_grp);
+}
+
+template <class T>
+void launch_csr_spmm_batched(const CsrMultiArgs<T>* arr, const int* starts, int n_grp, int total_blocks,
+                             hipStream_t s, bool wide, int max_rhs) {
+  if (total_blocks <= 0) return;
+  if (wide) spmm_dispatch<T, true>(max_rhs, arr, starts, n_grp, total_blocks, s);
+  else spmm_dispatch<T, false>(max_rhs, arr, starts, n_grp, total_blocks, s);
+  PAT_HIP(hipGetLastError());
+}
+
+template void launch_csr_spmm_batched<float>(const CsrMultiArgs<float>*, const int*, int, int, hipStream_t, bool, int);
+template void launch_csr_spmm_batched<double>(const CsrMultiArgs<double>*, const int*, int, int, hipStream_t, bool, int);
+
 template <class T>
 void launch_csr_spmv(const CsrArgs<T>& a, hipStream_t s) {
   const int blocks = (int)((a.n_rows + 3) / 4);

@@ -230,6 +230,21 @@ struct CsrArgs {
   int64_t n_rows;
 };
 
+// Y_r = M X_r for up to kMaxRhs right-hand sides sharing one CSR matrix (the
+// matrix streams once for all of them).
+constexpr int kMaxRhs = 8;
+template <class T>
+struct CsrMultiArgs {
+  const int64_t* ptr;
+  const int* col;
+  const T* val;
+  int64_t n_rows;
+  int nrhs;
+  const T* x[kMaxRhs];
+  T* y[kMaxRhs];
+  double* y64[kMaxRhs];
+};
+
 // Ordered final sum of one instance's gap partials.
 struct GapFinishArgs {
   const double* red;

@@ -72,7 +72,7 @@ struct Launch {
   int fwd_total = 0, adj_total = 0, pix_total = 0;
   // instances whose adjoint is the stored CSR of A^T
   DevBuf csr, csr_start;
-  int n_adj = 0, n_csr = 0, csr_total = 0;
+  int n_adj = 0, n_csr = 0, csr_total = 0, csr_max_rhs = 1;
   int lanes_log2 = 6;   // shared by every instance of one launch
   int max_tile = 32;    // shared by every instance of one launch
 };
@@ -105,6 +105,9 @@ void launch_csr_spmv(const CsrArgs<T>& a, hipStream_t s);
 template <class T>
 void launch_csr_spmv_batched(const CsrArgs<T>* arr, const int* starts, int n_inst, int total_blocks,
                              hipStream_t s, bool wide = false);
+template <class T>
+void launch_csr_spmm_batched(const CsrMultiArgs<T>* arr, const int* starts, int n_grp, int total_blocks,
+                             hipStream_t s, bool wide, int max_rhs);
 
 // ---- launchers (pdhg.hip)
 template <class T>

@@ -305,7 +305,7 @@ class Solver {
     const int n = (int)act.size();
     std::vector<FwdArgs<T>> fd(n), fg(n);
     std::vector<AdjArgs<T>> ad;
-    std::vector<CsrArgs<T>> cd;
+    std::vector<CsrMultiArgs<T>> cd;
     std::vector<InstDev<T>> id(n);
     std::vector<GapFinishArgs> gf(n);
     std::vector<int> fs(n + 1), as(1, 0), cs(1, 0), ps(n + 1);
@@ -327,16 +327,24 @@ class Solver {
       fg[k].red = ptr<double>(I.red);
       fg[k].red_stride = I.red_stride;
       if (I.csr) {
-        CsrArgs<T> c{};
-        c.ptr = ptr<int64_t>(I.g->csr_ptr);
-        c.col = ptr<int>(I.g->csr_col);
-        c.val = ptr<T>(I.g->csr_val);
-        c.x = ptr<T>(I.q);
-        c.y = ptr<T>(I.atq_part);
-        c.y64 = ptr<double>(I.atq64);
-        c.n_rows = I.g->n_pix();
-        cd.push_back(c);
-        cs.push_back(cs.back() + I.n_csr);
+        // instances sharing a geometry share one pass over its stored A^T
+        CsrMultiArgs<T>* grp = nullptr;
+        for (auto& c : cd)
+          if (c.ptr == ptr<int64_t>(I.g->csr_ptr) && c.nrhs < kMaxRhs) grp = &c;
+        if (!grp) {
+          cd.push_back(CsrMultiArgs<T>{});
+          grp = &cd.back();
+          grp->ptr = ptr<int64_t>(I.g->csr_ptr);
+          grp->col = ptr<int>(I.g->csr_col);
+          grp->val = ptr<T>(I.g->csr_val);
+          grp->n_rows = I.g->n_pix();
+          grp->nrhs = 0;
+          cs.push_back(cs.back() + I.n_csr);
+        }
+        grp->x[grp->nrhs] = ptr<T>(I.q);
+        grp->y[grp->nrhs] = ptr<T>(I.atq_part);
+        grp->y64[grp->nrhs] = ptr<double>(I.atq64);
+        ++grp->nrhs;
       } else {
         AdjArgs<T> a{};
         a.g = gd;
@@ -357,7 +365,7 @@ class Solver {
     up(L.fwd, fd.data(), sizeof(FwdArgs<T>) * n);
     up(L.fwd_gap, fg.data(), sizeof(FwdArgs<T>) * n);
     if (!ad.empty()) up(L.adj, ad.data(), sizeof(AdjArgs<T>) * ad.size());
-    if (!cd.empty()) up(L.csr, cd.data(), sizeof(CsrArgs<T>) * cd.size());
+    if (!cd.empty()) up(L.csr, cd.data(), sizeof(CsrMultiArgs<T>) * cd.size());
     up(L.inst, id.data(), sizeof(InstDev<T>) * n);
     up(L.gapfin, gf.data(), sizeof(GapFinishArgs) * n);
     up(L.fwd_start, fs.data(), sizeof(int) * (n + 1));
@@ -370,6 +378,8 @@ class Solver {
     L.adj_total = as.back();
     L.n_adj = (int)ad.size();
     L.n_csr = (int)cd.size();
+    L.csr_max_rhs = 1;
+    for (const auto& c : cd) L.csr_max_rhs = std::max(L.csr_max_rhs, c.nrhs);
     L.csr_total = cs.back();
     L.pix_total = ps[n];
     L.lanes_log2 = lanes_log2;
@@ -394,11 +404,12 @@ class Solver {
     launch_reg_dual<T>(L, s);
     if (L.n_adj > 0) launch_adjoint_batched<T>(L, s);
     if (L.n_csr > 0) {
-      launch_csr_spmv_batched<T>(ptr<CsrArgs<T>>(L.csr), ptr<int>(L.csr_start), L.n_csr, L.csr_total, s);
+      launch_csr_spmm_batched<T>(ptr<CsrMultiArgs<T>>(L.csr), ptr<int>(L.csr_start), L.n_csr,
+                                 L.csr_total, s, false, L.csr_max_rhs);
       // check iterations: A^T q once more with FP64 accumulation for the gap
       if (check)
-        launch_csr_spmv_batched<T>(ptr<CsrArgs<T>>(L.csr), ptr<int>(L.csr_start), L.n_csr, L.csr_total,
-                                   s, true);
+        launch_csr_spmm_batched<T>(ptr<CsrMultiArgs<T>>(L.csr), ptr<int>(L.csr_start), L.n_csr,
+                                   L.csr_total, s, true, L.csr_max_rhs);
     }
     launch_primal<T>(L, check, s);
     if (check) enqueue_gap(c);
@@ -784,8 +795,10 @@ extern "C" pat_status pat_pdhg_solve_batched(int32_t n, const pat_geometry* g, c
     PAT_CHECK_ARG(g && d_f && reg && opts && d_u_out, "NULL array");
     for (int i = 0; i < n; ++i) {
       pat::validate_instance(g[i], d_f[i], &reg[i], &opts[i], d_u_out[i]);
-      PAT_CHECK_ARG(g[i]->dtype == PAT_F32, "batched solves take FP32 geometries");
+      PAT_CHECK_ARG(g[i]->dtype == g[0]->dtype, "batched solves need one element type");
     }
+    if (g[0]->dtype == PAT_F64)
+      return pat::solve_impl<double>(n, g, d_f, reg, opts, d_u_out, info, stream);
     return pat::solve_impl<float>(n, g, d_f, reg, opts, d_u_out, info, stream);
   });
 }

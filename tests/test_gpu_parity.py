@@ -319,15 +319,24 @@ def test_converges_to_gap_and_matches_oracle_objective():
         assert info["primal"] == pytest.approx(ref["history"][-1]["P"], rel=1e-4)
 
 
-def test_batched_matches_single_solves():
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_batched_matches_single_solves(dt):
+    """Mixed sizes and regularisers in one batch; two instances share a
+    geometry (one pass over its stored A^T serves both)."""
     problems, singles = [], []
     specs = [("ragged", "tv", 0.01), ("arc90", "tgv", 0.01), ("tv64", "dtv", 0.02),
              ("ragged", "tgv", 0.005)]
+    shared = None
     for name, kind, lam in specs:
-        d, og, g = _geoms(name, "f32")
+        if name == "ragged" and shared is not None:
+            d, og, g = shared
+        else:
+            d, og, g = _geoms(name, dt)
+            if name == "ragged":
+                shared = (d, og, g)
         A = OG.forward_matrix(og)
-        f = to_dev(A @ np.random.default_rng(len(problems)).uniform(0, 1, og.n_pix), torch.float32)
-        reg, _ = _reg_pair(kind, og, "f32", lam)
+        f = to_dev(A @ np.random.default_rng(len(problems)).uniform(0, 1, og.n_pix), DT[dt])
+        reg, _ = _reg_pair(kind, og, dt, lam)
         problems.append((g, f, reg))
     us, infos, st = pat.solve_batched(problems, max_iter=300, gap_tol=1e-3, gap_every=10,
                                       graph_block=50)
