@@ -118,6 +118,21 @@ pat_status pat_geometry_set_launch(pat_geometry g, int32_t fwd_lanes_log2,
  * same weight products); results agree to rounding order. */
 pat_status pat_geometry_set_adjoint(pat_geometry g, int32_t mode, void* stream);
 
+/* Autotuner of the projector launch parameters. Times, with HIP events over
+ * `reps` stand-alone applies on `stream`, the forward with 16/32/64 lanes per
+ * bin and the adjoint as stored CSR or as tile scatter (tiles 16/32/64,
+ * several detector-group sizes), and keeps the fastest of each. If
+ * cache_path is non-NULL the choice is read from / appended to that text
+ * file, keyed by device architecture, geometry shape and element type, so a
+ * later call with the same key times nothing. `out` may be NULL. */
+typedef struct {
+  int32_t fwd_lanes_log2, adj_mode, adj_tile, adj_det_group;
+  double forward_ms, adjoint_ms;  /* measured (or cached) time per apply */
+  int32_t from_cache;
+} pat_autotune_result;
+pat_status pat_geometry_autotune(pat_geometry g, const char* cache_path, int32_t reps,
+                                 void* stream, pat_autotune_result* out);
+
 /* f = A u (Sec. 4.1 eq. K_def, discretised as above).
  * d_u: device [ny][nx]; d_f: device [n_det][n_t]; element type of g. */
 pat_status pat_forward(pat_geometry g, const void* d_u, void* d_f, void* stream);

@@ -46,6 +46,14 @@ class GeometryInfo(C.Structure):
     ]
 
 
+class AutotuneResult(C.Structure):
+    _fields_ = [
+        ("fwd_lanes_log2", C.c_int32), ("adj_mode", C.c_int32), ("adj_tile", C.c_int32),
+        ("adj_det_group", C.c_int32), ("forward_ms", C.c_double), ("adjoint_ms", C.c_double),
+        ("from_cache", C.c_int32),
+    ]
+
+
 class Regulariser(C.Structure):
     _fields_ = [
         ("kind", C.c_int32), ("lam", C.c_double), ("tgv_alpha0", C.c_double),
@@ -80,6 +88,8 @@ _SIGS = {
     "pat_geometry_get_info": ([C.c_void_p, C.POINTER(GeometryInfo)], C.c_int),
     "pat_geometry_set_launch": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32], C.c_int),
     "pat_geometry_set_adjoint": ([C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
+    "pat_geometry_autotune": ([C.c_void_p, C.c_char_p, C.c_int32, C.c_void_p,
+                               C.POINTER(AutotuneResult)], C.c_int),
     "pat_forward": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "pat_adjoint": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "pat_precond": ([C.c_void_p, C.POINTER(Regulariser), C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),

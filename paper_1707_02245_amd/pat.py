@@ -97,6 +97,14 @@ class Geometry:
         L.check(L.load().pat_geometry_set_adjoint(self._h, m, _stream()))
         return self.refresh_info()
 
+    def autotune(self, cache_path=None, reps=10):
+        """pat_geometry_autotune: time the launch candidates (or read the cache)."""
+        res = L.AutotuneResult()
+        path = cache_path.encode() if cache_path else None
+        L.check(L.load().pat_geometry_autotune(self._h, path, reps, _stream(), C.byref(res)))
+        self.refresh_info()
+        return {k: getattr(res, k) for k, _ in res._fields_}
+
     def close(self):
         if getattr(self, "_h", None):
             L.load().pat_geometry_destroy(self._h)

@@ -344,3 +344,24 @@ def test_batched_matches_single_solves(dt):
         u1, i1, _ = pat.solve(g, f, reg, max_iter=300, gap_tol=1e-3, gap_every=10, graph_block=50)
         assert info["iters"] == i1["iters"]
         assert np.array_equal(host(u), host(u1))
+
+
+def test_autotune_and_cache(tmp_path):
+    d, og, g = _geoms("arc90", "f32")
+    path = str(tmp_path / "tune.txt")
+    r1 = g.autotune(path, reps=3)
+    assert r1["from_cache"] == 0 and r1["fwd_lanes_log2"] in (4, 5, 6)
+    assert open(path).read().count("\n") == 1
+    g2 = pat.Geometry(dtype=torch.float32, **d)
+    r2 = g2.autotune(path, reps=3)
+    assert r2["from_cache"] == 1
+    assert (r2["fwd_lanes_log2"], r2["adj_mode"], r2["adj_tile"], r2["adj_det_group"]) == \
+        (r1["fwd_lanes_log2"], r1["adj_mode"], r1["adj_tile"], r1["adj_det_group"])
+    A = OG.forward_matrix(og)
+    rng = np.random.default_rng(3)
+    u = rng.standard_normal(og.n_pix)
+    y = rng.standard_normal(og.n_bins)
+    fu = host(g2.forward(to_dev(u.reshape(og.ny, og.nx), torch.float32)))
+    aty = host(g2.adjoint(to_dev(y.reshape(og.n_det, og.n_t), torch.float32)))
+    ef, ea = rel(fu, A @ u), rel(aty, A.T @ y)
+    assert ef <= 1e-5 and ea <= 1e-5, (ef, ea)
