@@ -236,6 +236,59 @@ pat_status pat_pdhg_solve_batched(int32_t n, const pat_geometry* g, const void* 
                                   const pat_regulariser* reg, const pat_solve_opts* opts,
                                   void* const* d_u_out, pat_solve_info* info, void* stream);
 
+/* ---- Learned warm start -------------------------------------------------
+ * A U-Net (`levels` levels, base_ch channels at the top, doubling per level;
+ * 3x3 convolutions with ReLU, 2x2 max pooling, 2x2 stride-2 transposed
+ * convolutions, skip concatenation, 1x1 head) maps the normalised
+ * backprojection x = (A^T f / A^T 1) / s, s = mean |A^T f / A^T 1|, to the
+ * normalised reconstruction u / s. Weights are FP32 masters used as bf16 in
+ * the matrix-core convolutions (FP32 accumulation); activations and the
+ * gradients passed between layers are bf16. The network only changes where
+ * PDHG starts (pat_solve_opts.d_u0); the gap decides the result. Images
+ * ([n][h][w] FP32, device) need h and w divisible by 2^(levels-1).
+ * Parameters are one FP32 vector in the order: per level l = 0..levels-1 two
+ * 3x3 convolutions (weights [Cout][3][3][Cin], bias [Cout]); per decoder level
+ * l = levels-2..0 the transposed convolution ([2][2][Cin][Cout], [Cout]) and
+ * two 3x3 convolutions; the head ([C0], [1]). */
+typedef struct pat_unet_s* pat_unet;
+typedef struct {
+  int32_t epochs, batch;  /* passes over the data; images per Adam step */
+  double lr;              /* Adam step size (beta1 0.9, beta2 0.999, eps 1e-8) */
+  uint64_t seed;          /* shuffling order */
+} pat_train_opts;
+
+/* He-normal weights from `seed`, zero biases. */
+pat_status pat_warmstart_create(int32_t levels, int32_t base_ch, uint64_t seed, pat_unet* out);
+pat_status pat_warmstart_destroy(pat_unet n);
+pat_status pat_warmstart_num_params(pat_unet n, int64_t* out);
+/* Copy the FP32 parameter vector to / from device memory (set resets Adam). */
+pat_status pat_warmstart_get_params(pat_unet n, float* d_dst, void* stream);
+pat_status pat_warmstart_set_params(pat_unet n, const float* d_src, void* stream);
+/* y = net(x) for `batch` images; d_in, d_out device FP32 [batch][h][w]. */
+pat_status pat_warmstart_forward(pat_unet n, int32_t batch, int32_t h, int32_t w, const float* d_in,
+                                 float* d_out, void* stream);
+/* Mean squared error of net(x) against d_target and its gradient with respect
+ * to every parameter (device FP32 [num_params]); *loss (host) if non-NULL. */
+pat_status pat_warmstart_grad(pat_unet n, int32_t batch, int32_t h, int32_t w, const float* d_in,
+                              const float* d_target, float* d_grad, double* loss, void* stream);
+/* Adam on the mean squared error over `count` pairs (device FP32
+ * [count][h][w] each), `epochs` shuffled passes in batches of opts->batch.
+ * *final_loss (host): mean loss of the last epoch. */
+pat_status pat_warmstart_train(pat_unet n, int32_t count, int32_t h, int32_t w, const float* d_inputs,
+                               const float* d_targets, const pat_train_opts* opts, double* final_loss,
+                               void* stream);
+/* Checkpoint: parameters and Adam state, raw little-endian with a header. */
+pat_status pat_warmstart_save(pat_unet n, const char* path);
+pat_status pat_warmstart_load(pat_unet n, const char* path);
+/* Network input (and target) of one measurement: d_f data of g (element type
+ * of g); d_u an optional reconstruction of the same type; outputs FP32 [ny][nx]
+ * d_x = normalised backprojection, d_t = d_u / s, and d_scale[0] = s. */
+pat_status pat_warmstart_normalize(pat_geometry g, const void* d_f, const void* d_u, float* d_x,
+                                   float* d_t, float* d_scale, void* stream);
+/* d_u0 = s net(x) for data d_f of g (element type of g), ready as
+ * pat_solve_opts.d_u0. Synchronous on return. */
+pat_status pat_warmstart_infer(pat_unet n, pat_geometry g, const void* d_f, void* d_u0, void* stream);
+
 const char* pat_status_string(pat_status s);
 /* Message of the last error on the calling thread ("" if none). */
 const char* pat_last_error(void);

@@ -82,6 +82,10 @@ class SolveInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TrainOpts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double), ("seed", C.c_uint64)]
+
+
 _SIGS = {
     "pat_geometry_create": ([C.POINTER(GeometryDesc), C.c_int, C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
     "pat_geometry_destroy": ([C.c_void_p], C.c_int),
@@ -101,6 +105,22 @@ _SIGS = {
     "pat_pdhg_solve_batched": ([C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                 C.POINTER(Regulariser), C.POINTER(SolveOpts), C.POINTER(C.c_void_p),
                                 C.POINTER(SolveInfo), C.c_void_p], C.c_int),
+    "pat_warmstart_create": ([C.c_int32, C.c_int32, C.c_uint64, C.POINTER(C.c_void_p)], C.c_int),
+    "pat_warmstart_destroy": ([C.c_void_p], C.c_int),
+    "pat_warmstart_num_params": ([C.c_void_p, C.POINTER(C.c_int64)], C.c_int),
+    "pat_warmstart_get_params": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "pat_warmstart_set_params": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "pat_warmstart_forward": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                               C.c_void_p], C.c_int),
+    "pat_warmstart_grad": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                            C.c_void_p, C.POINTER(C.c_double), C.c_void_p], C.c_int),
+    "pat_warmstart_train": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                             C.POINTER(TrainOpts), C.POINTER(C.c_double), C.c_void_p], C.c_int),
+    "pat_warmstart_save": ([C.c_void_p, C.c_char_p], C.c_int),
+    "pat_warmstart_load": ([C.c_void_p, C.c_char_p], C.c_int),
+    "pat_warmstart_normalize": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_void_p], C.c_int),
+    "pat_warmstart_infer": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "pat_status_string": ([C.c_int], C.c_char_p),
     "pat_last_error": ([], C.c_char_p),
 }

@@ -1,0 +1,67 @@
+// Internal definitions of the warm-start network kernels.
+#pragma once
+
+#include "pat_internal.hpp"
+
+namespace pat {
+namespace nn {
+
+// NHWC bf16 view: element (pixel p, channel c) at p * pitch + off + c.
+struct View {
+  const uint16_t* p = nullptr;
+  uint16_t* p16 = nullptr;
+  int H = 0, W = 0, C = 0, pitch = 0, off = 0;
+};
+
+inline View view(uint16_t* base, int H, int W, int C, int pitch, int off) {
+  View v;
+  v.p = base;
+  v.p16 = base;
+  v.H = H;
+  v.W = W;
+  v.C = C;
+  v.pitch = pitch;
+  v.off = off;
+  return v;
+}
+
+enum AMode { A_DIRECT = 0, A_CONV = 1, A_G22 = 2, A_T = 3, A_TG22 = 4 };
+enum BMode { B_W = 0, B_IM2COL = 1, B_T = 2 };
+enum EMode { E_ACT = 0, E_SHUF = 1, E_SPLIT = 2 };
+
+struct GemmDesc {
+  int M = 0, N = 0, K = 0, ksplit = 0;
+  int a_mode = A_DIRECT, a_sign = 1;
+  View a;
+  int b_mode = B_W;
+  View b;
+  const uint16_t* w = nullptr;  // B_W: [N][K]
+  int out_mode = E_ACT;
+  View out;                     // E_ACT, E_SHUF
+  float* out_f32 = nullptr;     // E_SPLIT: [nsplit][M][N]
+  const float* bias = nullptr;
+  int relu = 0;
+  View mask;                    // E_ACT: zero where mask <= 0 (null p: no mask)
+};
+
+void launch_gemm(const GemmDesc& d, hipStream_t s);
+void launch_splitk_reduce(const float* part, int nsplit, int M, int N, float* out, int permute_cout,
+                          hipStream_t s);
+void launch_maxpool(const View& in, const View& out, uint8_t* idx, int B, hipStream_t s);
+void launch_maxpool_back(const View& gout, const uint8_t* idx, const View& gskip, const View& act,
+                         const View& gin, int B, hipStream_t s);
+void launch_head(const View& h, const float* w, const float* b, float* y, int64_t P, hipStream_t s);
+void launch_mse(const float* y, const float* t, float* gy, double* part, double* loss, int64_t P,
+                hipStream_t s);
+void launch_head_back(const View& h, const float* w, const float* gy, const View& gh, float* part,
+                      int64_t P, int rows_per_block, hipStream_t s);
+void launch_colsum(const View& g, float* part, float* out, int64_t P, int rows_per_block, hipStream_t s);
+void launch_part_reduce(const float* part, int nblk, int C, int ld, float* out, hipStream_t s);
+void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                 float eps, float bc1, float bc2, hipStream_t s);
+void launch_prep_conv(const float* w, int Cout, int Cin, uint16_t* wf, uint16_t* wd, hipStream_t s);
+void launch_prep_convt(const float* w, int Cin, int Cout, uint16_t* wf, uint16_t* wd, hipStream_t s);
+void launch_to_bf16(const float* x, const View& out, int64_t P, hipStream_t s);
+
+}  // namespace nn
+}  // namespace pat

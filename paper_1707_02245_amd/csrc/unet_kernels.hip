@@ -1,0 +1,473 @@
+// Kernels of the warm-start network: a generic implicit-GEMM on the bf16 matrix
+// cores (FP32 accumulation) that serves every convolution of the network in
+// the forward pass and both backward passes, plus pooling, the 1x1 head, the
+// loss, bias gradients, split-K reduction, Adam and weight re-layout.
+//
+// Tensors are NHWC. Every activation view carries a channel pitch and offset,
+// so a transposed convolution writes the first half and an encoder
+// convolution the second half of one concatenation buffer without copies.
+//
+// The GEMM computes C[m][n] = sum_k A(m,k) B(n,k). A and B are fetched
+// element-wise through index maps (direct, 3x3 im2col with +/- tap offsets,
+// 2x2 sub-pixel gathers, transposed views), staged through LDS in 32-wide k
+// chunks and multiplied with __builtin_amdgcn_mfma_f32_16x16x16bf16_1k: lane
+// l supplies A[l%16][4(l/16)+r] and B[4(l/16)+r][l%16] and receives
+// D[4(l/16)+r][l%16], r = 0..3.
+
+#include "unet_internal.hpp"
+
+namespace pat {
+namespace nn {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
+  return (uint16_t)(u >> 16);
+}
+
+// ------------------------------------------------------------------ operand fetch
+
+__device__ __forceinline__ uint16_t fetch_a(const GemmDesc& d, int m, int k) {
+  if (m >= d.M || k >= d.K) return 0;
+  const View& v = d.a;
+  switch (d.a_mode) {
+    case A_DIRECT:
+      return v.p[(int64_t)m * v.pitch + v.off + k];
+    case A_CONV: {
+      const int tap = k / v.C, c = k - tap * v.C;
+      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+      const int x = m % v.W, t = m / v.W, y = t % v.H, b = t / v.H;
+      const int yy = y + d.a_sign * dy, xx = x + d.a_sign * dx;
+      if (yy < 0 || yy >= v.H || xx < 0 || xx >= v.W) return 0;
+      return v.p[((int64_t)(b * v.H + yy) * v.W + xx) * v.pitch + v.off + c];
+    }
+    case A_G22: {  // m: low-res pixel on (H/2, W/2); k = sub * C + c; source at full res
+      const int sub = k / v.C, c = k - sub * v.C;
+      const int w2 = v.W >> 1, h2 = v.H >> 1;
+      const int x = m % w2, t = m / w2, y = t % h2, b = t / h2;
+      const int yy = 2 * y + (sub >> 1), xx = 2 * x + (sub & 1);
+      return v.p[((int64_t)(b * v.H + yy) * v.W + xx) * v.pitch + v.off + c];
+    }
+    case A_T:  // m = channel, k = pixel
+      return v.p[(int64_t)k * v.pitch + v.off + m];
+    case A_TG22: {  // m = sub * C + c, k = low-res pixel; source at full res
+      const int sub = m / v.C, c = m - sub * v.C;
+      const int w2 = v.W >> 1, h2 = v.H >> 1;
+      const int x = k % w2, t = k / w2, y = t % h2, b = t / h2;
+      const int yy = 2 * y + (sub >> 1), xx = 2 * x + (sub & 1);
+      return v.p[((int64_t)(b * v.H + yy) * v.W + xx) * v.pitch + v.off + c];
+    }
+  }
+  return 0;
+}
+
+__device__ __forceinline__ uint16_t fetch_b(const GemmDesc& d, int n, int k) {
+  if (n >= d.N || k >= d.K) return 0;
+  const View& v = d.b;
+  switch (d.b_mode) {
+    case B_W:
+      return d.w[(int64_t)n * d.K + k];
+    case B_IM2COL: {  // n = tap * C + c, k = pixel
+      const int tap = n / v.C, c = n - tap * v.C;
+      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+      const int x = k % v.W, t = k / v.W, y = t % v.H, b = t / v.H;
+      const int yy = y + dy, xx = x + dx;
+      if (yy < 0 || yy >= v.H || xx < 0 || xx >= v.W) return 0;
+      return v.p[((int64_t)(b * v.H + yy) * v.W + xx) * v.pitch + v.off + c];
+    }
+    case B_T:  // n = channel, k = pixel
+      return v.p[(int64_t)k * v.pitch + v.off + n];
+  }
+  return 0;
+}
+
+// ------------------------------------------------------------------ the GEMM
+
+template <int WM, int WN>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmDesc d) {
+  constexpr int TM = 32 * WM, TN = 32 * WN, KC = 32, LD = KC + 8;
+  __shared__ uint16_t As[TM * LD];
+  __shared__ uint16_t Bs[TN * LD];
+  const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
+  const int kb = blockIdx.z * d.ksplit;
+  const int ke = min(d.K, kb + d.ksplit);
+  const int t = threadIdx.x, wave = t / 64, lane = t % 64;
+  const int wm = wave / WN, wn = wave % WN;
+  v4f acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = kb; k0 < ke; k0 += KC) {
+    // stage A (TM x KC) and B (TN x KC); element (row, kk) -> row * LD + kk
+    for (int e = t; e < TM * KC; e += 256) {
+      const int r = e / KC, kk = e % KC;
+      As[r * LD + kk] = (k0 + kk < ke) ? fetch_a(d, m0 + r, k0 + kk) : (uint16_t)0;
+    }
+    for (int e = t; e < TN * KC; e += 256) {
+      const int r = e / KC, kk = e % KC;
+      Bs[r * LD + kk] = (k0 + kk < ke) ? fetch_b(d, n0 + r, k0 + kk) : (uint16_t)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < KC; ks += 16) {
+      v4s a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const uint16_t* pa = As + (wm * 32 + i * 16 + lane % 16) * LD + ks + 4 * (lane / 16);
+        const uint16_t* pb = Bs + (wn * 32 + i * 16 + lane % 16) * LD + ks + 4 * (lane / 16);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          a[i][r] = (short)pa[r];
+          b[i][r] = (short)pb[r];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // epilogue
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int n = n0 + wn * 32 + j * 16 + lane % 16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * 32 + i * 16 + 4 * (lane / 16) + r;
+        if (m >= d.M || n >= d.N) continue;
+        float v = acc[i][j][r];
+        if (d.out_mode == E_SPLIT) {
+          d.out_f32[((int64_t)blockIdx.z * d.M + m) * d.N + n] = v;
+          continue;
+        }
+        if (d.out_mode == E_ACT) {
+          if (d.bias) v += d.bias[n];
+          if (d.relu) v = fmaxf(v, 0.f);
+          uint16_t h = f2bf(v);
+          if (d.mask.p && !(bf2f(d.mask.p[(int64_t)m * d.mask.pitch + d.mask.off + n]) > 0.f)) h = 0;
+          d.out.p16[(int64_t)m * d.out.pitch + d.out.off + n] = h;
+        } else if (d.out_mode == E_SHUF) {  // m: low-res pixel, n = sub * C + c
+          const int C = d.out.C;
+          const int sub = n / C, c = n - sub * C;
+          if (d.bias) v += d.bias[c];
+          const int w2 = d.out.W >> 1, h2 = d.out.H >> 1;
+          const int x = m % w2, tt = m / w2, y = tt % h2, b = tt / h2;
+          const int yy = 2 * y + (sub >> 1), xx = 2 * x + (sub & 1);
+          d.out.p16[((int64_t)(b * d.out.H + yy) * d.out.W + xx) * d.out.pitch + d.out.off + c] = f2bf(v);
+        }
+      }
+    }
+  }
+}
+
+void launch_gemm(const GemmDesc& d, hipStream_t s) {
+  const int nsplit = (d.K + d.ksplit - 1) / d.ksplit;
+  if (d.N <= 32) {
+    dim3 grid((d.M + 127) / 128, (d.N + 31) / 32, nsplit);
+    hipLaunchKernelGGL((gemm_kernel<4, 1>), grid, dim3(256), 0, s, d);
+  } else {
+    dim3 grid((d.M + 63) / 64, (d.N + 63) / 64, nsplit);
+    hipLaunchKernelGGL((gemm_kernel<2, 2>), grid, dim3(256), 0, s, d);
+  }
+  PAT_HIP(hipGetLastError());
+}
+
+// out[m][n] (with optional [ci][co] <- [(a,e,co)][ci] permutation) = sum_z part[z][m][n]
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(const float* __restrict__ part, int nsplit,
+                                                            int M, int N, float* __restrict__ out,
+                                                            int permute_cout) {
+  const int64_t total = (int64_t)M * N;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    float s = 0.f;
+    for (int z = 0; z < nsplit; ++z) s += part[(int64_t)z * total + i];
+    if (permute_cout > 0) {
+      // row m = sub * Cout + co, column n = ci -> [sub][ci][co]
+      const int m = (int)(i / N), n = (int)(i % N);
+      const int sub = m / permute_cout, co = m % permute_cout;
+      out[((int64_t)sub * N + n) * permute_cout + co] = s;
+    } else {
+      out[i] = s;
+    }
+  }
+}
+
+void launch_splitk_reduce(const float* part, int nsplit, int M, int N, float* out, int permute_cout,
+                          hipStream_t s) {
+  const int64_t total = (int64_t)M * N;
+  const int blocks = (int)std::min<int64_t>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL(splitk_reduce_kernel, dim3(blocks), dim3(256), 0, s, part, nsplit, M, N, out,
+                     permute_cout);
+  PAT_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ pooling
+
+// y[b][i][j][c] = max of the 2x2 window; idx = first maximum (row-major window order)
+__global__ __launch_bounds__(256) void maxpool_kernel(View in, View out, uint8_t* __restrict__ idx,
+                                                      int B) {
+  const int H2 = in.H / 2, W2 = in.W / 2, C = in.C;
+  const int64_t total = (int64_t)B * H2 * W2 * C;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e % C);
+    const int64_t p = e / C;
+    const int x = (int)(p % W2), t = (int)(p / W2), y = t % H2, b = t / H2;
+    float best = -INFINITY;
+    int bi = 0;
+    for (int q = 0; q < 4; ++q) {
+      const int yy = 2 * y + (q >> 1), xx = 2 * x + (q & 1);
+      const float v = bf2f(in.p[((int64_t)(b * in.H + yy) * in.W + xx) * in.pitch + in.off + c]);
+      if (v > best) { best = v; bi = q; }
+    }
+    out.p16[p * out.pitch + out.off + c] = f2bf(best);
+    idx[e] = (uint8_t)bi;
+  }
+}
+
+// g_in = bf16(route(g_out) + g_skip) * (act > 0), over the full-resolution grid
+__global__ __launch_bounds__(256) void maxpool_back_kernel(View gout, const uint8_t* __restrict__ idx,
+                                                           View gskip, View act, View gin, int B) {
+  const int H = gin.H, W = gin.W, C = gin.C, W2 = W / 2, H2 = H / 2;
+  const int64_t total = (int64_t)B * H * W * C;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e % C);
+    const int64_t p = e / C;
+    const int x = (int)(p % W), t = (int)(p / W), y = t % H, b = t / H;
+    const int64_t q = ((int64_t)(b * H2 + y / 2) * W2 + x / 2);
+    const int pos = ((y & 1) << 1) | (x & 1);
+    float v = (idx[q * C + c] == pos) ? bf2f(gout.p[q * gout.pitch + gout.off + c]) : 0.f;
+    v += bf2f(gskip.p[p * gskip.pitch + gskip.off + c]);
+    uint16_t h = f2bf(v);
+    if (!(bf2f(act.p[p * act.pitch + act.off + c]) > 0.f)) h = 0;
+    gin.p16[p * gin.pitch + gin.off + c] = h;
+  }
+}
+
+void launch_maxpool(const View& in, const View& out, uint8_t* idx, int B, hipStream_t s) {
+  const int64_t total = (int64_t)B * (in.H / 2) * (in.W / 2) * in.C;
+  const int blocks = (int)std::min<int64_t>((total + 255) / 256, 16384);
+  hipLaunchKernelGGL(maxpool_kernel, dim3(blocks), dim3(256), 0, s, in, out, idx, B);
+  PAT_HIP(hipGetLastError());
+}
+
+void launch_maxpool_back(const View& gout, const uint8_t* idx, const View& gskip, const View& act,
+                         const View& gin, int B, hipStream_t s) {
+  const int64_t total = (int64_t)B * gin.H * gin.W * gin.C;
+  const int blocks = (int)std::min<int64_t>((total + 255) / 256, 16384);
+  hipLaunchKernelGGL(maxpool_back_kernel, dim3(blocks), dim3(256), 0, s, gout, idx, gskip, act, gin, B);
+  PAT_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ head, loss, biases
+
+// y[p] = sum_c h[p][c] bf16(w[c]) + b  (one thread per pixel)
+__global__ __launch_bounds__(256) void head_kernel(View h, const float* __restrict__ w,
+                                                   const float* __restrict__ b, float* __restrict__ y,
+                                                   int64_t P) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  float s = 0.f;
+  for (int c = 0; c < h.C; ++c) s += bf2f(h.p[p * h.pitch + h.off + c]) * bf2f(f2bf(w[c]));
+  y[p] = s + b[0];
+}
+
+void launch_head(const View& h, const float* w, const float* b, float* y, int64_t P, hipStream_t s) {
+  hipLaunchKernelGGL(head_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, h, w, b, y, P);
+  PAT_HIP(hipGetLastError());
+}
+
+// gy = 2 (y - t) / P; per-block partial sums of (y - t)^2 for the loss
+__global__ __launch_bounds__(256) void mse_kernel(const float* __restrict__ y, const float* __restrict__ t,
+                                                  float* __restrict__ gy, double* __restrict__ part,
+                                                  int64_t P) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (p < P) {
+    const float d = y[p] - t[p];
+    gy[p] = 2.f * d / (float)P;
+    v = (double)d * d;
+  }
+  __shared__ double lds[8];
+  const double s = block_sum<256>(v, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void sum_part_kernel(const double* __restrict__ part, int n,
+                                                       double scale, double* __restrict__ out) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) v += part[i];
+  __shared__ double lds[8];
+  const double s = block_sum<256>(v, lds);
+  if (threadIdx.x == 0) *out = s * scale;
+}
+
+void launch_mse(const float* y, const float* t, float* gy, double* part, double* loss, int64_t P,
+                hipStream_t s) {
+  const int blocks = (int)((P + 255) / 256);
+  hipLaunchKernelGGL(mse_kernel, dim3(blocks), dim3(256), 0, s, y, t, gy, part, P);
+  hipLaunchKernelGGL(sum_part_kernel, dim3(1), dim3(256), 0, s, part, blocks, 1.0 / (double)P, loss);
+  PAT_HIP(hipGetLastError());
+}
+
+// head backward: gh[p][c] = bf16(gy[p] bf16(w[c])) * (h > 0); partial sums for gw, gb
+__global__ __launch_bounds__(256) void head_back_kernel(View h, const float* __restrict__ w,
+                                                        const float* __restrict__ gy, View gh,
+                                                        float* __restrict__ part, int64_t P,
+                                                        int rows_per_block) {
+  // part[block][c] for c < C: sum_p gy h; part[block][C]: sum_p gy
+  const int C = h.C;
+  const int64_t p0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t p1 = min(P, p0 + rows_per_block);
+  for (int c = threadIdx.x; c <= C; c += blockDim.x) {
+    float s = 0.f;
+    for (int64_t p = p0; p < p1; ++p) {
+      const float g = gy[p];
+      s += (c < C) ? g * bf2f(h.p[p * h.pitch + h.off + c]) : g;
+    }
+    part[(int64_t)blockIdx.x * (C + 1) + c] = s;
+  }
+  for (int64_t e = p0 * C + threadIdx.x; e < p1 * C; e += blockDim.x) {
+    const int64_t p = e / C;
+    const int c = (int)(e % C);
+    uint16_t v = f2bf(gy[p] * bf2f(f2bf(w[c])));
+    if (!(bf2f(h.p[p * h.pitch + h.off + c]) > 0.f)) v = 0;
+    gh.p16[p * gh.pitch + gh.off + c] = v;
+  }
+}
+
+void launch_head_back(const View& h, const float* w, const float* gy, const View& gh, float* part,
+                      int64_t P, int rows_per_block, hipStream_t s) {
+  const int blocks = (int)((P + rows_per_block - 1) / rows_per_block);
+  hipLaunchKernelGGL(head_back_kernel, dim3(blocks), dim3(256), 0, s, h, w, gy, gh, part, P,
+                     rows_per_block);
+  PAT_HIP(hipGetLastError());
+}
+
+// column sums of a bf16 NHWC gradient view: part[block][c] over a pixel range
+__global__ __launch_bounds__(256) void colsum_kernel(View g, float* __restrict__ part, int64_t P,
+                                                     int rows_per_block) {
+  const int64_t p0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t p1 = min(P, p0 + rows_per_block);
+  for (int c = threadIdx.x; c < g.C; c += blockDim.x) {
+    float s = 0.f;
+    for (int64_t p = p0; p < p1; ++p) s += bf2f(g.p[p * g.pitch + g.off + c]);
+    part[(int64_t)blockIdx.x * g.C + c] = s;
+  }
+}
+
+// out[c] = sum over blocks of part[block][c] (fixed order)
+__global__ __launch_bounds__(256) void part_reduce_kernel(const float* __restrict__ part, int nblk,
+                                                          int C, int ld, float* __restrict__ out) {
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < C; c += gridDim.x * blockDim.x) {
+    float s = 0.f;
+    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * ld + c];
+    out[c] = s;
+  }
+}
+
+void launch_colsum(const View& g, float* part, float* out, int64_t P, int rows_per_block, hipStream_t s) {
+  const int nblk = (int)((P + rows_per_block - 1) / rows_per_block);
+  hipLaunchKernelGGL(colsum_kernel, dim3(nblk), dim3(256), 0, s, g, part, P, rows_per_block);
+  hipLaunchKernelGGL(part_reduce_kernel, dim3((g.C + 255) / 256), dim3(256), 0, s, part, nblk, g.C, g.C, out);
+  PAT_HIP(hipGetLastError());
+}
+
+void launch_part_reduce(const float* part, int nblk, int C, int ld, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(part_reduce_kernel, dim3((C + 255) / 256), dim3(256), 0, s, part, nblk, C, ld, out);
+  PAT_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ parameters
+
+// Adam (Kingma & Ba) on the FP32 master copy; bc1 = 1 - beta1^t, bc2 = 1 - beta2^t
+__global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p, const float* __restrict__ g,
+                                                   float* __restrict__ m, float* __restrict__ v, int64_t n,
+                                                   float lr, float b1, float b2, float eps, float bc1,
+                                                   float bc2) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+  }
+}
+
+void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                 float eps, float bc1, float bc2, hipStream_t s) {
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(adam_kernel, dim3(blocks), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2, eps, bc1, bc2);
+  PAT_HIP(hipGetLastError());
+}
+
+// bf16 weight layouts from the FP32 master:
+//  conv3x3 [Cout][9][Cin]: forward B = same layout; dgrad B[ci][tap*Cout+co]
+//  convT  [2][2][Cin][Cout]: forward B[(sub*Cout+co)][ci]; dgrad B[ci][sub*Cout+co]
+__global__ __launch_bounds__(256) void prep_conv_kernel(const float* __restrict__ w, int Cout, int Cin,
+                                                        uint16_t* __restrict__ wf, uint16_t* __restrict__ wd) {
+  const int64_t n = (int64_t)Cout * 9 * Cin;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int ci = (int)(i % Cin);
+    const int64_t r = i / Cin;
+    const int tap = (int)(r % 9), co = (int)(r / 9);
+    const uint16_t h = f2bf(w[i]);
+    wf[i] = h;
+    wd[((int64_t)ci * 9 + tap) * Cout + co] = h;
+  }
+}
+
+__global__ __launch_bounds__(256) void prep_convt_kernel(const float* __restrict__ w, int Cin, int Cout,
+                                                         uint16_t* __restrict__ wf, uint16_t* __restrict__ wd) {
+  const int64_t n = (int64_t)4 * Cin * Cout;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int co = (int)(i % Cout);
+    const int64_t r = i / Cout;
+    const int ci = (int)(r % Cin), sub = (int)(r / Cin);
+    const uint16_t h = f2bf(w[i]);
+    wf[((int64_t)sub * Cout + co) * Cin + ci] = h;
+    wd[(int64_t)ci * 4 * Cout + sub * Cout + co] = h;
+  }
+}
+
+void launch_prep_conv(const float* w, int Cout, int Cin, uint16_t* wf, uint16_t* wd, hipStream_t s) {
+  const int64_t n = (int64_t)Cout * 9 * Cin;
+  hipLaunchKernelGGL(prep_conv_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256),
+                     0, s, w, Cout, Cin, wf, wd);
+  PAT_HIP(hipGetLastError());
+}
+
+void launch_prep_convt(const float* w, int Cin, int Cout, uint16_t* wf, uint16_t* wd, hipStream_t s) {
+  const int64_t n = (int64_t)4 * Cin * Cout;
+  hipLaunchKernelGGL(prep_convt_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256),
+                     0, s, w, Cin, Cout, wf, wd);
+  PAT_HIP(hipGetLastError());
+}
+
+// f32 [P] -> bf16 NHWC view with one channel
+__global__ __launch_bounds__(256) void to_bf16_kernel(const float* __restrict__ x, View out, int64_t P) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p < P) out.p16[p * out.pitch + out.off] = f2bf(x[p]);
+}
+
+void launch_to_bf16(const float* x, const View& out, int64_t P, hipStream_t s) {
+  hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, x, out, P);
+  PAT_HIP(hipGetLastError());
+}
+
+}  // namespace nn
+}  // namespace pat

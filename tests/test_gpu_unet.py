@@ -1,0 +1,137 @@
+"""GPU parity of the warm-start network (through the C ABI) against the FP64
+oracle network with the same bfloat16 rounding points.
+
+Tolerance: activations and inter-layer gradients are bfloat16 (8-bit
+mantissa, relative rounding 2^-9); the FP32 accumulation order differs from
+the oracle's, which can move a value across a bfloat16 rounding boundary or a
+ReLU kink, so outputs are compared to 1e-2 and gradients to 3e-2 relative L2.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import unet as U
+
+pytestmark = pytest.mark.gpu
+L = pytest.importorskip("paper_1707_02245_amd._lib")
+
+
+def _net(levels, base, seed=0):
+    lib = L.load()
+    h = C.c_void_p()
+    L.check(lib.pat_warmstart_create(levels, base, seed, C.byref(h)))
+    n = C.c_int64()
+    L.check(lib.pat_warmstart_num_params(h, C.byref(n)))
+    return lib, h, n.value
+
+
+def _flat(p, levels, base):
+    return np.concatenate([p[name].ravel() for name, _ in U.param_shapes(base, levels)])
+
+
+def _unflat(v, levels, base):
+    out, o = {}, 0
+    for name, shp in U.param_shapes(base, levels):
+        k = int(np.prod(shp))
+        out[name] = v[o:o + k].reshape(shp)
+        o += k
+    return out
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-30))
+
+
+def _setup(levels=4, base=8, B=2, H=16, W=24, seed=1):
+    rng = np.random.default_rng(seed)
+    p = U.init_params(rng, base, levels)
+    for k in p:
+        if k.endswith(".b"):
+            p[k] = 0.05 * rng.standard_normal(p[k].shape)
+    x = U.bf16(rng.standard_normal((B, H, W, 1)))
+    t = rng.standard_normal((B, H, W, 1))
+    lib, h, n = _net(levels, base)
+    flat = _flat(p, levels, base)
+    assert flat.size == n
+    dp = torch.tensor(flat, dtype=torch.float32, device="cuda")
+    L.check(lib.pat_warmstart_set_params(h, C.c_void_p(dp.data_ptr()), None))
+    # the GPU keeps FP32 masters: the oracle starts from the same FP32 values
+    p = _unflat(dp.cpu().numpy().astype(np.float64), levels, base)
+    return lib, h, n, p, x, t
+
+
+def test_parameter_count_matches_oracle():
+    lib, h, n = _net(4, 32)
+    assert n == sum(int(np.prod(s)) for _, s in U.param_shapes(32, 4))
+    lib.pat_warmstart_destroy(h)
+
+
+@pytest.mark.parametrize("shape", [(4, 8, 2, 16, 24), (3, 4, 1, 8, 8), (4, 32, 1, 32, 32)])
+def test_forward_matches_oracle(shape):
+    levels, base, B, H, W = shape
+    lib, h, n, p, x, t = _setup(levels, base, B, H, W)
+    dx = torch.tensor(x[..., 0], dtype=torch.float32, device="cuda").contiguous()
+    dy = torch.empty_like(dx)
+    print(f"net levels={levels} base={base} batch={B} {H}x{W}", flush=True)
+    L.check(lib.pat_warmstart_forward(h, B, H, W, C.c_void_p(dx.data_ptr()), C.c_void_p(dy.data_ptr()), None))
+    torch.cuda.synchronize()
+    y_ref, _ = U.forward(p, x, levels, quant=True)
+    e = _rel(dy.cpu().numpy(), y_ref[..., 0])
+    assert e <= 1e-2, e
+    lib.pat_warmstart_destroy(h)
+
+
+@pytest.mark.parametrize("shape", [(4, 8, 2, 16, 24), (3, 4, 1, 8, 8)])
+def test_gradients_match_oracle(shape):
+    levels, base, B, H, W = shape
+    lib, h, n, p, x, t = _setup(levels, base, B, H, W)
+    dx = torch.tensor(x[..., 0], dtype=torch.float32, device="cuda").contiguous()
+    dt = torch.tensor(t[..., 0], dtype=torch.float32, device="cuda").contiguous()
+    dg = torch.empty(n, dtype=torch.float32, device="cuda")
+    loss = C.c_double()
+    L.check(lib.pat_warmstart_grad(h, B, H, W, C.c_void_p(dx.data_ptr()), C.c_void_p(dt.data_ptr()),
+                                   C.c_void_p(dg.data_ptr()), C.byref(loss), None))
+    torch.cuda.synchronize()
+    y_ref, cache = U.forward(p, x, levels, quant=True)
+    l_ref, gy = U.mse(y_ref, t)
+    g_ref = U.backward(cache, gy, levels, quant=True)
+    assert loss.value == pytest.approx(l_ref, rel=1e-3)
+    got = _unflat(dg.cpu().numpy().astype(np.float64), levels, base)
+    errs = {k: _rel(got[k], g_ref[k]) for k in g_ref}
+    total = _rel(_flat(got, levels, base), _flat(g_ref, levels, base))
+    assert total <= 3e-2, (total, errs)
+    assert max(errs.values()) <= 1e-1, errs
+    lib.pat_warmstart_destroy(h)
+
+
+def test_training_reduces_loss_and_checkpoint_roundtrip(tmp_path):
+    levels, base, B, H, W = 4, 8, 4, 16, 16
+    lib, h, n = _net(levels, base, seed=3)
+    rng = np.random.default_rng(5)
+    xs = rng.standard_normal((16, H, W)).astype(np.float32)
+    ts = np.roll(xs, 1, axis=2) * 0.5  # a shift-and-scale map the network can learn
+    dx = torch.tensor(xs, device="cuda")
+    dt = torch.tensor(ts, device="cuda")
+    opts = L.TrainOpts(epochs=1, batch=B, lr=1e-3, seed=1)
+    l0 = C.c_double()
+    L.check(lib.pat_warmstart_train(h, 16, H, W, C.c_void_p(dx.data_ptr()), C.c_void_p(dt.data_ptr()),
+                                    C.byref(opts), C.byref(l0), None))
+    opts.epochs = 60
+    l1 = C.c_double()
+    L.check(lib.pat_warmstart_train(h, 16, H, W, C.c_void_p(dx.data_ptr()), C.c_void_p(dt.data_ptr()),
+                                    C.byref(opts), C.byref(l1), None))
+    assert np.isfinite(l1.value) and l1.value < 0.5 * l0.value, (l0.value, l1.value)
+    path = str(tmp_path / "net.bin")
+    L.check(lib.pat_warmstart_save(h, path.encode()))
+    lib2, h2, _ = _net(levels, base, seed=99)
+    L.check(lib2.pat_warmstart_load(h2, path.encode()))
+    a = torch.empty(n, device="cuda")
+    b = torch.empty(n, device="cuda")
+    L.check(lib.pat_warmstart_get_params(h, C.c_void_p(a.data_ptr()), None))
+    L.check(lib.pat_warmstart_get_params(h2, C.c_void_p(b.data_ptr()), None))
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    lib.pat_warmstart_destroy(h)
+    lib.pat_warmstart_destroy(h2)
