@@ -199,6 +199,8 @@ typedef struct {
   double theta;           /* extrapolation, 1.0 */
   double gap_box;         /* C of the box-restricted gap; > 0 */
   const void* d_u0;       /* optional warm start [ny][nx]; NULL = zero */
+  const void* d_y0;       /* optional dual start with d_u0 (TV, dTV): q [n_bins]
+                           * then r [2][N]; NULL = zero */
   const void* d_state_in; /* optional full state to resume from; NULL = none */
   void* d_state_out;      /* optional: receives the final state */
   pat_precond_h precond;  /* NULL: DIAG computed for this call */
@@ -214,8 +216,9 @@ typedef struct {
  * Sec. 3.3.3 is taken with x restricted to the box ||x||_inf <= gap_box
  * (the printed gap is infinite when G = 0):
  *   gap = P(x) + 1/2||q||^2 + <q, f> + gap_box ||K^T y||_1, rel_gap = gap / P(x).
- * A warm start that is non-finite or has P(u0) > P(0) = 1/2||f||^2 is
- * replaced by zero (info->fallback = 1).
+ * A warm start that is non-finite (u0, or y0 when given) or has
+ * P(u0) > P(0) = 1/2||f||^2 is replaced by zero (info->fallback = 1); ubar
+ * starts at u0.
  * d_f: device data [n_det][n_t]; d_u_out: device image [ny][nx].
  * Returns PAT_OK when rel_gap <= gap_tol (or max_iter ran with gap_tol <= 0),
  * PAT_NOT_CONVERGED at the cap, PAT_ERR_NUMERIC on a non-finite gap.
@@ -239,17 +242,19 @@ pat_status pat_pdhg_solve_batched(int32_t n, const pat_geometry* g, const void* 
 /* ---- Learned warm start -------------------------------------------------
  * A U-Net (`levels` levels, base_ch channels at the top, doubling per level;
  * 3x3 convolutions with ReLU, 2x2 max pooling, 2x2 stride-2 transposed
- * convolutions, skip concatenation, 1x1 head) maps the normalised
- * backprojection x = (A^T f / A^T 1) / s, s = mean |A^T f / A^T 1|, to the
- * normalised reconstruction u / s. Weights are FP32 masters used as bf16 in
- * the matrix-core convolutions (FP32 accumulation); activations and the
- * gradients passed between layers are bf16. The network only changes where
- * PDHG starts (pat_solve_opts.d_u0); the gap decides the result. Images
- * ([n][h][w] FP32, device) need h and w divisible by 2^(levels-1).
+ * convolutions, skip concatenation, 1x1 head with out_ch outputs) maps the
+ * normalised backprojection x = (A^T f / A^T 1) / s, s = mean |A^T f / A^T 1|,
+ * to the normalised TV reconstruction u / s (output 0) and, with out_ch = 3,
+ * its dual variable r / lambda (outputs 1, 2). Weights are FP32 masters used
+ * as bf16 in the matrix-core convolutions (FP32 accumulation); activations
+ * and the gradients passed between layers are bf16. The network only changes
+ * where PDHG starts (pat_solve_opts.d_u0, d_y0); the gap decides the result.
+ * Inputs are device FP32 [n][h][w]; outputs and targets device FP32 channel
+ * planes [n][out_ch][h][w]; h and w divisible by 2^(levels-1).
  * Parameters are one FP32 vector in the order: per level l = 0..levels-1 two
  * 3x3 convolutions (weights [Cout][3][3][Cin], bias [Cout]); per decoder level
  * l = levels-2..0 the transposed convolution ([2][2][Cin][Cout], [Cout]) and
- * two 3x3 convolutions; the head ([C0], [1]). */
+ * two 3x3 convolutions; the head ([out_ch][C0], [out_ch]). */
 typedef struct pat_unet_s* pat_unet;
 typedef struct {
   int32_t epochs, batch;  /* passes over the data; images per Adam step */
@@ -257,37 +262,48 @@ typedef struct {
   uint64_t seed;          /* shuffling order */
 } pat_train_opts;
 
-/* He-normal weights from `seed`, zero biases. */
-pat_status pat_warmstart_create(int32_t levels, int32_t base_ch, uint64_t seed, pat_unet* out);
+/* He-normal weights from `seed`, zero biases; levels in [2, 6], base_ch a
+ * multiple of 4 in [4, 256], out_ch in [1, 4]. */
+pat_status pat_warmstart_create(int32_t levels, int32_t base_ch, int32_t out_ch, uint64_t seed,
+                                pat_unet* out);
 pat_status pat_warmstart_destroy(pat_unet n);
 pat_status pat_warmstart_num_params(pat_unet n, int64_t* out);
 /* Copy the FP32 parameter vector to / from device memory (set resets Adam). */
 pat_status pat_warmstart_get_params(pat_unet n, float* d_dst, void* stream);
 pat_status pat_warmstart_set_params(pat_unet n, const float* d_src, void* stream);
-/* y = net(x) for `batch` images; d_in, d_out device FP32 [batch][h][w]. */
+/* y = net(x) for `batch` images: d_in [batch][h][w], d_out [batch][out_ch][h][w]. */
 pat_status pat_warmstart_forward(pat_unet n, int32_t batch, int32_t h, int32_t w, const float* d_in,
                                  float* d_out, void* stream);
-/* Mean squared error of net(x) against d_target and its gradient with respect
- * to every parameter (device FP32 [num_params]); *loss (host) if non-NULL. */
+/* Mean squared error of net(x) against d_target (over all outputs) and its
+ * gradient with respect to every parameter (device FP32 [num_params]);
+ * *loss (host) if non-NULL. */
 pat_status pat_warmstart_grad(pat_unet n, int32_t batch, int32_t h, int32_t w, const float* d_in,
                               const float* d_target, float* d_grad, double* loss, void* stream);
-/* Adam on the mean squared error over `count` pairs (device FP32
- * [count][h][w] each), `epochs` shuffled passes in batches of opts->batch.
- * *final_loss (host): mean loss of the last epoch. */
+/* Adam on the mean squared error over `count` pairs, `epochs` shuffled passes
+ * in batches of opts->batch (count / batch steps per epoch). *final_loss
+ * (host): mean loss of the last epoch. PAT_ERR_NUMERIC if it is non-finite. */
 pat_status pat_warmstart_train(pat_unet n, int32_t count, int32_t h, int32_t w, const float* d_inputs,
                                const float* d_targets, const pat_train_opts* opts, double* final_loss,
                                void* stream);
-/* Checkpoint: parameters and Adam state, raw little-endian with a header. */
+/* Checkpoint: parameters and Adam state, raw little-endian with a header
+ * ("PATUNET2", levels, base_ch, out_ch, num_params, step as int64). */
 pat_status pat_warmstart_save(pat_unet n, const char* path);
 pat_status pat_warmstart_load(pat_unet n, const char* path);
 /* Network input (and target) of one measurement: d_f data of g (element type
- * of g); d_u an optional reconstruction of the same type; outputs FP32 [ny][nx]
- * d_x = normalised backprojection, d_t = d_u / s, and d_scale[0] = s. */
-pat_status pat_warmstart_normalize(pat_geometry g, const void* d_f, const void* d_u, float* d_x,
-                                   float* d_t, float* d_scale, void* stream);
-/* d_u0 = s net(x) for data d_f of g (element type of g), ready as
- * pat_solve_opts.d_u0. Synchronous on return. */
-pat_status pat_warmstart_infer(pat_unet n, pat_geometry g, const void* d_f, void* d_u0, void* stream);
+ * of g). Outputs FP32: d_x [ny][nx] the normalised backprojection and
+ * d_scale[0] = s. With d_state (a solver state of g, layout of
+ * pat_state_elems, e.g. pat_solve_opts.d_state_out of a TV solve) the target
+ * planes d_t [t_channels][ny][nx]: u / s, and with t_channels = 3 also
+ * r_x / lambda, r_y / lambda (reg: the TV regulariser of that solve). */
+pat_status pat_warmstart_normalize(pat_geometry g, const pat_regulariser* reg, const void* d_f,
+                                   const void* d_state, float* d_x, float* d_t, int32_t t_channels,
+                                   float* d_scale, void* stream);
+/* Starting point for pat_pdhg_solve from data d_f of g (element type of g):
+ * d_u0 = s net(x)[0]. With d_y0 (out_ch = 3, reg TV) also the dual start
+ * q0 = A u0 - f [n_bins] followed by r0 = lambda P(net(x)[1], net(x)[2])
+ * [2][N], P the projection onto the unit disc per pixel. Synchronous. */
+pat_status pat_warmstart_infer(pat_unet n, pat_geometry g, const pat_regulariser* reg, const void* d_f,
+                               void* d_u0, void* d_y0, void* stream);
 
 const char* pat_status_string(pat_status s);
 /* Message of the last error on the calling thread ("" if none). */

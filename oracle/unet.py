@@ -9,11 +9,11 @@ concatenation (upsampled first, skip second) and a final 1x1 convolution:
   level 3:            conv(C_2 -> C_3), relu, conv(C_3 -> C_3), relu
   up l (l = 2..0):    convT2x2(C_{l+1} -> C_l), concat(., skip_l),
                       conv(2 C_l -> C_l), relu, conv(C_l -> C_l), relu
-  out:                conv1x1(C_0 -> 1)
+  out:                conv1x1(C_0 -> cout)
 
 with C_l = base * 2^l. Tensors are NHWC float64 arrays. Weights of a 3x3
 convolution are [Cout][3][3][Cin], of a transposed convolution [2][2][Cin][Cout],
-of the 1x1 head [Cin]. `quant` rounds weights and activations to bfloat16 where
+of the 1x1 head [cout][Cin]. `quant` rounds weights and activations to bfloat16 where
 the GPU kernels hold them in bfloat16 (accumulation stays exact here).
 
 Backward passes are written out by hand (no autodiff); finite differences pin
@@ -104,7 +104,7 @@ def convT2_backward(x, w, gy):
 
 # ---------------------------------------------------------------- network
 
-def param_shapes(base=32, levels=4, cin=1):
+def param_shapes(base=32, levels=4, cin=1, cout=1):
     """Ordered (name, shape) of every parameter tensor."""
     ch = [base * 2 ** l for l in range(levels)]
     shapes = []
@@ -117,14 +117,14 @@ def param_shapes(base=32, levels=4, cin=1):
         shapes += [(f"u{l}t.w", (2, 2, ch[l + 1], ch[l])), (f"u{l}t.b", (ch[l],)),
                    (f"u{l}a.w", (ch[l], 3, 3, 2 * ch[l])), (f"u{l}a.b", (ch[l],)),
                    (f"u{l}b.w", (ch[l], 3, 3, ch[l])), (f"u{l}b.b", (ch[l],))]
-    shapes += [("out.w", (ch[0],)), ("out.b", (1,))]
+    shapes += [("out.w", (cout, ch[0])), ("out.b", (cout,))]
     return shapes
 
 
-def init_params(rng, base=32, levels=4):
+def init_params(rng, base=32, levels=4, cout=1):
     """He-normal weights, zero biases."""
     p = {}
-    for name, shp in param_shapes(base, levels):
+    for name, shp in param_shapes(base, levels, cout=cout):
         if name.endswith(".b"):
             p[name] = np.zeros(shp)
         else:
@@ -134,13 +134,14 @@ def init_params(rng, base=32, levels=4):
             elif len(shp) == 4:
                 fan_in = int(np.prod(shp[1:]))
             else:
-                fan_in = shp[0]
+                fan_in = shp[1]
             p[name] = rng.standard_normal(shp) * np.sqrt(2.0 / fan_in)
     return p
 
 
 def forward(p, x, levels=4, quant=False):
-    """Network output and the cache needed by backward. x: [N][H][W][1]."""
+    """Network output [N][H][W][cout] and the cache needed by backward.
+    x: [N][H][W][1]."""
     P = {k: (_q(v, quant) if k.endswith(".w") else v) for k, v in p.items()}
     cache = {"x": x}
     h = x
@@ -164,7 +165,7 @@ def forward(p, x, levels=4, quant=False):
         cache[f"u{l}a.in"], cache[f"u{l}a.out"] = cat, a
         h = _q(np.maximum(conv3x3(a, P[f"u{l}b.w"], P[f"u{l}b.b"]), 0), quant)
         cache[f"u{l}b.in"], cache[f"u{l}b.out"] = a, h
-    y = np.einsum("nhwc,c->nhw", h, P["out.w"])[..., None] + P["out.b"]
+    y = np.einsum("nhwc,kc->nhwk", h, P["out.w"]) + P["out.b"]
     cache["out.in"] = h
     cache["P"] = P
     return y, cache
@@ -185,9 +186,9 @@ def backward(cache, gy, levels=4, quant=False):
     P = cache["P"]
     g = {}
     h = cache["out.in"]
-    g["out.w"] = np.einsum("nhwc,nhw->c", h, gy[..., 0])
-    g["out.b"] = np.array([gy.sum()])
-    gh = _q(gy[..., 0][..., None] * P["out.w"], quant)
+    g["out.w"] = np.einsum("nhwc,nhwk->kc", h, gy)
+    g["out.b"] = gy.sum(axis=(0, 1, 2))
+    gh = _q(np.einsum("nhwk,kc->nhwc", gy, P["out.w"]), quant)
     gskip = {}
     # decoder, from the output (level 0) up to level levels-2
     for l in range(0, levels - 1):

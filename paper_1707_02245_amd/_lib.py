@@ -65,7 +65,7 @@ class SolveOpts(C.Structure):
     _fields_ = [
         ("max_iter", C.c_int32), ("gap_tol", C.c_double), ("gap_every", C.c_int32),
         ("graph_block", C.c_int32), ("theta", C.c_double), ("gap_box", C.c_double),
-        ("d_u0", C.c_void_p), ("d_state_in", C.c_void_p), ("d_state_out", C.c_void_p),
+        ("d_u0", C.c_void_p), ("d_y0", C.c_void_p), ("d_state_in", C.c_void_p), ("d_state_out", C.c_void_p),
         ("precond", C.c_void_p),
     ]
 
@@ -105,7 +105,7 @@ _SIGS = {
     "pat_pdhg_solve_batched": ([C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                 C.POINTER(Regulariser), C.POINTER(SolveOpts), C.POINTER(C.c_void_p),
                                 C.POINTER(SolveInfo), C.c_void_p], C.c_int),
-    "pat_warmstart_create": ([C.c_int32, C.c_int32, C.c_uint64, C.POINTER(C.c_void_p)], C.c_int),
+    "pat_warmstart_create": ([C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.POINTER(C.c_void_p)], C.c_int),
     "pat_warmstart_destroy": ([C.c_void_p], C.c_int),
     "pat_warmstart_num_params": ([C.c_void_p, C.POINTER(C.c_int64)], C.c_int),
     "pat_warmstart_get_params": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
@@ -118,9 +118,10 @@ _SIGS = {
                              C.POINTER(TrainOpts), C.POINTER(C.c_double), C.c_void_p], C.c_int),
     "pat_warmstart_save": ([C.c_void_p, C.c_char_p], C.c_int),
     "pat_warmstart_load": ([C.c_void_p, C.c_char_p], C.c_int),
-    "pat_warmstart_normalize": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                                 C.c_void_p, C.c_void_p], C.c_int),
-    "pat_warmstart_infer": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "pat_warmstart_normalize": ([C.c_void_p, C.POINTER(Regulariser), C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p], C.c_int),
+    "pat_warmstart_infer": ([C.c_void_p, C.c_void_p, C.POINTER(Regulariser), C.c_void_p, C.c_void_p,
+                             C.c_void_p, C.c_void_p], C.c_int),
     "pat_status_string": ([C.c_int], C.c_char_p),
     "pat_last_error": ([], C.c_char_p),
 }

@@ -447,7 +447,7 @@ class Solver {
         }
       }
     }
-    // warm starts: accept only finite u0 with P(u0) <= P(0) = 1/2 ||f||^2
+    // warm starts: accept only a finite (u0[, y0]) with P(u0) <= P(0) = 1/2 ||f||^2
     bool any_u0 = false;
     for (int k : act) any_u0 |= (inst[k]->opts.d_u0 != nullptr && !inst[k]->opts.d_state_in);
     if (!any_u0) return;
@@ -465,15 +465,27 @@ class Solver {
       if (!I.opts.d_u0 || I.opts.d_state_in) continue;
       const double* r = h_results + a * GAP_NSLOTS;
       const double P0 = r[GAP_DATA] + r[GAP_REG];
-      launch_dot<T>(I.f, I.f, I.g->n_bins(), ptr<double>(part), 512, ptr<double>(acc), s);
-      double ff = 0.0;
+      const int64_t nb = I.g->n_bins(), N = I.g->n_pix();
+      launch_dot<T>(I.f, I.f, nb, ptr<double>(part), 512, ptr<double>(acc), s);
+      double ff = 0.0, yy = 0.0;
       PAT_HIP(hipMemcpyAsync(&ff, acc.p, sizeof(double), hipMemcpyDeviceToHost, s));
       PAT_HIP(hipStreamSynchronize(s));
-      if (!std::isfinite(P0) || P0 > 0.5 * ff) {
+      const T* y0 = static_cast<const T*>(I.opts.d_y0);
+      if (y0) {
+        // q0 [n_bins] then r0 [2][N]: a finite sum of squares means finite entries
+        launch_dot<T>(y0, y0, nb + 2 * N, ptr<double>(part), 512, ptr<double>(acc), s);
+        PAT_HIP(hipMemcpyAsync(&yy, acc.p, sizeof(double), hipMemcpyDeviceToHost, s));
+        PAT_HIP(hipStreamSynchronize(s));
+      }
+      if (!std::isfinite(P0) || P0 > 0.5 * ff || !std::isfinite(yy)) {
         I.fallback = 1;
         PAT_HIP(hipMemsetAsync(I.u.p, 0, I.u.bytes, s));
       } else {
         launch_pad<T>(ptr<T>(I.u), ptr<T>(I.ubar_pad), I.g->nx, I.g->ny, s);
+        if (y0) {
+          PAT_HIP(hipMemcpyAsync(I.q.p, y0, sizeof(T) * nb, hipMemcpyDeviceToDevice, s));
+          PAT_HIP(hipMemcpyAsync(I.r.p, y0 + nb, sizeof(T) * 2 * N, hipMemcpyDeviceToDevice, s));
+        }
       }
     }
     PAT_HIP(hipStreamSynchronize(s));
@@ -707,6 +719,10 @@ static void validate_instance(pat_geometry g, const void* f, const pat_regularis
   if (o->precond)
     PAT_CHECK_ARG(o->precond->g == g && o->precond->reg_kind == reg->kind,
                   "precond handle was made for another geometry or regulariser");
+  if (o->d_y0) {
+    PAT_CHECK_ARG(o->d_u0 != nullptr && o->d_state_in == nullptr, "d_y0 goes with d_u0 and no d_state_in");
+    PAT_CHECK_ARG(reg->kind == PAT_REG_TV || reg->kind == PAT_REG_DTV, "d_y0 needs a TV or dTV regulariser");
+  }
 }
 
 }  // namespace pat

@@ -9,7 +9,9 @@
 // Parameter order and layouts are those of the reference network: per level
 // l = 0..3 the two encoder 3x3 convolutions ([Cout][3][3][Cin] + bias), then
 // per decoder level l = 2..0 the 2x2 transposed convolution
-// ([2][2][Cin][Cout] + bias) and two 3x3 convolutions, then the 1x1 head.
+// ([2][2][Cin][Cout] + bias) and two 3x3 convolutions, then the 1x1 head
+// ([cout][C0] + bias). Outputs and targets are FP32 channel planes
+// [batch][cout][h][w].
 
 #include <algorithm>
 #include <cstdio>
@@ -42,7 +44,7 @@ struct Act {
 }  // namespace pat
 
 struct pat_unet_s {
-  int levels = 4, base = 32;
+  int levels = 4, base = 32, cout = 1;
   std::vector<pat::nn::Layer> layers;  // in parameter order (head excluded)
   int64_t head_w = 0, head_b = 0, n_params = 0, n_wbf16 = 0;
   pat::DevBuf params, grads, adam_m, adam_v, wf, wd;
@@ -85,9 +87,9 @@ static void build_layers(pat_unet_s* n) {
     add(0, n->ch(l), n->ch(l));
   }
   n->head_w = off;
-  off += n->ch(0);
+  off += (int64_t)n->cout * n->ch(0);
   n->head_b = off;
-  off += 1;
+  off += n->cout;
   n->n_params = off;
   n->n_wbf16 = woff;
 }
@@ -120,9 +122,9 @@ static void ensure_act(pat_unet_s* n, int B, int H, int W) {
   auto px = [&](int l) { return (int64_t)B * (H >> l) * (W >> l); };
   const size_t h = sizeof(uint16_t);
   a.x0.alloc(h * px(0));
-  a.y.alloc(sizeof(float) * px(0));
-  a.gy.alloc(sizeof(float) * px(0));
-  a.t.alloc(sizeof(float) * px(0));
+  a.y.alloc(sizeof(float) * px(0) * n->cout);
+  a.gy.alloc(sizeof(float) * px(0) * n->cout);  // also stages the input batch
+  a.t.alloc(sizeof(float) * px(0) * n->cout);
   for (int l = 0; l < n->levels; ++l) {
     a.a[l].alloc(h * px(l) * n->ch(l));
     a.g_a[l].alloc(h * px(l) * n->ch(l));
@@ -144,11 +146,11 @@ static void ensure_act(pat_unet_s* n, int B, int H, int W) {
   a.g_s3.alloc(h * px(L3) * n->ch(L3));
   a.ws.alloc(kWorkspace);
   // per-block partial sums: bias gradients (256 pixels per block, up to 2 C
-  // channels) and the head (1024 pixels per block, C0 + 1 sums)
-  int64_t part = (px(0) + 1023) / 1024 * (n->ch(0) + 1);
+  // channels) and the head (1024 pixels per block, cout (C0 + 1) sums)
+  int64_t part = (px(0) + 1023) / 1024 * n->cout * (n->ch(0) + 1);
   for (int l = 0; l < n->levels; ++l) part = std::max<int64_t>(part, (px(l) + 255) / 256 * 2 * n->ch(l));
   a.part.alloc(sizeof(float) * part);
-  a.loss_part.alloc(sizeof(double) * ((px(0) + 255) / 256 + 1));
+  a.loss_part.alloc(sizeof(double) * ((px(0) * n->cout + 255) / 256 + 1));
   a.loss.alloc(sizeof(double));
 }
 
@@ -326,7 +328,7 @@ static void forward(pat_unet_s* n, const float* x, hipStream_t s) {
     h = v.ub[l];
   }
   launch_head(h, ptr<float>(n->params) + n->head_w, ptr<float>(n->params) + n->head_b, ptr<float>(a.y),
-              P0, s);
+              P0, n->cout, (int64_t)a.H * a.W, s);
 }
 
 static void backward(pat_unet_s* n, hipStream_t s) {
@@ -337,14 +339,17 @@ static void backward(pat_unet_s* n, hipStream_t s) {
     return view(ptr<uint16_t>(b), a.H >> l, a.W >> l, C, pitch, off);
   };
   View none;
-  // head: gh = bf16(gy w) * (ub0 > 0)
+  // head: gh = bf16(sum_k gy_k w_k) * (ub0 > 0)
   const int C0 = n->ch(0);
   View g = gview(a.g_ub[0], 0, C0, C0, 0);
   const int rows = 1024;
   const int nblk = (int)((P0 + rows - 1) / rows);
   launch_head_back(v.ub[0], ptr<float>(n->params) + n->head_w, ptr<float>(a.gy), g, ptr<float>(a.part), P0,
-                   rows, s);
-  launch_part_reduce(ptr<float>(a.part), nblk, C0 + 1, C0 + 1, ptr<float>(n->grads) + n->head_w, s);
+                   n->cout, (int64_t)a.H * a.W, rows, s);
+  // part rows are [cout][C0] weight sums then cout bias sums: the head's
+  // parameter layout, so one reduction fills both
+  const int hk = n->cout * (C0 + 1);
+  launch_part_reduce(ptr<float>(a.part), nblk, hk, hk, ptr<float>(n->grads) + n->head_w, s);
   // decoder, level 0 up to levels-2
   for (int l = 0; l < n->levels - 1; ++l) {
     const int C = n->ch(l);
@@ -406,7 +411,7 @@ static void init_params(pat_unet_s* n, uint64_t seed, hipStream_t s) {
     for (int64_t i = 0; i < nw; ++i) h[L.w + i] = (float)(sd * nd(rng));
   }
   const double sd = std::sqrt(2.0 / n->ch(0));
-  for (int c = 0; c < n->ch(0); ++c) h[n->head_w + c] = (float)(sd * nd(rng));
+  for (int64_t c = 0; c < (int64_t)n->cout * n->ch(0); ++c) h[n->head_w + c] = (float)(sd * nd(rng));
   PAT_HIP(hipMemcpyAsync(n->params.p, h.data(), sizeof(float) * n->n_params, hipMemcpyHostToDevice, s));
   PAT_HIP(hipMemsetAsync(n->adam_m.p, 0, n->adam_m.bytes, s));
   PAT_HIP(hipMemsetAsync(n->adam_v.p, 0, n->adam_v.bytes, s));
@@ -418,7 +423,8 @@ static double train_step(pat_unet_s* n, const float* x, const float* t, double l
   Act& a = n->act;
   const int64_t P0 = (int64_t)a.B * a.H * a.W;
   forward(n, x, s);
-  launch_mse(ptr<float>(a.y), t, ptr<float>(a.gy), ptr<double>(a.loss_part), ptr<double>(a.loss), P0, s);
+  launch_mse(ptr<float>(a.y), t, ptr<float>(a.gy), ptr<double>(a.loss_part), ptr<double>(a.loss),
+             P0 * n->cout, s);
   backward(n, s);
   if (update) {
     ++n->step;
@@ -452,11 +458,14 @@ __global__ __launch_bounds__(256) void bp_ratio_kernel(const T* __restrict__ atf
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// scale = max(mean |bp|, 1e-12); x = bp / scale; t = u / scale (if u)
+// scale = max(mean |bp|, 1e-12); x = bp / scale; target planes (if u):
+// t[0] = u / scale, and with tc = 3 also t[1], t[2] = r_x / lambda, r_y / lambda
 template <class T>
 __global__ __launch_bounds__(256) void normalise_kernel(const double* __restrict__ part, int nblk, int64_t n,
                                                         float* __restrict__ x, const T* __restrict__ u,
-                                                        float* __restrict__ t, float* __restrict__ scale_out) {
+                                                        const T* __restrict__ r, double inv_lam,
+                                                        float* __restrict__ t, int tc,
+                                                        float* __restrict__ scale_out) {
   __shared__ double sc;
   if (threadIdx.x == 0) {
     double s = 0.0;
@@ -468,20 +477,42 @@ __global__ __launch_bounds__(256) void normalise_kernel(const double* __restrict
   const double inv = 1.0 / sc;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     x[i] = (float)(x[i] * inv);
-    if (u && t) t[i] = (float)((double)u[i] * inv);
+    if (u && t) {
+      t[i] = (float)((double)u[i] * inv);
+      if (tc == 3) {
+        t[n + i] = (float)((double)r[i] * inv_lam);
+        t[2 * n + i] = (float)((double)r[n + i] * inv_lam);
+      }
+    }
   }
 }
 
+// u0 = scale y[0]; with r0: r0 = lambda P(y[1], y[2]), P the projection onto
+// the unit disc (the dual ball of TV scaled to 1)
 template <class T>
 __global__ __launch_bounds__(256) void rescale_kernel(const float* __restrict__ y, const float* __restrict__ scale,
-                                                      T* __restrict__ u, int64_t n) {
+                                                      T* __restrict__ u, T* __restrict__ r, double lam, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) u[i] = (T)((double)y[i] * (double)*scale);
+  if (i >= n) return;
+  u[i] = (T)((double)y[i] * (double)*scale);
+  if (r) {
+    const double a = y[n + i], b = y[2 * n + i];
+    const double m = fmax(1.0, sqrt(a * a + b * b));
+    r[i] = (T)(lam * a / m);
+    r[n + i] = (T)(lam * b / m);
+  }
+}
+
+// q0 = A u0 - f (already holding A u0)
+template <class T>
+__global__ __launch_bounds__(256) void residual_kernel(T* __restrict__ q, const T* __restrict__ f, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) q[i] = q[i] - f[i];
 }
 
 template <class T>
-static void normalise_impl(pat_geometry g, const void* d_f, const void* d_u, float* d_x, float* d_t,
-                           float* d_scale, hipStream_t s) {
+static void normalise_impl(pat_geometry g, const pat_regulariser* reg, const void* d_f, const void* d_state,
+                           float* d_x, float* d_t, int tc, float* d_scale, hipStream_t s) {
   const int64_t N = g->n_pix(), nb = g->n_bins();
   DevBuf atf(sizeof(T) * N), at1(sizeof(T) * N), ones(sizeof(T) * nb);
   apply_adjoint<T>(g, static_cast<const T*>(d_f), ptr<T>(atf), s);
@@ -491,8 +522,11 @@ static void normalise_impl(pat_geometry g, const void* d_f, const void* d_u, flo
   DevBuf part(sizeof(double) * nblk);
   hipLaunchKernelGGL(bp_ratio_kernel<T>, dim3(nblk), dim3(256), 0, s, ptr<T>(atf), ptr<T>(at1), d_x,
                      ptr<double>(part), N);
+  const T* u = static_cast<const T*>(d_state);
+  const T* r = u ? u + 2 * N + nb : nullptr;  // state layout: u, ubar, q, r
+  const double inv_lam = (u && tc == 3) ? 1.0 / reg->lambda : 0.0;  // reg checked by the caller then
   hipLaunchKernelGGL(normalise_kernel<T>, dim3(std::min(nblk, 1024)), dim3(256), 0, s, ptr<double>(part), nblk,
-                     N, d_x, static_cast<const T*>(d_u), d_t, d_scale);
+                     N, d_x, u, r, inv_lam, d_t, tc, d_scale);
   PAT_HIP(hipGetLastError());
   PAT_HIP(hipStreamSynchronize(s));  // temporaries go out of scope
 }
@@ -504,14 +538,17 @@ using pat::nn::Act;
 
 static void check_net(pat_unet n) { PAT_CHECK_ARG(n != nullptr, "network is NULL"); }
 
-extern "C" pat_status pat_warmstart_create(int32_t levels, int32_t base_ch, uint64_t seed, pat_unet* out) {
+extern "C" pat_status pat_warmstart_create(int32_t levels, int32_t base_ch, int32_t out_ch, uint64_t seed,
+                                           pat_unet* out) {
   return guarded([&]() -> pat_status {
     PAT_CHECK_ARG(out != nullptr, "out is NULL");
     PAT_CHECK_ARG(levels >= 2 && levels <= 6, "levels must be in [2, 6]");
     PAT_CHECK_ARG(base_ch >= 4 && base_ch <= 256 && base_ch % 4 == 0, "base_ch must be a multiple of 4 in [4, 256]");
+    PAT_CHECK_ARG(out_ch >= 1 && out_ch <= 4, "out_ch must be in [1, 4]");
     std::unique_ptr<pat_unet_s> n(new pat_unet_s());
     n->levels = levels;
     n->base = base_ch;
+    n->cout = out_ch;
     pat::nn::build_layers(n.get());
     n->params.alloc(sizeof(float) * n->n_params);
     n->grads.alloc(sizeof(float) * n->n_params);
@@ -576,7 +613,8 @@ extern "C" pat_status pat_warmstart_forward(pat_unet n, int32_t batch, int32_t h
     hipStream_t s = static_cast<hipStream_t>(stream);
     pat::nn::ensure_act(n, batch, h, w);
     pat::nn::forward(n, d_in, s);
-    PAT_HIP(hipMemcpyAsync(d_out, n->act.y.p, sizeof(float) * (size_t)batch * h * w, hipMemcpyDeviceToDevice, s));
+    PAT_HIP(hipMemcpyAsync(d_out, n->act.y.p, sizeof(float) * (size_t)batch * n->cout * h * w,
+                           hipMemcpyDeviceToDevice, s));
     return PAT_OK;
   });
 }
@@ -610,7 +648,7 @@ extern "C" pat_status pat_warmstart_train(pat_unet n, int32_t count, int32_t h, 
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int B = opts->batch;
     pat::nn::ensure_act(n, B, h, w);
-    const int64_t img = (int64_t)h * w;
+    const int64_t img = (int64_t)h * w, timg = img * n->cout;
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
     std::mt19937_64 rng(opts->seed);
@@ -623,8 +661,8 @@ extern "C" pat_status pat_warmstart_train(pat_unet n, int32_t count, int32_t h, 
       for (int bi = 0; bi < per_epoch; ++bi) {
         for (int j = 0; j < B; ++j) {
           const int idx = order[(size_t)bi * B + j];
-          PAT_HIP(hipMemcpyAsync(pat::ptr<float>(n->act.t) + j * img, d_targets + idx * img, sizeof(float) * img,
-                                 hipMemcpyDeviceToDevice, s));
+          PAT_HIP(hipMemcpyAsync(pat::ptr<float>(n->act.t) + j * timg, d_targets + idx * timg,
+                                 sizeof(float) * timg, hipMemcpyDeviceToDevice, s));
           PAT_HIP(hipMemcpyAsync(pat::ptr<float>(n->act.gy) + j * img, d_inputs + idx * img, sizeof(float) * img,
                                  hipMemcpyDeviceToDevice, s));
         }
@@ -632,7 +670,7 @@ extern "C" pat_status pat_warmstart_train(pat_unet n, int32_t count, int32_t h, 
         pat::nn::forward(n, pat::ptr<float>(n->act.gy), s);
         pat::nn::launch_mse(pat::ptr<float>(n->act.y), pat::ptr<float>(n->act.t), pat::ptr<float>(n->act.gy),
                             pat::ptr<double>(n->act.loss_part), pat::ptr<double>(loss_hist) + bi,
-                            (int64_t)B * img, s);
+                            (int64_t)B * timg, s);
         pat::nn::backward(n, s);
         ++n->step;
         const double b1 = 0.9, b2 = 0.999;
@@ -668,8 +706,8 @@ extern "C" pat_status pat_warmstart_save(pat_unet n, const char* path) {
     PAT_HIP(hipMemcpy(v.data(), n->adam_v.p, sizeof(float) * n->n_params, hipMemcpyDeviceToHost));
     std::ofstream out(path, std::ios::binary | std::ios::trunc);
     PAT_CHECK_ARG((bool)out, "cannot open checkpoint for writing");
-    const char magic[8] = {'P', 'A', 'T', 'U', 'N', 'E', 'T', '1'};
-    const int64_t hdr[4] = {n->levels, n->base, n->n_params, n->step};
+    const char magic[8] = {'P', 'A', 'T', 'U', 'N', 'E', 'T', '2'};
+    const int64_t hdr[5] = {n->levels, n->base, n->cout, n->n_params, n->step};
     out.write(magic, 8);
     out.write(reinterpret_cast<const char*>(hdr), sizeof(hdr));
     out.write(reinterpret_cast<const char*>(p.data()), sizeof(float) * n->n_params);
@@ -687,11 +725,11 @@ extern "C" pat_status pat_warmstart_load(pat_unet n, const char* path) {
     std::ifstream in(path, std::ios::binary);
     PAT_CHECK_ARG((bool)in, "cannot open checkpoint");
     char magic[8];
-    int64_t hdr[4];
+    int64_t hdr[5];
     in.read(magic, 8);
     in.read(reinterpret_cast<char*>(hdr), sizeof(hdr));
-    PAT_CHECK_ARG((bool)in && std::string(magic, 8) == "PATUNET1", "not a network checkpoint");
-    PAT_CHECK_ARG(hdr[0] == n->levels && hdr[1] == n->base && hdr[2] == n->n_params,
+    PAT_CHECK_ARG((bool)in && std::string(magic, 8) == "PATUNET2", "not a network checkpoint");
+    PAT_CHECK_ARG(hdr[0] == n->levels && hdr[1] == n->base && hdr[2] == n->cout && hdr[3] == n->n_params,
                   "checkpoint was written for another network shape");
     std::vector<float> p(n->n_params), m(n->n_params), v(n->n_params);
     in.read(reinterpret_cast<char*>(p.data()), sizeof(float) * n->n_params);
@@ -701,45 +739,70 @@ extern "C" pat_status pat_warmstart_load(pat_unet n, const char* path) {
     PAT_HIP(hipMemcpy(n->params.p, p.data(), sizeof(float) * n->n_params, hipMemcpyHostToDevice));
     PAT_HIP(hipMemcpy(n->adam_m.p, m.data(), sizeof(float) * n->n_params, hipMemcpyHostToDevice));
     PAT_HIP(hipMemcpy(n->adam_v.p, v.data(), sizeof(float) * n->n_params, hipMemcpyHostToDevice));
-    n->step = hdr[3];
+    n->step = hdr[4];
     pat::nn::prep_weights(n, nullptr);
     PAT_HIP(hipDeviceSynchronize());
     return PAT_OK;
   });
 }
 
-extern "C" pat_status pat_warmstart_normalize(pat_geometry g, const void* d_f, const void* d_u, float* d_x,
-                                              float* d_t, float* d_scale, void* stream) {
+static void check_dual_reg(const pat_regulariser* reg) {
+  PAT_CHECK_ARG(reg != nullptr, "a dual start needs the regulariser");
+  PAT_CHECK_ARG(reg->kind == PAT_REG_TV, "dual starts are defined for TV only");
+  PAT_CHECK_ARG(std::isfinite(reg->lambda) && reg->lambda > 0.0, "lambda must be > 0");
+}
+
+extern "C" pat_status pat_warmstart_normalize(pat_geometry g, const pat_regulariser* reg, const void* d_f,
+                                              const void* d_state, float* d_x, float* d_t, int32_t t_channels,
+                                              float* d_scale, void* stream) {
   return guarded([&]() -> pat_status {
     PAT_CHECK_ARG(g != nullptr && d_f != nullptr && d_x != nullptr && d_scale != nullptr, "NULL argument");
-    PAT_CHECK_ARG((d_u == nullptr) == (d_t == nullptr), "d_u and d_t go together");
+    PAT_CHECK_ARG((d_state == nullptr) == (d_t == nullptr), "d_state and d_t go together");
+    PAT_CHECK_ARG(t_channels == 1 || t_channels == 3, "t_channels must be 1 or 3");
+    if (d_state && t_channels == 3) check_dual_reg(reg);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (g->dtype == PAT_F64) pat::normalise_impl<double>(g, d_f, d_u, d_x, d_t, d_scale, s);
-    else pat::normalise_impl<float>(g, d_f, d_u, d_x, d_t, d_scale, s);
+    if (g->dtype == PAT_F64) pat::normalise_impl<double>(g, reg, d_f, d_state, d_x, d_t, t_channels, d_scale, s);
+    else pat::normalise_impl<float>(g, reg, d_f, d_state, d_x, d_t, t_channels, d_scale, s);
     return PAT_OK;
   });
 }
 
 template <class T>
-static void infer_impl(pat_unet n, pat_geometry g, const void* d_f, void* d_u0, hipStream_t s) {
-  const int64_t N = g->n_pix();
-  pat::DevBuf x(sizeof(float) * N), sc(sizeof(float)), y(sizeof(float) * N);
-  pat::normalise_impl<T>(g, d_f, nullptr, pat::ptr<float>(x), nullptr, pat::ptr<float>(sc), s);
+static void infer_impl(pat_unet n, pat_geometry g, const pat_regulariser* reg, const void* d_f, void* d_u0,
+                       void* d_y0, hipStream_t s) {
+  const int64_t N = g->n_pix(), nb = g->n_bins();
+  pat::DevBuf x(sizeof(float) * N), sc(sizeof(float));
+  pat::normalise_impl<T>(g, reg, d_f, nullptr, pat::ptr<float>(x), nullptr, 1, pat::ptr<float>(sc), s);
   pat::nn::ensure_act(n, 1, g->ny, g->nx);
   pat::nn::forward(n, pat::ptr<float>(x), s);
-  hipLaunchKernelGGL(pat::rescale_kernel<T>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s,
-                     pat::ptr<float>(n->act.y), pat::ptr<float>(sc), static_cast<T*>(d_u0), N);
+  T* u0 = static_cast<T*>(d_u0);
+  T* q0 = static_cast<T*>(d_y0);
+  T* r0 = q0 ? q0 + nb : nullptr;
+  const unsigned blocks = (unsigned)((N + 255) / 256);
+  hipLaunchKernelGGL(pat::rescale_kernel<T>, dim3(blocks), dim3(256), 0, s, pat::ptr<float>(n->act.y),
+                     pat::ptr<float>(sc), u0, r0, r0 ? reg->lambda : 0.0, N);
   PAT_HIP(hipGetLastError());
+  if (q0) {
+    pat::apply_forward<T>(g, u0, q0, s);
+    hipLaunchKernelGGL(pat::residual_kernel<T>, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, q0,
+                       static_cast<const T*>(d_f), nb);
+    PAT_HIP(hipGetLastError());
+  }
   PAT_HIP(hipStreamSynchronize(s));
 }
 
-extern "C" pat_status pat_warmstart_infer(pat_unet n, pat_geometry g, const void* d_f, void* d_u0, void* stream) {
+extern "C" pat_status pat_warmstart_infer(pat_unet n, pat_geometry g, const pat_regulariser* reg, const void* d_f,
+                                          void* d_u0, void* d_y0, void* stream) {
   return guarded([&]() -> pat_status {
     check_net(n);
     PAT_CHECK_ARG(g != nullptr && d_f != nullptr && d_u0 != nullptr, "NULL argument");
+    if (d_y0) {
+      check_dual_reg(reg);
+      PAT_CHECK_ARG(n->cout == 3, "a dual start needs a network with 3 outputs");
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (g->dtype == PAT_F64) infer_impl<double>(n, g, d_f, d_u0, s);
-    else infer_impl<float>(n, g, d_f, d_u0, s);
+    if (g->dtype == PAT_F64) infer_impl<double>(n, g, reg, d_f, d_u0, d_y0, s);
+    else infer_impl<float>(n, g, reg, d_f, d_u0, d_y0, s);
     return PAT_OK;
   });
 }

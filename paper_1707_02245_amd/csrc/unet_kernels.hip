@@ -271,19 +271,24 @@ void launch_maxpool_back(const View& gout, const uint8_t* idx, const View& gskip
 
 // ------------------------------------------------------------------ head, loss, biases
 
-// y[p] = sum_c h[p][c] bf16(w[c]) + b  (one thread per pixel)
+// y[k] plane of pixel p = sum_c h[p][c] bf16(w[k][c]) + b[k]  (one thread per
+// pixel). Outputs are channel planes: y[((p / hw) K + k) hw + p % hw].
 __global__ __launch_bounds__(256) void head_kernel(View h, const float* __restrict__ w,
                                                    const float* __restrict__ b, float* __restrict__ y,
-                                                   int64_t P) {
+                                                   int64_t P, int K, int64_t hw) {
   const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= P) return;
-  float s = 0.f;
-  for (int c = 0; c < h.C; ++c) s += bf2f(h.p[p * h.pitch + h.off + c]) * bf2f(f2bf(w[c]));
-  y[p] = s + b[0];
+  const int64_t base = (p / hw) * K * hw + p % hw;
+  for (int k = 0; k < K; ++k) {
+    float s = 0.f;
+    for (int c = 0; c < h.C; ++c) s += bf2f(h.p[p * h.pitch + h.off + c]) * bf2f(f2bf(w[k * h.C + c]));
+    y[base + k * hw] = s + b[k];
+  }
 }
 
-void launch_head(const View& h, const float* w, const float* b, float* y, int64_t P, hipStream_t s) {
-  hipLaunchKernelGGL(head_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, h, w, b, y, P);
+void launch_head(const View& h, const float* w, const float* b, float* y, int64_t P, int K, int64_t hw,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(head_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, h, w, b, y, P, K, hw);
   PAT_HIP(hipGetLastError());
 }
 
@@ -320,36 +325,42 @@ void launch_mse(const float* y, const float* t, float* gy, double* part, double*
   PAT_HIP(hipGetLastError());
 }
 
-// head backward: gh[p][c] = bf16(gy[p] bf16(w[c])) * (h > 0); partial sums for gw, gb
+// head backward: gh[p][c] = bf16(sum_k gy[p][k] bf16(w[k][c])) * (h > 0), with
+// gy in channel planes like y; per-block partial sums part[block][0, K C) for
+// gw[k][c] = sum_p gy[p][k] h[p][c] and part[block][K C + k] for gb[k].
 __global__ __launch_bounds__(256) void head_back_kernel(View h, const float* __restrict__ w,
                                                         const float* __restrict__ gy, View gh,
-                                                        float* __restrict__ part, int64_t P,
-                                                        int rows_per_block) {
-  // part[block][c] for c < C: sum_p gy h; part[block][C]: sum_p gy
+                                                        float* __restrict__ part, int64_t P, int K,
+                                                        int64_t hw, int rows_per_block) {
   const int C = h.C;
   const int64_t p0 = (int64_t)blockIdx.x * rows_per_block;
   const int64_t p1 = min(P, p0 + rows_per_block);
-  for (int c = threadIdx.x; c <= C; c += blockDim.x) {
+  for (int e = threadIdx.x; e < K * (C + 1); e += blockDim.x) {
+    const int k = e < K * C ? e / C : e - K * C;
+    const int c = e < K * C ? e % C : -1;
     float s = 0.f;
     for (int64_t p = p0; p < p1; ++p) {
-      const float g = gy[p];
-      s += (c < C) ? g * bf2f(h.p[p * h.pitch + h.off + c]) : g;
+      const float g = gy[((p / hw) * K + k) * hw + p % hw];
+      s += (c >= 0) ? g * bf2f(h.p[p * h.pitch + h.off + c]) : g;
     }
-    part[(int64_t)blockIdx.x * (C + 1) + c] = s;
+    part[(int64_t)blockIdx.x * K * (C + 1) + e] = s;
   }
   for (int64_t e = p0 * C + threadIdx.x; e < p1 * C; e += blockDim.x) {
     const int64_t p = e / C;
     const int c = (int)(e % C);
-    uint16_t v = f2bf(gy[p] * bf2f(f2bf(w[c])));
+    const int64_t g0 = (p / hw) * K * hw + p % hw;
+    float acc = 0.f;
+    for (int k = 0; k < K; ++k) acc += gy[g0 + k * hw] * bf2f(f2bf(w[k * C + c]));
+    uint16_t v = f2bf(acc);
     if (!(bf2f(h.p[p * h.pitch + h.off + c]) > 0.f)) v = 0;
     gh.p16[p * gh.pitch + gh.off + c] = v;
   }
 }
 
 void launch_head_back(const View& h, const float* w, const float* gy, const View& gh, float* part,
-                      int64_t P, int rows_per_block, hipStream_t s) {
+                      int64_t P, int K, int64_t hw, int rows_per_block, hipStream_t s) {
   const int blocks = (int)((P + rows_per_block - 1) / rows_per_block);
-  hipLaunchKernelGGL(head_back_kernel, dim3(blocks), dim3(256), 0, s, h, w, gy, gh, part, P,
+  hipLaunchKernelGGL(head_back_kernel, dim3(blocks), dim3(256), 0, s, h, w, gy, gh, part, P, K, hw,
                      rows_per_block);
   PAT_HIP(hipGetLastError());
 }

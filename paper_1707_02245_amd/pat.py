@@ -199,11 +199,12 @@ class Precond:
 
 
 def _opts(max_iter, gap_tol, gap_every, graph_block, theta, gap_box, u0, state_in,
-          state_out, precond):
+          state_out, precond, y0=None):
     o = L.SolveOpts()
     o.max_iter, o.gap_tol, o.gap_every, o.graph_block = max_iter, gap_tol, gap_every, graph_block
     o.theta, o.gap_box = theta, gap_box
     o.d_u0 = u0.data_ptr() if u0 is not None else None
+    o.d_y0 = y0.data_ptr() if y0 is not None else None
     o.d_state_in = state_in.data_ptr() if state_in is not None else None
     o.d_state_out = state_out.data_ptr() if state_out is not None else None
     o.precond = precond.handle.value if precond is not None else None
@@ -212,7 +213,7 @@ def _opts(max_iter, gap_tol, gap_every, graph_block, theta, gap_box, u0, state_i
 
 def solve(geom: Geometry, f, reg: Reg, max_iter=2000, gap_tol=1e-4, gap_every=10,
           graph_block=50, theta=1.0, gap_box=2.0, u0=None, state_in=None, state_out=None,
-          precond: Precond | None = None, out=None):
+          precond: Precond | None = None, out=None, y0=None):
     """pat_pdhg_solve. Returns (u, info dict, status)."""
     _need(f, geom.dtype, geom.n_det * geom.n_t, "f")
     out = geom.image() if out is None else out
@@ -220,6 +221,8 @@ def solve(geom: Geometry, f, reg: Reg, max_iter=2000, gap_tol=1e-4, gap_every=10
     for name, t in (("u0", u0),):
         if t is not None:
             _need(t, geom.dtype, geom.nx * geom.ny, name)
+    if y0 is not None:
+        _need(y0, geom.dtype, geom.n_det * geom.n_t + 2 * geom.nx * geom.ny, "y0")
     if state_in is not None or state_out is not None:
         n_state = geom.state_elems(reg.kind)
     if state_in is not None:
@@ -230,7 +233,7 @@ def solve(geom: Geometry, f, reg: Reg, max_iter=2000, gap_tol=1e-4, gap_every=10
         _need(reg.theta, geom.dtype, geom.nx * geom.ny, "theta")
     r = reg.c_struct()
     o = _opts(max_iter, gap_tol, gap_every, graph_block, theta, gap_box, u0, state_in,
-              state_out, precond)
+              state_out, precond, y0)
     info = L.SolveInfo()
     st = L.check(L.load().pat_pdhg_solve(geom.handle, _ptr(f), C.byref(r), C.byref(o),
                                          _ptr(out), C.byref(info), _stream()))
@@ -238,8 +241,9 @@ def solve(geom: Geometry, f, reg: Reg, max_iter=2000, gap_tol=1e-4, gap_every=10
 
 
 def solve_batched(problems, max_iter=2000, gap_tol=1e-4, gap_every=10, graph_block=50,
-                  theta=1.0, gap_box=2.0):
-    """pat_pdhg_solve_batched over a list of (geom, f, reg[, precond]) tuples.
+                  theta=1.0, gap_box=2.0, states_out=None):
+    """pat_pdhg_solve_batched over a list of (geom, f, reg[, precond]) tuples;
+    states_out: optional list of state buffers (or None entries).
     Returns (list of u, list of info dicts, status)."""
     n = len(problems)
     geoms = (C.c_void_p * n)()
@@ -259,7 +263,10 @@ def solve_batched(problems, max_iter=2000, gap_tol=1e-4, gap_every=10, graph_blo
         fs[i] = f.data_ptr()
         outs[i] = u.data_ptr()
         regs[i] = reg.c_struct()
+        so = states_out[i] if states_out is not None else None
+        if so is not None:
+            _need(so, g.dtype, g.state_elems(reg.kind), f"states_out[{i}]")
         opts[i] = _opts(max_iter, gap_tol, gap_every, graph_block, theta, gap_box, None, None,
-                        None, pc)
+                        so, pc)
     st = L.check(L.load().pat_pdhg_solve_batched(n, geoms, fs, regs, opts, outs, infos, _stream()))
     return us, [infos[i].as_dict() for i in range(n)], st

@@ -1,0 +1,287 @@
+"""Learned warm start for PDHG: training pairs from the solver, training and
+evaluation, all through the C ABI (marshalling only).
+
+The network maps the normalised backprojection of the data to the normalised
+TV reconstruction and its dual variable (three output planes); at test time
+PDHG starts from its output: u0, q0 = A u0 - f and r0. The solver's gap decides
+the result and a start that is non-finite or worse than zero falls back to
+zero, so the fixed point never depends on the network.
+
+python -m paper_1707_02245_amd.warmstart train --n-train 256 --out weights.npy
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import math
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from . import pat
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class WarmStartNet:
+    """pat_unet handle."""
+
+    def __init__(self, levels=4, base=32, out_ch=3, seed=0):
+        lib = L.load()
+        h = C.c_void_p()
+        L.check(lib.pat_warmstart_create(levels, base, out_ch, seed, C.byref(h)))
+        self._h = h
+        n = C.c_int64()
+        L.check(lib.pat_warmstart_num_params(h, C.byref(n)))
+        self.n_params = n.value
+        self.levels, self.base, self.out_ch = levels, base, out_ch
+
+    def params(self) -> np.ndarray:
+        t = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        L.check(L.load().pat_warmstart_get_params(self._h, C.c_void_p(t.data_ptr()), _stream()))
+        return t.cpu().numpy()
+
+    def set_params(self, v: np.ndarray):
+        t = torch.tensor(np.asarray(v, dtype=np.float32), device="cuda")
+        L.check(L.load().pat_warmstart_set_params(self._h, C.c_void_p(t.data_ptr()), _stream()))
+        torch.cuda.synchronize()
+
+    def save_weights(self, path):
+        np.save(path, self.params())
+
+    def load_weights(self, path):
+        v = np.load(path, allow_pickle=False)
+        if v.shape != (self.n_params,):
+            raise ValueError(f"{path}: {v.shape} parameters, network has {self.n_params}")
+        self.set_params(v)
+
+    def train(self, inputs, targets, epochs, batch, lr, seed=0):
+        n, h, w = inputs.shape
+        opts = L.TrainOpts(epochs=epochs, batch=batch, lr=lr, seed=seed)
+        loss = C.c_double()
+        L.check(L.load().pat_warmstart_train(self._h, n, h, w, C.c_void_p(inputs.data_ptr()),
+                                             C.c_void_p(targets.data_ptr()), C.byref(opts),
+                                             C.byref(loss), _stream()))
+        return loss.value
+
+    def infer(self, geom: pat.Geometry, f, reg: pat.Reg, dual=True):
+        """(u0, y0): the primal start and, with dual, the dual start q0 then r0."""
+        u0 = geom.image()
+        y0 = (torch.empty(geom.n_det * geom.n_t + 2 * geom.nx * geom.ny, dtype=geom.dtype,
+                          device="cuda") if dual else None)
+        r = reg.c_struct()
+        L.check(L.load().pat_warmstart_infer(self._h, geom.handle, C.byref(r), C.c_void_p(f.data_ptr()),
+                                             C.c_void_p(u0.data_ptr()),
+                                             C.c_void_p(y0.data_ptr()) if dual else None, _stream()))
+        return u0, y0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.load().pat_warmstart_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def normalize(geom: pat.Geometry, f, reg: pat.Reg | None = None, state=None, channels=3):
+    """(x, t, scale): normalised backprojection, target planes (from a solver
+    state, else None), scale."""
+    x = torch.empty(geom.ny, geom.nx, dtype=torch.float32, device="cuda")
+    t = (torch.empty(channels, geom.ny, geom.nx, dtype=torch.float32, device="cuda")
+         if state is not None else None)
+    s = torch.empty(1, dtype=torch.float32, device="cuda")
+    r = reg.c_struct() if reg is not None else None
+    L.check(L.load().pat_warmstart_normalize(
+        geom.handle, C.byref(r) if r is not None else None, C.c_void_p(f.data_ptr()),
+        C.c_void_p(state.data_ptr()) if state is not None else None,
+        C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()) if t is not None else None, channels,
+        C.c_void_p(s.data_ptr()), _stream()))
+    return x, t, s
+
+
+_FINE = {}
+
+
+def _fine_geometry(desc):
+    key = tuple(sorted(desc.items()))
+    if key not in _FINE:
+        n = desc["nx"]
+        _FINE.clear()
+        _FINE[key] = pat.Geometry(dtype=torch.float64, **dict(desc, nx=2 * n, ny=2 * n))
+    return _FINE[key]
+
+
+def synth_data(desc, seed, noise=None, dtype=torch.float64):
+    """Data of one seeded phantom: the library's forward operator on the 2x
+    finer grid, plus relative Gaussian noise (level U(1%, 10%) by seed if not
+    given). Returns (f device tensor, ground truth [n][n], noise level)."""
+    import phantoms
+    n = desc["nx"]
+    case = phantoms.make_case("mixed", n, seed, desc["n_det"], desc["n_t"])
+    if noise is None:
+        noise = float(np.random.default_rng([seed, 7]).uniform(0.01, 0.10))
+    fine = _fine_geometry(desc)
+    fc = fine.forward(torch.tensor(case["u_fine"], dtype=torch.float64, device="cuda")).cpu().numpy()
+    f = fc + noise * np.linalg.norm(fc) / math.sqrt(fc.size) * case["noise"]
+    return torch.tensor(f, dtype=dtype, device="cuda"), case["u_gt"], noise
+
+
+def make_pairs(geom, desc, seeds, lam, gap_tol, cap, group=8, channels=3, log=None):
+    """Training pairs: PDHG (TV, lam) solutions to gap_tol in batches that
+    share the geometry; unconverged solves are dropped and counted.
+    Returns (inputs [n][h][w], targets [n][channels][h][w], stats)."""
+    reg = pat.Reg("tv", lam)
+    pc = pat.Precond(geom, reg, "diag")
+    n_state = geom.state_elems("tv")
+    xs, ts, iters, dropped = [], [], [], 0
+    t0 = time.perf_counter()
+    for g0 in range(0, len(seeds), group):
+        fs = [synth_data(desc, s, dtype=geom.dtype)[0] for s in seeds[g0:g0 + group]]
+        states = [torch.empty(n_state, dtype=geom.dtype, device="cuda") for _ in fs]
+        us, infos, st = pat.solve_batched([(geom, f, reg, pc) for f in fs], max_iter=cap,
+                                          gap_tol=gap_tol, gap_every=50, graph_block=50,
+                                          states_out=states)
+        for f, state, info in zip(fs, states, infos):
+            if not info["converged"]:
+                dropped += 1
+                continue
+            x, t, _ = normalize(geom, f, reg, state, channels)
+            xs.append(x)
+            ts.append(t)
+            iters.append(info["iters"])
+        if log:
+            log(f"pairs {g0 + len(fs)}/{len(seeds)}: iters {[i['iters'] for i in infos]} "
+                f"({time.perf_counter() - t0:.1f} s)")
+    return (torch.stack(xs).contiguous(), torch.stack(ts).contiguous(),
+            dict(seconds=time.perf_counter() - t0, iters=iters, dropped=dropped))
+
+
+STARTS = ("zero", "backprojection", "network_primal", "network")
+
+
+def evaluate(geom, desc, net, seeds, lam, gap_tol, cap, starts=STARTS):
+    """Iterations and seconds to gap_tol from zero, from the backprojection
+    A^T f / A^T 1, from the network's primal output alone and from its primal
+    and dual output (inference included in the seconds)."""
+    reg = pat.Reg("tv", lam)
+    pc = pat.Precond(geom, reg, "diag")
+    out = []
+    for s in seeds:
+        f, u_gt, noise = synth_data(desc, s, dtype=geom.dtype)
+        rec = {"seed": s, "noise": noise}
+        x, _, sc = normalize(geom, f)
+        bp = (x.double() * sc.double()).to(geom.dtype).contiguous()
+        for name in starts:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u0 = y0 = None
+            if name == "backprojection":
+                u0 = bp
+            elif name == "network_primal":
+                u0, _ = net.infer(geom, f, reg, dual=False)
+            elif name == "network":
+                u0, y0 = net.infer(geom, f, reg, dual=True)
+            u, info, st = pat.solve(geom, f, reg, max_iter=cap, gap_tol=gap_tol, gap_every=50,
+                                    graph_block=50, u0=u0, y0=y0, precond=pc)
+            torch.cuda.synchronize()
+            rec[name] = dict(iters=info["iters"], seconds=time.perf_counter() - t0,
+                             rel_gap=info["rel_gap"], primal=info["primal"],
+                             fallback=info["fallback"], status=st)
+        out.append(rec)
+    return out
+
+
+def val_loss(net, x, t, batch=8):
+    """Mean squared error of the network on held-out pairs."""
+    n, h, w = x.shape
+    y = torch.empty(batch, net.out_ch, h, w, dtype=torch.float32, device="cuda")
+    tot, cnt = 0.0, 0
+    for i in range(0, n - batch + 1, batch):
+        L.check(L.load().pat_warmstart_forward(net._h, batch, h, w, C.c_void_p(x[i:i + batch].data_ptr()),
+                                               C.c_void_p(y.data_ptr()), _stream()))
+        tot += float(((y - t[i:i + batch]) ** 2).sum())
+        cnt += y.numel()
+    return tot / max(cnt, 1)
+
+
+def _main(argv=None):
+    import phantoms
+    ap = argparse.ArgumentParser()
+    ap.add_argument("cmd", choices=["train"])
+    ap.add_argument("--n-train", type=int, default=512)
+    ap.add_argument("--n-val", type=int, default=16)
+    ap.add_argument("--n-test", type=int, default=4)
+    ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--lam", type=float, default=0.02)
+    ap.add_argument("--target-dtype", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--target-gap", type=float, default=1e-3)
+    ap.add_argument("--gap-tol", type=float, default=1e-4)
+    ap.add_argument("--cap", type=int, default=200000)
+    ap.add_argument("--epochs", type=int, default=240)
+    ap.add_argument("--chunk", type=int, default=10, help="epochs per training call")
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--base", type=int, default=32)
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--report", default=None)
+    a = ap.parse_args(argv)
+
+    def log(m):
+        print(f"[warmstart] {m}", flush=True)
+
+    wl = phantoms.WORKLOADS["tv256"]
+    desc = phantoms.geometry_desc(a.size, wl.n_det, wl.n_t)
+    geom = pat.Geometry(dtype=torch.float64, **desc)
+    tgeom = geom if a.target_dtype == "f64" else pat.Geometry(dtype=torch.float32, **desc)
+    train_seeds = list(range(10000, 10000 + a.n_train))
+    val_seeds = list(range(40000, 40000 + a.n_val))
+    test_seeds = list(range(50000, 50000 + a.n_test))
+    x, t, st = make_pairs(tgeom, desc, train_seeds, a.lam, a.target_gap, a.cap, log=log)
+    log(f"pairs done: {st['seconds']:.1f} s, mean iters {np.mean(st['iters']):.0f}, "
+        f"dropped {st['dropped']}")
+    xv, tv, _ = make_pairs(tgeom, desc, val_seeds, a.lam, a.target_gap, a.cap)
+    net = WarmStartNet(4, a.base, 3, seed=1)
+    t0 = time.perf_counter()
+    done, hist = 0, []
+    while done < a.epochs:
+        ep = min(a.chunk, a.epochs - done)
+        # step schedule: lr for 60% of the epochs, lr/3 for the next 25%, lr/10 after
+        frac = done / a.epochs
+        lr = a.lr if frac < 0.6 else (a.lr / 3 if frac < 0.85 else a.lr / 10)
+        loss = net.train(x, t, ep, a.batch, lr, seed=2 + done)
+        done += ep
+        vl = val_loss(net, xv, tv, a.batch)
+        hist.append(dict(epoch=done, lr=lr, loss=loss, val=vl))
+        log(f"epoch {done}: lr {lr:.1e} train {loss:.4e} val {vl:.4e} ({time.perf_counter() - t0:.0f} s)")
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    net.save_weights(a.out)
+    ev = evaluate(geom, desc, net, test_seeds, a.lam, a.gap_tol, a.cap)
+    for r in ev:
+        log(json.dumps(r))
+    summary = {}
+    for name in STARTS:
+        it = [r[name]["iters"] for r in ev]
+        sec = [r[name]["seconds"] for r in ev]
+        fb = sum(r[name]["fallback"] for r in ev)
+        summary[name] = dict(iters=float(np.mean(it)), seconds=float(np.mean(sec)), fallbacks=fb)
+        log(f"{name:15s} mean iters {np.mean(it):8.0f}  mean s {np.mean(sec):7.3f}  fallbacks {fb}")
+    rep = dict(pairs=st, train_seconds=t_train, history=hist, eval=ev, summary=summary, args=vars(a))
+    if a.report:
+        with open(a.report, "w") as fh:
+            json.dump(rep, fh)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(_main())

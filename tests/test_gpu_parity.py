@@ -294,6 +294,41 @@ def test_warm_start_and_fallback():
         assert info["fallback"] == 1 and rel(host(u), zero) <= 1e-10
 
 
+def test_dual_warm_start_and_fallback():
+    """A start (u0, q0, r0) runs the oracle's iteration from the same state
+    (ubar0 = u0); a non-finite dual start falls back to zero."""
+    d, og, g = _geoms("tv64", "f64")
+    A = OG.forward_matrix(og)
+    f, _ = synth_data(d, "disc", 3)
+    p = oracle_problem(A, f, 64, "tv", 0.05)
+    pc = OP.precond_diag(p)
+    fd = to_dev(f, torch.float64)
+    reg = pat.Reg("tv", 0.05)
+    good = OP.pdhg_solve(p, pc, iters=100)
+    st = OP.init_state(p, good["u"])
+    st["q"], st["r"] = good["q"].copy(), good["r"].copy()
+    ref = OP.pdhg_solve(p, pc, iters=40, state=st)
+    y0 = np.concatenate([good["q"], good["r"].ravel()])
+    n_state = g.state_elems("tv")
+    so = torch.empty(n_state, dtype=torch.float64, device="cuda")
+    u, info, _ = pat.solve(g, fd, reg, max_iter=40, gap_tol=0.0, gap_every=10, graph_block=20,
+                           u0=to_dev(good["u"].reshape(64, 64), torch.float64),
+                           y0=to_dev(y0, torch.float64), state_out=so)
+    assert info["fallback"] == 0 and rel(host(u), ref["u"]) <= 1e-10
+    got = split_state(host(so), "tv", 64 * 64, A.shape[0])
+    assert rel(got["q"], ref["q"]) <= 1e-10 and rel(got["r"], ref["r"]) <= 1e-10
+    zero = OP.pdhg_solve(p, pc, iters=40)["u"]
+    bad = y0.copy()
+    bad[7] = np.nan
+    u, info, _ = pat.solve(g, fd, reg, max_iter=40, gap_tol=0.0, gap_every=10, graph_block=20,
+                           u0=to_dev(good["u"].reshape(64, 64), torch.float64),
+                           y0=to_dev(bad, torch.float64))
+    assert info["fallback"] == 1 and rel(host(u), zero) <= 1e-10
+    with pytest.raises(pat.L.PatError):
+        pat.solve(g, fd, pat.Reg("tgv", 0.05, 0.1), max_iter=10,
+                  u0=to_dev(good["u"].reshape(64, 64), torch.float64), y0=to_dev(y0, torch.float64))
+
+
 def test_converges_to_gap_and_matches_oracle_objective():
     """Run to a gap tolerance: same stopping iteration as the oracle (up to one
     check interval, the FP32 gap rounding near the threshold) and the same

@@ -18,22 +18,22 @@ pytestmark = pytest.mark.gpu
 L = pytest.importorskip("paper_1707_02245_amd._lib")
 
 
-def _net(levels, base, seed=0):
+def _net(levels, base, seed=0, cout=1):
     lib = L.load()
     h = C.c_void_p()
-    L.check(lib.pat_warmstart_create(levels, base, seed, C.byref(h)))
+    L.check(lib.pat_warmstart_create(levels, base, cout, seed, C.byref(h)))
     n = C.c_int64()
     L.check(lib.pat_warmstart_num_params(h, C.byref(n)))
     return lib, h, n.value
 
 
-def _flat(p, levels, base):
-    return np.concatenate([p[name].ravel() for name, _ in U.param_shapes(base, levels)])
+def _flat(p, levels, base, cout=1):
+    return np.concatenate([p[name].ravel() for name, _ in U.param_shapes(base, levels, cout=cout)])
 
 
-def _unflat(v, levels, base):
+def _unflat(v, levels, base, cout=1):
     out, o = {}, 0
-    for name, shp in U.param_shapes(base, levels):
+    for name, shp in U.param_shapes(base, levels, cout=cout):
         k = int(np.prod(shp))
         out[name] = v[o:o + k].reshape(shp)
         o += k
@@ -44,51 +44,59 @@ def _rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-30))
 
 
-def _setup(levels=4, base=8, B=2, H=16, W=24, seed=1):
+def _setup(levels=4, base=8, B=2, H=16, W=24, seed=1, cout=1):
     rng = np.random.default_rng(seed)
-    p = U.init_params(rng, base, levels)
+    p = U.init_params(rng, base, levels, cout)
     for k in p:
         if k.endswith(".b"):
             p[k] = 0.05 * rng.standard_normal(p[k].shape)
     x = U.bf16(rng.standard_normal((B, H, W, 1)))
-    t = rng.standard_normal((B, H, W, 1))
-    lib, h, n = _net(levels, base)
-    flat = _flat(p, levels, base)
+    t = rng.standard_normal((B, H, W, cout))
+    lib, h, n = _net(levels, base, cout=cout)
+    flat = _flat(p, levels, base, cout)
     assert flat.size == n
     dp = torch.tensor(flat, dtype=torch.float32, device="cuda")
     L.check(lib.pat_warmstart_set_params(h, C.c_void_p(dp.data_ptr()), None))
     # the GPU keeps FP32 masters: the oracle starts from the same FP32 values
-    p = _unflat(dp.cpu().numpy().astype(np.float64), levels, base)
+    p = _unflat(dp.cpu().numpy().astype(np.float64), levels, base, cout)
     return lib, h, n, p, x, t
 
 
-def test_parameter_count_matches_oracle():
-    lib, h, n = _net(4, 32)
-    assert n == sum(int(np.prod(s)) for _, s in U.param_shapes(32, 4))
+def _planes(a):
+    """NHWC oracle array -> the library's [n][c][h][w] planes."""
+    return np.ascontiguousarray(np.moveaxis(a, -1, 1))
+
+
+@pytest.mark.parametrize("cout", [1, 3])
+def test_parameter_count_matches_oracle(cout):
+    lib, h, n = _net(4, 32, cout=cout)
+    assert n == sum(int(np.prod(s)) for _, s in U.param_shapes(32, 4, cout=cout))
     lib.pat_warmstart_destroy(h)
 
 
-@pytest.mark.parametrize("shape", [(4, 8, 2, 16, 24), (3, 4, 1, 8, 8), (4, 32, 1, 32, 32)])
+@pytest.mark.parametrize("shape", [(4, 8, 2, 16, 24, 1), (3, 4, 1, 8, 8, 1), (4, 32, 1, 32, 32, 1),
+                                   (4, 8, 2, 16, 24, 3)])
 def test_forward_matches_oracle(shape):
-    levels, base, B, H, W = shape
-    lib, h, n, p, x, t = _setup(levels, base, B, H, W)
+    levels, base, B, H, W, cout = shape
+    lib, h, n, p, x, t = _setup(levels, base, B, H, W, cout=cout)
     dx = torch.tensor(x[..., 0], dtype=torch.float32, device="cuda").contiguous()
-    dy = torch.empty_like(dx)
-    print(f"net levels={levels} base={base} batch={B} {H}x{W}", flush=True)
+    dy = torch.empty(B, cout, H, W, dtype=torch.float32, device="cuda")
+    print(f"net levels={levels} base={base} batch={B} {H}x{W} cout={cout}", flush=True)
     L.check(lib.pat_warmstart_forward(h, B, H, W, C.c_void_p(dx.data_ptr()), C.c_void_p(dy.data_ptr()), None))
     torch.cuda.synchronize()
     y_ref, _ = U.forward(p, x, levels, quant=True)
-    e = _rel(dy.cpu().numpy(), y_ref[..., 0])
+    e = _rel(dy.cpu().numpy(), _planes(y_ref))
     assert e <= 1e-2, e
     lib.pat_warmstart_destroy(h)
 
 
-@pytest.mark.parametrize("shape", [(4, 8, 2, 16, 24), (3, 4, 1, 8, 8)])
+@pytest.mark.parametrize("shape", [(4, 8, 2, 16, 24, 1), (3, 4, 1, 8, 8, 1), (4, 8, 2, 16, 24, 3)])
 def test_gradients_match_oracle(shape):
-    levels, base, B, H, W = shape
-    lib, h, n, p, x, t = _setup(levels, base, B, H, W)
+    levels, base, B, H, W, cout = shape
+    lib, h, n, p, x, t = _setup(levels, base, B, H, W, cout=cout)
+    print(f"net levels={levels} base={base} batch={B} {H}x{W} cout={cout}", flush=True)
     dx = torch.tensor(x[..., 0], dtype=torch.float32, device="cuda").contiguous()
-    dt = torch.tensor(t[..., 0], dtype=torch.float32, device="cuda").contiguous()
+    dt = torch.tensor(_planes(t), dtype=torch.float32, device="cuda").contiguous()
     dg = torch.empty(n, dtype=torch.float32, device="cuda")
     loss = C.c_double()
     L.check(lib.pat_warmstart_grad(h, B, H, W, C.c_void_p(dx.data_ptr()), C.c_void_p(dt.data_ptr()),
@@ -98,9 +106,9 @@ def test_gradients_match_oracle(shape):
     l_ref, gy = U.mse(y_ref, t)
     g_ref = U.backward(cache, gy, levels, quant=True)
     assert loss.value == pytest.approx(l_ref, rel=1e-3)
-    got = _unflat(dg.cpu().numpy().astype(np.float64), levels, base)
+    got = _unflat(dg.cpu().numpy().astype(np.float64), levels, base, cout)
     errs = {k: _rel(got[k], g_ref[k]) for k in g_ref}
-    total = _rel(_flat(got, levels, base), _flat(g_ref, levels, base))
+    total = _rel(_flat(got, levels, base, cout), _flat(g_ref, levels, base, cout))
     assert total <= 3e-2, (total, errs)
     assert max(errs.values()) <= 1e-1, errs
     lib.pat_warmstart_destroy(h)

@@ -48,16 +48,18 @@ def test_pool_and_transposed_conv_by_definition():
                     assert np.allclose(t[0, 2 * i + a, 2 * j + e], b + x[0, i, j] @ w[a, e])
 
 
-def test_gradients_by_finite_differences():
+@pytest.mark.parametrize("cout", [1, 3])
+def test_gradients_by_finite_differences(cout):
     rng = np.random.default_rng(2)
     base, levels = 3, 4
-    p = U.init_params(rng, base, levels)
+    p = U.init_params(rng, base, levels, cout)
     for k in p:
         if k.endswith(".b"):
             p[k] = 0.1 * rng.standard_normal(p[k].shape)
     x = rng.standard_normal((2, 8, 8, 1))
-    t = rng.standard_normal((2, 8, 8, 1))
+    t = rng.standard_normal((2, 8, 8, cout))
     y, cache = U.forward(p, x, levels)
+    assert y.shape == t.shape
     loss, gy = U.mse(y, t)
     g = U.backward(cache, gy, levels)
     assert set(g) == set(p)
@@ -78,6 +80,9 @@ def test_gradients_by_finite_differences():
 def test_parameter_count_of_the_32_channel_network():
     n = sum(int(np.prod(s)) for _, s in U.param_shapes(32, 4))
     assert 1.9e6 < n < 2.0e6
+    # three outputs add two rows of the 1x1 head
+    n3 = sum(int(np.prod(s)) for _, s in U.param_shapes(32, 4, cout=3))
+    assert n3 - n == 2 * (32 + 1)
 
 
 def test_adam_on_a_quadratic():
