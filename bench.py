@@ -44,6 +44,9 @@ def parse():
     p.add_argument("--apply-reps", type=int, default=50)
     p.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     p.add_argument("--no-batched", action="store_true", help="skip the batched leg")
+    p.add_argument("--no-learned", action="store_true", help="skip the learned warm-start leg")
+    p.add_argument("--learned-seeds", type=int, default=2,
+                   help="held-out phantoms of the learned warm-start leg")
     return p.parse_args()
 
 
@@ -113,6 +116,38 @@ def batched_leg(pat, torch, g, wl, fc, reg, pc, args, tdt, n_wl=4):
                 speedup=t_seq / t_batched, iters_batched=[i["iters"] for i in infos_b],
                 iters_sequential=iters_seq,
                 rel_gaps=[i["rel_gap"] for i in infos_b], status=st_b)
+
+
+WEIGHTS = os.path.join(ROOT, "paper_1707_02245_amd", "weights", "warmstart_tv256.npy")
+
+
+def learned_leg(pat, torch, g, args):
+    """The 256^2 TV warm-start workload (lambda 0.02, geometry of the TGV
+    workload, mixed phantom families, noise U(1%, 10%)): FP64 time to rel_gap
+    1e-4 from zero and from the trained network's start (inference included),
+    on held-out seeds."""
+    import phantoms
+    from paper_1707_02245_amd import warmstart as W
+    wl = phantoms.WORKLOADS["tv256"]
+    desc = phantoms.geometry_desc(wl.n, wl.n_det, wl.n_t)
+    net = W.WarmStartNet(4, 32, 3, seed=0)
+    net.load_weights(WEIGHTS)
+    reg = pat.Reg("tv", wl.lam)
+    pc = pat.Precond(g, reg, "diag")
+    seeds = list(wl.seeds[:args.learned_seeds])
+    # untimed warm-up of the inference path (activation buffers)
+    f0, _, _ = W.synth_data(desc, seeds[0], dtype=g.dtype)
+    net.infer(g, f0, reg, dual=True)
+    res = W.evaluate(g, desc, net, seeds, wl.lam, wl.gap_tol, args.cap,
+                     starts=("zero", "network"))
+    z = [r["zero"] for r in res]
+    n = [r["network"] for r in res]
+    t_z = sum(r["seconds"] for r in z)
+    t_n = sum(r["seconds"] for r in n)
+    return dict(workload="tv256: 256x256 TV (lambda 0.02), geometry of tgv256, FP64, rel_gap 1e-4",
+                seeds=seeds, zero_s=t_z / len(z), network_s=t_n / len(n),
+                zero_iters=[r["iters"] for r in z], network_iters=[r["iters"] for r in n],
+                fallbacks=sum(r["fallback"] for r in n), speedup=t_z / t_n)
 
 
 def cpu_baseline(desc, f, wl, gpu_iters, budget_s=20.0):
@@ -216,15 +251,27 @@ def main():
     n_win = info_g["n_window"]
     nnz = info_g["csr_nnz"]
     n_pix, n_bins = wl.n * wl.n, wl.n_det * wl.n_t
-    # algorithmic bytes of one A^T apply by the stored CSR: values + column
-    # indices + row offsets, the input vector once and the output once
-    adj_bytes = nnz * (esz + 4) + 8 * (n_pix + 1) + esz * (n_bins + n_pix)
+    side = info_g["csr_tile_side"] if info_g["adj_mode"] == 2 else 0
+    tname = "double" if esz == 8 else "float"
+    if side:
+        # algorithmic bytes of one A^T apply by the tiled CSR: values + 16-bit
+        # window offsets + row offsets + the per-(tile, detector) windows, the
+        # input vector once and the output once
+        n_tiles = -(-wl.n // side) ** 2
+        adj_bytes = nnz * (esz + 2) + 8 * (n_pix + 1) + 16 * n_tiles * wl.n_det + esz * (n_bins + n_pix)
+        kname = f"csr_tiled_kernel<{tname}, false, 1> (A^T by the stored CSR, {side}x{side} pixel tiles, LDS-staged input)"
+    else:
+        # plain CSR: values + 32-bit columns + row offsets, input and output once
+        adj_bytes = nnz * (esz + 4) + 8 * (n_pix + 1) + esz * (n_bins + n_pix)
+        kname = f"csr_spmv_kernel<{tname}, false> (A^T by the stored CSR)"
+    csr_equiv = nnz * (esz + 4) + 8 * (n_pix + 1) + esz * (n_bins + n_pix)
     apply = dict(forward_ms=t_fwd * 1e3, adjoint_ms=t_adj * 1e3, window_samples=n_win,
-                 csr_nnz=nnz, adjoint_bytes=adj_bytes,
+                 csr_nnz=nnz, adjoint_bytes=adj_bytes, csr_tile_side=side,
                  forward_gsamples_s=n_win / t_fwd * 1e-9,
-                 adjoint_gbs=adj_bytes / t_adj * 1e-9)
+                 adjoint_gbs=adj_bytes / t_adj * 1e-9,
+                 adjoint_plain_csr_equivalent_gbs=csr_equiv / t_adj * 1e-9)
     log(f"apply: {apply}")
-    roofline = {"kernel": f"csr_spmv_kernel<{'double' if esz == 8 else 'float'}> (A^T by the stored CSR)",
+    roofline = {"kernel": kname,
                 "bound": "hbm", "achieved": adj_bytes / t_adj * 1e-9, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": adj_bytes / t_adj * 1e-9 / HBM_PEAK_GBS,
                 "traffic": None, "bytes_per_launch": adj_bytes,
@@ -259,6 +306,13 @@ def main():
         log("batched leg: 4 wavelengths sharing the geometry")
         out["batched"] = batched_leg(pat, torch, g, wl, fc_np, reg, pc, args, tdt)
         log(f"batched: {out['batched']}")
+    if not args.no_learned:
+        if args.dtype != "f64":
+            log("learned leg runs in FP64 only; skipped")
+        else:
+            log("learned leg: TV 256^2 from zero vs from the network start")
+            out["learned"] = learned_leg(pat, torch, g, args)
+            log(f"learned: {out['learned']}")
     if not args.no_cpu:
         log("cpu baseline (oracle, bounded sample)")
         out["cpu_baseline"] = cpu_baseline(desc, f_np, wl, iters)

@@ -92,8 +92,11 @@ typedef struct {
   int64_t n_window;       /* arc samples inside the clip windows (work per apply) */
   int32_t dtype;          /* pat_dtype */
   int32_t fwd_lanes_log2, adj_tile, adj_det_group; /* launch parameters */
-  int32_t adj_mode;       /* 0 tile scatter, 1 stored CSR of A^T */
+  int32_t adj_mode;       /* 0 tile scatter, 1 stored CSR of A^T, 2 the CSR with
+                           * LDS-staged input windows (in effect) */
   int64_t csr_nnz;        /* non-zeros of the stored A^T (-1: not built) */
+  int32_t csr_tile_side;  /* pixel tile side of mode 2 (8 or 4; 0: none) */
+  int32_t csr_win_max;    /* largest staged window of a tile (elements) */
 } pat_geometry_info;
 
 /* Build the geometry tables on the device (FP64 host computation, rounded to
@@ -113,9 +116,13 @@ pat_status pat_geometry_set_launch(pat_geometry g, int32_t fwd_lanes_log2,
                                    int32_t adj_tile, int32_t adj_det_group);
 
 /* How pat_adjoint and the solvers apply A^T: 0 = matrix-free tile scatter
- * (no stored matrix), 1 = stored CSR of A^T (built on first use; default).
- * Both give the transpose of the same matrix (FP64 sample positions and the
- * same weight products); results agree to rounding order. */
+ * (no stored matrix), 1 = stored CSR of A^T (built at geometry creation),
+ * 2 = the same CSR read per 8x8 (or 4x4) pixel tile with the tile's input
+ * windows staged in LDS and 16-bit window offsets (default; falls back to 1
+ * when a tile's windows exceed 64 KB of LDS, reported by get_info). All give
+ * the transpose of the same matrix (FP64 sample positions and the same weight
+ * products); results agree to rounding order. Invalid mode:
+ * PAT_ERR_INVALID_ARG. */
 pat_status pat_geometry_set_adjoint(pat_geometry g, int32_t mode, void* stream);
 
 /* Autotuner of the projector launch parameters. Times, with HIP events over

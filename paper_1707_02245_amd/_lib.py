@@ -42,7 +42,8 @@ class GeometryInfo(C.Structure):
         ("n_samples", C.c_int64), ("n_window", C.c_int64),
         ("dtype", C.c_int32),
         ("fwd_lanes_log2", C.c_int32), ("adj_tile", C.c_int32), ("adj_det_group", C.c_int32),
-        ("adj_mode", C.c_int32), ("csr_nnz", C.c_int64),
+        ("adj_mode", C.c_int32), ("csr_nnz", C.c_int64), ("csr_tile_side", C.c_int32),
+        ("csr_win_max", C.c_int32),
     ]
 
 

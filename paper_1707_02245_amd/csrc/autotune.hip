@@ -1,8 +1,8 @@
 // Launch-parameter autotuner of the projector kernels, with an on-disk cache.
 //
 // Candidates: forward lanes per bin (16, 32, 64) and the adjoint path (stored
-// CSR, or the matrix-free tile scatter with 16/32/64-pixel tiles and a few
-// detector-group sizes). Each candidate is timed with HIP events over `reps`
+// CSR, plain or with LDS-staged input windows, or the matrix-free tile
+// scatter with 16/32/64-pixel tiles and a few detector-group sizes). Each candidate is timed with HIP events over `reps`
 // stand-alone applies on the caller's stream; the fastest of each kind is
 // kept. Results are cached per (device architecture, geometry shape, element
 // type) in a plain text file: one line per key, "key lanes adj_mode tile group".
@@ -92,12 +92,17 @@ void tune(pat_geometry_s* g, int reps, hipStream_t s, pat_autotune_result* res) 
     if (t < best_f) { best_f = t; best_l = l; }
   }
   g->lanes_log2 = best_l;
-  // adjoint: stored CSR vs scatter variants
+  // adjoint: stored CSR (plain and LDS-staged) vs scatter variants
   double best_a = 1e30;
   int best_mode = 1, best_tile = g->tile, best_group = g->det_group;
   g->adj_mode = 1;
   g->ensure_csr(s);
   best_a = time_op<T>(s, reps, [&] { apply_adjoint<T>(g, ptr<T>(f), ptr<T>(out_u), s); });
+  if (g->csr_side > 0) {
+    g->adj_mode = 2;
+    const double t = time_op<T>(s, reps, [&] { apply_adjoint<T>(g, ptr<T>(f), ptr<T>(out_u), s); });
+    if (t < best_a) { best_a = t; best_mode = 2; }
+  }
   const int tiles[3] = {16, 32, 64};
   for (int ti = 0; ti < 3; ++ti) {
     const int tile = tiles[ti];
@@ -143,12 +148,12 @@ extern "C" pat_status pat_geometry_autotune(pat_geometry g, const char* cache_pa
       int lanes = 0, mode = -1, tile = 0, group = 0;
       double tf = 0, ta = 0;
       if (in >> lanes >> mode >> tile >> group >> tf >> ta && lanes >= 4 && lanes <= 6 &&
-          (mode == 0 || mode == 1) && (tile == 16 || tile == 32 || tile == 64) && group >= 1 &&
+          (mode >= 0 && mode <= 2) && (tile == 16 || tile == 32 || tile == 64) && group >= 1 &&
           group <= g->n_det) {
         g->lanes_log2 = lanes;
         g->tile = tile;
         g->det_group = group;
-        if (mode == 1) g->ensure_csr(s);
+        if (mode != 0) g->ensure_csr(s);
         g->adj_mode = mode;
         res.forward_ms = tf;
         res.adjoint_ms = ta;

@@ -11,6 +11,13 @@
 // out in bin order (detector-major, then radius), so the build is
 // deterministic and needs no sort. A count pass and a fill pass share the
 // enumeration; the row offsets are a host prefix sum.
+//
+// Apply: the rows of one pixel tile (8 x 8, or 4 x 4 when the windows would
+// not fit) touch, per detector, a short run of consecutive radii (the circles
+// through the tile). The tiled kernel stages these windows of the input in
+// LDS once per tile and reads the non-zeros with 16-bit window offsets, so
+// the input gathers hit LDS instead of the L2 and each non-zero streams 2
+// index bytes instead of 4.
 
 #include <numeric>
 #include <type_traits>
@@ -113,6 +120,100 @@ __global__ __launch_bounds__(256) void csr_build_kernel(GeomDev g, int* __restri
   if (!row_ptr && lane == 0) row_cnt[pix] = total;
 }
 
+// Per tile and detector: the smallest and largest radius index of the
+// non-zeros of the tile's rows (rows hold bins in increasing order, so each
+// detector is one run found by binary search).
+__global__ __launch_bounds__(256) void csr_window_kernel(const int64_t* __restrict__ ptr, const int* __restrict__ col,
+                                                         int nx, int ny, int side, int tiles_x, int n_det, int n_t,
+                                                         int4* __restrict__ win) {
+  const int t = blockIdx.x;
+  const int tx = t % tiles_x, ty = t / tiles_x;
+  for (int d = threadIdx.x; d < n_det; d += blockDim.x) {
+    const int c0 = d * n_t, c1 = c0 + n_t;
+    int lo = n_t, hi = -1;
+    for (int r = 0; r < side * side; ++r) {
+      const int i = tx * side + r % side, j = ty * side + r / side;
+      if (i >= nx || j >= ny) continue;
+      const int64_t p = (int64_t)j * nx + i;
+      int64_t a = ptr[p], b = ptr[p + 1];
+      const int64_t end = b;
+      while (a < b) {
+        const int64_t m = (a + b) >> 1;
+        if (col[m] < c0) a = m + 1; else b = m;
+      }
+      for (int64_t e = a; e < end && col[e] < c1; ++e) {
+        const int k = col[e] - c0;
+        lo = min(lo, k);
+        hi = max(hi, k);
+      }
+    }
+    win[(int64_t)t * n_det + d] = hi < 0 ? make_int4(0, 0, 0, 0) : make_int4(lo, hi - lo + 1, 0, 0);
+  }
+}
+
+// lcol[e] = off + k - k0 of the entry's tile and detector (one wave per row)
+__global__ __launch_bounds__(256) void csr_lcol_kernel(const int64_t* __restrict__ ptr, const int* __restrict__ col,
+                                                       const int4* __restrict__ win, int nx, int ny, int side,
+                                                       int tiles_x, int n_det, int n_t,
+                                                       uint16_t* __restrict__ lcol) {
+  const int64_t N = (int64_t)nx * ny;
+  const int64_t pix = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (pix >= N) return;
+  const int i = (int)(pix % nx), j = (int)(pix / nx);
+  const int64_t t = (int64_t)(j / side) * tiles_x + i / side;
+  for (int64_t e = ptr[pix] + lane; e < ptr[pix + 1]; e += 64) {
+    const int c = col[e];
+    const int d = c / n_t, k = c - d * n_t;
+    const int4 w = win[t * n_det + d];
+    lcol[e] = (uint16_t)(w.z + k - w.x);
+  }
+}
+
+void build_csr_tiles(pat_geometry_s* geo, size_t esz, hipStream_t s) {
+  geo->csr_side = 0;
+  geo->csr_tiles_x = geo->csr_tiles_y = geo->csr_win_max = 0;
+  const int64_t N = geo->n_pix();
+  if (geo->csr_nnz <= 0) return;
+  const int nd = geo->n_det;
+  for (int side : {8, 4}) {
+    const int tx = (geo->nx + side - 1) / side, ty = (geo->ny + side - 1) / side;
+    const int64_t nt = (int64_t)tx * ty;
+    DevBuf win(sizeof(int4) * nt * nd);
+    hipLaunchKernelGGL(csr_window_kernel, dim3((unsigned)nt), dim3(256), 0, s, ptr<int64_t>(geo->csr_ptr),
+                       ptr<int>(geo->csr_col), geo->nx, geo->ny, side, tx, nd, geo->n_t, ptr<int4>(win));
+    PAT_HIP(hipGetLastError());
+    std::vector<int4> h(nt * nd);
+    PAT_HIP(hipMemcpyAsync(h.data(), win.p, sizeof(int4) * h.size(), hipMemcpyDeviceToHost, s));
+    PAT_HIP(hipStreamSynchronize(s));
+    int64_t win_max = 0;
+    for (int64_t t = 0; t < nt; ++t) {
+      int64_t off = 0;
+      for (int d = 0; d < nd; ++d) {
+        int4& w = h[t * nd + d];
+        w.z = (int)off;
+        off += w.y;
+      }
+      win_max = std::max(win_max, off);
+    }
+    // the 16-bit offsets and one right-hand side must fit the LDS budget
+    if (win_max < 1 || win_max > 65535 || (int64_t)esz * win_max > kCsrLdsBytes) continue;
+    PAT_HIP(hipMemcpyAsync(win.p, h.data(), sizeof(int4) * h.size(), hipMemcpyHostToDevice, s));
+    geo->csr_lcol.alloc(sizeof(uint16_t) * geo->csr_nnz);
+    hipLaunchKernelGGL(csr_lcol_kernel, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, s,
+                       ptr<int64_t>(geo->csr_ptr), ptr<int>(geo->csr_col), ptr<int4>(win), geo->nx, geo->ny,
+                       side, tx, nd, geo->n_t, ptr<uint16_t>(geo->csr_lcol));
+    PAT_HIP(hipGetLastError());
+    PAT_HIP(hipStreamSynchronize(s));
+    geo->csr_win = std::move(win);
+    geo->csr_side = side;
+    geo->csr_tiles_x = tx;
+    geo->csr_tiles_y = ty;
+    geo->csr_win_max = (int)win_max;
+    return;
+  }
+}
+
 template <class T>
 void build_csr_adjoint(pat_geometry_s* geo, hipStream_t s) {
   const GeomDev g = geo->dev();
@@ -140,6 +241,7 @@ void build_csr_adjoint(pat_geometry_s* geo, hipStream_t s) {
   PAT_HIP(hipGetLastError());
   PAT_HIP(hipStreamSynchronize(s));
   geo->csr_nnz = nnz;
+  build_csr_tiles(geo, sizeof(T), s);
 }
 
 // y[row] = sum_e val[e] x[col[e]]: one wave per row, lanes stride the row.
@@ -165,12 +267,13 @@ __global__ __launch_bounds__(256) void csr_spmv_kernel(CsrArgs<T> a0, const CsrA
   const int64_t row = (int64_t)blk * 4 + threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
   if (row >= a.n_rows) return;  // whole wave
-  const int64_t e0 = a.ptr[row], e1 = a.ptr[row + 1];
+  const gptr<const int64_t> rowp = as_global(a.ptr);
+  const int64_t e0 = rowp[row], e1 = rowp[row + 1];
   using Acc = typename std::conditional<WIDE, double, T>::type;
   Acc acc0 = Acc(0), acc1 = Acc(0), acc2 = Acc(0), acc3 = Acc(0);
-  const T* __restrict__ val = a.val;
-  const int* __restrict__ col = a.col;
-  const T* __restrict__ x = a.x;
+  const gptr<const T> val = as_global(a.val);
+  const gptr<const int> col = as_global(a.col);
+  const gptr<const T> x = as_global(a.x);
   int64_t e = e0 + lane;
   // four independent entries per lane in flight: the column loads of all four
   // are issued before the dependent gathers of x
@@ -219,15 +322,16 @@ __global__ __launch_bounds__(256) void csr_spmm_kernel(const CsrMultiArgs<T>* __
   const int nr = a.nrhs;
   using Acc = typename std::conditional<WIDE, double, T>::type;
   Acc acc[R];
-  const T* xs[R];
+  gptr<const T> xs[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     acc[r] = Acc(0);
-    xs[r] = a.x[r];
+    xs[r] = as_global(a.x[r]);
   }
-  const int64_t e0 = a.ptr[row], e1 = a.ptr[row + 1];
-  const T* __restrict__ val = a.val;
-  const int* __restrict__ col = a.col;
+  const gptr<const int64_t> rowp = as_global(a.ptr);
+  const int64_t e0 = rowp[row], e1 = rowp[row + 1];
+  const gptr<const T> val = as_global(a.val);
+  const gptr<const int> col = as_global(a.col);
   int64_t e = e0 + lane;
   for (; e + 64 < e1; e += 128) {
     const int c0 = __builtin_nontemporal_load(col + e);
@@ -304,6 +408,135 @@ void launch_csr_spmv_batched(const CsrArgs<T>* arr, const int* starts, int n_ins
                        starts, n_inst);
   PAT_HIP(hipGetLastError());
 }
+
+// One block per pixel tile (4 waves): stage the tile's input windows of every
+// right-hand side in LDS, then one wave per row as in the plain kernel with
+// the gathers served by LDS. Rows outside the image (ragged tiles) are skipped.
+template <class T, bool WIDE, int R>
+__global__ __launch_bounds__(256) void csr_tiled_kernel(CsrMultiArgs<T> a0, const CsrMultiArgs<T>* __restrict__ arr,
+                                                        const int* __restrict__ starts, int n_grp, int stride) {
+  extern __shared__ char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  int blk = blockIdx.x;
+  const CsrMultiArgs<T>* ap = &a0;
+  if (arr) {
+    int lo = 0, hi = n_grp;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (starts[mid] <= blk) lo = mid; else hi = mid;
+    }
+    ap = arr + lo;
+    blk -= starts[lo];
+  }
+  const CsrMultiArgs<T>& a = *ap;
+  const int nr = a.nrhs;
+  const int side = a.side;
+  const int tx = blk % a.tiles_x, ty = blk / a.tiles_x;
+  const int n_det = a.n_det, n_t = a.n_t, nx = a.nx, ny = a.ny;
+  const int4* __restrict__ win = a.win + (int64_t)blk * n_det;
+  for (int d = threadIdx.x; d < n_det; d += 256) {
+    const int4 w = win[d];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (R == 1 || r < nr) {
+        const gptr<const T> src = as_global(a.x[r]) + (int64_t)d * n_t + w.x;
+        T* dst = lds + r * stride + w.z;
+        for (int i = 0; i < w.y; ++i) dst[i] = src[i];
+      }
+    }
+  }
+  __syncthreads();
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int per_wave = side * side / 4;
+  using Acc = typename std::conditional<WIDE, double, T>::type;
+  const gptr<const int64_t> rowp = as_global(a.ptr);
+  const gptr<const uint16_t> lcol = as_global(a.lcol);
+  const gptr<const T> val = as_global(a.val);
+  for (int rr = wave * per_wave; rr < (wave + 1) * per_wave; ++rr) {
+    const int i = tx * side + rr % side, j = ty * side + rr / side;
+    if (i >= nx || j >= ny) continue;  // whole wave
+    const int64_t pix = (int64_t)j * nx + i;
+    const int64_t e0 = rowp[pix], e1 = rowp[pix + 1];
+    Acc acc[R][4];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[r][u] = Acc(0);
+    int64_t e = e0 + lane;
+    for (; e + 192 < e1; e += 256) {
+      uint16_t c[4];
+      T v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) c[u] = __builtin_nontemporal_load(lcol + e + 64 * u);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = __builtin_nontemporal_load(val + e + 64 * u);
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (R == 1 || r < nr)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc[r][u] += (Acc)v[u] * (Acc)lds[r * stride + c[u]];
+    }
+    for (; e < e1; e += 64) {
+      const uint16_t c = __builtin_nontemporal_load(lcol + e);
+      const T v = __builtin_nontemporal_load(val + e);
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (R == 1 || r < nr) acc[r][0] += (Acc)v * (Acc)lds[r * stride + c];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (R == 1 || r < nr) {
+        const Acc t = group_sum<64>((acc[r][0] + acc[r][1]) + (acc[r][2] + acc[r][3]));
+        if (lane == 0) {
+          if (WIDE) a.y64[r][pix] = (double)t;
+          else a.y[r][pix] = (T)t;
+        }
+      }
+    }
+  }
+}
+
+template <class T, bool WIDE>
+static void tiled_dispatch(int max_rhs, const CsrMultiArgs<T>& a0, const CsrMultiArgs<T>* arr, const int* starts,
+                           int n_grp, int blocks, int stride, hipStream_t s) {
+  PAT_CHECK_ARG(max_rhs >= 1 && max_rhs <= kMaxRhs, "bad right-hand side count");
+  const size_t shm = sizeof(T) * (size_t)stride * (size_t)max_rhs;
+  PAT_CHECK_ARG(shm <= (size_t)kCsrLdsBytes, "staged windows exceed the LDS budget");
+  if (max_rhs <= 1)
+    hipLaunchKernelGGL((csr_tiled_kernel<T, WIDE, 1>), dim3(blocks), dim3(256), shm, s, a0, arr, starts, n_grp, stride);
+  else if (max_rhs <= 2)
+    hipLaunchKernelGGL((csr_tiled_kernel<T, WIDE, 2>), dim3(blocks), dim3(256), shm, s, a0, arr, starts, n_grp, stride);
+  else if (max_rhs <= 4)
+    hipLaunchKernelGGL((csr_tiled_kernel<T, WIDE, 4>), dim3(blocks), dim3(256), shm, s, a0, arr, starts, n_grp, stride);
+  else
+    hipLaunchKernelGGL((csr_tiled_kernel<T, WIDE, kMaxRhs>), dim3(blocks), dim3(256), shm, s, a0, arr, starts, n_grp,
+                       stride);
+  PAT_HIP(hipGetLastError());
+}
+
+template <class T>
+void launch_csr_tiled(const CsrMultiArgs<T>& a, int lds_stride, hipStream_t s, bool wide) {
+  const int blocks = a.tiles_x * ((a.ny + a.side - 1) / a.side);
+  if (blocks <= 0) return;
+  if (wide) tiled_dispatch<T, true>(a.nrhs, a, nullptr, nullptr, 1, blocks, lds_stride, s);
+  else tiled_dispatch<T, false>(a.nrhs, a, nullptr, nullptr, 1, blocks, lds_stride, s);
+}
+
+template <class T>
+void launch_csr_tiled_batched(const CsrMultiArgs<T>* arr, const int* starts, int n_grp, int total_blocks,
+                              int lds_stride, hipStream_t s, bool wide, int max_rhs) {
+  if (total_blocks <= 0) return;
+  CsrMultiArgs<T> dummy{};
+  if (wide) tiled_dispatch<T, true>(max_rhs, dummy, arr, starts, n_grp, total_blocks, lds_stride, s);
+  else tiled_dispatch<T, false>(max_rhs, dummy, arr, starts, n_grp, total_blocks, lds_stride, s);
+}
+
+template void launch_csr_tiled<float>(const CsrMultiArgs<float>&, int, hipStream_t, bool);
+template void launch_csr_tiled<double>(const CsrMultiArgs<double>&, int, hipStream_t, bool);
+template void launch_csr_tiled_batched<float>(const CsrMultiArgs<float>*, const int*, int, int, int, hipStream_t,
+                                              bool, int);
+template void launch_csr_tiled_batched<double>(const CsrMultiArgs<double>*, const int*, int, int, int, hipStream_t,
+                                               bool, int);
 
 template void build_csr_adjoint<float>(pat_geometry_s*, hipStream_t);
 template void build_csr_adjoint<double>(pat_geometry_s*, hipStream_t);

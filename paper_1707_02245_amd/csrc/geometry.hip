@@ -326,8 +326,10 @@ extern "C" pat_status pat_geometry_get_info(pat_geometry g, pat_geometry_info* o
     out->fwd_lanes_log2 = g->lanes_log2;
     out->adj_tile = g->tile;
     out->adj_det_group = g->det_group;
-    out->adj_mode = g->adj_mode;
+    out->adj_mode = g->adj_mode != 0 ? g->effective_adj_mode() : 0;
     out->csr_nnz = g->csr_nnz;
+    out->csr_tile_side = g->csr_side;
+    out->csr_win_max = g->csr_win_max;
     return PAT_OK;
   });
 }
@@ -344,8 +346,8 @@ extern "C" pat_status pat_geometry_set_launch(pat_geometry g, int32_t lanes_log2
 extern "C" pat_status pat_geometry_set_adjoint(pat_geometry g, int32_t mode, void* stream) {
   return guarded([&]() -> pat_status {
     PAT_CHECK_ARG(g != nullptr, "geometry is NULL");
-    PAT_CHECK_ARG(mode == 0 || mode == 1, "adjoint mode must be 0 (scatter) or 1 (CSR)");
-    if (mode == 1) g->ensure_csr(static_cast<hipStream_t>(stream));
+    PAT_CHECK_ARG(mode >= 0 && mode <= 2, "adjoint mode must be 0 (scatter), 1 (CSR) or 2 (tiled CSR)");
+    if (mode != 0) g->ensure_csr(static_cast<hipStream_t>(stream));
     g->adj_mode = mode;
     return PAT_OK;
   });

@@ -96,6 +96,14 @@ struct DevBuf {
 
 template <class T> inline T* ptr(const DevBuf& b) { return static_cast<T*>(b.p); }
 
+// Global-memory view of a device pointer read from an argument table: loads
+// through generic pointers compile to flat loads, which also count against
+// the LDS counter and so serialise with LDS reads.
+template <class T> using gptr = __attribute__((address_space(1))) T*;
+template <class T> __device__ __forceinline__ gptr<const T> as_global(const T* p) {
+  return (gptr<const T>)p;
+}
+
 inline size_t dtype_size(int dt) { return dt == PAT_F64 ? sizeof(double) : sizeof(float); }
 
 // ---------------------------------------------------------------- device helpers
@@ -163,10 +171,11 @@ struct GeomDev {
 template <class T>
 __device__ __forceinline__ double2 table_cs(const GeomDev& g, int idx) {
   if constexpr (sizeof(T) == 8) {
-    return static_cast<const double2*>(g.cs)[idx];
+    const gptr<const double> c = as_global(static_cast<const double*>(g.cs)) + 2 * (int64_t)idx;
+    return make_double2(c[0], c[1]);
   } else {
-    const float2 c = static_cast<const float2*>(g.cs)[idx];
-    return make_double2((double)c.x, (double)c.y);
+    const gptr<const float> c = as_global(static_cast<const float*>(g.cs)) + 2 * (int64_t)idx;
+    return make_double2((double)c[0], (double)c[1]);
   }
 }
 
@@ -243,6 +252,12 @@ struct CsrMultiArgs {
   const T* x[kMaxRhs];
   T* y[kMaxRhs];
   double* y64[kMaxRhs];
+  // LDS-staged variant: rows grouped in side x side pixel tiles; per tile and
+  // detector the window {k0, len, off, 0} of the bins its rows touch, staged
+  // at LDS offset off; lcol = off + k - k0 replaces col
+  const uint16_t* lcol;
+  const int4* win;
+  int side, tiles_x, nx, ny, n_det, n_t;
 };
 
 // Ordered final sum of one instance's gap partials.

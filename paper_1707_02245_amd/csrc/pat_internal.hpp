@@ -17,10 +17,14 @@ struct pat_geometry_s {
   pat::DevBuf d_det, d_rad, d_moff, d_cs, d_win;
   // launch parameters
   int lanes_log2 = 6, tile = 32, det_group = 16;
-  // adjoint: 0 = tile scatter (matrix-free), 1 = stored CSR of A^T
-  int adj_mode = 1;
+  // adjoint: 0 = tile scatter (matrix-free), 1 = stored CSR of A^T,
+  // 2 = stored CSR with the input windows of pixel tiles staged in LDS
+  int adj_mode = 2;
   pat::DevBuf csr_ptr, csr_col, csr_val;
   int64_t csr_nnz = -1;  // -1: not built
+  // pixel tiles of the stored A^T (side 0: windows too large for LDS)
+  int csr_side = 0, csr_tiles_x = 0, csr_tiles_y = 0, csr_win_max = 0;
+  pat::DevBuf csr_lcol, csr_win;  // uint16 per non-zero; int4 per (tile, detector)
   // scratch of the stand-alone applies
   pat::DevBuf scratch_pad, scratch_part;
 
@@ -30,6 +34,9 @@ struct pat_geometry_s {
   void default_launch();
   pat::GeomDev dev() const;
   void ensure_csr(hipStream_t s);
+  int n_csr_tiles() const { return csr_tiles_x * csr_tiles_y; }
+  // the adjoint mode in effect (2 falls back to 1 without tiles)
+  int effective_adj_mode() const { return adj_mode == 2 && csr_side == 0 ? 1 : adj_mode; }
   int64_t n_bins() const { return (int64_t)n_det * n_t; }
   int64_t n_pix() const { return (int64_t)nx * ny; }
   int n_groups() const { return (n_det + det_group - 1) / det_group; }
@@ -73,6 +80,8 @@ struct Launch {
   // instances whose adjoint is the stored CSR of A^T
   DevBuf csr, csr_start;
   int n_adj = 0, n_csr = 0, csr_total = 0, csr_max_rhs = 1;
+  bool csr_tiled = false;  // LDS-staged kernel for every CSR group
+  int csr_stride = 0;      // its window length per right-hand side
   int lanes_log2 = 6;   // shared by every instance of one launch
   int max_tile = 32;    // shared by every instance of one launch
 };
@@ -100,6 +109,7 @@ void apply_adjoint(pat_geometry_s* g, const T* f, T* u, hipStream_t s);
 // ---- stored A^T (csr.hip)
 template <class T>
 void build_csr_adjoint(pat_geometry_s* geo, hipStream_t s);
+void build_csr_tiles(pat_geometry_s* geo, size_t esz, hipStream_t s);
 template <class T>
 void launch_csr_spmv(const CsrArgs<T>& a, hipStream_t s);
 template <class T>
@@ -108,6 +118,14 @@ void launch_csr_spmv_batched(const CsrArgs<T>* arr, const int* starts, int n_ins
 template <class T>
 void launch_csr_spmm_batched(const CsrMultiArgs<T>* arr, const int* starts, int n_grp, int total_blocks,
                              hipStream_t s, bool wide, int max_rhs);
+// LDS-staged variant: one block per pixel tile; lds_stride = window length
+// (elements) per right-hand side, at most kCsrLdsBytes / sizeof(T) / max_rhs.
+constexpr int kCsrLdsBytes = 64 * 1024;
+template <class T>
+void launch_csr_tiled(const CsrMultiArgs<T>& a, int lds_stride, hipStream_t s, bool wide);
+template <class T>
+void launch_csr_tiled_batched(const CsrMultiArgs<T>* arr, const int* starts, int n_grp, int total_blocks,
+                              int lds_stride, hipStream_t s, bool wide, int max_rhs);
 
 // ---- launchers (pdhg.hip)
 template <class T>

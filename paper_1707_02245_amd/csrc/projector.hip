@@ -106,7 +106,7 @@ __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T
     const double2 rr = g.rad[k];
     inv_m = rr.y;
     const int toff = g.moff[k].y;
-    const T* __restrict__ up = a.upad;
+    const gptr<const T> up = as_global(a.upad);
     const int P = g.pitch;
     const int nx = g.nx, ny = g.ny;
     // weighted 2x2 gather of one arc sample (zero outside the grid)
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T
       const T tx = (T)s.tx, ty = (T)s.ty;
       const T w00 = (T(1) - tx) * (T(1) - ty), w10 = tx * (T(1) - ty);
       const T w01 = (T(1) - tx) * ty, w11 = tx * ty;
-      const T* q = up + (int64_t)(s.iy + 1) * P + (s.ix + 1);
+      const gptr<const T> q = up + (int64_t)(s.iy + 1) * P + (s.ix + 1);
       return w00 * q[0] + w10 * q[1] + w01 * q[P] + w11 * q[P + 1];
     };
     const int rng[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
@@ -411,8 +411,28 @@ void forward_impl(pat_geometry g, const void* d_u, void* d_f, hipStream_t s) {
 
 template <class T>
 void adjoint_impl(pat_geometry g, const void* d_f, void* d_u, hipStream_t s) {
-  if (g->adj_mode == 1) {
-    g->ensure_csr(s);
+  if (g->adj_mode != 0) g->ensure_csr(s);
+  if (g->effective_adj_mode() == 2) {
+    pat::CsrMultiArgs<T> c{};
+    c.ptr = pat::ptr<int64_t>(g->csr_ptr);
+    c.col = pat::ptr<int>(g->csr_col);
+    c.val = pat::ptr<T>(g->csr_val);
+    c.n_rows = g->n_pix();
+    c.nrhs = 1;
+    c.x[0] = static_cast<const T*>(d_f);
+    c.y[0] = static_cast<T*>(d_u);
+    c.lcol = pat::ptr<uint16_t>(g->csr_lcol);
+    c.win = pat::ptr<int4>(g->csr_win);
+    c.side = g->csr_side;
+    c.tiles_x = g->csr_tiles_x;
+    c.nx = g->nx;
+    c.ny = g->ny;
+    c.n_det = g->n_det;
+    c.n_t = g->n_t;
+    pat::launch_csr_tiled<T>(c, g->csr_win_max, s, false);
+    return;
+  }
+  if (g->adj_mode != 0) {
     pat::CsrArgs<T> c{};
     c.ptr = pat::ptr<int64_t>(g->csr_ptr);
     c.col = pat::ptr<int>(g->csr_col);

@@ -249,7 +249,7 @@ class Solver {
       I.s.alloc(sizeof(T) * 3 * N);
     }
     const GeomDev gd = I.gdev(lanes_log2, tile);
-    I.csr = g->adj_mode == 1;
+    I.csr = g->adj_mode != 0;
     if (I.csr) g->ensure_csr(s);
     I.atq_part.alloc(sizeof(T) * (I.csr ? 1 : gd.n_groups) * N);
     if (I.csr) I.atq64.alloc(sizeof(double) * N);
@@ -309,6 +309,7 @@ class Solver {
     std::vector<InstDev<T>> id(n);
     std::vector<GapFinishArgs> gf(n);
     std::vector<int> fs(n + 1), as(1, 0), cs(1, 0), ps(n + 1);
+    std::vector<pat_geometry> csr_geo;  // geometry of each CSR group
     fs[0] = ps[0] = 0;
     for (int k = 0; k < n; ++k) {
       const Inst<T>& I = *inst[act[k]];
@@ -334,12 +335,23 @@ class Solver {
         if (!grp) {
           cd.push_back(CsrMultiArgs<T>{});
           grp = &cd.back();
-          grp->ptr = ptr<int64_t>(I.g->csr_ptr);
-          grp->col = ptr<int>(I.g->csr_col);
-          grp->val = ptr<T>(I.g->csr_val);
-          grp->n_rows = I.g->n_pix();
+          pat_geometry g = I.g;
+          grp->ptr = ptr<int64_t>(g->csr_ptr);
+          grp->col = ptr<int>(g->csr_col);
+          grp->val = ptr<T>(g->csr_val);
+          grp->n_rows = g->n_pix();
           grp->nrhs = 0;
-          cs.push_back(cs.back() + I.n_csr);
+          if (g->effective_adj_mode() == 2) {
+            grp->lcol = ptr<uint16_t>(g->csr_lcol);
+            grp->win = ptr<int4>(g->csr_win);
+            grp->side = g->csr_side;
+            grp->tiles_x = g->csr_tiles_x;
+          }
+          grp->nx = g->nx;
+          grp->ny = g->ny;
+          grp->n_det = g->n_det;
+          grp->n_t = g->n_t;
+          csr_geo.push_back(g);
         }
         grp->x[grp->nrhs] = ptr<T>(I.q);
         grp->y[grp->nrhs] = ptr<T>(I.atq_part);
@@ -357,6 +369,20 @@ class Solver {
       gf[k] = GapFinishArgs{ptr<double>(I.red), I.red_stride, I.n_fwd, I.n_pix};
       fs[k + 1] = fs[k] + I.n_fwd;
       ps[k + 1] = ps[k] + I.n_pix;
+    }
+    // CSR groups: the LDS-staged kernel when every group has tiles and the
+    // windows of all its right-hand sides fit the LDS budget, else the plain one
+    int max_rhs = 1, stride = 0;
+    bool tiled = !cd.empty();
+    for (size_t c = 0; c < cd.size(); ++c) {
+      max_rhs = std::max(max_rhs, cd[c].nrhs);
+      tiled = tiled && cd[c].lcol != nullptr;
+      if (cd[c].lcol) stride = std::max(stride, csr_geo[c]->csr_win_max);
+    }
+    tiled = tiled && (int64_t)sizeof(T) * stride * max_rhs <= kCsrLdsBytes;
+    for (size_t c = 0; c < cd.size(); ++c) {
+      const int blocks = tiled ? csr_geo[c]->n_csr_tiles() : (int)((cd[c].n_rows + 3) / 4);
+      cs.push_back(cs.back() + blocks);
     }
     auto up = [&](DevBuf& b, const void* src, size_t bytes) {
       b.ensure(bytes);
@@ -378,8 +404,9 @@ class Solver {
     L.adj_total = as.back();
     L.n_adj = (int)ad.size();
     L.n_csr = (int)cd.size();
-    L.csr_max_rhs = 1;
-    for (const auto& c : cd) L.csr_max_rhs = std::max(L.csr_max_rhs, c.nrhs);
+    L.csr_max_rhs = max_rhs;
+    L.csr_tiled = tiled;
+    L.csr_stride = stride;
     L.csr_total = cs.back();
     L.pix_total = ps[n];
     L.lanes_log2 = lanes_log2;
@@ -404,12 +431,15 @@ class Solver {
     launch_reg_dual<T>(L, s);
     if (L.n_adj > 0) launch_adjoint_batched<T>(L, s);
     if (L.n_csr > 0) {
-      launch_csr_spmm_batched<T>(ptr<CsrMultiArgs<T>>(L.csr), ptr<int>(L.csr_start), L.n_csr,
-                                 L.csr_total, s, false, L.csr_max_rhs);
       // check iterations: A^T q once more with FP64 accumulation for the gap
-      if (check)
-        launch_csr_spmm_batched<T>(ptr<CsrMultiArgs<T>>(L.csr), ptr<int>(L.csr_start), L.n_csr,
-                                   L.csr_total, s, true, L.csr_max_rhs);
+      for (int wide = 0; wide <= (check ? 1 : 0); ++wide) {
+        if (L.csr_tiled)
+          launch_csr_tiled_batched<T>(ptr<CsrMultiArgs<T>>(L.csr), ptr<int>(L.csr_start), L.n_csr,
+                                      L.csr_total, L.csr_stride, s, wide != 0, L.csr_max_rhs);
+        else
+          launch_csr_spmm_batched<T>(ptr<CsrMultiArgs<T>>(L.csr), ptr<int>(L.csr_start), L.n_csr,
+                                     L.csr_total, s, wide != 0, L.csr_max_rhs);
+      }
     }
     launch_primal<T>(L, check, s);
     if (check) enqueue_gap(c);

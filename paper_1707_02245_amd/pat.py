@@ -92,8 +92,9 @@ class Geometry:
         return self.refresh_info()
 
     def set_adjoint(self, mode):
-        """mode: "scatter" (matrix-free) or "csr" (stored A^T)."""
-        m = {"scatter": 0, "csr": 1}[mode]
+        """mode: "scatter" (matrix-free), "csr" (stored A^T) or "tiled" (stored
+        A^T with LDS-staged input windows)."""
+        m = {"scatter": 0, "csr": 1, "tiled": 2}[mode]
         L.check(L.load().pat_geometry_set_adjoint(self._h, m, _stream()))
         return self.refresh_info()
 

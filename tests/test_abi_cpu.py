@@ -74,3 +74,47 @@ def test_null_handles_rejected():
     assert lib.pat_pdhg_solve_batched(0, None, None, None, None, None, None,
                                       None) == L.PAT_ERR_INVALID_ARG
     assert lib.pat_geometry_destroy(None) == L.PAT_OK
+
+
+STRUCTS = {
+    "pat_geometry_desc": "GeometryDesc", "pat_geometry_info": "GeometryInfo",
+    "pat_autotune_result": "AutotuneResult", "pat_regulariser": "Regulariser",
+    "pat_solve_opts": "SolveOpts", "pat_solve_info": "SolveInfo", "pat_train_opts": "TrainOpts",
+}
+
+
+C_NAME = {"lam": "lambda"}  # ctypes names that are Python keywords
+
+
+def test_struct_layouts_match_the_binding(tmp_path):
+    """sizeof and every field offset of the C structs (compiled from the
+    header by the host C compiler) equal the ctypes mirrors."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    from paper_1707_02245_amd import _lib as L
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pat.h"', 'int main(void) {']
+    for cname, pyname in STRUCTS.items():
+        st = getattr(L, pyname)
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in st._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {C_NAME.get(fname, fname)}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln:
+            a, b, c = ln.split()
+            got[(a, b)] = int(c)
+    for cname, pyname in STRUCTS.items():
+        st = getattr(L, pyname)
+        assert got[(cname, "size")] == C.sizeof(st), cname
+        for fname, _ in st._fields_:
+            assert got[(cname, fname)] == getattr(st, fname).offset, (cname, fname)

@@ -56,7 +56,7 @@ def _geoms(name, dt):
     return d, og, g
 
 
-@pytest.mark.parametrize("adj", ["csr", "scatter"])
+@pytest.mark.parametrize("adj", ["tiled", "csr", "scatter"])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 @pytest.mark.parametrize("name", list(CASES))
 def test_forward_adjoint_elementwise(name, dt, adj):
@@ -88,7 +88,7 @@ def test_launch_shapes_agree_with_oracle(launch):
     assert ef <= 1e-5 and ea <= 1e-5, (ef, ea)
 
 
-@pytest.mark.parametrize("adj", ["csr", "scatter"])
+@pytest.mark.parametrize("adj", ["tiled", "csr", "scatter"])
 def test_adjoint_is_deterministic(adj):
     d = desc_for(96, 40, 150)
     g = pat.Geometry(dtype=torch.float32, **d)
@@ -107,13 +107,58 @@ def test_csr_matches_oracle_matrix_structure():
     assert g.info["csr_nnz"] == A.nnz
 
 
+def _expected_tiles(A, nx, ny, n_det, n_t, esz):
+    """Tile side and largest window of the LDS-staged adjoint: per tile of
+    side x side pixels and detector, the run of radii its non-zeros span; the
+    first side (8, then 4) whose largest per-tile sum of runs fits 64 KB of one
+    right-hand side and 16-bit offsets, else no tiles."""
+    At = A.T.tocsr()
+    At.eliminate_zeros()
+    for side in (8, 4):
+        tx, ty = -(-nx // side), -(-ny // side)
+        wmax = 0
+        for t in range(tx * ty):
+            lo = np.full(n_det, n_t)
+            hi = np.full(n_det, -1)
+            for r in range(side * side):
+                i, j = (t % tx) * side + r % side, (t // tx) * side + r // side
+                if i < nx and j < ny:
+                    cols = At.indices[At.indptr[j * nx + i]:At.indptr[j * nx + i + 1]]
+                    np.minimum.at(lo, cols // n_t, cols % n_t)
+                    np.maximum.at(hi, cols // n_t, cols % n_t)
+            wmax = max(wmax, int(np.sum(np.where(hi >= 0, hi - lo + 1, 0))))
+        if 1 <= wmax <= 65535 and wmax * esz <= 65536:
+            return side, wmax
+    return 0, 0
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(64, 16, 3500), (64, 16, 8000), (37, 7, 53)])
+def test_tile_choice_and_tiled_adjoint(shape, dt):
+    """Long windows (fine time sampling): 8x8 tiles, 4x4 tiles or the plain
+    CSR, as the LDS budget allows; the adjoint matches the oracle in each."""
+    n, n_det, n_t = shape
+    d = desc_for(n, n_det, n_t)
+    og = OG.make_geometry(d)
+    A = OG.forward_matrix(og)
+    side, wmax = _expected_tiles(A, n, n, n_det, n_t, 8 if dt == "f64" else 4)
+    print(f"tiles {shape} {dt}: expected side {side} window {wmax}", flush=True)
+    g = pat.Geometry(dtype=DT[dt], **d)
+    info = g.info
+    assert (info["csr_tile_side"], info["csr_win_max"]) == (side, wmax)
+    assert info["adj_mode"] == (2 if side else 1)
+    y = np.random.default_rng(4).standard_normal(og.n_bins)
+    aty = host(g.adjoint(to_dev(y.reshape(n_det, n_t), DT[dt])))
+    assert rel(aty, A.T @ y) <= TOL_APPLY[dt]
+
+
 FULL = {
     "tgv256": (256, 256, 512, 2 * math.pi),
     "dtv512": (512, 128, 1024, math.pi / 2),
 }
 
 
-@pytest.mark.parametrize("adj", ["csr", "scatter"])
+@pytest.mark.parametrize("adj", ["tiled", "csr", "scatter"])
 @pytest.mark.parametrize("name", list(FULL))
 def test_full_size_sampled_rows_columns_and_dot(name, adj):
     """Workload sizes: sampled rows of A and columns of A (= rows of A^T)
@@ -226,14 +271,17 @@ def test_fixed_iterations_full_state(kind, dt):
     assert abs(info["gap"] - g_ref["gap"]) <= (1e-10 if dt == "f64" else 1e-5) * g_ref["P"]
 
 
+@pytest.mark.parametrize("adj", ["tiled", "csr", "scatter"])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
-def test_tv64_workload_200_iterations(dt):
+def test_tv64_workload_200_iterations(dt, adj):
     """The 64^2 TV workload: lambda 0.05, DIAG, 200 iterations from zero, on
-    disc-phantom data synthesised on the 128^2 grid with 5% noise."""
+    disc-phantom data synthesised on the 128^2 grid with 5% noise (each
+    adjoint path of the solver)."""
     d = desc_for(64, 32, 128)
     og = OG.make_geometry(d)
     A = OG.forward_matrix(og)
     g = pat.Geometry(dtype=DT[dt], **d)
+    g.set_adjoint(adj)
     for seed in (0, 1):
         f, _ = synth_data(d, "disc", seed)
         p = oracle_problem(A, f, 64, "tv", 0.05)
@@ -241,7 +289,7 @@ def test_tv64_workload_200_iterations(dt):
         u, info, _ = pat.solve(g, to_dev(f, DT[dt]), pat.Reg("tv", 0.05), max_iter=200,
                                gap_tol=0.0, gap_every=50, graph_block=50)
         e = rel(host(u), ref["u"])
-        print(f"tv64 {dt} seed {seed}: rel L2 image {e:.3e}", flush=True)
+        print(f"tv64 {dt} {adj} seed {seed}: rel L2 image {e:.3e}", flush=True)
         assert e <= (1e-10 if dt == "f64" else 1e-3)
 
 
