@@ -30,6 +30,32 @@ sys.path.insert(0, ROOT)
 METRIC = "PDHG time-to-gap 1e-4 at 256²: plain vs batched vs learned start; A/Aᵀ GB/s"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the tiled FP64 A^T kernel at this workload: FETCH_SIZE and
+# WRITE_SIZE from two rocprofv3 counter passes, scaled by what the counters read for a
+# plain copy of known size (FETCH x 2, WRITE x 1); profiles/csr_tiled_tgv256_f64_hbm_traffic.md.
+# Reported only while the kernel's sources are the ones measured.
+MEASURED_TRAFFIC = {
+    "kernel": "csr_tiled_kernel<double, false, 1>",
+    "bytes_per_launch": 681.1e6,
+    "sources": {
+        "paper_1707_02245_amd/csrc/csr.hip":
+            "8c14c65f240ed3e66dddf86ba9b9d04cea9c9e8f4f9132659577d052c399ca20",
+        "paper_1707_02245_amd/csrc/pat_common.hpp":
+            "ad11e7f5d36da5d702f8f485361d91b396e202bfa6179932ef4da342084c1df0",
+    },
+}
+
+
+def measured_traffic(kernel_name):
+    import hashlib
+    if not kernel_name.startswith(MEASURED_TRAFFIC["kernel"]):
+        return None
+    for rel, digest in MEASURED_TRAFFIC["sources"].items():
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != digest:
+                return None
+    return MEASURED_TRAFFIC["bytes_per_launch"]
+
 
 def parse():
     p = argparse.ArgumentParser()
@@ -47,6 +73,9 @@ def parse():
     p.add_argument("--no-learned", action="store_true", help="skip the learned warm-start leg")
     p.add_argument("--learned-seeds", type=int, default=2,
                    help="held-out phantoms of the learned warm-start leg")
+    p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                   help="after the JSON line, stream MIB MiB through a plain elementwise copy "
+                        "(3 launches) as the reference for hardware byte counters")
     return p.parse_args()
 
 
@@ -207,7 +236,10 @@ def main():
     tdt = torch.float64 if args.dtype == "f64" else torch.float32
     esz = 8 if args.dtype == "f64" else 4
     g = pat.Geometry(dtype=tdt, **desc)
-    info_g = g.info
+    # launch shapes by the library's autotuner (outside the timed region)
+    tune = g.autotune(None, reps=10)
+    log(f"autotune: {tune}")
+    info_g = g.refresh_info()
     f = torch.tensor(f_np, dtype=tdt, device="cuda")
     reg = pat.Reg("tgv", wl.lam, wl.alpha0)
     t0 = time.perf_counter()
@@ -274,7 +306,9 @@ def main():
     roofline = {"kernel": kname,
                 "bound": "hbm", "achieved": adj_bytes / t_adj * 1e-9, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": adj_bytes / t_adj * 1e-9 / HBM_PEAK_GBS,
-                "traffic": None, "bytes_per_launch": adj_bytes,
+                "traffic": measured_traffic(kname) if (wl.name == "tgv256" and esz == 8) else None,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 counters, copy-calibrated)",
+                "bytes_per_launch": adj_bytes,
                 "avg_launch_us": t_adj * 1e6}
 
     out = {
@@ -295,6 +329,7 @@ def main():
                                "on a closed circle of radius 1.2, 512 time samples (radii 0..2.4), "
                                "DIAG step sizes, stop at relative box gap 1e-4 (C=2), gap every "
                                f"{args.gap_every} iterations, cap {args.cap}",
+                   "launch": {k: tune[k] for k in ("fwd_lanes_log2", "adj_mode")},
                    "iterations": iters, "rel_gap": infos[-1]["rel_gap"],
                    "loop_seconds": infos[-1]["seconds"], "precond_ms": t_precond * 1e3,
                    "cap2000": {"iters": info_cap["iters"], "rel_gap": info_cap["rel_gap"],
@@ -317,6 +352,15 @@ def main():
         log("cpu baseline (oracle, bounded sample)")
         out["cpu_baseline"] = cpu_baseline(desc, f_np, wl, iters)
     print(json.dumps(out), flush=True)
+    if args.calibrate_copy > 0:
+        # known traffic: reads and writes calibrate_copy MiB per launch
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.add(src, 0.0, out=dst)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 x {args.calibrate_copy} MiB read + written")
 
 
 if __name__ == "__main__":

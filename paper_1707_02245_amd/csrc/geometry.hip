@@ -270,13 +270,17 @@ void pat_geometry_s::set_launch(int lanes_log2_, int tile_, int det_group_) {
 }
 
 void pat_geometry_s::default_launch() {
-  // Enough adjoint workgroups to fill 256 CUs several times over.
-  tile = (nx >= 384 && ny >= 384) ? 32 : 32;
+  // Scatter adjoint: enough workgroups to fill 256 CUs several times over.
+  tile = 32;
   const int tiles = ((nx + tile - 1) / tile) * ((ny + tile - 1) / tile);
   int groups = std::max(1, (2048 + tiles - 1) / tiles);
   groups = std::min(groups, n_det);
   det_group = (n_det + groups - 1) / groups;
-  lanes_log2 = 6;
+  // Forward: 16 lanes per bin keep each lane on several arc samples at the
+  // workload sizes (about 200-450 in-window samples per bin); wider groups
+  // only for very long arcs. The autotuner refines this per geometry.
+  const double per_bin = n_bins() > 0 ? (double)n_window / (double)n_bins() : 0.0;
+  lanes_log2 = per_bin > 2048.0 ? 6 : (per_bin > 1024.0 ? 5 : 4);
 }
 
 using pat::guarded;
