@@ -414,7 +414,7 @@ void launch_csr_spmv_batched(const CsrArgs<T>* arr, const int* starts, int n_ins
 // the gathers served by LDS. Rows outside the image (ragged tiles) are skipped.
 template <class T, bool WIDE, int R>
 __global__ __launch_bounds__(256) void csr_tiled_kernel(CsrMultiArgs<T> a0, const CsrMultiArgs<T>* __restrict__ arr,
-                                                        const int* __restrict__ starts, int n_grp, int stride) {
+                                                        const int* __restrict__ starts, int n_grp) {
   extern __shared__ char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
   int blk = blockIdx.x;
@@ -431,6 +431,7 @@ __global__ __launch_bounds__(256) void csr_tiled_kernel(CsrMultiArgs<T> a0, cons
   const CsrMultiArgs<T>& a = *ap;
   const int nr = a.nrhs;
   const int side = a.side;
+  const int stride = a.lds_stride;
   const int tx = blk % a.tiles_x, ty = blk / a.tiles_x;
   const int n_det = a.n_det, n_t = a.n_t, nx = a.nx, ny = a.ny;
   const int4* __restrict__ win = a.win + (int64_t)blk * n_det;
@@ -470,18 +471,18 @@ __global__ __launch_bounds__(256) void csr_tiled_kernel(CsrMultiArgs<T> a0, cons
       for (int u = 0; u < 4; ++u) c[u] = __builtin_nontemporal_load(lcol + e + 64 * u);
 #pragma unroll
       for (int u = 0; u < 4; ++u) v[u] = __builtin_nontemporal_load(val + e + 64 * u);
+      // every slot is computed (slots past nrhs read stale LDS and are not
+      // stored): no per-slot branches between the LDS reads
 #pragma unroll
       for (int r = 0; r < R; ++r)
-        if (R == 1 || r < nr)
 #pragma unroll
-          for (int u = 0; u < 4; ++u) acc[r][u] += (Acc)v[u] * (Acc)lds[r * stride + c[u]];
+        for (int u = 0; u < 4; ++u) acc[r][u] += (Acc)v[u] * (Acc)lds[r * stride + c[u]];
     }
     for (; e < e1; e += 64) {
       const uint16_t c = __builtin_nontemporal_load(lcol + e);
       const T v = __builtin_nontemporal_load(val + e);
 #pragma unroll
-      for (int r = 0; r < R; ++r)
-        if (R == 1 || r < nr) acc[r][0] += (Acc)v * (Acc)lds[r * stride + c];
+      for (int r = 0; r < R; ++r) acc[r][0] += (Acc)v * (Acc)lds[r * stride + c];
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -496,47 +497,80 @@ __global__ __launch_bounds__(256) void csr_tiled_kernel(CsrMultiArgs<T> a0, cons
   }
 }
 
+template <class T, bool WIDE, int R>
+static void tiled_launch(size_t shm, const CsrMultiArgs<T>& a0, const CsrMultiArgs<T>* arr, const int* starts,
+                         int n_grp, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL((csr_tiled_kernel<T, WIDE, R>), dim3(blocks), dim3(256), shm, s, a0, arr, starts, n_grp);
+}
+
 template <class T, bool WIDE>
 static void tiled_dispatch(int max_rhs, const CsrMultiArgs<T>& a0, const CsrMultiArgs<T>* arr, const int* starts,
-                           int n_grp, int blocks, int stride, hipStream_t s) {
+                           int n_grp, int blocks, size_t shm, hipStream_t s) {
   PAT_CHECK_ARG(max_rhs >= 1 && max_rhs <= kMaxRhs, "bad right-hand side count");
-  const size_t shm = sizeof(T) * (size_t)stride * (size_t)max_rhs;
-  PAT_CHECK_ARG(shm <= (size_t)kCsrLdsBytes, "staged windows exceed the LDS budget");
-  if (max_rhs <= 1)
-    hipLaunchKernelGGL((csr_tiled_kernel<T, WIDE, 1>), dim3(blocks), dim3(256), shm, s, a0, arr, starts, n_grp, stride);
-  else if (max_rhs <= 2)
-    hipLaunchKernelGGL((csr_tiled_kernel<T, WIDE, 2>), dim3(blocks), dim3(256), shm, s, a0, arr, starts, n_grp, stride);
-  else if (max_rhs <= 4)
-    hipLaunchKernelGGL((csr_tiled_kernel<T, WIDE, 4>), dim3(blocks), dim3(256), shm, s, a0, arr, starts, n_grp, stride);
-  else
-    hipLaunchKernelGGL((csr_tiled_kernel<T, WIDE, kMaxRhs>), dim3(blocks), dim3(256), shm, s, a0, arr, starts, n_grp,
-                       stride);
+  PAT_CHECK_ARG(shm <= (size_t)device_lds_per_block(), "staged windows exceed the LDS of a workgroup");
+  if (max_rhs <= 1) tiled_launch<T, WIDE, 1>(shm, a0, arr, starts, n_grp, blocks, s);
+  else if (max_rhs <= 2) tiled_launch<T, WIDE, 2>(shm, a0, arr, starts, n_grp, blocks, s);
+  else if (max_rhs <= 4) tiled_launch<T, WIDE, 4>(shm, a0, arr, starts, n_grp, blocks, s);
+  else tiled_launch<T, WIDE, kMaxRhs>(shm, a0, arr, starts, n_grp, blocks, s);
   PAT_HIP(hipGetLastError());
 }
 
+int device_lds_per_block() {
+  static thread_local int cached_dev = -1, cached = 0;
+  int dev = 0;
+  PAT_HIP(hipGetDevice(&dev));
+  if (dev != cached_dev) {
+    int v = 0;
+    PAT_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    cached = v;
+    cached_dev = dev;
+  }
+  return cached;
+}
+
+template <class T, bool WIDE, int R>
+static void raise_lds(size_t shm) {
+  PAT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&csr_tiled_kernel<T, WIDE, R>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+}
+
 template <class T>
-void launch_csr_tiled(const CsrMultiArgs<T>& a, int lds_stride, hipStream_t s, bool wide) {
+void prepare_csr_tiled(int max_rhs, size_t shm) {
+  if (shm <= 65536) return;
+  PAT_CHECK_ARG(shm <= (size_t)device_lds_per_block(), "staged windows exceed the LDS of a workgroup");
+  if (max_rhs <= 1) { raise_lds<T, false, 1>(shm); raise_lds<T, true, 1>(shm); }
+  else if (max_rhs <= 2) { raise_lds<T, false, 2>(shm); raise_lds<T, true, 2>(shm); }
+  else if (max_rhs <= 4) { raise_lds<T, false, 4>(shm); raise_lds<T, true, 4>(shm); }
+  else { raise_lds<T, false, kMaxRhs>(shm); raise_lds<T, true, kMaxRhs>(shm); }
+}
+
+template <class T>
+void launch_csr_tiled(const CsrMultiArgs<T>& a, hipStream_t s, bool wide) {
   const int blocks = a.tiles_x * ((a.ny + a.side - 1) / a.side);
   if (blocks <= 0) return;
-  if (wide) tiled_dispatch<T, true>(a.nrhs, a, nullptr, nullptr, 1, blocks, lds_stride, s);
-  else tiled_dispatch<T, false>(a.nrhs, a, nullptr, nullptr, 1, blocks, lds_stride, s);
+  const size_t shm = sizeof(T) * (size_t)a.lds_stride * (size_t)a.nrhs;
+  prepare_csr_tiled<T>(a.nrhs, shm);
+  if (wide) tiled_dispatch<T, true>(a.nrhs, a, nullptr, nullptr, 1, blocks, shm, s);
+  else tiled_dispatch<T, false>(a.nrhs, a, nullptr, nullptr, 1, blocks, shm, s);
 }
 
 template <class T>
 void launch_csr_tiled_batched(const CsrMultiArgs<T>* arr, const int* starts, int n_grp, int total_blocks,
-                              int lds_stride, hipStream_t s, bool wide, int max_rhs) {
+                              size_t shm, hipStream_t s, bool wide, int max_rhs) {
   if (total_blocks <= 0) return;
   CsrMultiArgs<T> dummy{};
-  if (wide) tiled_dispatch<T, true>(max_rhs, dummy, arr, starts, n_grp, total_blocks, lds_stride, s);
-  else tiled_dispatch<T, false>(max_rhs, dummy, arr, starts, n_grp, total_blocks, lds_stride, s);
+  if (wide) tiled_dispatch<T, true>(max_rhs, dummy, arr, starts, n_grp, total_blocks, shm, s);
+  else tiled_dispatch<T, false>(max_rhs, dummy, arr, starts, n_grp, total_blocks, shm, s);
 }
 
-template void launch_csr_tiled<float>(const CsrMultiArgs<float>&, int, hipStream_t, bool);
-template void launch_csr_tiled<double>(const CsrMultiArgs<double>&, int, hipStream_t, bool);
-template void launch_csr_tiled_batched<float>(const CsrMultiArgs<float>*, const int*, int, int, int, hipStream_t,
+template void launch_csr_tiled<float>(const CsrMultiArgs<float>&, hipStream_t, bool);
+template void launch_csr_tiled<double>(const CsrMultiArgs<double>&, hipStream_t, bool);
+template void launch_csr_tiled_batched<float>(const CsrMultiArgs<float>*, const int*, int, int, size_t, hipStream_t,
                                               bool, int);
-template void launch_csr_tiled_batched<double>(const CsrMultiArgs<double>*, const int*, int, int, int, hipStream_t,
+template void launch_csr_tiled_batched<double>(const CsrMultiArgs<double>*, const int*, int, int, size_t, hipStream_t,
                                                bool, int);
+template void prepare_csr_tiled<float>(int, size_t);
+template void prepare_csr_tiled<double>(int, size_t);
 
 template void build_csr_adjoint<float>(pat_geometry_s*, hipStream_t);
 template void build_csr_adjoint<double>(pat_geometry_s*, hipStream_t);

@@ -258,6 +258,7 @@ struct CsrMultiArgs {
   const uint16_t* lcol;
   const int4* win;
   int side, tiles_x, nx, ny, n_det, n_t;
+  int lds_stride;  // staged elements per right-hand side (the geometry's largest window)
 };
 
 // Ordered final sum of one instance's gap partials.

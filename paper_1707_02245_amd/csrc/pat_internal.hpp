@@ -81,7 +81,7 @@ struct Launch {
   DevBuf csr, csr_start;
   int n_adj = 0, n_csr = 0, csr_total = 0, csr_max_rhs = 1;
   bool csr_tiled = false;  // LDS-staged kernel for every CSR group
-  int csr_stride = 0;      // its window length per right-hand side
+  size_t csr_shm = 0;      // its dynamic LDS per workgroup
   int lanes_log2 = 6;   // shared by every instance of one launch
   int max_tile = 32;    // shared by every instance of one launch
 };
@@ -118,14 +118,22 @@ void launch_csr_spmv_batched(const CsrArgs<T>* arr, const int* starts, int n_ins
 template <class T>
 void launch_csr_spmm_batched(const CsrMultiArgs<T>* arr, const int* starts, int n_grp, int total_blocks,
                              hipStream_t s, bool wide, int max_rhs);
-// LDS-staged variant: one block per pixel tile; lds_stride = window length
-// (elements) per right-hand side, at most kCsrLdsBytes / sizeof(T) / max_rhs.
+// LDS-staged variant: one block per pixel tile, the input windows of every
+// right-hand side staged in dynamic LDS (shm bytes: max_rhs times the largest
+// lds_stride of the groups, times sizeof(T); every slot up to max_rhs is
+// read). A geometry gets tiles when one
+// right-hand side fits kCsrLdsBytes; groups of several right-hand sides may use
+// up to the workgroup LDS of the device (prepare_csr_tiled raises the kernels'
+// limit beyond 64 KB, outside any graph capture).
 constexpr int kCsrLdsBytes = 64 * 1024;
+int device_lds_per_block();
 template <class T>
-void launch_csr_tiled(const CsrMultiArgs<T>& a, int lds_stride, hipStream_t s, bool wide);
+void launch_csr_tiled(const CsrMultiArgs<T>& a, hipStream_t s, bool wide);
 template <class T>
 void launch_csr_tiled_batched(const CsrMultiArgs<T>* arr, const int* starts, int n_grp, int total_blocks,
-                              int lds_stride, hipStream_t s, bool wide, int max_rhs);
+                              size_t shm, hipStream_t s, bool wide, int max_rhs);
+template <class T>
+void prepare_csr_tiled(int max_rhs, size_t shm);
 
 // ---- launchers (pdhg.hip)
 template <class T>

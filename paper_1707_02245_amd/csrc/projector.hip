@@ -429,7 +429,8 @@ void adjoint_impl(pat_geometry g, const void* d_f, void* d_u, hipStream_t s) {
     c.ny = g->ny;
     c.n_det = g->n_det;
     c.n_t = g->n_t;
-    pat::launch_csr_tiled<T>(c, g->csr_win_max, s, false);
+    c.lds_stride = g->csr_win_max;
+    pat::launch_csr_tiled<T>(c, s, false);
     return;
   }
   if (g->adj_mode != 0) {

@@ -310,6 +310,7 @@ class Solver {
     std::vector<GapFinishArgs> gf(n);
     std::vector<int> fs(n + 1), as(1, 0), cs(1, 0), ps(n + 1);
     std::vector<pat_geometry> csr_geo;  // geometry of each CSR group
+    const int lds_max = device_lds_per_block();
     fs[0] = ps[0] = 0;
     for (int k = 0; k < n; ++k) {
       const Inst<T>& I = *inst[act[k]];
@@ -328,10 +329,18 @@ class Solver {
       fg[k].red = ptr<double>(I.red);
       fg[k].red_stride = I.red_stride;
       if (I.csr) {
-        // instances sharing a geometry share one pass over its stored A^T
+        // instances sharing a geometry share one pass over its stored A^T: up
+        // to kMaxRhs, and for the tiled kernel as many as their staged
+        // windows fit the workgroup LDS
+        int cap = kMaxRhs;
+        if (I.g->effective_adj_mode() == 2) {
+          // a kernel instance of R slots (1, 2, 4 or 8) stages R windows
+          const int fit = lds_max / (int)(sizeof(T) * I.g->csr_win_max);
+          cap = fit >= kMaxRhs ? kMaxRhs : (fit >= 4 ? 4 : (fit >= 2 ? 2 : 1));
+        }
         CsrMultiArgs<T>* grp = nullptr;
         for (auto& c : cd)
-          if (c.ptr == ptr<int64_t>(I.g->csr_ptr) && c.nrhs < kMaxRhs) grp = &c;
+          if (c.ptr == ptr<int64_t>(I.g->csr_ptr) && c.nrhs < cap) grp = &c;
         if (!grp) {
           cd.push_back(CsrMultiArgs<T>{});
           grp = &cd.back();
@@ -346,6 +355,7 @@ class Solver {
             grp->win = ptr<int4>(g->csr_win);
             grp->side = g->csr_side;
             grp->tiles_x = g->csr_tiles_x;
+            grp->lds_stride = g->csr_win_max;
           }
           grp->nx = g->nx;
           grp->ny = g->ny;
@@ -372,14 +382,18 @@ class Solver {
     }
     // CSR groups: the LDS-staged kernel when every group has tiles and the
     // windows of all its right-hand sides fit the LDS budget, else the plain one
-    int max_rhs = 1, stride = 0;
+    int max_rhs = 1, max_stride = 0;
     bool tiled = !cd.empty();
     for (size_t c = 0; c < cd.size(); ++c) {
       max_rhs = std::max(max_rhs, cd[c].nrhs);
       tiled = tiled && cd[c].lcol != nullptr;
-      if (cd[c].lcol) stride = std::max(stride, csr_geo[c]->csr_win_max);
+      max_stride = std::max(max_stride, cd[c].lds_stride);
     }
-    tiled = tiled && (int64_t)sizeof(T) * stride * max_rhs <= kCsrLdsBytes;
+    // the kernel instance for max_rhs reads every slot of every group
+    const int r_inst = max_rhs <= 2 ? max_rhs : (max_rhs <= 4 ? 4 : kMaxRhs);
+    const size_t shm = sizeof(T) * (size_t)max_stride * (size_t)r_inst;
+    tiled = tiled && shm <= (size_t)lds_max;
+    if (tiled) prepare_csr_tiled<T>(max_rhs, shm);
     for (size_t c = 0; c < cd.size(); ++c) {
       const int blocks = tiled ? csr_geo[c]->n_csr_tiles() : (int)((cd[c].n_rows + 3) / 4);
       cs.push_back(cs.back() + blocks);
@@ -406,7 +420,7 @@ class Solver {
     L.n_csr = (int)cd.size();
     L.csr_max_rhs = max_rhs;
     L.csr_tiled = tiled;
-    L.csr_stride = stride;
+    L.csr_shm = shm;
     L.csr_total = cs.back();
     L.pix_total = ps[n];
     L.lanes_log2 = lanes_log2;
@@ -435,7 +449,7 @@ class Solver {
       for (int wide = 0; wide <= (check ? 1 : 0); ++wide) {
         if (L.csr_tiled)
           launch_csr_tiled_batched<T>(ptr<CsrMultiArgs<T>>(L.csr), ptr<int>(L.csr_start), L.n_csr,
-                                      L.csr_total, L.csr_stride, s, wide != 0, L.csr_max_rhs);
+                                      L.csr_total, L.csr_shm, s, wide != 0, L.csr_max_rhs);
         else
           launch_csr_spmm_batched<T>(ptr<CsrMultiArgs<T>>(L.csr), ptr<int>(L.csr_start), L.n_csr,
                                      L.csr_total, s, wide != 0, L.csr_max_rhs);

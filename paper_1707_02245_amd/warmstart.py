@@ -214,8 +214,64 @@ def val_loss(net, x, t, batch=8):
     return tot / max(cnt, 1)
 
 
+def unet_flops(base=32, levels=4, h=256, w=256, cout=3):
+    """Multiply-adds x 2 of one forward pass of the network on an h x w image."""
+    ch = [base * 2 ** l for l in range(levels)]
+    f, cin = 0, 1
+    for l in range(levels):
+        px = (h >> l) * (w >> l)
+        f += 2 * px * 9 * (cin * ch[l] + ch[l] * ch[l])
+        cin = ch[l]
+    for l in range(levels - 2, -1, -1):
+        px = (h >> l) * (w >> l)
+        f += 2 * px * (ch[l + 1] * ch[l] + 9 * (2 * ch[l] * ch[l] + ch[l] * ch[l]))
+    return f + 2 * h * w * ch[0] * cout
+
+
+def throughput(batch=8, steps=20, size=256, base=32, log=print):
+    """Training and inference rate of the network on random data (no solver):
+    seconds per Adam step and per forward batch, and the matrix-core rate
+    counting 3 forward passes per training image."""
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn(batch * steps, size, size, device="cuda", generator=g)
+    t = torch.randn(batch * steps, 3, size, size, device="cuda", generator=g)
+    net = WarmStartNet(4, base, 3, seed=0)
+    net.train(x[:batch], t[:batch], 1, batch, 1e-4)  # warm-up (buffers)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    net.train(x, t, 1, batch, 1e-4)
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / steps
+    y = torch.empty(batch, 3, size, size, device="cuda")
+    fwd = lambda: L.check(L.load().pat_warmstart_forward(net._h, batch, size, size, C.c_void_p(x.data_ptr()),
+                                                         C.c_void_p(y.data_ptr()), _stream()))
+    fwd()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fwd()
+    torch.cuda.synchronize()
+    t_fwd = (time.perf_counter() - t0) / steps
+    f1 = unet_flops(base, 4, size, size, 3)
+    res = dict(batch=batch, size=size, step_ms=t_step * 1e3, forward_ms=t_fwd * 1e3,
+               train_tflops=3 * f1 * batch / t_step * 1e-12, forward_tflops=f1 * batch / t_fwd * 1e-12,
+               gflop_forward_per_image=f1 * 1e-9)
+    log(f"throughput: {res}")
+    return res
+
+
 def _main(argv=None):
     import phantoms
+    if argv is None:
+        argv = sys.argv[1:]
+    if argv and argv[0] == "throughput":
+        tp = argparse.ArgumentParser()
+        tp.add_argument("cmd")
+        tp.add_argument("--batch", type=int, default=8)
+        tp.add_argument("--steps", type=int, default=20)
+        b = tp.parse_args(argv)
+        throughput(b.batch, b.steps, log=lambda m: print(f"[warmstart] {m}", flush=True))
+        return 0
     ap = argparse.ArgumentParser()
     ap.add_argument("cmd", choices=["train"])
     ap.add_argument("--n-train", type=int, default=512)
