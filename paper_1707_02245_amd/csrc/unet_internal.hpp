@@ -42,6 +42,9 @@ struct GemmDesc {
   const float* bias = nullptr;
   int relu = 0;
   View mask;                    // E_ACT: zero where mask <= 0 (null p: no mask)
+  // staging in 8-element (16-byte) vectors, set by launch_gemm when the
+  // layout allows it: 0 element-wise, 1 along k, 2 along m (A) / n (B)
+  int a_vec = 0, b_vec = 0;
 };
 
 void launch_gemm(const GemmDesc& d, hipStream_t s);

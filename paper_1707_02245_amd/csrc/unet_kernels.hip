@@ -85,13 +85,124 @@ __device__ __forceinline__ uint16_t fetch_b(const GemmDesc& d, int n, int k) {
   return 0;
 }
 
+// Address of 8 consecutive operand elements (nullptr: all zero padding).
+// Along k: A(m, k..k+7) or B(n, k..k+7); along m / n: A(m..m+7, k) or
+// B(n..n+7, k). Only called when launch_gemm found the layout aligned.
+__device__ __forceinline__ const uint16_t* addr8_a(const GemmDesc& d, int m, int k) {
+  const View& v = d.a;
+  switch (d.a_mode) {
+    case A_DIRECT:
+      return v.p + (int64_t)m * v.pitch + v.off + k;
+    case A_CONV: {
+      const int tap = k / v.C, c = k - tap * v.C;
+      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+      const int x = m % v.W, t = m / v.W, y = t % v.H, b = t / v.H;
+      const int yy = y + d.a_sign * dy, xx = x + d.a_sign * dx;
+      if (yy < 0 || yy >= v.H || xx < 0 || xx >= v.W) return nullptr;
+      return v.p + ((int64_t)(b * v.H + yy) * v.W + xx) * v.pitch + v.off + c;
+    }
+    case A_G22: {
+      const int sub = k / v.C, c = k - sub * v.C;
+      const int w2 = v.W >> 1, h2 = v.H >> 1;
+      const int x = m % w2, t = m / w2, y = t % h2, b = t / h2;
+      const int yy = 2 * y + (sub >> 1), xx = 2 * x + (sub & 1);
+      return v.p + ((int64_t)(b * v.H + yy) * v.W + xx) * v.pitch + v.off + c;
+    }
+    case A_T:
+      return v.p + (int64_t)k * v.pitch + v.off + m;
+    case A_TG22: {
+      const int sub = m / v.C, c = m - sub * v.C;
+      const int w2 = v.W >> 1, h2 = v.H >> 1;
+      const int x = k % w2, t = k / w2, y = t % h2, b = t / h2;
+      const int yy = 2 * y + (sub >> 1), xx = 2 * x + (sub & 1);
+      return v.p + ((int64_t)(b * v.H + yy) * v.W + xx) * v.pitch + v.off + c;
+    }
+  }
+  return nullptr;
+}
+
+__device__ __forceinline__ const uint16_t* addr8_b(const GemmDesc& d, int n, int k) {
+  const View& v = d.b;
+  switch (d.b_mode) {
+    case B_W:
+      return d.w + (int64_t)n * d.K + k;
+    case B_IM2COL: {
+      const int tap = n / v.C, c = n - tap * v.C;
+      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+      const int x = k % v.W, t = k / v.W, y = t % v.H, b = t / v.H;
+      const int yy = y + dy, xx = x + dx;
+      if (yy < 0 || yy >= v.H || xx < 0 || xx >= v.W) return nullptr;
+      return v.p + ((int64_t)(b * v.H + yy) * v.W + xx) * v.pitch + v.off + c;
+    }
+    case B_T:
+      return v.p + (int64_t)k * v.pitch + v.off + n;
+  }
+  return nullptr;
+}
+
+// Stage a ROWS x KC chunk of one operand into LDS (row-major, leading dim LD).
+template <bool IS_A, int ROWS, int KC, int LD>
+__device__ __forceinline__ void stage(const GemmDesc& d, uint16_t* S, int row0, int k0, int ke, int t) {
+  const int vec = IS_A ? d.a_vec : d.b_vec;
+  const int nrows = IS_A ? d.M : d.N;
+  if (vec == 1) {  // 8 consecutive k of one row: one 16-byte load, one 16-byte LDS store
+    for (int e = t; e < ROWS * KC / 8; e += 256) {
+      const int r = e / (KC / 8), kv = (e % (KC / 8)) * 8;
+      const int row = row0 + r, k = k0 + kv;
+      uint4 w = make_uint4(0, 0, 0, 0);
+      if (row < nrows) {
+        if (k + 8 <= ke) {
+          const uint16_t* p = IS_A ? addr8_a(d, row, k) : addr8_b(d, row, k);
+          if (p) w = *reinterpret_cast<const uint4*>(p);
+        } else {
+          uint16_t h[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i)
+            h[i] = (k + i < ke) ? (IS_A ? fetch_a(d, row, k + i) : fetch_b(d, row, k + i)) : (uint16_t)0;
+          w = make_uint4(h[0] | (uint32_t)h[1] << 16, h[2] | (uint32_t)h[3] << 16, h[4] | (uint32_t)h[5] << 16,
+                         h[6] | (uint32_t)h[7] << 16);
+        }
+      }
+      *reinterpret_cast<uint4*>(S + r * LD + kv) = w;
+    }
+  } else if (vec == 2) {  // 8 consecutive rows at one k: one 16-byte load, 8 LDS stores
+    for (int e = t; e < ROWS / 8 * KC; e += 256) {
+      const int rv = (e / KC) * 8, kk = e % KC;
+      const int row = row0 + rv, k = k0 + kk;
+      uint16_t h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (k < ke) {
+        if (row + 8 <= nrows) {
+          const uint16_t* p = IS_A ? addr8_a(d, row, k) : addr8_b(d, row, k);
+          if (p) {
+            const uint4 w = *reinterpret_cast<const uint4*>(p);
+            h[0] = w.x & 0xFFFF; h[1] = w.x >> 16; h[2] = w.y & 0xFFFF; h[3] = w.y >> 16;
+            h[4] = w.z & 0xFFFF; h[5] = w.z >> 16; h[6] = w.w & 0xFFFF; h[7] = w.w >> 16;
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < 8; ++i)
+            h[i] = (row + i < nrows) ? (IS_A ? fetch_a(d, row + i, k) : fetch_b(d, row + i, k)) : (uint16_t)0;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) S[(rv + i) * LD + kk] = h[i];
+    }
+  } else {
+    for (int e = t; e < ROWS * KC; e += 256) {
+      const int r = e / KC, kk = e % KC;
+      S[r * LD + kk] = (k0 + kk < ke) ? (IS_A ? fetch_a(d, row0 + r, k0 + kk) : fetch_b(d, row0 + r, k0 + kk))
+                                      : (uint16_t)0;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ the GEMM
 
 template <int WM, int WN>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmDesc d) {
   constexpr int TM = 32 * WM, TN = 32 * WN, KC = 32, LD = KC + 8;
-  __shared__ uint16_t As[TM * LD];
-  __shared__ uint16_t Bs[TN * LD];
+  __shared__ __align__(16) uint16_t As[TM * LD];
+  __shared__ __align__(16) uint16_t Bs[TN * LD];
   const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
   const int kb = blockIdx.z * d.ksplit;
   const int ke = min(d.K, kb + d.ksplit);
@@ -104,14 +215,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmDesc d) {
     for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
   for (int k0 = kb; k0 < ke; k0 += KC) {
     // stage A (TM x KC) and B (TN x KC); element (row, kk) -> row * LD + kk
-    for (int e = t; e < TM * KC; e += 256) {
-      const int r = e / KC, kk = e % KC;
-      As[r * LD + kk] = (k0 + kk < ke) ? fetch_a(d, m0 + r, k0 + kk) : (uint16_t)0;
-    }
-    for (int e = t; e < TN * KC; e += 256) {
-      const int r = e / KC, kk = e % KC;
-      Bs[r * LD + kk] = (k0 + kk < ke) ? fetch_b(d, n0 + r, k0 + kk) : (uint16_t)0;
-    }
+    stage<true, TM, KC, LD>(d, As, m0, k0, ke, t);
+    stage<false, TN, KC, LD>(d, Bs, n0, k0, ke, t);
     __syncthreads();
 #pragma unroll
     for (int ks = 0; ks < KC; ks += 16) {
@@ -169,7 +274,36 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmDesc d) {
   }
 }
 
-void launch_gemm(const GemmDesc& d, hipStream_t s) {
+static bool al16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// 8-element vectors stay inside one tensor row (a tap or sub-pixel block of
+// C channels) and are 16-byte aligned when channel counts, pitches, offsets
+// and base pointers are multiples of 8 elements and split-K chunks start on
+// multiples of 8.
+static void choose_vec(GemmDesc& d) {
+  d.a_vec = d.b_vec = 0;
+  if (d.ksplit % 8 != 0) return;
+  const View& a = d.a;
+  const bool a_rows = a.p && al16(a.p) && a.pitch % 8 == 0 && a.off % 8 == 0;
+  switch (d.a_mode) {
+    case A_DIRECT: if (a_rows) d.a_vec = 1; break;
+    case A_CONV:
+    case A_G22: if (a_rows && a.C % 8 == 0) d.a_vec = 1; break;
+    case A_T: if (a_rows) d.a_vec = 2; break;
+    case A_TG22: if (a_rows && a.C % 8 == 0) d.a_vec = 2; break;
+  }
+  const View& b = d.b;
+  const bool b_rows = b.p && al16(b.p) && b.pitch % 8 == 0 && b.off % 8 == 0;
+  switch (d.b_mode) {
+    case B_W: if (d.w && al16(d.w) && d.K % 8 == 0) d.b_vec = 1; break;
+    case B_IM2COL: if (b_rows && b.C % 8 == 0) d.b_vec = 2; break;
+    case B_T: if (b_rows) d.b_vec = 2; break;
+  }
+}
+
+void launch_gemm(const GemmDesc& d_in, hipStream_t s) {
+  GemmDesc d = d_in;
+  choose_vec(d);
   const int nsplit = (d.K + d.ksplit - 1) / d.ksplit;
   if (d.N <= 32) {
     dim3 grid((d.M + 127) / 128, (d.N + 31) / 32, nsplit);
@@ -377,25 +511,28 @@ __global__ __launch_bounds__(256) void colsum_kernel(View g, float* __restrict__
   }
 }
 
-// out[c] = sum over blocks of part[block][c] (fixed order)
+// out[c] = sum over blocks of part[block][c]: one workgroup per column,
+// threads stride the blocks, then a fixed reduction tree (deterministic)
 __global__ __launch_bounds__(256) void part_reduce_kernel(const float* __restrict__ part, int nblk,
                                                           int C, int ld, float* __restrict__ out) {
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < C; c += gridDim.x * blockDim.x) {
-    float s = 0.f;
-    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * ld + c];
-    out[c] = s;
-  }
+  const int c = blockIdx.x;
+  if (c >= C) return;
+  float s = 0.f;
+  for (int b = threadIdx.x; b < nblk; b += 256) s += part[(int64_t)b * ld + c];
+  __shared__ float lds[8];
+  s = block_sum<256>(s, lds);
+  if (threadIdx.x == 0) out[c] = s;
 }
 
 void launch_colsum(const View& g, float* part, float* out, int64_t P, int rows_per_block, hipStream_t s) {
   const int nblk = (int)((P + rows_per_block - 1) / rows_per_block);
   hipLaunchKernelGGL(colsum_kernel, dim3(nblk), dim3(256), 0, s, g, part, P, rows_per_block);
-  hipLaunchKernelGGL(part_reduce_kernel, dim3((g.C + 255) / 256), dim3(256), 0, s, part, nblk, g.C, g.C, out);
+  hipLaunchKernelGGL(part_reduce_kernel, dim3(g.C), dim3(256), 0, s, part, nblk, g.C, g.C, out);
   PAT_HIP(hipGetLastError());
 }
 
 void launch_part_reduce(const float* part, int nblk, int C, int ld, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(part_reduce_kernel, dim3((C + 255) / 256), dim3(256), 0, s, part, nblk, C, ld, out);
+  hipLaunchKernelGGL(part_reduce_kernel, dim3(C), dim3(256), 0, s, part, nblk, C, ld, out);
   PAT_HIP(hipGetLastError());
 }
 
