@@ -252,7 +252,8 @@ class Solver {
     I.csr = g->adj_mode != 0;
     if (I.csr) g->ensure_csr(s);
     I.atq_part.alloc(sizeof(T) * (I.csr ? 1 : gd.n_groups) * N);
-    if (I.csr) I.atq64.alloc(sizeof(double) * N);
+    // FP64-accumulated A^T q for the gap: only FP32 needs a separate pass
+    if (I.csr && sizeof(T) == 4) I.atq64.alloc(sizeof(double) * N);
     I.n_fwd = fwd_grid(g->n_det, g->n_t, lanes_log2);
     I.n_pix = pix_blocks(N);
     I.n_adj = I.csr ? 0 : gd.tiles_x * gd.tiles_y * gd.n_groups;
@@ -446,7 +447,8 @@ class Solver {
     if (L.n_adj > 0) launch_adjoint_batched<T>(L, s);
     if (L.n_csr > 0) {
       // check iterations: A^T q once more with FP64 accumulation for the gap
-      for (int wide = 0; wide <= (check ? 1 : 0); ++wide) {
+      // (FP32 only; the FP64 pass already accumulates in FP64)
+      for (int wide = 0; wide <= (check && sizeof(T) == 4 ? 1 : 0); ++wide) {
         if (L.csr_tiled)
           launch_csr_tiled_batched<T>(ptr<CsrMultiArgs<T>>(L.csr), ptr<int>(L.csr_start), L.n_csr,
                                       L.csr_total, L.csr_shm, s, wide != 0, L.csr_max_rhs);

@@ -198,9 +198,11 @@ __device__ __forceinline__ void stage(const GemmDesc& d, uint16_t* S, int row0, 
 
 // ------------------------------------------------------------------ the GEMM
 
-template <int WM, int WN>
+// WM x WN waves, each computing FM x FN 16x16 fragments: a TM x TN tile with
+// TM = 16 WM FM, TN = 16 WN FN.
+template <int WM, int WN, int FM, int FN>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmDesc d) {
-  constexpr int TM = 32 * WM, TN = 32 * WN, KC = 32, LD = KC + 8;
+  constexpr int TM = 16 * WM * FM, TN = 16 * WN * FN, KC = 32, LD = KC + 8;
   __shared__ __align__(16) uint16_t As[TM * LD];
   __shared__ __align__(16) uint16_t Bs[TN * LD];
   const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
@@ -208,11 +210,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmDesc d) {
   const int ke = min(d.K, kb + d.ksplit);
   const int t = threadIdx.x, wave = t / 64, lane = t % 64;
   const int wm = wave / WN, wn = wave % WN;
-  v4f acc[2][2];
+  v4f acc[FM][FN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < FN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
   for (int k0 = kb; k0 < ke; k0 += KC) {
     // stage A (TM x KC) and B (TN x KC); element (row, kk) -> row * LD + kk
     stage<true, TM, KC, LD>(d, As, m0, k0, ke, t);
@@ -220,34 +222,36 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmDesc d) {
     __syncthreads();
 #pragma unroll
     for (int ks = 0; ks < KC; ks += 16) {
-      v4s a[2], b[2];
+      v4s a[FM], b[FN];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const uint16_t* pa = As + (wm * 32 + i * 16 + lane % 16) * LD + ks + 4 * (lane / 16);
-        const uint16_t* pb = Bs + (wn * 32 + i * 16 + lane % 16) * LD + ks + 4 * (lane / 16);
+      for (int i = 0; i < FM; ++i) {
+        const uint16_t* pa = As + (wm * 16 * FM + i * 16 + lane % 16) * LD + ks + 4 * (lane / 16);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          a[i][r] = (short)pa[r];
-          b[i][r] = (short)pb[r];
-        }
+        for (int r = 0; r < 4; ++r) a[i][r] = (short)pa[r];
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < FN; ++j) {
+        const uint16_t* pb = Bs + (wn * 16 * FN + j * 16 + lane % 16) * LD + ks + 4 * (lane / 16);
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int r = 0; r < 4; ++r) b[j][r] = (short)pb[r];
+      }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
   // epilogue
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < FM; ++i) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int n = n0 + wn * 32 + j * 16 + lane % 16;
+    for (int j = 0; j < FN; ++j) {
+      const int n = n0 + wn * 16 * FN + j * 16 + lane % 16;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm * 32 + i * 16 + 4 * (lane / 16) + r;
+        const int m = m0 + wm * 16 * FM + i * 16 + 4 * (lane / 16) + r;
         if (m >= d.M || n >= d.N) continue;
         float v = acc[i][j][r];
         if (d.out_mode == E_SPLIT) {
@@ -305,12 +309,20 @@ void launch_gemm(const GemmDesc& d_in, hipStream_t s) {
   GemmDesc d = d_in;
   choose_vec(d);
   const int nsplit = (d.K + d.ksplit - 1) / d.ksplit;
+  // the largest tile that still gives every CU a few workgroups
+  auto blocks = [&](int tm, int tn) { return (int64_t)((d.M + tm - 1) / tm) * ((d.N + tn - 1) / tn) * nsplit; };
   if (d.N <= 32) {
     dim3 grid((d.M + 127) / 128, (d.N + 31) / 32, nsplit);
-    hipLaunchKernelGGL((gemm_kernel<4, 1>), grid, dim3(256), 0, s, d);
+    hipLaunchKernelGGL((gemm_kernel<4, 1, 2, 2>), grid, dim3(256), 0, s, d);
+  } else if (d.N >= 128 && blocks(128, 128) >= 1024) {
+    dim3 grid((d.M + 127) / 128, (d.N + 127) / 128, nsplit);
+    hipLaunchKernelGGL((gemm_kernel<2, 2, 4, 4>), grid, dim3(256), 0, s, d);
+  } else if (blocks(128, 64) >= 1024) {
+    dim3 grid((d.M + 127) / 128, (d.N + 63) / 64, nsplit);
+    hipLaunchKernelGGL((gemm_kernel<2, 2, 4, 2>), grid, dim3(256), 0, s, d);
   } else {
     dim3 grid((d.M + 63) / 64, (d.N + 63) / 64, nsplit);
-    hipLaunchKernelGGL((gemm_kernel<2, 2>), grid, dim3(256), 0, s, d);
+    hipLaunchKernelGGL((gemm_kernel<2, 2, 2, 2>), grid, dim3(256), 0, s, d);
   }
   PAT_HIP(hipGetLastError());
 }
