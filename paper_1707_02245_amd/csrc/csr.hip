@@ -412,9 +412,16 @@ void launch_csr_spmv_batched(const CsrArgs<T>* arr, const int* starts, int n_ins
 // One block per pixel tile (4 waves): stage the tile's input windows of every
 // right-hand side in LDS, then one wave per row as in the plain kernel with
 // the gathers served by LDS. Rows outside the image (ragged tiles) are skipped.
+// Several right-hand sides make the staged windows large (one workgroup per
+// CU), so their workgroups carry 16 waves instead of 4 to keep enough loads in
+// flight; the waves of a workgroup share one copy of the windows.
+template <int R> constexpr int tiled_threads() { return R == 1 ? 256 : 1024; }
+
 template <class T, bool WIDE, int R>
-__global__ __launch_bounds__(256) void csr_tiled_kernel(CsrMultiArgs<T> a0, const CsrMultiArgs<T>* __restrict__ arr,
-                                                        const int* __restrict__ starts, int n_grp) {
+__global__ __launch_bounds__(tiled_threads<R>()) void csr_tiled_kernel(CsrMultiArgs<T> a0,
+                                                                       const CsrMultiArgs<T>* __restrict__ arr,
+                                                                       const int* __restrict__ starts, int n_grp) {
+  constexpr int NT = tiled_threads<R>(), NW = NT / 64;
   extern __shared__ char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
   int blk = blockIdx.x;
@@ -435,7 +442,7 @@ __global__ __launch_bounds__(256) void csr_tiled_kernel(CsrMultiArgs<T> a0, cons
   const int tx = blk % a.tiles_x, ty = blk / a.tiles_x;
   const int n_det = a.n_det, n_t = a.n_t, nx = a.nx, ny = a.ny;
   const int4* __restrict__ win = a.win + (int64_t)blk * n_det;
-  for (int d = threadIdx.x; d < n_det; d += 256) {
+  for (int d = threadIdx.x; d < n_det; d += NT) {
     const int4 w = win[d];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -448,12 +455,12 @@ __global__ __launch_bounds__(256) void csr_tiled_kernel(CsrMultiArgs<T> a0, cons
   }
   __syncthreads();
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int per_wave = side * side / 4;
+  const int rows = side * side, per_wave = (rows + NW - 1) / NW;
   using Acc = typename std::conditional<WIDE, double, T>::type;
   const gptr<const int64_t> rowp = as_global(a.ptr);
   const gptr<const uint16_t> lcol = as_global(a.lcol);
   const gptr<const T> val = as_global(a.val);
-  for (int rr = wave * per_wave; rr < (wave + 1) * per_wave; ++rr) {
+  for (int rr = wave * per_wave; rr < min(rows, (wave + 1) * per_wave); ++rr) {
     const int i = tx * side + rr % side, j = ty * side + rr / side;
     if (i >= nx || j >= ny) continue;  // whole wave
     const int64_t pix = (int64_t)j * nx + i;
@@ -500,7 +507,8 @@ __global__ __launch_bounds__(256) void csr_tiled_kernel(CsrMultiArgs<T> a0, cons
 template <class T, bool WIDE, int R>
 static void tiled_launch(size_t shm, const CsrMultiArgs<T>& a0, const CsrMultiArgs<T>* arr, const int* starts,
                          int n_grp, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL((csr_tiled_kernel<T, WIDE, R>), dim3(blocks), dim3(256), shm, s, a0, arr, starts, n_grp);
+  hipLaunchKernelGGL((csr_tiled_kernel<T, WIDE, R>), dim3(blocks), dim3(tiled_threads<R>()), shm, s, a0, arr, starts,
+                     n_grp);
 }
 
 template <class T, bool WIDE>
