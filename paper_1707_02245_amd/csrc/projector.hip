@@ -109,15 +109,20 @@ __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T
     const gptr<const T> up = as_global(a.upad);
     const int P = g.pitch;
     const int nx = g.nx, ny = g.ny;
-    // weighted 2x2 gather of one arc sample (zero outside the grid)
-    auto tap = [&](int m) -> T {
-      const Sample s = arc_sample(p, rr.x, table_cs<T>(g, toff + m));
-      if (s.ix < -1 || s.ix >= nx || s.iy < -1 || s.iy >= ny) return T(0);
+    // weighted 2x2 gather of one arc sample (zero outside the grid). Branch
+    // free: a sample outside the padded grid reads the padded corner cell and
+    // its value is discarded, so the loads of both samples in flight issue
+    // together instead of behind per-sample branches.
+    auto tap = [&](const double2 cs) -> T {
+      const Sample s = arc_sample(p, rr.x, cs);
+      const bool in = (s.ix >= -1) & (s.ix < nx) & (s.iy >= -1) & (s.iy < ny);
+      const int o = in ? (s.iy + 1) * P + (s.ix + 1) : 0;
       const T tx = (T)s.tx, ty = (T)s.ty;
       const T w00 = (T(1) - tx) * (T(1) - ty), w10 = tx * (T(1) - ty);
       const T w01 = (T(1) - tx) * ty, w11 = tx * ty;
-      const gptr<const T> q = up + (int64_t)(s.iy + 1) * P + (s.ix + 1);
-      return w00 * q[0] + w10 * q[1] + w01 * q[P] + w11 * q[P + 1];
+      const gptr<const T> q = up + o;
+      const T v = w00 * q[0] + w10 * q[1] + w01 * q[P] + w11 * q[P + 1];
+      return in ? v : T(0);
     };
     const int rng[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
 #pragma unroll
@@ -126,11 +131,12 @@ __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T
       int m = rng[2 * r] + lane;
       // two samples per lane in flight
       for (; m + LANES < m1; m += 2 * LANES) {
-        const T t0 = tap(m);
-        const T t1 = tap(m + LANES);
+        const double2 c0 = table_cs<T>(g, toff + m), c1 = table_cs<T>(g, toff + m + LANES);
+        const T t0 = tap(c0);
+        const T t1 = tap(c1);
         acc += t0 + t1;
       }
-      if (m < m1) acc += tap(m);
+      if (m < m1) acc += tap(table_cs<T>(g, toff + m));
     }
   }
   acc = group_sum<LANES>(acc);
