@@ -71,6 +71,7 @@ def parse():
     p.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     p.add_argument("--no-batched", action="store_true", help="skip the batched leg")
     p.add_argument("--no-learned", action="store_true", help="skip the learned warm-start leg")
+    p.add_argument("--no-sweep", action="store_true", help="skip the uneven-size batched sweep leg")
     p.add_argument("--learned-seeds", type=int, default=2,
                    help="held-out phantoms of the learned warm-start leg")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -145,6 +146,56 @@ def batched_leg(pat, torch, g, wl, fc, reg, pc, args, tdt, n_wl=4):
                 speedup=t_seq / t_batched, iters_batched=[i["iters"] for i in infos_b],
                 iters_sequential=iters_seq,
                 rel_gaps=[i["rel_gap"] for i in infos_b], status=st_b)
+
+
+def sweep_leg(pat, torch, args, n_groups=4, n_wl=4, iters=2000):
+    """A reduced batched sweep: n_groups phantoms of uneven sizes
+    (128..384 squared) on random detector arcs (64-256 detectors, full or half
+    circle, 2N time samples), n_wl wavelengths each (amplitude x U(0.3, 1), 5%
+    noise) sharing their geometry, every instance with its own regulariser
+    (TV, TGV or dTV, lambda log-uniform in [1e-3, 1e-1], TGV alpha0 = 2 lambda,
+    dTV eta = 0.1). Fixed work per instance (iters iterations, FP64): batched
+    against the same instances solved one by one."""
+    import phantoms
+    rng = np.random.default_rng([args.seed, 5])
+    sizes = [128, 192, 256, 384]
+    problems, shapes = [], []
+    for gi in range(n_groups):
+        n = sizes[gi % len(sizes)]
+        n_det = int(rng.integers(64, 257))
+        span = 2 * math.pi if rng.random() < 0.5 else math.pi
+        desc = phantoms.geometry_desc(n, n_det, 2 * n, arc_span=span)
+        g = pat.Geometry(dtype=torch.float64, **desc)
+        case = phantoms.make_case(("disc", "vessel", "segment")[gi % 3], n, 300 + gi, n_det, 2 * n)
+        fine = pat.Geometry(dtype=torch.float64, **dict(desc, nx=2 * n, ny=2 * n))
+        fc = fine.forward(torch.tensor(case["u_fine"], dtype=torch.float64, device="cuda")).cpu().numpy()
+        fine.close()
+        theta = torch.tensor(case["theta"], dtype=torch.float64, device="cuda")
+        for w in range(n_wl):
+            fw = rng.uniform(0.3, 1.0) * fc
+            nz = phantoms.unit_noise(np.random.default_rng([args.seed, 6, gi, w]), n_det, 2 * n)
+            fw = fw + 0.05 * np.linalg.norm(fw) / math.sqrt(fw.size) * nz
+            kind = ("tv", "tgv", "dtv")[int(rng.integers(3))]
+            lam = float(10 ** rng.uniform(-3, -1))
+            reg = pat.Reg(kind, lam, 2 * lam if kind == "tgv" else 0.0, 0.1 if kind == "dtv" else 1.0,
+                          theta if kind == "dtv" else None)
+            problems.append((g, torch.tensor(fw, dtype=torch.float64, device="cuda"), reg))
+            shapes.append(f"{n}^2/{n_det}x{2 * n}/{'full' if span > 4 else 'half'}/{kind}")
+    kw = dict(max_iter=iters, gap_tol=0.0, gap_every=args.gap_every, graph_block=args.gap_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pat.solve_batched(problems, **kw)
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for g, f, reg in problems:
+        pat.solve(g, f, reg, **kw)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    n = len(problems)
+    return dict(instances=n, iterations_each=iters, shapes=shapes, batched_s=t_batched, sequential_s=t_seq,
+                speedup=t_seq / t_batched, instance_iterations_per_s_batched=n * iters / t_batched,
+                instance_iterations_per_s_sequential=n * iters / t_seq)
 
 
 WEIGHTS = os.path.join(ROOT, "paper_1707_02245_amd", "weights", "warmstart_tv256.npy")
@@ -341,6 +392,10 @@ def main():
         log("batched leg: 4 wavelengths sharing the geometry")
         out["batched"] = batched_leg(pat, torch, g, wl, fc_np, reg, pc, args, tdt)
         log(f"batched: {out['batched']}")
+    if not args.no_sweep and args.dtype == "f64":
+        log("sweep leg: 16 instances of uneven sizes, mixed regularisers, batched vs one by one")
+        out["sweep"] = sweep_leg(pat, torch, args)
+        log(f"sweep: { {k: v for k, v in out['sweep'].items() if k != 'shapes'} }")
     if not args.no_learned:
         if args.dtype != "f64":
             log("learned leg runs in FP64 only; skipped")
