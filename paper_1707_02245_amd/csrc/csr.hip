@@ -199,7 +199,8 @@ void build_csr_tiles(pat_geometry_s* geo, size_t esz, hipStream_t s) {
     // the 16-bit offsets and one right-hand side must fit the LDS budget
     if (win_max < 1 || win_max > 65535 || (int64_t)esz * win_max > kCsrLdsBytes) continue;
     PAT_HIP(hipMemcpyAsync(win.p, h.data(), sizeof(int4) * h.size(), hipMemcpyHostToDevice, s));
-    geo->csr_lcol.alloc(sizeof(uint16_t) * geo->csr_nnz);
+    geo->csr_lcol.alloc(sizeof(uint16_t) * (geo->csr_nnz + kCsrSlack));
+    PAT_HIP(hipMemsetAsync(ptr<uint16_t>(geo->csr_lcol) + geo->csr_nnz, 0, sizeof(uint16_t) * kCsrSlack, s));
     hipLaunchKernelGGL(csr_lcol_kernel, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, s,
                        ptr<int64_t>(geo->csr_ptr), ptr<int>(geo->csr_col), ptr<int4>(win), geo->nx, geo->ny,
                        side, tx, nd, geo->n_t, ptr<uint16_t>(geo->csr_lcol));
@@ -233,7 +234,10 @@ void build_csr_adjoint(pat_geometry_s* geo, hipStream_t s) {
   PAT_CHECK_ARG(nnz < (int64_t(1) << 31), "A^T has too many non-zeros for 32-bit columns");
   geo->csr_ptr.alloc(sizeof(int64_t) * (N + 1));
   geo->csr_col.alloc(sizeof(int) * std::max<int64_t>(nnz, 1));
-  geo->csr_val.alloc(sizeof(T) * std::max<int64_t>(nnz, 1));
+  // kCsrSlack zero entries past the end: the tiled kernel's aligned loads may
+  // read (and discard) up to 255 entries beyond a row
+  geo->csr_val.alloc(sizeof(T) * (nnz + kCsrSlack));
+  PAT_HIP(hipMemsetAsync(ptr<T>(geo->csr_val) + nnz, 0, sizeof(T) * kCsrSlack, s));
   PAT_HIP(hipMemcpyAsync(geo->csr_ptr.p, h_ptr.data(), sizeof(int64_t) * (N + 1),
                          hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(csr_build_kernel<T>, dim3(blocks), dim3(256), 0, s, g, (int*)nullptr,
@@ -470,26 +474,28 @@ __global__ __launch_bounds__(tiled_threads<R>()) void csr_tiled_kernel(CsrMultiA
     for (int r = 0; r < R; ++r)
 #pragma unroll
       for (int u = 0; u < 4; ++u) acc[r][u] = Acc(0);
-    int64_t e = e0 + lane;
-    for (; e + 192 < e1; e += 256) {
+    // each load instruction covers one aligned block of 64 entries; lanes
+    // outside [e0, e1) load (slack or a neighbouring row) and discard
+    for (int64_t base = e0 & ~int64_t(63); base < e1; base += 256) {
       uint16_t c[4];
       T v[4];
+      bool ok[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) c[u] = __builtin_nontemporal_load(lcol + e + 64 * u);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = __builtin_nontemporal_load(val + e + 64 * u);
+      for (int u = 0; u < 4; ++u) {
+        const int64_t e = base + 64 * u + lane;
+        ok[u] = e >= e0 && e < e1;
+        c[u] = __builtin_nontemporal_load(lcol + e);
+        v[u] = __builtin_nontemporal_load(val + e);
+      }
       // every slot is computed (slots past nrhs read stale LDS and are not
       // stored): no per-slot branches between the LDS reads
 #pragma unroll
       for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc[r][u] += (Acc)v[u] * (Acc)lds[r * stride + c[u]];
-    }
-    for (; e < e1; e += 64) {
-      const uint16_t c = __builtin_nontemporal_load(lcol + e);
-      const T v = __builtin_nontemporal_load(val + e);
-#pragma unroll
-      for (int r = 0; r < R; ++r) acc[r][0] += (Acc)v * (Acc)lds[r * stride + c];
+        for (int u = 0; u < 4; ++u) {
+          const Acc t = (Acc)v[u] * (Acc)lds[r * stride + (ok[u] ? c[u] : 0)];
+          acc[r][u] += ok[u] ? t : Acc(0);
+        }
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {

@@ -126,6 +126,7 @@ void launch_csr_spmm_batched(const CsrMultiArgs<T>* arr, const int* starts, int 
 // up to the workgroup LDS of the device (prepare_csr_tiled raises the kernels'
 // limit beyond 64 KB, outside any graph capture).
 constexpr int kCsrLdsBytes = 64 * 1024;
+constexpr int64_t kCsrSlack = 256;  // zero entries after the values and window offsets
 int device_lds_per_block();
 template <class T>
 void launch_csr_tiled(const CsrMultiArgs<T>& a, hipStream_t s, bool wide);
