@@ -464,11 +464,23 @@ __global__ __launch_bounds__(tiled_threads<R>()) void csr_tiled_kernel(CsrMultiA
   const gptr<const int64_t> rowp = as_global(a.ptr);
   const gptr<const uint16_t> lcol = as_global(a.lcol);
   const gptr<const T> val = as_global(a.val);
-  for (int rr = wave * per_wave; rr < min(rows, (wave + 1) * per_wave); ++rr) {
+  // the row offsets of the wave's rows (one row per lane) load together
+  // instead of once per row on the row's critical path
+  const int rr0 = wave * per_wave, rr1 = min(rows, rr0 + per_wave);
+  int64_t my_e0 = 0, my_e1 = 0;
+  if (rr0 + lane < rr1) {
+    const int i = tx * side + (rr0 + lane) % side, j = ty * side + (rr0 + lane) / side;
+    if (i < nx && j < ny) {
+      const int64_t pix = (int64_t)j * nx + i;
+      my_e0 = rowp[pix];
+      my_e1 = rowp[pix + 1];
+    }
+  }
+  for (int rr = rr0; rr < rr1; ++rr) {
     const int i = tx * side + rr % side, j = ty * side + rr / side;
     if (i >= nx || j >= ny) continue;  // whole wave
     const int64_t pix = (int64_t)j * nx + i;
-    const int64_t e0 = rowp[pix], e1 = rowp[pix + 1];
+    const int64_t e0 = __shfl(my_e0, rr - rr0, 64), e1 = __shfl(my_e1, rr - rr0, 64);
     Acc acc[R][4];
 #pragma unroll
     for (int r = 0; r < R; ++r)
