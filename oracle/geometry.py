@@ -10,10 +10,16 @@ the circular *mean* over equispaced arc samples with bilinear interpolation:
     A[(d,k), j] = (1/M_k) * sum_m  hat((X_dkm - x_j)/h) * hat((Y_dkm - y_j)/h)
 
     (X, Y)_dkm = p_d + r_k (cos phi_km, sin phi_km),  phi_km = 2 pi (m + 1/2) / M_k
-    r_k = c (t0 + k dt),  M_k = max(1, ceil(2 pi r_k s / h)),  hat(t) = max(0, 1 - |t|)
+    r_k = c (t0 + k dt),  M_k = max(1, 4 ceil(2 pi r_k s / (4 h))),  hat(t) = max(0, 1 - |t|)
 
 with pixel centres x_j on a cell-centred grid of pitch h and zero outside it.
 Bins are ordered b = d * n_t + k, pixels j = iy * nx + ix (row = y).
+
+The paper leaves the number of samples per circle open. M_k is the arc length
+in samples rounded up to a multiple of four, so every circle's sample set is
+unchanged by a quarter turn about its centre; a square grid centred in a ring
+of 4m evenly spaced detectors then gives an operator that commutes with the
+quarter turn (rotating the image shifts the data by m detectors).
 """
 from __future__ import annotations
 
@@ -57,8 +63,8 @@ class Geometry:
         return self.nx * self.ny
 
     def n_samples(self) -> np.ndarray:
-        """M_k = max(1, ceil(2 pi r_k s / h)) for every radius."""
-        m = np.ceil(2.0 * math.pi * self.radii * self.samples_per_pixel / self.h)
+        """M_k = max(1, 4 ceil(2 pi r_k s / (4 h))) for every radius."""
+        m = 4.0 * np.ceil(2.0 * math.pi * self.radii * self.samples_per_pixel / (4.0 * self.h))
         return np.maximum(1, m).astype(np.int64)
 
     def pixel_x(self) -> np.ndarray:

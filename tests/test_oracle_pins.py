@@ -136,11 +136,11 @@ def test_arc_detector_positions():
 
 
 def test_arc_sample_count_and_phase():
-    """M_k = max(1, ceil(2 pi r_k s / h)); a single sample sits at angle pi."""
+    """M_k is 2 pi r_k / h rounded up to a multiple of 4 (h = 1/8, r_k = k/20:
+    2.51, 5.03, 7.54, 10.05 samples of arc length give 4, 8, 8, 12); r_0 = 0
+    is a single sample."""
     g = _geom(16, 1, 5, det_xy=np.array([[0.0, 0.0]]), dt=0.05)
-    h = 2.0 / 16
-    want = [1] + [math.ceil(2 * math.pi * r / h) for r in g.radii[1:]]
-    assert list(g.n_samples()) == want
+    assert list(g.n_samples()) == [1, 4, 8, 8, 12]
     # r_0 = 0: one sample at the detector itself, which is a pixel corner here,
     # so the four surrounding pixels share weight 1/4 each
     row = G.forward_rows(g, np.array([0])).toarray().reshape(16, 16)
@@ -149,18 +149,62 @@ def test_arc_sample_count_and_phase():
 
 def test_arc_sample_phase_by_hand():
     """A detector on the centre of pixel (i, j) = (5, 9) and r = 0.3 h gives
-    M = ceil(2 pi 0.3) = 2 samples at phi = pi/2 and 3 pi/2, i.e. straight up
-    and down: weight 0.7 stays on the pixel and 0.15 goes to each vertical
-    neighbour (worked by hand from the hat functions)."""
+    M = 4 samples at phi = pi/4 + k pi/2, i.e. at offsets (+-a, +-a) pixels with
+    a = 0.3 / sqrt(2). Worked by hand from the hat functions, averaged over
+    the four samples: the pixel keeps (1 - a)^2, each of its four edge
+    neighbours gets a (1 - a) / 2 and each diagonal neighbour a^2 / 4 =
+    0.01125."""
     n, h = 16, 2.0 / 16
     x = -1.0 + 5.5 * h
     y = -1.0 + 9.5 * h
     g = _geom(n, 1, 2, det_xy=np.array([[x, y]]), dt=0.3 * h)
-    assert list(g.n_samples()) == [1, 2]
+    assert list(g.n_samples()) == [1, 4]
     row = G.forward_rows(g, np.array([1])).toarray().reshape(n, n)
+    a = 0.3 / math.sqrt(2.0)
     want = np.zeros((n, n))
-    want[9, 5], want[10, 5], want[8, 5] = 0.7, 0.15, 0.15
+    want[9, 5] = (1 - a) ** 2
+    want[8, 5] = want[10, 5] = want[9, 4] = want[9, 6] = a * (1 - a) / 2
+    want[8, 4] = want[8, 6] = want[10, 4] = want[10, 6] = 0.01125
     assert np.allclose(row, want, atol=1e-14)
+
+
+def _quarter_turn(u):
+    """Image rotated by +90 degrees about the grid centre: pixel (col i, row j)
+    moves to (col n-1-j, row i)."""
+    n = u.shape[0]
+    out = np.empty_like(u)
+    j, i = np.mgrid[0:n, 0:n]
+    out[i, n - 1 - j] = u[j, i]
+    return out
+
+
+@pytest.mark.parametrize("n,n_det,n_t", [(24, 8, 40), (17, 12, 33)])
+def test_quarter_turn_equivariance(n, n_det, n_t):
+    """Detectors evenly spaced on a closed circle about the grid centre, n_det
+    a multiple of 4: turning the image by 90 degrees about the centre moves
+    the data of detector d to detector d + n_det/4 (the samples of every
+    circle turn into samples of the same circle because M_k is a multiple of
+    four). With the arc length rounded up to any integer instead, the
+    sample sets no longer turn into each other and the identity fails."""
+    g = _geom(n, n_det, n_t)
+    A = G.forward_matrix(g)
+    u = np.random.default_rng(8).standard_normal((n, n))
+    f = (A @ u.ravel()).reshape(n_det, n_t)
+    fr = (A @ _quarter_turn(u).ravel()).reshape(n_det, n_t)
+    assert np.abs(fr - np.roll(f, n_det // 4, axis=0)).max() <= 1e-13 * np.abs(f).max()
+    # control: the same identity under M_k = ceil(2 pi r_k s / h)
+    plain = np.maximum(1, np.ceil(2 * math.pi * g.radii * g.samples_per_pixel / g.h)).astype(np.int64)
+    assert np.any(plain % 4 != 0)
+    orig = G.Geometry.n_samples
+    try:
+        G.Geometry.n_samples = lambda self: np.maximum(
+            1, np.ceil(2 * math.pi * self.radii * self.samples_per_pixel / self.h)).astype(np.int64)
+        A2 = G.forward_matrix(g)
+    finally:
+        G.Geometry.n_samples = orig
+    f2 = (A2 @ u.ravel()).reshape(n_det, n_t)
+    fr2 = (A2 @ _quarter_turn(u).ravel()).reshape(n_det, n_t)
+    assert np.abs(fr2 - np.roll(f2, n_det // 4, axis=0)).max() > 1e-4 * np.abs(f2).max()
 
 
 # ---------------------------------------------------------------- regulariser operators
