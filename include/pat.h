@@ -64,8 +64,10 @@ typedef struct pat_precond_s* pat_precond_h;
  *
  * Time sample k measures the mean of the image over the circle of radius
  * r_k = c (t0 + k dt) about the detector, sampled at M_k = max(1,
- * ceil(2 pi r_k samples_per_pixel / h)) points at angles 2 pi (m + 1/2) / M_k,
- * each read by bilinear interpolation with zero outside the grid:
+ * 4 ceil(2 pi r_k samples_per_pixel / (4 h))) points (the arc length in
+ * samples rounded up to a multiple of four, so each circle's samples are
+ * invariant under quarter turns) at angles 2 pi (m + 1/2) / M_k, each read by
+ * bilinear interpolation with zero outside the grid:
  *
  *   A[(d,k), j] = (1/M_k) sum_m hat((X_dkm - x_j)/h) hat((Y_dkm - y_j)/h),
  *   hat(t) = max(0, 1 - |t|).
@@ -96,14 +98,25 @@ typedef struct {
                            * LDS-staged input windows (in effect) */
   int64_t csr_nnz;        /* non-zeros of the stored A^T (-1: not built) */
   int32_t csr_tile_side;  /* pixel tile side of mode 2 (8 or 4; 0: none) */
-  int32_t csr_win_max;    /* largest staged window of a tile (elements) */
+  int32_t csr_win_max;    /* largest staged window of a tile, per quarter-turn
+                           * slot (elements) */
+  int32_t csr_rot;        /* 4: the stored A^T holds the rows of the first
+                           * n_det/4 detectors only and the others follow by
+                           * quarter turns; 1: all detectors stored */
+  int32_t sym_rot;        /* 4: the geometry is quarter-turn symmetric (nx ==
+                           * ny, n_det a multiple of 4, detector d + n_det/4 at
+                           * the quarter turn of detector d about the grid
+                           * centre, to 64 ulps); 1: not */
+  int32_t csr_waves;      /* waves per workgroup of mode 2 (4, 8 or 16) */
+  int32_t csr_lanes;      /* lanes per matrix row in mode 2 (16 or 64) */
 } pat_geometry_info;
 
 /* Build the geometry tables on the device (FP64 host computation, rounded to
  * the element type) and the stored transpose A^T (CSR, rows = pixels, columns
  * sorted bins; Sec. 3.3.1 computes the matrix once). Synchronous with respect
- * to `stream` on return. Memory: about (4 + element size) bytes per non-zero,
- * roughly 3.7 non-zeros per (pixel, detector) pair. */
+ * to `stream` on return. Memory: about (6 + element size) bytes per non-zero,
+ * roughly 3.7 non-zeros per (pixel, detector) pair, over a quarter of the
+ * detectors on quarter-turn symmetric geometries. */
 pat_status pat_geometry_create(const pat_geometry_desc* desc, pat_dtype dtype,
                                void* stream, pat_geometry* out);
 pat_status pat_geometry_destroy(pat_geometry g);
@@ -124,6 +137,21 @@ pat_status pat_geometry_set_launch(pat_geometry g, int32_t fwd_lanes_log2,
  * products); results agree to rounding order. Invalid mode:
  * PAT_ERR_INVALID_ARG. */
 pat_status pat_geometry_set_adjoint(pat_geometry g, int32_t mode, void* stream);
+
+/* Workgroup shape of adjoint mode 2 (autotuner hook): waves per workgroup
+ * (4, 8 or 16) and lanes per matrix row (16 or 64). Any valid pair gives the
+ * same result up to summation order. Invalid values: PAT_ERR_INVALID_ARG. */
+pat_status pat_geometry_set_tiled_launch(pat_geometry g, int32_t waves, int32_t row_lanes);
+
+/* Whether the stored A^T may use the quarter-turn symmetry (default 1). On a
+ * symmetric geometry (info.sym_rot == 4) the CSR then holds the rows of the
+ * first n_det/4 detectors only, a quarter of the non-zeros, and modes 1 and 2
+ * apply it to the four quarters of the data with the output turned by 0..3
+ * quarter turns (w(d + n_det/4, k, R p) = w(d, k, p) for the quarter turn R
+ * of the pixel grid). The result equals the full matrix's to rounding of the
+ * sample positions. Rebuilds the CSR (synchronous on `stream`) when the choice
+ * changes. Invalid handle: PAT_ERR_INVALID_ARG. */
+pat_status pat_geometry_set_symmetry(pat_geometry g, int32_t enable, void* stream);
 
 /* Autotuner of the projector launch parameters. Times, with HIP events over
  * `reps` stand-alone applies on `stream`, the forward with 16/32/64 lanes per
@@ -148,6 +176,19 @@ pat_status pat_forward(pat_geometry g, const void* d_u, void* d_f, void* stream)
  * transposed matrix, not a separately discretised adjoint). Deterministic.
  * d_f: device [n_det][n_t]; d_u: device [ny][nx]. */
 pat_status pat_adjoint(pat_geometry g, const void* d_f, void* d_u, void* stream);
+
+/* f = A u from a zero-bordered copy of the image, the form the solvers keep
+ * (no padding pass). d_upad: device [ny + 2][nx + 2] with u at rows 1..ny,
+ * columns 1..nx and zeros on the border (a non-zero border is read as image
+ * and gives a different result); d_f: device [n_det][n_t]. */
+pat_status pat_forward_padded(pat_geometry g, const void* d_upad, void* d_f, void* stream);
+
+/* A^T f as the stored matrix computes it before any summation: in modes 1
+ * and 2, info.csr_rot partial images (one per quarter turn) whose sum in
+ * order 0, 1, ... is pat_adjoint's result; the solvers fold that sum into
+ * their primal update. d_parts: device [csr_rot][ny][nx]. Mode 0 (matrix-free
+ * scatter): PAT_ERR_UNSUPPORTED. */
+pat_status pat_adjoint_partials(pat_geometry g, const void* d_f, void* d_parts, void* stream);
 
 /* Regulariser (Sec. 2.1, 2.2; Sec. 3.1 eqs. PD_TV, PD_TGV).
  *  TV      : lambda ||grad u||_{2,1}

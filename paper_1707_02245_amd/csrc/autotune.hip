@@ -1,11 +1,14 @@
 // Launch-parameter autotuner of the projector kernels, with an on-disk cache.
 //
 // Candidates: forward lanes per bin (16, 32, 64) and the adjoint path (stored
-// CSR, plain or with LDS-staged input windows, or the matrix-free tile
-// scatter with 16/32/64-pixel tiles and a few detector-group sizes). Each candidate is timed with HIP events over `reps`
+// CSR, plain or with LDS-staged input windows in workgroups of 4, 8 or 16 waves
+// and 16 or 64 lanes per row,
+// or the matrix-free tile scatter with 16/32/64-pixel tiles and a few
+// detector-group sizes). Each candidate is timed with HIP events over `reps`
 // stand-alone applies on the caller's stream; the fastest of each kind is
 // kept. Results are cached per (device architecture, geometry shape, element
-// type) in a plain text file: one line per key, "key lanes adj_mode tile group".
+// type, quarter-turn use) in a plain text file: one line per key,
+// "key lanes adj_mode tile group waves row_lanes t_forward t_adjoint".
 
 #include <algorithm>
 #include <cstdio>
@@ -30,9 +33,10 @@ std::string cache_key(const pat_geometry_s* g) {
   const size_t colon = arch.find(':');
   if (colon != std::string::npos) arch = arch.substr(0, colon);
   char buf[512];
-  std::snprintf(buf, sizeof(buf), "%s|nx=%d|ny=%d|ndet=%d|nt=%d|dt=%d|span=%.6f|r=%.6f|spp=%.4f|t=%.6g",
+  const int rot = (g->sym_enabled && g->sym_rot == 4) ? 4 : 1;
+  std::snprintf(buf, sizeof(buf), "v4|%s|nx=%d|ny=%d|ndet=%d|nt=%d|dt=%d|span=%.6f|r=%.6f|spp=%.4f|t=%.6g|rot=%d",
                 arch.c_str(), g->nx, g->ny, g->n_det, g->n_t, g->dtype, g->desc.arc_span,
-                g->desc.det_radius, g->desc.samples_per_pixel, g->desc.dt * g->desc.c / g->h);
+                g->desc.det_radius, g->desc.samples_per_pixel, g->desc.dt * g->desc.c / g->h, rot);
   return buf;
 }
 
@@ -97,11 +101,17 @@ void tune(pat_geometry_s* g, int reps, hipStream_t s, pat_autotune_result* res) 
   int best_mode = 1, best_tile = g->tile, best_group = g->det_group;
   g->adj_mode = 1;
   g->ensure_csr(s);
+  int best_wg = g->csr_waves, best_lanes = g->csr_lanes;
   best_a = time_op<T>(s, reps, [&] { apply_adjoint<T>(g, ptr<T>(f), ptr<T>(out_u), s); });
   if (g->csr_side > 0) {
     g->adj_mode = 2;
-    const double t = time_op<T>(s, reps, [&] { apply_adjoint<T>(g, ptr<T>(f), ptr<T>(out_u), s); });
-    if (t < best_a) { best_a = t; best_mode = 2; }
+    for (int lanes : {16, 64})
+      for (int wg : {4, 8, 16}) {
+        g->csr_waves = wg;
+        g->csr_lanes = lanes;
+        const double t = time_op<T>(s, reps, [&] { apply_adjoint<T>(g, ptr<T>(f), ptr<T>(out_u), s); });
+        if (t < best_a) { best_a = t; best_mode = 2; best_wg = wg; best_lanes = lanes; }
+      }
   }
   const int tiles[3] = {16, 32, 64};
   for (int ti = 0; ti < 3; ++ti) {
@@ -119,6 +129,8 @@ void tune(pat_geometry_s* g, int reps, hipStream_t s, pat_autotune_result* res) 
     }
   }
   g->adj_mode = best_mode;
+  g->csr_waves = best_wg;
+  g->csr_lanes = best_lanes;
   if (best_mode == 0) {
     g->tile = best_tile;
     g->det_group = best_group;
@@ -145,16 +157,18 @@ extern "C" pat_status pat_geometry_autotune(pat_geometry g, const char* cache_pa
     bool applied = false;
     if (it != cache.end()) {
       std::istringstream in(it->second);
-      int lanes = 0, mode = -1, tile = 0, group = 0;
+      int lanes = 0, mode = -1, tile = 0, group = 0, wg = -1, rl = -1;
       double tf = 0, ta = 0;
-      if (in >> lanes >> mode >> tile >> group >> tf >> ta && lanes >= 4 && lanes <= 6 &&
+      if (in >> lanes >> mode >> tile >> group >> wg >> rl >> tf >> ta && lanes >= 4 && lanes <= 6 &&
           (mode >= 0 && mode <= 2) && (tile == 16 || tile == 32 || tile == 64) && group >= 1 &&
-          group <= g->n_det) {
+          group <= g->n_det && (wg == 4 || wg == 8 || wg == 16) && (rl == 16 || rl == 64)) {
         g->lanes_log2 = lanes;
         g->tile = tile;
         g->det_group = group;
         if (mode != 0) g->ensure_csr(s);
         g->adj_mode = mode;
+        g->csr_waves = wg;
+        g->csr_lanes = rl;
         res.forward_ms = tf;
         res.adjoint_ms = ta;
         res.from_cache = 1;
@@ -165,8 +179,8 @@ extern "C" pat_status pat_geometry_autotune(pat_geometry g, const char* cache_pa
       if (g->dtype == PAT_F64) pat::tune<double>(g, reps, s, &res);
       else pat::tune<float>(g, reps, s, &res);
       char buf[128];
-      std::snprintf(buf, sizeof(buf), "%d %d %d %d %.6f %.6f", g->lanes_log2, g->adj_mode, g->tile,
-                    g->det_group, res.forward_ms, res.adjoint_ms);
+      std::snprintf(buf, sizeof(buf), "%d %d %d %d %d %d %.6f %.6f", g->lanes_log2, g->adj_mode, g->tile,
+                    g->det_group, g->csr_waves, g->csr_lanes, res.forward_ms, res.adjoint_ms);
       cache[key] = buf;
       pat::write_cache(cache_path, cache);
     }

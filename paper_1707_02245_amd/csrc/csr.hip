@@ -18,6 +18,15 @@
 // LDS once per tile and reads the non-zeros with 16-bit window offsets, so
 // the input gathers hit LDS instead of the L2 and each non-zero streams 2
 // index bytes instead of 4.
+//
+// Quarter turns: when detector d + n_det/4 sits at the quarter turn R of
+// detector d about the centre of a square grid and every circle's sample set
+// is invariant under quarter turns (M_k a multiple of four), the weights obey
+// w(d + t n_det/4, k, R^t p) = w(d, k, p). The matrix then stores the rows of
+// the first n_det/4 detectors only; one pass over it serves four slots, slot t
+// reading the data of detectors t n_det/4 .. (t+1) n_det/4 - 1 and writing
+// its partial image at the pixels turned by t quarter turns. The four partial
+// images are summed by the consumer in a fixed order.
 
 #include <numeric>
 #include <type_traits>
@@ -98,7 +107,7 @@ __device__ __forceinline__ int wave_excl_scan(int v, int lane, int* total) {
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void csr_build_kernel(GeomDev g, int* __restrict__ row_cnt,
+__global__ __launch_bounds__(256) void csr_build_kernel(GeomDev g, int nd, int* __restrict__ row_cnt,
                                                         const int64_t* __restrict__ row_ptr,
                                                         int* __restrict__ col, T* __restrict__ val) {
   const int64_t N = (int64_t)g.nx * g.ny;
@@ -108,9 +117,9 @@ __global__ __launch_bounds__(256) void csr_build_kernel(GeomDev g, int* __restri
   const int i = (int)(pix % g.nx), j = (int)(pix / g.nx);
   int64_t pos = row_ptr ? row_ptr[pix] : 0;
   int total = 0;
-  for (int d0 = 0; d0 < g.n_det; d0 += 64) {
+  for (int d0 = 0; d0 < nd; d0 += 64) {
     const int d = d0 + lane;
-    const int c = d < g.n_det ? enum_pixel_detector<T>(g, i, j, d, nullptr, nullptr) : 0;
+    const int c = d < nd ? enum_pixel_detector<T>(g, i, j, d, nullptr, nullptr) : 0;
     int sum;
     const int excl = wave_excl_scan(c, lane, &sum);
     if (row_ptr && c > 0) enum_pixel_detector<T>(g, i, j, d, col + pos + excl, val + pos + excl);
@@ -175,7 +184,7 @@ void build_csr_tiles(pat_geometry_s* geo, size_t esz, hipStream_t s) {
   geo->csr_tiles_x = geo->csr_tiles_y = geo->csr_win_max = 0;
   const int64_t N = geo->n_pix();
   if (geo->csr_nnz <= 0) return;
-  const int nd = geo->n_det;
+  const int nd = geo->csr_det();
   for (int side : {8, 4}) {
     const int tx = (geo->nx + side - 1) / side, ty = (geo->ny + side - 1) / side;
     const int64_t nt = (int64_t)tx * ty;
@@ -196,8 +205,9 @@ void build_csr_tiles(pat_geometry_s* geo, size_t esz, hipStream_t s) {
       }
       win_max = std::max(win_max, off);
     }
-    // the 16-bit offsets and one right-hand side must fit the LDS budget
-    if (win_max < 1 || win_max > 65535 || (int64_t)esz * win_max > kCsrLdsBytes) continue;
+    // the 16-bit offsets and one right-hand side (all its quarter-turn slots)
+    // must fit the LDS budget
+    if (win_max < 1 || win_max > 65535 || (int64_t)esz * win_max * geo->csr_rot > kCsrLdsBytes) continue;
     PAT_HIP(hipMemcpyAsync(win.p, h.data(), sizeof(int4) * h.size(), hipMemcpyHostToDevice, s));
     geo->csr_lcol.alloc(sizeof(uint16_t) * (geo->csr_nnz + kCsrSlack));
     PAT_HIP(hipMemsetAsync(ptr<uint16_t>(geo->csr_lcol) + geo->csr_nnz, 0, sizeof(uint16_t) * kCsrSlack, s));
@@ -219,9 +229,11 @@ template <class T>
 void build_csr_adjoint(pat_geometry_s* geo, hipStream_t s) {
   const GeomDev g = geo->dev();
   const int64_t N = geo->n_pix();
+  geo->csr_rot = (geo->sym_enabled && geo->sym_rot == 4) ? 4 : 1;
+  const int nd = geo->csr_det();
   DevBuf cnt(sizeof(int) * N);
   const int blocks = (int)((N + 3) / 4);
-  hipLaunchKernelGGL(csr_build_kernel<T>, dim3(blocks), dim3(256), 0, s, g, ptr<int>(cnt),
+  hipLaunchKernelGGL(csr_build_kernel<T>, dim3(blocks), dim3(256), 0, s, g, nd, ptr<int>(cnt),
                      (const int64_t*)nullptr, (int*)nullptr, (T*)nullptr);
   PAT_HIP(hipGetLastError());
   std::vector<int> h_cnt(N);
@@ -231,7 +243,7 @@ void build_csr_adjoint(pat_geometry_s* geo, hipStream_t s) {
   h_ptr[0] = 0;
   for (int64_t r = 0; r < N; ++r) h_ptr[r + 1] = h_ptr[r] + h_cnt[r];
   const int64_t nnz = h_ptr[N];
-  PAT_CHECK_ARG(nnz < (int64_t(1) << 31), "A^T has too many non-zeros for 32-bit columns");
+  PAT_CHECK_ARG(nnz <= (int64_t(1) << 31) - 512, "A^T has too many non-zeros for 32-bit indices");
   geo->csr_ptr.alloc(sizeof(int64_t) * (N + 1));
   geo->csr_col.alloc(sizeof(int) * std::max<int64_t>(nnz, 1));
   // kCsrSlack zero entries past the end: the tiled kernel's aligned loads may
@@ -240,7 +252,7 @@ void build_csr_adjoint(pat_geometry_s* geo, hipStream_t s) {
   PAT_HIP(hipMemsetAsync(ptr<T>(geo->csr_val) + nnz, 0, sizeof(T) * kCsrSlack, s));
   PAT_HIP(hipMemcpyAsync(geo->csr_ptr.p, h_ptr.data(), sizeof(int64_t) * (N + 1),
                          hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(csr_build_kernel<T>, dim3(blocks), dim3(256), 0, s, g, (int*)nullptr,
+  hipLaunchKernelGGL(csr_build_kernel<T>, dim3(blocks), dim3(256), 0, s, g, nd, (int*)nullptr,
                      ptr<int64_t>(geo->csr_ptr), ptr<int>(geo->csr_col), ptr<T>(geo->csr_val));
   PAT_HIP(hipGetLastError());
   PAT_HIP(hipStreamSynchronize(s));
@@ -308,18 +320,22 @@ __global__ __launch_bounds__(256) void csr_spmv_kernel(CsrArgs<T> a0, const CsrA
 }
 
 // Multi-RHS variant: one wave per row; every (column, value) pair loaded once
-// serves all right-hand sides of the group.
+// serves all slots of the group (right-hand sides, or their quarter turns).
 template <class T, bool WIDE, int R>
-__global__ __launch_bounds__(256) void csr_spmm_kernel(const CsrMultiArgs<T>* __restrict__ arr,
+__global__ __launch_bounds__(256) void csr_spmm_kernel(CsrMultiArgs<T> a0, const CsrMultiArgs<T>* __restrict__ arr,
                                                        const int* __restrict__ starts, int n_grp) {
   int blk = blockIdx.x;
-  int lo = 0, hi = n_grp;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (starts[mid] <= blk) lo = mid; else hi = mid;
+  const CsrMultiArgs<T>* ap = &a0;
+  if (arr) {
+    int lo = 0, hi = n_grp;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (starts[mid] <= blk) lo = mid; else hi = mid;
+    }
+    ap = arr + lo;
+    blk -= starts[lo];
   }
-  const CsrMultiArgs<T>& a = arr[lo];
-  blk -= starts[lo];
+  const CsrMultiArgs<T>& a = *ap;
   const int64_t row = (int64_t)blk * 4 + threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
   if (row >= a.n_rows) return;  // whole wave
@@ -353,39 +369,55 @@ __global__ __launch_bounds__(256) void csr_spmm_kernel(const CsrMultiArgs<T>* __
     for (int r = 0; r < R; ++r)
       if (r < nr) acc[r] += (Acc)v0 * (Acc)xs[r][c0];
   }
+  const int rot = a.rot;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     if (r < nr) {
       const Acc t = group_sum<64>(acc[r]);
       if (lane == 0) {
-        if (WIDE) a.y64[r][row] = (double)t;
-        else a.y[r][row] = (T)t;
+        const int64_t out = rot <= 1 ? row : quarter_turn((int)(row % a.nx), (int)(row / a.nx), a.nx, r % rot);
+        if (WIDE) a.y64[r][out] = (double)t;
+        else a.y[r][out] = (T)t;
       }
     }
   }
 }
 
 template <class T, bool WIDE>
-static void spmm_dispatch(int max_rhs, const CsrMultiArgs<T>* arr, const int* starts, int n_grp,
-                          int blocks, hipStream_t s) {
+static void spmm_dispatch(int max_rhs, const CsrMultiArgs<T>& a0, const CsrMultiArgs<T>* arr, const int* starts,
+                          int n_grp, int blocks, hipStream_t s) {
+  PAT_CHECK_ARG(max_rhs >= 1 && max_rhs <= kMaxRhs, "bad right-hand side count");
   if (max_rhs <= 1)
-    hipLaunchKernelGGL((csr_spmm_kernel<T, WIDE, 1>), dim3(blocks), dim3(256), 0, s, arr, starts, n_grp);
+    hipLaunchKernelGGL((csr_spmm_kernel<T, WIDE, 1>), dim3(blocks), dim3(256), 0, s, a0, arr, starts, n_grp);
   else if (max_rhs <= 2)
-    hipLaunchKernelGGL((csr_spmm_kernel<T, WIDE, 2>), dim3(blocks), dim3(256), 0, s, arr, starts, n_grp);
+    hipLaunchKernelGGL((csr_spmm_kernel<T, WIDE, 2>), dim3(blocks), dim3(256), 0, s, a0, arr, starts, n_grp);
   else if (max_rhs <= 4)
-    hipLaunchKernelGGL((csr_spmm_kernel<T, WIDE, 4>), dim3(blocks), dim3(256), 0, s, arr, starts, n_grp);
+    hipLaunchKernelGGL((csr_spmm_kernel<T, WIDE, 4>), dim3(blocks), dim3(256), 0, s, a0, arr, starts, n_grp);
   else
-    hipLaunchKernelGGL((csr_spmm_kernel<T, WIDE, kMaxRhs>), dim3(blocks), dim3(256), 0, s, arr, starts, n_grp);
+    hipLaunchKernelGGL((csr_spmm_kernel<T, WIDE, kMaxRhs>), dim3(blocks), dim3(256), 0, s, a0, arr, starts, n_grp);
 }
 
 template <class T>
 void launch_csr_spmm_batched(const CsrMultiArgs<T>* arr, const int* starts, int n_grp, int total_blocks,
                              hipStream_t s, bool wide, int max_rhs) {
   if (total_blocks <= 0) return;
-  if (wide) spmm_dispatch<T, true>(max_rhs, arr, starts, n_grp, total_blocks, s);
-  else spmm_dispatch<T, false>(max_rhs, arr, starts, n_grp, total_blocks, s);
+  CsrMultiArgs<T> dummy{};
+  if (wide) spmm_dispatch<T, true>(max_rhs, dummy, arr, starts, n_grp, total_blocks, s);
+  else spmm_dispatch<T, false>(max_rhs, dummy, arr, starts, n_grp, total_blocks, s);
   PAT_HIP(hipGetLastError());
 }
+
+template <class T>
+void launch_csr_spmm(const CsrMultiArgs<T>& a, hipStream_t s, bool wide) {
+  const int blocks = (int)((a.n_rows + 3) / 4);
+  if (blocks <= 0) return;
+  if (wide) spmm_dispatch<T, true>(a.nrhs, a, nullptr, nullptr, 1, blocks, s);
+  else spmm_dispatch<T, false>(a.nrhs, a, nullptr, nullptr, 1, blocks, s);
+  PAT_HIP(hipGetLastError());
+}
+
+template void launch_csr_spmm<float>(const CsrMultiArgs<float>&, hipStream_t, bool);
+template void launch_csr_spmm<double>(const CsrMultiArgs<double>&, hipStream_t, bool);
 
 template void launch_csr_spmm_batched<float>(const CsrMultiArgs<float>*, const int*, int, int, hipStream_t, bool, int);
 template void launch_csr_spmm_batched<double>(const CsrMultiArgs<double>*, const int*, int, int, hipStream_t, bool, int);
@@ -413,19 +445,17 @@ void launch_csr_spmv_batched(const CsrArgs<T>* arr, const int* starts, int n_ins
   PAT_HIP(hipGetLastError());
 }
 
-// One block per pixel tile (4 waves): stage the tile's input windows of every
-// right-hand side in LDS, then one wave per row as in the plain kernel with
-// the gathers served by LDS. Rows outside the image (ragged tiles) are skipped.
-// Several right-hand sides make the staged windows large (one workgroup per
-// CU), so their workgroups carry 16 waves instead of 4 to keep enough loads in
-// flight; the waves of a workgroup share one copy of the windows.
-template <int R> constexpr int tiled_threads() { return R == 1 ? 256 : 1024; }
-
-template <class T, bool WIDE, int R>
-__global__ __launch_bounds__(tiled_threads<R>()) void csr_tiled_kernel(CsrMultiArgs<T> a0,
-                                                                       const CsrMultiArgs<T>* __restrict__ arr,
-                                                                       const int* __restrict__ starts, int n_grp) {
-  constexpr int NT = tiled_threads<R>(), NW = NT / 64;
+// One block per pixel tile (NT / 64 waves): stage the tile's input windows of
+// every slot in LDS, then one wave per row as in the plain kernel with the
+// gathers served by LDS. Rows outside the image (ragged tiles) are skipped.
+// Large staged windows leave room for one workgroup per CU, so those
+// workgroups carry 16 waves instead of 4 to keep enough loads in flight; the
+// waves of a workgroup share one copy of the windows.
+template <class T, bool WIDE, int R, int NT, int LPR>
+__global__ __launch_bounds__(NT) void csr_tiled_kernel(CsrMultiArgs<T> a0, const CsrMultiArgs<T>* __restrict__ arr,
+                                                       const int* __restrict__ starts, int n_grp) {
+  constexpr int NW = NT / 64;
+  constexpr int RPW = 64 / LPR;  // rows a wave works on at once
   extern __shared__ char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
   int blk = blockIdx.x;
@@ -446,98 +476,164 @@ __global__ __launch_bounds__(tiled_threads<R>()) void csr_tiled_kernel(CsrMultiA
   const int tx = blk % a.tiles_x, ty = blk / a.tiles_x;
   const int n_det = a.n_det, n_t = a.n_t, nx = a.nx, ny = a.ny;
   const int4* __restrict__ win = a.win + (int64_t)blk * n_det;
-  for (int d = threadIdx.x; d < n_det; d += NT) {
+  // staging: one thread per (slot, detector) window, four loads in flight
+  const int n_pairs = (R == 1 ? 1 : nr) * n_det;
+  for (int p = threadIdx.x; p < n_pairs; p += NT) {
+    const int r = R == 1 ? 0 : p / n_det, d = R == 1 ? p : p - r * n_det;
     const int4 w = win[d];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (R == 1 || r < nr) {
-        const gptr<const T> src = as_global(a.x[r]) + (int64_t)d * n_t + w.x;
-        T* dst = lds + r * stride + w.z;
-        for (int i = 0; i < w.y; ++i) dst[i] = src[i];
-      }
+    const gptr<const T> src = as_global(a.x[r]) + (int64_t)d * n_t + w.x;
+    T* dst = lds + r * stride + w.z;
+    int i = 0;
+    for (; i + 4 <= w.y; i += 4) {
+      const T v0 = src[i], v1 = src[i + 1], v2 = src[i + 2], v3 = src[i + 3];
+      dst[i] = v0;
+      dst[i + 1] = v1;
+      dst[i + 2] = v2;
+      dst[i + 3] = v3;
     }
+    for (; i < w.y; ++i) dst[i] = src[i];
   }
   __syncthreads();
+  // Rows: LPR lanes per row (16 or 64), so a wave works on RPW rows at once
+  // (batch b of wave w holds rows rr0 + RPW b + 0..RPW-1); with 16 lanes a
+  // row reduces over its lanes by DPP moves instead of LDS permutes. Short
+  // rows (quarter-turn storage, about 240 entries) favour 16 lanes, long rows
+  // 64. Entry indices fit 32 bits (the matrix is limited to 2^31 - 512
+  // entries).
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int grp = lane / LPR, gl = lane % LPR;
   const int rows = side * side, per_wave = (rows + NW - 1) / NW;
+  const int rr0 = wave * per_wave, rr1 = min(rows, rr0 + per_wave);
+  const int n_batch = rr1 > rr0 ? (rr1 - rr0 + RPW - 1) / RPW : 0;
   using Acc = typename std::conditional<WIDE, double, T>::type;
   const gptr<const int64_t> rowp = as_global(a.ptr);
   const gptr<const uint16_t> lcol = as_global(a.lcol);
   const gptr<const T> val = as_global(a.val);
-  // the row offsets of the wave's rows (one row per lane) load together
-  // instead of once per row on the row's critical path
-  const int rr0 = wave * per_wave, rr1 = min(rows, rr0 + per_wave);
-  int64_t my_e0 = 0, my_e1 = 0;
-  if (rr0 + lane < rr1) {
-    const int i = tx * side + (rr0 + lane) % side, j = ty * side + (rr0 + lane) / side;
-    if (i < nx && j < ny) {
-      const int64_t pix = (int64_t)j * nx + i;
-      my_e0 = rowp[pix];
-      my_e1 = rowp[pix + 1];
-    }
-  }
-  for (int rr = rr0; rr < rr1; ++rr) {
-    const int i = tx * side + rr % side, j = ty * side + rr / side;
-    if (i >= nx || j >= ny) continue;  // whole wave
-    const int64_t pix = (int64_t)j * nx + i;
-    const int64_t e0 = __shfl(my_e0, rr - rr0, 64), e1 = __shfl(my_e1, rr - rr0, 64);
-    Acc acc[R][4];
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc[r][u] = Acc(0);
-    // each load instruction covers one aligned block of 64 entries; lanes
-    // outside [e0, e1) load (slack or a neighbouring row) and discard
-    for (int64_t base = e0 & ~int64_t(63); base < e1; base += 256) {
-      uint16_t c[4];
-      T v[4];
-      bool ok[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int64_t e = base + 64 * u + lane;
-        ok[u] = e >= e0 && e < e1;
-        c[u] = __builtin_nontemporal_load(lcol + e);
-        v[u] = __builtin_nontemporal_load(val + e);
+  // row of this lane's group in batch b: [e0, e1) (empty outside the tile's
+  // rows or the image)
+  auto row_range = [&](int b, int& e0, int& e1) {
+    const int rr = rr0 + RPW * b + grp;
+    e0 = e1 = 0;
+    if (rr < rr1) {
+      const int i = tx * side + rr % side, j = ty * side + rr / side;
+      if (i < nx && j < ny) {
+        const int64_t pix = (int64_t)j * nx + i;
+        e0 = (int)rowp[pix];
+        e1 = (int)rowp[pix + 1];
       }
-      // every slot is computed (slots past nrhs read stale LDS and are not
-      // stored): no per-slot branches between the LDS reads
+    }
+  };
+  // Software pipeline: a group of four LPR-entry blocks per row (block-
+  // aligned) is loaded one step ahead: the row's next group, the row's last
+  // group again (marked stale, all lanes masked) once the row is done and
+  // other rows of the batch go on, or the next batch's first group. Every
+  // group starts at or before its row's end, so its loads stay within the
+  // 256 entries of slack after the matrix. Lanes outside [e0, e1) contribute
+  // fma(0, x, acc) = acc.
+  constexpr int NA = R >= 4 ? 2 : 4;  // accumulators per slot
+  int c[4];  // 16-bit offsets held unpacked (packing would wait on the loads)
+  T v[4];
+  auto load_group = [&](int base, int* cc, T* vv) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      cc[u] = (int)__builtin_nontemporal_load(lcol + (base + LPR * u + gl));
+      vv[u] = __builtin_nontemporal_load(val + (base + LPR * u + gl));
+    }
+  };
+  if (n_batch > 0) {
+    int e0, e1;
+    row_range(0, e0, e1);
+    int base = e0 & ~(LPR - 1);
+    load_group(base, c, v);
+    for (int b = 0; b < n_batch; ++b) {
+      const bool has_next = b + 1 < n_batch;
+      int ne0 = 0, ne1 = 0;
+      if (has_next) row_range(b + 1, ne0, ne1);
+      Acc acc[R][NA];
 #pragma unroll
       for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const Acc t = (Acc)v[u] * (Acc)lds[r * stride + (ok[u] ? c[u] : 0)];
-          acc[r][u] += ok[u] ? t : Acc(0);
-        }
-    }
+        for (int u = 0; u < NA; ++u) acc[r][u] = Acc(0);
+      bool stale = false;
+      while (true) {
+        const int nb = base + 4 * LPR;
+        const bool more = !stale && nb < e1;
+        const bool any = __any(more);
+        const int next = any ? (more ? nb : base) : (has_next ? (ne0 & ~(LPR - 1)) : base);
+        int cn[4];
+        T vn[4];
+        load_group(next, cn, vn);
+        // every slot is computed (slots past nrhs read stale LDS and are not
+        // stored): no per-slot branches between the LDS reads
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (R == 1 || r < nr) {
-        const Acc t = group_sum<64>((acc[r][0] + acc[r][1]) + (acc[r][2] + acc[r][3]));
-        if (lane == 0) {
-          if (WIDE) a.y64[r][pix] = (double)t;
-          else a.y[r][pix] = (T)t;
+        for (int u = 0; u < 4; ++u) {
+          const int e = base + LPR * u + gl;
+          const bool ok = !stale && e >= e0 && e < e1;
+          const Acc vm = ok ? (Acc)v[u] : Acc(0);
+          const int cu = ok ? c[u] : 0;
+#pragma unroll
+          for (int r = 0; r < R; ++r) acc[r][u % NA] = fma(vm, (Acc)lds[r * stride + cu], acc[r][u % NA]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          c[u] = cn[u];
+          v[u] = vn[u];
+        }
+        if (!any) break;
+        stale = !more;
+        base = next;
+      }
+      const int rr = rr0 + RPW * b + grp;
+      const int i = tx * side + rr % side, j = ty * side + rr / side;
+      const bool store = gl == 0 && rr < rr1 && i < nx && j < ny;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (R == 1 || r < nr) {
+          const Acc part = NA == 4 ? (acc[r][0] + acc[r][1]) + (acc[r][2 % NA] + acc[r][3 % NA])
+                                   : acc[r][0] + acc[r][1];
+          const Acc sum = LPR == 16 ? row16_sum(part) : group_sum<64>(part);
+          if (store) {
+            const int64_t out = (R == 1 || a.rot <= 1) ? (int64_t)j * nx + i : quarter_turn(i, j, nx, r % a.rot);
+            if (WIDE) a.y64[r][out] = (double)sum;
+            else a.y[r][out] = (T)sum;
+          }
         }
       }
+      e0 = ne0;
+      e1 = ne1;
+      base = ne0 & ~(LPR - 1);
     }
   }
+}
+
+template <class T, bool WIDE, int R, int NT>
+static void tiled_launch_nt(size_t shm, const CsrMultiArgs<T>& a0, const CsrMultiArgs<T>* arr, const int* starts,
+                            int n_grp, int blocks, hipStream_t s, int lanes) {
+  if (lanes == 64)
+    hipLaunchKernelGGL((csr_tiled_kernel<T, WIDE, R, NT, 64>), dim3(blocks), dim3(NT), shm, s, a0, arr, starts, n_grp);
+  else
+    hipLaunchKernelGGL((csr_tiled_kernel<T, WIDE, R, NT, 16>), dim3(blocks), dim3(NT), shm, s, a0, arr, starts, n_grp);
 }
 
 template <class T, bool WIDE, int R>
 static void tiled_launch(size_t shm, const CsrMultiArgs<T>& a0, const CsrMultiArgs<T>* arr, const int* starts,
-                         int n_grp, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL((csr_tiled_kernel<T, WIDE, R>), dim3(blocks), dim3(tiled_threads<R>()), shm, s, a0, arr, starts,
-                     n_grp);
+                         int n_grp, int blocks, hipStream_t s, int waves, int lanes) {
+  if (waves == 16) tiled_launch_nt<T, WIDE, R, 1024>(shm, a0, arr, starts, n_grp, blocks, s, lanes);
+  else if (waves == 8) tiled_launch_nt<T, WIDE, R, 512>(shm, a0, arr, starts, n_grp, blocks, s, lanes);
+  else tiled_launch_nt<T, WIDE, R, 256>(shm, a0, arr, starts, n_grp, blocks, s, lanes);
 }
 
 template <class T, bool WIDE>
 static void tiled_dispatch(int max_rhs, const CsrMultiArgs<T>& a0, const CsrMultiArgs<T>* arr, const int* starts,
-                           int n_grp, int blocks, size_t shm, hipStream_t s) {
+                           int n_grp, int blocks, size_t shm, hipStream_t s, int waves, int lanes) {
+  PAT_CHECK_ARG(waves == 4 || waves == 8 || waves == 16, "tiled workgroups carry 4, 8 or 16 waves");
+  PAT_CHECK_ARG(lanes == 16 || lanes == 64, "tiled rows take 16 or 64 lanes");
   PAT_CHECK_ARG(max_rhs >= 1 && max_rhs <= kMaxRhs, "bad right-hand side count");
   PAT_CHECK_ARG(shm <= (size_t)device_lds_per_block(), "staged windows exceed the LDS of a workgroup");
-  if (max_rhs <= 1) tiled_launch<T, WIDE, 1>(shm, a0, arr, starts, n_grp, blocks, s);
-  else if (max_rhs <= 2) tiled_launch<T, WIDE, 2>(shm, a0, arr, starts, n_grp, blocks, s);
-  else if (max_rhs <= 4) tiled_launch<T, WIDE, 4>(shm, a0, arr, starts, n_grp, blocks, s);
-  else tiled_launch<T, WIDE, kMaxRhs>(shm, a0, arr, starts, n_grp, blocks, s);
+  if (max_rhs <= 1) tiled_launch<T, WIDE, 1>(shm, a0, arr, starts, n_grp, blocks, s, waves, lanes);
+  else if (max_rhs <= 2) tiled_launch<T, WIDE, 2>(shm, a0, arr, starts, n_grp, blocks, s, waves, lanes);
+  else if (max_rhs <= 4) tiled_launch<T, WIDE, 4>(shm, a0, arr, starts, n_grp, blocks, s, waves, lanes);
+  else tiled_launch<T, WIDE, kMaxRhs>(shm, a0, arr, starts, n_grp, blocks, s, waves, lanes);
   PAT_HIP(hipGetLastError());
 }
 
@@ -554,10 +650,20 @@ int device_lds_per_block() {
   return cached;
 }
 
+template <class T, bool WIDE, int R, int LPR>
+static void raise_lds_l(size_t shm) {
+  PAT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&csr_tiled_kernel<T, WIDE, R, 256, LPR>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+  PAT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&csr_tiled_kernel<T, WIDE, R, 512, LPR>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+  PAT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&csr_tiled_kernel<T, WIDE, R, 1024, LPR>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+}
+
 template <class T, bool WIDE, int R>
 static void raise_lds(size_t shm) {
-  PAT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&csr_tiled_kernel<T, WIDE, R>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+  raise_lds_l<T, WIDE, R, 16>(shm);
+  raise_lds_l<T, WIDE, R, 64>(shm);
 }
 
 template <class T>
@@ -571,30 +677,32 @@ void prepare_csr_tiled(int max_rhs, size_t shm) {
 }
 
 template <class T>
-void launch_csr_tiled(const CsrMultiArgs<T>& a, hipStream_t s, bool wide) {
+void launch_csr_tiled(const CsrMultiArgs<T>& a, hipStream_t s, bool wide, int waves, int lanes) {
   const int blocks = a.tiles_x * ((a.ny + a.side - 1) / a.side);
   if (blocks <= 0) return;
-  const size_t shm = sizeof(T) * (size_t)a.lds_stride * (size_t)a.nrhs;
+  // every slot of the kernel instance is staged (1, 2, 4 or kMaxRhs)
+  const int r_inst = a.nrhs <= 2 ? a.nrhs : (a.nrhs <= 4 ? 4 : kMaxRhs);
+  const size_t shm = sizeof(T) * (size_t)a.lds_stride * (size_t)r_inst;
   prepare_csr_tiled<T>(a.nrhs, shm);
-  if (wide) tiled_dispatch<T, true>(a.nrhs, a, nullptr, nullptr, 1, blocks, shm, s);
-  else tiled_dispatch<T, false>(a.nrhs, a, nullptr, nullptr, 1, blocks, shm, s);
+  if (wide) tiled_dispatch<T, true>(a.nrhs, a, nullptr, nullptr, 1, blocks, shm, s, waves, lanes);
+  else tiled_dispatch<T, false>(a.nrhs, a, nullptr, nullptr, 1, blocks, shm, s, waves, lanes);
 }
 
 template <class T>
 void launch_csr_tiled_batched(const CsrMultiArgs<T>* arr, const int* starts, int n_grp, int total_blocks,
-                              size_t shm, hipStream_t s, bool wide, int max_rhs) {
+                              size_t shm, hipStream_t s, bool wide, int max_rhs, int waves, int lanes) {
   if (total_blocks <= 0) return;
   CsrMultiArgs<T> dummy{};
-  if (wide) tiled_dispatch<T, true>(max_rhs, dummy, arr, starts, n_grp, total_blocks, shm, s);
-  else tiled_dispatch<T, false>(max_rhs, dummy, arr, starts, n_grp, total_blocks, shm, s);
+  if (wide) tiled_dispatch<T, true>(max_rhs, dummy, arr, starts, n_grp, total_blocks, shm, s, waves, lanes);
+  else tiled_dispatch<T, false>(max_rhs, dummy, arr, starts, n_grp, total_blocks, shm, s, waves, lanes);
 }
 
-template void launch_csr_tiled<float>(const CsrMultiArgs<float>&, hipStream_t, bool);
-template void launch_csr_tiled<double>(const CsrMultiArgs<double>&, hipStream_t, bool);
+template void launch_csr_tiled<float>(const CsrMultiArgs<float>&, hipStream_t, bool, int, int);
+template void launch_csr_tiled<double>(const CsrMultiArgs<double>&, hipStream_t, bool, int, int);
 template void launch_csr_tiled_batched<float>(const CsrMultiArgs<float>*, const int*, int, int, size_t, hipStream_t,
-                                              bool, int);
+                                              bool, int, int, int);
 template void launch_csr_tiled_batched<double>(const CsrMultiArgs<double>*, const int*, int, int, size_t, hipStream_t,
-                                               bool, int);
+                                               bool, int, int, int);
 template void prepare_csr_tiled<float>(int, size_t);
 template void prepare_csr_tiled<double>(int, size_t);
 

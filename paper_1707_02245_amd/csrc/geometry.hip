@@ -7,6 +7,8 @@
 //
 //     gx = gdx_d + rho_k cos(phi_km),  gy = gdy_d + rho_k sin(phi_km),
 //     phi_km = 2 pi (m + 1/2) / M_k,   rho_k = r_k / h,
+//     M_k = max(1, 4 ceil(2 pi r_k s / (4 h)))   (a multiple of four, so each
+//     circle's samples are invariant under quarter turns),
 //
 // evaluated in FP64 from FP64 tables by every kernel that touches samples, so
 // the forward and the adjoint see bit-identical positions and weights.
@@ -156,7 +158,7 @@ void validate_geometry_desc(const pat_geometry_desc* d) {
     PAT_CHECK_ARG(d->det_radius >= 0.0, "det_radius must be >= 0");
   }
   const double r_max = d->c * (d->t0 + d->dt * (d->n_t - 1));
-  const double m_max = std::ceil(kTwoPi * r_max * d->samples_per_pixel / hx);
+  const double m_max = 4.0 * std::ceil(kTwoPi * r_max * d->samples_per_pixel / (4.0 * hx));
   PAT_CHECK_ARG(m_max < 4.0e6, "too many arc samples per circle");
 }
 
@@ -190,13 +192,34 @@ void pat_geometry_s::build_host() {
   for (int k = 0; k < n_t; ++k) {
     const double r = d.c * (d.t0 + k * d.dt);
     radius[k] = r;
-    const double m = std::ceil(kTwoPi * r * d.samples_per_pixel / h);
+    const double m = 4.0 * std::ceil(kTwoPi * r * d.samples_per_pixel / (4.0 * h));
     M[k] = std::max(1, (int)m);
     off[k] = acc;
     acc += M[k];
   }
   n_samples_per_det = acc;
   PAT_CHECK_ARG(acc < (int64_t(1) << 31), "sample table too large");
+  // Quarter-turn symmetry: in grid index units the quarter turn about the
+  // centre c = (n-1)/2 of a square grid maps (gx, gy) to (n-1-gy, gx); the
+  // ring is symmetric when detector d + n_det/4 sits there for every d (to 64
+  // ulps of the coordinates). With every M_k a multiple of four (or the single
+  // sample of r = 0, at the detector itself) the sample sets follow.
+  sym_rot = 1;
+  if (nx == ny && n_det % 4 == 0) {
+    const int q = n_det / 4;
+    bool ok = true;
+    auto gx = [&](int i) { return (det_xy[2 * i] - d.x_min) / h - 0.5; };
+    auto gy = [&](int i) { return (det_xy[2 * i + 1] - d.y_min) / h - 0.5; };
+    for (int i = 0; i < n_det && ok; ++i) {
+      const int j = (i + q) % n_det;
+      const double ex = (double)(nx - 1) - gy(i), ey = gx(i);
+      const double tol = 64.0 * 2.220446049250313e-16 *
+                         std::max({1.0, std::fabs(ex), std::fabs(ey), std::fabs(gx(j)), std::fabs(gy(j))});
+      ok = std::fabs(gx(j) - ex) <= tol && std::fabs(gy(j) - ey) <= tol;
+    }
+    for (int k = 0; k < n_t && ok; ++k) ok = (M[k] % 4 == 0) || radius[k] == 0.0;
+    if (ok) sym_rot = 4;
+  }
 }
 
 void pat_geometry_s::upload(hipStream_t stream) {
@@ -242,20 +265,13 @@ void pat_geometry_s::upload(hipStream_t stream) {
   d_det.alloc(sizeof(double2) * n_det);
   d_rad.alloc(sizeof(double2) * n_t);
   d_moff.alloc(sizeof(int2) * n_t);
-  // the table is stored in the element type (positions are still FP64)
-  std::vector<float2> h_cs32;
-  if (dtype == PAT_F32) {
-    h_cs32.resize(n_samples_per_det);
-    for (int64_t i = 0; i < n_samples_per_det; ++i)
-      h_cs32[i] = make_float2((float)h_cs[i].x, (float)h_cs[i].y);
-  }
-  d_cs.alloc((dtype == PAT_F32 ? sizeof(float2) : sizeof(double2)) * n_samples_per_det);
+  // the table is FP64 for every element type (positions are FP64)
+  d_cs.alloc(sizeof(double2) * n_samples_per_det);
   d_win.alloc(sizeof(int4) * 2 * nb);
   PAT_HIP(hipMemcpyAsync(d_det.p, h_det.data(), d_det.bytes, hipMemcpyHostToDevice, stream));
   PAT_HIP(hipMemcpyAsync(d_rad.p, h_rad.data(), d_rad.bytes, hipMemcpyHostToDevice, stream));
   PAT_HIP(hipMemcpyAsync(d_moff.p, h_moff.data(), d_moff.bytes, hipMemcpyHostToDevice, stream));
-  PAT_HIP(hipMemcpyAsync(d_cs.p, dtype == PAT_F32 ? (const void*)h_cs32.data() : (const void*)h_cs.data(),
-                         d_cs.bytes, hipMemcpyHostToDevice, stream));
+  PAT_HIP(hipMemcpyAsync(d_cs.p, h_cs.data(), d_cs.bytes, hipMemcpyHostToDevice, stream));
   PAT_HIP(hipMemcpyAsync(d_win.p, h_win.data(), d_win.bytes, hipMemcpyHostToDevice, stream));
   PAT_HIP(hipStreamSynchronize(stream));
 }
@@ -334,6 +350,10 @@ extern "C" pat_status pat_geometry_get_info(pat_geometry g, pat_geometry_info* o
     out->csr_nnz = g->csr_nnz;
     out->csr_tile_side = g->csr_side;
     out->csr_win_max = g->csr_win_max;
+    out->csr_rot = g->csr_nnz >= 0 ? g->csr_rot : 1;
+    out->sym_rot = g->sym_rot;
+    out->csr_waves = g->csr_waves;
+    out->csr_lanes = g->csr_lanes;
     return PAT_OK;
   });
 }
@@ -353,6 +373,34 @@ extern "C" pat_status pat_geometry_set_adjoint(pat_geometry g, int32_t mode, voi
     PAT_CHECK_ARG(mode >= 0 && mode <= 2, "adjoint mode must be 0 (scatter), 1 (CSR) or 2 (tiled CSR)");
     if (mode != 0) g->ensure_csr(static_cast<hipStream_t>(stream));
     g->adj_mode = mode;
+    return PAT_OK;
+  });
+}
+
+extern "C" pat_status pat_geometry_set_tiled_launch(pat_geometry g, int32_t waves, int32_t row_lanes) {
+  return guarded([&]() -> pat_status {
+    PAT_CHECK_ARG(g != nullptr, "geometry is NULL");
+    PAT_CHECK_ARG(waves == 4 || waves == 8 || waves == 16, "waves per workgroup must be 4, 8 or 16");
+    PAT_CHECK_ARG(row_lanes == 16 || row_lanes == 64, "lanes per row must be 16 or 64");
+    g->csr_waves = waves;
+    g->csr_lanes = row_lanes;
+    return PAT_OK;
+  });
+}
+
+extern "C" pat_status pat_geometry_set_symmetry(pat_geometry g, int32_t enable, void* stream) {
+  return guarded([&]() -> pat_status {
+    PAT_CHECK_ARG(g != nullptr, "geometry is NULL");
+    const bool want = enable != 0;
+    if (want == g->sym_enabled) return PAT_OK;
+    g->sym_enabled = want;
+    const int rot = (want && g->sym_rot == 4) ? 4 : 1;
+    if (g->csr_nnz >= 0 && rot != g->csr_rot) {
+      hipStream_t s = static_cast<hipStream_t>(stream);
+      PAT_HIP(hipStreamSynchronize(s));  // no apply may still read the old matrix
+      g->drop_csr();
+      g->ensure_csr(s);
+    }
     return PAT_OK;
   });
 }

@@ -121,6 +121,29 @@ __device__ __forceinline__ T group_sum(T v) {
   return v;
 }
 
+// Sum over each row of 16 lanes by DPP moves (rotate by 8 and 4 within the
+// row, then swap lanes 2 and 1 apart within quads); every lane of the row
+// ends with the row's sum, lane 0 of the row in a fixed order.
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <class T>
+__device__ __forceinline__ T row16_sum(T x) {
+  x += dpp_move<0x128>(x);  // row_ror:8
+  x += dpp_move<0x124>(x);  // row_ror:4
+  x += dpp_move<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += dpp_move<0xB1>(x);   // quad_perm [1,0,3,2]
+  return x;
+}
+
 // Deterministic block reduction into one value per block (blockDim.x = NT).
 template <int NT, class T>
 __device__ __forceinline__ T block_sum(T v, T* lds) {
@@ -157,7 +180,7 @@ struct GeomDev {
   const double2* det;    // [n_det] detector position in pixel-index units
   const double2* rad;    // [n_t] (r_k / h, 1 / M_k)
   const int2* moff;      // [n_t] (M_k, offset of radius k in the table)
-  const void* cs;        // [sum M_k] (cos, sin) of 2 pi (m + 1/2) / M_k, element type
+  const void* cs;        // [sum M_k] (cos, sin) of 2 pi (m + 1/2) / M_k, FP64
   const int4* win;       // [n_bins][2]: four sample ranges [m0,m1) per bin
   double kscale, koff;   // radius index of a radius rho in pixel units: rho*kscale - koff
   int lanes_log2;        // forward: lanes per bin, log2 (4..6)
@@ -167,16 +190,12 @@ struct GeomDev {
   int n_groups;          // ceil(n_det / det_group)
 };
 
-// (cos, sin) of an arc sample from the table of the element type, widened to FP64.
+// (cos, sin) of an arc sample from the FP64 table (every element type: an FP32
+// table would put errors of r_k / h times 6e-8 pixels into the positions).
 template <class T>
 __device__ __forceinline__ double2 table_cs(const GeomDev& g, int idx) {
-  if constexpr (sizeof(T) == 8) {
-    const gptr<const double> c = as_global(static_cast<const double*>(g.cs)) + 2 * (int64_t)idx;
-    return make_double2(c[0], c[1]);
-  } else {
-    const gptr<const float> c = as_global(static_cast<const float*>(g.cs)) + 2 * (int64_t)idx;
-    return make_double2((double)c[0], (double)c[1]);
-  }
+  const gptr<const double> c = as_global(static_cast<const double*>(g.cs)) + 2 * (int64_t)idx;
+  return make_double2(c[0], c[1]);
 }
 
 // Forward projection of one instance.
@@ -221,7 +240,7 @@ struct InstDev {
   const T* tau_u;     // [N]
   const T* tau_v;     // [N] (both components share one value)
   const T* atq_part;  // [n_groups][N] partial A^T q per detector group
-  const double* atq64;  // [N] A^T q accumulated in FP64 (check iterations; may be null)
+  const double* atq64;  // [n_groups][N] A^T q accumulated in FP64 (check iterations; may be null)
   T* upad_gap;        // [(ny+2)(nx+2)] padded u+ written on check iterations
   double* red;        // partial sums [GAP_NSLOTS][red_stride]
   int red_stride;
@@ -257,9 +276,23 @@ struct CsrMultiArgs {
   // at LDS offset off; lcol = off + k - k0 replaces col
   const uint16_t* lcol;
   const int4* win;
-  int side, tiles_x, nx, ny, n_det, n_t;
-  int lds_stride;  // staged elements per right-hand side (the geometry's largest window)
+  int side, tiles_x, nx, ny, n_det, n_t;  // n_det: detectors of the stored matrix
+  int lds_stride;  // staged elements per slot (the geometry's largest window)
+  // quarter-turn slots: with rot = 4 the matrix holds the first n_det rows of
+  // a ring of 4 n_det detectors and slot r writes y[r] at the pixel turned by
+  // r % 4 quarter turns; x[r] is then the data of detectors from
+  // (r % 4) n_det on. rot = 1: no turn.
+  int rot;
 };
+
+// Pixel (i, j) of a square n x n grid turned by t quarter turns (counter-
+// clockwise, about the grid centre): (i, j) -> (n-1-j, i).
+__device__ __forceinline__ int64_t quarter_turn(int i, int j, int n, int t) {
+  int a = i, b = j;
+  if (t & 2) { a = n - 1 - i; b = n - 1 - j; }
+  if (t & 1) { const int c = a; a = n - 1 - b; b = c; }
+  return (int64_t)b * n + a;
+}
 
 // Ordered final sum of one instance's gap partials.
 struct GapFinishArgs {

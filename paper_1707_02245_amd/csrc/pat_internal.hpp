@@ -22,8 +22,17 @@ struct pat_geometry_s {
   int adj_mode = 2;
   pat::DevBuf csr_ptr, csr_col, csr_val;
   int64_t csr_nnz = -1;  // -1: not built
-  // pixel tiles of the stored A^T (side 0: windows too large for LDS)
+  // quarter-turn symmetry: sym_rot = 4 when detector d + n_det/4 sits at the
+  // quarter turn of detector d about the centre of a square grid (1 if not);
+  // csr_rot = 4 when the stored A^T holds the first n_det/4 detectors only
+  int sym_rot = 1, csr_rot = 1;
+  bool sym_enabled = true;
+  // pixel tiles of the stored A^T (side 0: windows too large for LDS);
+  // csr_win_max is per quarter-turn slot
   int csr_side = 0, csr_tiles_x = 0, csr_tiles_y = 0, csr_win_max = 0;
+  // waves per workgroup of the tiled kernel (4, 8 or 16) and lanes per row
+  // (16 or 64)
+  int csr_waves = 4, csr_lanes = 16;
   pat::DevBuf csr_lcol, csr_win;  // uint16 per non-zero; int4 per (tile, detector)
   // scratch of the stand-alone applies
   pat::DevBuf scratch_pad, scratch_part;
@@ -35,6 +44,8 @@ struct pat_geometry_s {
   pat::GeomDev dev() const;
   void ensure_csr(hipStream_t s);
   int n_csr_tiles() const { return csr_tiles_x * csr_tiles_y; }
+  int csr_det() const { return n_det / csr_rot; }  // detectors in the stored A^T
+  void drop_csr();
   // the adjoint mode in effect (2 falls back to 1 without tiles)
   int effective_adj_mode() const { return adj_mode == 2 && csr_side == 0 ? 1 : adj_mode; }
   int64_t n_bins() const { return (int64_t)n_det * n_t; }
@@ -82,6 +93,8 @@ struct Launch {
   int n_adj = 0, n_csr = 0, csr_total = 0, csr_max_rhs = 1;
   bool csr_tiled = false;  // LDS-staged kernel for every CSR group
   size_t csr_shm = 0;      // its dynamic LDS per workgroup
+  int csr_waves = 4;       // its waves per workgroup
+  int csr_lanes = 16;      // its lanes per row
   int lanes_log2 = 6;   // shared by every instance of one launch
   int max_tile = 32;    // shared by every instance of one launch
 };
@@ -129,10 +142,18 @@ constexpr int kCsrLdsBytes = 64 * 1024;
 constexpr int64_t kCsrSlack = 256;  // zero entries after the values and window offsets
 int device_lds_per_block();
 template <class T>
-void launch_csr_tiled(const CsrMultiArgs<T>& a, hipStream_t s, bool wide);
+void launch_csr_tiled(const CsrMultiArgs<T>& a, hipStream_t s, bool wide, int waves, int lanes);
 template <class T>
 void launch_csr_tiled_batched(const CsrMultiArgs<T>* arr, const int* starts, int n_grp, int total_blocks,
-                              size_t shm, hipStream_t s, bool wide, int max_rhs);
+                              size_t shm, hipStream_t s, bool wide, int max_rhs, int waves, int lanes);
+// Default workgroup shape of the tiled kernel for a dynamic LDS size: 16
+// waves when the windows leave room for a single workgroup per CU, else 4.
+inline int csr_waves_for(size_t shm) { return shm > 80 * 1024 ? 16 : 4; }
+// Default lanes per row for a mean row length (entries): 64 for long rows.
+inline int csr_lanes_for(double mean_row) { return mean_row >= 512.0 ? 64 : 16; }
+// Multi-RHS plain kernel for one group given on the host.
+template <class T>
+void launch_csr_spmm(const CsrMultiArgs<T>& a, hipStream_t s, bool wide);
 template <class T>
 void prepare_csr_tiled(int max_rhs, size_t shm);
 

@@ -154,7 +154,11 @@ __global__ __launch_bounds__(256) void primal_kernel(const InstDev<T>* __restric
     const T tau = a.tau_u[p];
     T un;
     // the gap's dual residual K^T y: FP64 A^T q when available
-    const double atq_d = (CHECK && a.atq64) ? a.atq64[p] : (double)atq;
+    double atq_d = (double)atq;
+    if (CHECK && a.atq64) {
+      atq_d = 0.0;
+      for (int gi = 0; gi < a.n_groups; ++gi) atq_d += a.atq64[gi * N + p];
+    }
     if (a.kind == PAT_REG_TIKHONOV) {
       // u <- prox_{tau G}(u - tau A^T q), G = lam/2 ||u||^2
       un = (u_old - tau * atq) / (T(1) + tau * a.lam);

@@ -399,6 +399,19 @@ void pat_geometry_s::ensure_csr(hipStream_t s) {
   if (csr_nnz >= 0) return;
   if (dtype == PAT_F64) pat::build_csr_adjoint<double>(this, s);
   else pat::build_csr_adjoint<float>(this, s);
+  csr_waves = pat::csr_waves_for(csr_side ? (dtype == PAT_F64 ? 8 : 4) * (size_t)csr_win_max * csr_rot : 0);
+  csr_lanes = pat::csr_lanes_for(n_pix() > 0 ? (double)csr_nnz / (double)n_pix() : 0.0);
+}
+
+void pat_geometry_s::drop_csr() {
+  csr_ptr.release();
+  csr_col.release();
+  csr_val.release();
+  csr_lcol.release();
+  csr_win.release();
+  csr_nnz = -1;
+  csr_rot = 1;
+  csr_side = csr_tiles_x = csr_tiles_y = csr_win_max = 0;
 }
 
 namespace {
@@ -416,40 +429,66 @@ void forward_impl(pat_geometry g, const void* d_u, void* d_f, hipStream_t s) {
 }
 
 template <class T>
-void adjoint_impl(pat_geometry g, const void* d_f, void* d_u, hipStream_t s) {
+void forward_padded_impl(pat_geometry g, const void* d_upad, void* d_f, hipStream_t s) {
+  pat::FwdArgs<T> a{};
+  a.g = g->dev();
+  a.upad = static_cast<const T*>(d_upad);
+  a.out = static_cast<T*>(d_f);
+  pat::launch_forward<T>(pat::FWD_PLAIN, a, g->lanes_log2, s);
+}
+
+// parts: csr_rot partial images (or null: sum into d_u)
+template <class T>
+void adjoint_impl(pat_geometry g, const void* d_f, void* d_u, hipStream_t s, T* parts = nullptr) {
   if (g->adj_mode != 0) g->ensure_csr(s);
-  if (g->effective_adj_mode() == 2) {
+  const int mode = g->effective_adj_mode();
+  if (mode != 0) {
+    const int64_t N = g->n_pix();
+    const int rot = g->csr_rot;
     pat::CsrMultiArgs<T> c{};
     c.ptr = pat::ptr<int64_t>(g->csr_ptr);
     c.col = pat::ptr<int>(g->csr_col);
     c.val = pat::ptr<T>(g->csr_val);
-    c.n_rows = g->n_pix();
-    c.nrhs = 1;
-    c.x[0] = static_cast<const T*>(d_f);
-    c.y[0] = static_cast<T*>(d_u);
-    c.lcol = pat::ptr<uint16_t>(g->csr_lcol);
-    c.win = pat::ptr<int4>(g->csr_win);
-    c.side = g->csr_side;
-    c.tiles_x = g->csr_tiles_x;
+    c.n_rows = N;
     c.nx = g->nx;
     c.ny = g->ny;
-    c.n_det = g->n_det;
+    c.n_det = g->csr_det();
     c.n_t = g->n_t;
-    c.lds_stride = g->csr_win_max;
-    pat::launch_csr_tiled<T>(c, s, false);
+    c.rot = rot;
+    c.nrhs = rot;
+    // with quarter turns each slot writes a partial image, summed in order
+    T* part = parts ? parts : static_cast<T*>(d_u);
+    if (rot > 1 && !parts) {
+      g->scratch_part.ensure(sizeof(T) * (size_t)rot * N);
+      part = pat::ptr<T>(g->scratch_part);
+    }
+    for (int r = 0; r < rot; ++r) {
+      c.x[r] = static_cast<const T*>(d_f) + (int64_t)r * c.n_det * g->n_t;
+      c.y[r] = part + (int64_t)r * N;
+    }
+    if (mode == 2) {
+      c.lcol = pat::ptr<uint16_t>(g->csr_lcol);
+      c.win = pat::ptr<int4>(g->csr_win);
+      c.side = g->csr_side;
+      c.tiles_x = g->csr_tiles_x;
+      c.lds_stride = g->csr_win_max;
+      pat::launch_csr_tiled<T>(c, s, false, g->csr_waves, g->csr_lanes);
+    } else if (rot > 1) {
+      pat::launch_csr_spmm<T>(c, s, false);
+    } else {
+      pat::CsrArgs<T> p{};
+      p.ptr = c.ptr;
+      p.col = c.col;
+      p.val = c.val;
+      p.x = c.x[0];
+      p.y = c.y[0];
+      p.n_rows = N;
+      pat::launch_csr_spmv<T>(p, s);
+    }
+    if (rot > 1 && !parts) pat::launch_reduce_groups<T>(part, static_cast<T*>(d_u), rot, N, s);
     return;
   }
-  if (g->adj_mode != 0) {
-    pat::CsrArgs<T> c{};
-    c.ptr = pat::ptr<int64_t>(g->csr_ptr);
-    c.col = pat::ptr<int>(g->csr_col);
-    c.val = pat::ptr<T>(g->csr_val);
-    c.x = static_cast<const T*>(d_f);
-    c.y = static_cast<T*>(d_u);
-    c.n_rows = g->n_pix();
-    pat::launch_csr_spmv<T>(c, s);
-    return;
-  }
+  PAT_CHECK_ARG(parts == nullptr, "partial images need a stored A^T (adjoint mode 1 or 2)");
   pat::AdjArgs<T> a{};
   a.g = g->dev();
   a.data = static_cast<const T*>(d_f);
@@ -485,6 +524,32 @@ extern "C" pat_status pat_forward(pat_geometry g, const void* d_u, void* d_f, vo
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (g->dtype == PAT_F64) forward_impl<double>(g, d_u, d_f, s);
     else forward_impl<float>(g, d_u, d_f, s);
+    return PAT_OK;
+  });
+}
+
+extern "C" pat_status pat_forward_padded(pat_geometry g, const void* d_upad, void* d_f, void* stream) {
+  return pat::guarded([&]() -> pat_status {
+    PAT_CHECK_ARG(g != nullptr, "geometry is NULL");
+    PAT_CHECK_ARG(d_upad != nullptr && d_f != nullptr, "NULL buffer");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (g->dtype == PAT_F64) forward_padded_impl<double>(g, d_upad, d_f, s);
+    else forward_padded_impl<float>(g, d_upad, d_f, s);
+    return PAT_OK;
+  });
+}
+
+extern "C" pat_status pat_adjoint_partials(pat_geometry g, const void* d_f, void* d_parts, void* stream) {
+  return pat::guarded([&]() -> pat_status {
+    PAT_CHECK_ARG(g != nullptr, "geometry is NULL");
+    PAT_CHECK_ARG(d_parts != nullptr && d_f != nullptr, "NULL buffer");
+    if (g->adj_mode == 0) {
+      pat::set_error("partial images need a stored A^T (adjoint mode 1 or 2)");
+      return PAT_ERR_UNSUPPORTED;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (g->dtype == PAT_F64) adjoint_impl<double>(g, d_f, nullptr, s, static_cast<double*>(d_parts));
+    else adjoint_impl<float>(g, d_f, nullptr, s, static_cast<float*>(d_parts));
     return PAT_OK;
   });
 }

@@ -251,9 +251,10 @@ class Solver {
     const GeomDev gd = I.gdev(lanes_log2, tile);
     I.csr = g->adj_mode != 0;
     if (I.csr) g->ensure_csr(s);
-    I.atq_part.alloc(sizeof(T) * (I.csr ? 1 : gd.n_groups) * N);
+    // the stored A^T with quarter turns writes one partial image per turn
+    I.atq_part.alloc(sizeof(T) * (I.csr ? g->csr_rot : gd.n_groups) * N);
     // FP64-accumulated A^T q for the gap: only FP32 needs a separate pass
-    if (I.csr && sizeof(T) == 4) I.atq64.alloc(sizeof(double) * N);
+    if (I.csr && sizeof(T) == 4) I.atq64.alloc(sizeof(double) * g->csr_rot * N);
     I.n_fwd = fwd_grid(g->n_det, g->n_t, lanes_log2);
     I.n_pix = pix_blocks(N);
     I.n_adj = I.csr ? 0 : gd.tiles_x * gd.tiles_y * gd.n_groups;
@@ -276,7 +277,7 @@ class Solver {
     const GeomDev gd = I.gdev(lanes_log2, tile);
     d.nx = I.g->nx;
     d.ny = I.g->ny;
-    d.n_groups = I.csr ? 1 : gd.n_groups;
+    d.n_groups = I.csr ? I.g->csr_rot : gd.n_groups;
     d.n_bins = (int)I.g->n_bins();
     d.kind = I.reg.kind;
     d.lam = (T)I.reg.lambda;
@@ -331,8 +332,9 @@ class Solver {
       fg[k].red_stride = I.red_stride;
       if (I.csr) {
         // instances sharing a geometry share one pass over its stored A^T: up
-        // to kMaxRhs, and for the tiled kernel as many as their staged
-        // windows fit the workgroup LDS
+        // to kMaxRhs slots (rot per instance), and for the tiled kernel as
+        // many as their staged windows fit the workgroup LDS
+        const int rot = I.g->csr_rot;
         int cap = kMaxRhs;
         if (I.g->effective_adj_mode() == 2) {
           // a kernel instance of R slots (1, 2, 4 or 8) stages R windows
@@ -341,7 +343,7 @@ class Solver {
         }
         CsrMultiArgs<T>* grp = nullptr;
         for (auto& c : cd)
-          if (c.ptr == ptr<int64_t>(I.g->csr_ptr) && c.nrhs < cap) grp = &c;
+          if (c.ptr == ptr<int64_t>(I.g->csr_ptr) && c.nrhs + rot <= cap) grp = &c;
         if (!grp) {
           cd.push_back(CsrMultiArgs<T>{});
           grp = &cd.back();
@@ -360,14 +362,17 @@ class Solver {
           }
           grp->nx = g->nx;
           grp->ny = g->ny;
-          grp->n_det = g->n_det;
+          grp->n_det = g->csr_det();
           grp->n_t = g->n_t;
+          grp->rot = rot;
           csr_geo.push_back(g);
         }
-        grp->x[grp->nrhs] = ptr<T>(I.q);
-        grp->y[grp->nrhs] = ptr<T>(I.atq_part);
-        grp->y64[grp->nrhs] = ptr<double>(I.atq64);
-        ++grp->nrhs;
+        for (int r = 0; r < rot; ++r) {
+          grp->x[grp->nrhs] = ptr<T>(I.q) + (int64_t)r * grp->n_det * grp->n_t;
+          grp->y[grp->nrhs] = ptr<T>(I.atq_part) + (int64_t)r * I.g->n_pix();
+          grp->y64[grp->nrhs] = I.atq64.p ? ptr<double>(I.atq64) + (int64_t)r * I.g->n_pix() : nullptr;
+          ++grp->nrhs;
+        }
       } else {
         AdjArgs<T> a{};
         a.g = gd;
@@ -395,6 +400,15 @@ class Solver {
     const size_t shm = sizeof(T) * (size_t)max_stride * (size_t)r_inst;
     tiled = tiled && shm <= (size_t)lds_max;
     if (tiled) prepare_csr_tiled<T>(max_rhs, shm);
+    // workgroup shape: the geometry's tuned choice for a single group, else by LDS
+    int waves = csr_waves_for(shm);
+    double mean_row = 0.0;
+    for (pat_geometry g : csr_geo) mean_row = std::max(mean_row, (double)g->csr_nnz / (double)g->n_pix());
+    int lanes = csr_lanes_for(mean_row);
+    if (tiled && cd.size() == 1 && cd[0].nrhs == csr_geo[0]->csr_rot) {
+      waves = csr_geo[0]->csr_waves;
+      lanes = csr_geo[0]->csr_lanes;
+    }
     for (size_t c = 0; c < cd.size(); ++c) {
       const int blocks = tiled ? csr_geo[c]->n_csr_tiles() : (int)((cd[c].n_rows + 3) / 4);
       cs.push_back(cs.back() + blocks);
@@ -422,6 +436,8 @@ class Solver {
     L.csr_max_rhs = max_rhs;
     L.csr_tiled = tiled;
     L.csr_shm = shm;
+    L.csr_waves = waves;
+    L.csr_lanes = lanes;
     L.csr_total = cs.back();
     L.pix_total = ps[n];
     L.lanes_log2 = lanes_log2;
@@ -451,7 +467,7 @@ class Solver {
       for (int wide = 0; wide <= (check && sizeof(T) == 4 ? 1 : 0); ++wide) {
         if (L.csr_tiled)
           launch_csr_tiled_batched<T>(ptr<CsrMultiArgs<T>>(L.csr), ptr<int>(L.csr_start), L.n_csr,
-                                      L.csr_total, L.csr_shm, s, wide != 0, L.csr_max_rhs);
+                                      L.csr_total, L.csr_shm, s, wide != 0, L.csr_max_rhs, L.csr_waves, L.csr_lanes);
         else
           launch_csr_spmm_batched<T>(ptr<CsrMultiArgs<T>>(L.csr), ptr<int>(L.csr_start), L.n_csr,
                                      L.csr_total, s, wide != 0, L.csr_max_rhs);

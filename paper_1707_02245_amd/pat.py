@@ -98,6 +98,18 @@ class Geometry:
         L.check(L.load().pat_geometry_set_adjoint(self._h, m, _stream()))
         return self.refresh_info()
 
+    def set_tiled_launch(self, waves, row_lanes):
+        """Workgroup shape of the tiled adjoint: waves per workgroup (4, 8, 16)
+        and lanes per matrix row (16, 64)."""
+        L.check(L.load().pat_geometry_set_tiled_launch(self._h, waves, row_lanes))
+        return self.refresh_info()
+
+    def set_symmetry(self, enable):
+        """Let the stored A^T use the quarter-turn symmetry of the geometry
+        (rows of a quarter of the detectors only) or store every detector."""
+        L.check(L.load().pat_geometry_set_symmetry(self._h, 1 if enable else 0, _stream()))
+        return self.refresh_info()
+
     def autotune(self, cache_path=None, reps=10):
         """pat_geometry_autotune: time the launch candidates (or read the cache)."""
         res = L.AutotuneResult()
@@ -137,6 +149,24 @@ class Geometry:
         out = self.image() if out is None else out
         _need(out, self.dtype, self.nx * self.ny, "out")
         L.check(L.load().pat_adjoint(self._h, _ptr(f), _ptr(out), _stream()))
+        return out
+
+    def forward_padded(self, upad, out=None):
+        """f = A u from the zero-bordered image [ny+2][nx+2] (pat_forward_padded)."""
+        _need(upad, self.dtype, (self.nx + 2) * (self.ny + 2), "upad")
+        out = self.data() if out is None else out
+        _need(out, self.dtype, self.n_det * self.n_t, "out")
+        L.check(L.load().pat_forward_padded(self._h, _ptr(upad), _ptr(out), _stream()))
+        return out
+
+    def adjoint_partials(self, f, out=None):
+        """The csr_rot partial images of A^T f (pat_adjoint_partials)."""
+        _need(f, self.dtype, self.n_det * self.n_t, "f")
+        rot = self.info["csr_rot"]
+        if out is None:
+            out = torch.zeros((rot, self.ny, self.nx), dtype=self.dtype, device="cuda")
+        _need(out, self.dtype, rot * self.nx * self.ny, "out")
+        L.check(L.load().pat_adjoint_partials(self._h, _ptr(f), _ptr(out), _stream()))
         return out
 
     def state_elems(self, kind):

@@ -73,6 +73,47 @@ def test_forward_adjoint_elementwise(name, dt, adj):
     assert ef <= TOL_APPLY[dt] and ea <= TOL_APPLY[dt], (ef, ea)
 
 
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("name", ["tv64", "ragged"])
+def test_tiled_workgroup_shapes(name, dt):
+    """Every workgroup shape of the tiled adjoint (4/8/16 waves, 16/64 lanes
+    per row) matches the oracle, with quarter-turn storage (tv64) and
+    without (ragged)."""
+    d, og, g = _geoms(name, dt)
+    A = OG.forward_matrix(og)
+    y = np.random.default_rng(12).standard_normal(og.n_bins)
+    ref = A.T @ y
+    yd = to_dev(y.reshape(og.n_det, og.n_t), DT[dt])
+    g.set_adjoint("tiled")
+    assert g.info["csr_rot"] == (4 if name == "tv64" else 1)
+    for waves in (4, 8, 16):
+        for lanes in (16, 64):
+            g.set_tiled_launch(waves, lanes)
+            e = rel(host(g.adjoint(yd)), ref)
+            assert e <= TOL_APPLY[dt], (waves, lanes, e)
+    with pytest.raises(RuntimeError):
+        g.set_tiled_launch(2, 16)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_forward_padded_and_partials_entry_points(dt):
+    """pat_forward_padded on the zero-bordered image equals pat_forward; with
+    the full stored matrix (no quarter turns) the one partial image is the
+    adjoint; the matrix-free mode has no partials."""
+    d, og, g = _geoms("ragged", dt)
+    u = to_dev(np.random.default_rng(6).standard_normal((og.ny, og.nx)), DT[dt])
+    upad = torch.zeros((og.ny + 2, og.nx + 2), dtype=DT[dt], device="cuda")
+    upad[1:-1, 1:-1] = u
+    assert np.array_equal(host(g.forward_padded(upad)), host(g.forward(u)))
+    y = to_dev(np.random.default_rng(7).standard_normal((og.n_det, og.n_t)), DT[dt])
+    g.set_adjoint("tiled")
+    assert g.info["csr_rot"] == 1
+    assert np.array_equal(host(g.adjoint_partials(y))[0], host(g.adjoint(y)))
+    g.set_adjoint("scatter")
+    with pytest.raises(RuntimeError):
+        g.adjoint_partials(y, torch.zeros((1, og.ny, og.nx), dtype=DT[dt], device="cuda"))
+
+
 @pytest.mark.parametrize("launch", [(4, 16, 1), (5, 32, 3), (6, 64, 7)])
 def test_launch_shapes_agree_with_oracle(launch):
     d, og, g = _geoms("ragged", "f32")
@@ -107,12 +148,21 @@ def test_csr_matches_oracle_matrix_structure():
     assert g.info["csr_nnz"] == A.nnz
 
 
-def _expected_tiles(A, nx, ny, n_det, n_t, esz):
+def _quarter_turn_symmetric(d):
+    """A closed ring of 4m detectors about the centre of a square grid."""
+    return (d["nx"] == d["ny"] and d["n_det"] % 4 == 0 and d.get("det_xy") is None
+            and abs(d["arc_span"] - 2 * math.pi) < 1e-12 and d["det_cx"] == 0.0
+            and d["det_cy"] == 0.0 and d["x_min"] == -d["x_max"] and d["y_min"] == -d["y_max"])
+
+
+def _expected_tiles(A, nx, ny, n_det, n_t, esz, rot=1):
     """Tile side and largest window of the LDS-staged adjoint: per tile of
     side x side pixels and detector, the run of radii its non-zeros span; the
-    first side (8, then 4) whose largest per-tile sum of runs fits 64 KB of one
-    right-hand side and 16-bit offsets, else no tiles."""
-    At = A.T.tocsr()
+    first side (8, then 4) whose largest per-tile sum of runs over the stored
+    detectors (the first n_det/rot) fits 16-bit offsets and, times rot slots,
+    64 KB, else no tiles."""
+    n_det //= rot
+    At = A[:n_det * n_t].T.tocsr()
     At.eliminate_zeros()
     for side in (8, 4):
         tx, ty = -(-nx // side), -(-ny // side)
@@ -127,7 +177,7 @@ def _expected_tiles(A, nx, ny, n_det, n_t, esz):
                     np.minimum.at(lo, cols // n_t, cols % n_t)
                     np.maximum.at(hi, cols // n_t, cols % n_t)
             wmax = max(wmax, int(np.sum(np.where(hi >= 0, hi - lo + 1, 0))))
-        if 1 <= wmax <= 65535 and wmax * esz <= 65536:
+        if 1 <= wmax <= 65535 and wmax * esz * rot <= 65536:
             return side, wmax
     return 0, 0
 
@@ -141,15 +191,62 @@ def test_tile_choice_and_tiled_adjoint(shape, dt):
     d = desc_for(n, n_det, n_t)
     og = OG.make_geometry(d)
     A = OG.forward_matrix(og)
-    side, wmax = _expected_tiles(A, n, n, n_det, n_t, 8 if dt == "f64" else 4)
-    print(f"tiles {shape} {dt}: expected side {side} window {wmax}", flush=True)
+    rot = 4 if _quarter_turn_symmetric(d) else 1
+    side, wmax = _expected_tiles(A, n, n, n_det, n_t, 8 if dt == "f64" else 4, rot)
+    print(f"tiles {shape} {dt}: expected side {side} window {wmax} rot {rot}", flush=True)
     g = pat.Geometry(dtype=DT[dt], **d)
     info = g.info
+    assert (info["sym_rot"], info["csr_rot"]) == (rot, rot)
     assert (info["csr_tile_side"], info["csr_win_max"]) == (side, wmax)
     assert info["adj_mode"] == (2 if side else 1)
     y = np.random.default_rng(4).standard_normal(og.n_bins)
     aty = host(g.adjoint(to_dev(y.reshape(n_det, n_t), DT[dt])))
     assert rel(aty, A.T @ y) <= TOL_APPLY[dt]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(64, 32, 128), (45, 12, 70)])
+def test_quarter_turn_storage(shape, dt):
+    """A ring of 4m detectors about a square grid: the stored A^T keeps the
+    rows of the first m detectors only (exactly the oracle's non-zeros of
+    those rows) and the quarter-turn adjoint (tiled and plain) matches the
+    oracle's A^T and the fully stored matrix; a ring that is not symmetric
+    (shifted centre) stores every detector."""
+    n, n_det, n_t = shape
+    d = desc_for(n, n_det, n_t)
+    og = OG.make_geometry(d)
+    A = OG.forward_matrix(og)
+    A.eliminate_zeros()
+    y = np.random.default_rng(9).standard_normal(og.n_bins)
+    ref = A.T @ y
+    print(f"quarter turns {shape} {dt}", flush=True)
+    g = pat.Geometry(dtype=DT[dt], **d)
+    info = g.info
+    assert (info["sym_rot"], info["csr_rot"]) == (4, 4)
+    assert info["csr_nnz"] == A[:(n_det // 4) * n_t].nnz
+    yd = to_dev(y.reshape(n_det, n_t), DT[dt])
+    out = {}
+    for adj in ("tiled", "csr"):
+        g.set_adjoint(adj)
+        out[adj] = host(g.adjoint(yd))
+        assert rel(out[adj], ref) <= TOL_APPLY[dt], adj
+    # the partial images sum (in order) to the adjoint, bit for bit
+    parts = g.adjoint_partials(yd)
+    assert tuple(parts.shape) == (4, n, n)
+    acc = torch.zeros_like(parts[0])
+    for r in range(4):
+        acc = acc + parts[r]
+    assert np.array_equal(host(acc), out["csr"])
+    g.set_symmetry(False)
+    assert (g.info["sym_rot"], g.info["csr_rot"], g.info["csr_nnz"]) == (4, 1, A.nnz)
+    for adj in ("tiled", "csr"):
+        g.set_adjoint(adj)
+        full = host(g.adjoint(yd))
+        assert rel(full, out[adj]) <= TOL_APPLY[dt], adj
+    g.set_symmetry(True)
+    assert g.info["csr_rot"] == 4
+    g2 = pat.Geometry(dtype=DT[dt], **dict(d, det_cx=0.01))
+    assert (g2.info["sym_rot"], g2.info["csr_rot"]) == (1, 1)
 
 
 FULL = {
