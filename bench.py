@@ -30,31 +30,32 @@ sys.path.insert(0, ROOT)
 METRIC = "PDHG time-to-gap 1e-4 at 256²: plain vs batched vs learned start; A/Aᵀ GB/s"
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per launch of the tiled FP64 A^T kernel at this workload: FETCH_SIZE and
-# WRITE_SIZE from two rocprofv3 counter passes, scaled by what the counters read for a
-# plain copy of known size (FETCH x 2, WRITE x 1); profiles/csr_tiled_tgv256_f64_hbm_traffic.md.
-# Reported only while the kernel's sources are the ones measured.
-MEASURED_TRAFFIC = {
-    "kernel": "csr_tiled_kernel<double, false, 1>",
-    "bytes_per_launch": 677.7e6,
-    "sources": {
-        "paper_1707_02245_amd/csrc/csr.hip":
-            "c545ff7b11d129494bd3b488d5d361cfeb60fc801f7341ca48ffebecf82038e5",
-        "paper_1707_02245_amd/csrc/pat_common.hpp":
-            "a7f20fa19ba05bc46cf519d7fe3950703ad46f3603285620ab0f958e66f48fd7",
-    },
-}
+# HBM bytes per launch at this workload (FP64): FETCH_SIZE and WRITE_SIZE from two
+# rocprofv3 counter passes, scaled by what the counters read for a plain copy of known
+# size (FETCH x 2, WRITE x 1); profiles/*_hbm_traffic.md. An entry is reported only
+# while the kernel's sources are the ones measured.
+MEASURED_TRAFFIC = []
 
 
 def measured_traffic(kernel_name):
     import hashlib
-    if not kernel_name.startswith(MEASURED_TRAFFIC["kernel"]):
-        return None
-    for rel, digest in MEASURED_TRAFFIC["sources"].items():
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            if hashlib.sha256(fh.read()).hexdigest() != digest:
-                return None
-    return MEASURED_TRAFFIC["bytes_per_launch"]
+    for ent in MEASURED_TRAFFIC:
+        if not kernel_name.startswith(ent["kernel"]):
+            continue
+        ok = True
+        for rel, digest in ent["sources"].items():
+            with open(os.path.join(ROOT, rel), "rb") as fh:
+                ok = ok and hashlib.sha256(fh.read()).hexdigest() == digest
+        return ent["bytes_per_launch"] if ok else None
+    return None
+
+
+# FP64 flops the forward gather needs per arc sample: the position (2 FMA), the
+# fractional offsets (2), three linear interpolations of the 2x2 taps (3 x (1 + FMA))
+# and the accumulation (1); FMA = 2 flops.
+FWD_FLOPS_PER_SAMPLE = 4 + 2 + 9 + 1
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 
 def parse():
@@ -324,43 +325,72 @@ def main():
     _, info_cap, _ = pat.solve(g, f, reg, max_iter=wl.max_iter, gap_tol=wl.gap_tol,
                                gap_every=args.gap_every, graph_block=args.gap_every, precond=pc)
 
-    # operator applies: HIP events on the stream the library launches on
+    # operator applies: HIP events on the stream the library launches on. The
+    # kernels the solver runs are timed alone: the forward gather on the
+    # zero-bordered image (no padding pass) and A^T into its partial images
+    # (the solver sums them in its primal update).
     u = torch.randn(wl.n, wl.n, dtype=tdt, device="cuda")
+    upad = torch.zeros(wl.n + 2, wl.n + 2, dtype=tdt, device="cuda")
+    upad[1:-1, 1:-1] = u
     y = torch.randn(wl.n_det, wl.n_t, dtype=tdt, device="cuda")
     fo = g.data()
     ao = g.image()
-    t_fwd = time_apply(lambda: g.forward(u, fo), args.apply_reps, torch)
-    t_adj = time_apply(lambda: g.adjoint(y, ao), args.apply_reps, torch)
+    rot = info_g["csr_rot"]
+    parts = torch.zeros((rot, wl.n, wl.n), dtype=tdt, device="cuda")
+    t_fwd = time_apply(lambda: g.forward_padded(upad, fo), args.apply_reps, torch)
+    t_adj = time_apply(lambda: g.adjoint_partials(y, parts), args.apply_reps, torch)
+    t_adj_sum = time_apply(lambda: g.adjoint(y, ao), args.apply_reps, torch)
     n_win = info_g["n_window"]
     nnz = info_g["csr_nnz"]
     n_pix, n_bins = wl.n * wl.n, wl.n_det * wl.n_t
     side = info_g["csr_tile_side"] if info_g["adj_mode"] == 2 else 0
     tname = "double" if esz == 8 else "float"
+    lanes = 1 << info_g["fwd_lanes_log2"]
+    waves, row_lanes = info_g["csr_waves"], info_g["csr_lanes"]
     if side:
-        # algorithmic bytes of one A^T apply by the tiled CSR: values + 16-bit
-        # window offsets + row offsets + the per-(tile, detector) windows, the
-        # input vector once and the output once
+        # algorithmic bytes of one A^T pass by the tiled CSR: values + 16-bit
+        # window offsets + row offsets + the per-(tile, stored detector)
+        # windows, the data once and the rot partial images once
         n_tiles = -(-wl.n // side) ** 2
-        adj_bytes = nnz * (esz + 2) + 8 * (n_pix + 1) + 16 * n_tiles * wl.n_det + esz * (n_bins + n_pix)
-        kname = f"csr_tiled_kernel<{tname}, false, 1> (A^T by the stored CSR, {side}x{side} pixel tiles, LDS-staged input)"
+        adj_bytes = (nnz * (esz + 2) + 8 * (n_pix + 1) + 16 * n_tiles * (wl.n_det // rot)
+                     + esz * (n_bins + rot * n_pix))
+        akname = (f"csr_tiled_kernel<{tname}, false, {1 if rot == 1 else 4}, {64 * waves}, {row_lanes}> "
+                  f"(A^T by the stored CSR, {side}x{side} pixel tiles, LDS-staged input, {rot} quarter-turn slots)")
     else:
-        # plain CSR: values + 32-bit columns + row offsets, input and output once
-        adj_bytes = nnz * (esz + 4) + 8 * (n_pix + 1) + esz * (n_bins + n_pix)
-        kname = f"csr_spmv_kernel<{tname}, false> (A^T by the stored CSR)"
-    csr_equiv = nnz * (esz + 4) + 8 * (n_pix + 1) + esz * (n_bins + n_pix)
-    apply = dict(forward_ms=t_fwd * 1e3, adjoint_ms=t_adj * 1e3, window_samples=n_win,
-                 csr_nnz=nnz, adjoint_bytes=adj_bytes, csr_tile_side=side,
+        adj_bytes = nnz * (esz + 4) + 8 * (n_pix + 1) + esz * (n_bins + rot * n_pix)
+        akname = f"csr_spmv_kernel<{tname}, false> (A^T by the stored CSR)"
+    # the bytes the same A^T would stream from the full (unsymmetrised) CSR
+    full_csr_equiv = nnz * rot * (esz + 4) + 8 * (n_pix + 1) + esz * (n_bins + n_pix)
+    fwd_flops = n_win * FWD_FLOPS_PER_SAMPLE
+    apply = dict(forward_ms=t_fwd * 1e3, adjoint_ms=t_adj * 1e3, adjoint_summed_ms=t_adj_sum * 1e3,
+                 window_samples=n_win, csr_nnz=nnz, csr_rot=rot, adjoint_bytes=adj_bytes,
+                 csr_tile_side=side, csr_waves=waves, csr_row_lanes=row_lanes,
                  forward_gsamples_s=n_win / t_fwd * 1e-9,
+                 forward_tflops=fwd_flops / t_fwd * 1e-12,
                  adjoint_gbs=adj_bytes / t_adj * 1e-9,
-                 adjoint_plain_csr_equivalent_gbs=csr_equiv / t_adj * 1e-9)
+                 adjoint_gbs_frac_of_hbm=adj_bytes / t_adj * 1e-9 / HBM_PEAK_GBS,
+                 adjoint_full_csr_equivalent_gbs=full_csr_equiv / t_adj * 1e-9,
+                 adjoint_kernel=akname,
+                 adjoint_traffic=measured_traffic(akname) if (wl.name == "tgv256" and esz == 8) else None)
     log(f"apply: {apply}")
-    roofline = {"kernel": kname,
-                "bound": "hbm", "achieved": adj_bytes / t_adj * 1e-9, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": adj_bytes / t_adj * 1e-9 / HBM_PEAK_GBS,
-                "traffic": measured_traffic(kname) if (wl.name == "tgv256" and esz == 8) else None,
-                "traffic_unit": "HBM bytes per launch (rocprofv3 counters, copy-calibrated)",
-                "bytes_per_launch": adj_bytes,
-                "avg_launch_us": t_adj * 1e6}
+    peak = FP64_VECTOR_PEAK_TFLOPS if esz == 8 else FP32_VECTOR_PEAK_TFLOPS
+    if t_fwd >= t_adj:
+        fkname = (f"fwd_kernel<{tname}, 0, {lanes}> (forward gather: 2x2 bilinear taps per arc sample from "
+                  f"the cache-resident image, FP64 positions; the solver's instance adds the dual step)")
+        roofline = {"kernel": fkname, "bound": "alu",
+                    "achieved": fwd_flops / t_fwd * 1e-12, "peak": peak, "unit": "TFLOP/s",
+                    "frac": fwd_flops / t_fwd * 1e-12 / peak,
+                    "traffic": measured_traffic(fkname) if (wl.name == "tgv256" and esz == 8) else None,
+                    "traffic_unit": "HBM bytes per launch (rocprofv3 counters, copy-calibrated)",
+                    "flops_per_launch": fwd_flops, "flops_per_sample": FWD_FLOPS_PER_SAMPLE,
+                    "avg_launch_us": t_fwd * 1e6}
+    else:
+        roofline = {"kernel": akname, "bound": "hbm",
+                    "achieved": adj_bytes / t_adj * 1e-9, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": adj_bytes / t_adj * 1e-9 / HBM_PEAK_GBS,
+                    "traffic": apply["adjoint_traffic"],
+                    "traffic_unit": "HBM bytes per launch (rocprofv3 counters, copy-calibrated)",
+                    "bytes_per_launch": adj_bytes, "avg_launch_us": t_adj * 1e6}
 
     out = {
         "metric": METRIC,
@@ -380,7 +410,9 @@ def main():
                                "on a closed circle of radius 1.2, 512 time samples (radii 0..2.4), "
                                "DIAG step sizes, stop at relative box gap 1e-4 (C=2), gap every "
                                f"{args.gap_every} iterations, cap {args.cap}",
-                   "launch": {k: tune[k] for k in ("fwd_lanes_log2", "adj_mode")},
+                   "launch": {k: tune[k] for k in ("fwd_lanes_log2", "adj_mode")} | {
+                       "csr_waves": info_g["csr_waves"], "csr_row_lanes": info_g["csr_lanes"],
+                       "csr_quarter_turn_slots": info_g["csr_rot"]},
                    "iterations": iters, "rel_gap": infos[-1]["rel_gap"],
                    "loop_seconds": infos[-1]["seconds"], "precond_ms": t_precond * 1e3,
                    "cap2000": {"iters": info_cap["iters"], "rel_gap": info_cap["rel_gap"],

@@ -106,23 +106,29 @@ __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T
     const double2 rr = g.rad[k];
     inv_m = rr.y;
     const int toff = g.moff[k].y;
-    const gptr<const T> up = as_global(a.upad);
+    const gptr<const char> ub = as_global(reinterpret_cast<const char*>(a.upad));
     const int P = g.pitch;
+    const unsigned rowb = (unsigned)P * (unsigned)sizeof(T);
     const int nx = g.nx, ny = g.ny;
-    // weighted 2x2 gather of one arc sample (zero outside the grid). Branch
-    // free: a sample outside the padded grid reads the padded corner cell and
-    // its value is discarded, so the loads of both samples in flight issue
-    // together instead of behind per-sample branches.
+    // Bilinear value of one arc sample from its 2x2 cell, as three linear
+    // interpolations (the same function as the weight products). Branch free:
+    // a sample whose cell is not inside the padded grid reads the cell at
+    // offset P - 1 instead (last border column of row 0 and, wrapping, the
+    // first border column of rows 1 and 2: all four taps are zero), so the
+    // loads of both samples in flight issue together.
     auto tap = [&](const double2 cs) -> T {
       const Sample s = arc_sample(p, rr.x, cs);
-      const bool in = (s.ix >= -1) & (s.ix < nx) & (s.iy >= -1) & (s.iy < ny);
-      const int o = in ? (s.iy + 1) * P + (s.ix + 1) : 0;
+      const bool in = ((unsigned)(s.ix + 1) <= (unsigned)nx) & ((unsigned)(s.iy + 1) <= (unsigned)ny);
+      const int o = in ? (int)__umul24((unsigned)(s.iy + 1), (unsigned)P) + (s.ix + 1) : P - 1;
       const T tx = (T)s.tx, ty = (T)s.ty;
-      const T w00 = (T(1) - tx) * (T(1) - ty), w10 = tx * (T(1) - ty);
-      const T w01 = (T(1) - tx) * ty, w11 = tx * ty;
-      const gptr<const T> q = up + o;
-      const T v = w00 * q[0] + w10 * q[1] + w01 * q[P] + w11 * q[P + 1];
-      return in ? v : T(0);
+      // 32-bit byte offsets from the uniform base (the padded image is far
+      // below 4 GB): scalar-base loads without 64-bit address arithmetic
+      const unsigned off = (unsigned)o * (unsigned)sizeof(T);
+      const gptr<const T> q0 = (gptr<const T>)(ub + off), q1 = (gptr<const T>)(ub + (off + rowb));
+      const T q00 = q0[0], q10 = q0[1], q01 = q1[0], q11 = q1[1];
+      const T lo = fma(tx, q10 - q00, q00);
+      const T hi = fma(tx, q11 - q01, q01);
+      return fma(ty, hi - lo, lo);
     };
     const int rng[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
 #pragma unroll
