@@ -109,6 +109,8 @@ typedef struct {
                            * centre, to 64 ulps); 1: not */
   int32_t csr_waves;      /* waves per workgroup of mode 2 (4, 8 or 16) */
   int32_t csr_lanes;      /* lanes per matrix row in mode 2 (16 or 64) */
+  int32_t fwd_path;      /* forward: 0/1 gather (radius-/detector-major), 2 LDS tiles */
+  int64_t fwd_pairs;      /* (bin, sample range) pairs of path 2 */
 } pat_geometry_info;
 
 /* Build the geometry tables on the device (FP64 host computation, rounded to
@@ -137,6 +139,18 @@ pat_status pat_geometry_set_launch(pat_geometry g, int32_t fwd_lanes_log2,
  * products); results agree to rounding order. Invalid mode:
  * PAT_ERR_INVALID_ARG. */
 pat_status pat_geometry_set_adjoint(pat_geometry g, int32_t mode, void* stream);
+
+/* How pat_forward and the solvers apply A (autotuner hook). 0 and 1: one
+ * group of lanes per bin gathers its arc samples' 2x2 cells from the cached
+ * image; a workgroup takes one radius for several detectors (0) or several
+ * consecutive radii of one detector (1); both give the same result bit for
+ * bit. 2: the image is cut into tiles of 64 x 64 cells staged in LDS; each
+ * workgroup sums, for a chunk of the tile's (bin, sample range) pairs, the
+ * samples whose cell lies in the tile, and a second pass adds each bin's
+ * partial sums in a fixed order (same operator, different summation order).
+ * Selecting path 2 builds its tables (synchronous on `stream`). Invalid
+ * path: PAT_ERR_INVALID_ARG. */
+pat_status pat_geometry_set_forward_path(pat_geometry g, int32_t path, void* stream);
 
 /* Workgroup shape of adjoint mode 2 (autotuner hook): waves per workgroup
  * (4, 8 or 16) and lanes per matrix row (16 or 64). Any valid pair gives the

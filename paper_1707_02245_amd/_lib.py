@@ -44,7 +44,8 @@ class GeometryInfo(C.Structure):
         ("fwd_lanes_log2", C.c_int32), ("adj_tile", C.c_int32), ("adj_det_group", C.c_int32),
         ("adj_mode", C.c_int32), ("csr_nnz", C.c_int64), ("csr_tile_side", C.c_int32),
         ("csr_win_max", C.c_int32), ("csr_rot", C.c_int32), ("sym_rot", C.c_int32),
-        ("csr_waves", C.c_int32), ("csr_lanes", C.c_int32),
+        ("csr_waves", C.c_int32), ("csr_lanes", C.c_int32), ("fwd_path", C.c_int32),
+        ("fwd_pairs", C.c_int64),
     ]
 
 
@@ -96,6 +97,7 @@ _SIGS = {
     "pat_geometry_set_adjoint": ([C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
     "pat_geometry_set_symmetry": ([C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
     "pat_geometry_set_tiled_launch": ([C.c_void_p, C.c_int32, C.c_int32], C.c_int),
+    "pat_geometry_set_forward_path": ([C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
     "pat_geometry_autotune": ([C.c_void_p, C.c_char_p, C.c_int32, C.c_void_p,
                                C.POINTER(AutotuneResult)], C.c_int),
     "pat_forward": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),

@@ -21,6 +21,7 @@
 #include <cstring>
 #include <memory>
 #include <new>
+#include <thread>
 
 #include "pat_internal.hpp"
 
@@ -276,6 +277,82 @@ void pat_geometry_s::upload(hipStream_t stream) {
   PAT_HIP(hipStreamSynchronize(stream));
 }
 
+// Pairs of the LDS-tiled forward. Cell (cx, cy) = (ix + 1, iy + 1) of a
+// sample at grid position (gx, gy), ix = floor(gx), reads padded-image pixels
+// cx..cx+1, cy..cy+1; cells in [0, nx] x [0, ny] can carry weight. Tile
+// (tx, ty) holds cells [tx TS, tx TS + TS) x [ty TS, ty TS + TS), i.e. the
+// samples with gx in [tx TS - 1, tx TS + TS - 1) (likewise y). For every bin
+// and tile the conservative sample ranges of the circle inside that box
+// (circle_box_ranges) become pairs; the kernel keeps the samples whose cell
+// is in the tile, so every sample counts in exactly one tile.
+void pat_geometry_s::ensure_fwd_tiles(hipStream_t stream) {
+  if (fwd_n_pairs >= 0) return;
+  const int TS = pat::kFwdTile;
+  const int ntx = (nx + 1 + TS - 1) / TS, nty = (ny + 1 + TS - 1) / TS, ntiles = ntx * nty;
+  std::vector<std::vector<int4>> per_tile(ntiles);
+  auto work = [&](int t0, int t1) {
+    for (int t = t0; t < t1; ++t) {
+      const int tx = t % ntx, ty = t / ntx;
+      const double x0 = tx * TS - 1.0, x1 = std::min(tx * TS + TS, nx + 1) - 1.0;
+      const double y0 = ty * TS - 1.0, y1 = std::min(ty * TS + TS, ny + 1) - 1.0;
+      std::vector<int4>& out = per_tile[t];
+      for (int d = 0; d < n_det; ++d) {
+        const double cx = (det_xy[2 * d] - desc.x_min) / h - 0.5;
+        const double cy = (det_xy[2 * d + 1] - desc.y_min) / h - 0.5;
+        for (int k = 0; k < n_t; ++k) {
+          Range rg[4];
+          const int n = pat::circle_box_ranges(cx, cy, radius[k] / h, M[k], x0, x1, y0, y1, rg);
+          for (int j = 0; j < n; ++j) out.push_back(make_int4(d * n_t + k, rg[j].a, rg[j].b, 0));
+        }
+      }
+    }
+  };
+  const int nthr = std::max(1, std::min(8, ntiles));
+  std::vector<std::thread> th;
+  for (int w = 0; w < nthr; ++w) th.emplace_back(work, (int)((int64_t)ntiles * w / nthr), (int)((int64_t)ntiles * (w + 1) / nthr));
+  for (auto& x : th) x.join();
+  // longest pairs first within a tile, so that the pairs a group of lanes
+  // works on together have similar lengths (ties keep bin order)
+  for (auto& v : per_tile)
+    std::stable_sort(v.begin(), v.end(), [](const int4& p, const int4& q) { return p.z - p.y > q.z - q.y; });
+  // partial slots bin-major (each bin's pairs in tile order), workgroups of
+  // up to kFwdChunk pairs of one tile
+  const int64_t nb = n_bins();
+  std::vector<int> bin_off(nb + 1, 0);
+  int64_t np = 0;
+  for (const auto& v : per_tile) {
+    np += (int64_t)v.size();
+    for (const int4& p : v) ++bin_off[p.x + 1];
+  }
+  PAT_CHECK_ARG(np < (int64_t(1) << 31), "too many forward tile pairs");
+  for (int64_t b = 0; b < nb; ++b) bin_off[b + 1] += bin_off[b];
+  std::vector<int> fill(bin_off.begin(), bin_off.end() - 1);
+  std::vector<int4> pairs;
+  pairs.reserve(np);
+  std::vector<int4> blocks;
+  for (int t = 0; t < ntiles; ++t) {
+    const int p0 = (int)pairs.size();
+    for (int4 p : per_tile[t]) {
+      p.w = fill[p.x]++;
+      pairs.push_back(p);
+    }
+    const int p1 = (int)pairs.size();
+    for (int c = p0; c < p1; c += pat::kFwdChunk)
+      blocks.push_back(make_int4((t % ntx) * TS, (t / ntx) * TS, c, std::min(p1, c + pat::kFwdChunk)));
+  }
+  fwd_pair.alloc(sizeof(int4) * std::max<int64_t>(np, 1));
+  fwd_block.alloc(sizeof(int4) * std::max<size_t>(blocks.size(), 1));
+  fwd_bin_off.alloc(sizeof(int) * (nb + 1));
+  if (np > 0)
+    PAT_HIP(hipMemcpyAsync(fwd_pair.p, pairs.data(), sizeof(int4) * np, hipMemcpyHostToDevice, stream));
+  if (!blocks.empty())
+    PAT_HIP(hipMemcpyAsync(fwd_block.p, blocks.data(), sizeof(int4) * blocks.size(), hipMemcpyHostToDevice, stream));
+  PAT_HIP(hipMemcpyAsync(fwd_bin_off.p, bin_off.data(), sizeof(int) * (nb + 1), hipMemcpyHostToDevice, stream));
+  PAT_HIP(hipStreamSynchronize(stream));
+  fwd_n_pairs = np;
+  fwd_n_blocks = (int)blocks.size();
+}
+
 void pat_geometry_s::set_launch(int lanes_log2_, int tile_, int det_group_) {
   PAT_CHECK_ARG(lanes_log2_ >= 4 && lanes_log2_ <= 6, "forward lanes per bin must be 16, 32 or 64");
   PAT_CHECK_ARG(tile_ == 16 || tile_ == 32 || tile_ == 64, "adjoint tile must be 16, 32 or 64");
@@ -354,6 +431,8 @@ extern "C" pat_status pat_geometry_get_info(pat_geometry g, pat_geometry_info* o
     out->sym_rot = g->sym_rot;
     out->csr_waves = g->csr_waves;
     out->csr_lanes = g->csr_lanes;
+    out->fwd_path = g->fwd_path;
+    out->fwd_pairs = g->fwd_n_pairs;
     return PAT_OK;
   });
 }
@@ -373,6 +452,16 @@ extern "C" pat_status pat_geometry_set_adjoint(pat_geometry g, int32_t mode, voi
     PAT_CHECK_ARG(mode >= 0 && mode <= 2, "adjoint mode must be 0 (scatter), 1 (CSR) or 2 (tiled CSR)");
     if (mode != 0) g->ensure_csr(static_cast<hipStream_t>(stream));
     g->adj_mode = mode;
+    return PAT_OK;
+  });
+}
+
+extern "C" pat_status pat_geometry_set_forward_path(pat_geometry g, int32_t path, void* stream) {
+  return guarded([&]() -> pat_status {
+    PAT_CHECK_ARG(g != nullptr, "geometry is NULL");
+    PAT_CHECK_ARG(path >= 0 && path <= 2, "forward path must be 0, 1 or 2");
+    if (path == 2) g->ensure_fwd_tiles(static_cast<hipStream_t>(stream));
+    g->fwd_path = path;
     return PAT_OK;
   });
 }

@@ -184,6 +184,11 @@ struct GeomDev {
   const int4* win;       // [n_bins][2]: four sample ranges [m0,m1) per bin
   double kscale, koff;   // radius index of a radius rho in pixel units: rho*kscale - koff
   int lanes_log2;        // forward: lanes per bin, log2 (4..6)
+  int fwd_path;          // forward: 0/1 gather (radius-/detector-major), 2 LDS tiles
+  const int4* fpair;     // path 2: pairs {bin, m0, m1, partial slot}
+  const int4* fblock;    // path 2: workgroups {cell x0, cell y0, pair0, pair1}
+  const int* fbin_off;   // path 2: [n_bins + 1] partial offsets per bin
+  int n_fblocks;         // path 2: workgroups
   int tile;              // adjoint: tile edge in pixels
   int tiles_x, tiles_y;
   int det_group;         // adjoint: detectors per workgroup
@@ -209,6 +214,7 @@ struct FwdArgs {
   const T* q;         // GAP: dual variable for F*
   double* red;        // GAP: partial sums [GAP_NSLOTS][red_stride]
   int red_stride;
+  T* part;            // path 2: partial sums [pairs]
 };
 
 // Adjoint projection of one instance into per-detector-group partial images.

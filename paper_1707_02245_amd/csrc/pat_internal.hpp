@@ -17,6 +17,13 @@ struct pat_geometry_s {
   pat::DevBuf d_det, d_rad, d_moff, d_cs, d_win;
   // launch parameters
   int lanes_log2 = 6, tile = 32, det_group = 16;
+  int fwd_path = 0;  // forward path: 0/1 gather (see fwd_grid), 2 LDS tiles
+  // LDS-tiled forward (path 2): pairs {bin, m0, m1, partial slot} in tile
+  // order, workgroup descriptors {cell x0, cell y0, first pair, end pair},
+  // per-bin offsets of the partial sums (bin-major)
+  pat::DevBuf fwd_pair, fwd_block, fwd_bin_off, scratch_fpart;
+  int64_t fwd_n_pairs = -1;  // -1: not built
+  int fwd_n_blocks = 0;
   // adjoint: 0 = tile scatter (matrix-free), 1 = stored CSR of A^T,
   // 2 = stored CSR with the input windows of pixel tiles staged in LDS
   int adj_mode = 2;
@@ -43,6 +50,7 @@ struct pat_geometry_s {
   void default_launch();
   pat::GeomDev dev() const;
   void ensure_csr(hipStream_t s);
+  void ensure_fwd_tiles(hipStream_t s);
   int n_csr_tiles() const { return csr_tiles_x * csr_tiles_y; }
   int csr_det() const { return n_det / csr_rot; }  // detectors in the stored A^T
   void drop_csr();
@@ -74,11 +82,19 @@ enum FwdMode { FWD_PLAIN = 0, FWD_DUAL = 1, FWD_GAP = 2, FWD_ROWSUM = 3 };
 
 constexpr int kThreads = 256;
 
-// Forward grid: radius-major, one block per (radius, group of 256/lanes detectors).
-inline int fwd_grid(int n_det, int n_t, int lanes_log2) {
+// Forward grid (the blocks whose epilogue writes bins and gap sums): paths 0
+// and 1 gather with one block per group of 256/lanes bins, path 0 (radius-
+// major) grouping detectors of one radius, path 1 (detector-major) radii of
+// one detector; path 2 sums partials with one thread per bin.
+inline int fwd_grid(int n_det, int n_t, int lanes_log2, int path) {
   const int bpb = kThreads >> lanes_log2;
-  return ((n_det + bpb - 1) / bpb) * n_t;
+  if (path == 2) return (int)(((int64_t)n_det * n_t + kThreads - 1) / kThreads);
+  return path == 1 ? n_det * ((n_t + bpb - 1) / bpb) : ((n_det + bpb - 1) / bpb) * n_t;
 }
+// LDS-tiled forward: tile side in cells, pairs and threads per workgroup
+constexpr int kFwdTile = 64;
+constexpr int kFwdChunk = 256;
+constexpr int kFwdTileThreads = 256;
 inline int pix_blocks(int64_t n) { return (int)((n + kThreads - 1) / kThreads); }
 
 // Batched launch tables: args arrays and instance block offsets on the device.
@@ -95,6 +111,11 @@ struct Launch {
   size_t csr_shm = 0;      // its dynamic LDS per workgroup
   int csr_waves = 4;       // its waves per workgroup
   int csr_lanes = 16;      // its lanes per row
+  // LDS-tiled forward for every instance: gather blocks (per-instance
+  // workgroup descriptors) before the per-bin sums
+  bool fwd_tiled = false;
+  DevBuf fwdt_start;
+  int fwdt_total = 0;
   int lanes_log2 = 6;   // shared by every instance of one launch
   int max_tile = 32;    // shared by every instance of one launch
 };
@@ -106,6 +127,8 @@ template <class T>
 void launch_forward(int mode, const FwdArgs<T>& a, int lanes_log2, hipStream_t s);
 template <class T>
 void launch_forward_batched(int mode, const Launch<T>& L, int lanes_log2, hipStream_t s);
+template <class T>
+void attach_fwd_part(pat_geometry_s* g, FwdArgs<T>& a);
 template <class T>
 void launch_adjoint(const AdjArgs<T>& a, hipStream_t s);
 template <class T>

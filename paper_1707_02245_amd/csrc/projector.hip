@@ -76,6 +76,42 @@ void launch_pad(const T* u, T* upad, int nx, int ny, hipStream_t s) {
 
 // ------------------------------------------------------------------ forward
 
+// The value val = (A x)_b of bin b, computed by this thread (writer), goes
+// to its destination: the data (PLAIN), the dual data step of PDHGM (DUAL),
+// the reciprocal row sum (ROWSUM) or the block's gap sums (GAP: every thread
+// of the block takes part in the reduction).
+template <class T, int MODE>
+__device__ __forceinline__ void fwd_epilogue(const FwdArgs<T>& a, int blk, bool writer, int64_t b, T val) {
+  if (MODE == FWD_GAP) {
+    __shared__ double lds[8];
+    double d_data = 0.0, d_fs = 0.0;
+    if (writer) {
+      const double res = (double)val - (double)a.f[b];
+      const double qb = (double)a.q[b];
+      d_data = 0.5 * res * res;
+      d_fs = 0.5 * qb * qb + qb * (double)a.f[b];
+    }
+    const double s0 = block_sum<256>(d_data, lds);
+    const double s1 = block_sum<256>(d_fs, lds);
+    if (threadIdx.x == 0) {
+      a.red[GAP_DATA * (int64_t)a.red_stride + blk] = s0;
+      a.red[GAP_FSTAR * (int64_t)a.red_stride + blk] = s1;
+    }
+    return;
+  }
+  if (!writer) return;
+  if (MODE == FWD_PLAIN) {
+    a.out[b] = val;
+  } else if (MODE == FWD_DUAL) {
+    // q <- prox_{sigma F1*}(q + sigma A ubar) = (q + sigma (A ubar - f)) / (1 + sigma)
+    const T sg = a.sigma[b];
+    a.out[b] = (a.out[b] + sg * (val - a.f[b])) / (T(1) + sg);
+  } else if (MODE == FWD_ROWSUM) {
+    // A >= 0, so the absolute row sum is A 1; empty rows get sigma = 1
+    a.out[b] = val > T(0) ? T(1) / val : T(1);
+  }
+}
+
 template <class T, int MODE, int LANES>
 __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T>* __restrict__ arr,
                                                   const int* __restrict__ starts, int n_inst) {
@@ -91,11 +127,20 @@ __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T
   const GeomDev& g = a.g;
   constexpr int BPB = 256 / LANES;
   const int sub = threadIdx.x / LANES, lane = threadIdx.x % LANES;
-  // radius-major order: consecutive blocks take the same radius for successive
-  // detector groups, so a radius' (cos, sin) table is reused from L2
-  const int n_dg = (g.n_det + BPB - 1) / BPB;
-  const int k = blk / n_dg;
-  const int d = (blk - k * n_dg) * BPB + sub;
+  // radius-major order: a block takes one radius for BPB detectors (the
+  // radius' (cos, sin) table is shared); detector-major: BPB consecutive
+  // radii of one detector, concentric arcs whose samples at similar angles
+  // share cache lines
+  int k, d;
+  if (g.fwd_path == 1) {
+    const int n_kg = (g.n_t + BPB - 1) / BPB;
+    d = blk / n_kg;
+    k = (blk - d * n_kg) * BPB + sub;
+  } else {
+    const int n_dg = (g.n_det + BPB - 1) / BPB;
+    k = blk / n_dg;
+    d = (blk - k * n_dg) * BPB + sub;
+  }
   const bool valid = d < g.n_det && k < g.n_t;
   const int b = d * g.n_t + k;
   T acc = T(0);
@@ -146,35 +191,115 @@ __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T
     }
   }
   acc = group_sum<LANES>(acc);
-  const T val = acc * (T)inv_m;
-  if (MODE == FWD_GAP) {
-    __shared__ double lds[8];
-    double d_data = 0.0, d_fs = 0.0;
-    if (valid && lane == 0) {
-      const double res = (double)val - (double)a.f[b];
-      const double qb = (double)a.q[b];
-      d_data = 0.5 * res * res;
-      d_fs = 0.5 * qb * qb + qb * (double)a.f[b];
-    }
-    const double s0 = block_sum<256>(d_data, lds);
-    const double s1 = block_sum<256>(d_fs, lds);
-    if (threadIdx.x == 0) {
-      a.red[GAP_DATA * (int64_t)a.red_stride + blk] = s0;
-      a.red[GAP_FSTAR * (int64_t)a.red_stride + blk] = s1;
-    }
-    return;
+  fwd_epilogue<T, MODE>(a, blk, valid && lane == 0, b, acc * (T)inv_m);
+}
+
+// LDS-tiled forward, gather pass: a workgroup stages tile cells [x0, x0 +
+// TS] x [y0, y0 + TS] of the padded image in LDS and sums, 16 lanes per pair,
+// the samples of its pairs whose cell lies in the tile; each pair's sum goes
+// to its partial slot. A group of 16 lanes works on four pairs at once (their
+// record, detector, radius and table loads issue together) so that the short
+// per-pair chains of dependent loads overlap.
+template <class T, int NT>
+__global__ __launch_bounds__(NT) void fwd_tiled_kernel(FwdArgs<T> a0, const FwdArgs<T>* __restrict__ arr,
+                                                       const int* __restrict__ starts, int n_inst) {
+  constexpr int TS = kFwdTile, W = TS + 1, NG = NT / 16, J = 4;
+  __shared__ T tile[W * W];
+  int blk = blockIdx.x;
+  const FwdArgs<T>* ap = &a0;
+  if (arr) {
+    const int i = find_inst(starts, n_inst, blk);
+    ap = arr + i;
+    blk -= starts[i];
   }
-  if (!valid || lane != 0) return;
-  if (MODE == FWD_PLAIN) {
-    a.out[b] = val;
-  } else if (MODE == FWD_DUAL) {
-    // q <- prox_{sigma F1*}(q + sigma A ubar) = (q + sigma (A ubar - f)) / (1 + sigma)
-    const T sg = a.sigma[b];
-    a.out[b] = (a.out[b] + sg * (val - a.f[b])) / (T(1) + sg);
-  } else if (MODE == FWD_ROWSUM) {
-    // A >= 0, so the absolute row sum is A 1; empty rows get sigma = 1
-    a.out[b] = val > T(0) ? T(1) / val : T(1);
+  const FwdArgs<T>& a = *ap;
+  const GeomDev& g = a.g;
+  const int4 bd = g.fblock[blk];
+  const int x0 = bd.x, y0 = bd.y;
+  const int P = g.pitch, PR = g.ny + 2;
+  const gptr<const T> up = as_global(a.upad);
+  for (int i = threadIdx.x; i < W * W; i += NT) {
+    const int r = i / W, c = i - r * W;
+    const int px = x0 + c, py = y0 + r;
+    tile[i] = (px < P && py < PR) ? up[(int64_t)py * P + px] : T(0);
   }
+  __syncthreads();
+  const int grp = threadIdx.x >> 4, gl = threadIdx.x & 15;
+  const int4* __restrict__ pairs = g.fpair;
+  for (int q0 = bd.z + grp; q0 < bd.w; q0 += J * NG) {
+    int m0[J], len[J], slot[J], toff[J];
+    double2 p[J];
+    double rho[J];
+    int bins[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int q = q0 + j * NG;
+      int4 pr = make_int4(0, 0, 0, -1);
+      if (q < bd.w) pr = pairs[q];
+      bins[j] = pr.x;
+      m0[j] = pr.y;
+      len[j] = pr.z - pr.y;
+      slot[j] = pr.w;
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int d = bins[j] / g.n_t, k = bins[j] - d * g.n_t;
+      p[j] = g.det[d];
+      rho[j] = g.rad[k].x;
+      toff[j] = g.moff[k].y + m0[j];
+    }
+    const int cnt = max(max(len[0], len[1]), max(len[2], len[3]));
+    T acc[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) acc[j] = T(0);
+    for (int s = gl; s < cnt; s += 16) {
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const bool live = s < len[j];
+        const Sample sm = arc_sample(p[j], rho[j], table_cs<T>(g, live ? toff[j] + s : 0));
+        const int cx = sm.ix + 1 - x0, cy = sm.iy + 1 - y0;
+        const bool in = live & ((unsigned)cx < (unsigned)TS) & ((unsigned)cy < (unsigned)TS);
+        const int o = in ? cy * W + cx : 0;
+        const T tx = (T)sm.tx, ty = (T)sm.ty;
+        const T q00 = tile[o], q10 = tile[o + 1], q01 = tile[o + W], q11 = tile[o + W + 1];
+        const T lo = fma(tx, q10 - q00, q00);
+        const T hi = fma(tx, q11 - q01, q01);
+        acc[j] += in ? fma(ty, hi - lo, lo) : T(0);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const T sum = row16_sum(acc[j]);
+      if (gl == 0 && slot[j] >= 0) a.part[slot[j]] = sum;
+    }
+  }
+}
+
+// LDS-tiled forward, per-bin pass: the bin's partial sums in slot order,
+// times 1/M_k, into the epilogue.
+template <class T, int MODE>
+__global__ __launch_bounds__(256) void fwd_reduce_kernel(FwdArgs<T> a0, const FwdArgs<T>* __restrict__ arr,
+                                                         const int* __restrict__ starts, int n_inst) {
+  int blk = blockIdx.x;
+  const FwdArgs<T>* ap = &a0;
+  if (arr) {
+    const int i = find_inst(starts, n_inst, blk);
+    ap = arr + i;
+    blk -= starts[i];
+  }
+  const FwdArgs<T>& a = *ap;
+  const GeomDev& g = a.g;
+  const int64_t nb = (int64_t)g.n_det * g.n_t;
+  const int64_t b = (int64_t)blk * 256 + threadIdx.x;
+  const bool valid = b < nb;
+  T val = T(0);
+  if (valid) {
+    T acc = T(0);
+    const int s1 = g.fbin_off[b + 1];
+    for (int s = g.fbin_off[b]; s < s1; ++s) acc += a.part[s];
+    val = acc * (T)g.rad[b % g.n_t].y;
+  }
+  fwd_epilogue<T, MODE>(a, blk, valid, b, val);
 }
 
 template <class T, int MODE>
@@ -201,14 +326,44 @@ static void fwd_mode_dispatch(int mode, int lanes_log2, int blocks, const FwdArg
 }
 
 template <class T>
+static void reduce_mode_dispatch(int mode, int blocks, const FwdArgs<T>& a0, const FwdArgs<T>* arr,
+                                 const int* starts, int n, hipStream_t s) {
+  if (blocks <= 0) return;
+  switch (mode) {
+    case FWD_PLAIN: hipLaunchKernelGGL((fwd_reduce_kernel<T, FWD_PLAIN>), dim3(blocks), dim3(256), 0, s, a0, arr, starts, n); break;
+    case FWD_DUAL: hipLaunchKernelGGL((fwd_reduce_kernel<T, FWD_DUAL>), dim3(blocks), dim3(256), 0, s, a0, arr, starts, n); break;
+    case FWD_GAP: hipLaunchKernelGGL((fwd_reduce_kernel<T, FWD_GAP>), dim3(blocks), dim3(256), 0, s, a0, arr, starts, n); break;
+    default: hipLaunchKernelGGL((fwd_reduce_kernel<T, FWD_ROWSUM>), dim3(blocks), dim3(256), 0, s, a0, arr, starts, n); break;
+  }
+  PAT_HIP(hipGetLastError());
+}
+
+template <class T>
 void launch_forward(int mode, const FwdArgs<T>& a, int lanes_log2, hipStream_t s) {
-  const int blocks = fwd_grid(a.g.n_det, a.g.n_t, lanes_log2);
+  const int blocks = fwd_grid(a.g.n_det, a.g.n_t, lanes_log2, a.g.fwd_path);
+  if (a.g.fwd_path == 2) {
+    PAT_CHECK_ARG(a.g.fpair != nullptr && a.part != nullptr, "tiled forward without its tables");
+    if (a.g.n_fblocks > 0)
+      hipLaunchKernelGGL((fwd_tiled_kernel<T, kFwdTileThreads>), dim3(a.g.n_fblocks), dim3(kFwdTileThreads), 0, s, a,
+                         (const FwdArgs<T>*)nullptr, (const int*)nullptr, 1);
+    PAT_HIP(hipGetLastError());
+    reduce_mode_dispatch<T>(mode, blocks, a, nullptr, nullptr, 1, s);
+    return;
+  }
   fwd_mode_dispatch<T>(mode, lanes_log2, blocks, a, nullptr, nullptr, 1, s);
 }
 
 template <class T>
 void launch_forward_batched(int mode, const Launch<T>& L, int lanes_log2, hipStream_t s) {
   FwdArgs<T> dummy{};
+  if (L.fwd_tiled) {
+    if (L.fwdt_total > 0)
+      hipLaunchKernelGGL((fwd_tiled_kernel<T, kFwdTileThreads>), dim3(L.fwdt_total), dim3(kFwdTileThreads), 0, s, dummy,
+                         ptr<FwdArgs<T>>(L.fwd), ptr<int>(L.fwdt_start), L.n);
+    PAT_HIP(hipGetLastError());
+    reduce_mode_dispatch<T>(mode, L.fwd_total, dummy, ptr<FwdArgs<T>>(L.fwd), ptr<int>(L.fwd_start), L.n, s);
+    return;
+  }
   fwd_mode_dispatch<T>(mode, lanes_log2, L.fwd_total, dummy, ptr<FwdArgs<T>>(L.fwd),
                        ptr<int>(L.fwd_start), L.n, s);
 }
@@ -393,6 +548,11 @@ pat::GeomDev pat_geometry_s::dev() const {
   g.kscale = h / (desc.c * desc.dt);
   g.koff = desc.t0 / desc.dt;
   g.lanes_log2 = lanes_log2;
+  g.fwd_path = fwd_path;
+  g.fpair = fwd_n_pairs >= 0 ? pat::ptr<int4>(fwd_pair) : nullptr;
+  g.fblock = fwd_n_pairs >= 0 ? pat::ptr<int4>(fwd_block) : nullptr;
+  g.fbin_off = fwd_n_pairs >= 0 ? pat::ptr<int>(fwd_bin_off) : nullptr;
+  g.n_fblocks = fwd_n_blocks;
   g.tile = (dtype == PAT_F64 && tile == 64) ? 32 : tile;
   g.tiles_x = (nx + g.tile - 1) / g.tile;
   g.tiles_y = (ny + g.tile - 1) / g.tile;
@@ -431,8 +591,25 @@ void forward_impl(pat_geometry g, const void* d_u, void* d_f, hipStream_t s) {
   a.g = g->dev();
   a.upad = upad;
   a.out = static_cast<T*>(d_f);
+  pat::attach_fwd_part<T>(g, a);
   pat::launch_forward<T>(pat::FWD_PLAIN, a, g->lanes_log2, s);
 }
+
+}  // namespace
+
+namespace pat {
+// Partial-sum scratch of the tiled forward (path 2) for stand-alone applies.
+template <class T>
+void attach_fwd_part(pat_geometry g, FwdArgs<T>& a) {
+  if (g->fwd_path != 2) return;
+  g->scratch_fpart.ensure(sizeof(T) * (size_t)std::max<int64_t>(g->fwd_n_pairs, 1));
+  a.part = ptr<T>(g->scratch_fpart);
+}
+template void attach_fwd_part<float>(pat_geometry, FwdArgs<float>&);
+template void attach_fwd_part<double>(pat_geometry, FwdArgs<double>&);
+}  // namespace pat
+
+namespace {
 
 template <class T>
 void forward_padded_impl(pat_geometry g, const void* d_upad, void* d_f, hipStream_t s) {
@@ -440,6 +617,7 @@ void forward_padded_impl(pat_geometry g, const void* d_upad, void* d_f, hipStrea
   a.g = g->dev();
   a.upad = static_cast<const T*>(d_upad);
   a.out = static_cast<T*>(d_f);
+  pat::attach_fwd_part<T>(g, a);
   pat::launch_forward<T>(pat::FWD_PLAIN, a, g->lanes_log2, s);
 }
 

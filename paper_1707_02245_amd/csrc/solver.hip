@@ -71,6 +71,7 @@ static void precond_diag(pat_precond_s* pc, const pat_regulariser* reg, const T*
   a.g = g->dev();
   a.upad = ptr<T>(pad);
   a.out = ptr<T>(pc->sigma_q);
+  attach_fwd_part<T>(g, a);
   launch_forward<T>(FWD_ROWSUM, a, g->lanes_log2, s);
   // column sums of A: A^T 1
   apply_adjoint<T>(g, ptr<T>(ones), ptr<T>(colsum), s);
@@ -177,7 +178,7 @@ struct Inst {
   const T* f = nullptr;
   T* u_out = nullptr;
   pat_solve_info* info = nullptr;
-  DevBuf u, ubar_pad, q, r, v, vbar, s, upad_gap, atq_part, atq64, red, dmat;
+  DevBuf u, ubar_pad, q, r, v, vbar, s, upad_gap, atq_part, atq64, red, dmat, fpart;
   pat_precond_s* pc = nullptr;
   std::unique_ptr<pat_precond_s> own_pc;
   int n_fwd = 0, n_pix = 0, n_adj = 0, n_csr = 0, red_stride = 0;
@@ -255,7 +256,11 @@ class Solver {
     I.atq_part.alloc(sizeof(T) * (I.csr ? g->csr_rot : gd.n_groups) * N);
     // FP64-accumulated A^T q for the gap: only FP32 needs a separate pass
     if (I.csr && sizeof(T) == 4) I.atq64.alloc(sizeof(double) * g->csr_rot * N);
-    I.n_fwd = fwd_grid(g->n_det, g->n_t, lanes_log2);
+    // gap partial sums: enough blocks for any forward path (build_launch
+    // picks the path of the batch)
+    I.n_fwd = std::max({fwd_grid(g->n_det, g->n_t, lanes_log2, 0), fwd_grid(g->n_det, g->n_t, lanes_log2, 1),
+                        fwd_grid(g->n_det, g->n_t, lanes_log2, 2)});
+    if (g->fwd_path == 2) I.fpart.alloc(sizeof(T) * (size_t)std::max<int64_t>(g->fwd_n_pairs, 1));
     I.n_pix = pix_blocks(N);
     I.n_adj = I.csr ? 0 : gd.tiles_x * gd.tiles_y * gd.n_groups;
     I.n_csr = I.csr ? (int)((N + 3) / 4) : 0;
@@ -305,6 +310,11 @@ class Solver {
   // Upload the launch tables of the active instances.
   void build_launch() {
     const int n = (int)act.size();
+    // the LDS-tiled forward when every instance's geometry uses it, else the
+    // gather kernel (radius-major for those that chose tiles)
+    bool fwd_tiled = n > 0;
+    for (int k = 0; k < n; ++k) fwd_tiled = fwd_tiled && inst[act[k]]->g->fwd_path == 2 && inst[act[k]]->fpart.p;
+    std::vector<int> ts(n + 1, 0);
     std::vector<FwdArgs<T>> fd(n), fg(n);
     std::vector<AdjArgs<T>> ad;
     std::vector<CsrMultiArgs<T>> cd;
@@ -330,6 +340,11 @@ class Solver {
       fg[k].q = ptr<T>(I.q);
       fg[k].red = ptr<double>(I.red);
       fg[k].red_stride = I.red_stride;
+      const int path = fwd_tiled ? 2 : (I.g->fwd_path == 2 ? 0 : I.g->fwd_path);
+      fd[k].g.fwd_path = fg[k].g.fwd_path = path;
+      fd[k].part = fg[k].part = ptr<T>(I.fpart);
+      const int n_fwd = fwd_grid(I.g->n_det, I.g->n_t, lanes_log2, path);
+      ts[k + 1] = ts[k] + (fwd_tiled ? I.g->fwd_n_blocks : 0);
       if (I.csr) {
         // instances sharing a geometry share one pass over its stored A^T: up
         // to kMaxRhs slots (rot per instance), and for the tiled kernel as
@@ -382,8 +397,8 @@ class Solver {
         as.push_back(as.back() + I.n_adj);
       }
       id[k] = inst_dev(I);
-      gf[k] = GapFinishArgs{ptr<double>(I.red), I.red_stride, I.n_fwd, I.n_pix};
-      fs[k + 1] = fs[k] + I.n_fwd;
+      gf[k] = GapFinishArgs{ptr<double>(I.red), I.red_stride, n_fwd, I.n_pix};
+      fs[k + 1] = fs[k] + n_fwd;
       ps[k + 1] = ps[k] + I.n_pix;
     }
     // CSR groups: the LDS-staged kernel when every group has tiles and the
@@ -424,12 +439,15 @@ class Solver {
     up(L.inst, id.data(), sizeof(InstDev<T>) * n);
     up(L.gapfin, gf.data(), sizeof(GapFinishArgs) * n);
     up(L.fwd_start, fs.data(), sizeof(int) * (n + 1));
+    up(L.fwdt_start, ts.data(), sizeof(int) * (n + 1));
     up(L.adj_start, as.data(), sizeof(int) * as.size());
     up(L.csr_start, cs.data(), sizeof(int) * cs.size());
     up(L.pix_start, ps.data(), sizeof(int) * (n + 1));
     PAT_HIP(hipStreamSynchronize(s));  // host vectors go out of scope
     L.n = n;
     L.fwd_total = fs[n];
+    L.fwd_tiled = fwd_tiled;
+    L.fwdt_total = ts[n];
     L.adj_total = as.back();
     L.n_adj = (int)ad.size();
     L.n_csr = (int)cd.size();

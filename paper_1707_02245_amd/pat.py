@@ -98,6 +98,11 @@ class Geometry:
         L.check(L.load().pat_geometry_set_adjoint(self._h, m, _stream()))
         return self.refresh_info()
 
+    def set_forward_path(self, path):
+        """Forward path: 0/1 gather (radius-/detector-major blocks), 2 LDS tiles."""
+        L.check(L.load().pat_geometry_set_forward_path(self._h, path, _stream()))
+        return self.refresh_info()
+
     def set_tiled_launch(self, waves, row_lanes):
         """Workgroup shape of the tiled adjoint: waves per workgroup (4, 8, 16)
         and lanes per matrix row (16, 64)."""
