@@ -34,7 +34,23 @@ HBM_PEAK_GBS = 8000.0
 # rocprofv3 counter passes, scaled by what the counters read for a plain copy of known
 # size (FETCH x 2, WRITE x 1); profiles/*_hbm_traffic.md. An entry is reported only
 # while the kernel's sources are the ones measured.
-MEASURED_TRAFFIC = []
+_SRC_FWD = {"paper_1707_02245_amd/csrc/projector.hip":
+            "aa572fca3ababe17ba8e52e1e12cf296afa82a299d17e4acc65d9ff2be5696d9",
+            "paper_1707_02245_amd/csrc/pat_common.hpp":
+            "f400c8fb3593a8183f0effb99481bb3ae19d2a625a5716d4bd5c94bd98332ee0"}
+_SRC_ADJ = {"paper_1707_02245_amd/csrc/csr.hip":
+            "0b4705b3cebb390c88ae83f6959bb68a1c720e02597f05fb5002085f7bf1cb34",
+            "paper_1707_02245_amd/csrc/pat_common.hpp":
+            "f400c8fb3593a8183f0effb99481bb3ae19d2a625a5716d4bd5c94bd98332ee0"}
+MEASURED_TRAFFIC = [
+    # profiles/fwd_gather_tgv256_f64_hbm_traffic.md
+    {"kernel": "fwd_kernel<double, 0, 16>", "bytes_per_launch": 34.88e6, "sources": _SRC_FWD},
+    {"kernel": "fwd_kernel<double, 0, 32>", "bytes_per_launch": 28.54e6, "sources": _SRC_FWD},
+    {"kernel": "fwd_kernel<double, 0, 64>", "bytes_per_launch": 42.54e6, "sources": _SRC_FWD},
+    # profiles/csr_tiled_tgv256_f64_hbm_traffic.md
+    {"kernel": "csr_tiled_kernel<double, false, 4, 256, 16>", "bytes_per_launch": 199.78e6, "sources": _SRC_ADJ},
+    {"kernel": "csr_tiled_kernel<double, false, 4, 512, 16>", "bytes_per_launch": 205.40e6, "sources": _SRC_ADJ},
+]
 
 
 def measured_traffic(kernel_name):
@@ -383,7 +399,11 @@ def main():
                     "traffic": measured_traffic(fkname) if (wl.name == "tgv256" and esz == 8) else None,
                     "traffic_unit": "HBM bytes per launch (rocprofv3 counters, copy-calibrated)",
                     "flops_per_launch": fwd_flops, "flops_per_sample": FWD_FLOPS_PER_SAMPLE,
-                    "avg_launch_us": t_fwd * 1e6}
+                    "avg_launch_us": t_fwd * 1e6,
+                    "limiter": ("vector-memory address pipeline, not FP64 arithmetic: rocprofv3 counters "
+                                "(profiles/fwd_gather_tgv256_f64_counters.md) show the texture address and "
+                                "data units busy most of the kernel and about 34 cache lines per wave load, "
+                                "with VALU issue about a third busy")}
     else:
         roofline = {"kernel": akname, "bound": "hbm",
                     "achieved": adj_bytes / t_adj * 1e-9, "peak": HBM_PEAK_GBS,
