@@ -39,7 +39,7 @@ _SRC_FWD = {"paper_1707_02245_amd/csrc/projector.hip":
             "paper_1707_02245_amd/csrc/pat_common.hpp":
             "f400c8fb3593a8183f0effb99481bb3ae19d2a625a5716d4bd5c94bd98332ee0"}
 _SRC_ADJ = {"paper_1707_02245_amd/csrc/csr.hip":
-            "0b4705b3cebb390c88ae83f6959bb68a1c720e02597f05fb5002085f7bf1cb34",
+            "2093e2a6145352ef22eea248fdbb763e4a1f69922986fcf57e7d740bbace044a",
             "paper_1707_02245_amd/csrc/pat_common.hpp":
             "f400c8fb3593a8183f0effb99481bb3ae19d2a625a5716d4bd5c94bd98332ee0"}
 MEASURED_TRAFFIC = [

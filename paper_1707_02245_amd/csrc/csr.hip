@@ -446,11 +446,12 @@ void launch_csr_spmv_batched(const CsrArgs<T>* arr, const int* starts, int n_ins
 }
 
 // One block per pixel tile (NT / 64 waves): stage the tile's input windows of
-// every slot in LDS, then one wave per row as in the plain kernel with the
-// gathers served by LDS. Rows outside the image (ragged tiles) are skipped.
-// Large staged windows leave room for one workgroup per CU, so those
-// workgroups carry 16 waves instead of 4 to keep enough loads in flight; the
-// waves of a workgroup share one copy of the windows.
+// every slot in LDS, then LPR lanes per matrix row with the gathers served by
+// LDS. Rows outside the image (ragged tiles) store nothing. The workgroup size
+// (4, 8 or 16 waves) and LPR are launch choices (the autotuner's): large
+// staged windows leave room for one workgroup per CU, where 16 waves keep
+// enough loads in flight; the waves of a workgroup share one copy of the
+// windows.
 template <class T, bool WIDE, int R, int NT, int LPR>
 __global__ __launch_bounds__(NT) void csr_tiled_kernel(CsrMultiArgs<T> a0, const CsrMultiArgs<T>* __restrict__ arr,
                                                        const int* __restrict__ starts, int n_grp) {

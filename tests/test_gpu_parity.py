@@ -281,13 +281,21 @@ def test_quarter_turn_storage(shape, dt):
         g.set_adjoint(adj)
         out[adj] = host(g.adjoint(yd))
         assert rel(out[adj], ref) <= TOL_APPLY[dt], adj
-    # the partial images sum (in order) to the adjoint, bit for bit
-    parts = g.adjoint_partials(yd)
-    assert tuple(parts.shape) == (4, n, n)
-    acc = torch.zeros_like(parts[0])
-    for r in range(4):
-        acc = acc + parts[r]
-    assert np.array_equal(host(acc), out["csr"])
+    # the partial images sum (in order) to the adjoint, bit for bit, in both
+    # stored modes; partial r holds the data of detectors r n_det/4 ..
+    for adj in ("tiled", "csr"):
+        g.set_adjoint(adj)
+        parts = g.adjoint_partials(yd)
+        assert tuple(parts.shape) == (4, n, n)
+        acc = torch.zeros_like(parts[0])
+        for r in range(4):
+            acc = acc + parts[r]
+        assert np.array_equal(host(acc), out[adj]), adj
+        q = n_det // 4
+        for r in (0, 3):
+            yr = np.zeros_like(y).reshape(n_det, n_t)
+            yr[r * q:(r + 1) * q] = y.reshape(n_det, n_t)[r * q:(r + 1) * q]
+            assert rel(host(parts[r]), A.T @ yr.ravel()) <= TOL_APPLY[dt], (adj, r)
     g.set_symmetry(False)
     assert (g.info["sym_rot"], g.info["csr_rot"], g.info["csr_nnz"]) == (4, 1, A.nnz)
     for adj in ("tiled", "csr"):
