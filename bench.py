@@ -221,8 +221,8 @@ WEIGHTS = os.path.join(ROOT, "paper_1707_02245_amd", "weights", "warmstart_tv256
 def learned_leg(pat, torch, g, args):
     """The 256^2 TV warm-start workload (lambda 0.02, geometry of the TGV
     workload, mixed phantom families, noise U(1%, 10%)): FP64 time to rel_gap
-    1e-4 from zero and from the trained network's start (inference included),
-    on held-out seeds."""
+    1e-4 from zero, from the backprojection A^T f / A^T 1 and from the trained
+    network's start (inference included), on held-out seeds."""
     import phantoms
     from paper_1707_02245_amd import warmstart as W
     wl = phantoms.WORKLOADS["tv256"]
@@ -236,15 +236,19 @@ def learned_leg(pat, torch, g, args):
     f0, _, _ = W.synth_data(desc, seeds[0], dtype=g.dtype)
     net.infer(g, f0, reg, dual=True)
     res = W.evaluate(g, desc, net, seeds, wl.lam, wl.gap_tol, args.cap,
-                     starts=("zero", "network"))
+                     starts=("zero", "backprojection", "network"))
     z = [r["zero"] for r in res]
+    b = [r["backprojection"] for r in res]
     n = [r["network"] for r in res]
     t_z = sum(r["seconds"] for r in z)
+    t_b = sum(r["seconds"] for r in b)
     t_n = sum(r["seconds"] for r in n)
     return dict(workload="tv256: 256x256 TV (lambda 0.02), geometry of tgv256, FP64, rel_gap 1e-4",
-                seeds=seeds, zero_s=t_z / len(z), network_s=t_n / len(n),
-                zero_iters=[r["iters"] for r in z], network_iters=[r["iters"] for r in n],
-                fallbacks=sum(r["fallback"] for r in n), speedup=t_z / t_n)
+                seeds=seeds, zero_s=t_z / len(z), backprojection_s=t_b / len(b), network_s=t_n / len(n),
+                zero_iters=[r["iters"] for r in z], backprojection_iters=[r["iters"] for r in b],
+                network_iters=[r["iters"] for r in n],
+                fallbacks=sum(r["fallback"] for r in n), speedup=t_z / t_n,
+                speedup_vs_backprojection=t_b / t_n)
 
 
 def cpu_baseline(desc, f, wl, gpu_iters, budget_s=20.0):
