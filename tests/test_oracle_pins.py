@@ -207,6 +207,27 @@ def test_quarter_turn_equivariance(n, n_det, n_t):
     assert np.abs(fr2 - np.roll(f2, n_det // 4, axis=0)).max() > 1e-4 * np.abs(f2).max()
 
 
+@pytest.mark.parametrize("n,n_det,n_t", [(24, 8, 40), (17, 16, 33)])
+def test_mirror_equivariance(n, n_det, n_t):
+    """Detectors at angles 2 pi d / n_det from angle 0: mirroring the image
+    across the horizontal centre line (row j -> n-1-j) moves the data of
+    detector d to detector n_det - d (every circle's samples at angles
+    2 pi (m + 1/2) / M_k are mirror symmetric, m -> M_k - 1 - m). A ring
+    started half a spacing off has no such pairing."""
+    g = _geom(n, n_det, n_t)
+    A = G.forward_matrix(g)
+    u = np.random.default_rng(10).standard_normal((n, n))
+    f = (A @ u.ravel()).reshape(n_det, n_t)
+    fm = (A @ u[::-1].ravel()).reshape(n_det, n_t)
+    idx = (n_det - np.arange(n_det)) % n_det
+    assert np.abs(fm[idx] - f).max() <= 1e-13 * np.abs(f).max()
+    g2 = _geom(n, n_det, n_t, arc_center=math.pi / (2 * n_det))
+    A2 = G.forward_matrix(g2)
+    f2 = (A2 @ u.ravel()).reshape(n_det, n_t)
+    fm2 = (A2 @ u[::-1].ravel()).reshape(n_det, n_t)
+    assert np.abs(fm2[idx] - f2).max() > 1e-3 * np.abs(f2).max()
+
+
 # ---------------------------------------------------------------- regulariser operators
 
 def test_grad_norm_closed_form():
