@@ -35,21 +35,21 @@ HBM_PEAK_GBS = 8000.0
 # size (FETCH x 2, WRITE x 1); profiles/*_hbm_traffic.md. An entry is reported only
 # while the kernel's sources are the ones measured.
 _SRC_FWD = {"paper_1707_02245_amd/csrc/projector.hip":
-            "aa572fca3ababe17ba8e52e1e12cf296afa82a299d17e4acc65d9ff2be5696d9",
+            "e17f2ed6c639c836939b2245a5eae95fd63845ddade831cfb18c7f529b2a8cbd",
             "paper_1707_02245_amd/csrc/pat_common.hpp":
             "f400c8fb3593a8183f0effb99481bb3ae19d2a625a5716d4bd5c94bd98332ee0"}
 _SRC_ADJ = {"paper_1707_02245_amd/csrc/csr.hip":
-            "2093e2a6145352ef22eea248fdbb763e4a1f69922986fcf57e7d740bbace044a",
+            "9504a1198ed465a2988b12f56c4427214dbb8462d7eec20dfa7442d264d15fc8",
             "paper_1707_02245_amd/csrc/pat_common.hpp":
             "f400c8fb3593a8183f0effb99481bb3ae19d2a625a5716d4bd5c94bd98332ee0"}
 MEASURED_TRAFFIC = [
     # profiles/fwd_gather_tgv256_f64_hbm_traffic.md
-    {"kernel": "fwd_kernel<double, 0, 16>", "bytes_per_launch": 34.88e6, "sources": _SRC_FWD},
-    {"kernel": "fwd_kernel<double, 0, 32>", "bytes_per_launch": 28.54e6, "sources": _SRC_FWD},
-    {"kernel": "fwd_kernel<double, 0, 64>", "bytes_per_launch": 42.54e6, "sources": _SRC_FWD},
+    {"kernel": "fwd_kernel<double, 0, 16>", "bytes_per_launch": 40.42e6, "sources": _SRC_FWD},
+    {"kernel": "fwd_kernel<double, 0, 32>", "bytes_per_launch": 39.41e6, "sources": _SRC_FWD},
+    {"kernel": "fwd_kernel<double, 0, 64>", "bytes_per_launch": 42.55e6, "sources": _SRC_FWD},
     # profiles/csr_tiled_tgv256_f64_hbm_traffic.md
-    {"kernel": "csr_tiled_kernel<double, false, 4, 256, 16>", "bytes_per_launch": 199.78e6, "sources": _SRC_ADJ},
-    {"kernel": "csr_tiled_kernel<double, false, 4, 512, 16>", "bytes_per_launch": 205.40e6, "sources": _SRC_ADJ},
+    {"kernel": "csr_tiled_kernel<double, false, 4, 256, 16>", "bytes_per_launch": 199.67e6, "sources": _SRC_ADJ},
+    {"kernel": "csr_tiled_kernel<double, false, 4, 512, 16>", "bytes_per_launch": 205.64e6, "sources": _SRC_ADJ},
 ]
 
 

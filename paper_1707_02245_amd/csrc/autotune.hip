@@ -35,7 +35,7 @@ std::string cache_key(const pat_geometry_s* g) {
   if (colon != std::string::npos) arch = arch.substr(0, colon);
   char buf[512];
   const int rot = (g->sym_enabled && g->sym_rot == 4) ? 4 : 1;
-  std::snprintf(buf, sizeof(buf), "v5|%s|nx=%d|ny=%d|ndet=%d|nt=%d|dt=%d|span=%.6f|r=%.6f|spp=%.4f|t=%.6g|rot=%d",
+  std::snprintf(buf, sizeof(buf), "v6|%s|nx=%d|ny=%d|ndet=%d|nt=%d|dt=%d|span=%.6f|r=%.6f|spp=%.4f|t=%.6g|rot=%d",
                 arch.c_str(), g->nx, g->ny, g->n_det, g->n_t, g->dtype, g->desc.arc_span,
                 g->desc.det_radius, g->desc.samples_per_pixel, g->desc.dt * g->desc.c / g->h, rot);
   return buf;

@@ -530,15 +530,38 @@ __global__ __launch_bounds__(NT) void csr_tiled_kernel(CsrMultiArgs<T> a0, const
   // other rows of the batch go on, or the next batch's first group. Every
   // group starts at or before its row's end, so its loads stay within the
   // 256 entries of slack after the matrix. Lanes outside [e0, e1) contribute
-  // fma(0, x, acc) = acc.
-  constexpr int NA = R >= 4 ? 2 : 4;  // accumulators per slot
+  // a zero product.
+  //
+  // Entries of a group per lane: with 4-byte values lane gl takes the four
+  // consecutive entries 4 gl .. 4 gl + 3 (one 8-byte load of their offsets,
+  // two 8-byte loads of values: half the load instructions, which bound the
+  // 4-byte case); with 8-byte values it takes gl, gl + LPR, gl + 2 LPR,
+  // gl + 3 LPR (consecutive lanes on consecutive entries), the better order
+  // once the value bytes themselves bound the pass. Group bases are multiples
+  // of LPR and the arrays start 256-byte aligned, so the wide loads are
+  // aligned.
+  constexpr bool kConsec = sizeof(T) == 4;
+  typedef T T2 __attribute__((ext_vector_type(2)));
   int c[4];  // 16-bit offsets held unpacked (packing would wait on the loads)
   T v[4];
   auto load_group = [&](int base, int* cc, T* vv) {
+    if constexpr (kConsec) {
+      const int e = base + 4 * gl;
+      const uint64_t w = __builtin_nontemporal_load((gptr<const uint64_t>)(lcol + e));
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      cc[u] = (int)__builtin_nontemporal_load(lcol + (base + LPR * u + gl));
-      vv[u] = __builtin_nontemporal_load(val + (base + LPR * u + gl));
+      for (int u = 0; u < 4; ++u) cc[u] = (int)((w >> (16 * u)) & 0xffffu);
+      const T2 lo = __builtin_nontemporal_load((gptr<const T2>)(val + e));
+      const T2 hi = __builtin_nontemporal_load((gptr<const T2>)(val + e + 2));
+      vv[0] = lo.x;
+      vv[1] = lo.y;
+      vv[2] = hi.x;
+      vv[3] = hi.y;
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        cc[u] = (int)__builtin_nontemporal_load(lcol + (base + LPR * u + gl));
+        vv[u] = __builtin_nontemporal_load(val + (base + LPR * u + gl));
+      }
     }
   };
   if (n_batch > 0) {
@@ -550,11 +573,12 @@ __global__ __launch_bounds__(NT) void csr_tiled_kernel(CsrMultiArgs<T> a0, const
       const bool has_next = b + 1 < n_batch;
       int ne0 = 0, ne1 = 0;
       if (has_next) row_range(b + 1, ne0, ne1);
-      Acc acc[R][NA];
+      // one accumulator per slot; each group adds its four products as a
+      // fixed tree, so a slot's summation order does not depend on how many
+      // slots the launch carries (batched and single solves agree bitwise)
+      Acc acc[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int u = 0; u < NA; ++u) acc[r][u] = Acc(0);
+      for (int r = 0; r < R; ++r) acc[r] = Acc(0);
       bool stale = false;
       while (true) {
         const int nb = base + 4 * LPR;
@@ -566,14 +590,21 @@ __global__ __launch_bounds__(NT) void csr_tiled_kernel(CsrMultiArgs<T> a0, const
         load_group(next, cn, vn);
         // every slot is computed (slots past nrhs read stale LDS and are not
         // stored): no per-slot branches between the LDS reads
+        Acc vm[4];
+        int cu[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int e = base + LPR * u + gl;
+          const int e = kConsec ? base + 4 * gl + u : base + LPR * u + gl;
           const bool ok = !stale && e >= e0 && e < e1;
-          const Acc vm = ok ? (Acc)v[u] : Acc(0);
-          const int cu = ok ? c[u] : 0;
+          vm[u] = ok ? (Acc)v[u] : Acc(0);
+          cu[u] = ok ? c[u] : 0;
+        }
 #pragma unroll
-          for (int r = 0; r < R; ++r) acc[r][u % NA] = fma(vm, (Acc)lds[r * stride + cu], acc[r][u % NA]);
+        for (int r = 0; r < R; ++r) {
+          const T* x = lds + r * stride;
+          const Acc p01 = fma(vm[1], (Acc)x[cu[1]], vm[0] * (Acc)x[cu[0]]);
+          const Acc p23 = fma(vm[3], (Acc)x[cu[3]], vm[2] * (Acc)x[cu[2]]);
+          acc[r] += p01 + p23;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -590,9 +621,7 @@ __global__ __launch_bounds__(NT) void csr_tiled_kernel(CsrMultiArgs<T> a0, const
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (R == 1 || r < nr) {
-          const Acc part = NA == 4 ? (acc[r][0] + acc[r][1]) + (acc[r][2 % NA] + acc[r][3 % NA])
-                                   : acc[r][0] + acc[r][1];
-          const Acc sum = LPR == 16 ? row16_sum(part) : group_sum<64>(part);
+          const Acc sum = LPR == 16 ? row16_sum(acc[r]) : group_sum<64>(acc[r]);
           if (store) {
             const int64_t out = (R == 1 || a.rot <= 1) ? (int64_t)j * nx + i : quarter_turn(i, j, nx, r % a.rot);
             if (WIDE) a.y64[r][out] = (double)sum;

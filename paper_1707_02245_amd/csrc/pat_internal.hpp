@@ -169,9 +169,11 @@ void launch_csr_tiled(const CsrMultiArgs<T>& a, hipStream_t s, bool wide, int wa
 template <class T>
 void launch_csr_tiled_batched(const CsrMultiArgs<T>* arr, const int* starts, int n_grp, int total_blocks,
                               size_t shm, hipStream_t s, bool wide, int max_rhs, int waves, int lanes);
-// Default workgroup shape of the tiled kernel for a dynamic LDS size: 16
-// waves when the windows leave room for a single workgroup per CU, else 4.
-inline int csr_waves_for(size_t shm) { return shm > 80 * 1024 ? 16 : 4; }
+// Default workgroup shape of the tiled kernel for a dynamic LDS size and
+// element size: 16 waves when the windows leave room for a single workgroup
+// per CU, else 8 for 4-byte elements (their wide loads leave each wave fewer
+// instructions to issue) and 4 for 8-byte ones.
+inline int csr_waves_for(size_t shm, size_t esz) { return shm > 80 * 1024 ? 16 : (esz == 4 ? 8 : 4); }
 // Default lanes per row for a mean row length (entries): 64 for long rows.
 inline int csr_lanes_for(double mean_row) { return mean_row >= 512.0 ? 64 : 16; }
 // Multi-RHS plain kernel for one group given on the host.

@@ -565,7 +565,8 @@ void pat_geometry_s::ensure_csr(hipStream_t s) {
   if (csr_nnz >= 0) return;
   if (dtype == PAT_F64) pat::build_csr_adjoint<double>(this, s);
   else pat::build_csr_adjoint<float>(this, s);
-  csr_waves = pat::csr_waves_for(csr_side ? (dtype == PAT_F64 ? 8 : 4) * (size_t)csr_win_max * csr_rot : 0);
+  const size_t esz = dtype == PAT_F64 ? 8 : 4;
+  csr_waves = pat::csr_waves_for(csr_side ? esz * (size_t)csr_win_max * csr_rot : 0, esz);
   csr_lanes = pat::csr_lanes_for(n_pix() > 0 ? (double)csr_nnz / (double)n_pix() : 0.0);
 }
 

@@ -416,7 +416,7 @@ class Solver {
     tiled = tiled && shm <= (size_t)lds_max;
     if (tiled) prepare_csr_tiled<T>(max_rhs, shm);
     // workgroup shape: the geometry's tuned choice for a single group, else by LDS
-    int waves = csr_waves_for(shm);
+    int waves = csr_waves_for(shm, sizeof(T));
     double mean_row = 0.0;
     for (pat_geometry g : csr_geo) mean_row = std::max(mean_row, (double)g->csr_nnz / (double)g->n_pix());
     int lanes = csr_lanes_for(mean_row);

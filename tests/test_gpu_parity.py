@@ -635,6 +635,36 @@ def test_batched_on_four_pixel_tiles():
     assert rel(host(us[1]), ref["u"]) <= 1e-10
 
 
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_batched_bitwise_with_long_rows(dt):
+    """A geometry without quarter-turn storage (one slot, rows of about 110
+    entries, several per lane) batched with a quarter-turn geometry (four
+    slots): the shared tiled launch then carries four slots for both, and the
+    long-row instance still equals its single solve bitwise, because each
+    slot's summation order does not depend on how many slots a launch
+    carries."""
+    d_long = desc_for(36, 18, 120)
+    og = OG.make_geometry(d_long)
+    A = OG.forward_matrix(og)
+    g_long = pat.Geometry(dtype=DT[dt], **d_long)
+    d4, og4, g4 = _geoms("tv64", dt)
+    assert g_long.info["csr_rot"] == 1 and g4.info["csr_rot"] == 4
+    assert g_long.info["adj_mode"] == 2 and g4.info["adj_mode"] == 2
+    rng = np.random.default_rng(15)
+    fl = A @ rng.uniform(0, 1, og.n_pix)
+    f_long = to_dev(fl, DT[dt])
+    f4 = to_dev(OG.forward_matrix(og4) @ rng.uniform(0, 1, og4.n_pix), DT[dt])
+    reg = pat.Reg("tv", 0.01)
+    problems = [(g4, f4, reg), (g_long, f_long, reg)]
+    us, infos, st = pat.solve_batched(problems, max_iter=40, gap_tol=0.0, gap_every=20, graph_block=20)
+    for (g, f, reg_), u in zip(problems, us):
+        u1, _, _ = pat.solve(g, f, reg, max_iter=40, gap_tol=0.0, gap_every=20, graph_block=20)
+        assert np.array_equal(host(u), host(u1))
+    p = oracle_problem(A, fl, 36, "tv", 0.01)
+    ref = OP.pdhg_solve(p, OP.precond_diag(p), iters=40)
+    assert rel(host(us[1]), ref["u"]) <= (1e-10 if dt == "f64" else 1e-3)
+
 def test_autotune_and_cache(tmp_path):
     d, og, g = _geoms("arc90", "f32")
     path = str(tmp_path / "tune.txt")
