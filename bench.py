@@ -39,17 +39,17 @@ _SRC_FWD = {"paper_1707_02245_amd/csrc/projector.hip":
             "paper_1707_02245_amd/csrc/pat_common.hpp":
             "f400c8fb3593a8183f0effb99481bb3ae19d2a625a5716d4bd5c94bd98332ee0"}
 _SRC_ADJ = {"paper_1707_02245_amd/csrc/csr.hip":
-            "9504a1198ed465a2988b12f56c4427214dbb8462d7eec20dfa7442d264d15fc8",
+            "b470afe964977095acf55b26eb15ff530103019d8f62d7157a19af51c17d66db",
             "paper_1707_02245_amd/csrc/pat_common.hpp":
             "f400c8fb3593a8183f0effb99481bb3ae19d2a625a5716d4bd5c94bd98332ee0"}
 MEASURED_TRAFFIC = [
     # profiles/fwd_gather_tgv256_f64_hbm_traffic.md
-    {"kernel": "fwd_kernel<double, 0, 16>", "bytes_per_launch": 40.42e6, "sources": _SRC_FWD},
-    {"kernel": "fwd_kernel<double, 0, 32>", "bytes_per_launch": 39.41e6, "sources": _SRC_FWD},
+    {"kernel": "fwd_kernel<double, 0, 16>", "bytes_per_launch": 34.88e6, "sources": _SRC_FWD},
+    {"kernel": "fwd_kernel<double, 0, 32>", "bytes_per_launch": 28.53e6, "sources": _SRC_FWD},
     {"kernel": "fwd_kernel<double, 0, 64>", "bytes_per_launch": 42.55e6, "sources": _SRC_FWD},
     # profiles/csr_tiled_tgv256_f64_hbm_traffic.md
-    {"kernel": "csr_tiled_kernel<double, false, 4, 256, 16>", "bytes_per_launch": 199.67e6, "sources": _SRC_ADJ},
-    {"kernel": "csr_tiled_kernel<double, false, 4, 512, 16>", "bytes_per_launch": 205.64e6, "sources": _SRC_ADJ},
+    {"kernel": "csr_tiled_kernel<double, false, 4, 256, 16>", "bytes_per_launch": 210.13e6, "sources": _SRC_ADJ},
+    {"kernel": "csr_tiled_kernel<double, false, 4, 512, 16>", "bytes_per_launch": 227.47e6, "sources": _SRC_ADJ},
 ]
 
 

@@ -524,43 +524,52 @@ __global__ __launch_bounds__(NT) void csr_tiled_kernel(CsrMultiArgs<T> a0, const
       }
     }
   };
-  // Software pipeline: a group of four LPR-entry blocks per row (block-
+  // Software pipeline: a group of G LPR-entry blocks per row (block-
   // aligned) is loaded one step ahead: the row's next group, the row's last
   // group again (marked stale, all lanes masked) once the row is done and
   // other rows of the batch go on, or the next batch's first group. Every
-  // group starts at or before its row's end, so its loads stay within the
-  // 256 entries of slack after the matrix. Lanes outside [e0, e1) contribute
-  // a zero product.
+  // group starts at or before its row's end and spans G LPR <= 256 entries,
+  // so its loads stay within the 256 entries of slack after the matrix.
+  // Lanes outside [e0, e1) contribute a zero product.
   //
-  // Entries of a group per lane: with 4-byte values lane gl takes the four
-  // consecutive entries 4 gl .. 4 gl + 3 (one 8-byte load of their offsets,
-  // two 8-byte loads of values: half the load instructions, which bound the
-  // 4-byte case); with 8-byte values it takes gl, gl + LPR, gl + 2 LPR,
-  // gl + 3 LPR (consecutive lanes on consecutive entries), the better order
-  // once the value bytes themselves bound the pass. Group bases are multiples
-  // of LPR and the arrays start 256-byte aligned, so the wide loads are
-  // aligned.
-  constexpr bool kConsec = sizeof(T) == 4;
+  // Entries per lane: runs of K consecutive entries, K = 16 bytes of values
+  // (2 doubles or 4 floats): one 16-byte value load and one 4- or 8-byte
+  // offset load per run, consecutive lanes on consecutive runs, so a wave's
+  // value load covers 1 KB contiguous. Lane gl's entry u of a group is
+  // base + K gl + K LPR (u / K) + u % K. With 8-byte values, 16-lane rows and
+  // four slots a lane takes G = 8 entries per step (more bytes in flight per
+  // wave at no loss of occupancy), else 4; a lane's entries and the order of
+  // its additions are the same for both (an 8-entry step adds its products as
+  // two 4-entry steps would), so G may follow the slot count. Group bases are
+  // multiples of LPR and the arrays start 256-byte aligned, so every wide
+  // load is aligned.
+  constexpr int K = 16 / (int)sizeof(T);
+  constexpr int G = (sizeof(T) == 8 && LPR == 16 && R == 4) ? 8 : 4;
+  static_assert(G % K == 0 && (G == 4 || G == 8) && G * LPR <= kCsrSlack, "a group must stay within the slack");
   typedef T T2 __attribute__((ext_vector_type(2)));
-  int c[4];  // 16-bit offsets held unpacked (packing would wait on the loads)
-  T v[4];
+  typedef T T4 __attribute__((ext_vector_type(4)));
+  int c[G];  // 16-bit offsets held unpacked (packing would wait on the loads)
+  T v[G];
   auto load_group = [&](int base, int* cc, T* vv) {
-    if constexpr (kConsec) {
-      const int e = base + 4 * gl;
-      const uint64_t w = __builtin_nontemporal_load((gptr<const uint64_t>)(lcol + e));
 #pragma unroll
-      for (int u = 0; u < 4; ++u) cc[u] = (int)((w >> (16 * u)) & 0xffffu);
-      const T2 lo = __builtin_nontemporal_load((gptr<const T2>)(val + e));
-      const T2 hi = __builtin_nontemporal_load((gptr<const T2>)(val + e + 2));
-      vv[0] = lo.x;
-      vv[1] = lo.y;
-      vv[2] = hi.x;
-      vv[3] = hi.y;
-    } else {
+    for (int q = 0; q < G / K; ++q) {
+      const int e = base + K * gl + K * LPR * q;
+      if constexpr (K == 2) {
+        const uint32_t w = __builtin_nontemporal_load((gptr<const uint32_t>)(lcol + e));
+        cc[2 * q] = (int)(w & 0xffffu);
+        cc[2 * q + 1] = (int)(w >> 16);
+        const T2 p = __builtin_nontemporal_load((gptr<const T2>)(val + e));
+        vv[2 * q] = p.x;
+        vv[2 * q + 1] = p.y;
+      } else {
+        const uint64_t w = __builtin_nontemporal_load((gptr<const uint64_t>)(lcol + e));
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        cc[u] = (int)__builtin_nontemporal_load(lcol + (base + LPR * u + gl));
-        vv[u] = __builtin_nontemporal_load(val + (base + LPR * u + gl));
+        for (int t = 0; t < 4; ++t) cc[4 * q + t] = (int)((w >> (16 * t)) & 0xffffu);
+        const T4 p = __builtin_nontemporal_load((gptr<const T4>)(val + e));
+        vv[4 * q] = p.x;
+        vv[4 * q + 1] = p.y;
+        vv[4 * q + 2] = p.z;
+        vv[4 * q + 3] = p.w;
       }
     }
   };
@@ -573,28 +582,29 @@ __global__ __launch_bounds__(NT) void csr_tiled_kernel(CsrMultiArgs<T> a0, const
       const bool has_next = b + 1 < n_batch;
       int ne0 = 0, ne1 = 0;
       if (has_next) row_range(b + 1, ne0, ne1);
-      // one accumulator per slot; each group adds its four products as a
-      // fixed tree, so a slot's summation order does not depend on how many
-      // slots the launch carries (batched and single solves agree bitwise)
+      // one accumulator per slot; each 4 entries of a lane add their products
+      // as a fixed tree, so a slot's summation order does not depend on how
+      // many slots the launch carries (batched and single solves agree
+      // bitwise)
       Acc acc[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) acc[r] = Acc(0);
       bool stale = false;
       while (true) {
-        const int nb = base + 4 * LPR;
+        const int nb = base + G * LPR;
         const bool more = !stale && nb < e1;
         const bool any = __any(more);
         const int next = any ? (more ? nb : base) : (has_next ? (ne0 & ~(LPR - 1)) : base);
-        int cn[4];
-        T vn[4];
+        int cn[G];
+        T vn[G];
         load_group(next, cn, vn);
         // every slot is computed (slots past nrhs read stale LDS and are not
         // stored): no per-slot branches between the LDS reads
-        Acc vm[4];
-        int cu[4];
+        Acc vm[G];
+        int cu[G];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int e = kConsec ? base + 4 * gl + u : base + LPR * u + gl;
+        for (int u = 0; u < G; ++u) {
+          const int e = base + K * gl + K * LPR * (u / K) + u % K;
           const bool ok = !stale && e >= e0 && e < e1;
           vm[u] = ok ? (Acc)v[u] : Acc(0);
           cu[u] = ok ? c[u] : 0;
@@ -602,12 +612,14 @@ __global__ __launch_bounds__(NT) void csr_tiled_kernel(CsrMultiArgs<T> a0, const
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const T* x = lds + r * stride;
-          const Acc p01 = fma(vm[1], (Acc)x[cu[1]], vm[0] * (Acc)x[cu[0]]);
-          const Acc p23 = fma(vm[3], (Acc)x[cu[3]], vm[2] * (Acc)x[cu[2]]);
-          acc[r] += p01 + p23;
+          Acc p[G / 2];
+#pragma unroll
+          for (int h = 0; h < G / 2; ++h) p[h] = fma(vm[2 * h + 1], (Acc)x[cu[2 * h + 1]], vm[2 * h] * (Acc)x[cu[2 * h]]);
+#pragma unroll
+          for (int h = 0; h < G / 2; h += 2) acc[r] += p[h] + p[h + 1];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < G; ++u) {
           c[u] = cn[u];
           v[u] = vn[u];
         }
