@@ -127,6 +127,10 @@ template <class T>
 void launch_forward(int mode, const FwdArgs<T>& a, int lanes_log2, hipStream_t s);
 template <class T>
 void launch_forward_batched(int mode, const Launch<T>& L, int lanes_log2, hipStream_t s);
+// forward with the data term's dual step and the regulariser's dual step in
+// one launch (two launches for the LDS-tiled forward)
+template <class T>
+void launch_forward_reg_batched(const Launch<T>& L, int lanes_log2, hipStream_t s);
 template <class T>
 void attach_fwd_part(pat_geometry_s* g, FwdArgs<T>& a);
 template <class T>

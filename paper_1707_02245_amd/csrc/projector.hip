@@ -20,6 +20,7 @@
 // run-to-run deterministic (one wave per accumulator, no cross-wave atomics).
 
 #include "pat_internal.hpp"
+#include "reg_dual.hpp"
 
 namespace pat {
 
@@ -112,10 +113,22 @@ __device__ __forceinline__ void fwd_epilogue(const FwdArgs<T>& a, int blk, bool 
   }
 }
 
-template <class T, int MODE, int LANES>
+// With FUSED the launch also carries the regulariser's dual step, which reads
+// the same extrapolated image as the forward's dual data step and writes
+// disjoint state: blocks from n_fwd on run it (so filling the forward's last
+// wave of blocks) and the blocks before them the forward.
+template <class T, int MODE, int LANES, bool FUSED = false>
 __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T>* __restrict__ arr,
-                                                  const int* __restrict__ starts, int n_inst) {
+                                                  const int* __restrict__ starts, int n_inst, int n_fwd,
+                                                  const InstDev<T>* __restrict__ rarr,
+                                                  const int* __restrict__ rstarts, int rn) {
   int blk = blockIdx.x;
+  if constexpr (FUSED) {
+    if (blk >= n_fwd) {
+      reg_dual_block<T>(rarr, rstarts, rn, blk - n_fwd);
+      return;
+    }
+  }
   FwdArgs<T> a;
   if (arr) {
     const int i = find_inst(starts, n_inst, blk);
@@ -306,9 +319,12 @@ template <class T, int MODE>
 static void fwd_dispatch(int lanes_log2, int blocks, const FwdArgs<T>& a0, const FwdArgs<T>* arr,
                          const int* starts, int n, hipStream_t s) {
   switch (lanes_log2) {
-    case 4: hipLaunchKernelGGL((fwd_kernel<T, MODE, 16>), dim3(blocks), dim3(256), 0, s, a0, arr, starts, n); break;
-    case 5: hipLaunchKernelGGL((fwd_kernel<T, MODE, 32>), dim3(blocks), dim3(256), 0, s, a0, arr, starts, n); break;
-    default: hipLaunchKernelGGL((fwd_kernel<T, MODE, 64>), dim3(blocks), dim3(256), 0, s, a0, arr, starts, n); break;
+    case 4: hipLaunchKernelGGL((fwd_kernel<T, MODE, 16>), dim3(blocks), dim3(256), 0, s, a0, arr, starts, n, blocks,
+                         nullptr, nullptr, 0); break;
+    case 5: hipLaunchKernelGGL((fwd_kernel<T, MODE, 32>), dim3(blocks), dim3(256), 0, s, a0, arr, starts, n, blocks,
+                         nullptr, nullptr, 0); break;
+    default: hipLaunchKernelGGL((fwd_kernel<T, MODE, 64>), dim3(blocks), dim3(256), 0, s, a0, arr, starts, n, blocks,
+                         nullptr, nullptr, 0); break;
   }
 }
 
@@ -351,6 +367,33 @@ void launch_forward(int mode, const FwdArgs<T>& a, int lanes_log2, hipStream_t s
     return;
   }
   fwd_mode_dispatch<T>(mode, lanes_log2, blocks, a, nullptr, nullptr, 1, s);
+}
+
+template <class T>
+void launch_forward_reg_batched(const Launch<T>& L, int lanes_log2, hipStream_t s) {
+  if (L.fwd_tiled || L.fwd_total <= 0 || L.pix_total <= 0) {
+    launch_forward_batched<T>(FWD_DUAL, L, lanes_log2, s);
+    launch_reg_dual<T>(L, s);
+    return;
+  }
+  const dim3 grid((unsigned)(L.fwd_total + L.pix_total));
+  const FwdArgs<T>* fa = ptr<FwdArgs<T>>(L.fwd);
+  const InstDev<T>* ra = ptr<InstDev<T>>(L.inst);
+  switch (lanes_log2) {
+    case 4:
+      hipLaunchKernelGGL((fwd_kernel<T, FWD_DUAL, 16, true>), grid, dim3(256), 0, s, FwdArgs<T>{}, fa,
+                         ptr<int>(L.fwd_start), L.n, L.fwd_total, ra, ptr<int>(L.pix_start), L.n);
+      break;
+    case 5:
+      hipLaunchKernelGGL((fwd_kernel<T, FWD_DUAL, 32, true>), grid, dim3(256), 0, s, FwdArgs<T>{}, fa,
+                         ptr<int>(L.fwd_start), L.n, L.fwd_total, ra, ptr<int>(L.pix_start), L.n);
+      break;
+    default:
+      hipLaunchKernelGGL((fwd_kernel<T, FWD_DUAL, 64, true>), grid, dim3(256), 0, s, FwdArgs<T>{}, fa,
+                         ptr<int>(L.fwd_start), L.n, L.fwd_total, ra, ptr<int>(L.pix_start), L.n);
+      break;
+  }
+  PAT_HIP(hipGetLastError());
 }
 
 template <class T>
@@ -523,6 +566,7 @@ void launch_reduce_groups(const T* part, T* out, int n_groups, int64_t n, hipStr
   template void launch_pad<T>(const T*, T*, int, int, hipStream_t);                         \
   template void launch_forward<T>(int, const FwdArgs<T>&, int, hipStream_t);                \
   template void launch_forward_batched<T>(int, const Launch<T>&, int, hipStream_t);        \
+  template void launch_forward_reg_batched<T>(const Launch<T>&, int, hipStream_t);          \
   template void launch_adjoint<T>(const AdjArgs<T>&, hipStream_t);                          \
   template void launch_adjoint_batched<T>(const Launch<T>&, hipStream_t);                   \
   template void launch_reduce_groups<T>(const T*, T*, int, int64_t, hipStream_t);

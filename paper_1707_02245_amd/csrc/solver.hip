@@ -476,8 +476,7 @@ class Solver {
   }
 
   void enqueue_iteration(bool check, int c) {
-    launch_forward_batched<T>(FWD_DUAL, L, lanes_log2, s);
-    launch_reg_dual<T>(L, s);
+    launch_forward_reg_batched<T>(L, lanes_log2, s);
     if (L.n_adj > 0) launch_adjoint_batched<T>(L, s);
     if (L.n_csr > 0) {
       // check iterations: A^T q once more with FP64 accumulation for the gap
