@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # size (FETCH x 2, WRITE x 1); profiles/*_hbm_traffic.md. An entry is reported only
 # while the kernel's sources are the ones measured.
 _SRC_FWD = {"paper_1707_02245_amd/csrc/projector.hip":
-            "67d8172fa940f7458dce6658a1e09c7c9ff95de3d6daa514c2998b43db27b2ce",
+            "bbaa17ef51931596277ca0a1224996da146bbcd1f00504c5be472b6a7f81b6ac",
             "paper_1707_02245_amd/csrc/pat_common.hpp":
             "f400c8fb3593a8183f0effb99481bb3ae19d2a625a5716d4bd5c94bd98332ee0"}
 _SRC_ADJ = {"paper_1707_02245_amd/csrc/csr.hip":
@@ -44,9 +44,9 @@ _SRC_ADJ = {"paper_1707_02245_amd/csrc/csr.hip":
             "f400c8fb3593a8183f0effb99481bb3ae19d2a625a5716d4bd5c94bd98332ee0"}
 MEASURED_TRAFFIC = [
     # profiles/fwd_gather_tgv256_f64_hbm_traffic.md
-    {"kernel": "fwd_kernel<double, 0, 16, false>", "bytes_per_launch": 34.88e6, "sources": _SRC_FWD},
-    {"kernel": "fwd_kernel<double, 0, 32, false>", "bytes_per_launch": 28.54e6, "sources": _SRC_FWD},
-    {"kernel": "fwd_kernel<double, 0, 64, false>", "bytes_per_launch": 42.55e6, "sources": _SRC_FWD},
+    {"kernel": "fwd_kernel<double, 0, 16, false, 1>", "bytes_per_launch": 34.88e6, "sources": _SRC_FWD},
+    {"kernel": "fwd_kernel<double, 0, 32, false, 1>", "bytes_per_launch": 28.53e6, "sources": _SRC_FWD},
+    {"kernel": "fwd_kernel<double, 0, 64, false, 1>", "bytes_per_launch": 42.55e6, "sources": _SRC_FWD},
     # profiles/csr_tiled_tgv256_f64_hbm_traffic.md
     {"kernel": "csr_tiled_kernel<double, false, 4, 256, 16>", "bytes_per_launch": 210.13e6, "sources": _SRC_ADJ},
     {"kernel": "csr_tiled_kernel<double, false, 4, 512, 16>", "bytes_per_launch": 227.47e6, "sources": _SRC_ADJ},
@@ -395,7 +395,7 @@ def main():
     log(f"apply: {apply}")
     peak = FP64_VECTOR_PEAK_TFLOPS if esz == 8 else FP32_VECTOR_PEAK_TFLOPS
     if t_fwd >= t_adj:
-        fkname = (f"fwd_kernel<{tname}, 0, {lanes}, false> (forward gather: 2x2 bilinear taps per arc sample from "
+        fkname = (f"fwd_kernel<{tname}, 0, {lanes}, false, 1> (forward gather: 2x2 bilinear taps per arc sample from "
                   f"the cache-resident image, FP64 positions; the solver's instance adds the dual step and "
                   f"carries the regulariser's dual step in the same launch)")
         roofline = {"kernel": fkname, "bound": "alu",

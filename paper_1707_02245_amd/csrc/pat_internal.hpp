@@ -116,6 +116,9 @@ struct Launch {
   bool fwd_tiled = false;
   DevBuf fwdt_start;
   int fwdt_total = 0;
+  // 2 to 4 instances on one geometry (gather forward): each forward block
+  // serves all fwd_ni of them (fwd_ni_blocks blocks); 1 otherwise
+  int fwd_ni = 1, fwd_ni_blocks = 0;
   int lanes_log2 = 6;   // shared by every instance of one launch
   int max_tile = 32;    // shared by every instance of one launch
 };

@@ -116,8 +116,11 @@ __device__ __forceinline__ void fwd_epilogue(const FwdArgs<T>& a, int blk, bool 
 // With FUSED the launch also carries the regulariser's dual step, which reads
 // the same extrapolated image as the forward's dual data step and writes
 // disjoint state: blocks from n_fwd on run it (so filling the forward's last
-// wave of blocks) and the blocks before them the forward.
-template <class T, int MODE, int LANES, bool FUSED = false>
+// wave of blocks) and the blocks before them the forward. With NI > 1 the NI
+// instances of arr share one geometry and each block serves all of them: a
+// sample's table entry, position and cell are computed once and its 2x2 taps
+// read from each instance's image.
+template <class T, int MODE, int LANES, bool FUSED = false, int NI = 1>
 __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T>* __restrict__ arr,
                                                   const int* __restrict__ starts, int n_inst, int n_fwd,
                                                   const InstDev<T>* __restrict__ rarr,
@@ -130,7 +133,9 @@ __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T
     }
   }
   FwdArgs<T> a;
-  if (arr) {
+  if constexpr (NI > 1) {
+    a = arr[0];
+  } else if (arr) {
     const int i = find_inst(starts, n_inst, blk);
     a = arr[i];
     blk -= starts[i];
@@ -156,7 +161,9 @@ __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T
   }
   const bool valid = d < g.n_det && k < g.n_t;
   const int b = d * g.n_t + k;
-  T acc = T(0);
+  T acc[NI];
+#pragma unroll
+  for (int i = 0; i < NI; ++i) acc[i] = T(0);
   double inv_m = 0.0;
   if (valid) {
     const int4 w0 = g.win[2 * (int64_t)b], w1 = g.win[2 * (int64_t)b + 1];
@@ -164,7 +171,9 @@ __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T
     const double2 rr = g.rad[k];
     inv_m = rr.y;
     const int toff = g.moff[k].y;
-    const gptr<const char> ub = as_global(reinterpret_cast<const char*>(a.upad));
+    gptr<const char> ub[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) ub[i] = as_global(reinterpret_cast<const char*>(NI > 1 ? arr[i].upad : a.upad));
     const int P = g.pitch;
     const unsigned rowb = (unsigned)P * (unsigned)sizeof(T);
     const int nx = g.nx, ny = g.ny;
@@ -174,7 +183,7 @@ __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T
     // offset P - 1 instead (last border column of row 0 and, wrapping, the
     // first border column of rows 1 and 2: all four taps are zero), so the
     // loads of both samples in flight issue together.
-    auto tap = [&](const double2 cs) -> T {
+    auto tap = [&](const double2 cs, T* t) {
       const Sample s = arc_sample(p, rr.x, cs);
       const bool in = ((unsigned)(s.ix + 1) <= (unsigned)nx) & ((unsigned)(s.iy + 1) <= (unsigned)ny);
       const int o = in ? (int)__umul24((unsigned)(s.iy + 1), (unsigned)P) + (s.ix + 1) : P - 1;
@@ -182,11 +191,14 @@ __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T
       // 32-bit byte offsets from the uniform base (the padded image is far
       // below 4 GB): scalar-base loads without 64-bit address arithmetic
       const unsigned off = (unsigned)o * (unsigned)sizeof(T);
-      const gptr<const T> q0 = (gptr<const T>)(ub + off), q1 = (gptr<const T>)(ub + (off + rowb));
-      const T q00 = q0[0], q10 = q0[1], q01 = q1[0], q11 = q1[1];
-      const T lo = fma(tx, q10 - q00, q00);
-      const T hi = fma(tx, q11 - q01, q01);
-      return fma(ty, hi - lo, lo);
+#pragma unroll
+      for (int i = 0; i < NI; ++i) {
+        const gptr<const T> q0 = (gptr<const T>)(ub[i] + off), q1 = (gptr<const T>)(ub[i] + (off + rowb));
+        const T q00 = q0[0], q10 = q0[1], q01 = q1[0], q11 = q1[1];
+        const T lo = fma(tx, q10 - q00, q00);
+        const T hi = fma(tx, q11 - q01, q01);
+        t[i] = fma(ty, hi - lo, lo);
+      }
     };
     const int rng[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
 #pragma unroll
@@ -196,15 +208,28 @@ __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T
       // two samples per lane in flight
       for (; m + LANES < m1; m += 2 * LANES) {
         const double2 c0 = table_cs<T>(g, toff + m), c1 = table_cs<T>(g, toff + m + LANES);
-        const T t0 = tap(c0);
-        const T t1 = tap(c1);
-        acc += t0 + t1;
+        T t0[NI], t1[NI];
+        tap(c0, t0);
+        tap(c1, t1);
+#pragma unroll
+        for (int i = 0; i < NI; ++i) acc[i] += t0[i] + t1[i];
       }
-      if (m < m1) acc += tap(table_cs<T>(g, toff + m));
+      if (m < m1) {
+        T t0[NI];
+        tap(table_cs<T>(g, toff + m), t0);
+#pragma unroll
+        for (int i = 0; i < NI; ++i) acc[i] += t0[i];
+      }
     }
   }
-  acc = group_sum<LANES>(acc);
-  fwd_epilogue<T, MODE>(a, blk, valid && lane == 0, b, acc * (T)inv_m);
+#pragma unroll
+  for (int i = 0; i < NI; ++i) acc[i] = group_sum<LANES>(acc[i]);
+  if constexpr (NI == 1) {
+    fwd_epilogue<T, MODE>(a, blk, valid && lane == 0, b, acc[0] * (T)inv_m);
+  } else {
+#pragma unroll
+    for (int i = 0; i < NI; ++i) fwd_epilogue<T, MODE>(arr[i], blk, valid && lane == 0, b, acc[i] * (T)inv_m);
+  }
 }
 
 // LDS-tiled forward, gather pass: a workgroup stages tile cells [x0, x0 +
@@ -369,8 +394,46 @@ void launch_forward(int mode, const FwdArgs<T>& a, int lanes_log2, hipStream_t s
   fwd_mode_dispatch<T>(mode, lanes_log2, blocks, a, nullptr, nullptr, 1, s);
 }
 
+// NI instances on one geometry: every block serves all of them; with FUSED the
+// regulariser's dual step of all instances follows in extra blocks
+template <class T, int MODE, bool FUSED, int NI>
+static void fwd_ni_launch(int lanes_log2, const Launch<T>& L, const FwdArgs<T>* arr, hipStream_t s) {
+  const int n_fwd = L.fwd_ni_blocks;
+  const dim3 grid((unsigned)(n_fwd + (FUSED ? L.pix_total : 0)));
+  const InstDev<T>* ra = FUSED ? ptr<InstDev<T>>(L.inst) : nullptr;
+  const int* rs = FUSED ? ptr<int>(L.pix_start) : nullptr;
+  const int rn = FUSED ? L.n : 0;
+  switch (lanes_log2) {
+    case 4:
+      hipLaunchKernelGGL((fwd_kernel<T, MODE, 16, FUSED, NI>), grid, dim3(256), 0, s, FwdArgs<T>{}, arr, nullptr, NI,
+                         n_fwd, ra, rs, rn);
+      break;
+    case 5:
+      hipLaunchKernelGGL((fwd_kernel<T, MODE, 32, FUSED, NI>), grid, dim3(256), 0, s, FwdArgs<T>{}, arr, nullptr, NI,
+                         n_fwd, ra, rs, rn);
+      break;
+    default:
+      hipLaunchKernelGGL((fwd_kernel<T, MODE, 64, FUSED, NI>), grid, dim3(256), 0, s, FwdArgs<T>{}, arr, nullptr, NI,
+                         n_fwd, ra, rs, rn);
+      break;
+  }
+  PAT_HIP(hipGetLastError());
+}
+
+template <class T, int MODE, bool FUSED>
+static void fwd_ni_dispatch(int lanes_log2, const Launch<T>& L, hipStream_t s) {
+  const FwdArgs<T>* arr = ptr<FwdArgs<T>>(L.fwd);
+  if (L.fwd_ni == 2) fwd_ni_launch<T, MODE, FUSED, 2>(lanes_log2, L, arr, s);
+  else if (L.fwd_ni == 3) fwd_ni_launch<T, MODE, FUSED, 3>(lanes_log2, L, arr, s);
+  else fwd_ni_launch<T, MODE, FUSED, 4>(lanes_log2, L, arr, s);
+}
+
 template <class T>
 void launch_forward_reg_batched(const Launch<T>& L, int lanes_log2, hipStream_t s) {
+  if (!L.fwd_tiled && L.fwd_ni > 1 && L.fwd_ni_blocks > 0 && L.pix_total > 0) {
+    fwd_ni_dispatch<T, FWD_DUAL, true>(lanes_log2, L, s);
+    return;
+  }
   if (L.fwd_tiled || L.fwd_total <= 0 || L.pix_total <= 0) {
     launch_forward_batched<T>(FWD_DUAL, L, lanes_log2, s);
     launch_reg_dual<T>(L, s);
@@ -398,6 +461,11 @@ void launch_forward_reg_batched(const Launch<T>& L, int lanes_log2, hipStream_t 
 
 template <class T>
 void launch_forward_batched(int mode, const Launch<T>& L, int lanes_log2, hipStream_t s) {
+  if (!L.fwd_tiled && L.fwd_ni > 1 && L.fwd_ni_blocks > 0 && (mode == FWD_DUAL || mode == FWD_GAP)) {
+    if (mode == FWD_DUAL) fwd_ni_dispatch<T, FWD_DUAL, false>(lanes_log2, L, s);
+    else fwd_ni_dispatch<T, FWD_GAP, false>(lanes_log2, L, s);
+    return;
+  }
   FwdArgs<T> dummy{};
   if (L.fwd_tiled) {
     if (L.fwdt_total > 0)

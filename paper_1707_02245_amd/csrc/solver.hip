@@ -447,6 +447,10 @@ class Solver {
     L.n = n;
     L.fwd_total = fs[n];
     L.fwd_tiled = fwd_tiled;
+    bool one_geo = n >= 2 && n <= 4 && !fwd_tiled;
+    for (int k = 1; k < n && one_geo; ++k) one_geo = inst[act[k]]->g == inst[act[0]]->g;
+    L.fwd_ni = one_geo ? n : 1;
+    L.fwd_ni_blocks = one_geo ? fs[1] : 0;
     L.fwdt_total = ts[n];
     L.adj_total = as.back();
     L.n_adj = (int)ad.size();
