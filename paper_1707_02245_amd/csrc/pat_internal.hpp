@@ -178,9 +178,13 @@ void launch_csr_tiled_batched(const CsrMultiArgs<T>* arr, const int* starts, int
                               size_t shm, hipStream_t s, bool wide, int max_rhs, int waves, int lanes);
 // Default workgroup shape of the tiled kernel for a dynamic LDS size and
 // element size: 16 waves when the windows leave room for a single workgroup
-// per CU, else 8 for 4-byte elements (their wide loads leave each wave fewer
-// instructions to issue) and 4 for 8-byte ones.
-inline int csr_waves_for(size_t shm, size_t esz) { return shm > 80 * 1024 ? 16 : (esz == 4 ? 8 : 4); }
+// per CU (160 KB of LDS), 8 for 4-byte elements (their wide loads leave each
+// wave fewer instructions to issue) or when at most two workgroups fit, else
+// 4 (three or more workgroups per CU).
+inline int csr_waves_for(size_t shm, size_t esz) {
+  if (shm > 80 * 1024) return 16;
+  return (esz == 4 || 3 * shm > 160 * 1024) ? 8 : 4;
+}
 // Default lanes per row for a mean row length (entries): 64 for long rows.
 inline int csr_lanes_for(double mean_row) { return mean_row >= 512.0 ? 64 : 16; }
 // Multi-RHS plain kernel for one group given on the host.
