@@ -608,6 +608,7 @@ def test_batched_shared_geometry_four_right_hand_sides(dt):
         u1, i1, _ = pat.solve(g, f, reg, max_iter=60, gap_tol=0.0, gap_every=20, graph_block=20)
         assert info["iters"] == i1["iters"] == 60
         assert np.array_equal(host(u), host(u1))
+        assert info["rel_gap"] == i1["rel_gap"]
     p = oracle_problem(A, fs[3], 128, "tv", 0.01)
     ref = OP.pdhg_solve(p, OP.precond_diag(p), iters=60)
     assert rel(host(us[3]), ref["u"]) <= (1e-10 if dt == "f64" else 1e-3)
@@ -678,9 +679,11 @@ def test_batched_three_on_one_geometry(dt):
     regs = [pat.Reg("tv", 0.01), pat.Reg("tgv", 0.01, 0.02), pat.Reg("tv", 0.02)]
     problems = [(g, to_dev(f, DT[dt]), r) for f, r in zip(fs, regs)]
     us, infos, st = pat.solve_batched(problems, max_iter=60, gap_tol=0.0, gap_every=20, graph_block=20)
-    for (g_, f, r), u in zip(problems, us):
-        u1, _, _ = pat.solve(g, f, r, max_iter=60, gap_tol=0.0, gap_every=20, graph_block=20)
+    for (g_, f, r), u, info in zip(problems, us, infos):
+        u1, i1, _ = pat.solve(g, f, r, max_iter=60, gap_tol=0.0, gap_every=20, graph_block=20)
         assert np.array_equal(host(u), host(u1))
+        # the gap terms come from the shared forward block too
+        assert info["rel_gap"] == i1["rel_gap"]
     p = oracle_problem(A, fs[0], 64, "tv", 0.01)
     ref = OP.pdhg_solve(p, OP.precond_diag(p), iters=60)
     assert rel(host(us[0]), ref["u"]) <= (1e-10 if dt == "f64" else 1e-3)
