@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # size (FETCH x 2, WRITE x 1); profiles/*_hbm_traffic.md. An entry is reported only
 # while the kernel's sources are the ones measured.
 _SRC_FWD = {"paper_1707_02245_amd/csrc/projector.hip":
-            "bbaa17ef51931596277ca0a1224996da146bbcd1f00504c5be472b6a7f81b6ac",
+            "47c73fc029740225c649384ae3401d1194e7d512a73245eaed5e67d0588e8b8f",
             "paper_1707_02245_amd/csrc/pat_common.hpp":
             "f400c8fb3593a8183f0effb99481bb3ae19d2a625a5716d4bd5c94bd98332ee0"}
 _SRC_ADJ = {"paper_1707_02245_amd/csrc/csr.hip":

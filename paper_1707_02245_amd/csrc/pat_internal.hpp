@@ -116,9 +116,12 @@ struct Launch {
   bool fwd_tiled = false;
   DevBuf fwdt_start;
   int fwdt_total = 0;
-  // 2 to 4 instances on one geometry (gather forward): each forward block
-  // serves all fwd_ni of them (fwd_ni_blocks blocks); 1 otherwise
-  int fwd_ni = 1, fwd_ni_blocks = 0;
+  // instances grouped by geometry, up to four per group (gather forward):
+  // each forward block serves a whole group. fwd_ni slots per group (the
+  // largest group; unused slots have no image), group block offsets in
+  // fwdg_start; fwd_ni == 1 when no two instances share a geometry
+  DevBuf fwdg, fwdg_gap, fwdg_start;
+  int fwd_ni = 1, fwd_ni_blocks = 0, fwd_ni_groups = 0;
   int lanes_log2 = 6;   // shared by every instance of one launch
   int max_tile = 32;    // shared by every instance of one launch
 };

@@ -116,10 +116,12 @@ __device__ __forceinline__ void fwd_epilogue(const FwdArgs<T>& a, int blk, bool 
 // With FUSED the launch also carries the regulariser's dual step, which reads
 // the same extrapolated image as the forward's dual data step and writes
 // disjoint state: blocks from n_fwd on run it (so filling the forward's last
-// wave of blocks) and the blocks before them the forward. With NI > 1 the NI
-// instances of arr share one geometry and each block serves all of them: a
-// sample's table entry, position and cell are computed once and its 2x2 taps
-// read from each instance's image.
+// wave of blocks) and the blocks before them the forward. With NI > 1 arr
+// holds groups of NI slots, each group's instances on one geometry (slots
+// after the group's last instance have no image), and starts the groups'
+// block offsets: each block serves a whole group, a sample's table entry,
+// position and cell computed once and its 2x2 taps read from each
+// instance's image.
 template <class T, int MODE, int LANES, bool FUSED = false, int NI = 1>
 __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T>* __restrict__ arr,
                                                   const int* __restrict__ starts, int n_inst, int n_fwd,
@@ -133,8 +135,14 @@ __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T
     }
   }
   FwdArgs<T> a;
+  int cnt = 1;  // instances in this block's group
   if constexpr (NI > 1) {
+    const int gi = find_inst(starts, n_inst, blk);
+    arr += (int64_t)NI * gi;
+    blk -= starts[gi];
     a = arr[0];
+#pragma unroll
+    for (int i = 1; i < NI; ++i) cnt += arr[i].upad != nullptr;
   } else if (arr) {
     const int i = find_inst(starts, n_inst, blk);
     a = arr[i];
@@ -193,6 +201,10 @@ __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T
       const unsigned off = (unsigned)o * (unsigned)sizeof(T);
 #pragma unroll
       for (int i = 0; i < NI; ++i) {
+        if (NI > 1 && i >= cnt) {
+          t[i] = T(0);
+          continue;
+        }
         const gptr<const T> q0 = (gptr<const T>)(ub[i] + off), q1 = (gptr<const T>)(ub[i] + (off + rowb));
         const T q00 = q0[0], q10 = q0[1], q01 = q1[0], q11 = q1[1];
         const T lo = fma(tx, q10 - q00, q00);
@@ -228,7 +240,8 @@ __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T
     fwd_epilogue<T, MODE>(a, blk, valid && lane == 0, b, acc[0] * (T)inv_m);
   } else {
 #pragma unroll
-    for (int i = 0; i < NI; ++i) fwd_epilogue<T, MODE>(arr[i], blk, valid && lane == 0, b, acc[i] * (T)inv_m);
+    for (int i = 0; i < NI; ++i)
+      if (i < cnt) fwd_epilogue<T, MODE>(arr[i], blk, valid && lane == 0, b, acc[i] * (T)inv_m);
   }
 }
 
@@ -394,10 +407,12 @@ void launch_forward(int mode, const FwdArgs<T>& a, int lanes_log2, hipStream_t s
   fwd_mode_dispatch<T>(mode, lanes_log2, blocks, a, nullptr, nullptr, 1, s);
 }
 
-// NI instances on one geometry: every block serves all of them; with FUSED the
-// regulariser's dual step of all instances follows in extra blocks
+// Instances grouped by geometry: every block serves a group of up to NI; with
+// FUSED the regulariser's dual step of all instances follows in extra blocks
 template <class T, int MODE, bool FUSED, int NI>
 static void fwd_ni_launch(int lanes_log2, const Launch<T>& L, const FwdArgs<T>* arr, hipStream_t s) {
+  const int* gs = ptr<int>(L.fwdg_start);
+  const int ng = L.fwd_ni_groups;
   const int n_fwd = L.fwd_ni_blocks;
   const dim3 grid((unsigned)(n_fwd + (FUSED ? L.pix_total : 0)));
   const InstDev<T>* ra = FUSED ? ptr<InstDev<T>>(L.inst) : nullptr;
@@ -405,15 +420,15 @@ static void fwd_ni_launch(int lanes_log2, const Launch<T>& L, const FwdArgs<T>* 
   const int rn = FUSED ? L.n : 0;
   switch (lanes_log2) {
     case 4:
-      hipLaunchKernelGGL((fwd_kernel<T, MODE, 16, FUSED, NI>), grid, dim3(256), 0, s, FwdArgs<T>{}, arr, nullptr, NI,
+      hipLaunchKernelGGL((fwd_kernel<T, MODE, 16, FUSED, NI>), grid, dim3(256), 0, s, FwdArgs<T>{}, arr, gs, ng,
                          n_fwd, ra, rs, rn);
       break;
     case 5:
-      hipLaunchKernelGGL((fwd_kernel<T, MODE, 32, FUSED, NI>), grid, dim3(256), 0, s, FwdArgs<T>{}, arr, nullptr, NI,
+      hipLaunchKernelGGL((fwd_kernel<T, MODE, 32, FUSED, NI>), grid, dim3(256), 0, s, FwdArgs<T>{}, arr, gs, ng,
                          n_fwd, ra, rs, rn);
       break;
     default:
-      hipLaunchKernelGGL((fwd_kernel<T, MODE, 64, FUSED, NI>), grid, dim3(256), 0, s, FwdArgs<T>{}, arr, nullptr, NI,
+      hipLaunchKernelGGL((fwd_kernel<T, MODE, 64, FUSED, NI>), grid, dim3(256), 0, s, FwdArgs<T>{}, arr, gs, ng,
                          n_fwd, ra, rs, rn);
       break;
   }
@@ -422,7 +437,7 @@ static void fwd_ni_launch(int lanes_log2, const Launch<T>& L, const FwdArgs<T>* 
 
 template <class T, int MODE, bool FUSED>
 static void fwd_ni_dispatch(int lanes_log2, const Launch<T>& L, hipStream_t s) {
-  const FwdArgs<T>* arr = ptr<FwdArgs<T>>(L.fwd);
+  const FwdArgs<T>* arr = ptr<FwdArgs<T>>(L.fwdg);
   if (L.fwd_ni == 2) fwd_ni_launch<T, MODE, FUSED, 2>(lanes_log2, L, arr, s);
   else if (L.fwd_ni == 3) fwd_ni_launch<T, MODE, FUSED, 3>(lanes_log2, L, arr, s);
   else fwd_ni_launch<T, MODE, FUSED, 4>(lanes_log2, L, arr, s);

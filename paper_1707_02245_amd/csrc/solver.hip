@@ -428,10 +428,50 @@ class Solver {
       const int blocks = tiled ? csr_geo[c]->n_csr_tiles() : (int)((cd[c].n_rows + 3) / 4);
       cs.push_back(cs.back() + blocks);
     }
+    // forward groups: instances on one geometry, up to four per group, share
+    // each forward block (gather forward only)
+    std::vector<std::vector<int>> fgrp;
+    if (!fwd_tiled) {
+      for (int k = 0; k < n; ++k) {
+        std::vector<int>* into = nullptr;
+        for (auto& gr : fgrp)
+          if (gr.size() < 4 && inst[act[gr[0]]]->g == inst[act[k]]->g) {
+            into = &gr;
+            break;
+          }
+        if (into) into->push_back(k);
+        else fgrp.push_back({k});
+      }
+    }
+    int ni = 1;
+    for (const auto& gr : fgrp) ni = std::max(ni, (int)gr.size());
+    std::vector<FwdArgs<T>> gdual, ggap;
+    std::vector<int> gs(1, 0);
+    if (ni > 1) {
+      for (const auto& gr : fgrp) {
+        for (int i = 0; i < ni; ++i) {
+          FwdArgs<T> x = fd[gr[0]], y = fg[gr[0]];
+          if (i < (int)gr.size()) {
+            x = fd[gr[i]];
+            y = fg[gr[i]];
+          } else {
+            x.upad = y.upad = nullptr;  // unused slot
+          }
+          gdual.push_back(x);
+          ggap.push_back(y);
+        }
+        gs.push_back(gs.back() + (fs[gr[0] + 1] - fs[gr[0]]));
+      }
+    }
     auto up = [&](DevBuf& b, const void* src, size_t bytes) {
       b.ensure(bytes);
       PAT_HIP(hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, s));
     };
+    if (ni > 1) {
+      up(L.fwdg, gdual.data(), sizeof(FwdArgs<T>) * gdual.size());
+      up(L.fwdg_gap, ggap.data(), sizeof(FwdArgs<T>) * ggap.size());
+      up(L.fwdg_start, gs.data(), sizeof(int) * gs.size());
+    }
     up(L.fwd, fd.data(), sizeof(FwdArgs<T>) * n);
     up(L.fwd_gap, fg.data(), sizeof(FwdArgs<T>) * n);
     if (!ad.empty()) up(L.adj, ad.data(), sizeof(AdjArgs<T>) * ad.size());
@@ -447,10 +487,9 @@ class Solver {
     L.n = n;
     L.fwd_total = fs[n];
     L.fwd_tiled = fwd_tiled;
-    bool one_geo = n >= 2 && n <= 4 && !fwd_tiled;
-    for (int k = 1; k < n && one_geo; ++k) one_geo = inst[act[k]]->g == inst[act[0]]->g;
-    L.fwd_ni = one_geo ? n : 1;
-    L.fwd_ni_blocks = one_geo ? fs[1] : 0;
+    L.fwd_ni = ni;
+    L.fwd_ni_blocks = ni > 1 ? gs.back() : 0;
+    L.fwd_ni_groups = ni > 1 ? (int)fgrp.size() : 0;
     L.fwdt_total = ts[n];
     L.adj_total = as.back();
     L.n_adj = (int)ad.size();
@@ -472,8 +511,10 @@ class Solver {
   void enqueue_gap(int c) {
     // the gap forward uses the second FwdArgs table (input u+, gap epilogue)
     std::swap(L.fwd, L.fwd_gap);
+    std::swap(L.fwdg, L.fwdg_gap);
     launch_forward_batched<T>(FWD_GAP, L, lanes_log2, s);
     std::swap(L.fwd, L.fwd_gap);
+    std::swap(L.fwdg, L.fwdg_gap);
     launch_gap_reg<T>(L, s);
     launch_gap_finish(ptr<GapFinishArgs>(L.gapfin), L.n,
                       ptr<double>(results) + (size_t)c * L.n * GAP_NSLOTS, s);
