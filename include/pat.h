@@ -256,8 +256,12 @@ pat_status pat_state_elems(pat_geometry g, int32_t reg_kind, int64_t* out);
 typedef struct {
   int32_t max_iter;       /* iterations to run (cap); > 0 */
   double gap_tol;         /* stop when rel_gap <= gap_tol; <= 0: run max_iter */
-  int32_t gap_every;      /* check interval in iterations (>= 1) */
-  int32_t graph_block;    /* iterations per captured HIP graph (>= 1; 0 = off) */
+  int32_t gap_every;      /* gap interval in iterations (>= 1) */
+  int32_t graph_block;    /* iterations per captured HIP graph (>= 0; 0 = off),
+                           * rounded up to a multiple of gap_every. The gap is
+                           * evaluated, and stopping decided, once per block:
+                           * every graph_block iterations (every gap_every with
+                           * graphs off) and at max_iter. */
   double theta;           /* extrapolation, 1.0 */
   double gap_box;         /* C of the box-restricted gap; > 0 */
   const void* d_u0;       /* optional warm start [ny][nx]; NULL = zero */
@@ -330,6 +334,14 @@ pat_status pat_warmstart_create(int32_t levels, int32_t base_ch, int32_t out_ch,
                                 pat_unet* out);
 pat_status pat_warmstart_destroy(pat_unet n);
 pat_status pat_warmstart_num_params(pat_unet n, int64_t* out);
+/* Tile rule of the matrix-core convolution GEMMs, process-wide (a tuning and
+ * test hook): 0 automatic (128x128 or 128x64 tiles only where the launch has
+ * at least 1024 workgroups, else 64x64), 1 the largest tile the column count
+ * allows, 2 128x64, 3 64x64; layers with at most 32 output columns always
+ * take 128x32. The tiles differ only in how output elements are grouped into
+ * workgroups; each element accumulates along k in the same chunks. Invalid
+ * mode: PAT_ERR_INVALID_ARG. */
+pat_status pat_warmstart_set_gemm_tiles(int32_t mode);
 /* Copy the FP32 parameter vector to / from device memory (set resets Adam). */
 pat_status pat_warmstart_get_params(pat_unet n, float* d_dst, void* stream);
 pat_status pat_warmstart_set_params(pat_unet n, const float* d_src, void* stream);

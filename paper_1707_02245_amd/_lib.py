@@ -115,6 +115,7 @@ _SIGS = {
                                 C.POINTER(SolveInfo), C.c_void_p], C.c_int),
     "pat_warmstart_create": ([C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.POINTER(C.c_void_p)], C.c_int),
     "pat_warmstart_destroy": ([C.c_void_p], C.c_int),
+    "pat_warmstart_set_gemm_tiles": ([C.c_int32], C.c_int),
     "pat_warmstart_num_params": ([C.c_void_p, C.POINTER(C.c_int64)], C.c_int),
     "pat_warmstart_get_params": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "pat_warmstart_set_params": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),

@@ -582,6 +582,10 @@ __global__ __launch_bounds__(NT) void csr_tiled_kernel(CsrMultiArgs<T> a0, const
       const bool has_next = b + 1 < n_batch;
       int ne0 = 0, ne1 = 0;
       if (has_next) row_range(b + 1, ne0, ne1);
+      // a row without entries stores an exact zero: in a pixel tile that no
+      // arc reaches nothing is staged, and its masked lanes would multiply 0
+      // by whatever the LDS holds (possibly a NaN)
+      const bool row_empty = e0 == e1;
       // one accumulator per slot; each 4 entries of a lane add their products
       // as a fixed tree, so a slot's summation order does not depend on how
       // many slots the launch carries (batched and single solves agree
@@ -633,7 +637,8 @@ __global__ __launch_bounds__(NT) void csr_tiled_kernel(CsrMultiArgs<T> a0, const
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (R == 1 || r < nr) {
-          const Acc sum = LPR == 16 ? row16_sum(acc[r]) : group_sum<64>(acc[r]);
+          const Acc tot = LPR == 16 ? row16_sum(acc[r]) : group_sum<64>(acc[r]);
+          const Acc sum = row_empty ? Acc(0) : tot;
           if (store) {
             const int64_t out = (R == 1 || a.rot <= 1) ? (int64_t)j * nx + i : quarter_turn(i, j, nx, r % a.rot);
             if (WIDE) a.y64[r][out] = (double)sum;

@@ -2,15 +2,17 @@
 // with the step-size rules of Sec. 3.3.2 and the gap stopping rule of
 // Sec. 3.3.3, for one instance or many instances sharing every launch.
 //
-// One iteration is four launches over all active instances:
-//   1. forward gather of ubar with the dual data step fused (q update)
-//   2. regulariser dual step (r, and s for TGV)
-//   3. adjoint scatter of q into per-detector-group partial images
-//   4. primal step (sums the partials, u and v updates, extrapolation)
-// and a check iteration adds: forward gather of u+ with the data and F* terms
-// reduced, the regulariser value reduced, and an ordered final sum per
-// instance. Blocks of iterations are captured once as a HIP graph and
-// replayed; the only device-to-host traffic is the gap sums per block.
+// One iteration is three launches over all active instances:
+//   1. forward gather of ubar with the dual data step fused (q update), and in
+//      the same launch the regulariser's dual step (r, and s for TGV)
+//   2. A^T q into one partial image per quarter turn (stored CSR) or per
+//      detector group (matrix-free scatter)
+//   3. primal step (sums the partials, u and v updates, extrapolation)
+// The last iteration of a block adds the gap: forward gather of u+ with the
+// data and F* terms reduced, the regulariser value reduced, and an ordered
+// final sum per instance. Blocks of iterations are captured once as a HIP
+// graph and replayed; the only device-to-host traffic is the gap sums per
+// block, and stopping is decided there.
 
 #include <chrono>
 #include <cstring>
@@ -227,8 +229,7 @@ class Solver {
     for (auto& ip : inst) alloc_instance(*ip);
     act.clear();
     for (size_t i = 0; i < inst.size(); ++i) act.push_back((int)i);
-    const int per_block = graph_block > 0 ? graph_block : 1;
-    max_checks = per_block / gap_every + 2;
+    max_checks = 1;  // one gap evaluation per block
     results.alloc(sizeof(double) * max_checks * inst.size() * GAP_NSLOTS);
     PAT_HIP(hipHostMalloc((void**)&h_results, sizeof(double) * max_checks * inst.size() * GAP_NSLOTS,
                           hipHostMallocDefault));
@@ -692,11 +693,10 @@ class Solver {
       for (int k : act) cap = std::min(cap, inst[k]->opts.max_iter);
       const int block = graph_block > 0 ? graph_block : gap_every;
       const int steps = std::min(block, cap - n_done);
-      std::vector<int> checks;
-      for (int t = 0; t < steps; ++t) {
-        const int n = n_done + t + 1;
-        if (n % gap_every == 0 || n == cap || t == steps - 1) checks.push_back(t);
-      }
+      // the gap is evaluated once per block, at its last iteration (the
+      // block ends at a multiple of gap_every or at the cap): a check inside
+      // a block could not stop the solve there
+      const std::vector<int> checks(1, steps - 1);
       if (graph_block > 0) {
         PAT_HIP(hipGraphLaunch(graph_for(steps, checks), s));
       } else {

@@ -572,6 +572,14 @@ extern "C" pat_status pat_warmstart_destroy(pat_unet n) {
   });
 }
 
+extern "C" pat_status pat_warmstart_set_gemm_tiles(int32_t mode) {
+  return guarded([&]() -> pat_status {
+    PAT_CHECK_ARG(mode >= 0 && mode <= 3, "gemm tile mode must be 0..3");
+    pat::nn::set_gemm_tiles(mode);
+    return PAT_OK;
+  });
+}
+
 extern "C" pat_status pat_warmstart_num_params(pat_unet n, int64_t* out) {
   return guarded([&]() -> pat_status {
     check_net(n);

@@ -48,6 +48,7 @@ struct GemmDesc {
 };
 
 void launch_gemm(const GemmDesc& d, hipStream_t s);
+void set_gemm_tiles(int mode);
 void launch_splitk_reduce(const float* part, int nsplit, int M, int N, float* out, int permute_cout,
                           hipStream_t s);
 void launch_maxpool(const View& in, const View& out, uint8_t* idx, int B, hipStream_t s);

@@ -14,6 +14,8 @@
 // l supplies A[l%16][4(l/16)+r] and B[4(l/16)+r][l%16] and receives
 // D[4(l/16)+r][l%16], r = 0..3.
 
+#include <climits>
+
 #include "unet_internal.hpp"
 
 namespace pat {
@@ -305,19 +307,26 @@ static void choose_vec(GemmDesc& d) {
   }
 }
 
+// Tile rule of launch_gemm (process-wide): 0 automatic, 1 the largest tile
+// the column count allows, 2 128x64, 3 64x64 (for N > 32; N <= 32 always
+// takes 128x32). Each output element accumulates along k in the same chunks.
+static int g_gemm_tiles = 0;
+void set_gemm_tiles(int mode) { g_gemm_tiles = mode; }
+
 void launch_gemm(const GemmDesc& d_in, hipStream_t s) {
   GemmDesc d = d_in;
   choose_vec(d);
   const int nsplit = (d.K + d.ksplit - 1) / d.ksplit;
   // the largest tile that still gives every CU a few workgroups
+  const int64_t min_blocks = g_gemm_tiles == 1 ? 0 : (g_gemm_tiles >= 2 ? INT64_MAX : 1024);
   auto blocks = [&](int tm, int tn) { return (int64_t)((d.M + tm - 1) / tm) * ((d.N + tn - 1) / tn) * nsplit; };
   if (d.N <= 32) {
     dim3 grid((d.M + 127) / 128, (d.N + 31) / 32, nsplit);
     hipLaunchKernelGGL((gemm_kernel<4, 1, 2, 2>), grid, dim3(256), 0, s, d);
-  } else if (d.N >= 128 && blocks(128, 128) >= 1024) {
+  } else if (d.N >= 128 && blocks(128, 128) >= min_blocks) {
     dim3 grid((d.M + 127) / 128, (d.N + 127) / 128, nsplit);
     hipLaunchKernelGGL((gemm_kernel<2, 2, 4, 4>), grid, dim3(256), 0, s, d);
-  } else if (blocks(128, 64) >= 1024) {
+  } else if (g_gemm_tiles == 2 || blocks(128, 64) >= min_blocks) {
     dim3 grid((d.M + 127) / 128, (d.N + 63) / 64, nsplit);
     hipLaunchKernelGGL((gemm_kernel<2, 2, 4, 2>), grid, dim3(256), 0, s, d);
   } else {

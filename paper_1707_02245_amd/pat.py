@@ -247,7 +247,7 @@ def _opts(max_iter, gap_tol, gap_every, graph_block, theta, gap_box, u0, state_i
     return o
 
 
-def solve(geom: Geometry, f, reg: Reg, max_iter=2000, gap_tol=1e-4, gap_every=10,
+def solve(geom: Geometry, f, reg: Reg, max_iter=2000, gap_tol=1e-4, gap_every=50,
           graph_block=50, theta=1.0, gap_box=2.0, u0=None, state_in=None, state_out=None,
           precond: Precond | None = None, out=None, y0=None):
     """pat_pdhg_solve. Returns (u, info dict, status)."""
@@ -276,7 +276,7 @@ def solve(geom: Geometry, f, reg: Reg, max_iter=2000, gap_tol=1e-4, gap_every=10
     return out, info.as_dict(), st
 
 
-def solve_batched(problems, max_iter=2000, gap_tol=1e-4, gap_every=10, graph_block=50,
+def solve_batched(problems, max_iter=2000, gap_tol=1e-4, gap_every=50, graph_block=50,
                   theta=1.0, gap_box=2.0, states_out=None):
     """pat_pdhg_solve_batched over a list of (geom, f, reg[, precond]) tuples;
     states_out: optional list of state buffers (or None entries).

@@ -493,3 +493,30 @@ def test_psnr_closed_form():
     v = u + 0.1
     assert M.psnr(v, u) == pytest.approx(10 * math.log10(4.0 / 0.01))
     assert M.psnr_as_printed(v, u) == pytest.approx(10 * math.log10(2.0 / 0.01))
+
+
+def test_residual_two_lst_steps_by_hand():
+    """Residual of Sec. 3.3.3, ||u^n - u^(n-1)|| / ||u^(n-1)||, after two LS-T
+    steps worked by hand. A = diag(1, 2), f = (1, 1), alpha = 1; DIAG steps
+    sigma = tau = (1, 1/2); from zero:
+      pixel 1: q1 = -1/2, u1 = 1/4, ubar1 = 1/2; q2 = -1/2, u2 = 3/8
+      pixel 2: q1 = -1/3, u1 = 2/9, ubar1 = 4/9; q2 = -7/27, u2 = 26/81
+    so u2 - u1 = (1/8, 8/81) and the residual is
+      sqrt(1/64 + 64/6561) / sqrt(1/16 + 4/81).
+    A 1-norm, a missing norm in the denominator or a wrong iterate pair gives
+    another number."""
+    A = sp.csr_matrix(np.diag([1.0, 2.0]))
+    p = P.Problem(A, np.array([1.0, 1.0]), 2, 1, "lst", 1.0)
+    pc = P.precond_diag(p)
+    assert np.allclose(pc["sigma_q"], [1.0, 0.5]) and np.allclose(pc["tau_u"], [1.0, 0.5])
+    st = P.init_state(p)
+    P.pdhg_step(p, pc, st)
+    assert np.allclose(st["q"], [-1 / 2, -1 / 3], rtol=0, atol=1e-15)
+    assert np.allclose(st["u"], [1 / 4, 2 / 9], rtol=0, atol=1e-15)
+    assert np.allclose(st["ubar"], [1 / 2, 4 / 9], rtol=0, atol=1e-15)
+    assert math.isinf(P.residual(st))  # u^0 = 0: no relative change defined
+    P.pdhg_step(p, pc, st)
+    assert np.allclose(st["q"], [-1 / 2, -7 / 27], rtol=0, atol=1e-15)
+    assert np.allclose(st["u"], [3 / 8, 26 / 81], rtol=0, atol=1e-15)
+    want = math.sqrt(1 / 64 + 64 / 6561) / math.sqrt(1 / 16 + 4 / 81)
+    assert P.residual(st) == pytest.approx(want, rel=1e-14)
