@@ -87,6 +87,10 @@ def parse():
     p.add_argument("--apply-reps", type=int, default=50)
     p.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     p.add_argument("--no-batched", action="store_true", help="skip the batched leg")
+    p.add_argument("--no-fused", action="store_true",
+                   help="skip the per-kernel timing of 64 batched 512^2 TGV instances")
+    p.add_argument("--no-extra-adjoints", action="store_true",
+                   help="skip A^T at full storage (256^2) and at the 512^2 limited-angle workload")
     p.add_argument("--no-learned", action="store_true", help="skip the learned warm-start leg")
     p.add_argument("--no-sweep", action="store_true", help="skip the uneven-size batched sweep leg")
     p.add_argument("--learned-seeds", type=int, default=2,
@@ -118,12 +122,13 @@ def make_inputs(pat, torch, seed):
 
 
 def time_apply(fn, reps, torch, trials=3):
-    """Average duration of fn() on the current stream, by HIP events: the best
-    of `trials` runs of `reps` launches each (right after a long solve a
-    single run sometimes reads 15-30% slow)."""
+    """Average duration of fn() on the current stream (the stream the library
+    launches on), by HIP events: the mean over `trials` runs of `reps`
+    launches each, after one untimed launch. The timed launches are the ones
+    a kernel trace of this command lists after the autotuner's."""
     fn()
     torch.cuda.synchronize()
-    best = float("inf")
+    total = 0.0
     for _ in range(trials):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -132,8 +137,116 @@ def time_apply(fn, reps, torch, trials=3):
             fn()
         e1.record()
         torch.cuda.synchronize()
-        best = min(best, e0.elapsed_time(e1) / reps * 1e-3)
-    return best
+        total += e0.elapsed_time(e1) * 1e-3
+    return total / (trials * reps)
+
+
+def tiled_adjoint_bytes(info, n, n_det, n_t, esz):
+    """Algorithmic bytes of one A^T pass by the tiled stored CSR: values and
+    16-bit window offsets per stored non-zero, row offsets, the per-(tile,
+    stored detector) windows, the data once and the partial images once."""
+    rot, side, nnz = info["csr_rot"], info["csr_tile_side"], info["csr_nnz"]
+    n_tiles = -(-n // side) ** 2
+    return (nnz * (esz + 2) + 8 * (n * n + 1) + 16 * n_tiles * (n_det // rot)
+            + esz * (n_det * n_t + rot * n * n))
+
+
+def extra_adjoints(pat, torch, tdt, esz, reps):
+    """A^T by the tiled stored CSR where the ring gives no quarter turns to
+    use: the 256^2 workload stored in full, and the 512^2 limited-angle
+    workload (128 detectors over 90 degrees x 1024 samples)."""
+    import phantoms
+    out = {}
+    for name, (n, n_det, n_t, span, sym) in {
+            "tgv256_full_storage": (256, 256, 512, 2 * math.pi, False),
+            "dtv512": (512, 128, 1024, math.pi / 2, True)}.items():
+        g = pat.Geometry(dtype=tdt, **phantoms.geometry_desc(n, n_det, n_t, arc_span=span))
+        if not sym:
+            g.set_symmetry(False)
+        info = g.refresh_info()
+        y = torch.randn(n_det, n_t, dtype=tdt, device="cuda")
+        parts = torch.zeros((info["csr_rot"], n, n), dtype=tdt, device="cuda")
+        t = time_apply(lambda: g.adjoint_partials(y, parts), reps, torch)
+        byt = tiled_adjoint_bytes(info, n, n_det, n_t, esz)
+        tname = "double" if esz == 8 else "float"
+        kname = (f"csr_tiled_kernel<{tname}, false, {1 if info['csr_rot'] == 1 else 4}, "
+                 f"{64 * info['csr_waves']}, {info['csr_lanes']}>")
+        out[name] = dict(kernel=kname, csr_nnz=info["csr_nnz"], csr_rot=info["csr_rot"],
+                         tile_side=info["csr_tile_side"], bytes=byt, avg_launch_us=t * 1e6,
+                         gbs=byt / t * 1e-9, frac_of_hbm=byt / t * 1e-9 / HBM_PEAK_GBS,
+                         traffic=measured_traffic(f"{name}:{kname}"))
+        g.close()
+        del parts, y
+        torch.cuda.empty_cache()
+    return out
+
+
+def fused_step_leg(pat, torch, args, n_inst=64, reps=20):
+    """The solver's pixel kernels over a batch whose state is far larger than
+    the caches: n_inst TGV instances of 512^2 on the limited-angle geometry
+    (each with its own step sizes), FP64. Times each launch of the iteration
+    (pat_pdhg_kernel_times) and rates the regulariser's dual step and the
+    primal step against HBM by the bytes they must move: dual step 15 arrays
+    (reads ubar, vbar x2, r x2, s x3, sigma_r, sigma_s; writes r x2, s x3),
+    primal step 16 + R arrays (reads the R partial images of A^T q, u, tau_u,
+    r x2, s x3, v x2, tau_v; writes u, ubar, v x2, vbar x2), 8 bytes each per
+    pixel; neighbour reads of the stencils come from the caches."""
+    import phantoms
+    n, n_det, n_t = 512, 128, 1024
+    g = pat.Geometry(dtype=torch.float64, **phantoms.geometry_desc(n, n_det, n_t, arc_span=math.pi / 2))
+    rot = g.info["csr_rot"]
+    rng = np.random.default_rng([args.seed, 9])
+    problems = []
+    for i in range(n_inst):
+        f = torch.tensor(rng.standard_normal((n_det, n_t)) * 0.01, dtype=torch.float64, device="cuda")
+        problems.append((g, f, pat.Reg("tgv", 0.02, 0.04)))
+    t = pat.kernel_times(problems, reps=reps)
+    px = n_inst * n * n
+    b_dual = 15 * 8 * px
+    b_primal = (16 + rot) * 8 * px
+    state_bytes = n_inst * (8 * n * n * (1 + 1 + 1 + 2 + 2 + 2 + 3 + rot + 1 + 1 + 1 + 1)
+                            + 8 * n_det * n_t * 3)
+    res = dict(instances=n_inst, image=f"{n}x{n}", geometry=f"{n_det} detectors over 90 deg x {n_t}",
+               regulariser="tgv", dtype="f64", aggregate_state_bytes=state_bytes,
+               reg_dual_us=t["reg_dual_ms"] * 1e3, primal_us=t["primal_ms"] * 1e3,
+               forward_with_dual_steps_us=t["forward_dual_ms"] * 1e3, adjoint_us=t["adjoint_ms"] * 1e3,
+               reg_dual_bytes=b_dual, primal_bytes=b_primal,
+               reg_dual_gbs=b_dual / (t["reg_dual_ms"] * 1e-3) * 1e-9,
+               primal_gbs=b_primal / (t["primal_ms"] * 1e-3) * 1e-9)
+    res["reg_dual_frac_of_hbm"] = res["reg_dual_gbs"] / HBM_PEAK_GBS
+    res["primal_frac_of_hbm"] = res["primal_gbs"] / HBM_PEAK_GBS
+    res["step_gbs"] = (b_dual + b_primal) / ((t["reg_dual_ms"] + t["primal_ms"]) * 1e-3) * 1e-9
+    res["step_frac_of_hbm"] = res["step_gbs"] / HBM_PEAK_GBS
+    res["reg_dual_traffic"] = measured_traffic("fused64:reg_dual_kernel<double>")
+    res["primal_traffic"] = measured_traffic("fused64:primal_kernel<double, false>")
+    del problems
+    g.close()
+    torch.cuda.empty_cache()
+    return res
+
+
+def host_cpu():
+    """Host cores and CPU model (lscpu "Model name", else /proc/cpuinfo)."""
+    import subprocess
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    if model is None:
+        try:
+            with open("/proc/cpuinfo") as fh:
+                for line in fh:
+                    if line.startswith("model name"):
+                        model = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+    return os.cpu_count(), model
 
 
 def batched_leg(pat, torch, g, wl, fc, reg, pc, args, tdt, n_wl=4):
@@ -290,7 +403,9 @@ def cpu_baseline(desc, f, wl, gpu_iters, budget_s=20.0):
     scale = wl.n_det / n_sub
     # two A-applies per iteration in the subset step; add the other detectors
     t_iter = t_iter_sub + (scale - 1.0) * t_apply_sub
+    host_cores, cpu_model = host_cpu()
     return dict(value=t_iter * gpu_iters, unit="s", cores=1, kind="oracle",
+                host_cores=host_cores, cpu_model=cpu_model,
                 sample=(f"FP64 oracle (SciPy CSR, single thread): {its} PDHG iterations of the "
                         f"256^2 TGV workload with the rows of {n_sub} of 256 detectors plus "
                         f"{reps} A/A^T applies of that subset, scaled to 256 detectors and to "
@@ -329,6 +444,23 @@ def main():
         return pat.solve(g, f, reg, max_iter=args.cap, gap_tol=wl.gap_tol,
                          gap_every=args.gap_every, graph_block=args.gap_every, precond=pc)
 
+    # operator applies, before the long solve: HIP events on the stream the
+    # library launches on. The kernels the solver runs are timed alone: the
+    # forward gather on the zero-bordered image (no padding pass) and A^T into
+    # its partial images (the solver sums them in its primal update).
+    u = torch.randn(wl.n, wl.n, dtype=tdt, device="cuda")
+    upad = torch.zeros(wl.n + 2, wl.n + 2, dtype=tdt, device="cuda")
+    upad[1:-1, 1:-1] = u
+    y = torch.randn(wl.n_det, wl.n_t, dtype=tdt, device="cuda")
+    fo = g.data()
+    ao = g.image()
+    rot = info_g["csr_rot"]
+    parts = torch.zeros((rot, wl.n, wl.n), dtype=tdt, device="cuda")
+    t_fwd = time_apply(lambda: g.forward_padded(upad, fo), args.apply_reps, torch)
+    t_adj = time_apply(lambda: g.adjoint_partials(y, parts), args.apply_reps, torch)
+    t_adj_sum = time_apply(lambda: g.adjoint(y, ao), args.apply_reps, torch)
+    log(f"applies: forward {t_fwd * 1e6:.1f} us, A^T {t_adj * 1e6:.1f} us (summed {t_adj_sum * 1e6:.1f} us)")
+
     for w in range(args.warmup):
         _, info, st = step()
         log(f"warmup {w}: iters {info['iters']} rel_gap {info['rel_gap']:.3e} "
@@ -350,21 +482,6 @@ def main():
     _, info_cap, _ = pat.solve(g, f, reg, max_iter=wl.max_iter, gap_tol=wl.gap_tol,
                                gap_every=args.gap_every, graph_block=args.gap_every, precond=pc)
 
-    # operator applies: HIP events on the stream the library launches on. The
-    # kernels the solver runs are timed alone: the forward gather on the
-    # zero-bordered image (no padding pass) and A^T into its partial images
-    # (the solver sums them in its primal update).
-    u = torch.randn(wl.n, wl.n, dtype=tdt, device="cuda")
-    upad = torch.zeros(wl.n + 2, wl.n + 2, dtype=tdt, device="cuda")
-    upad[1:-1, 1:-1] = u
-    y = torch.randn(wl.n_det, wl.n_t, dtype=tdt, device="cuda")
-    fo = g.data()
-    ao = g.image()
-    rot = info_g["csr_rot"]
-    parts = torch.zeros((rot, wl.n, wl.n), dtype=tdt, device="cuda")
-    t_fwd = time_apply(lambda: g.forward_padded(upad, fo), args.apply_reps, torch)
-    t_adj = time_apply(lambda: g.adjoint_partials(y, parts), args.apply_reps, torch)
-    t_adj_sum = time_apply(lambda: g.adjoint(y, ao), args.apply_reps, torch)
     n_win = info_g["n_window"]
     nnz = info_g["csr_nnz"]
     n_pix, n_bins = wl.n * wl.n, wl.n_det * wl.n_t
@@ -373,12 +490,7 @@ def main():
     lanes = 1 << info_g["fwd_lanes_log2"]
     waves, row_lanes = info_g["csr_waves"], info_g["csr_lanes"]
     if side:
-        # algorithmic bytes of one A^T pass by the tiled CSR: values + 16-bit
-        # window offsets + row offsets + the per-(tile, stored detector)
-        # windows, the data once and the rot partial images once
-        n_tiles = -(-wl.n // side) ** 2
-        adj_bytes = (nnz * (esz + 2) + 8 * (n_pix + 1) + 16 * n_tiles * (wl.n_det // rot)
-                     + esz * (n_bins + rot * n_pix))
+        adj_bytes = tiled_adjoint_bytes(info_g, wl.n, wl.n_det, wl.n_t, esz)
         akname = (f"csr_tiled_kernel<{tname}, false, {1 if rot == 1 else 4}, {64 * waves}, {row_lanes}> "
                   f"(A^T by the stored CSR, {side}x{side} pixel tiles, LDS-staged input, {rot} quarter-turn slots)")
     else:
@@ -397,6 +509,8 @@ def main():
                  adjoint_full_csr_equivalent_gbs=full_csr_equiv / t_adj * 1e-9,
                  adjoint_kernel=akname,
                  adjoint_traffic=measured_traffic(akname) if (wl.name == "tgv256" and esz == 8) else None)
+    if not args.no_extra_adjoints:
+        apply["adjoint_other_workloads"] = extra_adjoints(pat, torch, tdt, esz, args.apply_reps)
     log(f"apply: {apply}")
     peak = FP64_VECTOR_PEAK_TFLOPS if esz == 8 else FP32_VECTOR_PEAK_TFLOPS
     if t_fwd >= t_adj:
@@ -451,6 +565,10 @@ def main():
         "apply": apply,
         "roofline": roofline,
     }
+    if not args.no_fused:
+        log("fused-step leg: 64 TGV instances of 512^2 in one batch, per-kernel times")
+        out["fused_step"] = fused_step_leg(pat, torch, args)
+        log(f"fused step: {out['fused_step']}")
     if not args.no_batched:
         log("batched leg: 4 wavelengths sharing the geometry")
         out["batched"] = batched_leg(pat, torch, g, wl, fc_np, reg, pc, args, tdt)

@@ -305,6 +305,23 @@ pat_status pat_pdhg_solve_batched(int32_t n, const pat_geometry* g, const void* 
                                   const pat_regulariser* reg, const pat_solve_opts* opts,
                                   void* const* d_u_out, pat_solve_info* info, void* stream);
 
+/* Per-kernel timing of the solver's iteration (a benchmark and tuning hook):
+ * sets up the n instances as pat_pdhg_solve_batched does (zero start; each
+ * instance's own step sizes unless opts[i].precond is given), then times
+ * each launch of an iteration with HIP events on `stream`, `reps` launches
+ * after one untimed launch, and writes the average per launch in ms:
+ *   ms[0] the forward launch (A ubar with the dual data step, Sec. 3.2 prox of
+ *         F1*, and the regulariser's dual step in the same launch),
+ *   ms[1] the regulariser's dual step alone (r, and s for TGV),
+ *   ms[2] A^T q into the partial images,
+ *   ms[3] the primal step (u, v and the extrapolation).
+ * Every launch covers all instances. The state the timed launches leave is
+ * discarded. Arguments as pat_pdhg_solve_batched (d_u0, d_y0 and d_state_in
+ * must be NULL); reps >= 1. Synchronous on return. */
+pat_status pat_pdhg_kernel_times(int32_t n, const pat_geometry* g, const void* const* d_f,
+                                 const pat_regulariser* reg, const pat_solve_opts* opts,
+                                 int32_t reps, double* ms, void* stream);
+
 /* ---- Learned warm start -------------------------------------------------
  * A U-Net (`levels` levels, base_ch channels at the top, doubling per level;
  * 3x3 convolutions with ReLU, 2x2 max pooling, 2x2 stride-2 transposed

@@ -113,6 +113,9 @@ _SIGS = {
     "pat_pdhg_solve_batched": ([C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                 C.POINTER(Regulariser), C.POINTER(SolveOpts), C.POINTER(C.c_void_p),
                                 C.POINTER(SolveInfo), C.c_void_p], C.c_int),
+    "pat_pdhg_kernel_times": ([C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                               C.POINTER(Regulariser), C.POINTER(SolveOpts), C.c_int32,
+                               C.POINTER(C.c_double), C.c_void_p], C.c_int),
     "pat_warmstart_create": ([C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.POINTER(C.c_void_p)], C.c_int),
     "pat_warmstart_destroy": ([C.c_void_p], C.c_int),
     "pat_warmstart_set_gemm_tiles": ([C.c_int32], C.c_int),

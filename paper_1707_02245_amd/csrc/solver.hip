@@ -523,6 +523,13 @@ class Solver {
 
   void enqueue_iteration(bool check, int c) {
     launch_forward_reg_batched<T>(L, lanes_log2, s);
+    enqueue_adjoint(check);
+    launch_primal<T>(L, check, s);
+    if (check) enqueue_gap(c);
+  }
+
+  // A^T q of every active instance into its partial images
+  void enqueue_adjoint(bool check) {
     if (L.n_adj > 0) launch_adjoint_batched<T>(L, s);
     if (L.n_csr > 0) {
       // check iterations: A^T q once more with FP64 accumulation for the gap
@@ -536,8 +543,6 @@ class Solver {
                                      L.csr_total, s, wide != 0, L.csr_max_rhs);
       }
     }
-    launch_primal<T>(L, check, s);
-    if (check) enqueue_gap(c);
   }
 
   void init_state() {
@@ -834,6 +839,61 @@ static pat_status solve_impl(int n, const pat_geometry* g, const void* const* d_
   return st;
 }
 
+// Average duration (ms) of each launch of the solver's iteration, by HIP
+// events over `reps` launches after one untimed launch, on instances set up
+// as the batched solver sets them up (zero start).
+template <class T>
+static void kernel_times_impl(int n, const pat_geometry* g, const void* const* d_f, const pat_regulariser* reg,
+                              const pat_solve_opts* opts, int reps, double* ms, void* stream) {
+  hipStream_t owned = nullptr;
+  hipStream_t s = solve_stream(stream, &owned);
+  struct StreamGuard {
+    hipStream_t h;
+    ~StreamGuard() {
+      if (h) { (void)hipStreamSynchronize(h); (void)hipStreamDestroy(h); }
+    }
+  } guard{owned};
+  Solver<T> S;
+  S.gap_every = opts[0].gap_every;
+  S.graph_block = opts[0].graph_block;
+  for (int i = 0; i < n; ++i) {
+    auto I = std::make_unique<Inst<T>>();
+    I->g = g[i];
+    I->reg = reg[i];
+    I->opts = opts[i];
+    I->f = static_cast<const T*>(d_f[i]);
+    S.inst.push_back(std::move(I));
+  }
+  S.setup(s);
+  S.build_launch();
+  S.init_state();
+  hipEvent_t e0, e1;
+  PAT_HIP(hipEventCreate(&e0));
+  PAT_HIP(hipEventCreate(&e1));
+  auto timeit = [&](auto&& fn) {
+    fn();
+    PAT_HIP(hipEventRecord(e0, s));
+    for (int k = 0; k < reps; ++k) fn();
+    PAT_HIP(hipEventRecord(e1, s));
+    PAT_HIP(hipEventSynchronize(e1));
+    float t = 0.f;
+    PAT_HIP(hipEventElapsedTime(&t, e0, e1));
+    return (double)t / reps;
+  };
+  try {
+    ms[0] = timeit([&] { launch_forward_reg_batched<T>(S.L, S.lanes_log2, s); });
+    ms[1] = timeit([&] { launch_reg_dual<T>(S.L, s); });
+    ms[2] = timeit([&] { S.enqueue_adjoint(false); });
+    ms[3] = timeit([&] { launch_primal<T>(S.L, false, s); });
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
 static void validate_instance(pat_geometry g, const void* f, const pat_regulariser* reg,
                               const pat_solve_opts* o, void* u) {
   PAT_CHECK_ARG(g != nullptr, "geometry is NULL");
@@ -940,5 +1000,29 @@ extern "C" pat_status pat_pdhg_solve_batched(int32_t n, const pat_geometry* g, c
     if (g[0]->dtype == PAT_F64)
       return pat::solve_impl<double>(n, g, d_f, reg, opts, d_u_out, info, stream);
     return pat::solve_impl<float>(n, g, d_f, reg, opts, d_u_out, info, stream);
+  });
+}
+
+extern "C" pat_status pat_pdhg_kernel_times(int32_t n, const pat_geometry* g, const void* const* d_f,
+                                            const pat_regulariser* reg, const pat_solve_opts* opts,
+                                            int32_t reps, double* ms, void* stream) {
+  return guarded([&]() -> pat_status {
+    PAT_CHECK_ARG(n >= 1, "n must be >= 1");
+    PAT_CHECK_ARG(reps >= 1, "reps must be >= 1");
+    PAT_CHECK_ARG(g && d_f && reg && opts && ms, "NULL array");
+    for (int i = 0; i < n; ++i) {
+      PAT_CHECK_ARG(g[i] != nullptr && d_f[i] != nullptr, "NULL geometry or data");
+      pat::validate_regulariser(g[i], &reg[i]);
+      PAT_CHECK_ARG(opts[i].d_u0 == nullptr && opts[i].d_y0 == nullptr && opts[i].d_state_in == nullptr,
+                    "kernel timing starts from zero (no warm start or state)");
+      PAT_CHECK_ARG(opts[i].gap_every >= 1 && opts[i].graph_block >= 0, "bad gap_every or graph_block");
+      if (opts[i].precond)
+        PAT_CHECK_ARG(opts[i].precond->g == g[i] && opts[i].precond->reg_kind == reg[i].kind,
+                      "precond handle was made for another geometry or regulariser");
+      PAT_CHECK_ARG(g[i]->dtype == g[0]->dtype, "one element type for all instances");
+    }
+    if (g[0]->dtype == PAT_F64) pat::kernel_times_impl<double>(n, g, d_f, reg, opts, reps, ms, stream);
+    else pat::kernel_times_impl<float>(n, g, d_f, reg, opts, reps, ms, stream);
+    return PAT_OK;
   });
 }

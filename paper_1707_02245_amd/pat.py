@@ -306,3 +306,25 @@ def solve_batched(problems, max_iter=2000, gap_tol=1e-4, gap_every=50, graph_blo
                         so, pc)
     st = L.check(L.load().pat_pdhg_solve_batched(n, geoms, fs, regs, opts, outs, infos, _stream()))
     return us, [infos[i].as_dict() for i in range(n)], st
+
+
+def kernel_times(problems, reps=20, gap_every=50, graph_block=50):
+    """pat_pdhg_kernel_times over a list of (geom, f, reg[, precond]) tuples:
+    average ms per launch of the solver's forward launch (with both dual
+    steps), the regulariser dual step alone, A^T and the primal step."""
+    n = len(problems)
+    geoms = (C.c_void_p * n)()
+    fs = (C.c_void_p * n)()
+    regs = (L.Regulariser * n)()
+    opts = (L.SolveOpts * n)()
+    for i, p in enumerate(problems):
+        g, f, reg = p[0], p[1], p[2]
+        pc = p[3] if len(p) > 3 else None
+        _need(f, g.dtype, g.n_det * g.n_t, f"f[{i}]")
+        geoms[i] = g.handle.value
+        fs[i] = f.data_ptr()
+        regs[i] = reg.c_struct()
+        opts[i] = _opts(1, 0.0, gap_every, graph_block, 1.0, 2.0, None, None, None, pc)
+    ms = (C.c_double * 4)()
+    L.check(L.load().pat_pdhg_kernel_times(n, geoms, fs, regs, opts, reps, ms, _stream()))
+    return dict(forward_dual_ms=ms[0], reg_dual_ms=ms[1], adjoint_ms=ms[2], primal_ms=ms[3])

@@ -494,10 +494,12 @@ def _assert_gap_terms(info, p, ref, kind, dt):
     assert abs(info["fstar"] - g_ref["Fstar"]) <= (1e-10 if f64 else 1e-5) * g_ref["P"]
     # the library reports ||A^T q||^2 for LS-T (the oracle's R is that over 2 alpha)
     kty = info["kty_l1"] / (2.0 * p.lam) if kind == "tikhonov" else info["kty_l1"]
-    assert kty == pytest.approx(g_ref["R"], rel=1e-8 if f64 else 2e-2)
+    assert kty == pytest.approx(g_ref["R"], rel=1e-8 if f64 else 1e-4)
     # near convergence the gap is a small difference of O(P) terms: compare on the scale of P
     assert abs(info["gap"] - g_ref["gap"]) <= (1e-10 if f64 else 1e-5) * g_ref["P"]
-    assert info["residual"] == pytest.approx(res_ref, rel=1e-8 if f64 else 5e-2)
+    # FP32: the change of u over one iteration is a difference of nearly
+    # equal FP32 values (measured 6e-5 relative on the LS-T state)
+    assert info["residual"] == pytest.approx(res_ref, rel=1e-8 if f64 else 1e-3)
 
 
 @pytest.mark.parametrize("adj", ["tiled", "csr", "scatter"])
