@@ -204,6 +204,21 @@ pat_status pat_forward_padded(pat_geometry g, const void* d_upad, void* d_f, voi
  * scatter): PAT_ERR_UNSUPPORTED. */
 pat_status pat_adjoint_partials(pat_geometry g, const void* d_f, void* d_parts, void* stream);
 
+/* pat_adjoint for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same result bit for bit, with the partial images that
+ * pat_adjoint sums into d_u kept in a fixed 16 MiB device array of the
+ * library (one per GPU, held until the process ends) instead of memory the
+ * geometry allocates on first use. Nothing is allocated.
+ * Needs csr_rot * N (stored A^T) or detector groups * N (matrix-free scatter)
+ * elements of scratch, none when pat_adjoint writes d_u directly; more than
+ * 16 MiB -> PAT_ERR_INVALID_ARG. The stored A^T must already exist in modes 1
+ * and 2 (geometry creation or pat_geometry_set_adjoint builds it), else
+ * PAT_ERR_INVALID_ARG. Calls on one GPU share its array: calls that overlap
+ * in time on one GPU (different streams or host threads) race; calls ordered
+ * on one stream do not. Arguments as pat_adjoint. */
+pat_status pat_adjoint_noalloc(pat_geometry g, const void* d_f, void* d_u, void* stream);
+
 /* Regulariser (Sec. 2.1, 2.2; Sec. 3.1 eqs. PD_TV, PD_TGV).
  *  TV      : lambda ||grad u||_{2,1}
  *  TGV     : lambda ||grad u - v||_{2,1} + tgv_alpha0 ||E v||_{F,1}

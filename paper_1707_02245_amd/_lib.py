@@ -102,6 +102,7 @@ _SIGS = {
                                C.POINTER(AutotuneResult)], C.c_int),
     "pat_forward": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "pat_adjoint": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "pat_adjoint_noalloc": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "pat_forward_padded": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "pat_adjoint_partials": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "pat_precond": ([C.c_void_p, C.POINTER(Regulariser), C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),

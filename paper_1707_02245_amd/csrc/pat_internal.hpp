@@ -151,6 +151,13 @@ template <class T>
 void apply_forward(pat_geometry_s* g, const T* u, T* f, hipStream_t s);
 template <class T>
 void apply_adjoint(pat_geometry_s* g, const T* f, T* u, hipStream_t s);
+// Bytes of partial images the stand-alone A^T sums into its output (0: it
+// writes the output directly), and A^T with those partials in caller-given
+// device memory (nothing allocated; the stored A^T must already exist in
+// modes 1 and 2).
+size_t adjoint_scratch_bytes(const pat_geometry_s* g);
+template <class T>
+void apply_adjoint_scratch(pat_geometry_s* g, const T* f, T* u, T* scratch, hipStream_t s);
 
 // ---- stored A^T (csr.hip)
 template <class T>

@@ -749,10 +749,18 @@ void forward_padded_impl(pat_geometry g, const void* d_upad, void* d_f, hipStrea
   pat::launch_forward<T>(pat::FWD_PLAIN, a, g->lanes_log2, s);
 }
 
-// parts: csr_rot partial images (or null: sum into d_u)
+// parts: csr_rot partial images (or null: sum into d_u). scratch: device
+// memory for the partial images that are summed into d_u (at least
+// pat::adjoint_scratch_bytes(g) bytes), or null to use the geometry's own
+// (allocated on first use); with a scratch given nothing is allocated and a
+// missing stored A^T is an error instead of being built.
 template <class T>
-void adjoint_impl(pat_geometry g, const void* d_f, void* d_u, hipStream_t s, T* parts = nullptr) {
-  if (g->adj_mode != 0) g->ensure_csr(s);
+void adjoint_impl(pat_geometry g, const void* d_f, void* d_u, hipStream_t s, T* parts = nullptr,
+                  T* scratch = nullptr) {
+  if (g->adj_mode != 0) {
+    if (scratch) PAT_CHECK_ARG(g->csr_nnz >= 0, "the stored A^T is not built (pat_geometry_set_adjoint builds it)");
+    else g->ensure_csr(s);
+  }
   const int mode = g->effective_adj_mode();
   if (mode != 0) {
     const int64_t N = g->n_pix();
@@ -771,8 +779,12 @@ void adjoint_impl(pat_geometry g, const void* d_f, void* d_u, hipStream_t s, T* 
     // with quarter turns each slot writes a partial image, summed in order
     T* part = parts ? parts : static_cast<T*>(d_u);
     if (rot > 1 && !parts) {
-      g->scratch_part.ensure(sizeof(T) * (size_t)rot * N);
-      part = pat::ptr<T>(g->scratch_part);
+      if (scratch) {
+        part = scratch;
+      } else {
+        g->scratch_part.ensure(sizeof(T) * (size_t)rot * N);
+        part = pat::ptr<T>(g->scratch_part);
+      }
     }
     for (int r = 0; r < rot; ++r) {
       c.x[r] = static_cast<const T*>(d_f) + (int64_t)r * c.n_det * g->n_t;
@@ -810,8 +822,12 @@ void adjoint_impl(pat_geometry g, const void* d_f, void* d_u, hipStream_t s, T* 
     pat::launch_adjoint<T>(a, s);
     return;
   }
-  g->scratch_part.ensure(sizeof(T) * (size_t)ng * g->n_pix());
-  a.part = pat::ptr<T>(g->scratch_part);
+  if (scratch) {
+    a.part = scratch;
+  } else {
+    g->scratch_part.ensure(sizeof(T) * (size_t)ng * g->n_pix());
+    a.part = pat::ptr<T>(g->scratch_part);
+  }
   pat::launch_adjoint<T>(a, s);
   pat::launch_reduce_groups<T>(a.part, static_cast<T*>(d_u), ng, g->n_pix(), s);
 }
@@ -819,6 +835,19 @@ void adjoint_impl(pat_geometry g, const void* d_f, void* d_u, hipStream_t s, T* 
 }  // namespace
 
 namespace pat {
+size_t adjoint_scratch_bytes(const pat_geometry_s* g) {
+  const size_t es = dtype_size(g->dtype);
+  if (g->adj_mode != 0 && g->effective_adj_mode() != 0)
+    return g->csr_rot > 1 ? es * (size_t)g->csr_rot * (size_t)g->n_pix() : 0;
+  const int ng = g->n_groups();
+  return ng > 1 ? es * (size_t)ng * (size_t)g->n_pix() : 0;
+}
+template <class T>
+void apply_adjoint_scratch(pat_geometry g, const T* f, T* u, T* scratch, hipStream_t s) {
+  adjoint_impl<T>(g, f, u, s, nullptr, scratch);
+}
+template void apply_adjoint_scratch<float>(pat_geometry, const float*, float*, float*, hipStream_t);
+template void apply_adjoint_scratch<double>(pat_geometry, const double*, double*, double*, hipStream_t);
 template <class T>
 void apply_forward(pat_geometry g, const T* u, T* f, hipStream_t s) { forward_impl<T>(g, u, f, s); }
 template <class T>
