@@ -22,6 +22,13 @@ Step sizes (Sec. 3.3.2):
            iteration (1000 steps) times 1.05 (the top of the gradient's spectrum is
            clustered, so the power estimate approaches from below slowly).
 
+Accelerated PDHGM (Sec. 3.3 mentions the O(1/n^2) rate of Chambolle and
+Pock's Algorithm 2 when part of the objective is uniformly convex):
+accel_schedule gives per-iteration multipliers of the primal and dual steps
+and the extrapolation theta_n. The rate holds for LS-T, whose G is strongly
+convex; for TV, TGV and dTV (G = 0) a positive gamma only makes the schedule
+shift weight from the primal to the dual steps until its bound freezes it.
+
 Gap (Sec. 3.3.3): with G = 0 the conjugate G* is the indicator of {0}, so the
 printed gap is infinite until K^T y = 0 exactly. The gap used restricts x to the
 box ||x||_inf <= C, whose conjugate is C ||.||_1:
@@ -210,10 +217,18 @@ def init_state(p: Problem, u0=None) -> dict:
     return st
 
 
-def pdhg_step(p: Problem, pc: dict, st: dict, theta: float = 1.0) -> None:
+def pdhg_step(p: Problem, pc: dict, st: dict, theta: float = 1.0,
+              dual_mult: float = 1.0, primal_mult: float = 1.0) -> None:
     """One iteration: the dual steps at (ubar[, vbar]), then the primal steps,
-    then the extrapolation (Algorithm 1 for tv/dtv, Algorithm 2 for tgv)."""
+    then the extrapolation (Algorithm 1 for tv/dtv, Algorithm 2 for tgv).
+
+    dual_mult and primal_mult scale every dual step size (sigma) and every
+    primal step size (tau) of this iteration; the accelerated variant varies
+    them from one iteration to the next (see accel_schedule)."""
     A, N = p.A, p.N
+    if dual_mult != 1.0 or primal_mult != 1.0:
+        pc = {k: (v * primal_mult if k.startswith("tau") else v * dual_mult)
+              for k, v in pc.items() if k.startswith(("tau", "sigma"))}
     sq = pc["sigma_q"]
     # q^{n+1} = prox_{sigma1 F1*}(q^n + sigma1 K ubar^n)
     st["q"] = prox_f1_conj(st["q"] + sq * (A @ st["ubar"]), p.f, sq)
@@ -243,6 +258,34 @@ def pdhg_step(p: Problem, pc: dict, st: dict, theta: float = 1.0) -> None:
     st["n"] += 1
 
 
+def accel_schedule(gamma: float, step_max: float):
+    """Step multipliers of the accelerated PDHGM (Chambolle and Pock's
+    Algorithm 2, the O(1/n^2) variant that Sec. 3.3 mentions), applied to the
+    preconditioned steps: iteration n takes the dual steps b_n Sigma and the
+    primal steps a_n T, then extrapolates with theta_n, where
+
+      a_0 = b_0 = 1,  theta_n = 1 / sqrt(1 + 2 gamma a_n),
+      a_{n+1} = theta_n a_n,  b_{n+1} = b_n / theta_n   (so a_n b_n = 1).
+
+    gamma is the modulus of strong convexity of G in the metric of T (for
+    G = alpha/2 ||u||^2 with diagonal T: alpha min_j T_jj). The first
+    update that would take b above step_max is not made: from then on
+    theta_n = 1 and a_n, b_n stay fixed, i.e. plain PDHGM with the steps
+    (a T, b Sigma), whose product is unchanged, so the iteration converges to
+    a saddle point of the same problem. Yields (b_n, a_n, theta_n)."""
+    a = b = 1.0
+    frozen = gamma <= 0.0
+    while True:
+        th = 1.0
+        if not frozen:
+            th = 1.0 / np.sqrt(1.0 + 2.0 * gamma * a)
+            if b / th > step_max:
+                frozen, th = True, 1.0
+        yield b, a, th
+        if not frozen:
+            a, b = th * a, b / th
+
+
 def residual(st: dict) -> float:
     """||u^n - u^{n-1}|| / ||u^{n-1}|| (Sec. 3.3.3, norm in the denominator)."""
     prev = st.get("u_prev")
@@ -254,14 +297,22 @@ def residual(st: dict) -> float:
 
 def pdhg_solve(p: Problem, pc: dict, iters: int | None = None, tol: float | None = None,
                max_iter: int = 2000, gap_every: int = 10, box: float = 2.0,
-               u0=None, theta: float = 1.0, state: dict | None = None) -> dict:
+               u0=None, theta: float = 1.0, state: dict | None = None,
+               accel_gamma: float = 0.0, accel_step_max: float = 1.0) -> dict:
     """Run PDHGM for a fixed number of iterations, or until rel_gap <= tol
-    (checked every gap_every iterations, capped at max_iter)."""
+    (checked every gap_every iterations, capped at max_iter). With
+    accel_gamma > 0 the step sizes and the extrapolation follow
+    accel_schedule (theta is then 1 after the schedule freezes)."""
     st = state if state is not None else init_state(p, u0)
     history = []
     n_target = iters if iters is not None else max_iter
+    sched = accel_schedule(accel_gamma, accel_step_max) if accel_gamma > 0.0 else None
     while st["n"] < n_target:
-        pdhg_step(p, pc, st, theta)
+        if sched is not None:
+            b, a, th = next(sched)
+            pdhg_step(p, pc, st, th, dual_mult=b, primal_mult=a)
+        else:
+            pdhg_step(p, pc, st, theta)
         if tol is not None and (st["n"] % gap_every == 0 or st["n"] == n_target):
             g = gap_terms(p, st, box)
             g["n"] = st["n"]

@@ -520,3 +520,112 @@ def test_residual_two_lst_steps_by_hand():
     assert np.allclose(st["u"], [3 / 8, 26 / 81], rtol=0, atol=1e-15)
     want = math.sqrt(1 / 64 + 64 / 6561) / math.sqrt(1 / 16 + 4 / 81)
     assert P.residual(st) == pytest.approx(want, rel=1e-14)
+
+
+# ---------------------------------------------------------------- accelerated PDHGM
+
+def test_accel_two_lst_steps_by_hand():
+    """Two steps of the accelerated variant worked by hand on the 1-pixel LS-T
+    problem A = 1, f = 1, alpha = 1 (sigma = tau = 1) with gamma = 1:
+      n = 0: b = a = 1: q1 = -1/2, u1 = 1/4; theta0 = 1/sqrt(3),
+             ubar1 = u1 + theta0 u1, a1 = 1/sqrt(3), b1 = sqrt(3)
+      n = 1: q2 = (q1 + sqrt(3) (ubar1 - 1)) / (1 + sqrt(3))
+                = ((-1 - 3 sqrt(3)) / 4) / (1 + sqrt(3)),
+             u2 = (u1 - q2 / sqrt(3)) / (1 + 1/sqrt(3)),
+             theta1 = 1 / sqrt(1 + 2/sqrt(3)), ubar2 = u2 + theta1 (u2 - u1).
+    Using the updated a or b within a step, or the next theta in the
+    extrapolation, gives other numbers."""
+    r3 = math.sqrt(3.0)
+    p = P.Problem(sp.csr_matrix(np.array([[1.0]])), np.array([1.0]), 1, 1, "lst", 1.0)
+    pc = P.precond_diag(p)
+    st = P.init_state(p)
+    sched = P.accel_schedule(1.0, 1e9)
+    b, a, th = next(sched)
+    assert (b, a) == (1.0, 1.0) and th == pytest.approx(1 / r3, rel=1e-15)
+    P.pdhg_step(p, pc, st, th, dual_mult=b, primal_mult=a)
+    assert st["q"][0] == pytest.approx(-0.5, rel=1e-15)
+    assert st["u"][0] == pytest.approx(0.25, rel=1e-15)
+    assert st["ubar"][0] == pytest.approx(0.25 * (1 + 1 / r3), rel=1e-15)
+    b, a, th = next(sched)
+    assert b == pytest.approx(r3, rel=1e-15) and a == pytest.approx(1 / r3, rel=1e-15)
+    P.pdhg_step(p, pc, st, th, dual_mult=b, primal_mult=a)
+    q2 = ((-1 - 3 * r3) / 4) / (1 + r3)
+    u2 = (0.25 - q2 / r3) / (1 + 1 / r3)
+    th1 = 1 / math.sqrt(1 + 2 / r3)
+    assert st["q"][0] == pytest.approx(q2, rel=1e-14)
+    assert st["u"][0] == pytest.approx(u2, rel=1e-14)
+    assert st["ubar"][0] == pytest.approx(u2 + th1 * (u2 - 0.25), rel=1e-14)
+
+
+def test_accel_schedule_invariants_and_freeze():
+    """a_n b_n = 1 at every step, theta_n in (0, 1], b_n never above the
+    bound, and after the freeze theta = 1 with constant steps."""
+    sched = P.accel_schedule(0.7, 5.0)
+    seen_freeze, prev = False, None
+    for n in range(400):
+        b, a, th = next(sched)
+        assert a * b == pytest.approx(1.0, rel=1e-12)
+        assert 0.0 < th <= 1.0 and b <= 5.0
+        if prev is not None and th == 1.0 and prev[2] == 1.0:
+            assert (b, a) == prev[:2]
+            seen_freeze = True
+        prev = (b, a, th)
+    assert seen_freeze and prev[0] > 4.0
+    # without a bound the primal multiplier decays as 1/(gamma n): from
+    # 1/a_{n+1}^2 = 1/a_n^2 + 2 gamma / a_n, 1/a_n = gamma n + O(log n)
+    sched = P.accel_schedule(0.7, math.inf)
+    for n in range(200001):
+        b, a, th = next(sched)
+        if n in (20000, 200000):
+            assert 0.7 * n * a == pytest.approx(1.0, rel=2e-3 if n == 20000 else 3e-4), (n, 0.7 * n * a)
+
+
+def test_accel_rate_bound_on_lst():
+    """LS-T (G = alpha/2 ||u||^2 is alpha min(tau)-strongly convex in the
+    metric of T): Chambolle-Pock's Theorem 2 bound for Algorithm 2 (an
+    invariant the plain iteration also satisfies here, since F1* is strongly
+    convex as well; the two hand-worked steps pin the schedule's arithmetic),
+    N^2 ||u^N - u*||_T^-1^2 <= (1 + eps) (||u0 - u*||_T^-1^2 + ||y0 - y*||_S^-1^2) / gamma^2,
+    with u* the normal-equations solution and y* = A u* - f."""
+    p = _tiny("lst", lam=0.05)
+    pc = P.precond_diag(p)
+    Ad = p.A.toarray()
+    us = np.linalg.solve(Ad.T @ Ad + p.lam * np.eye(p.N), Ad.T @ p.f)
+    ys = Ad @ us - p.f
+    gamma = p.lam * pc["tau_u"].min()
+    rhs = (np.sum(us ** 2 / pc["tau_u"]) + np.sum(ys ** 2 / pc["sigma_q"])) / gamma ** 2
+    st = P.init_state(p)
+    sched = P.accel_schedule(gamma, math.inf)
+    n = 0
+    for N in (50, 200, 800, 3200):
+        while n < N:
+            b, a, th = next(sched)
+            P.pdhg_step(p, pc, st, th, dual_mult=b, primal_mult=a)
+            n += 1
+        lhs = N * N * np.sum((st["u"] - us) ** 2 / pc["tau_u"])
+        assert lhs <= 1.25 * rhs, (N, lhs, rhs)
+
+
+def test_accel_gamma_zero_is_plain():
+    p = _tiny("tgv", lam=0.02)
+    pc = P.precond_diag(p)
+    a = P.pdhg_solve(p, pc, iters=40)
+    b = P.pdhg_solve(p, pc, iters=40, accel_gamma=0.0, accel_step_max=7.0)
+    assert all(np.array_equal(a[k], b[k]) for k in ("u", "ubar", "q", "r", "v", "s"))
+
+
+@pytest.mark.parametrize("kind,tol", [("tv", 1e-9), ("tgv", 1e-7)])
+def test_accel_same_minimiser(kind, tol):
+    """With the schedule frozen at a bounded step ratio the accelerated
+    iteration is plain PDHGM with rescaled steps: it reaches the same tiny
+    gap, and its objective matches the independent smooth solver."""
+    p = _tiny(kind, lam=0.01)
+    pc = P.precond_diag(p)
+    st = P.pdhg_solve(p, pc, tol=tol, max_iter=400000, gap_every=25, box=2.0,
+                      accel_gamma=1.0, accel_step_max=4.0)
+    h = st["history"][-1]
+    assert h["rel_gap"] <= tol and h["gap"] >= -1e-14
+    eps = 1e-7
+    ref = _smoothed_minimum(p, eps)
+    bias = eps * p.N * (p.lam + (p.alpha0 if kind == "tgv" else 0.0))
+    assert ref - bias - 1e-12 <= h["P"] <= ref + h["gap"] + 1e-12, (h["P"], ref, bias, h["gap"])
