@@ -285,6 +285,22 @@ typedef struct {
   const void* d_state_in; /* optional full state to resume from; NULL = none */
   void* d_state_out;      /* optional: receives the final state */
   pat_precond_h precond;  /* NULL: DIAG computed for this call */
+  /* Accelerated PDHGM (Sec. 3.3: the O(1/n^2) variant, Chambolle and Pock's
+   * Algorithm 2) on the preconditioned steps: iteration n uses the dual steps
+   * b_n Sigma and the primal steps a_n T and extrapolates with theta_n,
+   *   a_0 = b_0 = 1, theta_n = 1/sqrt(1 + 2 accel_gamma a_n),
+   *   a_{n+1} = theta_n a_n, b_{n+1} = b_n / theta_n,
+   * until an update would take b above accel_step_max; from then on
+   * theta = 1 and the steps stay fixed (plain PDHGM with steps a T, b Sigma,
+   * so the solve converges to a saddle point of the same problem).
+   * accel_gamma is the modulus of strong convexity of G in the metric of T
+   * (Tikhonov: lambda times the smallest tau_u); for TV, TGV and dTV (G = 0)
+   * a positive value is a step-ratio schedule, not a rate guarantee.
+   * accel_gamma = 0: plain PDHGM with `theta` (accel_step_max unused).
+   * accel_gamma > 0 needs theta = 1 and accel_step_max >= 1. The schedule
+   * restarts from a = b = 1 on d_state_in. */
+  double accel_gamma;
+  double accel_step_max;
 } pat_solve_opts;
 
 typedef struct {

@@ -69,7 +69,7 @@ class SolveOpts(C.Structure):
         ("max_iter", C.c_int32), ("gap_tol", C.c_double), ("gap_every", C.c_int32),
         ("graph_block", C.c_int32), ("theta", C.c_double), ("gap_box", C.c_double),
         ("d_u0", C.c_void_p), ("d_y0", C.c_void_p), ("d_state_in", C.c_void_p), ("d_state_out", C.c_void_p),
-        ("precond", C.c_void_p),
+        ("precond", C.c_void_p), ("accel_gamma", C.c_double), ("accel_step_max", C.c_double),
     ]
 
 

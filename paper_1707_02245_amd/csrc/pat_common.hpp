@@ -215,6 +215,8 @@ struct FwdArgs {
   double* red;        // GAP: partial sums [GAP_NSLOTS][red_stride]
   int red_stride;
   T* part;            // path 2: partial sums [pairs]
+  const double* mult; // DUAL: step multipliers {dual, primal, theta} of this
+                      // iteration (accelerated schedule; null: plain steps)
 };
 
 // Adjoint projection of one instance into per-detector-group partial images.
@@ -250,6 +252,8 @@ struct InstDev {
   T* upad_gap;        // [(ny+2)(nx+2)] padded u+ written on check iterations
   double* red;        // partial sums [GAP_NSLOTS][red_stride]
   int red_stride;
+  const double* mult; // step multipliers {dual, primal, theta} of this
+                      // iteration (accelerated schedule; null: plain steps)
 };
 
 // y = M x for a CSR matrix M (rows n_rows).

@@ -212,6 +212,9 @@ template <class T>
 void launch_pattern(T* x, int64_t n, hipStream_t s);
 template <class T>
 void launch_gap_reg(const Launch<T>& L, hipStream_t s);
+// Step multipliers of iteration t of a block for every instance:
+// cur[i][0..2] = sched[i][t][0..2] (sched holds `block` iterations per instance).
+void launch_accel_step(const double* sched, double* cur, int n_inst, int block, int t, hipStream_t s);
 // Sum the partial sums of every instance: out[inst][slot] (double).
 void launch_gap_finish(const GapFinishArgs* args, int n_inst, double* out, hipStream_t s);
 template <class T>

@@ -79,7 +79,11 @@ __global__ __launch_bounds__(256) void primal_kernel(const InstDev<T>* __restric
     T atq = T(0);
     for (int gi = 0; gi < a.n_groups; ++gi) atq += a.atq_part[gi * N + p];
     const T u_old = a.u[p];
-    const T tau = a.tau_u[p];
+    // the accelerated schedule scales every primal step of the iteration and
+    // sets its extrapolation
+    const T pm = a.mult ? (T)a.mult[1] : T(1);
+    const T th = a.mult ? (T)a.mult[2] : a.theta_ex;
+    const T tau = a.mult ? a.tau_u[p] * pm : a.tau_u[p];
     T un;
     // the gap's dual residual K^T y: FP64 A^T q when available
     double atq_d = (double)atq;
@@ -97,7 +101,7 @@ __global__ __launch_bounds__(256) void primal_kernel(const InstDev<T>* __restric
       if (CHECK) kty = fabs(atq_d + bt_r<T, double>(a, p, i, j, N));
     }
     a.u[p] = un;
-    const T ubar = un + a.theta_ex * (un - u_old);
+    const T ubar = un + th * (un - u_old);
     const int P = nx + 2;
     a.ubar_pad[(int64_t)(j + 1) * P + (i + 1)] = ubar;
     if (CHECK) {
@@ -118,13 +122,13 @@ __global__ __launch_bounds__(256) void primal_kernel(const InstDev<T>* __restric
       const T dy_yy = ay ? syy[p + nx] - c_yy : T(0);
       const T gvx = -dx_xx - dy_xy - a.r[p];
       const T gvy = -dx_xy - dy_yy - a.r[N + p];
-      const T tv = a.tau_v[p];
+      const T tv = a.mult ? a.tau_v[p] * pm : a.tau_v[p];
       const T vx = a.v[p], vy = a.v[N + p];
       const T vxn = vx - tv * gvx, vyn = vy - tv * gvy;
       a.v[p] = vxn;
       a.v[N + p] = vyn;
-      a.vbar[p] = vxn + a.theta_ex * (vxn - vx);
-      a.vbar[N + p] = vyn + a.theta_ex * (vyn - vy);
+      a.vbar[p] = vxn + th * (vxn - vx);
+      a.vbar[N + p] = vyn + th * (vyn - vy);
       if (CHECK) {
         const double ex = -((ax ? (double)sxx[p + 1] : (double)c_xx) - (double)c_xx) -
                           ((ay ? (double)sxy[p + nx] : (double)c_xy) - (double)c_xy) - (double)a.r[p];
@@ -156,6 +160,26 @@ void launch_primal(const Launch<T>& L, bool check, hipStream_t s) {
   else
     hipLaunchKernelGGL((primal_kernel<T, false>), dim3(L.pix_total), dim3(256), 0, s,
                        ptr<InstDev<T>>(L.inst), ptr<int>(L.pix_start), L.n);
+  PAT_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ accelerated schedule
+
+// cur[i] = sched[i][t] for every instance i (3 doubles each): the step
+// multipliers of iteration t of the current block, read by the iteration's
+// forward, regulariser and primal launches.
+__global__ __launch_bounds__(256) void accel_step_kernel(const double* __restrict__ sched,
+                                                         double* __restrict__ cur, int n_inst,
+                                                         int block, int t) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= 3 * n_inst) return;
+  const int i = e / 3, k = e % 3;
+  cur[e] = sched[((int64_t)i * block + t) * 3 + k];
+}
+
+void launch_accel_step(const double* sched, double* cur, int n_inst, int block, int t, hipStream_t s) {
+  const int blocks = (3 * n_inst + 255) / 256;
+  hipLaunchKernelGGL(accel_step_kernel, dim3(blocks), dim3(256), 0, s, sched, cur, n_inst, block, t);
   PAT_HIP(hipGetLastError());
 }
 

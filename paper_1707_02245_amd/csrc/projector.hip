@@ -105,7 +105,7 @@ __device__ __forceinline__ void fwd_epilogue(const FwdArgs<T>& a, int blk, bool 
     a.out[b] = val;
   } else if (MODE == FWD_DUAL) {
     // q <- prox_{sigma F1*}(q + sigma A ubar) = (q + sigma (A ubar - f)) / (1 + sigma)
-    const T sg = a.sigma[b];
+    const T sg = a.mult ? a.sigma[b] * (T)a.mult[0] : a.sigma[b];
     a.out[b] = (a.out[b] + sg * (val - a.f[b])) / (T(1) + sg);
   } else if (MODE == FWD_ROWSUM) {
     // A >= 0, so the absolute row sum is A 1; empty rows get sigma = 1

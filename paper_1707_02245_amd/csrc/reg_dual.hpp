@@ -50,7 +50,9 @@ __device__ __forceinline__ void reg_dual_block(const InstDev<T>* __restrict__ ar
   const T gx = ax ? ub[1] - c : T(0);
   const T gy = ay ? ub[P] - c : T(0);
   T rx = a.r[p], ry = a.r[N + p];
-  const T sr = a.sigma_r[p];
+  // the accelerated schedule scales every dual step of the iteration
+  const T dm = a.mult ? (T)a.mult[0] : T(1);
+  const T sr = a.mult ? a.sigma_r[p] * dm : a.sigma_r[p];
   if (a.kind == PAT_REG_TV) {
     rx += sr * gx;
     ry += sr * gy;
@@ -73,7 +75,7 @@ __device__ __forceinline__ void reg_dual_block(const InstDev<T>* __restrict__ ar
     const T e1 = (ax ? vx : T(0)) - vx_l;
     const T e4 = (ay ? vy : T(0)) - vy_d;
     const T e2 = T(0.5) * (((ay ? vx : T(0)) - vx_d) + ((ax ? vy : T(0)) - vy_l));
-    const T ss = a.sigma_s[p];
+    const T ss = a.mult ? a.sigma_s[p] * dm : a.sigma_s[p];
     T s1 = a.s[p] + ss * e1, s2 = a.s[N + p] + ss * e2, s4 = a.s[2 * N + p] + ss * e4;
     const T n = sqrt(s1 * s1 + T(2) * s2 * s2 + s4 * s4);
     if (n > a.alpha0) {

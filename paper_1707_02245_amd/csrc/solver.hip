@@ -49,6 +49,12 @@ static void validate_opts(const pat_solve_opts* o) {
   PAT_CHECK_ARG(std::isfinite(o->theta) && o->theta >= 0.0 && o->theta <= 1.0,
                 "theta must be in [0, 1]");
   PAT_CHECK_ARG(std::isfinite(o->gap_box) && o->gap_box > 0.0, "gap_box must be > 0");
+  PAT_CHECK_ARG(std::isfinite(o->accel_gamma) && o->accel_gamma >= 0.0, "accel_gamma must be finite and >= 0");
+  if (o->accel_gamma > 0.0) {
+    PAT_CHECK_ARG(!std::isnan(o->accel_step_max) && o->accel_step_max >= 1.0,
+                  "accel_step_max must be >= 1 with accel_gamma > 0");
+    PAT_CHECK_ARG(o->theta == 1.0, "the accelerated schedule sets theta itself: pass theta = 1");
+  }
 }
 
 // ------------------------------------------------------------------ step sizes
@@ -191,6 +197,30 @@ struct Inst {
   pat_status status = PAT_NOT_CONVERGED;
   double last[GAP_NSLOTS] = {0, 0, 0, 0, 0, 0};
   double rel_gap = INFINITY, gap = INFINITY, primal = 0, fstar = 0, kty = 0, residual = 0;
+  // accelerated schedule (Chambolle-Pock Algorithm 2 on the preconditioned
+  // steps): multipliers of the next iteration's dual (acc_b) and primal
+  // (acc_a) steps; frozen once the dual steps would grow beyond accel_step_max
+  bool accel = false, acc_frozen = false;
+  double acc_a = 1.0, acc_b = 1.0;
+
+  // the next iteration's {dual, primal, theta}; advances the schedule
+  void next_mult(double* m) {
+    double th = accel ? 1.0 : opts.theta;
+    if (accel && !acc_frozen) {
+      th = 1.0 / std::sqrt(1.0 + 2.0 * opts.accel_gamma * acc_a);
+      if (acc_b / th > opts.accel_step_max) {
+        acc_frozen = true;
+        th = 1.0;
+      }
+    }
+    m[0] = acc_b;
+    m[1] = acc_a;
+    m[2] = th;
+    if (accel && !acc_frozen) {
+      acc_a *= th;
+      acc_b /= th;
+    }
+  }
 
   GeomDev gdev(int lanes_log2, int tile) const {
     GeomDev d = g->dev();
@@ -214,11 +244,19 @@ class Solver {
   DevBuf results;        // [max_checks][n_active][GAP_NSLOTS]
   double* h_results = nullptr;
   int max_checks = 0;
+  // accelerated schedule: multipliers of every instance for one block
+  // [n_inst][block][3] (host pinned and device), the current iteration's
+  // [n_inst][3] read by the kernels
+  bool any_accel = false;
+  int sched_block = 1;
+  DevBuf sched, cur;
+  double* h_sched = nullptr;
   std::map<std::string, hipGraphExec_t> graphs;
 
   ~Solver() {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     if (h_results) (void)hipHostFree(h_results);
+    if (h_sched) (void)hipHostFree(h_sched);
   }
 
   void setup(hipStream_t stream) {
@@ -233,6 +271,34 @@ class Solver {
     results.alloc(sizeof(double) * max_checks * inst.size() * GAP_NSLOTS);
     PAT_HIP(hipHostMalloc((void**)&h_results, sizeof(double) * max_checks * inst.size() * GAP_NSLOTS,
                           hipHostMallocDefault));
+    for (auto& ip : inst) {
+      ip->accel = ip->opts.accel_gamma > 0.0;
+      any_accel = any_accel || ip->accel;
+    }
+    if (any_accel) {
+      sched_block = graph_block > 0 ? graph_block : gap_every;
+      const size_t n = inst.size();
+      sched.alloc(sizeof(double) * 3 * n * sched_block);
+      cur.alloc(sizeof(double) * 3 * n);
+      PAT_HIP(hipHostMalloc((void**)&h_sched, sizeof(double) * 3 * n * sched_block, hipHostMallocDefault));
+      // plain multipliers until the first block's are uploaded
+      for (size_t i = 0; i < n * sched_block; ++i) {
+        h_sched[3 * i] = h_sched[3 * i + 1] = 1.0;
+        h_sched[3 * i + 2] = inst[i / sched_block]->accel ? 1.0 : inst[i / sched_block]->opts.theta;
+      }
+      PAT_HIP(hipMemcpyAsync(cur.p, h_sched, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s));
+      PAT_HIP(hipStreamSynchronize(s));
+    }
+  }
+
+  // Multipliers of the next `steps` iterations of every active instance.
+  void upload_schedule(int steps) {
+    if (!any_accel) return;
+    for (int k : act) {
+      Inst<T>& I = *inst[k];
+      for (int t = 0; t < steps; ++t) I.next_mult(h_sched + ((size_t)k * sched_block + t) * 3);
+    }
+    PAT_HIP(hipMemcpyAsync(sched.p, h_sched, sched.bytes, hipMemcpyHostToDevice, s));
   }
 
   void alloc_instance(Inst<T>& I) {
@@ -305,7 +371,14 @@ class Solver {
     d.upad_gap = ptr<T>(I.upad_gap);
     d.red = ptr<double>(I.red);
     d.red_stride = I.red_stride;
+    d.mult = I.accel ? ptr<double>(cur) + 3 * inst_index(I) : nullptr;
     return d;
+  }
+
+  int inst_index(const Inst<T>& I) const {
+    for (size_t i = 0; i < inst.size(); ++i)
+      if (inst[i].get() == &I) return (int)i;
+    return 0;
   }
 
   // Upload the launch tables of the active instances.
@@ -334,6 +407,7 @@ class Solver {
       fd[k].out = ptr<T>(I.q);
       fd[k].f = I.f;
       fd[k].sigma = ptr<T>(I.pc->sigma_q);
+      fd[k].mult = I.accel ? ptr<double>(cur) + 3 * act[k] : nullptr;
       fg[k] = FwdArgs<T>{};
       fg[k].g = gd;
       fg[k].upad = ptr<T>(I.upad_gap);
@@ -521,7 +595,8 @@ class Solver {
                       ptr<double>(results) + (size_t)c * L.n * GAP_NSLOTS, s);
   }
 
-  void enqueue_iteration(bool check, int c) {
+  void enqueue_iteration(int t, bool check, int c) {
+    if (any_accel) launch_accel_step(ptr<double>(sched), ptr<double>(cur), (int)inst.size(), sched_block, t, s);
     launch_forward_reg_batched<T>(L, lanes_log2, s);
     enqueue_adjoint(check);
     launch_primal<T>(L, check, s);
@@ -678,7 +753,7 @@ class Solver {
     size_t c = 0;
     for (int t = 0; t < steps; ++t) {
       const bool chk = c < checks.size() && checks[c] == t;
-      enqueue_iteration(chk, (int)c);
+      enqueue_iteration(t, chk, (int)c);
       if (chk) ++c;
     }
   }
@@ -702,6 +777,7 @@ class Solver {
       // block ends at a multiple of gap_every or at the cap): a check inside
       // a block could not stop the solve there
       const std::vector<int> checks(1, steps - 1);
+      upload_schedule(steps);
       if (graph_block > 0) {
         PAT_HIP(hipGraphLaunch(graph_for(steps, checks), s));
       } else {

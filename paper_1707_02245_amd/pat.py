@@ -235,8 +235,9 @@ class Precond:
 
 
 def _opts(max_iter, gap_tol, gap_every, graph_block, theta, gap_box, u0, state_in,
-          state_out, precond, y0=None):
+          state_out, precond, y0=None, accel_gamma=0.0, accel_step_max=1.0):
     o = L.SolveOpts()
+    o.accel_gamma, o.accel_step_max = accel_gamma, accel_step_max
     o.max_iter, o.gap_tol, o.gap_every, o.graph_block = max_iter, gap_tol, gap_every, graph_block
     o.theta, o.gap_box = theta, gap_box
     o.d_u0 = u0.data_ptr() if u0 is not None else None
@@ -249,8 +250,9 @@ def _opts(max_iter, gap_tol, gap_every, graph_block, theta, gap_box, u0, state_i
 
 def solve(geom: Geometry, f, reg: Reg, max_iter=2000, gap_tol=1e-4, gap_every=50,
           graph_block=50, theta=1.0, gap_box=2.0, u0=None, state_in=None, state_out=None,
-          precond: Precond | None = None, out=None, y0=None):
-    """pat_pdhg_solve. Returns (u, info dict, status)."""
+          precond: Precond | None = None, out=None, y0=None, accel_gamma=0.0, accel_step_max=1.0):
+    """pat_pdhg_solve. Returns (u, info dict, status). accel_gamma > 0 runs
+    the accelerated schedule (pat_solve_opts.accel_gamma, accel_step_max)."""
     _need(f, geom.dtype, geom.n_det * geom.n_t, "f")
     out = geom.image() if out is None else out
     n_state = None
@@ -269,7 +271,7 @@ def solve(geom: Geometry, f, reg: Reg, max_iter=2000, gap_tol=1e-4, gap_every=50
         _need(reg.theta, geom.dtype, geom.nx * geom.ny, "theta")
     r = reg.c_struct()
     o = _opts(max_iter, gap_tol, gap_every, graph_block, theta, gap_box, u0, state_in,
-              state_out, precond, y0)
+              state_out, precond, y0, accel_gamma, accel_step_max)
     info = L.SolveInfo()
     st = L.check(L.load().pat_pdhg_solve(geom.handle, _ptr(f), C.byref(r), C.byref(o),
                                          _ptr(out), C.byref(info), _stream()))
@@ -277,9 +279,10 @@ def solve(geom: Geometry, f, reg: Reg, max_iter=2000, gap_tol=1e-4, gap_every=50
 
 
 def solve_batched(problems, max_iter=2000, gap_tol=1e-4, gap_every=50, graph_block=50,
-                  theta=1.0, gap_box=2.0, states_out=None):
+                  theta=1.0, gap_box=2.0, states_out=None, accel=None):
     """pat_pdhg_solve_batched over a list of (geom, f, reg[, precond]) tuples;
-    states_out: optional list of state buffers (or None entries).
+    states_out: optional list of state buffers (or None entries); accel:
+    optional list of (accel_gamma, accel_step_max) per instance.
     Returns (list of u, list of info dicts, status)."""
     n = len(problems)
     geoms = (C.c_void_p * n)()
@@ -302,8 +305,9 @@ def solve_batched(problems, max_iter=2000, gap_tol=1e-4, gap_every=50, graph_blo
         so = states_out[i] if states_out is not None else None
         if so is not None:
             _need(so, g.dtype, g.state_elems(reg.kind), f"states_out[{i}]")
+        ag, am = accel[i] if accel is not None else (0.0, 1.0)
         opts[i] = _opts(max_iter, gap_tol, gap_every, graph_block, theta, gap_box, None, None,
-                        so, pc)
+                        so, pc, None, ag, am)
     st = L.check(L.load().pat_pdhg_solve_batched(n, geoms, fs, regs, opts, outs, infos, _stream()))
     return us, [infos[i].as_dict() for i in range(n)], st
 

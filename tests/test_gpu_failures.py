@@ -64,6 +64,10 @@ BAD = {
     "gap_box<0": (dict(kind="tv", lam=0.02), dict(gap_box=-2.0)),
     "gap_tol nan": (dict(kind="tv", lam=0.02), dict(gap_tol=math.nan)),
     "theta>1": (dict(kind="tv", lam=0.02), dict(theta=1.5)),
+    "accel_gamma<0": (dict(kind="tv", lam=0.02), dict(accel_gamma=-1.0, accel_step_max=4.0)),
+    "accel_gamma inf": (dict(kind="tv", lam=0.02), dict(accel_gamma=math.inf, accel_step_max=4.0)),
+    "accel_step_max<1": (dict(kind="tv", lam=0.02), dict(accel_gamma=1.0, accel_step_max=0.5)),
+    "accel with theta<1": (dict(kind="tv", lam=0.02), dict(accel_gamma=1.0, accel_step_max=4.0, theta=0.5)),
 }
 
 

@@ -502,6 +502,73 @@ def _assert_gap_terms(info, p, ref, kind, dt):
     assert info["residual"] == pytest.approx(res_ref, rel=1e-8 if f64 else 1e-3)
 
 
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("kind", ["tv", "tgv", "dtv", "tikhonov"])
+def test_accelerated_fixed_iterations_full_state(kind, dt):
+    """Accelerated PDHGM (step multipliers and theta_n of the schedule, frozen
+    at a dual-step factor of 3 after four updates) for 60 iterations across
+    three graph blocks: full state and gap terms against the oracle."""
+    name = "arc90" if kind == "dtv" else "ragged"
+    d, og, g = _geoms(name, dt)
+    A = OG.forward_matrix(og)
+    rng = np.random.default_rng(14)
+    f = A @ np.clip(rng.uniform(-0.2, 1, og.n_pix), 0, None) + 0.01 * rng.standard_normal(og.n_bins)
+    reg, th = _reg_pair(kind, og, dt)
+    p = oracle_problem(A, f, og.nx, kind, reg.lam, reg.alpha0, reg.eta, th, ny=og.ny)
+    ref = OP.pdhg_solve(p, OP.precond_diag(p), iters=60, accel_gamma=0.5, accel_step_max=3.0)
+    st = torch.zeros(g.state_elems(kind), dtype=DT[dt], device="cuda")
+    u, info, status = pat.solve(g, to_dev(f, DT[dt]), reg, max_iter=60, gap_tol=0.0, gap_every=10,
+                                graph_block=20, state_out=st, accel_gamma=0.5, accel_step_max=3.0)
+    got = split_state(host(st), kind, og.n_pix, og.n_bins)
+    tol = 1e-10 if dt == "f64" else 1e-4
+    print(f"accelerated {kind} {dt}: rel u {rel(got['u'], ref['u']):.2e}", flush=True)
+    assert info["iters"] == 60
+    for key in ("u", "ubar", "q", "r", "v", "vbar", "s"):
+        if key in got and key in ref:
+            e = rel(got[key], ref[key])
+            assert e <= tol, (key, e)
+    _assert_gap_terms(info, p, ref, kind, dt)
+
+
+def test_accelerated_converges_like_the_oracle():
+    """Accelerated solve to a gap tolerance (gap every 50): the same stopping
+    iteration and objective as the oracle's accelerated run."""
+    d = desc_for(48, 24, 96)
+    og = OG.make_geometry(d)
+    A = OG.forward_matrix(og)
+    f, _ = synth_data(d, "disc", 5)
+    p = oracle_problem(A, f, 48, "tv", 0.01)
+    ref = OP.pdhg_solve(p, OP.precond_diag(p), tol=1e-3, max_iter=20000, gap_every=50,
+                        accel_gamma=1.0, accel_step_max=4.0)
+    g = pat.Geometry(dtype=torch.float64, **d)
+    u, info, st = pat.solve(g, to_dev(f, torch.float64), pat.Reg("tv", 0.01), max_iter=20000, gap_tol=1e-3,
+                            gap_every=50, graph_block=50, accel_gamma=1.0, accel_step_max=4.0)
+    print(f"accelerated: iters {info['iters']} (oracle {ref['history'][-1]['n']})", flush=True)
+    assert st == 0 and info["iters"] == ref["history"][-1]["n"]
+    assert info["primal"] == pytest.approx(ref["history"][-1]["P"], rel=1e-9)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_accelerated_and_plain_in_one_batch(dt):
+    """A batch mixing accelerated and plain instances (two sharing a
+    geometry): every instance equals its single solve bit for bit."""
+    d, og, g = _geoms("ragged", dt)
+    A = OG.forward_matrix(og)
+    rng = np.random.default_rng(31)
+    problems, accel = [], []
+    for i, kind in enumerate(["tv", "tgv", "tv"]):
+        f = A @ rng.uniform(0, 1, og.n_pix)
+        problems.append((g, to_dev(f, DT[dt]), pat.Reg(kind, 0.02, 0.04)))
+        accel.append((0.5 * i, 3.0) if i else (0.0, 1.0))
+    us, infos, st = pat.solve_batched(problems, max_iter=120, gap_tol=0.0, gap_every=20, graph_block=40,
+                                      accel=accel)
+    for (gg, f, reg), (ag, am), ub, ib in zip(problems, accel, us, infos):
+        u1, i1, _ = pat.solve(gg, f, reg, max_iter=120, gap_tol=0.0, gap_every=20, graph_block=40,
+                              accel_gamma=ag, accel_step_max=am)
+        assert torch.equal(ub, u1), (reg.kind, ag)
+        assert ib["rel_gap"] == i1["rel_gap"]
+
+
 @pytest.mark.parametrize("adj", ["tiled", "csr", "scatter"])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_tv64_workload_200_iterations(dt, adj):
