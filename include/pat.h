@@ -427,6 +427,50 @@ pat_status pat_warmstart_normalize(pat_geometry g, const pat_regulariser* reg, c
 pat_status pat_warmstart_infer(pat_unet n, pat_geometry g, const pat_regulariser* reg, const void* d_f,
                                void* d_u0, void* d_y0, void* stream);
 
+/* ---- Calibrated forward model and preprocessing (Sec. 4.1, 4.2) ----------
+ * The measured pressure at detector x_d is the circular projection of the
+ * image convolved in time with the calibration measurement of a point source
+ * at x_p taken at retarded time (eq. FW_full). With the circular-mean
+ * operator A of this library, (1/t) K u = 2 pi c A u, so
+ *   p_d = s_d (A u)_d *_t pcal_d(. + tau_d),
+ *   s_d = 2 pi c |x_d - x_p|,  tau_d = |x_d - x_p| / c,
+ * where the sampled convolution is dt sum_j a_j b_{k-j}. Preprocessing
+ * deconvolves with the regularised filter of eq. deconv and rescales
+ * (eq. f_rewrite):
+ *   f_d = F^-1{ F{p_d} conj(D_d) / (|D_d|^2 + eps) } / s_d,
+ *   D_d = dt F{pcal_d} exp(i omega tau_d),
+ * which gives A u back when the calibration spectrum has no zeros and eps is
+ * small. Every transform is an L-point DFT, L the smallest power of two
+ * >= 2 n_t (zero padding; at most 4096), so the retarded shift is a phase
+ * ramp. Signals are device arrays [n_det][n_t] in the element type of the
+ * geometry, sampled like the data; the transforms run in FP64. */
+typedef struct pat_calib_s* pat_calib;
+/* Spectra of the calibration d_pcal [n_det][n_t] (the pressure each detector
+ * recorded from a point source at (xp, yp)) with regularisation eps > 0,
+ * computed once on the device. A detector at the source, eps <= 0 or
+ * non-finite values: PAT_ERR_INVALID_ARG; n_t > 2048: PAT_ERR_UNSUPPORTED.
+ * The handle keeps g, which must outlive it. Synchronous. */
+pat_status pat_calib_create(pat_geometry g, const void* d_pcal, double xp, double yp, double eps, void* stream,
+                            pat_calib* out);
+pat_status pat_calib_destroy(pat_calib c);
+/* d_p = measured pressure of image d_u [ny][nx] (eq. FW_full). */
+pat_status pat_pressure_forward(pat_calib c, const void* d_u, void* d_p, void* stream);
+/* d_f = data for the reconstruction from measured pressure d_p (eqs. deconv,
+ * f_rewrite). d_p and d_f may not overlap. */
+pat_status pat_preprocess(pat_calib c, const void* d_p, void* d_f, void* stream);
+
+/* Peak signal-to-noise ratio of an image against its ground truth (Sec. 5.4),
+ * in the form the paper prints (maximum of the ground truth not squared)
+ * and in the standard form:
+ *   printed  = 10 log10(max(u_gt) / (||u - u_gt||^2 / n)),
+ *   standard = 10 log10(max(u_gt)^2 / (||u - u_gt||^2 / n)).
+ * d_u, d_gt: device arrays of n elements of `dtype`; FP64 reductions on the
+ * GPU in a fixed order. Results to host doubles; +inf when u == u_gt.
+ * n < 1, NULL pointers: PAT_ERR_INVALID_ARG; max(u_gt) <= 0 or non-finite
+ * values: PAT_ERR_NUMERIC. Synchronous on return. */
+pat_status pat_psnr(int32_t dtype, int64_t n, const void* d_u, const void* d_gt, double* psnr_printed,
+                    double* psnr_standard, void* stream);
+
 const char* pat_status_string(pat_status s);
 /* Message of the last error on the calling thread ("" if none). */
 const char* pat_last_error(void);

@@ -135,6 +135,13 @@ _SIGS = {
                                  C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p], C.c_int),
     "pat_warmstart_infer": ([C.c_void_p, C.c_void_p, C.POINTER(Regulariser), C.c_void_p, C.c_void_p,
                              C.c_void_p, C.c_void_p], C.c_int),
+    "pat_calib_create": ([C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_void_p,
+                          C.POINTER(C.c_void_p)], C.c_int),
+    "pat_calib_destroy": ([C.c_void_p], C.c_int),
+    "pat_pressure_forward": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "pat_preprocess": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "pat_psnr": ([C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                  C.c_void_p], C.c_int),
     "pat_status_string": ([C.c_int], C.c_char_p),
     "pat_last_error": ([], C.c_char_p),
 }

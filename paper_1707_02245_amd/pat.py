@@ -332,3 +332,55 @@ def kernel_times(problems, reps=20, gap_every=50, graph_block=50):
     ms = (C.c_double * 4)()
     L.check(L.load().pat_pdhg_kernel_times(n, geoms, fs, regs, opts, reps, ms, _stream()))
     return dict(forward_dual_ms=ms[0], reg_dual_ms=ms[1], adjoint_ms=ms[2], primal_ms=ms[3])
+
+
+def psnr(u, u_gt):
+    """pat_psnr: (printed, standard) PSNR of u against u_gt (Sec. 5.4)."""
+    if u.dtype != u_gt.dtype or u.numel() != u_gt.numel():
+        raise ValueError("u and u_gt need one dtype and size")
+    _need(u, u.dtype, u.numel(), "u")
+    _need(u_gt, u.dtype, u.numel(), "u_gt")
+    a, b = C.c_double(), C.c_double()
+    L.check(L.load().pat_psnr(_DT[u.dtype], u.numel(), _ptr(u), _ptr(u_gt), C.byref(a), C.byref(b), _stream()))
+    return a.value, b.value
+
+
+class Calibration:
+    """pat_calib: calibrated pressure model and preprocessing (Sec. 4.1, 4.2)."""
+
+    def __init__(self, geom: Geometry, pcal, xp, yp, eps):
+        _need(pcal, geom.dtype, geom.n_det * geom.n_t, "pcal")
+        self.geom = geom
+        h = C.c_void_p()
+        L.check(L.load().pat_calib_create(geom.handle, _ptr(pcal), float(xp), float(yp), float(eps), _stream(),
+                                          C.byref(h)))
+        self._h = h
+
+    def pressure(self, u, out=None):
+        """Measured pressure of image u (pat_pressure_forward)."""
+        g = self.geom
+        _need(u, g.dtype, g.nx * g.ny, "u")
+        out = g.data() if out is None else out
+        _need(out, g.dtype, g.n_det * g.n_t, "out")
+        L.check(L.load().pat_pressure_forward(self._h, _ptr(u), _ptr(out), _stream()))
+        return out
+
+    def preprocess(self, p, out=None):
+        """Data for the reconstruction from measured pressure (pat_preprocess)."""
+        g = self.geom
+        _need(p, g.dtype, g.n_det * g.n_t, "p")
+        out = g.data() if out is None else out
+        _need(out, g.dtype, g.n_det * g.n_t, "out")
+        L.check(L.load().pat_preprocess(self._h, _ptr(p), _ptr(out), _stream()))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.load().pat_calib_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

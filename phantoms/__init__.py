@@ -44,6 +44,9 @@ __all__ = [
     "make_case",
     "block_mean",
     "unit_noise",
+    "rotated_array_angles",
+    "uniform_subset",
+    "detectors_xy",
 ]
 
 
@@ -100,6 +103,42 @@ def geometry_desc(n: int, n_det: int, n_t: int, arc_span: float = 2 * math.pi,
                 arc_center=0.0, arc_span=arc_span,
                 n_t=n_t, t0=0.0, dt=r_max / (n_t - 1), c=1.0,
                 samples_per_pixel=samples_per_pixel)
+
+
+def rotated_array_angles(n_array: int = 64, span_deg: float = 172.0, n_rot: int = 6,
+                         rot_deg: float = 60.0) -> np.ndarray:
+    """Detector angles of an array of n_array elements spread evenly over
+    span_deg (both ends included, centred on angle 0) scanned at n_rot
+    rotations rot_deg apart (Sec. 6.1: 64 detectors over 172 degrees, six
+    rotations of 60 degrees, 384 locations). Radians in [0, 2 pi), sorted."""
+    base = np.deg2rad(-0.5 * span_deg + span_deg * np.arange(n_array) / (n_array - 1))
+    ang = (base[None, :] + np.deg2rad(rot_deg) * np.arange(n_rot)[:, None]).ravel()
+    return np.sort(np.mod(ang, 2 * math.pi))
+
+
+def uniform_subset(angles: np.ndarray, count: int) -> np.ndarray:
+    """A uniform compressive sampling of the scanned locations: for each of
+    count equispaced target angles (starting at the first location) the
+    nearest location not taken yet. The rotated arcs overlap (six 172-degree
+    arcs cover 472 degrees), so every k-th of the sorted angles would not be
+    even. Sorted radians."""
+    if not 1 <= count <= len(angles):
+        raise ValueError("count must be between 1 and the number of locations")
+    free = np.ones(len(angles), dtype=bool)
+    out = []
+    for k in range(count):
+        t = angles[0] + 2 * math.pi * k / count
+        dist = np.abs(np.angle(np.exp(1j * (angles - t))))
+        dist[~free] = np.inf
+        i = int(np.argmin(dist))
+        free[i] = False
+        out.append(angles[i])
+    return np.sort(np.mod(np.array(out), 2 * math.pi))
+
+
+def detectors_xy(angles: np.ndarray, radius: float = 1.2) -> np.ndarray:
+    """Point detectors at the given angles on a circle about the origin [n][2]."""
+    return np.stack([radius * np.cos(angles), radius * np.sin(angles)], axis=1)
 
 
 def pixel_centres(n: int, lo: float = -1.0, hi: float = 1.0):
