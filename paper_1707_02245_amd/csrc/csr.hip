@@ -550,23 +550,10 @@ __global__ __launch_bounds__(NT) void csr_tiled_kernel(CsrMultiArgs<T> a0, const
   typedef T T4 __attribute__((ext_vector_type(4)));
   int c[G];  // 16-bit offsets held unpacked (packing would wait on the loads)
   T v[G];
-  // A lane loads only the runs that overlap its row's entries [lo, hi): the
-  // rest of a group (before the row's first entry, past its last, or a whole
-  // group that is only a placeholder) is masked out of the sums anyway, and
-  // not loading it keeps the row ends from pulling the neighbouring rows'
-  // cache lines.
-  auto load_group = [&](int base, int lo, int hi, int* cc, T* vv) {
+  auto load_group = [&](int base, int* cc, T* vv) {
 #pragma unroll
     for (int q = 0; q < G / K; ++q) {
       const int e = base + K * gl + K * LPR * q;
-      if (e + K <= lo || e >= hi) {
-#pragma unroll
-        for (int t = 0; t < K; ++t) {
-          cc[K * q + t] = 0;
-          vv[K * q + t] = T(0);
-        }
-        continue;
-      }
       if constexpr (K == 2) {
         const uint32_t w = __builtin_nontemporal_load((gptr<const uint32_t>)(lcol + e));
         cc[2 * q] = (int)(w & 0xffffu);
@@ -590,7 +577,7 @@ __global__ __launch_bounds__(NT) void csr_tiled_kernel(CsrMultiArgs<T> a0, const
     int e0, e1;
     row_range(0, e0, e1);
     int base = e0 & ~(LPR - 1);
-    load_group(base, e0, e1, c, v);
+    load_group(base, c, v);
     for (int b = 0; b < n_batch; ++b) {
       const bool has_next = b + 1 < n_batch;
       int ne0 = 0, ne1 = 0;
@@ -612,13 +599,9 @@ __global__ __launch_bounds__(NT) void csr_tiled_kernel(CsrMultiArgs<T> a0, const
         const bool more = !stale && nb < e1;
         const bool any = __any(more);
         const int next = any ? (more ? nb : base) : (has_next ? (ne0 & ~(LPR - 1)) : base);
-        // the entries the next step uses: the rest of this row, the next
-        // batch's row, or none (a stale placeholder)
-        const int nlo = any ? e0 : ne0;
-        const int nhi = any ? (more ? e1 : 0) : (has_next ? ne1 : 0);
         int cn[G];
         T vn[G];
-        load_group(next, nlo, nhi, cn, vn);
+        load_group(next, cn, vn);
         // every slot is computed (slots past nrhs read stale LDS and are not
         // stored): no per-slot branches between the LDS reads
         Acc vm[G];

@@ -159,19 +159,6 @@ __device__ __forceinline__ T block_sum(T v, T* lds) {
   return s;  // valid in thread 0
 }
 
-// Logical block served by workgroup i of a launch of nb workgroups. The
-// hardware deals workgroups to the 8 XCDs in turn (i on XCD i % 8), each with
-// its own L2; giving every XCD one contiguous chunk of the logical blocks
-// (the k-th workgroup of an XCD serves the k-th block of its chunk) lets a
-// pixel stencil find the rows above and below it in the L2 that the
-// neighbouring blocks just filled. A permutation of [0, nb).
-__device__ __forceinline__ int xcd_block(int i, int nb) {
-  constexpr int X = 8;
-  const int q = nb / X, r = nb % X;
-  const int x = i % X, k = i / X;
-  return x * q + min(x, r) + k;
-}
-
 // Block maximum (valid in thread 0), same layout as block_sum.
 template <int NT, class T>
 __device__ __forceinline__ T block_max(T v, T* lds) {

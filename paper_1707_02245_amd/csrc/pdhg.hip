@@ -23,7 +23,7 @@ namespace pat {
 template <class T>
 __global__ __launch_bounds__(256) void reg_dual_kernel(const InstDev<T>* __restrict__ arr,
                                                        const int* __restrict__ starts, int n_inst) {
-  reg_dual_block<T>(arr, starts, n_inst, blockIdx.x, gridDim.x);
+  reg_dual_block<T>(arr, starts, n_inst, blockIdx.x);
 }
 
 template <class T>
@@ -66,7 +66,7 @@ __device__ __forceinline__ A bt_r(const InstDev<T>& a, int64_t p, int i, int j, 
 template <class T, bool CHECK>
 __global__ __launch_bounds__(256) void primal_kernel(const InstDev<T>* __restrict__ arr,
                                                      const int* __restrict__ starts, int n_inst) {
-  int blk = xcd_block(blockIdx.x, gridDim.x);
+  int blk = blockIdx.x;
   const int ii = find_inst_p(starts, n_inst, blk);
   const InstDev<T> a = arr[ii];
   blk -= starts[ii];
@@ -188,7 +188,7 @@ void launch_accel_step(const double* sched, double* cur, int n_inst, int block, 
 template <class T>
 __global__ __launch_bounds__(256) void gap_reg_kernel(const InstDev<T>* __restrict__ arr,
                                                       const int* __restrict__ starts, int n_inst) {
-  int blk = xcd_block(blockIdx.x, gridDim.x);
+  int blk = blockIdx.x;
   const int ii = find_inst_p(starts, n_inst, blk);
   const InstDev<T> a = arr[ii];
   blk -= starts[ii];

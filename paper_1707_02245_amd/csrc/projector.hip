@@ -130,7 +130,7 @@ __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T
   int blk = blockIdx.x;
   if constexpr (FUSED) {
     if (blk >= n_fwd) {
-      reg_dual_block<T>(rarr, rstarts, rn, blk - n_fwd, (int)gridDim.x - n_fwd);
+      reg_dual_block<T>(rarr, rstarts, rn, blk - n_fwd);
       return;
     }
   }

@@ -30,13 +30,11 @@ __device__ __forceinline__ void project2(T& a, T& b, T rad) {
   }
 }
 
-// Pixels [256 b, 256 b + 256) of the instances' concatenated block ranges
-// (starts: first block of each instance, n_inst entries), b the logical
-// block of workgroup blk of the nb that run this step (xcd_block).
+// Pixels [256 blk, 256 blk + 256) of the instances' concatenated block
+// ranges (starts: first block of each instance, n_inst entries).
 template <class T>
 __device__ __forceinline__ void reg_dual_block(const InstDev<T>* __restrict__ arr, const int* __restrict__ starts,
-                                               int n_inst, int blk, int nb) {
-  blk = xcd_block(blk, nb);
+                                               int n_inst, int blk) {
   const int ii = find_inst_p(starts, n_inst, blk);
   const InstDev<T> a = arr[ii];
   blk -= starts[ii];

@@ -279,10 +279,11 @@ def solve(geom: Geometry, f, reg: Reg, max_iter=2000, gap_tol=1e-4, gap_every=50
 
 
 def solve_batched(problems, max_iter=2000, gap_tol=1e-4, gap_every=50, graph_block=50,
-                  theta=1.0, gap_box=2.0, states_out=None, accel=None):
+                  theta=1.0, gap_box=2.0, states_out=None, accel=None, states_in=None):
     """pat_pdhg_solve_batched over a list of (geom, f, reg[, precond]) tuples;
-    states_out: optional list of state buffers (or None entries); accel:
-    optional list of (accel_gamma, accel_step_max) per instance.
+    states_out / states_in: optional lists of state buffers (or None
+    entries) to export / resume from; accel: optional list of
+    (accel_gamma, accel_step_max) per instance.
     Returns (list of u, list of info dicts, status)."""
     n = len(problems)
     geoms = (C.c_void_p * n)()
@@ -305,8 +306,11 @@ def solve_batched(problems, max_iter=2000, gap_tol=1e-4, gap_every=50, graph_blo
         so = states_out[i] if states_out is not None else None
         if so is not None:
             _need(so, g.dtype, g.state_elems(reg.kind), f"states_out[{i}]")
+        si = states_in[i] if states_in is not None else None
+        if si is not None:
+            _need(si, g.dtype, g.state_elems(reg.kind), f"states_in[{i}]")
         ag, am = accel[i] if accel is not None else (0.0, 1.0)
-        opts[i] = _opts(max_iter, gap_tol, gap_every, graph_block, theta, gap_box, None, None,
+        opts[i] = _opts(max_iter, gap_tol, gap_every, graph_block, theta, gap_box, None, si,
                         so, pc, None, ag, am)
     st = L.check(L.load().pat_pdhg_solve_batched(n, geoms, fs, regs, opts, outs, infos, _stream()))
     return us, [infos[i].as_dict() for i in range(n)], st

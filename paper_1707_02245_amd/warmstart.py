@@ -55,10 +55,20 @@ class WarmStartNet:
     def save_weights(self, path):
         np.save(path, self.params())
 
-    def load_weights(self, path):
+    def load_weights(self, path, check_operator=True):
+        """Parameters from a .npy file; with check_operator the manifest beside
+        it (same name, .json) must carry this library's operator fingerprint."""
         v = np.load(path, allow_pickle=False)
         if v.shape != (self.n_params,):
             raise ValueError(f"{path}: {v.shape} parameters, network has {self.n_params}")
+        if check_operator:
+            import os
+            man = os.path.splitext(path)[0] + ".json"
+            with open(man) as fh:
+                fp = json.load(fh).get("operator_fingerprint")
+            if fp != operator_fingerprint():
+                raise ValueError(f"{path} was trained on another forward operator (fingerprint {fp}, "
+                                 f"this library {operator_fingerprint()})")
         self.set_params(v)
 
     def train(self, inputs, targets, epochs, batch, lr, seed=0):
@@ -91,6 +101,28 @@ class WarmStartNet:
             self.close()
         except Exception:
             pass
+
+
+_FINGERPRINT = []
+
+
+def operator_fingerprint() -> str:
+    """Fingerprint of the discrete forward operator this library computes: a
+    hash of the FP64 A u of a fixed image on a small geometry (32^2, 8
+    detectors x 64 samples), rounded to 9 decimals. It changes when the
+    operator's definition changes (sample counts, phases, weights), not when
+    its kernels are tuned."""
+    if not _FINGERPRINT:
+        import hashlib
+        import phantoms
+        g = pat.Geometry(dtype=torch.float64, **phantoms.geometry_desc(32, 8, 64))
+        i = np.arange(32)
+        u = ((7 * i[:, None] + 3 * i[None, :]) % 11) / 10.0
+        f = g.forward(torch.tensor(u, dtype=torch.float64, device="cuda")).cpu().numpy()
+        g.close()
+        txt = ",".join(f"{x:.9f}" for x in f.ravel())
+        _FINGERPRINT.append(hashlib.sha256(txt.encode()).hexdigest()[:16])
+    return _FINGERPRINT[0]
 
 
 def normalize(geom: pat.Geometry, f, reg: pat.Reg | None = None, state=None, channels=3):
@@ -169,7 +201,7 @@ def make_pairs(geom, desc, seeds, lam, gap_tol, cap, group=8, channels=3, log=No
 STARTS = ("zero", "backprojection", "network_primal", "network")
 
 
-def evaluate(geom, desc, net, seeds, lam, gap_tol, cap, starts=STARTS):
+def evaluate(geom, desc, net, seeds, lam, gap_tol, cap, starts=STARTS, log=None):
     """Iterations and seconds to gap_tol from zero, from the backprojection
     A^T f / A^T 1, from the network's primal output alone and from its primal
     and dual output (inference included in the seconds)."""
@@ -198,6 +230,8 @@ def evaluate(geom, desc, net, seeds, lam, gap_tol, cap, starts=STARTS):
                              rel_gap=info["rel_gap"], primal=info["primal"],
                              fallback=info["fallback"], status=st)
         out.append(rec)
+        if log:
+            log(json.dumps(rec))
     return out
 
 
@@ -260,6 +294,67 @@ def throughput(batch=8, steps=20, size=256, base=32, log=print):
     return res
 
 
+def _summarise(ev, log):
+    """Mean and median iterations and seconds (inference included) per start."""
+    summary = {}
+    if not ev:
+        return summary
+    for name in STARTS:
+        if name not in ev[0]:
+            continue
+        it = [r[name]["iters"] for r in ev]
+        sec = [r[name]["seconds"] for r in ev]
+        fb = sum(r[name]["fallback"] for r in ev)
+        summary[name] = dict(iters_mean=float(np.mean(it)), iters_median=float(np.median(it)),
+                             seconds_mean=float(np.mean(sec)), seconds_median=float(np.median(sec)),
+                             fallbacks=fb)
+        log(f"{name:15s} mean iters {np.mean(it):8.0f} median {np.median(it):8.0f}  mean s {np.mean(sec):7.3f} "
+            f"median s {np.median(sec):7.3f}  fallbacks {fb}")
+    return summary
+
+
+def _evaluate_cmd(argv):
+    """evaluate --weights W --seeds A:B [--report R]: time to the gap from
+    zero, the backprojection and the network's starts on held-out seeds; the
+    summary is also written into the weights' manifest."""
+    import os
+    import phantoms
+    ap = argparse.ArgumentParser()
+    ap.add_argument("cmd")
+    ap.add_argument("--weights", required=True)
+    ap.add_argument("--seeds", default="50000:50064")
+    ap.add_argument("--lam", type=float, default=0.02)
+    ap.add_argument("--gap-tol", type=float, default=1e-4)
+    ap.add_argument("--cap", type=int, default=200000)
+    ap.add_argument("--report", default=None)
+    a = ap.parse_args(argv)
+
+    def log(m):
+        print(f"[warmstart] {m}", flush=True)
+
+    wl = phantoms.WORKLOADS["tv256"]
+    desc = phantoms.geometry_desc(wl.n, wl.n_det, wl.n_t)
+    geom = pat.Geometry(dtype=torch.float64, **desc)
+    net = WarmStartNet(4, 32, 3, seed=0)
+    net.load_weights(a.weights)
+    lo, hi = (int(x) for x in a.seeds.split(":"))
+    f0, _, _ = synth_data(desc, lo, dtype=geom.dtype)
+    net.infer(geom, f0, pat.Reg("tv", a.lam), dual=True)  # untimed warm-up of the inference buffers
+    ev = evaluate(geom, desc, net, list(range(lo, hi)), a.lam, a.gap_tol, a.cap, log=log)
+    summary = _summarise(ev, log)
+    if a.report:
+        with open(a.report, "w") as fh:
+            json.dump(dict(eval=ev, summary=summary, args=vars(a)), fh)
+    man = os.path.splitext(a.weights)[0] + ".json"
+    with open(man) as fh:
+        m = json.load(fh)
+    m["evaluation"] = dict(seeds=f"{lo}..{hi - 1}", gap_tol=a.gap_tol, dtype="f64",
+                           note="seconds include the network's inference", summary=summary)
+    with open(man, "w") as fh:
+        json.dump(m, fh, indent=1)
+    return 0
+
+
 def _main(argv=None):
     import phantoms
     if argv is None:
@@ -272,6 +367,8 @@ def _main(argv=None):
         b = tp.parse_args(argv)
         throughput(b.batch, b.steps, log=lambda m: print(f"[warmstart] {m}", flush=True))
         return 0
+    if argv and argv[0] == "evaluate":
+        return _evaluate_cmd(argv)
     ap = argparse.ArgumentParser()
     ap.add_argument("cmd", choices=["train"])
     ap.add_argument("--n-train", type=int, default=512)
@@ -322,20 +419,29 @@ def _main(argv=None):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     net.save_weights(a.out)
-    ev = evaluate(geom, desc, net, test_seeds, a.lam, a.gap_tol, a.cap)
-    for r in ev:
-        log(json.dumps(r))
-    summary = {}
-    for name in STARTS:
-        it = [r[name]["iters"] for r in ev]
-        sec = [r[name]["seconds"] for r in ev]
-        fb = sum(r[name]["fallback"] for r in ev)
-        summary[name] = dict(iters=float(np.mean(it)), seconds=float(np.mean(sec)), fallbacks=fb)
-        log(f"{name:15s} mean iters {np.mean(it):8.0f}  mean s {np.mean(sec):7.3f}  fallbacks {fb}")
+    ev = evaluate(geom, desc, net, test_seeds, a.lam, a.gap_tol, a.cap, log=log) if a.n_test > 0 else []
+    summary = _summarise(ev, log)
     rep = dict(pairs=st, train_seconds=t_train, history=hist, eval=ev, summary=summary, args=vars(a))
     if a.report:
         with open(a.report, "w") as fh:
             json.dump(rep, fh)
+    import os
+    manifest = dict(
+        network=dict(levels=4, base_channels=a.base, outputs=["u/s", "r_x/lambda", "r_y/lambda"],
+                     parameters=net.n_params),
+        operator_fingerprint=operator_fingerprint(),
+        workload=(f"{a.size}x{a.size} TV (lambda {a.lam}), {wl.n_det} detectors on a closed circle of radius "
+                  f"1.2, {wl.n_t} time samples; mixed disc/vessel/segment phantoms, noise U(1%, 10%)"),
+        training=dict(pairs=len(st["iters"]), dropped=st["dropped"], train_seeds=f"10000..{10000 + a.n_train - 1}",
+                      val_seeds=f"40000..{40000 + a.n_val - 1}",
+                      targets=f"PDHG TV solutions in {a.target_dtype.upper()} to rel_gap {a.target_gap} (batched)",
+                      target_generation_s=st["seconds"], epochs=a.epochs, batch=a.batch,
+                      lr=f"{a.lr}, /3 after 60% of the epochs, /10 after 85%", train_s=t_train,
+                      final_train_loss=hist[-1]["loss"], final_val_loss=hist[-1]["val"]),
+        evaluation=dict(seeds=f"50000..{50000 + a.n_test - 1}", gap_tol=a.gap_tol, dtype="f64",
+                        summary=summary))
+    with open(os.path.splitext(a.out)[0] + ".json", "w") as fh:
+        json.dump(manifest, fh, indent=1)
     return 0
 
 

@@ -59,14 +59,23 @@ def test_pressure_and_preprocess_match_oracle(dt_name):
 
 
 def test_round_trip_gives_the_projection():
-    """A causal pulse without spectral zeros and a tiny eps: preprocessing
-    the modelled pressure gives A u back (FP64)."""
-    d = desc_for(48, 16, 96)
+    """A causal pulse without spectral zeros arriving on a whole sample (the
+    source at the ring's centre, 97 samples: travel time 48 dt) and a tiny
+    eps: preprocessing the modelled pressure gives A u back (FP64). (A pulse
+    starting between samples is not band-limited, so its shifted spectrum
+    does not describe a causal pulse and the window's truncation is not
+    undone.)"""
+    d = desc_for(48, 16, 97)
     og = OG.make_geometry(d)
     A = OG.forward_matrix(og)
     g = pat.Geometry(dtype=torch.float64, **d)
     u = np.clip(np.random.default_rng(6).uniform(-0.2, 1.0, (48, 48)), 0, None)
-    cal = pat.Calibration(g, to_dev(_pulses(og, 1.0, "causal"), torch.float64), XP, YP, 1e-24)
+    dist = np.hypot(og.det_xy[:, 0], og.det_xy[:, 1])
+    k0 = np.rint(dist / d["dt"]).astype(int)
+    assert np.all(k0 == 48) and np.allclose(dist / d["dt"], 48, rtol=0, atol=1e-9)
+    k = np.arange(97)
+    pcal = np.where(k[None, :] >= k0[:, None], np.exp(-np.maximum(k[None, :] - k0[:, None], 0) / 3.0), 0.0)
+    cal = pat.Calibration(g, to_dev(pcal, torch.float64), 0.0, 0.0, 1e-24)
     f = host(cal.preprocess(cal.pressure(to_dev(u, torch.float64))))
     e = rel(f, A @ u.ravel())
     print(f"round trip: rel {e:.2e}", flush=True)
