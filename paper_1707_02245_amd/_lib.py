@@ -5,7 +5,8 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpat.so")
+# PAT_LIB selects another build of the same library (e.g. the host-sanitized one)
+LIB_PATH = os.environ.get("PAT_LIB") or os.path.join(_HERE, "libpat.so")
 
 PAT_OK = 0
 PAT_NOT_CONVERGED = 1
