@@ -550,10 +550,16 @@ __global__ __launch_bounds__(NT) void csr_tiled_kernel(CsrMultiArgs<T> a0, const
   typedef T T4 __attribute__((ext_vector_type(4)));
   int c[G];  // 16-bit offsets held unpacked (packing would wait on the loads)
   T v[G];
-  auto load_group = [&](int base, int* cc, T* vv) {
+  // Lanes whose run starts at or after their row's end (hi) load the row's
+  // last run instead (or the group's first when the row has nothing there):
+  // the values are masked out of the sums either way, and the loads stay
+  // unconditional and in flight together but touch no cache line beyond
+  // the row's own.
+  auto load_group = [&](int base, int hi, int* cc, T* vv) {
+    const int last = max(base, (hi - 1) & ~(K - 1));
 #pragma unroll
     for (int q = 0; q < G / K; ++q) {
-      const int e = base + K * gl + K * LPR * q;
+      const int e = min(base + K * gl + K * LPR * q, last);
       if constexpr (K == 2) {
         const uint32_t w = __builtin_nontemporal_load((gptr<const uint32_t>)(lcol + e));
         cc[2 * q] = (int)(w & 0xffffu);
@@ -577,7 +583,7 @@ __global__ __launch_bounds__(NT) void csr_tiled_kernel(CsrMultiArgs<T> a0, const
     int e0, e1;
     row_range(0, e0, e1);
     int base = e0 & ~(LPR - 1);
-    load_group(base, c, v);
+    load_group(base, e1, c, v);
     for (int b = 0; b < n_batch; ++b) {
       const bool has_next = b + 1 < n_batch;
       int ne0 = 0, ne1 = 0;
@@ -599,9 +605,12 @@ __global__ __launch_bounds__(NT) void csr_tiled_kernel(CsrMultiArgs<T> a0, const
         const bool more = !stale && nb < e1;
         const bool any = __any(more);
         const int next = any ? (more ? nb : base) : (has_next ? (ne0 & ~(LPR - 1)) : base);
+        // the row end of the next step's entries: this row's while it has
+        // more, the next batch's row, or none (a stale placeholder)
+        const int nhi = any ? (more ? e1 : 0) : (has_next ? ne1 : 0);
         int cn[G];
         T vn[G];
-        load_group(next, cn, vn);
+        load_group(next, nhi, cn, vn);
         // every slot is computed (slots past nrhs read stale LDS and are not
         // stored): no per-slot branches between the LDS reads
         Acc vm[G];

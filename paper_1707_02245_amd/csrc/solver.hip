@@ -248,6 +248,7 @@ class Solver {
   // [n_inst][block][3] (host pinned and device), the current iteration's
   // [n_inst][3] read by the kernels
   bool any_accel = false;
+  bool accel_live = false;  // some instance's multipliers still change
   int sched_block = 1;
   DevBuf sched, cur;
   double* h_sched = nullptr;
@@ -275,6 +276,7 @@ class Solver {
       ip->accel = ip->opts.accel_gamma > 0.0;
       any_accel = any_accel || ip->accel;
     }
+    accel_live = any_accel;
     if (any_accel) {
       sched_block = graph_block > 0 ? graph_block : gap_every;
       const size_t n = inst.size();
@@ -292,8 +294,19 @@ class Solver {
   }
 
   // Multipliers of the next `steps` iterations of every active instance.
+  // Once every active accelerated instance's schedule has frozen, its fixed
+  // multipliers are written to the kernels' slot once and later blocks run
+  // without the per-iteration selection launch.
   void upload_schedule(int steps) {
-    if (!any_accel) return;
+    if (!accel_live) return;
+    bool all_frozen = true;
+    for (int k : act) all_frozen = all_frozen && (!inst[k]->accel || inst[k]->acc_frozen);
+    if (all_frozen) {
+      for (int k : act) inst[k]->next_mult(h_sched + (size_t)k * 3);
+      PAT_HIP(hipMemcpyAsync(cur.p, h_sched, cur.bytes, hipMemcpyHostToDevice, s));
+      accel_live = false;
+      return;
+    }
     for (int k : act) {
       Inst<T>& I = *inst[k];
       for (int t = 0; t < steps; ++t) I.next_mult(h_sched + ((size_t)k * sched_block + t) * 3);
@@ -596,7 +609,7 @@ class Solver {
   }
 
   void enqueue_iteration(int t, bool check, int c) {
-    if (any_accel) launch_accel_step(ptr<double>(sched), ptr<double>(cur), (int)inst.size(), sched_block, t, s);
+    if (accel_live) launch_accel_step(ptr<double>(sched), ptr<double>(cur), (int)inst.size(), sched_block, t, s);
     launch_forward_reg_batched<T>(L, lanes_log2, s);
     enqueue_adjoint(check);
     launch_primal<T>(L, check, s);
@@ -726,7 +739,7 @@ class Solver {
   }
 
   hipGraphExec_t graph_for(int steps, const std::vector<int>& checks) {
-    std::string key = std::to_string(steps);
+    std::string key = std::to_string(steps) + (accel_live ? "s" : "");
     for (int c : checks) key += "," + std::to_string(c);
     auto it = graphs.find(key);
     if (it != graphs.end()) return it->second;
