@@ -80,6 +80,8 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--workload", default="tgv256", choices=["tgv256", "dtv512"],
+                   help="the timed reconstruction: 256^2 TGV (the headline) or 512^2 limited-angle dTV")
     p.add_argument("--steps", type=int, default=1)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--cap", type=int, default=100000,
@@ -113,11 +115,11 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def make_inputs(pat, torch, seed):
-    """Vessel-tree phantom (2x finer grid) -> data by the library's FP64 forward
-    operator on the 512^2 grid -> 10% relative Gaussian noise."""
+def make_inputs(pat, torch, seed, name="tgv256"):
+    """The workload's phantom (2x finer grid) -> data by the library's FP64
+    forward operator on that grid -> the workload's relative Gaussian noise."""
     import phantoms
-    wl = phantoms.WORKLOADS["tgv256"]
+    wl = phantoms.WORKLOADS[name]
     desc = phantoms.geometry_desc(wl.n, wl.n_det, wl.n_t, arc_span=wl.arc_span)
     case = phantoms.make_case(wl.family, wl.n, seed, wl.n_det, wl.n_t)
     fine = dict(desc, nx=2 * wl.n, ny=2 * wl.n)
@@ -437,7 +439,7 @@ def main():
     torch.cuda.init()
     dev = torch.cuda.get_device_properties(0)
     log(f"device {dev.name}")
-    wl, desc, case, f_np, fc_np = make_inputs(pat, torch, args.seed)
+    wl, desc, case, f_np, fc_np = make_inputs(pat, torch, args.seed, args.workload)
     tdt = torch.float64 if args.dtype == "f64" else torch.float32
     esz = 8 if args.dtype == "f64" else 4
     g = pat.Geometry(dtype=tdt, **desc)
@@ -446,7 +448,10 @@ def main():
     log(f"autotune: {tune}")
     info_g = g.refresh_info()
     f = torch.tensor(f_np, dtype=tdt, device="cuda")
-    reg = pat.Reg("tgv", wl.lam, wl.alpha0)
+    if wl.reg == "dtv":
+        reg = pat.Reg("dtv", wl.lam, 0.0, wl.eta, torch.tensor(case["theta"], dtype=tdt, device="cuda"))
+    else:
+        reg = pat.Reg(wl.reg, wl.lam, wl.alpha0)
     t0 = time.perf_counter()
     pc = pat.Precond(g, reg, "diag")
     torch.cuda.synchronize()
@@ -563,12 +568,16 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": args.dtype,
-        "data": ("synthetic: vessel-tree phantom (seed %d) rasterised on 512^2, data from the "
-                 "FP64 forward operator on that grid + 10%% relative Gaussian noise" % args.seed),
-        "config": {"workload": f"tgv256 ({args.dtype}): 256x256 TGV2 (alpha1=0.02, alpha0=0.04), 256 detectors "
-                               "on a closed circle of radius 1.2, 512 time samples (radii 0..2.4), "
-                               "DIAG step sizes, stop at relative box gap 1e-4 (C=2), gap every "
-                               f"{args.gap_every} iterations, cap {args.cap}",
+        "data": (f"synthetic: {wl.family} phantom (seed {args.seed}) rasterised on {2 * wl.n}^2, data from the "
+                 f"FP64 forward operator on that grid + {100 * wl.noise:.0f}% relative Gaussian noise"),
+        "config": {"workload": (f"tgv256 ({args.dtype}): 256x256 TGV2 (alpha1=0.02, alpha0=0.04), 256 detectors "
+                                "on a closed circle of radius 1.2, 512 time samples (radii 0..2.4), "
+                                "DIAG step sizes, stop at relative box gap 1e-4 (C=2), gap every "
+                                f"{args.gap_every} iterations, cap {args.cap}") if wl.name == "tgv256" else
+                               (f"{wl.name} ({args.dtype}): {wl.n}x{wl.n} {wl.reg} (lambda {wl.lam}, eta {wl.eta}), "
+                                f"{wl.n_det} detectors over {math.degrees(wl.arc_span):.0f} degrees of a circle of "
+                                f"radius 1.2, {wl.n_t} time samples, {wl.family} phantom, DIAG step sizes, stop at "
+                                f"relative box gap 1e-4 (C=2), gap every {args.gap_every} iterations, cap {args.cap}"),
                    "solver": (f"accelerated PDHGM (Chambolle-Pock Algorithm 2 step schedule on the DIAG steps, "
                               f"gamma {args.accel_gamma}, frozen once the dual steps have grown "
                               f"{args.accel_step_max}x; same problem and gap certificate as constant steps, "

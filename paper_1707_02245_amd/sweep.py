@@ -30,9 +30,12 @@ from . import pat
 SIZES = (128, 192, 256, 384, 512)
 
 
-def build_instances(seed=300, n_groups=16, n_wl=4, noise=0.05, dtype=torch.float64, autotune=True, log=print):
+def build_instances(seed=300, n_groups=16, n_wl=4, noise=0.05, dtype=torch.float64, autotune=True, log=print,
+                    groups=None):
     """Geometries, data and regularisers of the sweep (seeded); returns
-    (problems, meta) with problems as (geometry, data, regulariser) tuples."""
+    (problems, meta) with problems as (geometry, data, regulariser) tuples.
+    groups: optional range of group indices to build (the random draws of
+    the others are still made, so every group is the same in any subset)."""
     import phantoms
     rng = np.random.default_rng(seed)
     problems, meta, geoms = [], [], []
@@ -41,6 +44,12 @@ def build_instances(seed=300, n_groups=16, n_wl=4, noise=0.05, dtype=torch.float
         n_det = int(rng.integers(64, 257))
         span = 2 * math.pi if rng.random() < 0.5 else math.pi
         family = ("disc", "vessel", "segment")[int(rng.integers(3))]
+        if groups is not None and gi not in groups:
+            for w in range(n_wl):  # the draws of this group's wavelengths
+                rng.uniform(0.3, 1.0)
+                rng.integers(3)
+                rng.uniform(-3, -1)
+            continue
         desc = phantoms.geometry_desc(n, n_det, 2 * n, arc_span=span)
         g = pat.Geometry(dtype=dtype, **desc)
         if autotune:
@@ -112,13 +121,19 @@ def main(argv=None):
     ap.add_argument("--no-batched", action="store_true", help="skip the batched solve")
     ap.add_argument("--only", default=None, metavar="A:B",
                     help="one by one: only instances A..B-1 (the rest in other calls)")
+    ap.add_argument("--group-range", default=None, metavar="A:B",
+                    help="build and solve only groups A..B-1 (same instances as in the full sweep)")
+    ap.add_argument("--single-rate", type=int, default=0, metavar="N",
+                    help="time N iterations of every instance solved alone (seconds per iteration of the "
+                         "one-by-one solves, to extrapolate their time to each instance's iteration count)")
     ap.add_argument("--json", default=None)
     a = ap.parse_args(argv)
 
     def log(msg):
         print(f"[sweep] {msg}", flush=True)
 
-    problems, meta, geoms = build_instances(seed=a.seed, n_groups=a.groups, log=log)
+    grp = range(*(int(x) for x in a.group_range.split(":"))) if a.group_range else None
+    problems, meta, geoms = build_instances(seed=a.seed, n_groups=a.groups, log=log, groups=grp)
     res = dict(instances=len(problems), gap_tol=a.gap_tol, cap=a.cap, meta=meta)
     if not a.no_batched:
         log(f"batched solve of {len(problems)} instances")
@@ -129,6 +144,25 @@ def main(argv=None):
     if a.json:
         with open(a.json, "w") as fh:
             json.dump(res, fh, indent=1)
+    if a.single_rate > 0:
+        rates = []
+        for k, (g, f, reg) in enumerate(problems):
+            pat.solve(g, f, reg, max_iter=50, gap_tol=0.0, gap_every=50, graph_block=50)  # graphs, buffers
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pat.solve(g, f, reg, max_iter=a.single_rate, gap_tol=0.0, gap_every=50, graph_block=50)
+            torch.cuda.synchronize()
+            rates.append((time.perf_counter() - t0) / a.single_rate)
+            log(f"instance {k} alone: {rates[-1] * 1e6:.1f} us per iteration")
+        res["single_s_per_iteration"] = rates
+        if "batched" in res:
+            est = sum(r * b["iters"] for r, b in zip(rates, res["batched"]))
+            res["one_by_one_estimated_s"] = est
+            log(f"one by one, extrapolated from {a.single_rate} iterations each to the batched run's "
+                f"iteration counts: {est:.1f} s against batched {res['batched_s']:.1f} s")
+        if a.json:
+            with open(a.json, "w") as fh:
+                json.dump(res, fh, indent=1)
     if a.one_by_one:
         seq, t_seq = [], 0.0
         lo, hi = (int(x) for x in a.only.split(":")) if a.only else (0, len(problems))
