@@ -111,6 +111,8 @@ typedef struct {
   int32_t csr_lanes;      /* lanes per matrix row in mode 2 (16 or 64) */
   int32_t fwd_path;      /* forward: 0/1 gather (radius-/detector-major), 2 LDS tiles */
   int64_t fwd_pairs;      /* (bin, sample range) pairs of path 2 */
+  int32_t fwd_sym;        /* 4: the forward runs in quarter-turn form (see
+                           * pat_geometry_set_forward_symmetry); 1: not */
 } pat_geometry_info;
 
 /* Build the geometry tables on the device (FP64 host computation, rounded to
@@ -157,6 +159,21 @@ pat_status pat_geometry_set_forward_path(pat_geometry g, int32_t path, void* str
  * same result up to summation order. Invalid values: PAT_ERR_INVALID_ARG. */
 pat_status pat_geometry_set_tiled_launch(pat_geometry g, int32_t waves, int32_t row_lanes);
 
+/* Whether the forward may use the quarter-turn symmetry (default 0, the
+ * autotuner times both; takes effect on symmetric geometries, info.sym_rot ==
+ * 4, with gather paths 0 and 1). The weights obey w(d + t n_det/4, k, R^t p) = w(d, k, p) for the quarter
+ * turn R of the pixel grid, so the bins of detector d + t n_det/4 are those of
+ * detector d on the image turned by t quarter turns: the gather then runs over
+ * the first n_det/4 detectors and each arc sample's table entry, position and
+ * cell serve four bins, read from the image and three turned copies (built by
+ * a padding pass in stand-alone applies and by the primal step in the
+ * solvers). Same operator; bins of the last three quarters agree with the
+ * direct evaluation to rounding of the sample positions, and pat_adjoint with
+ * the quarter-turn CSR is then its exact transpose. Solver instances take the
+ * setting in effect when the solve starts. Invalid handle:
+ * PAT_ERR_INVALID_ARG. */
+pat_status pat_geometry_set_forward_symmetry(pat_geometry g, int32_t enable);
+
 /* Whether the stored A^T may use the quarter-turn symmetry (default 1). On a
  * symmetric geometry (info.sym_rot == 4) the CSR then holds the rows of the
  * first n_det/4 detectors only, a quarter of the non-zeros, and modes 1 and 2
@@ -169,8 +186,9 @@ pat_status pat_geometry_set_symmetry(pat_geometry g, int32_t enable, void* strea
 
 /* Autotuner of the projector launch parameters. Times, with HIP events over
  * `reps` stand-alone applies on `stream`, the forward with 16/32/64 lanes per
- * bin and the adjoint as stored CSR or as tile scatter (tiles 16/32/64,
- * several detector-group sizes), and keeps the fastest of each. If
+ * bin in either block order, by LDS tiles, and (symmetric geometries) in
+ * quarter-turn form, and the adjoint as stored CSR or as tile scatter (tiles
+ * 16/32/64, several detector-group sizes), and keeps the fastest of each. If
  * cache_path is non-NULL the choice is read from / appended to that text
  * file, keyed by device architecture, geometry shape and element type, so a
  * later call with the same key times nothing. `out` may be NULL. */

@@ -47,6 +47,7 @@ class GeometryInfo(C.Structure):
         ("csr_win_max", C.c_int32), ("csr_rot", C.c_int32), ("sym_rot", C.c_int32),
         ("csr_waves", C.c_int32), ("csr_lanes", C.c_int32), ("fwd_path", C.c_int32),
         ("fwd_pairs", C.c_int64),
+        ("fwd_sym", C.c_int32),
     ]
 
 
@@ -97,6 +98,7 @@ _SIGS = {
     "pat_geometry_set_launch": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32], C.c_int),
     "pat_geometry_set_adjoint": ([C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
     "pat_geometry_set_symmetry": ([C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
+    "pat_geometry_set_forward_symmetry": ([C.c_void_p, C.c_int32], C.c_int),
     "pat_geometry_set_tiled_launch": ([C.c_void_p, C.c_int32, C.c_int32], C.c_int),
     "pat_geometry_set_forward_path": ([C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
     "pat_geometry_autotune": ([C.c_void_p, C.c_char_p, C.c_int32, C.c_void_p,

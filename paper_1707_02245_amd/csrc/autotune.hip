@@ -1,7 +1,8 @@
 // Launch-parameter autotuner of the projector kernels, with an on-disk cache.
 //
-// Candidates: forward lanes per bin (16, 32, 64) and block order (radius- or
-// detector-major), and the adjoint path (stored
+// Candidates: forward lanes per bin (16, 32, 64), block order (radius- or
+// detector-major) and, on quarter-turn symmetric geometries, the direct or
+// the quarter-turn form, and the adjoint path (stored
 // CSR, plain or with LDS-staged input windows in workgroups of 4, 8 or 16 waves
 // and 16 or 64 lanes per row,
 // or the matrix-free tile scatter with 16/32/64-pixel tiles and a few
@@ -9,7 +10,8 @@
 // stand-alone applies on the caller's stream; the fastest of each kind is
 // kept. Results are cached per (device architecture, geometry shape, element
 // type, quarter-turn use) in a plain text file: one line per key,
-// "key lanes fwd_path adj_mode tile group waves row_lanes t_forward t_adjoint".
+// "key lanes fwd_path fwd_sym adj_mode tile group waves row_lanes t_forward
+// t_adjoint".
 
 #include <algorithm>
 #include <cstdio>
@@ -35,7 +37,7 @@ std::string cache_key(const pat_geometry_s* g) {
   if (colon != std::string::npos) arch = arch.substr(0, colon);
   char buf[512];
   const int rot = (g->sym_enabled && g->sym_rot == 4) ? 4 : 1;
-  std::snprintf(buf, sizeof(buf), "v6|%s|nx=%d|ny=%d|ndet=%d|nt=%d|dt=%d|span=%.6f|r=%.6f|spp=%.4f|t=%.6g|rot=%d",
+  std::snprintf(buf, sizeof(buf), "v7|%s|nx=%d|ny=%d|ndet=%d|nt=%d|dt=%d|span=%.6f|r=%.6f|spp=%.4f|t=%.6g|rot=%d",
                 arch.c_str(), g->nx, g->ny, g->n_det, g->n_t, g->dtype, g->desc.arc_span,
                 g->desc.det_radius, g->desc.samples_per_pixel, g->desc.dt * g->desc.c / g->h, rot);
   return buf;
@@ -91,17 +93,27 @@ void tune(pat_geometry_s* g, int reps, hipStream_t s, pat_autotune_result* res) 
   // forward: lanes per bin
   double best_f = 1e30;
   int best_l = g->lanes_log2, best_o = g->fwd_path;
+  bool best_sym = g->fwd_sym;
   g->ensure_fwd_tiles(s);
   for (int o = 0; o <= 2; ++o)
-    for (int l = 4; l <= 6; ++l) {
-      if (o == 2 && l != 4) continue;  // the tiled path has one shape
-      g->lanes_log2 = l;
-      g->fwd_path = o;
-      const double t = time_op<T>(s, reps, [&] { apply_forward<T>(g, ptr<T>(u), ptr<T>(out_f), s); });
-      if (t < best_f) { best_f = t; best_l = l; best_o = o; }
-    }
+    for (int l = 4; l <= 6; ++l)
+      for (int sym = 0; sym <= 1; ++sym) {
+        if (o == 2 && l != 4) continue;  // the tiled path has one shape
+        if (sym && (o == 2 || g->sym_rot != 4)) continue;  // no quarter-turn form
+        g->lanes_log2 = l;
+        g->fwd_path = o;
+        g->fwd_sym = sym != 0;
+        const double t = time_op<T>(s, reps, [&] { apply_forward<T>(g, ptr<T>(u), ptr<T>(out_f), s); });
+        if (t < best_f) {
+          best_f = t;
+          best_l = l;
+          best_o = o;
+          best_sym = sym != 0;
+        }
+      }
   g->lanes_log2 = best_l;
   g->fwd_path = best_o;
+  g->fwd_sym = best_sym;
   // adjoint: stored CSR (plain and LDS-staged) vs scatter variants
   double best_a = 1e30;
   int best_mode = 1, best_tile = g->tile, best_group = g->det_group;
@@ -163,15 +175,16 @@ extern "C" pat_status pat_geometry_autotune(pat_geometry g, const char* cache_pa
     bool applied = false;
     if (it != cache.end()) {
       std::istringstream in(it->second);
-      int lanes = 0, mode = -1, tile = 0, group = 0, wg = -1, rl = -1, fo = -1;
+      int lanes = 0, mode = -1, tile = 0, group = 0, wg = -1, rl = -1, fo = -1, fsym = -1;
       double tf = 0, ta = 0;
-      if (in >> lanes >> fo >> mode >> tile >> group >> wg >> rl >> tf >> ta && lanes >= 4 && lanes <= 6 &&
-          (fo >= 0 && fo <= 2) &&
+      if (in >> lanes >> fo >> fsym >> mode >> tile >> group >> wg >> rl >> tf >> ta && lanes >= 4 && lanes <= 6 &&
+          (fo >= 0 && fo <= 2) && (fsym == 0 || fsym == 1) &&
           (mode >= 0 && mode <= 2) && (tile == 16 || tile == 32 || tile == 64) && group >= 1 &&
           group <= g->n_det && (wg == 4 || wg == 8 || wg == 16) && (rl == 16 || rl == 64)) {
         g->lanes_log2 = lanes;
         if (fo == 2) g->ensure_fwd_tiles(s);
         g->fwd_path = fo;
+        g->fwd_sym = fsym != 0;
         g->tile = tile;
         g->det_group = group;
         if (mode != 0) g->ensure_csr(s);
@@ -188,8 +201,9 @@ extern "C" pat_status pat_geometry_autotune(pat_geometry g, const char* cache_pa
       if (g->dtype == PAT_F64) pat::tune<double>(g, reps, s, &res);
       else pat::tune<float>(g, reps, s, &res);
       char buf[128];
-      std::snprintf(buf, sizeof(buf), "%d %d %d %d %d %d %d %.6f %.6f", g->lanes_log2, g->fwd_path, g->adj_mode,
-                    g->tile, g->det_group, g->csr_waves, g->csr_lanes, res.forward_ms, res.adjoint_ms);
+      std::snprintf(buf, sizeof(buf), "%d %d %d %d %d %d %d %d %.6f %.6f", g->lanes_log2, g->fwd_path,
+                    g->fwd_sym ? 1 : 0, g->adj_mode, g->tile, g->det_group, g->csr_waves, g->csr_lanes,
+                    res.forward_ms, res.adjoint_ms);
       cache[key] = buf;
       pat::write_cache(cache_path, cache);
     }

@@ -21,6 +21,7 @@
 #include <cstring>
 #include <memory>
 #include <new>
+#include <numeric>
 #include <thread>
 
 #include "pat_internal.hpp"
@@ -246,6 +247,7 @@ void pat_geometry_s::upload(hipStream_t stream) {
   // i.e. lie in the box [-1, nx] x [-1, ny] of index space
   const int64_t nb = (int64_t)n_det * n_t;
   std::vector<int4> h_win(2 * nb);
+  std::vector<int64_t> work(n_t, 0);
   n_window = 0;
   for (int i = 0; i < n_det; ++i) {
     for (int k = 0; k < n_t; ++k) {
@@ -257,6 +259,7 @@ void pat_geometry_s::upload(hipStream_t stream) {
         v[2 * j] = rg[j].a;
         v[2 * j + 1] = rg[j].b;
         n_window += rg[j].b - rg[j].a;
+        work[k] += rg[j].b - rg[j].a;
       }
       const int64_t b = (int64_t)i * n_t + k;
       h_win[2 * b] = make_int4(v[0], v[1], v[2], v[3]);
@@ -269,6 +272,13 @@ void pat_geometry_s::upload(hipStream_t stream) {
   // the table is FP64 for every element type (positions are FP64)
   d_cs.alloc(sizeof(double2) * n_samples_per_det);
   d_win.alloc(sizeof(int4) * 2 * nb);
+  // the radius-major gather takes its heaviest radii first, so that the
+  // light ones fill the end of the launch
+  std::vector<int> kord(n_t);
+  std::iota(kord.begin(), kord.end(), 0);
+  std::stable_sort(kord.begin(), kord.end(), [&](int a, int b) { return work[a] > work[b]; });
+  d_kord.alloc(sizeof(int) * n_t);
+  PAT_HIP(hipMemcpyAsync(d_kord.p, kord.data(), d_kord.bytes, hipMemcpyHostToDevice, stream));
   PAT_HIP(hipMemcpyAsync(d_det.p, h_det.data(), d_det.bytes, hipMemcpyHostToDevice, stream));
   PAT_HIP(hipMemcpyAsync(d_rad.p, h_rad.data(), d_rad.bytes, hipMemcpyHostToDevice, stream));
   PAT_HIP(hipMemcpyAsync(d_moff.p, h_moff.data(), d_moff.bytes, hipMemcpyHostToDevice, stream));
@@ -433,6 +443,7 @@ extern "C" pat_status pat_geometry_get_info(pat_geometry g, pat_geometry_info* o
     out->csr_lanes = g->csr_lanes;
     out->fwd_path = g->fwd_path;
     out->fwd_pairs = g->fwd_n_pairs;
+    out->fwd_sym = g->fwd_qt() ? 4 : 1;
     return PAT_OK;
   });
 }
@@ -473,6 +484,14 @@ extern "C" pat_status pat_geometry_set_tiled_launch(pat_geometry g, int32_t wave
     PAT_CHECK_ARG(row_lanes == 16 || row_lanes == 64, "lanes per row must be 16 or 64");
     g->csr_waves = waves;
     g->csr_lanes = row_lanes;
+    return PAT_OK;
+  });
+}
+
+extern "C" pat_status pat_geometry_set_forward_symmetry(pat_geometry g, int32_t enable) {
+  return guarded([&]() -> pat_status {
+    PAT_CHECK_ARG(g != nullptr, "geometry is NULL");
+    g->fwd_sym = enable != 0;
     return PAT_OK;
   });
 }

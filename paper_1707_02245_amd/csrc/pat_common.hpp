@@ -198,6 +198,8 @@ struct GeomDev {
   const int2* moff;      // [n_t] (M_k, offset of radius k in the table)
   const void* cs;        // [sum M_k] (cos, sin) of 2 pi (m + 1/2) / M_k, FP64
   const int4* win;       // [n_bins][2]: four sample ranges [m0,m1) per bin
+  const int* kord;       // [n_t] radii by decreasing window samples (the
+                         // radius-major gather's block order; null: 0..n_t-1)
   double kscale, koff;   // radius index of a radius rho in pixel units: rho*kscale - koff
   int lanes_log2;        // forward: lanes per bin, log2 (4..6)
   int fwd_path;          // forward: 0/1 gather (radius-/detector-major), 2 LDS tiles
@@ -233,6 +235,12 @@ struct FwdArgs {
   T* part;            // path 2: partial sums [pairs]
   const double* mult; // DUAL: step multipliers {dual, primal, theta} of this
                       // iteration (accelerated schedule; null: plain steps)
+  // Quarter-turn slots (the gather's QT form): g.n_det is a quarter of the
+  // detectors and slot t (0..3) reads the image turned by t quarter turns at
+  // upad + t slot_img, writes the bins of detectors t n_det/4 .. at out + t
+  // slot_bins (f, sigma and q likewise) and its gap partials at red + t slot_red.
+  int64_t slot_img, slot_bins;
+  int slot_red;
 };
 
 // Adjoint projection of one instance into per-detector-group partial images.
@@ -270,6 +278,9 @@ struct InstDev {
   int red_stride;
   const double* mult; // step multipliers {dual, primal, theta} of this
                       // iteration (accelerated schedule; null: plain steps)
+  int rot_slots;      // 4: ubar_pad and upad_gap hold, after the image, its
+                      // copies turned by 1, 2 and 3 quarter turns (padded
+                      // size apart) for the quarter-turn forward; else 1
 };
 
 // y = M x for a CSR matrix M (rows n_rows).
@@ -312,11 +323,18 @@ struct CsrMultiArgs {
 };
 
 // Pixel (i, j) of a square n x n grid turned by t quarter turns (counter-
-// clockwise, about the grid centre): (i, j) -> (n-1-j, i).
-__device__ __forceinline__ int64_t quarter_turn(int i, int j, int n, int t) {
-  int a = i, b = j;
+// clockwise, about the grid centre): (i, j) -> (n-1-j, i), as coordinates
+// (a, b) and as the linear index b n + a.
+__device__ __forceinline__ void quarter_turn_xy(int i, int j, int n, int t, int& a, int& b) {
+  a = i;
+  b = j;
   if (t & 2) { a = n - 1 - i; b = n - 1 - j; }
   if (t & 1) { const int c = a; a = n - 1 - b; b = c; }
+}
+
+__device__ __forceinline__ int64_t quarter_turn(int i, int j, int n, int t) {
+  int a, b;
+  quarter_turn_xy(i, j, n, t, a, b);
   return (int64_t)b * n + a;
 }
 

@@ -34,6 +34,10 @@ struct pat_geometry_s {
   // csr_rot = 4 when the stored A^T holds the first n_det/4 detectors only
   int sym_rot = 1, csr_rot = 1;
   bool sym_enabled = true;
+  // the forward in quarter-turn form on symmetric geometries (gather paths;
+  // off by default, the autotuner times it)
+  bool fwd_sym = false;
+  bool fwd_qt() const { return fwd_sym && sym_rot == 4 && fwd_path != 2; }
   // pixel tiles of the stored A^T (side 0: windows too large for LDS);
   // csr_win_max is per quarter-turn slot
   int csr_side = 0, csr_tiles_x = 0, csr_tiles_y = 0, csr_win_max = 0;
@@ -43,6 +47,8 @@ struct pat_geometry_s {
   pat::DevBuf csr_lcol, csr_win;  // uint16 per non-zero; int4 per (tile, detector)
   // scratch of the stand-alone applies
   pat::DevBuf scratch_pad, scratch_part;
+  // radii by decreasing samples in their clip windows (over all detectors)
+  pat::DevBuf d_kord;
 
   void build_host();
   void upload(hipStream_t stream);
@@ -131,6 +137,12 @@ template <class T>
 void launch_pad(const T* u, T* upad, int nx, int ny, hipStream_t s);
 template <class T>
 void launch_forward(int mode, const FwdArgs<T>& a, int lanes_log2, hipStream_t s);
+// quarter-turn forward: the padded image and its turned copies (slots), and
+// the gather over a quarter of the detectors in slot form (PLAIN or DUAL)
+template <class T>
+void launch_rot_pad(const T* src, bool src_padded, T* dst, int n, int slots, hipStream_t s);
+template <class T>
+void launch_forward_qt(int mode, const FwdArgs<T>& a, int lanes_log2, hipStream_t s);
 template <class T>
 void launch_forward_batched(int mode, const Launch<T>& L, int lanes_log2, hipStream_t s);
 // forward with the data term's dual step and the regulariser's dual step in

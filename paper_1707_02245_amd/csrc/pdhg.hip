@@ -109,6 +109,19 @@ __global__ __launch_bounds__(256) void primal_kernel(const InstDev<T>* __restric
       u2 = (double)u_old * (double)u_old;
       a.upad_gap[(int64_t)(j + 1) * P + (i + 1)] = un;
     }
+    if (a.rot_slots == 4) {
+      // the quarter-turn forward's copies: slot t holds the image turned by t
+      // quarter turns, so this pixel's value lands where t turns bring it here
+      const int64_t PP = (int64_t)P * (ny + 2);
+#pragma unroll
+      for (int t = 1; t < 4; ++t) {
+        int x, y;
+        quarter_turn_xy(i, j, nx, (4 - t) & 3, x, y);
+        const int64_t o = t * PP + (int64_t)(y + 1) * P + (x + 1);
+        a.ubar_pad[o] = ubar;
+        if (CHECK) a.upad_gap[o] = un;
+      }
+    }
     if (a.kind == PAT_REG_TGV) {
       // v <- v - tau_v (E^T s - r); (E^T s)_x = -dx+ sxx - dy+ sxy, (E^T s)_y = -dx+ sxy - dy+ syy
       const bool ax = i < nx - 1, ay = j < ny - 1;

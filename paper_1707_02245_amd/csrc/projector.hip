@@ -22,6 +22,15 @@
 #include "pat_internal.hpp"
 #include "reg_dual.hpp"
 
+#ifndef PAT_FWD_LPT
+#define PAT_FWD_LPT 1
+#endif
+#ifdef PAT_FWD_WPE
+#define PAT_FWD_ATTR __attribute__((amdgpu_waves_per_eu(PAT_FWD_WPE)))
+#else
+#define PAT_FWD_ATTR
+#endif
+
 namespace pat {
 
 constexpr double kTwoPiD = 6.283185307179586476925286766559;
@@ -75,6 +84,40 @@ void launch_pad(const T* u, T* upad, int nx, int ny, hipStream_t s) {
   PAT_HIP(hipGetLastError());
 }
 
+// Padded copies of an n x n image for the quarter-turn forward: slot t (at
+// dst + t (n+2)^2) holds the padded image turned by t quarter turns, slot_t(x,
+// y) = upad(R^t (x, y)) on the (n+2) x (n+2) padded grid (the border maps to
+// the border). src is the image [n][n] or, with src_padded, its padded copy.
+template <class T>
+__global__ __launch_bounds__(256) void rot_pad_kernel(const T* __restrict__ src, int src_padded,
+                                                      T* __restrict__ dst, int n, int slots) {
+  const int P = n + 2;
+  const int64_t np = (int64_t)P * P;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < np * slots;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int t = (int)(idx / np);
+    const int64_t q = idx - t * np;
+    int a, b;
+    quarter_turn_xy((int)(q % P), (int)(q / P), P, t, a, b);
+    T v;
+    if (src_padded) {
+      v = src[(int64_t)b * P + a];
+    } else {
+      const int i = a - 1, j = b - 1;
+      v = (i >= 0 && i < n && j >= 0 && j < n) ? src[(int64_t)j * n + i] : T(0);
+    }
+    dst[idx] = v;
+  }
+}
+
+template <class T>
+void launch_rot_pad(const T* src, bool src_padded, T* dst, int n, int slots, hipStream_t s) {
+  const int64_t total = (int64_t)(n + 2) * (n + 2) * slots;
+  const int blocks = (int)std::min<int64_t>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(rot_pad_kernel<T>, dim3(blocks), dim3(256), 0, s, src, src_padded ? 1 : 0, dst, n, slots);
+  PAT_HIP(hipGetLastError());
+}
+
 // ------------------------------------------------------------------ forward
 
 // The value val = (A x)_b of bin b, computed by this thread (writer), goes
@@ -121,9 +164,14 @@ __device__ __forceinline__ void fwd_epilogue(const FwdArgs<T>& a, int blk, bool 
 // after the group's last instance have no image), and starts the groups'
 // block offsets: each block serves a whole group, a sample's table entry,
 // position and cell computed once and its 2x2 taps read from each
-// instance's image.
-template <class T, int MODE, int LANES, bool FUSED = false, int NI = 1>
-__global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T>* __restrict__ arr,
+// instance's image. On a quarter-turn symmetric geometry the bins of detector
+// d + t n_det/4 are those of detector d on the image turned by t quarter
+// turns, so a group's slots can also be the four turned images of one
+// instance over the first n_det/4 detectors (the solvers build such slot
+// arrays); with QT (NI = 4) a0 alone describes the four slots (its slot
+// fields), the form of the stand-alone forward.
+template <class T, int MODE, int LANES, bool FUSED = false, int NI = 1, bool QT = false>
+__global__ __launch_bounds__(256) PAT_FWD_ATTR void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T>* __restrict__ arr,
                                                   const int* __restrict__ starts, int n_inst, int n_fwd,
                                                   const InstDev<T>* __restrict__ rarr,
                                                   const int* __restrict__ rstarts, int rn) {
@@ -136,7 +184,11 @@ __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T
   }
   FwdArgs<T> a;
   int cnt = 1;  // instances in this block's group
-  if constexpr (NI > 1) {
+  if constexpr (QT) {
+    static_assert(NI == 4, "quarter-turn slots come in fours");
+    a = a0;
+    cnt = NI;
+  } else if constexpr (NI > 1) {
     const int gi = find_inst(starts, n_inst, blk);
     arr += (int64_t)NI * gi;
     blk -= starts[gi];
@@ -166,6 +218,7 @@ __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T
     const int n_dg = (g.n_det + BPB - 1) / BPB;
     k = blk / n_dg;
     d = (blk - k * n_dg) * BPB + sub;
+    if (g.kord) k = g.kord[k];
   }
   const bool valid = d < g.n_det && k < g.n_t;
   const int b = d * g.n_t + k;
@@ -181,7 +234,8 @@ __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T
     const int toff = g.moff[k].y;
     gptr<const char> ub[NI];
 #pragma unroll
-    for (int i = 0; i < NI; ++i) ub[i] = as_global(reinterpret_cast<const char*>(NI > 1 ? arr[i].upad : a.upad));
+    for (int i = 0; i < NI; ++i)
+      ub[i] = as_global(reinterpret_cast<const char*>(QT ? a.upad + i * a.slot_img : (NI > 1 ? arr[i].upad : a.upad)));
     const int P = g.pitch;
     const unsigned rowb = (unsigned)P * (unsigned)sizeof(T);
     const int nx = g.nx, ny = g.ny;
@@ -201,7 +255,7 @@ __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T
       const unsigned off = (unsigned)o * (unsigned)sizeof(T);
 #pragma unroll
       for (int i = 0; i < NI; ++i) {
-        if (NI > 1 && i >= cnt) {
+        if (NI > 1 && !QT && i >= cnt) {
           t[i] = T(0);
           continue;
         }
@@ -236,7 +290,19 @@ __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T
   }
 #pragma unroll
   for (int i = 0; i < NI; ++i) acc[i] = group_sum<LANES>(acc[i]);
-  if constexpr (NI == 1) {
+  if constexpr (QT) {
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      FwdArgs<T> ai = a;
+      const int64_t ob = i * a.slot_bins;
+      if (ai.out) ai.out += ob;
+      if (ai.f) ai.f += ob;
+      if (ai.sigma) ai.sigma += ob;
+      if (ai.q) ai.q += ob;
+      if (ai.red) ai.red += i * a.slot_red;
+      fwd_epilogue<T, MODE>(ai, blk, valid && lane == 0, b, acc[i] * (T)inv_m);
+    }
+  } else if constexpr (NI == 1) {
     fwd_epilogue<T, MODE>(a, blk, valid && lane == 0, b, acc[0] * (T)inv_m);
   } else {
 #pragma unroll
@@ -405,6 +471,32 @@ void launch_forward(int mode, const FwdArgs<T>& a, int lanes_log2, hipStream_t s
     return;
   }
   fwd_mode_dispatch<T>(mode, lanes_log2, blocks, a, nullptr, nullptr, 1, s);
+}
+
+// Stand-alone forward in quarter-turn form: a.g holds a quarter of the
+// detectors and the slot fields of a locate the turned images and the other
+// quarters' bins (the solvers use the slot-array form of the NI = 4 gather).
+template <class T>
+void launch_forward_qt(int mode, const FwdArgs<T>& a, int lanes_log2, hipStream_t s) {
+  PAT_CHECK_ARG(mode == FWD_PLAIN, "quarter-turn stand-alone forward: plain mode only");
+  const int blocks = fwd_grid(a.g.n_det, a.g.n_t, lanes_log2, a.g.fwd_path);
+  if (blocks <= 0) return;
+  const FwdArgs<T>* none = nullptr;
+  switch (lanes_log2) {
+    case 4:
+      hipLaunchKernelGGL((fwd_kernel<T, FWD_PLAIN, 16, false, 4, true>), dim3(blocks), dim3(256), 0, s, a, none,
+                         nullptr, 1, blocks, nullptr, nullptr, 0);
+      break;
+    case 5:
+      hipLaunchKernelGGL((fwd_kernel<T, FWD_PLAIN, 32, false, 4, true>), dim3(blocks), dim3(256), 0, s, a, none,
+                         nullptr, 1, blocks, nullptr, nullptr, 0);
+      break;
+    default:
+      hipLaunchKernelGGL((fwd_kernel<T, FWD_PLAIN, 64, false, 4, true>), dim3(blocks), dim3(256), 0, s, a, none,
+                         nullptr, 1, blocks, nullptr, nullptr, 0);
+      break;
+  }
+  PAT_HIP(hipGetLastError());
 }
 
 // Instances grouped by geometry: every block serves a group of up to NI; with
@@ -647,6 +739,8 @@ void launch_reduce_groups(const T* part, T* out, int n_groups, int64_t n, hipStr
 
 #define PAT_INST_PROJ(T)                                                                    \
   template void launch_pad<T>(const T*, T*, int, int, hipStream_t);                         \
+  template void launch_rot_pad<T>(const T*, bool, T*, int, int, hipStream_t);               \
+  template void launch_forward_qt<T>(int, const FwdArgs<T>&, int, hipStream_t);             \
   template void launch_forward<T>(int, const FwdArgs<T>&, int, hipStream_t);                \
   template void launch_forward_batched<T>(int, const Launch<T>&, int, hipStream_t);        \
   template void launch_forward_reg_batched<T>(const Launch<T>&, int, hipStream_t);          \
@@ -672,6 +766,11 @@ pat::GeomDev pat_geometry_s::dev() const {
   g.moff = pat::ptr<int2>(d_moff);
   g.cs = d_cs.p;
   g.win = pat::ptr<int4>(d_win);
+#if PAT_FWD_LPT
+  g.kord = pat::ptr<int>(d_kord);
+#else
+  g.kord = nullptr;
+#endif
   g.kscale = h / (desc.c * desc.dt);
   g.koff = desc.t0 / desc.dt;
   g.lanes_log2 = lanes_log2;
@@ -710,8 +809,31 @@ void pat_geometry_s::drop_csr() {
 
 namespace {
 
+// Quarter-turn form of a stand-alone forward: the four turned padded copies
+// of the input in the geometry's scratch, then the gather over the first
+// quarter of the detectors.
+template <class T>
+void forward_qt_impl(pat_geometry g, const T* src, bool src_padded, T* f, hipStream_t s) {
+  const int64_t P = (int64_t)(g->nx + 2) * (g->ny + 2);
+  g->scratch_pad.ensure(sizeof(T) * (size_t)(4 * P));
+  T* slots = pat::ptr<T>(g->scratch_pad);
+  pat::launch_rot_pad<T>(src, src_padded, slots, g->nx, 4, s);
+  pat::FwdArgs<T> a{};
+  a.g = g->dev();
+  a.g.n_det = g->n_det / 4;
+  a.upad = slots;
+  a.out = f;
+  a.slot_img = P;
+  a.slot_bins = (int64_t)a.g.n_det * g->n_t;
+  pat::launch_forward_qt<T>(pat::FWD_PLAIN, a, g->lanes_log2, s);
+}
+
 template <class T>
 void forward_impl(pat_geometry g, const void* d_u, void* d_f, hipStream_t s) {
+  if (g->fwd_qt()) {
+    forward_qt_impl<T>(g, static_cast<const T*>(d_u), false, static_cast<T*>(d_f), s);
+    return;
+  }
   g->scratch_pad.ensure(sizeof(T) * (size_t)(g->nx + 2) * (g->ny + 2));
   T* upad = pat::ptr<T>(g->scratch_pad);
   pat::launch_pad<T>(static_cast<const T*>(d_u), upad, g->nx, g->ny, s);
@@ -741,6 +863,10 @@ namespace {
 
 template <class T>
 void forward_padded_impl(pat_geometry g, const void* d_upad, void* d_f, hipStream_t s) {
+  if (g->fwd_qt()) {
+    forward_qt_impl<T>(g, static_cast<const T*>(d_upad), true, static_cast<T*>(d_f), s);
+    return;
+  }
   pat::FwdArgs<T> a{};
   a.g = g->dev();
   a.upad = static_cast<const T*>(d_upad);

@@ -191,6 +191,9 @@ struct Inst {
   std::unique_ptr<pat_precond_s> own_pc;
   int n_fwd = 0, n_pix = 0, n_adj = 0, n_csr = 0, red_stride = 0;
   bool csr = false;  // adjoint by the stored CSR of A^T
+  // forward in quarter-turn form: ubar_pad and upad_gap hold four slots (the
+  // image and its copies turned by 1..3 quarter turns)
+  bool qt = false;
   int iters = 0;
   bool active = true, converged = false;
   int fallback = 0;
@@ -319,9 +322,11 @@ class Solver {
     const int64_t N = g->n_pix(), nb = g->n_bins();
     const size_t P = (size_t)(g->nx + 2) * (g->ny + 2);
     const int kind = I.reg.kind;
+    I.qt = g->fwd_qt();
+    const int slots = I.qt ? 4 : 1;
     I.u.alloc(sizeof(T) * N);
-    I.ubar_pad.alloc(sizeof(T) * P);
-    I.upad_gap.alloc(sizeof(T) * P);
+    I.ubar_pad.alloc(sizeof(T) * slots * P);
+    I.upad_gap.alloc(sizeof(T) * slots * P);
     I.q.alloc(sizeof(T) * nb);
     if (kind != PAT_REG_TIKHONOV) I.r.alloc(sizeof(T) * 2 * N);
     if (kind == PAT_REG_TGV) {
@@ -340,6 +345,10 @@ class Solver {
     // picks the path of the batch)
     I.n_fwd = std::max({fwd_grid(g->n_det, g->n_t, lanes_log2, 0), fwd_grid(g->n_det, g->n_t, lanes_log2, 1),
                         fwd_grid(g->n_det, g->n_t, lanes_log2, 2)});
+    // quarter-turn form: four slots of partials over a quarter's blocks
+    if (I.qt)
+      I.n_fwd = std::max({I.n_fwd, 4 * fwd_grid(g->n_det / 4, g->n_t, lanes_log2, 0),
+                          4 * fwd_grid(g->n_det / 4, g->n_t, lanes_log2, 1)});
     if (g->fwd_path == 2) I.fpart.alloc(sizeof(T) * (size_t)std::max<int64_t>(g->fwd_n_pairs, 1));
     I.n_pix = pix_blocks(N);
     I.n_adj = I.csr ? 0 : gd.tiles_x * gd.tiles_y * gd.n_groups;
@@ -385,6 +394,7 @@ class Solver {
     d.red = ptr<double>(I.red);
     d.red_stride = I.red_stride;
     d.mult = I.accel ? ptr<double>(cur) + 3 * inst_index(I) : nullptr;
+    d.rot_slots = I.qt ? 4 : 1;
     return d;
   }
 
@@ -401,6 +411,9 @@ class Solver {
     // gather kernel (radius-major for those that chose tiles)
     bool fwd_tiled = n > 0;
     for (int k = 0; k < n; ++k) fwd_tiled = fwd_tiled && inst[act[k]]->g->fwd_path == 2 && inst[act[k]]->fpart.p;
+    // instances in quarter-turn form (gather forward only)
+    std::vector<bool> qt(n, false);
+    for (int k = 0; k < n; ++k) qt[k] = !fwd_tiled && inst[act[k]]->qt;
     std::vector<int> ts(n + 1, 0);
     std::vector<FwdArgs<T>> fd(n), fg(n);
     std::vector<AdjArgs<T>> ad;
@@ -431,7 +444,16 @@ class Solver {
       const int path = fwd_tiled ? 2 : (I.g->fwd_path == 2 ? 0 : I.g->fwd_path);
       fd[k].g.fwd_path = fg[k].g.fwd_path = path;
       fd[k].part = fg[k].part = ptr<T>(I.fpart);
-      const int n_fwd = fwd_grid(I.g->n_det, I.g->n_t, lanes_log2, path);
+      int n_fwd = fwd_grid(I.g->n_det, I.g->n_t, lanes_log2, path);
+      int n_fwd_parts = n_fwd;  // gap partials of the forward
+      if (qt[k]) {
+        // a quarter of the detectors; the group's four slots (below) read the
+        // image turned by t quarter turns for the bins of detectors t n_det/4 ..
+        const int q = I.g->n_det / 4;
+        fd[k].g.n_det = fg[k].g.n_det = q;
+        n_fwd = fwd_grid(q, I.g->n_t, lanes_log2, path);
+        n_fwd_parts = 4 * n_fwd;
+      }
       ts[k + 1] = ts[k] + (fwd_tiled ? I.g->fwd_n_blocks : 0);
       if (I.csr) {
         // instances sharing a geometry share one pass over its stored A^T: up
@@ -485,7 +507,7 @@ class Solver {
         as.push_back(as.back() + I.n_adj);
       }
       id[k] = inst_dev(I);
-      gf[k] = GapFinishArgs{ptr<double>(I.red), I.red_stride, n_fwd, I.n_pix};
+      gf[k] = GapFinishArgs{ptr<double>(I.red), I.red_stride, n_fwd_parts, I.n_pix};
       fs[k + 1] = fs[k] + n_fwd;
       ps[k + 1] = ps[k] + I.n_pix;
     }
@@ -516,30 +538,46 @@ class Solver {
       const int blocks = tiled ? csr_geo[c]->n_csr_tiles() : (int)((cd[c].n_rows + 3) / 4);
       cs.push_back(cs.back() + blocks);
     }
-    // forward groups: instances on one geometry, up to four per group, share
-    // each forward block (gather forward only)
+    // forward groups (gather forward only): instances on one geometry, up to
+    // four per group, share each forward block; an instance in quarter-turn
+    // form is a group of its own whose four slots are its turned images
     std::vector<std::vector<int>> fgrp;
     if (!fwd_tiled) {
       for (int k = 0; k < n; ++k) {
         std::vector<int>* into = nullptr;
-        for (auto& gr : fgrp)
-          if (gr.size() < 4 && inst[act[gr[0]]]->g == inst[act[k]]->g) {
-            into = &gr;
-            break;
-          }
+        if (!qt[k])
+          for (auto& gr : fgrp)
+            if (!qt[gr[0]] && gr.size() < 4 && inst[act[gr[0]]]->g == inst[act[k]]->g) {
+              into = &gr;
+              break;
+            }
         if (into) into->push_back(k);
         else fgrp.push_back({k});
       }
     }
     int ni = 1;
-    for (const auto& gr : fgrp) ni = std::max(ni, (int)gr.size());
+    for (const auto& gr : fgrp) ni = std::max(ni, qt[gr[0]] ? 4 : (int)gr.size());
     std::vector<FwdArgs<T>> gdual, ggap;
     std::vector<int> gs(1, 0);
     if (ni > 1) {
       for (const auto& gr : fgrp) {
         for (int i = 0; i < ni; ++i) {
           FwdArgs<T> x = fd[gr[0]], y = fg[gr[0]];
-          if (i < (int)gr.size()) {
+          if (qt[gr[0]]) {
+            // slot i: the image turned by i quarter turns and the bins, data,
+            // steps and gap partials of detectors i n_det/4 ..
+            const Inst<T>& I = *inst[act[gr[0]]];
+            const int64_t P = (int64_t)(I.g->nx + 2) * (I.g->ny + 2);
+            const int64_t ob = (int64_t)i * x.g.n_det * x.g.n_t;
+            x.upad += i * P;
+            x.out += ob;
+            x.f += ob;
+            x.sigma += ob;
+            y.upad += i * P;
+            y.f += ob;
+            y.q += ob;
+            y.red += (int64_t)i * (fs[gr[0] + 1] - fs[gr[0]]);
+          } else if (i < (int)gr.size()) {
             x = fd[gr[i]];
             y = fg[gr[i]];
           } else {
@@ -633,6 +671,13 @@ class Solver {
     }
   }
 
+  // Padded copy of an image into a state buffer (and its turned copies in
+  // quarter-turn form).
+  void pad_slots(const Inst<T>& I, const T* src, T* dst) {
+    if (I.qt) launch_rot_pad<T>(src, false, dst, I.g->nx, 4, s);
+    else launch_pad<T>(src, dst, I.g->nx, I.g->ny, s);
+  }
+
   void init_state() {
     for (int k : act) {
       Inst<T>& I = *inst[k];
@@ -640,8 +685,8 @@ class Solver {
       const int64_t N = g->n_pix(), nb = g->n_bins();
       const size_t P = (size_t)(g->nx + 2) * (g->ny + 2);
       PAT_HIP(hipMemsetAsync(I.u.p, 0, sizeof(T) * N, s));
-      PAT_HIP(hipMemsetAsync(I.ubar_pad.p, 0, sizeof(T) * P, s));
-      PAT_HIP(hipMemsetAsync(I.upad_gap.p, 0, sizeof(T) * P, s));
+      PAT_HIP(hipMemsetAsync(I.ubar_pad.p, 0, I.ubar_pad.bytes, s));
+      PAT_HIP(hipMemsetAsync(I.upad_gap.p, 0, I.upad_gap.bytes, s));
       PAT_HIP(hipMemsetAsync(I.q.p, 0, sizeof(T) * nb, s));
       if (I.r.p) PAT_HIP(hipMemsetAsync(I.r.p, 0, I.r.bytes, s));
       if (I.v.p) PAT_HIP(hipMemsetAsync(I.v.p, 0, I.v.bytes, s));
@@ -650,7 +695,7 @@ class Solver {
       if (I.opts.d_state_in) {
         const T* st = static_cast<const T*>(I.opts.d_state_in);
         PAT_HIP(hipMemcpyAsync(I.u.p, st, sizeof(T) * N, hipMemcpyDeviceToDevice, s));
-        launch_pad<T>(st + N, ptr<T>(I.ubar_pad), g->nx, g->ny, s);
+        pad_slots(I, st + N, ptr<T>(I.ubar_pad));
         int64_t o = 2 * N;
         PAT_HIP(hipMemcpyAsync(I.q.p, st + o, sizeof(T) * nb, hipMemcpyDeviceToDevice, s));
         o += nb;
@@ -673,7 +718,7 @@ class Solver {
       Inst<T>& I = *inst[k];
       if (!I.opts.d_u0 || I.opts.d_state_in) continue;
       PAT_HIP(hipMemcpyAsync(I.u.p, I.opts.d_u0, sizeof(T) * I.g->n_pix(), hipMemcpyDeviceToDevice, s));
-      launch_pad<T>(ptr<T>(I.u), ptr<T>(I.upad_gap), I.g->nx, I.g->ny, s);
+      pad_slots(I, ptr<T>(I.u), ptr<T>(I.upad_gap));
     }
     enqueue_gap(0);
     read_results(1);
@@ -699,7 +744,7 @@ class Solver {
         I.fallback = 1;
         PAT_HIP(hipMemsetAsync(I.u.p, 0, I.u.bytes, s));
       } else {
-        launch_pad<T>(ptr<T>(I.u), ptr<T>(I.ubar_pad), I.g->nx, I.g->ny, s);
+        pad_slots(I, ptr<T>(I.u), ptr<T>(I.ubar_pad));
         if (y0) {
           PAT_HIP(hipMemcpyAsync(I.q.p, y0, sizeof(T) * nb, hipMemcpyDeviceToDevice, s));
           PAT_HIP(hipMemcpyAsync(I.r.p, y0 + nb, sizeof(T) * 2 * N, hipMemcpyDeviceToDevice, s));

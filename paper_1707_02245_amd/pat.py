@@ -109,6 +109,13 @@ class Geometry:
         L.check(L.load().pat_geometry_set_tiled_launch(self._h, waves, row_lanes))
         return self.refresh_info()
 
+    def set_forward_symmetry(self, enable):
+        """Let the forward use the quarter-turn symmetry of the geometry (the
+        bins of the first quarter of the detectors on the image and its three
+        turned copies) or evaluate every detector directly."""
+        L.check(L.load().pat_geometry_set_forward_symmetry(self._h, 1 if enable else 0))
+        return self.refresh_info()
+
     def set_symmetry(self, enable):
         """Let the stored A^T use the quarter-turn symmetry of the geometry
         (rows of a quarter of the detectors only) or store every detector."""
