@@ -113,6 +113,8 @@ typedef struct {
   int64_t fwd_pairs;      /* (bin, sample range) pairs of path 2 */
   int32_t fwd_sym;        /* 4: the forward runs in quarter-turn form (see
                            * pat_geometry_set_forward_symmetry); 1: not */
+  int64_t fwd_entries;    /* non-zeros of the stored A of forward path 3
+                           * (-1: not built, 0: not available) */
 } pat_geometry_info;
 
 /* Build the geometry tables on the device (FP64 host computation, rounded to
@@ -150,8 +152,18 @@ pat_status pat_geometry_set_adjoint(pat_geometry g, int32_t mode, void* stream);
  * workgroup sums, for a chunk of the tile's (bin, sample range) pairs, the
  * samples whose cell lies in the tile, and a second pass adds each bin's
  * partial sums in a fixed order (same operator, different summation order).
- * Selecting path 2 builds its tables (synchronous on `stream`). Invalid
- * path: PAT_ERR_INVALID_ARG. */
+ * 3 (quarter-turn symmetric geometries with the symmetric A^T storage): the
+ * stored A of the first n_det/4 detectors, the stored quarter of A^T read the
+ * other way (Sec. 3.3.1: the matrix computed once), grouped by 16 x 16 pixel
+ * tiles; a workgroup stages its tile of the image turned by 0..3 quarter
+ * turns in LDS and streams the tile's entries (one-byte pixel, weight) once
+ * for the four quarters of the ring, and a second pass adds each bin's
+ * per-tile partials in tile order. It is the exact transpose of the stored
+ * A^T (same entries). About (1 + element size) bytes per stored non-zero.
+ * Selecting path 2 or 3 builds its tables (synchronous on `stream`); path 3
+ * on a geometry that does not allow it: PAT_ERR_UNSUPPORTED (also when a
+ * tile touches more than 12288 bins); pat_geometry_set_symmetry(0) returns
+ * the forward to path 0. Invalid path: PAT_ERR_INVALID_ARG. */
 pat_status pat_geometry_set_forward_path(pat_geometry g, int32_t path, void* stream);
 
 /* Workgroup shape of adjoint mode 2 (autotuner hook): waves per workgroup

@@ -48,6 +48,7 @@ class GeometryInfo(C.Structure):
         ("csr_waves", C.c_int32), ("csr_lanes", C.c_int32), ("fwd_path", C.c_int32),
         ("fwd_pairs", C.c_int64),
         ("fwd_sym", C.c_int32),
+        ("fwd_entries", C.c_int64),
     ]
 
 

@@ -2,7 +2,8 @@
 //
 // Candidates: forward lanes per bin (16, 32, 64), block order (radius- or
 // detector-major) and, on quarter-turn symmetric geometries, the direct or
-// the quarter-turn form, and the adjoint path (stored
+// the quarter-turn form, the LDS-tiled gather, the stored A by pixel tiles
+// (symmetric geometries), and the adjoint path (stored
 // CSR, plain or with LDS-staged input windows in workgroups of 4, 8 or 16 waves
 // and 16 or 64 lanes per row,
 // or the matrix-free tile scatter with 16/32/64-pixel tiles and a few
@@ -95,11 +96,14 @@ void tune(pat_geometry_s* g, int reps, hipStream_t s, pat_autotune_result* res) 
   int best_l = g->lanes_log2, best_o = g->fwd_path;
   bool best_sym = g->fwd_sym;
   g->ensure_fwd_tiles(s);
-  for (int o = 0; o <= 2; ++o)
+  // the stored A (path 3) where the geometry allows it
+  if (g->sym_rot == 4 && g->sym_enabled) g->ensure_fmat(s);
+  const int max_path = g->fm_entries > 0 ? 3 : 2;
+  for (int o = 0; o <= max_path; ++o)
     for (int l = 4; l <= 6; ++l)
       for (int sym = 0; sym <= 1; ++sym) {
-        if (o == 2 && l != 4) continue;  // the tiled path has one shape
-        if (sym && (o == 2 || g->sym_rot != 4)) continue;  // no quarter-turn form
+        if (o >= 2 && l != 4) continue;  // the tiled and stored paths have one shape
+        if (sym && (o >= 2 || g->sym_rot != 4)) continue;  // no quarter-turn form
         g->lanes_log2 = l;
         g->fwd_path = o;
         g->fwd_sym = sym != 0;
@@ -178,11 +182,15 @@ extern "C" pat_status pat_geometry_autotune(pat_geometry g, const char* cache_pa
       int lanes = 0, mode = -1, tile = 0, group = 0, wg = -1, rl = -1, fo = -1, fsym = -1;
       double tf = 0, ta = 0;
       if (in >> lanes >> fo >> fsym >> mode >> tile >> group >> wg >> rl >> tf >> ta && lanes >= 4 && lanes <= 6 &&
-          (fo >= 0 && fo <= 2) && (fsym == 0 || fsym == 1) &&
+          (fo >= 0 && fo <= 3) && (fsym == 0 || fsym == 1) &&
           (mode >= 0 && mode <= 2) && (tile == 16 || tile == 32 || tile == 64) && group >= 1 &&
           group <= g->n_det && (wg == 4 || wg == 8 || wg == 16) && (rl == 16 || rl == 64)) {
         g->lanes_log2 = lanes;
         if (fo == 2) g->ensure_fwd_tiles(s);
+        if (fo == 3) {
+          g->ensure_fmat(s);
+          if (g->fm_entries <= 0) fo = 0;  // not buildable here: the gather
+        }
         g->fwd_path = fo;
         g->fwd_sym = fsym != 0;
         g->tile = tile;

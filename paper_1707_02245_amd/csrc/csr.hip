@@ -179,6 +179,13 @@ __global__ __launch_bounds__(256) void csr_lcol_kernel(const int64_t* __restrict
   }
 }
 
+void launch_csr_windows(const pat_geometry_s* geo, int side, int tiles_x, int64_t n_tiles, int4* win,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(csr_window_kernel, dim3((unsigned)n_tiles), dim3(256), 0, s, ptr<int64_t>(geo->csr_ptr),
+                     ptr<int>(geo->csr_col), geo->nx, geo->ny, side, tiles_x, geo->csr_det(), geo->n_t, win);
+  PAT_HIP(hipGetLastError());
+}
+
 void build_csr_tiles(pat_geometry_s* geo, size_t esz, hipStream_t s) {
   geo->csr_side = 0;
   geo->csr_tiles_x = geo->csr_tiles_y = geo->csr_win_max = 0;

@@ -444,6 +444,7 @@ extern "C" pat_status pat_geometry_get_info(pat_geometry g, pat_geometry_info* o
     out->fwd_path = g->fwd_path;
     out->fwd_pairs = g->fwd_n_pairs;
     out->fwd_sym = g->fwd_qt() ? 4 : 1;
+    out->fwd_entries = g->fm_entries;
     return PAT_OK;
   });
 }
@@ -470,8 +471,19 @@ extern "C" pat_status pat_geometry_set_adjoint(pat_geometry g, int32_t mode, voi
 extern "C" pat_status pat_geometry_set_forward_path(pat_geometry g, int32_t path, void* stream) {
   return guarded([&]() -> pat_status {
     PAT_CHECK_ARG(g != nullptr, "geometry is NULL");
-    PAT_CHECK_ARG(path >= 0 && path <= 2, "forward path must be 0, 1 or 2");
+    PAT_CHECK_ARG(path >= 0 && path <= 3, "forward path must be 0, 1, 2 or 3");
     if (path == 2) g->ensure_fwd_tiles(static_cast<hipStream_t>(stream));
+    if (path == 3) {
+      if (g->sym_rot != 4 || !g->sym_enabled) {
+        pat::set_error("forward path 3 needs a quarter-turn symmetric geometry with the symmetric A^T storage");
+        return PAT_ERR_UNSUPPORTED;
+      }
+      g->ensure_fmat(static_cast<hipStream_t>(stream));
+      if (g->fm_entries <= 0) {
+        pat::set_error("forward path 3: a pixel tile touches more bins than its build supports");
+        return PAT_ERR_UNSUPPORTED;
+      }
+    }
     g->fwd_path = path;
     return PAT_OK;
   });
@@ -509,6 +521,8 @@ extern "C" pat_status pat_geometry_set_symmetry(pat_geometry g, int32_t enable, 
       g->drop_csr();
       g->ensure_csr(s);
     }
+    // the stored A (path 3) is the quarter-turn storage read the other way
+    if (g->fwd_path == 3 && g->csr_rot != 4) g->fwd_path = 0;
     return PAT_OK;
   });
 }

@@ -144,6 +144,14 @@ __device__ __forceinline__ T row16_sum(T x) {
   return x;
 }
 
+// Sum over the four lanes of a quad (every lane gets it).
+template <class T>
+__device__ __forceinline__ T quad_sum(T x) {
+  x += dpp_move<0x4E>(x);  // quad_perm [2,3,0,1]
+  x += dpp_move<0xB1>(x);  // quad_perm [1,0,3,2]
+  return x;
+}
+
 // Deterministic block reduction into one value per block (blockDim.x = NT).
 template <int NT, class T>
 __device__ __forceinline__ T block_sum(T v, T* lds) {
@@ -211,6 +219,16 @@ struct GeomDev {
   int tiles_x, tiles_y;
   int det_group;         // adjoint: detectors per workgroup
   int n_groups;          // ceil(n_det / det_group)
+  // path 3, the stored A of the first n_det/4 detectors by 16 x 16 pixel
+  // tiles (quarter-turn symmetric geometries): entries grouped by tile, then
+  // by bin (segments), then by pixel; partial sums numbered bin-major
+  const uint8_t* fm_off;   // [entries] pixel of the entry within its tile
+  const void* fm_w;        // [entries] weight, element type
+  const int4* fm_seg;      // [segments, tile-major] {first entry, entries, 0, 0}
+  const int4* fm_chunk;    // [workgroups] {tile, first segment, end segment, 0}
+  const int* fm_binseg;    // [n_det/4 n_t + 1] each bin's range in fm_segidx
+  const int* fm_segidx;    // [segments] each bin's segments, in tile order
+  int fm_nseg, fm_tiles_x, fm_nchunk;
 };
 
 // (cos, sin) of an arc sample from the FP64 table (every element type: an FP32

@@ -17,7 +17,7 @@ struct pat_geometry_s {
   pat::DevBuf d_det, d_rad, d_moff, d_cs, d_win;
   // launch parameters
   int lanes_log2 = 6, tile = 32, det_group = 16;
-  int fwd_path = 0;  // forward path: 0/1 gather (see fwd_grid), 2 LDS tiles
+  int fwd_path = 0;  // forward path: 0/1 gather (see fwd_grid), 2 LDS tiles, 3 stored A
   // LDS-tiled forward (path 2): pairs {bin, m0, m1, partial slot} in tile
   // order, workgroup descriptors {cell x0, cell y0, first pair, end pair},
   // per-bin offsets of the partial sums (bin-major)
@@ -37,7 +37,7 @@ struct pat_geometry_s {
   // the forward in quarter-turn form on symmetric geometries (gather paths;
   // off by default, the autotuner times it)
   bool fwd_sym = false;
-  bool fwd_qt() const { return fwd_sym && sym_rot == 4 && fwd_path != 2; }
+  bool fwd_qt() const { return fwd_sym && sym_rot == 4 && fwd_path < 2; }
   // pixel tiles of the stored A^T (side 0: windows too large for LDS);
   // csr_win_max is per quarter-turn slot
   int csr_side = 0, csr_tiles_x = 0, csr_tiles_y = 0, csr_win_max = 0;
@@ -49,6 +49,13 @@ struct pat_geometry_s {
   pat::DevBuf scratch_pad, scratch_part;
   // radii by decreasing samples in their clip windows (over all detectors)
   pat::DevBuf d_kord;
+  // forward path 3: the stored A of the first n_det/4 detectors by pixel
+  // tiles (GeomDev fm_*); fm_entries -1: not built, 0: not available
+  pat::DevBuf fm_off, fm_w, fm_seg, fm_chunk, fm_binseg, fm_segidx;
+  int64_t fm_entries = -1;
+  int fm_nseg = 0, fm_nchunk = 0, fm_tiles_x = 0;
+  void ensure_fmat(hipStream_t s);
+  void drop_fmat();
 
   void build_host();
   void upload(hipStream_t stream);
@@ -128,6 +135,10 @@ struct Launch {
   // fwdg_start; fwd_ni == 1 when no two instances share a geometry
   DevBuf fwdg, fwdg_gap, fwdg_start;
   int fwd_ni = 1, fwd_ni_blocks = 0, fwd_ni_groups = 0;
+  // instances whose forward is the stored A (path 3): their slot-form args
+  // (dual / gap), workgroup offsets of the tile pass and of the per-bin pass
+  DevBuf fm, fm_gap, fm_start, fmr_start;
+  int fm_n = 0, fm_total = 0, fmr_total = 0;
   int lanes_log2 = 6;   // shared by every instance of one launch
   int max_tile = 32;    // shared by every instance of one launch
 };
@@ -171,10 +182,30 @@ size_t adjoint_scratch_bytes(const pat_geometry_s* g);
 template <class T>
 void apply_adjoint_scratch(pat_geometry_s* g, const T* f, T* u, T* scratch, hipStream_t s);
 
+// ---- stored A by pixel tiles, forward path 3 (fmat.hip)
+constexpr int kFmSide = 16;             // tile side (a pixel in one byte)
+constexpr int kFmChunkEntries = 4096;   // entries per workgroup (whole segments)
+template <class T>
+void build_fmat(pat_geometry_s* geo, hipStream_t s);
+// workgroups of the per-bin pass over n_det (a quarter) x n_t bins
+inline int fmat_reduce_blocks(int n_det, int n_t) { return (int)(((int64_t)n_det * n_t + 15) / 16); }
+// A u of one instance in quarter-turn slot form (a.g.n_det the quarter,
+// a.part 4 partials per segment, slot fields set); mode PLAIN
+template <class T>
+void launch_forward_fmat(int mode, const FwdArgs<T>& a, hipStream_t s);
+// the path-3 instances of a batch (L.fm*), mode DUAL (with the regulariser's
+// dual step of every instance in the same launch when fused) or GAP
+template <class T>
+void launch_fmat_batched(int mode, bool fused_reg, const Launch<T>& L, hipStream_t s);
+
 // ---- stored A^T (csr.hip)
 template <class T>
 void build_csr_adjoint(pat_geometry_s* geo, hipStream_t s);
 void build_csr_tiles(pat_geometry_s* geo, size_t esz, hipStream_t s);
+// per pixel tile (side x side) and stored detector: {first radius, radii, 0, 0}
+// of the tile's non-zeros in the stored A^T
+void launch_csr_windows(const pat_geometry_s* geo, int side, int tiles_x, int64_t n_tiles, int4* win,
+                        hipStream_t s);
 template <class T>
 void launch_csr_spmv(const CsrArgs<T>& a, hipStream_t s);
 template <class T>

@@ -21,15 +21,7 @@
 
 #include "pat_internal.hpp"
 #include "reg_dual.hpp"
-
-#ifndef PAT_FWD_LPT
-#define PAT_FWD_LPT 1
-#endif
-#ifdef PAT_FWD_WPE
-#define PAT_FWD_ATTR __attribute__((amdgpu_waves_per_eu(PAT_FWD_WPE)))
-#else
-#define PAT_FWD_ATTR
-#endif
+#include "fwd_epilogue.hpp"
 
 namespace pat {
 
@@ -120,42 +112,6 @@ void launch_rot_pad(const T* src, bool src_padded, T* dst, int n, int slots, hip
 
 // ------------------------------------------------------------------ forward
 
-// The value val = (A x)_b of bin b, computed by this thread (writer), goes
-// to its destination: the data (PLAIN), the dual data step of PDHGM (DUAL),
-// the reciprocal row sum (ROWSUM) or the block's gap sums (GAP: every thread
-// of the block takes part in the reduction).
-template <class T, int MODE>
-__device__ __forceinline__ void fwd_epilogue(const FwdArgs<T>& a, int blk, bool writer, int64_t b, T val) {
-  if (MODE == FWD_GAP) {
-    __shared__ double lds[8];
-    double d_data = 0.0, d_fs = 0.0;
-    if (writer) {
-      const double res = (double)val - (double)a.f[b];
-      const double qb = (double)a.q[b];
-      d_data = 0.5 * res * res;
-      d_fs = 0.5 * qb * qb + qb * (double)a.f[b];
-    }
-    const double s0 = block_sum<256>(d_data, lds);
-    const double s1 = block_sum<256>(d_fs, lds);
-    if (threadIdx.x == 0) {
-      a.red[GAP_DATA * (int64_t)a.red_stride + blk] = s0;
-      a.red[GAP_FSTAR * (int64_t)a.red_stride + blk] = s1;
-    }
-    return;
-  }
-  if (!writer) return;
-  if (MODE == FWD_PLAIN) {
-    a.out[b] = val;
-  } else if (MODE == FWD_DUAL) {
-    // q <- prox_{sigma F1*}(q + sigma A ubar) = (q + sigma (A ubar - f)) / (1 + sigma)
-    const T sg = a.mult ? a.sigma[b] * (T)a.mult[0] : a.sigma[b];
-    a.out[b] = (a.out[b] + sg * (val - a.f[b])) / (T(1) + sg);
-  } else if (MODE == FWD_ROWSUM) {
-    // A >= 0, so the absolute row sum is A 1; empty rows get sigma = 1
-    a.out[b] = val > T(0) ? T(1) / val : T(1);
-  }
-}
-
 // With FUSED the launch also carries the regulariser's dual step, which reads
 // the same extrapolated image as the forward's dual data step and writes
 // disjoint state: blocks from n_fwd on run it (so filling the forward's last
@@ -171,7 +127,7 @@ __device__ __forceinline__ void fwd_epilogue(const FwdArgs<T>& a, int blk, bool 
 // arrays); with QT (NI = 4) a0 alone describes the four slots (its slot
 // fields), the form of the stand-alone forward.
 template <class T, int MODE, int LANES, bool FUSED = false, int NI = 1, bool QT = false>
-__global__ __launch_bounds__(256) PAT_FWD_ATTR void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T>* __restrict__ arr,
+__global__ __launch_bounds__(256) void fwd_kernel(FwdArgs<T> a0, const FwdArgs<T>* __restrict__ arr,
                                                   const int* __restrict__ starts, int n_inst, int n_fwd,
                                                   const InstDev<T>* __restrict__ rarr,
                                                   const int* __restrict__ rstarts, int rn) {
@@ -536,7 +492,17 @@ static void fwd_ni_dispatch(int lanes_log2, const Launch<T>& L, hipStream_t s) {
 }
 
 template <class T>
+static void launch_gather_batched(int mode, const Launch<T>& L, int lanes_log2, hipStream_t s);
+
+template <class T>
 void launch_forward_reg_batched(const Launch<T>& L, int lanes_log2, hipStream_t s) {
+  if (L.fm_n > 0) {
+    // the gather instances without the regulariser, which runs in the stored
+    // forward's tile pass
+    launch_gather_batched<T>(FWD_DUAL, L, lanes_log2, s);
+    launch_fmat_batched<T>(FWD_DUAL, true, L, s);
+    return;
+  }
   if (!L.fwd_tiled && L.fwd_ni > 1 && L.fwd_ni_blocks > 0 && L.pix_total > 0) {
     fwd_ni_dispatch<T, FWD_DUAL, true>(lanes_log2, L, s);
     return;
@@ -568,6 +534,12 @@ void launch_forward_reg_batched(const Launch<T>& L, int lanes_log2, hipStream_t 
 
 template <class T>
 void launch_forward_batched(int mode, const Launch<T>& L, int lanes_log2, hipStream_t s) {
+  launch_gather_batched<T>(mode, L, lanes_log2, s);
+  if (L.fm_n > 0) launch_fmat_batched<T>(mode, false, L, s);
+}
+
+template <class T>
+static void launch_gather_batched(int mode, const Launch<T>& L, int lanes_log2, hipStream_t s) {
   if (!L.fwd_tiled && L.fwd_ni > 1 && L.fwd_ni_blocks > 0 && (mode == FWD_DUAL || mode == FWD_GAP)) {
     if (mode == FWD_DUAL) fwd_ni_dispatch<T, FWD_DUAL, false>(lanes_log2, L, s);
     else fwd_ni_dispatch<T, FWD_GAP, false>(lanes_log2, L, s);
@@ -766,11 +738,7 @@ pat::GeomDev pat_geometry_s::dev() const {
   g.moff = pat::ptr<int2>(d_moff);
   g.cs = d_cs.p;
   g.win = pat::ptr<int4>(d_win);
-#if PAT_FWD_LPT
   g.kord = pat::ptr<int>(d_kord);
-#else
-  g.kord = nullptr;
-#endif
   g.kscale = h / (desc.c * desc.dt);
   g.koff = desc.t0 / desc.dt;
   g.lanes_log2 = lanes_log2;
@@ -784,7 +752,35 @@ pat::GeomDev pat_geometry_s::dev() const {
   g.tiles_y = (ny + g.tile - 1) / g.tile;
   g.det_group = det_group;
   g.n_groups = n_groups();
+  const bool fm = fm_entries > 0;
+  g.fm_off = fm ? pat::ptr<uint8_t>(fm_off) : nullptr;
+  g.fm_w = fm ? fm_w.p : nullptr;
+  g.fm_seg = fm ? pat::ptr<int4>(fm_seg) : nullptr;
+  g.fm_chunk = fm ? pat::ptr<int4>(fm_chunk) : nullptr;
+  g.fm_binseg = fm ? pat::ptr<int>(fm_binseg) : nullptr;
+  g.fm_segidx = fm ? pat::ptr<int>(fm_segidx) : nullptr;
+  g.fm_nseg = fm ? fm_nseg : 0;
+  g.fm_tiles_x = fm_tiles_x;
+  g.fm_nchunk = fm ? fm_nchunk : 0;
   return g;
+}
+
+void pat_geometry_s::ensure_fmat(hipStream_t s) {
+  if (fm_entries >= 0) return;
+  ensure_csr(s);
+  if (dtype == PAT_F64) pat::build_fmat<double>(this, s);
+  else pat::build_fmat<float>(this, s);
+}
+
+void pat_geometry_s::drop_fmat() {
+  fm_off.release();
+  fm_w.release();
+  fm_seg.release();
+  fm_chunk.release();
+  fm_binseg.release();
+  fm_segidx.release();
+  fm_entries = -1;
+  fm_nseg = fm_nchunk = fm_tiles_x = 0;
 }
 
 void pat_geometry_s::ensure_csr(hipStream_t s) {
@@ -797,6 +793,7 @@ void pat_geometry_s::ensure_csr(hipStream_t s) {
 }
 
 void pat_geometry_s::drop_csr() {
+  drop_fmat();  // built from the CSR
   csr_ptr.release();
   csr_col.release();
   csr_val.release();
@@ -828,8 +825,31 @@ void forward_qt_impl(pat_geometry g, const T* src, bool src_padded, T* f, hipStr
   pat::launch_forward_qt<T>(pat::FWD_PLAIN, a, g->lanes_log2, s);
 }
 
+// The stored A by pixel tiles (path 3) from a padded image: four partials per
+// segment in the geometry's scratch, then the per-bin pass.
+template <class T>
+void forward_fmat_impl(pat_geometry g, const T* upad, T* f, hipStream_t s) {
+  PAT_CHECK_ARG(g->fm_entries > 0, "forward path 3 without its stored matrix");
+  g->scratch_fpart.ensure(sizeof(T) * 4 * (size_t)std::max(g->fm_nseg, 1));
+  pat::FwdArgs<T> a{};
+  a.g = g->dev();
+  a.g.n_det = g->n_det / 4;
+  a.upad = upad;
+  a.out = f;
+  a.part = pat::ptr<T>(g->scratch_fpart);
+  a.slot_bins = (int64_t)a.g.n_det * g->n_t;
+  pat::launch_forward_fmat<T>(pat::FWD_PLAIN, a, s);
+}
+
 template <class T>
 void forward_impl(pat_geometry g, const void* d_u, void* d_f, hipStream_t s) {
+  if (g->fwd_path == 3) {
+    g->scratch_pad.ensure(sizeof(T) * (size_t)(g->nx + 2) * (g->ny + 2));
+    T* upad = pat::ptr<T>(g->scratch_pad);
+    pat::launch_pad<T>(static_cast<const T*>(d_u), upad, g->nx, g->ny, s);
+    forward_fmat_impl<T>(g, upad, static_cast<T*>(d_f), s);
+    return;
+  }
   if (g->fwd_qt()) {
     forward_qt_impl<T>(g, static_cast<const T*>(d_u), false, static_cast<T*>(d_f), s);
     return;
@@ -863,6 +883,10 @@ namespace {
 
 template <class T>
 void forward_padded_impl(pat_geometry g, const void* d_upad, void* d_f, hipStream_t s) {
+  if (g->fwd_path == 3) {
+    forward_fmat_impl<T>(g, static_cast<const T*>(d_upad), static_cast<T*>(d_f), s);
+    return;
+  }
   if (g->fwd_qt()) {
     forward_qt_impl<T>(g, static_cast<const T*>(d_upad), true, static_cast<T*>(d_f), s);
     return;

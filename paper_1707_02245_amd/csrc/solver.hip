@@ -194,6 +194,9 @@ struct Inst {
   // forward in quarter-turn form: ubar_pad and upad_gap hold four slots (the
   // image and its copies turned by 1..3 quarter turns)
   bool qt = false;
+  // forward by the stored A of the first n_det/4 detectors (path 3): fpart
+  // holds its four partials per segment
+  bool fm = false;
   int iters = 0;
   bool active = true, converged = false;
   int fallback = 0;
@@ -350,6 +353,12 @@ class Solver {
       I.n_fwd = std::max({I.n_fwd, 4 * fwd_grid(g->n_det / 4, g->n_t, lanes_log2, 0),
                           4 * fwd_grid(g->n_det / 4, g->n_t, lanes_log2, 1)});
     if (g->fwd_path == 2) I.fpart.alloc(sizeof(T) * (size_t)std::max<int64_t>(g->fwd_n_pairs, 1));
+    I.fm = g->fwd_path == 3 && g->fm_entries > 0;
+    if (I.fm) {
+      I.fpart.alloc(sizeof(T) * 4 * (size_t)std::max(g->fm_nseg, 1));
+      // the per-bin pass writes gap partials per turn and block
+      I.n_fwd = std::max(I.n_fwd, 4 * fmat_reduce_blocks(g->n_det / 4, g->n_t));
+    }
     I.n_pix = pix_blocks(N);
     I.n_adj = I.csr ? 0 : gd.tiles_x * gd.tiles_y * gd.n_groups;
     I.n_csr = I.csr ? (int)((N + 3) / 4) : 0;
@@ -411,9 +420,15 @@ class Solver {
     // gather kernel (radius-major for those that chose tiles)
     bool fwd_tiled = n > 0;
     for (int k = 0; k < n; ++k) fwd_tiled = fwd_tiled && inst[act[k]]->g->fwd_path == 2 && inst[act[k]]->fpart.p;
-    // instances in quarter-turn form (gather forward only)
-    std::vector<bool> qt(n, false);
-    for (int k = 0; k < n; ++k) qt[k] = !fwd_tiled && inst[act[k]]->qt;
+    // instances in quarter-turn form (gather forward only) and instances
+    // whose forward is the stored A (path 3, outside the gather launches)
+    std::vector<bool> qt(n, false), fm(n, false);
+    for (int k = 0; k < n; ++k) {
+      qt[k] = !fwd_tiled && inst[act[k]]->qt;
+      fm[k] = inst[act[k]]->fm;
+    }
+    std::vector<FwdArgs<T>> fmd, fmg;
+    std::vector<int> fms(1, 0), fmrs(1, 0);
     std::vector<int> ts(n + 1, 0);
     std::vector<FwdArgs<T>> fd(n), fg(n);
     std::vector<AdjArgs<T>> ad;
@@ -441,7 +456,7 @@ class Solver {
       fg[k].q = ptr<T>(I.q);
       fg[k].red = ptr<double>(I.red);
       fg[k].red_stride = I.red_stride;
-      const int path = fwd_tiled ? 2 : (I.g->fwd_path == 2 ? 0 : I.g->fwd_path);
+      const int path = fwd_tiled ? 2 : (I.g->fwd_path >= 2 ? 0 : I.g->fwd_path);
       fd[k].g.fwd_path = fg[k].g.fwd_path = path;
       fd[k].part = fg[k].part = ptr<T>(I.fpart);
       int n_fwd = fwd_grid(I.g->n_det, I.g->n_t, lanes_log2, path);
@@ -453,6 +468,21 @@ class Solver {
         fd[k].g.n_det = fg[k].g.n_det = q;
         n_fwd = fwd_grid(q, I.g->n_t, lanes_log2, path);
         n_fwd_parts = 4 * n_fwd;
+      } else if (fm[k]) {
+        // no gather blocks: the stored A's two passes in slot form
+        const int q = I.g->n_det / 4;
+        const int nrb = fmat_reduce_blocks(q, I.g->n_t);
+        FwdArgs<T> x = fd[k], y = fg[k];
+        x.g = y.g = I.g->dev();
+        x.g.n_det = y.g.n_det = q;
+        x.slot_bins = y.slot_bins = (int64_t)q * I.g->n_t;
+        y.slot_red = nrb;
+        fmd.push_back(x);
+        fmg.push_back(y);
+        fms.push_back(fms.back() + I.g->fm_nchunk);
+        fmrs.push_back(fmrs.back() + nrb);
+        n_fwd = 0;
+        n_fwd_parts = 4 * nrb;
       }
       ts[k + 1] = ts[k] + (fwd_tiled ? I.g->fwd_n_blocks : 0);
       if (I.csr) {
@@ -544,6 +574,7 @@ class Solver {
     std::vector<std::vector<int>> fgrp;
     if (!fwd_tiled) {
       for (int k = 0; k < n; ++k) {
+        if (fm[k]) continue;
         std::vector<int>* into = nullptr;
         if (!qt[k])
           for (auto& gr : fgrp)
@@ -609,7 +640,16 @@ class Solver {
     up(L.adj_start, as.data(), sizeof(int) * as.size());
     up(L.csr_start, cs.data(), sizeof(int) * cs.size());
     up(L.pix_start, ps.data(), sizeof(int) * (n + 1));
+    if (!fmd.empty()) {
+      up(L.fm, fmd.data(), sizeof(FwdArgs<T>) * fmd.size());
+      up(L.fm_gap, fmg.data(), sizeof(FwdArgs<T>) * fmg.size());
+      up(L.fm_start, fms.data(), sizeof(int) * fms.size());
+      up(L.fmr_start, fmrs.data(), sizeof(int) * fmrs.size());
+    }
     PAT_HIP(hipStreamSynchronize(s));  // host vectors go out of scope
+    L.fm_n = (int)fmd.size();
+    L.fm_total = fms.back();
+    L.fmr_total = fmrs.back();
     L.n = n;
     L.fwd_total = fs[n];
     L.fwd_tiled = fwd_tiled;
@@ -638,9 +678,11 @@ class Solver {
     // the gap forward uses the second FwdArgs table (input u+, gap epilogue)
     std::swap(L.fwd, L.fwd_gap);
     std::swap(L.fwdg, L.fwdg_gap);
+    std::swap(L.fm, L.fm_gap);
     launch_forward_batched<T>(FWD_GAP, L, lanes_log2, s);
     std::swap(L.fwd, L.fwd_gap);
     std::swap(L.fwdg, L.fwdg_gap);
+    std::swap(L.fm, L.fm_gap);
     launch_gap_reg<T>(L, s);
     launch_gap_finish(ptr<GapFinishArgs>(L.gapfin), L.n,
                       ptr<double>(results) + (size_t)c * L.n * GAP_NSLOTS, s);

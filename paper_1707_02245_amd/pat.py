@@ -99,7 +99,8 @@ class Geometry:
         return self.refresh_info()
 
     def set_forward_path(self, path):
-        """Forward path: 0/1 gather (radius-/detector-major blocks), 2 LDS tiles."""
+        """Forward path: 0/1 gather (radius-/detector-major blocks), 2 LDS tiles,
+        3 the stored A by pixel tiles (quarter-turn symmetric geometries)."""
         L.check(L.load().pat_geometry_set_forward_path(self._h, path, _stream()))
         return self.refresh_info()
 
