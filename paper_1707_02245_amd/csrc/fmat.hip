@@ -120,7 +120,8 @@ __global__ __launch_bounds__(256) void fmat_kernel(FwdArgs<T> a0, const FwdArgs<
   constexpr int S2 = kFmSide * kFmSide;
   // pixel r's four turns at img[4 r .. 4 r + 3]: slot t holds the image
   // turned by t quarter turns, u_t(p) = u(R^t p)
-  __shared__ __align__(16) T img[4 * S2];
+  constexpr int kPix = 4;
+  __shared__ __align__(16) T img[kPix * S2];
   const int4 ch = g.fm_chunk[blk];
   const int x0 = (ch.x % g.fm_tiles_x) * kFmSide, y0 = (ch.x / g.fm_tiles_x) * kFmSide;
   const int n = g.nx, P = g.pitch;
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(256) void fmat_kernel(FwdArgs<T> a0, const FwdArgs<
       quarter_turn_xy(i, j, n, t, x, y);
       v = up[(int64_t)(y + 1) * P + (x + 1)];
     }
-    img[4 * r + t] = v;
+    img[kPix * r + t] = v;
   }
   __syncthreads();
   const int quad = threadIdx.x / kLps, ql = threadIdx.x % kLps;
@@ -172,7 +173,7 @@ __global__ __launch_bounds__(256) void fmat_kernel(FwdArgs<T> a0, const FwdArgs<
       T wa[4], wb[4];
       load(e, oa, wa);
       load(two ? e + 4 * kLps : e, ob, wb);
-      auto pixel = [&](int o) -> T4 { return *reinterpret_cast<const T4*>(img + 4 * o); };
+      auto pixel = [&](int o) -> T4 { return *reinterpret_cast<const T4*>(img + kPix * o); };
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const T4 px = pixel((oa >> (8 * k)) & 0xFF);
