@@ -38,21 +38,25 @@ HBM_PEAK_GBS = 8000.0
 # size (FETCH x 2, WRITE x 1); profiles/*_hbm_traffic.md. An entry is reported only
 # while the kernel's sources are the ones measured.
 _SRC_FWD = {"paper_1707_02245_amd/csrc/projector.hip":
-            "47c73fc029740225c649384ae3401d1194e7d512a73245eaed5e67d0588e8b8f",
+            "dac4e7ecd78374581f9fb3bdaa72fe62eb5e9dd1e8eb9456f69948380b789b12",
             "paper_1707_02245_amd/csrc/pat_common.hpp":
-            "f400c8fb3593a8183f0effb99481bb3ae19d2a625a5716d4bd5c94bd98332ee0"}
+            "cfcbba40b7f22a819d8564e336b95b702bef06d20d034345790c0ca8412ea1d2"}
 _SRC_ADJ = {"paper_1707_02245_amd/csrc/csr.hip":
-            "b470afe964977095acf55b26eb15ff530103019d8f62d7157a19af51c17d66db",
+            "3040aa591c28c22f8e93010f102c44657b3b859840285bf95ee966a505330612",
             "paper_1707_02245_amd/csrc/pat_common.hpp":
-            "f400c8fb3593a8183f0effb99481bb3ae19d2a625a5716d4bd5c94bd98332ee0"}
+            "cfcbba40b7f22a819d8564e336b95b702bef06d20d034345790c0ca8412ea1d2"}
 MEASURED_TRAFFIC = [
     # profiles/fwd_gather_tgv256_f64_hbm_traffic.md
-    {"kernel": "fwd_kernel<double, 0, 16, false, 1>", "bytes_per_launch": 34.88e6, "sources": _SRC_FWD},
-    {"kernel": "fwd_kernel<double, 0, 32, false, 1>", "bytes_per_launch": 28.53e6, "sources": _SRC_FWD},
-    {"kernel": "fwd_kernel<double, 0, 64, false, 1>", "bytes_per_launch": 42.55e6, "sources": _SRC_FWD},
+    {"kernel": "fwd_kernel<double, 0, 16, false, 1, false>", "bytes_per_launch": 34.45e6, "sources": _SRC_FWD},
+    {"kernel": "fwd_kernel<double, 0, 32, false, 1, false>", "bytes_per_launch": 39.38e6, "sources": _SRC_FWD},
+    {"kernel": "fwd_kernel<double, 0, 64, false, 1, false>", "bytes_per_launch": 42.56e6, "sources": _SRC_FWD},
     # profiles/csr_tiled_tgv256_f64_hbm_traffic.md
-    {"kernel": "csr_tiled_kernel<double, false, 4, 256, 16>", "bytes_per_launch": 210.13e6, "sources": _SRC_ADJ},
-    {"kernel": "csr_tiled_kernel<double, false, 4, 512, 16>", "bytes_per_launch": 227.47e6, "sources": _SRC_ADJ},
+    {"kernel": "csr_tiled_kernel<double, false, 4, 256, 16>", "bytes_per_launch": 187.77e6, "sources": _SRC_ADJ},
+    {"kernel": "csr_tiled_kernel<double, false, 4, 512, 16>", "bytes_per_launch": 189.63e6, "sources": _SRC_ADJ},
+    {"kernel": "csr_tiled_kernel<double, false, 4, 1024, 16>", "bytes_per_launch": 193.50e6, "sources": _SRC_ADJ},
+    {"kernel": "csr_tiled_kernel<double, false, 4, 256, 64>", "bytes_per_launch": 181.09e6, "sources": _SRC_ADJ},
+    {"kernel": "csr_tiled_kernel<double, false, 4, 512, 64>", "bytes_per_launch": 180.97e6, "sources": _SRC_ADJ},
+    {"kernel": "csr_tiled_kernel<double, false, 4, 1024, 64>", "bytes_per_launch": 182.29e6, "sources": _SRC_ADJ},
 ]
 
 
@@ -533,10 +537,26 @@ def main():
         apply["adjoint_other_workloads"] = extra_adjoints(pat, torch, tdt, esz, args.apply_reps)
     log(f"apply: {apply}")
     peak = FP64_VECTOR_PEAK_TFLOPS if esz == 8 else FP32_VECTOR_PEAK_TFLOPS
-    if t_fwd >= t_adj:
-        fkname = (f"fwd_kernel<{tname}, 0, {lanes}, false, 1> (forward gather: 2x2 bilinear taps per arc sample from "
-                  f"the cache-resident image, FP64 positions; the solver's instance adds the dual step and "
-                  f"carries the regulariser's dual step in the same launch)")
+    fpath = info_g["fwd_path"]
+    if fpath == 3:
+        # the stored A: two passes, bound by the stream of its entries
+        fm_bytes = info_g["fwd_entries"] * (1 + esz)
+        apply["forward_stored_bytes"] = fm_bytes
+    if t_fwd >= t_adj and fpath == 3:
+        fkname = (f"fmat_kernel<{tname}, false> + fmat_reduce_kernel<{tname}, 0> (forward by the stored A of the "
+                  f"first quarter of the detectors, 16x16 pixel tiles, four quarter-turn slots; both passes)")
+        roofline = {"kernel": fkname, "bound": "hbm",
+                    "achieved": fm_bytes / t_fwd * 1e-9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": fm_bytes / t_fwd * 1e-9 / HBM_PEAK_GBS, "traffic": None,
+                    "traffic_unit": "HBM bytes per launch (rocprofv3 counters, copy-calibrated)",
+                    "bytes_per_launch": fm_bytes, "avg_launch_us": t_fwd * 1e6}
+    elif t_fwd >= t_adj:
+        qt = info_g["fwd_sym"] == 4
+        fkname = (f"fwd_kernel<{tname}, 0, {lanes}, false, {4 if qt else 1}, {'true' if qt else 'false'}> "
+                  f"(forward gather{' in quarter-turn form, after a padding pass' if qt else ''}: 2x2 bilinear "
+                  f"taps per arc sample from the cache-resident image, FP64 positions, "
+                  f"{'detector' if fpath == 1 else 'radius'}-major blocks; the solver's instance adds the dual "
+                  f"step and carries the regulariser's dual step in the same launch)")
         roofline = {"kernel": fkname, "bound": "alu",
                     "achieved": fwd_flops / t_fwd * 1e-12, "peak": peak, "unit": "TFLOP/s",
                     "frac": fwd_flops / t_fwd * 1e-12 / peak,

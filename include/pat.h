@@ -171,9 +171,9 @@ pat_status pat_geometry_set_forward_path(pat_geometry g, int32_t path, void* str
  * same result up to summation order. Invalid values: PAT_ERR_INVALID_ARG. */
 pat_status pat_geometry_set_tiled_launch(pat_geometry g, int32_t waves, int32_t row_lanes);
 
-/* Whether the forward may use the quarter-turn symmetry (default 0, the
- * autotuner times both; takes effect on symmetric geometries, info.sym_rot ==
- * 4, with gather paths 0 and 1). The weights obey w(d + t n_det/4, k, R^t p) = w(d, k, p) for the quarter
+/* Whether the forward may use the quarter-turn symmetry (default 0;
+ * pat_geometry_autotune turns it off; takes effect on symmetric geometries,
+ * info.sym_rot == 4, with gather paths 0 and 1). The weights obey w(d + t n_det/4, k, R^t p) = w(d, k, p) for the quarter
  * turn R of the pixel grid, so the bins of detector d + t n_det/4 are those of
  * detector d on the image turned by t quarter turns: the gather then runs over
  * the first n_det/4 detectors and each arc sample's table entry, position and
@@ -198,9 +198,10 @@ pat_status pat_geometry_set_symmetry(pat_geometry g, int32_t enable, void* strea
 
 /* Autotuner of the projector launch parameters. Times, with HIP events over
  * `reps` stand-alone applies on `stream`, the forward with 16/32/64 lanes per
- * bin in either block order, by LDS tiles, and (symmetric geometries) in
- * quarter-turn form, and the adjoint as stored CSR or as tile scatter (tiles
- * 16/32/64, several detector-group sizes), and keeps the fastest of each. If
+ * bin in either block order, by LDS tiles and (symmetric geometries) by the
+ * stored A, and the adjoint as stored CSR or as tile scatter (tiles 16/32/64,
+ * several detector-group sizes), and keeps the fastest of each; the
+ * quarter-turn form of the gather is left off. If
  * cache_path is non-NULL the choice is read from / appended to that text
  * file, keyed by device architecture, geometry shape and element type, so a
  * later call with the same key times nothing. `out` may be NULL. */
