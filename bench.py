@@ -45,11 +45,20 @@ _SRC_ADJ = {"paper_1707_02245_amd/csrc/csr.hip":
             "3040aa591c28c22f8e93010f102c44657b3b859840285bf95ee966a505330612",
             "paper_1707_02245_amd/csrc/pat_common.hpp":
             "cfcbba40b7f22a819d8564e336b95b702bef06d20d034345790c0ca8412ea1d2"}
+_SRC_FMAT = {"paper_1707_02245_amd/csrc/fmat.hip":
+             "81021914c1473d70865fe97420dfc4684d62ffc8032a989d2a95d173ab7e602a",
+             "paper_1707_02245_amd/csrc/fwd_epilogue.hpp":
+             "e8308bc255c13bd6e6b36f8e6a7bb41666da4a8efe5470fdf8b3331cc7a56af9",
+             "paper_1707_02245_amd/csrc/pat_common.hpp":
+             "cfcbba40b7f22a819d8564e336b95b702bef06d20d034345790c0ca8412ea1d2"}
 MEASURED_TRAFFIC = [
     # profiles/fwd_gather_tgv256_f64_hbm_traffic.md
     {"kernel": "fwd_kernel<double, 0, 16, false, 1, false>", "bytes_per_launch": 34.45e6, "sources": _SRC_FWD},
     {"kernel": "fwd_kernel<double, 0, 32, false, 1, false>", "bytes_per_launch": 39.38e6, "sources": _SRC_FWD},
     {"kernel": "fwd_kernel<double, 0, 64, false, 1, false>", "bytes_per_launch": 42.56e6, "sources": _SRC_FWD},
+    # both passes of the stored A (path 3): 238.33 + 27.44 MB
+    {"kernel": "fmat_kernel<double, false> + fmat_reduce_kernel<double, 0>", "bytes_per_launch": 265.77e6,
+     "sources": _SRC_FMAT},
     # profiles/csr_tiled_tgv256_f64_hbm_traffic.md
     {"kernel": "csr_tiled_kernel<double, false, 4, 256, 16>", "bytes_per_launch": 187.77e6, "sources": _SRC_ADJ},
     {"kernel": "csr_tiled_kernel<double, false, 4, 512, 16>", "bytes_per_launch": 189.63e6, "sources": _SRC_ADJ},
@@ -547,7 +556,8 @@ def main():
                   f"first quarter of the detectors, 16x16 pixel tiles, four quarter-turn slots; both passes)")
         roofline = {"kernel": fkname, "bound": "hbm",
                     "achieved": fm_bytes / t_fwd * 1e-9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": fm_bytes / t_fwd * 1e-9 / HBM_PEAK_GBS, "traffic": None,
+                    "frac": fm_bytes / t_fwd * 1e-9 / HBM_PEAK_GBS,
+                    "traffic": measured_traffic(fkname) if (wl.name == "tgv256" and esz == 8) else None,
                     "traffic_unit": "HBM bytes per launch (rocprofv3 counters, copy-calibrated)",
                     "bytes_per_launch": fm_bytes, "avg_launch_us": t_fwd * 1e6}
     elif t_fwd >= t_adj:
