@@ -10,12 +10,20 @@ Models (Sec. 3.1, eqs. PD_TV and PD_TGV), with F1 = 1/2 ||. - f||^2:
                                                     F3 = alpha0 ||.||_{F,1}, G = 0
   lst : x = u,      K x = A u,                      G = alpha/2 ||u||^2
         (Tikhonov least squares of Sec. 2; a pin with a closed-form solution)
+  wav : x = u,      K x = (A u, W u),               F2 = lam ||.||_1,      G = 0
+        (eq. min_wav: Algorithm 1 with grad -> W and div -> W^{-1} = W^T,
+        W the dual-tree transform of oracle.wavelet; the dual r holds one
+        real number per coefficient, so the prox of F2* clips it to [-lam, lam])
 
 Step sizes (Sec. 3.3.2):
   diag  -- sigma_i = 1/sum_j |K_ij|, tau_j = 1/sum_i |K_ij| over the stacked K
            (diagonal preconditioning); the rows of one pixel's dual vector share
            the smallest of their sigmas so that the pointwise projection stays
-           the exact prox; rows without entries get sigma = 1.
+           the exact prox; rows without entries get sigma = 1. For wav the W
+           rows take sigma = 1 and W's column sums are replaced by 1: in the
+           lemma behind the diagonal steps, Cauchy-Schwarz on the W rows gives
+           way to Parseval's identity ||W x|| = ||x||, so with tau_j =
+           1/(sum_i |A_ij| + 1) the preconditioned operator still has norm <= 1.
   block -- the paper's two-block rule: sigma1 tau L1^2 < 1/4, sigma2 tau L2^2 < 1/4
            with L1 = ||A|| and L2 the norm of the regulariser block, here
            tau = 1/(2 max(L1, L2)), sigma_i = 0.99/(4 tau L_i^2), norms by power
@@ -44,13 +52,14 @@ import numpy as np
 import scipy.sparse as sp
 
 from .operators import grad_matrix, sym_grad_matrix, dtv_matrix
+from .wavelet import dtwt_matrix
 from .prox import prox_f1_conj, project_ball, prox_tikhonov
 
 
 class Problem:
     """One reconstruction problem: A, data f, regulariser and its weights."""
 
-    def __init__(self, A, f, nx, ny, kind, lam, alpha0=0.0, eta=1.0, theta=None):
+    def __init__(self, A, f, nx, ny, kind, lam, alpha0=0.0, eta=1.0, theta=None, levels=3):
         self.A = sp.csr_matrix(A)
         self.f = np.asarray(f, dtype=np.float64).reshape(-1)
         self.nx, self.ny = nx, ny
@@ -66,6 +75,9 @@ class Problem:
             self.B = dtv_matrix(nx, ny, theta, eta)
         elif kind == "lst":
             self.B = None
+        elif kind == "wav":
+            self.levels = int(levels)
+            self.B = dtwt_matrix(nx, ny, self.levels)
         else:
             raise ValueError(kind)
         self.E = sym_grad_matrix(nx, ny) if kind == "tgv" else None
@@ -75,7 +87,7 @@ class Problem:
         A, N = self.A, self.N
         if self.kind == "lst":
             return A
-        if self.kind in ("tv", "dtv"):
+        if self.kind in ("tv", "dtv", "wav"):
             return sp.vstack([A, self.B], format="csr")
         Z = sp.csr_matrix((A.shape[0], 2 * N))
         I2 = sp.identity(2 * N, format="csr")
@@ -87,7 +99,7 @@ class Problem:
     def reg_block(self) -> sp.csr_matrix:
         """The part of K that is not A (acting on x)."""
         N = self.N
-        if self.kind in ("tv", "dtv"):
+        if self.kind in ("tv", "dtv", "wav"):
             return self.B
         I2 = sp.identity(2 * N, format="csr")
         Z2 = sp.csr_matrix((4 * N, N))
@@ -95,7 +107,14 @@ class Problem:
 
 
 def precond_diag(p: Problem) -> dict:
-    """sigma_i = 1/sum_j|K_ij|, tau_j = 1/sum_i|K_ij|, block-min over dual vectors."""
+    """sigma_i = 1/sum_j|K_ij|, tau_j = 1/sum_i|K_ij|, block-min over dual vectors
+    (wav: sigma_r = 1, tau_j = 1/(sum_i|A_ij| + 1); see the module doc)."""
+    if p.kind == "wav":
+        A = abs(p.A)
+        rs = np.asarray(A.sum(axis=1)).reshape(-1)
+        cs = np.asarray(A.sum(axis=0)).reshape(-1)
+        sig = np.where(rs > 0, 1.0 / np.where(rs > 0, rs, 1.0), 1.0)
+        return dict(sigma_q=sig, tau_u=1.0 / (cs + 1.0), sigma_r=np.ones(p.B.shape[0]))
     K = abs(p.stacked())
     rs = np.asarray(K.sum(axis=1)).reshape(-1)
     cs = np.asarray(K.sum(axis=0)).reshape(-1)
@@ -145,7 +164,8 @@ def precond_block(p: Problem, iters: int = BLOCK_POWER_ITERS) -> dict:
     s1 = 0.99 / (4.0 * tau * L1 * L1)
     s2 = 0.99 / (4.0 * tau * L2 * L2)
     N = p.N
-    out = dict(sigma_q=np.full(p.A.shape[0], s1), sigma_r=np.full(N, s2),
+    out = dict(sigma_q=np.full(p.A.shape[0], s1),
+               sigma_r=np.full(p.B.shape[0] if p.kind == "wav" else N, s2),
                tau_u=np.full(N, tau), L1=L1, L2=L2)
     if p.kind == "tgv":
         out["sigma_s"] = np.full(N, s2)
@@ -165,6 +185,8 @@ def primal_objective(p: Problem, u, v=None) -> float:
     P = 0.5 * float(res @ res)
     if p.kind in ("tv", "dtv"):
         P += p.lam * _pointwise_norm_sum((p.B @ u).reshape(2, p.N))
+    elif p.kind == "wav":
+        P += p.lam * float(np.sum(np.abs(p.B @ u)))
     elif p.kind == "tgv":
         P += p.lam * _pointwise_norm_sum((p.B @ u).reshape(2, p.N) - v)
         P += p.alpha0 * _pointwise_norm_sum((p.E @ v.reshape(-1)).reshape(4, p.N))
@@ -210,6 +232,8 @@ def init_state(p: Problem, u0=None) -> dict:
     st = dict(u=u, ubar=u.copy(), q=np.zeros(m), n=0)
     if p.kind in ("tv", "dtv", "tgv"):
         st["r"] = np.zeros((2, N))
+    elif p.kind == "wav":
+        st["r"] = np.zeros((1, p.B.shape[0]))
     if p.kind == "tgv":
         st["v"] = np.zeros((2, N))
         st["vbar"] = np.zeros((2, N))
@@ -234,9 +258,9 @@ def pdhg_step(p: Problem, pc: dict, st: dict, theta: float = 1.0,
     st["q"] = prox_f1_conj(st["q"] + sq * (A @ st["ubar"]), p.f, sq)
     q = st["q"]
     u_old = st["u"]
-    if p.kind in ("tv", "dtv"):
+    if p.kind in ("tv", "dtv", "wav"):
         # r^{n+1} = prox_{sigma2 F2*}(r^n + sigma2 B ubar^n)
-        Bu = (p.B @ st["ubar"]).reshape(2, N)
+        Bu = (p.B @ st["ubar"]).reshape(st["r"].shape)
         st["r"] = project_ball(st["r"] + pc["sigma_r"] * Bu, p.lam)
         # u^{n+1} = u^n - tau (A^T q^{n+1} + B^T r^{n+1})
         u_new = u_old - pc["tau_u"] * (A.T @ q + p.B.T @ st["r"].reshape(-1))
