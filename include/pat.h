@@ -7,8 +7,9 @@
  *
  *   min_u 1/2 ||A u - f||^2 + R(u)                      (Sec. 2, eq. min_prob)
  *
- * with R = TV (eq. min_TV), TGV2 (eq. min_TGV), directional TV, or Tikhonov
- * (LS-T, Sec. 2), solved in saddle-point form (Sec. 3.1) by the first-order
+ * with R = TV (eq. min_TV), TGV2 (eq. min_TGV), directional TV, the l1 norm
+ * of dual-tree wavelet coefficients (eq. min_wav) or Tikhonov (LS-T, Sec. 2),
+ * solved in saddle-point form (Sec. 3.1) by the first-order
  * primal-dual algorithm PDHGM (Algorithms 1 and 2) with diagonal or two-block
  * step sizes (Sec. 3.3.2) and the primal-dual gap as stopping rule (Sec. 3.3.3).
  *
@@ -258,28 +259,68 @@ pat_status pat_adjoint_noalloc(pat_geometry g, const void* d_f, void* d_u, void*
  *            xi = (-sin theta, cos theta), theta = d_dtv_theta [ny][nx]
  *            (device, element type of the geometry)
  *  TIKHONOV: lambda/2 ||u||^2 (LS-T, a test problem with a closed form)
+ *  WAVELET : lambda ||W u||_1 (Sec. 2.2, eq. min_wav), W the dual-tree
+ *            transform of pat_wavelet_forward with wav_levels levels; the
+ *            dual variable holds one number per coefficient (4 N of them)
  * grad uses unit-spacing forward differences with a zero last difference;
  * E uses the backward differences -grad^T and counts the off-diagonal twice.
  * Validation: lambda < 0 or non-finite, tgv_alpha0 < 0, dtv_eta not in
- * (0, 1], DTV without d_dtv_theta -> PAT_ERR_INVALID_ARG. */
-typedef enum { PAT_REG_TV = 0, PAT_REG_TGV = 1, PAT_REG_DTV = 2, PAT_REG_TIKHONOV = 3 } pat_reg_kind;
+ * (0, 1], DTV without d_dtv_theta, WAVELET with wav_levels outside 1..8 or
+ * nx, ny not multiples of 2^wav_levels -> PAT_ERR_INVALID_ARG. */
+typedef enum {
+  PAT_REG_TV = 0, PAT_REG_TGV = 1, PAT_REG_DTV = 2, PAT_REG_TIKHONOV = 3, PAT_REG_WAVELET = 4
+} pat_reg_kind;
 typedef struct {
   int32_t kind;           /* pat_reg_kind */
   double lambda;
   double tgv_alpha0;
   double dtv_eta;
   const void* d_dtv_theta;
+  int32_t wav_levels;     /* WAVELET: decomposition levels J (1..8) */
 } pat_regulariser;
+
+/* The dual-tree wavelet transform W of the wavelet model (Sec. 2.2, eq.
+ * min_wav, which takes W from the dual-tree complex wavelet transform; the
+ * paper does not print its filters, so this library fixes them):
+ *  - 1-D filters: the orthonormal 4-tap Daubechies lowpass
+ *    h = (1 + s, 3 + s, 3 - s, 1 - s) / (4 sqrt 2), s = sqrt 3, and its
+ *    mirror highpass g[k] = (-1)^k h[3 - k]; periodic analysis
+ *    y[i] = sum_k c[k] x[(2 i + k + shift) mod n].
+ *  - Trees a and b: at level 1 tree b filters the signal advanced by one
+ *    sample (shift 1), from level 2 on it uses the time-reversed filters of
+ *    tree a (shift 0); tree a always uses h, g with shift 0.
+ *  - 2-D: four separable trees (row tree, column tree) in {a, b}^2, each a
+ *    J-level orthonormal transform recursing on its own lowpass band; per
+ *    level and orientation (LH: lowpass along y, highpass along x; HL; HH)
+ *    the four trees' bands combine into p = (aa - bb)/sqrt2,
+ *    q = (aa + bb)/sqrt2, s = (ab + ba)/sqrt2, t = (ab - ba)/sqrt2; the four
+ *    level-J lowpass bands stay per tree. All scaled by 1/2, so that
+ *    W^T W = I and ||W|| = 1.
+ *  - Coefficient order (4 N): for level j = 1..J, for orientation LH, HL,
+ *    HH, for band p, q, s, t, the (ny/2^j) x (nx/2^j) band row-major; then
+ *    the level-J lowpass bands of trees aa, ab, ba, bb.
+ * pat_wavelet_forward: d_c = W d_u; pat_wavelet_adjoint: d_u = W^T d_c.
+ * d_u: device [ny][nx], d_c: device [4 nx ny], element type `dtype`
+ * (pat_dtype); arithmetic in the element type. Allocates a work buffer of
+ * 1.25 nx ny elements per call. Validation: levels outside 1..8, nx or ny
+ * not a positive multiple of 2^levels, NULL pointers -> PAT_ERR_INVALID_ARG. */
+pat_status pat_wavelet_forward(int32_t dtype, int32_t nx, int32_t ny, int32_t levels,
+                               const void* d_u, void* d_c, void* stream);
+pat_status pat_wavelet_adjoint(int32_t dtype, int32_t nx, int32_t ny, int32_t levels,
+                               const void* d_c, void* d_u, void* stream);
 
 /* Step sizes (Sec. 3.3.2).
  *  DIAG : sigma_i = 1 / sum_j |K_ij|, tau_j = 1 / sum_i |K_ij| over the
  *         stacked operator K = [A; B] (TGV: [A 0; grad -I; 0 E]); the rows of
  *         one pixel's dual vector share the smallest of their sigmas; rows
- *         with no entries get sigma = 1.
+ *         with no entries get sigma = 1. WAVELET: the rows of W take
+ *         sigma = 1 and tau_j = 1 / (sum_i |A_ij| + 1): with W^T W = I,
+ *         ||W x|| = ||x|| takes the place of W's column sums in the bound
+ *         ||Sigma^(1/2) K T^(1/2)|| <= 1.
  *  BLOCK: scalar sigma1 (data), sigma2 (regulariser) and tau with
  *         sigma_i tau L_i^2 = 0.99/4, tau = 1/(2 max(L1, L2)), L1 = ||A||,
  *         L2 = ||B|| (TGV: the block [grad -I; 0 E]); norms by 1000 power
- *         iterations times 1.05. */
+ *         iterations times 1.05 (WAVELET: L2 = ||W||, the same way). */
 typedef enum { PAT_PRECOND_DIAG = 0, PAT_PRECOND_BLOCK = 1 } pat_precond_kind;
 
 /* Compute step sizes for (g, reg). The handle keeps device arrays and must
@@ -287,14 +328,15 @@ typedef enum { PAT_PRECOND_DIAG = 0, PAT_PRECOND_BLOCK = 1 } pat_precond_kind;
 pat_status pat_precond(pat_geometry g, const pat_regulariser* reg, int32_t kind,
                        void* stream, pat_precond_h* out);
 /* Export one step-size array to caller memory (device, element type of g):
- * which = 0 sigma_q [n_bins], 1 sigma_r [N], 2 sigma_s [N] (TGV),
+ * which = 0 sigma_q [n_bins], 1 sigma_r [N] (WAVELET: [4 N]), 2 sigma_s [N] (TGV),
  * 3 tau_u [N], 4 tau_v [2][N] (TGV). Missing arrays: PAT_ERR_INVALID_ARG. */
 pat_status pat_precond_get(pat_precond_h p, int32_t which, void* d_dst, void* stream);
 pat_status pat_precond_destroy(pat_precond_h p);
 
 /* Solver state for warm restarts and resume, in one device buffer of the
  * geometry's element type, concatenated in this order:
- *   u [N], ubar [N], q [n_bins], r [2][N] (not LS-T),
+ *   u [N], ubar [N], q [n_bins], r [2][N] (TV, TGV, DTV) or [4 N] (WAVELET,
+ *   in the coefficient order of pat_wavelet_forward),
  *   TGV only: v [2][N], vbar [2][N], s [3][N] (s_xx, s_xy, s_yy).
  * pat_state_elems gives the length in elements. */
 pat_status pat_state_elems(pat_geometry g, int32_t reg_kind, int64_t* out);
@@ -339,7 +381,7 @@ typedef struct {
   double rel_gap, gap, primal, fstar, kty_l1, residual, seconds;
 } pat_solve_info;
 
-/* PDHGM (Algorithm 1 for TV/DTV/LS-T, Algorithm 2 for TGV) with theta
+/* PDHGM (Algorithm 1 for TV/DTV/WAVELET/LS-T, Algorithm 2 for TGV) with theta
  * extrapolation, from zero, from d_u0, or from d_state_in. The gap of
  * Sec. 3.3.3 is taken with x restricted to the box ||x||_inf <= gap_box
  * (the printed gap is infinite when G = 0):
@@ -374,7 +416,8 @@ pat_status pat_pdhg_solve_batched(int32_t n, const pat_geometry* g, const void* 
  * after one untimed launch, and writes the average per launch in ms:
  *   ms[0] the forward launch (A ubar with the dual data step, Sec. 3.2 prox of
  *         F1*, and the regulariser's dual step in the same launch),
- *   ms[1] the regulariser's dual step alone (r, and s for TGV),
+ *   ms[1] the regulariser's dual step alone (r, and s for TGV; WAVELET: the
+ *         transform's dual step and W^T r, which run outside the forward),
  *   ms[2] A^T q into the partial images,
  *   ms[3] the primal step (u, v and the extrapolation).
  * Every launch covers all instances. The state the timed launches leave is

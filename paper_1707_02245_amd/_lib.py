@@ -17,7 +17,7 @@ PAT_ERR_NUMERIC = -4
 PAT_ERR_UNSUPPORTED = -5
 
 PAT_F32, PAT_F64 = 0, 1
-PAT_REG_TV, PAT_REG_TGV, PAT_REG_DTV, PAT_REG_TIKHONOV = 0, 1, 2, 3
+PAT_REG_TV, PAT_REG_TGV, PAT_REG_DTV, PAT_REG_TIKHONOV, PAT_REG_WAVELET = 0, 1, 2, 3, 4
 PAT_PRECOND_DIAG, PAT_PRECOND_BLOCK = 0, 1
 
 
@@ -63,7 +63,7 @@ class AutotuneResult(C.Structure):
 class Regulariser(C.Structure):
     _fields_ = [
         ("kind", C.c_int32), ("lam", C.c_double), ("tgv_alpha0", C.c_double),
-        ("dtv_eta", C.c_double), ("d_dtv_theta", C.c_void_p),
+        ("dtv_eta", C.c_double), ("d_dtv_theta", C.c_void_p), ("wav_levels", C.c_int32),
     ]
 
 
@@ -146,6 +146,10 @@ _SIGS = {
     "pat_preprocess": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "pat_psnr": ([C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
                   C.c_void_p], C.c_int),
+    "pat_wavelet_forward": ([C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                             C.c_void_p], C.c_int),
+    "pat_wavelet_adjoint": ([C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                             C.c_void_p], C.c_int),
     "pat_status_string": ([C.c_int], C.c_char_p),
     "pat_last_error": ([], C.c_char_p),
 }

@@ -280,7 +280,7 @@ struct InstDev {
   // state
   T* u;               // [N]
   T* ubar_pad;        // [(ny+2)(nx+2)], zero border
-  T* r;               // [2][N]
+  T* r;               // [2][N] (WAVELET: [4 N], coefficient order)
   T* v;               // [2][N]  (TGV)
   T* vbar;            // [2][N]  (TGV)
   T* s;               // [3][N]  (TGV)
@@ -296,6 +296,8 @@ struct InstDev {
   int red_stride;
   const double* mult; // step multipliers {dual, primal, theta} of this
                       // iteration (accelerated schedule; null: plain steps)
+  const T* wtr;       // WAVELET: W^T r [N] of this iteration
+  const double* wtr64;  // WAVELET, FP32 check iterations: W^T r in FP64 (else null)
   int rot_slots;      // 4: ubar_pad and upad_gap hold, after the image, its
                       // copies turned by 1, 2 and 3 quarter turns (padded
                       // size apart) for the quarter-turn forward; else 1
@@ -360,6 +362,7 @@ __device__ __forceinline__ int64_t quarter_turn(int i, int j, int n, int t) {
 struct GapFinishArgs {
   const double* red;
   int stride, n_fwd, n_pix;
+  int n_reg;  // partials of the regulariser value (n_pix, or the wavelet gap's workgroups)
 };
 
 }  // namespace pat

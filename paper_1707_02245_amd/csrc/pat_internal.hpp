@@ -246,6 +246,43 @@ void launch_csr_spmm(const CsrMultiArgs<T>& a, hipStream_t s, bool wide);
 template <class T>
 void prepare_csr_tiled(int max_rhs, size_t shm);
 
+// ---- dual-tree wavelet transform W (wavelet.hip)
+constexpr int kWavMaxLevels = 8;
+// The image W reads: img[y * pitch + x], y < ny, x < nx (nx, ny multiples of 2^levels).
+template <class T>
+struct WavInput {
+  int nx, ny, levels;
+  const T* img;
+  int pitch;
+};
+// Where the coefficients go: coef (W u), the dual step on r, or the gap sum.
+template <class T>
+struct WavDual {
+  T* coef;
+  T* r;                // dual variable [4 N]
+  const T* sigma;      // its step sizes [4 N]
+  const double* mult;  // step multipliers of the accelerated schedule, or null
+  T lam;
+  double* red;         // gap: wav_gap_blocks partial sums
+};
+// Work buffer of the lowpass bands between levels (elements of the arithmetic type).
+int64_t wav_work_elems(int nx, int ny);
+// Partial sums the gap pass writes (one per workgroup, levels in order).
+int wav_gap_blocks(int nx, int ny, int levels);
+void check_wavelet_shape(int nx, int ny, int levels);
+// coef = W img
+template <class T>
+void launch_wav_forward(const WavInput<T>& in, T* coef, T* work, hipStream_t s);
+// r <- clip(r + sigma mult[0] W img, -lam, lam)
+template <class T>
+void launch_wav_dual(const WavInput<T>& in, const WavDual<T>& d, T* work, hipStream_t s);
+// red[b] = lam sum |W img| over the coefficients of workgroup b (FP64 arithmetic)
+template <class T>
+void launch_wav_gap(const WavInput<T>& in, T lam, double* red, double* work, hipStream_t s);
+// out = W^T coef, arithmetic and output in A (T, or FP64 for the gap of FP32)
+template <class T, class A>
+void launch_wav_adjoint(int nx, int ny, int levels, const T* coef, A* out, A* work, hipStream_t s);
+
 // ---- launchers (pdhg.hip)
 template <class T>
 void launch_reg_dual(const Launch<T>& L, hipStream_t s);

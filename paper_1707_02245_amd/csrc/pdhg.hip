@@ -95,6 +95,10 @@ __global__ __launch_bounds__(256) void primal_kernel(const InstDev<T>* __restric
       // u <- prox_{tau G}(u - tau A^T q), G = lam/2 ||u||^2
       un = (u_old - tau * atq) / (T(1) + tau * a.lam);
       if (CHECK) kty = atq_d * atq_d;
+    } else if (a.kind == PAT_REG_WAVELET) {
+      // B^T r = W^T r, synthesised after the dual step of this iteration
+      un = u_old - tau * (atq + a.wtr[p]);
+      if (CHECK) kty = fabs(atq_d + (a.wtr64 ? a.wtr64[p] : (double)a.wtr[p]));
     } else {
       const T gdir = atq + bt_r(a, p, i, j, N);
       un = u_old - tau * gdir;
@@ -204,6 +208,8 @@ __global__ __launch_bounds__(256) void gap_reg_kernel(const InstDev<T>* __restri
   int blk = blockIdx.x;
   const int ii = find_inst_p(starts, n_inst, blk);
   const InstDev<T> a = arr[ii];
+  // the wavelet value lam ||W u||_1 comes from the transform's own gap pass
+  if (a.kind == PAT_REG_WAVELET) return;
   blk -= starts[ii];
   const int nx = a.nx, ny = a.ny;
   const int64_t N = (int64_t)nx * ny;
@@ -262,7 +268,7 @@ __global__ __launch_bounds__(256) void gap_finish_kernel(const GapFinishArgs* __
   double* out = out_base + (int64_t)blockIdx.x * GAP_NSLOTS;
   __shared__ double lds[8];
   for (int slot = 0; slot < GAP_NSLOTS; ++slot) {
-    const int cnt = (slot == GAP_DATA || slot == GAP_FSTAR) ? a.n_fwd : a.n_pix;
+    const int cnt = (slot == GAP_DATA || slot == GAP_FSTAR) ? a.n_fwd : (slot == GAP_REG ? a.n_reg : a.n_pix);
     double v = 0.0;
     for (int b = threadIdx.x; b < cnt; b += 256) v += a.red[slot * (int64_t)a.stride + b];
     const double s = block_sum<256>(v, lds);
@@ -297,6 +303,14 @@ __global__ __launch_bounds__(256) void precond_pix_kernel(int kind, int nx, int 
   auto inv_or_one = [](double s) { return s > 0.0 ? 1.0 / s : 1.0; };
   if (kind == PAT_REG_TIKHONOV) {
     tau_u[p] = (T)inv_or_one(ca);
+    return;
+  }
+  if (kind == PAT_REG_WAVELET) {
+    // W^T W = I: ||W x|| = ||x|| stands in for W's column sums, so 1 is added
+    // to A's, and W's rows take sigma = 1 (four coefficients per pixel)
+    tau_u[p] = (T)(1.0 / (ca + 1.0));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sigma_r[k * N + p] = T(1);
     return;
   }
   if (kind == PAT_REG_TV) {

@@ -41,7 +41,7 @@ __device__ __forceinline__ void reg_dual_block(const InstDev<T>* __restrict__ ar
   const int nx = a.nx, ny = a.ny;
   const int64_t N = (int64_t)nx * ny;
   const int64_t p = (int64_t)blk * 256 + threadIdx.x;
-  if (p >= N || a.kind == PAT_REG_TIKHONOV) return;
+  if (p >= N || a.kind == PAT_REG_TIKHONOV || a.kind == PAT_REG_WAVELET) return;
   const int i = (int)(p % nx), j = (int)(p / nx);
   const int P = nx + 2;
   const T* __restrict__ ub = a.ubar_pad + (int64_t)(j + 1) * P + (i + 1);

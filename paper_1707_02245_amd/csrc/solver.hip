@@ -26,7 +26,7 @@ namespace pat {
 
 void validate_regulariser(const pat_geometry_s* g, const pat_regulariser* r) {
   PAT_CHECK_ARG(r != nullptr, "regulariser is NULL");
-  PAT_CHECK_ARG(r->kind >= PAT_REG_TV && r->kind <= PAT_REG_TIKHONOV, "unknown regulariser kind");
+  PAT_CHECK_ARG(r->kind >= PAT_REG_TV && r->kind <= PAT_REG_WAVELET, "unknown regulariser kind");
   PAT_CHECK_ARG(std::isfinite(r->lambda) && r->lambda >= 0.0, "lambda must be finite and >= 0");
   if (r->kind == PAT_REG_TGV)
     PAT_CHECK_ARG(std::isfinite(r->tgv_alpha0) && r->tgv_alpha0 >= 0.0,
@@ -37,7 +37,7 @@ void validate_regulariser(const pat_geometry_s* g, const pat_regulariser* r) {
     PAT_CHECK_ARG(r->d_dtv_theta != nullptr, "DTV needs d_dtv_theta");
   }
   if (r->kind == PAT_REG_TIKHONOV) PAT_CHECK_ARG(r->lambda > 0.0, "Tikhonov lambda must be > 0");
-  (void)g;
+  if (r->kind == PAT_REG_WAVELET) check_wavelet_shape(g->nx, g->ny, r->wav_levels);
 }
 
 static void validate_opts(const pat_solve_opts* o) {
@@ -119,7 +119,14 @@ static void precond_block(pat_precond_s* pc, const pat_regulariser* reg, const T
     apply_adjoint<T>(g, ptr<T>(tmp_b), y, s);
   });
   double L2 = 0.0;
-  if (reg->kind != PAT_REG_TIKHONOV) {
+  if (reg->kind == PAT_REG_WAVELET) {
+    DevBuf z(sizeof(T) * 4 * N), work(sizeof(T) * wav_work_elems(g->nx, g->ny));
+    L2 = kPowerSafety * power_norm<T>(N, s, [&](const T* x, T* y) {
+      WavInput<T> in{g->nx, g->ny, reg->wav_levels, x, g->nx};
+      launch_wav_forward<T>(in, ptr<T>(z), ptr<T>(work), s);
+      launch_wav_adjoint<T, T>(g->nx, g->ny, reg->wav_levels, ptr<T>(z), y, ptr<T>(work), s);
+    });
+  } else if (reg->kind != PAT_REG_TIKHONOV) {
     const bool tgv = reg->kind == PAT_REG_TGV;
     const int64_t nx_ = tgv ? 3 * N : N;
     DevBuf z(sizeof(T) * (tgv ? 5 : 2) * N);
@@ -135,7 +142,7 @@ static void precond_block(pat_precond_s* pc, const pat_regulariser* reg, const T
   const double s2 = L2 > 0.0 ? 0.99 / (4.0 * tau * L2 * L2) : 1.0;
   launch_fill<T>(ptr<T>(pc->sigma_q), (T)s1, nb, s);
   launch_fill<T>(ptr<T>(pc->tau_u), (T)tau, N, s);
-  if (pc->sigma_r.p) launch_fill<T>(ptr<T>(pc->sigma_r), (T)s2, N, s);
+  if (pc->sigma_r.p) launch_fill<T>(ptr<T>(pc->sigma_r), (T)s2, (int64_t)(pc->sigma_r.bytes / sizeof(T)), s);
   if (pc->sigma_s.p) launch_fill<T>(ptr<T>(pc->sigma_s), (T)s2, N, s);
   if (pc->tau_v.p) launch_fill<T>(ptr<T>(pc->tau_v), (T)tau, N, s);
   PAT_HIP(hipStreamSynchronize(s));
@@ -150,7 +157,8 @@ static pat_precond_s* make_precond(pat_geometry g, const pat_regulariser* reg, i
   const int64_t N = g->n_pix();
   pc->sigma_q.alloc(es * g->n_bins());
   pc->tau_u.alloc(es * N);
-  if (reg->kind != PAT_REG_TIKHONOV) pc->sigma_r.alloc(es * N);
+  // one step per pixel's dual vector; the wavelet's one per coefficient
+  if (reg->kind != PAT_REG_TIKHONOV) pc->sigma_r.alloc(es * (reg->kind == PAT_REG_WAVELET ? 4 : 1) * N);
   if (reg->kind == PAT_REG_TGV) {
     pc->sigma_s.alloc(es * N);
     pc->tau_v.alloc(es * N);
@@ -173,7 +181,8 @@ static pat_precond_s* make_precond(pat_geometry g, const pat_regulariser* reg, i
 int64_t state_elems(const pat_geometry_s* g, int kind) {
   const int64_t N = g->n_pix(), nb = g->n_bins();
   int64_t n = 2 * N + nb;
-  if (kind != PAT_REG_TIKHONOV) n += 2 * N;
+  if (kind == PAT_REG_WAVELET) n += 4 * N;
+  else if (kind != PAT_REG_TIKHONOV) n += 2 * N;
   if (kind == PAT_REG_TGV) n += 7 * N;
   return n;
 }
@@ -187,6 +196,10 @@ struct Inst {
   T* u_out = nullptr;
   pat_solve_info* info = nullptr;
   DevBuf u, ubar_pad, q, r, v, vbar, s, upad_gap, atq_part, atq64, red, dmat, fpart;
+  // wavelet model: W^T r (and in FP64 for the gap of FP32), the transform's
+  // work buffer (FP64-sized), and the gap pass's partial sums
+  DevBuf wtr, wtr64, wwork;
+  int n_reg = 0;
   pat_precond_s* pc = nullptr;
   std::unique_ptr<pat_precond_s> own_pc;
   int n_fwd = 0, n_pix = 0, n_adj = 0, n_csr = 0, red_stride = 0;
@@ -331,7 +344,14 @@ class Solver {
     I.ubar_pad.alloc(sizeof(T) * slots * P);
     I.upad_gap.alloc(sizeof(T) * slots * P);
     I.q.alloc(sizeof(T) * nb);
-    if (kind != PAT_REG_TIKHONOV) I.r.alloc(sizeof(T) * 2 * N);
+    if (kind == PAT_REG_WAVELET) {
+      I.r.alloc(sizeof(T) * 4 * N);
+      I.wtr.alloc(sizeof(T) * N);
+      if (sizeof(T) == 4) I.wtr64.alloc(sizeof(double) * N);
+      I.wwork.alloc(sizeof(double) * wav_work_elems(g->nx, g->ny));
+    } else if (kind != PAT_REG_TIKHONOV) {
+      I.r.alloc(sizeof(T) * 2 * N);
+    }
     if (kind == PAT_REG_TGV) {
       I.v.alloc(sizeof(T) * 2 * N);
       I.vbar.alloc(sizeof(T) * 2 * N);
@@ -362,7 +382,8 @@ class Solver {
     I.n_pix = pix_blocks(N);
     I.n_adj = I.csr ? 0 : gd.tiles_x * gd.tiles_y * gd.n_groups;
     I.n_csr = I.csr ? (int)((N + 3) / 4) : 0;
-    I.red_stride = std::max(I.n_fwd, I.n_pix);
+    I.n_reg = kind == PAT_REG_WAVELET ? wav_gap_blocks(g->nx, g->ny, I.reg.wav_levels) : I.n_pix;
+    I.red_stride = std::max({I.n_fwd, I.n_pix, I.n_reg});
     I.red.alloc(sizeof(double) * GAP_NSLOTS * I.red_stride);
     compute_dmat<T>(g, &I.reg, I.dmat, s);
     if (I.opts.precond) {
@@ -404,6 +425,8 @@ class Solver {
     d.red_stride = I.red_stride;
     d.mult = I.accel ? ptr<double>(cur) + 3 * inst_index(I) : nullptr;
     d.rot_slots = I.qt ? 4 : 1;
+    d.wtr = ptr<T>(I.wtr);
+    d.wtr64 = ptr<double>(I.wtr64);
     return d;
   }
 
@@ -537,7 +560,7 @@ class Solver {
         as.push_back(as.back() + I.n_adj);
       }
       id[k] = inst_dev(I);
-      gf[k] = GapFinishArgs{ptr<double>(I.red), I.red_stride, n_fwd_parts, I.n_pix};
+      gf[k] = GapFinishArgs{ptr<double>(I.red), I.red_stride, n_fwd_parts, I.n_pix, I.n_reg};
       fs[k + 1] = fs[k] + n_fwd;
       ps[k + 1] = ps[k] + I.n_pix;
     }
@@ -684,6 +707,7 @@ class Solver {
     std::swap(L.fwdg, L.fwdg_gap);
     std::swap(L.fm, L.fm_gap);
     launch_gap_reg<T>(L, s);
+    enqueue_wavelet_gap();
     launch_gap_finish(ptr<GapFinishArgs>(L.gapfin), L.n,
                       ptr<double>(results) + (size_t)c * L.n * GAP_NSLOTS, s);
   }
@@ -691,9 +715,55 @@ class Solver {
   void enqueue_iteration(int t, bool check, int c) {
     if (accel_live) launch_accel_step(ptr<double>(sched), ptr<double>(cur), (int)inst.size(), sched_block, t, s);
     launch_forward_reg_batched<T>(L, lanes_log2, s);
+    enqueue_wavelet_dual();
+    enqueue_wavelet_synthesis(check);
     enqueue_adjoint(check);
     launch_primal<T>(L, check, s);
     if (check) enqueue_gap(c);
+  }
+
+  // Wavelet model, one launch per level and instance. The transform reads the
+  // interior of a padded state image.
+  WavInput<T> wav_input(const Inst<T>& I, const DevBuf& upad) const {
+    const int P = I.g->nx + 2;
+    return WavInput<T>{I.g->nx, I.g->ny, I.reg.wav_levels, ptr<T>(upad) + P + 1, P};
+  }
+
+  // The dual step r <- clip(r + sigma W ubar, -lam, lam).
+  void enqueue_wavelet_dual() {
+    for (int k : act) {
+      Inst<T>& I = *inst[k];
+      if (I.reg.kind != PAT_REG_WAVELET) continue;
+      WavDual<T> d{};
+      d.r = ptr<T>(I.r);
+      d.sigma = ptr<T>(I.pc->sigma_r);
+      d.mult = I.accel ? ptr<double>(cur) + 3 * k : nullptr;
+      d.lam = (T)I.reg.lambda;
+      launch_wav_dual<T>(wav_input(I, I.ubar_pad), d, ptr<T>(I.wwork), s);
+    }
+  }
+
+  // W^T r of the new r for the primal step (on check iterations of FP32 also
+  // in FP64, for the gap's dual residual).
+  void enqueue_wavelet_synthesis(bool check) {
+    for (int k : act) {
+      Inst<T>& I = *inst[k];
+      if (I.reg.kind != PAT_REG_WAVELET) continue;
+      launch_wav_adjoint<T, T>(I.g->nx, I.g->ny, I.reg.wav_levels, ptr<T>(I.r), ptr<T>(I.wtr), ptr<T>(I.wwork), s);
+      if (check && I.wtr64.p)
+        launch_wav_adjoint<T, double>(I.g->nx, I.g->ny, I.reg.wav_levels, ptr<T>(I.r), ptr<double>(I.wtr64),
+                                      ptr<double>(I.wwork), s);
+    }
+  }
+
+  // The gap's lam ||W u+||_1 into the regulariser partials.
+  void enqueue_wavelet_gap() {
+    for (int k : act) {
+      Inst<T>& I = *inst[k];
+      if (I.reg.kind != PAT_REG_WAVELET) continue;
+      launch_wav_gap<T>(wav_input(I, I.upad_gap), (T)I.reg.lambda,
+                        ptr<double>(I.red) + (size_t)GAP_REG * I.red_stride, ptr<double>(I.wwork), s);
+    }
   }
 
   // A^T q of every active instance into its partial images
@@ -742,8 +812,8 @@ class Solver {
         PAT_HIP(hipMemcpyAsync(I.q.p, st + o, sizeof(T) * nb, hipMemcpyDeviceToDevice, s));
         o += nb;
         if (I.r.p) {
-          PAT_HIP(hipMemcpyAsync(I.r.p, st + o, sizeof(T) * 2 * N, hipMemcpyDeviceToDevice, s));
-          o += 2 * N;
+          PAT_HIP(hipMemcpyAsync(I.r.p, st + o, I.r.bytes, hipMemcpyDeviceToDevice, s));
+          o += (int64_t)(I.r.bytes / sizeof(T));
         }
         if (I.reg.kind == PAT_REG_TGV) {
           PAT_HIP(hipMemcpyAsync(I.v.p, st + o, sizeof(T) * 2 * N, hipMemcpyDeviceToDevice, s));
@@ -944,8 +1014,8 @@ class Solver {
         PAT_HIP(hipMemcpyAsync(st + o, I.q.p, sizeof(T) * nb, hipMemcpyDeviceToDevice, s));
         o += nb;
         if (I.r.p) {
-          PAT_HIP(hipMemcpyAsync(st + o, I.r.p, sizeof(T) * 2 * N, hipMemcpyDeviceToDevice, s));
-          o += 2 * N;
+          PAT_HIP(hipMemcpyAsync(st + o, I.r.p, I.r.bytes, hipMemcpyDeviceToDevice, s));
+          o += (int64_t)(I.r.bytes / sizeof(T));
         }
         if (I.reg.kind == PAT_REG_TGV) {
           PAT_HIP(hipMemcpyAsync(st + o, I.v.p, sizeof(T) * 2 * N, hipMemcpyDeviceToDevice, s));
@@ -1058,7 +1128,11 @@ static void kernel_times_impl(int n, const pat_geometry* g, const void* const* d
   };
   try {
     ms[0] = timeit([&] { launch_forward_reg_batched<T>(S.L, S.lanes_log2, s); });
-    ms[1] = timeit([&] { launch_reg_dual<T>(S.L, s); });
+    ms[1] = timeit([&] {
+      launch_reg_dual<T>(S.L, s);
+      S.enqueue_wavelet_dual();
+      S.enqueue_wavelet_synthesis(false);
+    });
     ms[2] = timeit([&] { S.enqueue_adjoint(false); });
     ms[3] = timeit([&] { launch_primal<T>(S.L, false, s); });
   } catch (...) {
@@ -1145,7 +1219,7 @@ extern "C" pat_status pat_precond_destroy(pat_precond_h p) {
 extern "C" pat_status pat_state_elems(pat_geometry g, int32_t reg_kind, int64_t* out) {
   return guarded([&]() -> pat_status {
     PAT_CHECK_ARG(g != nullptr && out != nullptr, "NULL argument");
-    PAT_CHECK_ARG(reg_kind >= PAT_REG_TV && reg_kind <= PAT_REG_TIKHONOV, "unknown regulariser kind");
+    PAT_CHECK_ARG(reg_kind >= PAT_REG_TV && reg_kind <= PAT_REG_WAVELET, "unknown regulariser kind");
     *out = pat::state_elems(g, reg_kind);
     return PAT_OK;
   });

@@ -1,0 +1,408 @@
+// Dual-tree wavelet transform W of the wavelet model (arXiv:1707.02245,
+// Sec. 2.2 eq. min_wav: lam ||W u||_1 with W from the dual-tree complex
+// wavelet transform, ||W|| = 1 and W^T as its inverse) and the solver's
+// wavelet steps (Algorithm 1 with grad -> W and div -> W^T).
+//
+// Filters (the paper does not print them): the orthonormal 4-tap Daubechies
+// pair h = (1 + s, 3 + s, 3 - s, 1 - s) / (4 sqrt 2), s = sqrt 3, and
+// g[k] = (-1)^k h[3 - k]; periodic analysis y[i] = sum_k c[k] x[(2i + k +
+// shift) mod n]. Tree a: (h, g), shift 0. Tree b: at level 1 (h, g) on the
+// signal advanced by one sample, from level 2 on the time-reversed pair with
+// shift 0. The 2-D transform runs the four trees (row tree, column tree) in
+// {a, b}^2, each recursing on its own lowpass band; per level the detail
+// bands of the trees combine into the oriented bands p, q, s, t (sums and
+// differences over sqrt 2), and everything carries a factor 1/2 so that
+// W^T W = I. Coefficient order: level-major, then orientation (LH, HL, HH),
+// then band (p, q, s, t), row-major inside a band; the level-J lowpass bands
+// of trees aa, ab, ba, bb at the end.
+//
+// One launch per level. Analysis: one thread per coefficient position of the
+// level reads the 4 x 4 input taps of each tree (cached loads; the level-1
+// input is the image shared by all trees), forms the 16 tree subbands and
+// writes the 12 oriented detail coefficients and the 4 lowpass values (the
+// next level's input, or the last level's lowpass coefficients). The
+// coefficients go out as W u (stand-alone), into the dual step
+// r <- clip(r + sigma c, -lam, lam) (the prox of the conjugate of
+// lam ||.||_1, Sec. 3.2), or into lam sum |c| (the gap's regulariser value).
+// Synthesis (W^T): one thread per input position of the level gathers the 2 x
+// 2 taps per tree that reach it from the level's subbands, undoing the band
+// combination on the fly.
+
+#include "pat_internal.hpp"
+
+namespace pat {
+
+namespace {
+
+// Filters of one level: [tree a, tree b] lowpass, highpass and shift.
+struct WavFilters {
+  double lo[2][4], hi[2][4];
+  int shift[2];
+  double kc;  // 1 / (2 sqrt 2): the band combination's 1/sqrt 2 times the frame's 1/2
+};
+
+WavFilters wav_filters(int level) {
+  const double s3 = std::sqrt(3.0), d = 4.0 * std::sqrt(2.0);
+  const double h[4] = {(1.0 + s3) / d, (3.0 + s3) / d, (3.0 - s3) / d, (1.0 - s3) / d};
+  WavFilters f{};
+  for (int t = 0; t < 2; ++t) {
+    const bool rev = t == 1 && level >= 2;
+    double c[4];
+    for (int k = 0; k < 4; ++k) c[k] = rev ? h[3 - k] : h[k];
+    for (int k = 0; k < 4; ++k) {
+      f.lo[t][k] = c[k];
+      f.hi[t][k] = (k % 2 ? -1.0 : 1.0) * c[3 - k];
+    }
+    f.shift[t] = (t == 1 && level == 1) ? 1 : 0;
+  }
+  f.kc = 0.5 / std::sqrt(2.0);
+  return f;
+}
+
+enum { WAV_PLAIN = 0, WAV_DUAL = 1, WAV_GAP = 2 };
+
+// One analysis level. Input grid cy x cx (the image at level 1, else the
+// previous level's four lowpass bands); output grid (cy/2) x (cx/2).
+template <class T, class A>
+struct WavAnaArgs {
+  int cx, cy;
+  const T* img;        // level 1: img[y * pitch + x]
+  int pitch;
+  const A* ll_in;      // levels >= 2: [4][cy][cx]
+  A* ll_out;           // not the last level: [4][cy/2][cx/2]
+  int64_t band_off;    // first detail band of the level in the coefficient vector
+  int64_t ll_off;      // last level: the lowpass bands; else -1
+  T* coef;             // PLAIN: W u
+  T* r;                // DUAL: the dual variable (coefficient order)
+  const T* sigma;      // DUAL: its step sizes
+  const double* mult;  // DUAL: {dual, primal, theta} multipliers or null
+  T lam;               // DUAL: clip bound; GAP: weight
+  double* red;         // GAP: one partial sum per workgroup
+  WavFilters f;
+};
+
+template <class T, class A, int MODE, bool FIRST>
+__global__ __launch_bounds__(256) void wav_analysis_kernel(WavAnaArgs<T, A> a) {
+  const int hx = a.cx >> 1, hy = a.cy >> 1;
+  const int64_t S = (int64_t)hx * hy;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double gap = 0.0;
+  if (e < S) {
+    const int ix = (int)(e % hx), iy = (int)(e / hx);
+    A sub[4][4];  // [tree aa, ab, ba, bb][LL, LH, HL, HH]
+    // level 1: the 5 x 5 patch at (2 iy, 2 ix) serves every tree (shifts 0, 1)
+    A patch[FIRST ? 5 : 1][FIRST ? 5 : 1];
+    if (FIRST) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        const int y = (2 * iy + k) % a.cy;
+#pragma unroll
+        for (int m = 0; m < 5; ++m) patch[k][m] = (A)a.img[(int64_t)y * a.pitch + (2 * ix + m) % a.cx];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int ty = t >> 1, tx = t & 1;
+      const int sy = a.f.shift[ty], sx = a.f.shift[tx];
+      A rl[4], rh[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        A x[4];
+        if (FIRST) {
+#pragma unroll
+          for (int m = 0; m < 4; ++m) x[m] = sy ? (sx ? patch[k + 1][m + 1] : patch[k + 1][m])
+                                                : (sx ? patch[k][m + 1] : patch[k][m]);
+        } else {
+          const A* in = a.ll_in + (int64_t)t * a.cx * a.cy + (int64_t)((2 * iy + k + sy) % a.cy) * a.cx;
+#pragma unroll
+          for (int m = 0; m < 4; ++m) x[m] = in[(2 * ix + m + sx) % a.cx];
+        }
+        A l = A(0), h = A(0);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          l += (A)a.f.lo[tx][m] * x[m];
+          h += (A)a.f.hi[tx][m] * x[m];
+        }
+        rl[k] = l;
+        rh[k] = h;
+      }
+      A ll = A(0), lh = A(0), hl = A(0), hh = A(0);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        ll += (A)a.f.lo[ty][k] * rl[k];
+        lh += (A)a.f.lo[ty][k] * rh[k];
+        hl += (A)a.f.hi[ty][k] * rl[k];
+        hh += (A)a.f.hi[ty][k] * rh[k];
+      }
+      sub[t][0] = ll;
+      sub[t][1] = lh;
+      sub[t][2] = hl;
+      sub[t][3] = hh;
+    }
+    auto emit = [&](int64_t idx, A v) {
+      if (MODE == WAV_PLAIN) {
+        a.coef[idx] = (T)v;
+      } else if (MODE == WAV_DUAL) {
+        const T sr = a.mult ? a.sigma[idx] * (T)a.mult[0] : a.sigma[idx];
+        const T rr = a.r[idx] + sr * (T)v;
+        a.r[idx] = rr > a.lam ? a.lam : (rr < -a.lam ? -a.lam : rr);
+      } else {
+        gap += fabs((double)v);
+      }
+    };
+    // oriented bands p = (aa - bb), q = (aa + bb), s = (ab + ba), t = (ab - ba),
+    // each over sqrt 2, times the frame factor 1/2
+    const A kc = (A)a.f.kc;
+#pragma unroll
+    for (int o = 0; o < 3; ++o) {
+      const A aa = sub[0][o + 1], ab = sub[1][o + 1], ba = sub[2][o + 1], bb = sub[3][o + 1];
+      const int64_t base = a.band_off + (int64_t)(4 * o) * S + e;
+      emit(base, kc * (aa - bb));
+      emit(base + S, kc * (aa + bb));
+      emit(base + 2 * S, kc * (ab + ba));
+      emit(base + 3 * S, kc * (ab - ba));
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (a.ll_off >= 0) emit(a.ll_off + t * S + e, A(0.5) * sub[t][0]);
+      else a.ll_out[t * S + e] = sub[t][0];
+    }
+  }
+  if (MODE == WAV_GAP) {
+    __shared__ double lds[8];
+    const double s = block_sum<256>(gap * (double)a.lam, lds);
+    if (threadIdx.x == 0) a.red[blockIdx.x] = s;
+  }
+}
+
+// One synthesis level: the level's subbands (grid (cy/2) x (cx/2)) back to
+// its input grid cy x cx.
+template <class T, class A>
+struct WavSynArgs {
+  int cx, cy;
+  const T* coef;       // the coefficient vector
+  int64_t band_off;    // first detail band of the level
+  int64_t ll_off;      // last level: the lowpass bands; else -1
+  const A* ll_in;      // not the last level: [4][cy/2][cx/2] (from the level above)
+  A* ll_out;           // levels >= 2: [4][cy][cx]
+  A* out;              // level 1: the image [cy][cx], summed over the trees
+  WavFilters f;
+};
+
+template <class T, class A>
+__global__ __launch_bounds__(256) void wav_synthesis_kernel(WavSynArgs<T, A> a) {
+  const int64_t n = (int64_t)a.cx * a.cy;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const int x = (int)(e % a.cx), y = (int)(e / a.cx);
+  const int hx = a.cx >> 1;
+  const int64_t S = (int64_t)hx * (a.cy >> 1);
+  const A kc = (A)a.f.kc;
+  A total = A(0);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int ty = t >> 1, tx = t & 1;
+    // the taps k that reach sample y are those with y - shift - k even, from
+    // position ((y - shift - k) mod cy) / 2 of the level
+    int ky[2], iy[2], kx[2], ix[2];
+    const int py = (y - a.f.shift[ty]) & 1, px = (x - a.f.shift[tx]) & 1;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      ky[u] = py + 2 * u;
+      iy[u] = (((y - a.f.shift[ty] - ky[u]) % a.cy + a.cy) % a.cy) >> 1;
+      kx[u] = px + 2 * u;
+      ix[u] = (((x - a.f.shift[tx] - kx[u]) % a.cx + a.cx) % a.cx) >> 1;
+    }
+    A acc = A(0);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const int64_t pos = (int64_t)iy[u] * hx + ix[v];
+        A sub[4];
+        sub[0] = a.ll_off >= 0 ? A(0.5) * (A)a.coef[a.ll_off + t * S + pos] : a.ll_in[t * S + pos];
+#pragma unroll
+        for (int o = 0; o < 3; ++o) {
+          const T* c = a.coef + a.band_off + (int64_t)(4 * o) * S + pos;
+          // tree t's share of the oriented bands (the transposed combination)
+          A val;
+          if (t == 0) val = (A)c[0] + (A)c[S];            // aa: p + q
+          else if (t == 3) val = (A)c[S] - (A)c[0];       // bb: q - p
+          else if (t == 1) val = (A)c[2 * S] + (A)c[3 * S];  // ab: s + t
+          else val = (A)c[2 * S] - (A)c[3 * S];           // ba: s - t
+          sub[o + 1] = kc * val;
+        }
+        const A ly = (A)a.f.lo[ty][ky[u]], hy = (A)a.f.hi[ty][ky[u]];
+        const A lx = (A)a.f.lo[tx][kx[v]], hx_ = (A)a.f.hi[tx][kx[v]];
+        acc += ly * (lx * sub[0] + hx_ * sub[1]) + hy * (lx * sub[2] + hx_ * sub[3]);
+      }
+    }
+    if (a.out) total += acc;
+    else a.ll_out[t * n + e] = acc;
+  }
+  if (a.out) a.out[e] = total;
+}
+
+inline int64_t band_size(int nx, int ny, int j) { return (int64_t)(nx >> j) * (ny >> j); }
+
+// Start of level j's detail bands (j = levels + 1: the lowpass bands).
+inline int64_t level_offset(int nx, int ny, int j) {
+  int64_t o = 0;
+  for (int l = 1; l < j; ++l) o += 12 * band_size(nx, ny, l);
+  return o;
+}
+
+// Lowpass bands of level l in the work buffer: odd levels at 0, even at N.
+template <class A>
+inline A* ll_region(A* work, int nx, int ny, int l) {
+  return (l & 1) ? work : work + (int64_t)nx * ny;
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+int64_t wav_work_elems(int nx, int ny) { return (int64_t)nx * ny + ((int64_t)nx * ny + 3) / 4; }
+
+int wav_gap_blocks(int nx, int ny, int levels) {
+  int b = 0;
+  for (int j = 1; j <= levels; ++j) b += (int)blocks_for(band_size(nx, ny, j));
+  return b;
+}
+
+template <class T, class A>
+static void analysis(int mode, const WavInput<T>& in, const WavDual<T>& d, A* work, hipStream_t s) {
+  const int nx = in.nx, ny = in.ny, J = in.levels;
+  double* red = d.red;
+  for (int j = 1; j <= J; ++j) {
+    WavAnaArgs<T, A> a{};
+    a.cx = nx >> (j - 1);
+    a.cy = ny >> (j - 1);
+    a.img = in.img;
+    a.pitch = in.pitch;
+    a.ll_in = j >= 2 ? ll_region(work, nx, ny, j - 1) : nullptr;
+    a.ll_out = j < J ? ll_region(work, nx, ny, j) : nullptr;
+    a.band_off = level_offset(nx, ny, j);
+    a.ll_off = j == J ? level_offset(nx, ny, J + 1) : -1;
+    a.coef = d.coef;
+    a.r = d.r;
+    a.sigma = d.sigma;
+    a.mult = d.mult;
+    a.lam = d.lam;
+    a.red = red;
+    a.f = wav_filters(j);
+    const unsigned grid = blocks_for(band_size(nx, ny, j));
+#define PAT_WAV_ANA(M, F) \
+  hipLaunchKernelGGL((wav_analysis_kernel<T, A, M, F>), dim3(grid), dim3(256), 0, s, a)
+    if (mode == WAV_PLAIN) { if (j == 1) PAT_WAV_ANA(WAV_PLAIN, true); else PAT_WAV_ANA(WAV_PLAIN, false); }
+    else if (mode == WAV_DUAL) { if (j == 1) PAT_WAV_ANA(WAV_DUAL, true); else PAT_WAV_ANA(WAV_DUAL, false); }
+    else { if (j == 1) PAT_WAV_ANA(WAV_GAP, true); else PAT_WAV_ANA(WAV_GAP, false); }
+#undef PAT_WAV_ANA
+    PAT_HIP(hipGetLastError());
+    if (red) red += grid;
+  }
+}
+
+template <class T, class A>
+static void synthesis(int nx, int ny, int J, const T* coef, A* out, A* work, hipStream_t s) {
+  for (int j = J; j >= 1; --j) {
+    WavSynArgs<T, A> a{};
+    a.cx = nx >> (j - 1);
+    a.cy = ny >> (j - 1);
+    a.coef = coef;
+    a.band_off = level_offset(nx, ny, j);
+    a.ll_off = j == J ? level_offset(nx, ny, J + 1) : -1;
+    a.ll_in = j < J ? ll_region(work, nx, ny, j) : nullptr;
+    a.ll_out = j >= 2 ? ll_region(work, nx, ny, j - 1) : nullptr;
+    a.out = j == 1 ? out : nullptr;
+    a.f = wav_filters(j);
+    hipLaunchKernelGGL((wav_synthesis_kernel<T, A>), dim3(blocks_for((int64_t)a.cx * a.cy)), dim3(256), 0, s, a);
+    PAT_HIP(hipGetLastError());
+  }
+}
+
+template <class T>
+void launch_wav_forward(const WavInput<T>& in, T* coef, T* work, hipStream_t s) {
+  WavDual<T> d{};
+  d.coef = coef;
+  analysis<T, T>(WAV_PLAIN, in, d, work, s);
+}
+
+template <class T>
+void launch_wav_dual(const WavInput<T>& in, const WavDual<T>& d, T* work, hipStream_t s) {
+  analysis<T, T>(WAV_DUAL, in, d, work, s);
+}
+
+template <class T>
+void launch_wav_gap(const WavInput<T>& in, T lam, double* red, double* work, hipStream_t s) {
+  WavDual<T> d{};
+  d.lam = lam;
+  d.red = red;
+  analysis<T, double>(WAV_GAP, in, d, work, s);
+}
+
+template <class T, class A>
+void launch_wav_adjoint(int nx, int ny, int levels, const T* coef, A* out, A* work, hipStream_t s) {
+  synthesis<T, A>(nx, ny, levels, coef, out, work, s);
+}
+
+#define PAT_INST_WAV(T)                                                                          \
+  template void launch_wav_forward<T>(const WavInput<T>&, T*, T*, hipStream_t);                 \
+  template void launch_wav_dual<T>(const WavInput<T>&, const WavDual<T>&, T*, hipStream_t);     \
+  template void launch_wav_gap<T>(const WavInput<T>&, T, double*, double*, hipStream_t);        \
+  template void launch_wav_adjoint<T, T>(int, int, int, const T*, T*, T*, hipStream_t);
+PAT_INST_WAV(float)
+PAT_INST_WAV(double)
+template void launch_wav_adjoint<float, double>(int, int, int, const float*, double*, double*, hipStream_t);
+
+void check_wavelet_shape(int nx, int ny, int levels) {
+  PAT_CHECK_ARG(levels >= 1 && levels <= kWavMaxLevels, "wavelet levels must be in 1..8");
+  PAT_CHECK_ARG(nx > 0 && ny > 0 && nx % (1 << levels) == 0 && ny % (1 << levels) == 0,
+                "the image sides must be positive multiples of 2^levels");
+}
+
+}  // namespace pat
+
+// ------------------------------------------------------------------ C ABI
+
+template <class T>
+static void wavelet_apply(bool adjoint, int nx, int ny, int levels, const void* in, void* out, hipStream_t s) {
+  pat::DevBuf work(sizeof(T) * (size_t)pat::wav_work_elems(nx, ny));
+  if (adjoint) {
+    pat::launch_wav_adjoint<T, T>(nx, ny, levels, static_cast<const T*>(in), static_cast<T*>(out),
+                                  pat::ptr<T>(work), s);
+  } else {
+    pat::WavInput<T> w{};
+    w.nx = nx;
+    w.ny = ny;
+    w.levels = levels;
+    w.img = static_cast<const T*>(in);
+    w.pitch = nx;
+    pat::launch_wav_forward<T>(w, static_cast<T*>(out), pat::ptr<T>(work), s);
+  }
+  // the work buffer is freed on return
+  PAT_HIP(hipStreamSynchronize(s));
+}
+
+static pat_status wavelet_entry(bool adjoint, int32_t dtype, int32_t nx, int32_t ny, int32_t levels,
+                                const void* in, void* out, void* stream) {
+  return pat::guarded([&]() -> pat_status {
+    PAT_CHECK_ARG(dtype == PAT_F32 || dtype == PAT_F64, "unknown dtype");
+    PAT_CHECK_ARG(in != nullptr && out != nullptr, "NULL argument");
+    pat::check_wavelet_shape(nx, ny, levels);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dtype == PAT_F64) wavelet_apply<double>(adjoint, nx, ny, levels, in, out, s);
+    else wavelet_apply<float>(adjoint, nx, ny, levels, in, out, s);
+    return PAT_OK;
+  });
+}
+
+extern "C" pat_status pat_wavelet_forward(int32_t dtype, int32_t nx, int32_t ny, int32_t levels,
+                                          const void* d_u, void* d_c, void* stream) {
+  return wavelet_entry(false, dtype, nx, ny, levels, d_u, d_c, stream);
+}
+
+extern "C" pat_status pat_wavelet_adjoint(int32_t dtype, int32_t nx, int32_t ny, int32_t levels,
+                                          const void* d_c, void* d_u, void* stream) {
+  return wavelet_entry(true, dtype, nx, ny, levels, d_c, d_u, stream);
+}

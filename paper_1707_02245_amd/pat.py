@@ -16,7 +16,7 @@ from . import _lib as L
 
 _DT = {torch.float32: L.PAT_F32, torch.float64: L.PAT_F64}
 _KIND = {"tv": L.PAT_REG_TV, "tgv": L.PAT_REG_TGV, "dtv": L.PAT_REG_DTV,
-         "tikhonov": L.PAT_REG_TIKHONOV, "lst": L.PAT_REG_TIKHONOV}
+         "tikhonov": L.PAT_REG_TIKHONOV, "lst": L.PAT_REG_TIKHONOV, "wav": L.PAT_REG_WAVELET}
 
 
 def _stream():
@@ -190,18 +190,21 @@ class Geometry:
 
 @dataclass
 class Reg:
-    """Regulariser: kind in tv | tgv | dtv | tikhonov."""
+    """Regulariser: kind in tv | tgv | dtv | tikhonov | wav (levels: the
+    wavelet transform's decomposition levels)."""
     kind: str
     lam: float
     alpha0: float = 0.0
     eta: float = 1.0
     theta: torch.Tensor | None = None
+    levels: int = 3
 
     def c_struct(self):
         r = L.Regulariser()
         r.kind = _KIND[self.kind]
         r.lam, r.tgv_alpha0, r.dtv_eta = self.lam, self.alpha0, self.eta
         r.d_dtv_theta = self.theta.data_ptr() if self.theta is not None else None
+        r.wav_levels = self.levels
         return r
 
 
@@ -226,6 +229,8 @@ class Precond:
         idx = ["sigma_q", "sigma_r", "sigma_s", "tau_u", "tau_v"].index(which)
         g = self.geom
         n = {0: g.n_det * g.n_t, 4: 2 * g.nx * g.ny}.get(idx, g.nx * g.ny)
+        if idx == 1 and self.reg.kind == "wav":
+            n = 4 * g.nx * g.ny
         out = torch.empty(n, dtype=g.dtype, device="cuda")
         L.check(L.load().pat_precond_get(self._h, idx, _ptr(out), _stream()))
         return out
@@ -344,6 +349,23 @@ def kernel_times(problems, reps=20, gap_every=50, graph_block=50):
     ms = (C.c_double * 4)()
     L.check(L.load().pat_pdhg_kernel_times(n, geoms, fs, regs, opts, reps, ms, _stream()))
     return dict(forward_dual_ms=ms[0], reg_dual_ms=ms[1], adjoint_ms=ms[2], primal_ms=ms[3])
+
+
+def wavelet_forward(u, levels):
+    """c = W u (pat_wavelet_forward): u a CUDA float tensor [ny][nx]; c [4 nx ny]."""
+    ny, nx = u.shape
+    _need(u, u.dtype, nx * ny, "u")
+    c = torch.empty(4 * nx * ny, dtype=u.dtype, device=u.device)
+    L.check(L.load().pat_wavelet_forward(_DT[u.dtype], nx, ny, levels, _ptr(u), _ptr(c), _stream()))
+    return c
+
+
+def wavelet_adjoint(c, nx, ny, levels):
+    """u = W^T c (pat_wavelet_adjoint): c a CUDA float tensor [4 nx ny]; u [ny][nx]."""
+    _need(c, c.dtype, 4 * nx * ny, "c")
+    u = torch.empty((ny, nx), dtype=c.dtype, device=c.device)
+    L.check(L.load().pat_wavelet_adjoint(_DT[c.dtype], nx, ny, levels, _ptr(c), _ptr(u), _stream()))
+    return u
 
 
 def psnr(u, u_gt):

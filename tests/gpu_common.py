@@ -66,7 +66,10 @@ def split_state(st, kind, N, nb):
     st = np.asarray(st, dtype=np.float64)
     out = {"u": st[:N], "ubar": st[N:2 * N], "q": st[2 * N:2 * N + nb]}
     o = 2 * N + nb
-    if kind != "tikhonov":
+    if kind == "wav":
+        out["r"] = st[o:o + 4 * N].reshape(1, 4 * N)
+        o += 4 * N
+    elif kind != "tikhonov":
         out["r"] = st[o:o + 2 * N].reshape(2, N)
         o += 2 * N
     if kind == "tgv":
@@ -77,7 +80,7 @@ def split_state(st, kind, N, nb):
     return out
 
 
-def oracle_problem(A, f, n, kind, lam, alpha0=0.0, eta=1.0, theta=None, ny=None):
+def oracle_problem(A, f, n, kind, lam, alpha0=0.0, eta=1.0, theta=None, ny=None, levels=3):
     ny = n if ny is None else ny
     return OP.Problem(A, f, n, ny, "lst" if kind == "tikhonov" else kind, lam,
-                      alpha0=alpha0, eta=eta, theta=theta)
+                      alpha0=alpha0, eta=eta, theta=theta, levels=levels)

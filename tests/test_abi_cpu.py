@@ -76,6 +76,19 @@ def test_null_handles_rejected():
     assert lib.pat_geometry_destroy(None) == L.PAT_OK
 
 
+def test_wavelet_transform_validation():
+    """pat_wavelet_forward / _adjoint reject bad shapes, levels, dtypes and
+    NULL pointers before any device work."""
+    L, lib = _lib()
+    x = C.c_void_p(256)  # never dereferenced: every case fails validation first
+    bad = [(1, 12, 8, 3, x, x), (1, 8, 8, 0, x, x), (1, 512, 512, 9, x, x), (1, 0, 8, 1, x, x),
+           (2, 8, 8, 1, x, x), (1, 8, 8, 1, None, x), (1, 8, 8, 1, x, None), (0, 8, 6, 2, x, x)]
+    for args in bad:
+        for fn in (lib.pat_wavelet_forward, lib.pat_wavelet_adjoint):
+            assert fn(*args, None) == L.PAT_ERR_INVALID_ARG, args
+            assert b"invalid argument" in lib.pat_last_error()
+
+
 STRUCTS = {
     "pat_geometry_desc": "GeometryDesc", "pat_geometry_info": "GeometryInfo",
     "pat_autotune_result": "AutotuneResult", "pat_regulariser": "Regulariser",
