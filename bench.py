@@ -93,8 +93,9 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--workload", default="tgv256", choices=["tgv256", "dtv512"],
-                   help="the timed reconstruction: 256^2 TGV (the headline) or 512^2 limited-angle dTV")
+    p.add_argument("--workload", default="tgv256", choices=["tgv256", "dtv512", "wav256"],
+                   help="the timed reconstruction: 256^2 TGV (the headline), 512^2 limited-angle dTV or "
+                        "256^2 dual-tree wavelet l1")
     p.add_argument("--steps", type=int, default=1)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--cap", type=int, default=100000,
@@ -115,6 +116,8 @@ def parse():
     p.add_argument("--no-extra-adjoints", action="store_true",
                    help="skip A^T at full storage (256^2) and at the 512^2 limited-angle workload")
     p.add_argument("--no-learned", action="store_true", help="skip the learned warm-start leg")
+    p.add_argument("--no-wavelet", action="store_true",
+                   help="skip the wavelet leg (transform at 4096^2, wavelet steps of the 256^2 iteration)")
     p.add_argument("--no-sweep", action="store_true", help="skip the uneven-size batched sweep leg")
     p.add_argument("--learned-seeds", type=int, default=2,
                    help="held-out phantoms of the learned warm-start leg")
@@ -356,6 +359,46 @@ def sweep_leg(pat, torch, args, n_groups=4, n_wl=4, iters=2000):
                 instance_iterations_per_s_sequential=n * iters / t_seq)
 
 
+def wavelet_bytes(nx, ny, levels, esz, dual=False):
+    """Algorithmic HBM bytes of one W (or W^T) by per-level launches: the
+    image, the 4 N coefficients, and the lowpass bands each level writes and
+    the next reads back; the solver's dual step reads and writes the
+    coefficients' dual variable instead of writing them."""
+    n = nx * ny
+    lowpass = sum(4 * (nx >> j) * (ny >> j) for j in range(1, levels))
+    return esz * (n + (8 if dual else 4) * n + 2 * lowpass)
+
+
+def wavelet_leg(pat, torch, g, f, args, n=4096, levels=3, reps=20):
+    """The wavelet transform alone at n^2 (FP64, a working set far beyond the
+    caches), W and W^T by their per-level launches with a caller's work
+    buffer, against the HBM roofline; and the wavelet steps of one solver
+    iteration of the 256^2 workload (pat_pdhg_kernel_times: the dual step in
+    the analysis and W^T r, beside the forward, A^T and primal launches)."""
+    tdt = torch.float64
+    u = torch.rand((n, n), dtype=tdt, device="cuda")
+    c = torch.empty(4 * n * n, dtype=tdt, device="cuda")
+    v = torch.empty((n, n), dtype=tdt, device="cuda")
+    work = pat.wavelet_work(n, n, tdt)
+    t_w = time_apply(lambda: pat.wavelet_forward(u, levels, out=c, work=work), reps, torch)
+    t_wt = time_apply(lambda: pat.wavelet_adjoint(c, n, n, levels, out=v, work=work), reps, torch)
+    b = wavelet_bytes(n, n, levels, 8)
+    out = dict(size=f"{n}x{n}", levels=levels, dtype="f64", bytes_per_transform=b,
+               forward_us=t_w * 1e6, adjoint_us=t_wt * 1e6,
+               forward_gbs=b / t_w * 1e-9, adjoint_gbs=b / t_wt * 1e-9,
+               forward_frac_of_hbm=b / t_w * 1e-9 / HBM_PEAK_GBS,
+               adjoint_frac_of_hbm=b / t_wt * 1e-9 / HBM_PEAK_GBS,
+               parseval_rel_err=abs(float(c.norm() / u.norm()) - 1.0))
+    del u, c, v, work
+    torch.cuda.empty_cache()
+    if g.dtype == tdt and g.nx % 8 == 0 and g.ny % 8 == 0:
+        reg = pat.Reg("wav", 0.01, levels=levels)
+        ms = pat.kernel_times([(g, f, reg)], reps=reps, gap_every=args.gap_every, graph_block=args.gap_every)
+        out["iteration_256"] = dict(forward_ms=ms["forward_dual_ms"], wavelet_steps_ms=ms["reg_dual_ms"],
+                                    adjoint_ms=ms["adjoint_ms"], primal_ms=ms["primal_ms"])
+    return out
+
+
 WEIGHTS = os.path.join(ROOT, "paper_1707_02245_amd", "weights", "warmstart_tv256.npy")
 
 
@@ -397,7 +440,7 @@ def learned_leg(pat, torch, g, args):
                 speedup_vs_backprojection=t_b / t_n)
 
 
-def cpu_baseline(desc, f, wl, gpu_iters, budget_s=20.0):
+def cpu_baseline(desc, f, wl, gpu_iters, theta=None, budget_s=20.0):
     """FP64 oracle on a bounded sample: PDHG steps of the oracle on the full
     image with the rows of A of a subset of detectors, the A / A^T part scaled
     to all detectors, times the iteration count the GPU needed."""
@@ -409,7 +452,8 @@ def cpu_baseline(desc, f, wl, gpu_iters, budget_s=20.0):
     A = OG.forward_matrix(OG.make_geometry(sub))
     t_build = time.perf_counter() - t0
     fs = np.asarray(f).reshape(wl.n_det, wl.n_t)[:n_sub].ravel()
-    p = OP.Problem(A, fs, wl.n, wl.n, "tgv", wl.lam, alpha0=wl.alpha0)
+    p = OP.Problem(A, fs, wl.n, wl.n, wl.reg, wl.lam, alpha0=wl.alpha0, eta=wl.eta, theta=theta,
+                   levels=wl.levels)
     pc = OP.precond_diag(p)
     st = OP.init_state(p)
     x = np.random.default_rng(0).standard_normal(A.shape[1])
@@ -435,8 +479,8 @@ def cpu_baseline(desc, f, wl, gpu_iters, budget_s=20.0):
     return dict(value=t_iter * gpu_iters, unit="s", cores=1, kind="oracle",
                 host_cores=host_cores, cpu_model=cpu_model,
                 sample=(f"FP64 oracle (SciPy CSR, single thread): {its} PDHG iterations of the "
-                        f"256^2 TGV workload with the rows of {n_sub} of 256 detectors plus "
-                        f"{reps} A/A^T applies of that subset, scaled to 256 detectors and to "
+                        f"{wl.name} workload with the rows of {n_sub} of {wl.n_det} detectors plus "
+                        f"{reps} A/A^T applies of that subset, scaled to {wl.n_det} detectors and to "
                         f"the GPU's {gpu_iters} iterations (extrapolated)"),
                 seconds_per_iteration=t_iter, build_s_subset=t_build)
 
@@ -463,6 +507,8 @@ def main():
     f = torch.tensor(f_np, dtype=tdt, device="cuda")
     if wl.reg == "dtv":
         reg = pat.Reg("dtv", wl.lam, 0.0, wl.eta, torch.tensor(case["theta"], dtype=tdt, device="cuda"))
+    elif wl.reg == "wav":
+        reg = pat.Reg("wav", wl.lam, levels=wl.levels)
     else:
         reg = pat.Reg(wl.reg, wl.lam, wl.alpha0)
     t0 = time.perf_counter()
@@ -604,7 +650,8 @@ def main():
                                 "on a closed circle of radius 1.2, 512 time samples (radii 0..2.4), "
                                 "DIAG step sizes, stop at relative box gap 1e-4 (C=2), gap every "
                                 f"{args.gap_every} iterations, cap {args.cap}") if wl.name == "tgv256" else
-                               (f"{wl.name} ({args.dtype}): {wl.n}x{wl.n} {wl.reg} (lambda {wl.lam}, eta {wl.eta}), "
+                               (f"{wl.name} ({args.dtype}): {wl.n}x{wl.n} {wl.reg} (lambda {wl.lam}, "
+                                f"{f'{wl.levels} levels' if wl.reg == 'wav' else f'eta {wl.eta}'}), "
                                 f"{wl.n_det} detectors over {math.degrees(wl.arc_span):.0f} degrees of a circle of "
                                 f"radius 1.2, {wl.n_t} time samples, {wl.family} phantom, DIAG step sizes, stop at "
                                 f"relative box gap 1e-4 (C=2), gap every {args.gap_every} iterations, cap {args.cap}"),
@@ -655,9 +702,14 @@ def main():
             log("learned leg: TV 256^2 from zero vs from the network start")
             out["learned"] = learned_leg(pat, torch, g, args)
             log(f"learned: {out['learned']}")
+    if not args.no_wavelet:
+        log("wavelet leg: W and W^T at 4096^2, wavelet steps of the 256^2 iteration")
+        out["wavelet"] = wavelet_leg(pat, torch, g, f, args)
+        log(f"wavelet: {out['wavelet']}")
     if not args.no_cpu:
         log("cpu baseline (oracle, bounded sample)")
-        out["cpu_baseline"] = cpu_baseline(desc, f_np, wl, iters)
+        out["cpu_baseline"] = cpu_baseline(desc, f_np, wl, iters,
+                                           theta=case["theta"] if wl.reg == "dtv" else None)
     print(json.dumps(out), flush=True)
     if args.calibrate_copy > 0:
         # known traffic: reads and writes calibrate_copy MiB per launch

@@ -301,13 +301,19 @@ typedef struct {
  *    the level-J lowpass bands of trees aa, ab, ba, bb.
  * pat_wavelet_forward: d_c = W d_u; pat_wavelet_adjoint: d_u = W^T d_c.
  * d_u: device [ny][nx], d_c: device [4 nx ny], element type `dtype`
- * (pat_dtype); arithmetic in the element type. Allocates a work buffer of
- * 1.25 nx ny elements per call. Validation: levels outside 1..8, nx or ny
- * not a positive multiple of 2^levels, NULL pointers -> PAT_ERR_INVALID_ARG. */
+ * (pat_dtype); arithmetic in the element type. d_work: device work buffer
+ * for the lowpass bands between levels, at least pat_wavelet_work_elems
+ * elements (nx ny + ceil(nx ny / 4)) of the element type, 16-byte aligned,
+ * owned by the caller
+ * (the call is then stream-ordered and allocates nothing); NULL: the call
+ * allocates one and returns once `stream` has finished. Validation: levels
+ * outside 1..8, nx or ny not a positive multiple of 2^levels, NULL d_u or
+ * d_c, unknown dtype -> PAT_ERR_INVALID_ARG. */
+int64_t pat_wavelet_work_elems(int32_t nx, int32_t ny);
 pat_status pat_wavelet_forward(int32_t dtype, int32_t nx, int32_t ny, int32_t levels,
-                               const void* d_u, void* d_c, void* stream);
+                               const void* d_u, void* d_c, void* d_work, void* stream);
 pat_status pat_wavelet_adjoint(int32_t dtype, int32_t nx, int32_t ny, int32_t levels,
-                               const void* d_c, void* d_u, void* stream);
+                               const void* d_c, void* d_u, void* d_work, void* stream);
 
 /* Step sizes (Sec. 3.3.2).
  *  DIAG : sigma_i = 1 / sum_j |K_ij|, tau_j = 1 / sum_i |K_ij| over the

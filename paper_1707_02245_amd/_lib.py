@@ -146,10 +146,11 @@ _SIGS = {
     "pat_preprocess": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "pat_psnr": ([C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
                   C.c_void_p], C.c_int),
+    "pat_wavelet_work_elems": ([C.c_int32, C.c_int32], C.c_int64),
     "pat_wavelet_forward": ([C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
-                             C.c_void_p], C.c_int),
+                             C.c_void_p, C.c_void_p], C.c_int),
     "pat_wavelet_adjoint": ([C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
-                             C.c_void_p], C.c_int),
+                             C.c_void_p, C.c_void_p], C.c_int),
     "pat_status_string": ([C.c_int], C.c_char_p),
     "pat_last_error": ([], C.c_char_p),
 }

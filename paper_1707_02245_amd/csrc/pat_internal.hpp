@@ -83,6 +83,9 @@ struct pat_precond_s {
   int reg_kind = 0;
   int kind = PAT_PRECOND_DIAG;
   double L1 = 0.0, L2 = 0.0;  // BLOCK mode norms
+  // WAVELET: every coefficient's dual step is this one value (DIAG 1, BLOCK
+  // sigma2); sigma_r holds it per coefficient for export only
+  double sigma_w = 1.0;
   pat::DevBuf sigma_q, sigma_r, sigma_s, tau_u, tau_v;
 };
 
@@ -260,7 +263,7 @@ template <class T>
 struct WavDual {
   T* coef;
   T* r;                // dual variable [4 N]
-  const T* sigma;      // its step sizes [4 N]
+  T sigma;             // its step size (one value for all coefficients)
   const double* mult;  // step multipliers of the accelerated schedule, or null
   T lam;
   double* red;         // gap: wav_gap_blocks partial sums

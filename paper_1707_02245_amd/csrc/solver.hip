@@ -140,6 +140,7 @@ static void precond_block(pat_precond_s* pc, const pat_regulariser* reg, const T
   const double tau = 1.0 / (2.0 * std::max(L1, L2));
   const double s1 = 0.99 / (4.0 * tau * L1 * L1);
   const double s2 = L2 > 0.0 ? 0.99 / (4.0 * tau * L2 * L2) : 1.0;
+  if (reg->kind == PAT_REG_WAVELET) pc->sigma_w = s2;
   launch_fill<T>(ptr<T>(pc->sigma_q), (T)s1, nb, s);
   launch_fill<T>(ptr<T>(pc->tau_u), (T)tau, N, s);
   if (pc->sigma_r.p) launch_fill<T>(ptr<T>(pc->sigma_r), (T)s2, (int64_t)(pc->sigma_r.bytes / sizeof(T)), s);
@@ -736,7 +737,7 @@ class Solver {
       if (I.reg.kind != PAT_REG_WAVELET) continue;
       WavDual<T> d{};
       d.r = ptr<T>(I.r);
-      d.sigma = ptr<T>(I.pc->sigma_r);
+      d.sigma = (T)I.pc->sigma_w;
       d.mult = I.accel ? ptr<double>(cur) + 3 * k : nullptr;
       d.lam = (T)I.reg.lambda;
       launch_wav_dual<T>(wav_input(I, I.ubar_pad), d, ptr<T>(I.wwork), s);

@@ -24,9 +24,11 @@
 // coefficients go out as W u (stand-alone), into the dual step
 // r <- clip(r + sigma c, -lam, lam) (the prox of the conjugate of
 // lam ||.||_1, Sec. 3.2), or into lam sum |c| (the gap's regulariser value).
-// Synthesis (W^T): one thread per input position of the level gathers the 2 x
-// 2 taps per tree that reach it from the level's subbands, undoing the band
-// combination on the fly.
+// Synthesis (W^T): one thread per coefficient position of the level reads the
+// 16 values of the positions whose taps reach its 2 x 2 block of input
+// samples (4 positions, 9 at level 1 where tree b is shifted), undoes the
+// band combination and writes the block for every tree (the image, summed
+// over the trees, at level 1).
 
 #include "pat_internal.hpp"
 
@@ -74,7 +76,7 @@ struct WavAnaArgs {
   int64_t ll_off;      // last level: the lowpass bands; else -1
   T* coef;             // PLAIN: W u
   T* r;                // DUAL: the dual variable (coefficient order)
-  const T* sigma;      // DUAL: its step sizes
+  T sigma;             // DUAL: its step size
   const double* mult;  // DUAL: {dual, primal, theta} multipliers or null
   T lam;               // DUAL: clip bound; GAP: weight
   double* red;         // GAP: one partial sum per workgroup
@@ -100,22 +102,34 @@ __global__ __launch_bounds__(256) void wav_analysis_kernel(WavAnaArgs<T, A> a) {
         for (int m = 0; m < 5; ++m) patch[k][m] = (A)a.img[(int64_t)y * a.pitch + (2 * ix + m) % a.cx];
       }
     }
+    // from level 2 on every shift is 0 and the four taps of a row are two
+    // aligned pairs unless they wrap around the right edge
+    const bool pairs = !FIRST && 2 * ix + 3 < a.cx;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int ty = t >> 1, tx = t & 1;
-      const int sy = a.f.shift[ty], sx = a.f.shift[tx];
+      const int sy = FIRST ? ty : 0, sx = FIRST ? tx : 0;
       A rl[4], rh[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         A x[4];
         if (FIRST) {
 #pragma unroll
-          for (int m = 0; m < 4; ++m) x[m] = sy ? (sx ? patch[k + 1][m + 1] : patch[k + 1][m])
-                                                : (sx ? patch[k][m + 1] : patch[k][m]);
+          for (int m = 0; m < 4; ++m) x[m] = patch[k + sy][m + sx];
         } else {
-          const A* in = a.ll_in + (int64_t)t * a.cx * a.cy + (int64_t)((2 * iy + k + sy) % a.cy) * a.cx;
+          const A* in = a.ll_in + (int64_t)t * a.cx * a.cy + (int64_t)((2 * iy + k) % a.cy) * a.cx;
+          if (pairs) {
+            using A2 = typename Vec2<A>::type;
+            const A2 p0 = *reinterpret_cast<const A2*>(in + 2 * ix);
+            const A2 p1 = *reinterpret_cast<const A2*>(in + 2 * ix + 2);
+            x[0] = p0.x;
+            x[1] = p0.y;
+            x[2] = p1.x;
+            x[3] = p1.y;
+          } else {
 #pragma unroll
-          for (int m = 0; m < 4; ++m) x[m] = in[(2 * ix + m + sx) % a.cx];
+            for (int m = 0; m < 4; ++m) x[m] = in[(2 * ix + m) % a.cx];
+          }
         }
         A l = A(0), h = A(0);
 #pragma unroll
@@ -139,33 +153,53 @@ __global__ __launch_bounds__(256) void wav_analysis_kernel(WavAnaArgs<T, A> a) {
       sub[t][2] = hl;
       sub[t][3] = hh;
     }
-    auto emit = [&](int64_t idx, A v) {
-      if (MODE == WAV_PLAIN) {
-        a.coef[idx] = (T)v;
-      } else if (MODE == WAV_DUAL) {
-        const T sr = a.mult ? a.sigma[idx] * (T)a.mult[0] : a.sigma[idx];
-        const T rr = a.r[idx] + sr * (T)v;
-        a.r[idx] = rr > a.lam ? a.lam : (rr < -a.lam ? -a.lam : rr);
-      } else {
-        gap += fabs((double)v);
-      }
-    };
-    // oriented bands p = (aa - bb), q = (aa + bb), s = (ab + ba), t = (ab - ba),
-    // each over sqrt 2, times the frame factor 1/2
+    // the coefficients of this position: oriented bands p = (aa - bb),
+    // q = (aa + bb), s = (ab + ba), t = (ab - ba), each over sqrt 2, times the
+    // frame factor 1/2; on the last level the four lowpass bands times 1/2
+    const bool last = a.ll_off >= 0;
     const A kc = (A)a.f.kc;
+    A val[16];
+    int64_t idx[16];
 #pragma unroll
     for (int o = 0; o < 3; ++o) {
       const A aa = sub[0][o + 1], ab = sub[1][o + 1], ba = sub[2][o + 1], bb = sub[3][o + 1];
       const int64_t base = a.band_off + (int64_t)(4 * o) * S + e;
-      emit(base, kc * (aa - bb));
-      emit(base + S, kc * (aa + bb));
-      emit(base + 2 * S, kc * (ab + ba));
-      emit(base + 3 * S, kc * (ab - ba));
+      val[4 * o] = kc * (aa - bb);
+      val[4 * o + 1] = kc * (aa + bb);
+      val[4 * o + 2] = kc * (ab + ba);
+      val[4 * o + 3] = kc * (ab - ba);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) idx[4 * o + b] = base + b * S;
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      if (a.ll_off >= 0) emit(a.ll_off + t * S + e, A(0.5) * sub[t][0]);
-      else a.ll_out[t * S + e] = sub[t][0];
+      val[12 + t] = A(0.5) * sub[t][0];
+      idx[12 + t] = a.ll_off + t * S + e;
+      if (!last) a.ll_out[t * S + e] = sub[t][0];
+    }
+    const int n_out = last ? 16 : 12;
+    if (MODE == WAV_PLAIN) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (k < n_out) a.coef[idx[k]] = (T)val[k];
+    } else if (MODE == WAV_DUAL) {
+      // every load of r before the first store, so that the loads overlap
+      const T sr = a.mult ? a.sigma * (T)a.mult[0] : a.sigma;
+      T rv[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (k < n_out) rv[k] = a.r[idx[k]];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        if (k < n_out) {
+          const T rr = rv[k] + sr * (T)val[k];
+          a.r[idx[k]] = rr > a.lam ? a.lam : (rr < -a.lam ? -a.lam : rr);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (k < n_out) gap += fabs((double)val[k]);
     }
   }
   if (MODE == WAV_GAP) {
@@ -189,58 +223,84 @@ struct WavSynArgs {
   WavFilters f;
 };
 
-template <class T, class A>
+// One thread per position (X, Y) of the level writes the 2 x 2 block of
+// samples (2Y + dy, 2X + dx) of its input grid. Tap k of the analysis at
+// position i reaches sample 2 i + k + shift, so sample 2Y + dy takes tap
+// k = 2 a + dy - shift from position Y - a (mod cy/2), for a = 0, 1 (and 2
+// when the shift is 1, at level 1), each valid k once: the positions of
+// offsets a, b in {0, 1, 2} hold every term. Their 16 values (12 oriented
+// detail bands, 4 lowpass) are read once per thread and turned back into the
+// trees' subbands (the transposed band combination).
+template <class T, class A, bool FIRST>
 __global__ __launch_bounds__(256) void wav_synthesis_kernel(WavSynArgs<T, A> a) {
-  const int64_t n = (int64_t)a.cx * a.cy;
+  const int hx = a.cx >> 1, hy = a.cy >> 1;
+  const int64_t S = (int64_t)hx * hy;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= n) return;
-  const int x = (int)(e % a.cx), y = (int)(e / a.cx);
-  const int hx = a.cx >> 1;
-  const int64_t S = (int64_t)hx * (a.cy >> 1);
+  if (e >= S) return;
+  const int X = (int)(e % hx), Y = (int)(e / hx);
   const A kc = (A)a.f.kc;
-  A total = A(0);
+  constexpr int NA = FIRST ? 3 : 2;
+  A acc[4][2][2];  // [tree][dy][dx]
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int ty = t >> 1, tx = t & 1;
-    // the taps k that reach sample y are those with y - shift - k even, from
-    // position ((y - shift - k) mod cy) / 2 of the level
-    int ky[2], iy[2], kx[2], ix[2];
-    const int py = (y - a.f.shift[ty]) & 1, px = (x - a.f.shift[tx]) & 1;
+  for (int t = 0; t < 4; ++t)
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      ky[u] = py + 2 * u;
-      iy[u] = (((y - a.f.shift[ty] - ky[u]) % a.cy + a.cy) % a.cy) >> 1;
-      kx[u] = px + 2 * u;
-      ix[u] = (((x - a.f.shift[tx] - kx[u]) % a.cx + a.cx) % a.cx) >> 1;
-    }
-    A acc = A(0);
+    for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
+      for (int dx = 0; dx < 2; ++dx) acc[t][dy][dx] = A(0);
 #pragma unroll
-      for (int v = 0; v < 2; ++v) {
-        const int64_t pos = (int64_t)iy[u] * hx + ix[v];
-        A sub[4];
-        sub[0] = a.ll_off >= 0 ? A(0.5) * (A)a.coef[a.ll_off + t * S + pos] : a.ll_in[t * S + pos];
+  for (int ay = 0; ay < NA; ++ay) {
+    const int iy = (Y - ay + hy) % hy;
 #pragma unroll
-        for (int o = 0; o < 3; ++o) {
-          const T* c = a.coef + a.band_off + (int64_t)(4 * o) * S + pos;
-          // tree t's share of the oriented bands (the transposed combination)
-          A val;
-          if (t == 0) val = (A)c[0] + (A)c[S];            // aa: p + q
-          else if (t == 3) val = (A)c[S] - (A)c[0];       // bb: q - p
-          else if (t == 1) val = (A)c[2 * S] + (A)c[3 * S];  // ab: s + t
-          else val = (A)c[2 * S] - (A)c[3 * S];           // ba: s - t
-          sub[o + 1] = kc * val;
+    for (int ax = 0; ax < NA; ++ax) {
+      const int ix = (X - ax + hx) % hx;
+      const int64_t pos = (int64_t)iy * hx + ix;
+      A sub[4][4];  // [tree][LL, LH, HL, HH]
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        sub[t][0] = a.ll_off >= 0 ? A(0.5) * (A)a.coef[a.ll_off + t * S + pos] : a.ll_in[t * S + pos];
+#pragma unroll
+      for (int o = 0; o < 3; ++o) {
+        const T* c = a.coef + a.band_off + (int64_t)(4 * o) * S + pos;
+        const A p = (A)c[0], q = (A)c[S], s = (A)c[2 * S], u = (A)c[3 * S];
+        sub[0][o + 1] = kc * (p + q);  // aa
+        sub[1][o + 1] = kc * (s + u);  // ab
+        sub[2][o + 1] = kc * (s - u);  // ba
+        sub[3][o + 1] = kc * (q - p);  // bb
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int ty = t >> 1, tx = t & 1;
+        const int sy = FIRST ? ty : 0, sx = FIRST ? tx : 0;
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+          const int ky = 2 * ay + dy - sy;
+          if (ky < 0 || ky > 3) continue;
+          const A ly = (A)a.f.lo[ty][ky], gy = (A)a.f.hi[ty][ky];
+#pragma unroll
+          for (int dx = 0; dx < 2; ++dx) {
+            const int kx = 2 * ax + dx - sx;
+            if (kx < 0 || kx > 3) continue;
+            const A lx = (A)a.f.lo[tx][kx], gx = (A)a.f.hi[tx][kx];
+            acc[t][dy][dx] += ly * (lx * sub[t][0] + gx * sub[t][1]) + gy * (lx * sub[t][2] + gx * sub[t][3]);
+          }
         }
-        const A ly = (A)a.f.lo[ty][ky[u]], hy = (A)a.f.hi[ty][ky[u]];
-        const A lx = (A)a.f.lo[tx][kx[v]], hx_ = (A)a.f.hi[tx][kx[v]];
-        acc += ly * (lx * sub[0] + hx_ * sub[1]) + hy * (lx * sub[2] + hx_ * sub[3]);
       }
     }
-    if (a.out) total += acc;
-    else a.ll_out[t * n + e] = acc;
   }
-  if (a.out) a.out[e] = total;
+  const int64_t n = (int64_t)a.cx * a.cy;
+#pragma unroll
+  for (int dy = 0; dy < 2; ++dy) {
+    const int64_t row = (int64_t)(2 * Y + dy) * a.cx + 2 * X;
+#pragma unroll
+    for (int dx = 0; dx < 2; ++dx) {
+      if (FIRST) {
+        a.out[row + dx] = (acc[0][dy][dx] + acc[1][dy][dx]) + (acc[2][dy][dx] + acc[3][dy][dx]);
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) a.ll_out[t * n + row + dx] = acc[t][dy][dx];
+      }
+    }
+  }
 }
 
 inline int64_t band_size(int nx, int ny, int j) { return (int64_t)(nx >> j) * (ny >> j); }
@@ -316,7 +376,9 @@ static void synthesis(int nx, int ny, int J, const T* coef, A* out, A* work, hip
     a.ll_out = j >= 2 ? ll_region(work, nx, ny, j - 1) : nullptr;
     a.out = j == 1 ? out : nullptr;
     a.f = wav_filters(j);
-    hipLaunchKernelGGL((wav_synthesis_kernel<T, A>), dim3(blocks_for((int64_t)a.cx * a.cy)), dim3(256), 0, s, a);
+    const unsigned grid = blocks_for(band_size(nx, ny, j));
+    if (j == 1) hipLaunchKernelGGL((wav_synthesis_kernel<T, A, true>), dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((wav_synthesis_kernel<T, A, false>), dim3(grid), dim3(256), 0, s, a);
     PAT_HIP(hipGetLastError());
   }
 }
@@ -366,43 +428,48 @@ void check_wavelet_shape(int nx, int ny, int levels) {
 // ------------------------------------------------------------------ C ABI
 
 template <class T>
-static void wavelet_apply(bool adjoint, int nx, int ny, int levels, const void* in, void* out, hipStream_t s) {
-  pat::DevBuf work(sizeof(T) * (size_t)pat::wav_work_elems(nx, ny));
-  if (adjoint) {
-    pat::launch_wav_adjoint<T, T>(nx, ny, levels, static_cast<const T*>(in), static_cast<T*>(out),
-                                  pat::ptr<T>(work), s);
-  } else {
-    pat::WavInput<T> w{};
-    w.nx = nx;
-    w.ny = ny;
-    w.levels = levels;
-    w.img = static_cast<const T*>(in);
-    w.pitch = nx;
-    pat::launch_wav_forward<T>(w, static_cast<T*>(out), pat::ptr<T>(work), s);
+static void wavelet_apply(bool adjoint, int nx, int ny, int levels, const void* in, void* out, void* d_work,
+                          hipStream_t s) {
+  pat::DevBuf own;
+  T* work = static_cast<T*>(d_work);
+  if (!work) {
+    own.alloc(sizeof(T) * (size_t)pat::wav_work_elems(nx, ny));
+    work = pat::ptr<T>(own);
   }
-  // the work buffer is freed on return
-  PAT_HIP(hipStreamSynchronize(s));
+  if (adjoint) {
+    pat::launch_wav_adjoint<T, T>(nx, ny, levels, static_cast<const T*>(in), static_cast<T*>(out), work, s);
+  } else {
+    const pat::WavInput<T> w{nx, ny, levels, static_cast<const T*>(in), nx};
+    pat::launch_wav_forward<T>(w, static_cast<T*>(out), work, s);
+  }
+  // a work buffer of the call's own is freed on return
+  if (own.p) PAT_HIP(hipStreamSynchronize(s));
 }
 
 static pat_status wavelet_entry(bool adjoint, int32_t dtype, int32_t nx, int32_t ny, int32_t levels,
-                                const void* in, void* out, void* stream) {
+                                const void* in, void* out, void* d_work, void* stream) {
   return pat::guarded([&]() -> pat_status {
     PAT_CHECK_ARG(dtype == PAT_F32 || dtype == PAT_F64, "unknown dtype");
     PAT_CHECK_ARG(in != nullptr && out != nullptr, "NULL argument");
+    PAT_CHECK_ARG((reinterpret_cast<uintptr_t>(d_work) & 15) == 0, "d_work must be 16-byte aligned");
     pat::check_wavelet_shape(nx, ny, levels);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (dtype == PAT_F64) wavelet_apply<double>(adjoint, nx, ny, levels, in, out, s);
-    else wavelet_apply<float>(adjoint, nx, ny, levels, in, out, s);
+    if (dtype == PAT_F64) wavelet_apply<double>(adjoint, nx, ny, levels, in, out, d_work, s);
+    else wavelet_apply<float>(adjoint, nx, ny, levels, in, out, d_work, s);
     return PAT_OK;
   });
 }
 
+extern "C" int64_t pat_wavelet_work_elems(int32_t nx, int32_t ny) {
+  return nx > 0 && ny > 0 ? pat::wav_work_elems(nx, ny) : 0;
+}
+
 extern "C" pat_status pat_wavelet_forward(int32_t dtype, int32_t nx, int32_t ny, int32_t levels,
-                                          const void* d_u, void* d_c, void* stream) {
-  return wavelet_entry(false, dtype, nx, ny, levels, d_u, d_c, stream);
+                                          const void* d_u, void* d_c, void* d_work, void* stream) {
+  return wavelet_entry(false, dtype, nx, ny, levels, d_u, d_c, d_work, stream);
 }
 
 extern "C" pat_status pat_wavelet_adjoint(int32_t dtype, int32_t nx, int32_t ny, int32_t levels,
-                                          const void* d_c, void* d_u, void* stream) {
-  return wavelet_entry(true, dtype, nx, ny, levels, d_c, d_u, stream);
+                                          const void* d_c, void* d_u, void* d_work, void* stream) {
+  return wavelet_entry(true, dtype, nx, ny, levels, d_c, d_u, d_work, stream);
 }

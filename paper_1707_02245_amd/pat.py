@@ -351,20 +351,34 @@ def kernel_times(problems, reps=20, gap_every=50, graph_block=50):
     return dict(forward_dual_ms=ms[0], reg_dual_ms=ms[1], adjoint_ms=ms[2], primal_ms=ms[3])
 
 
-def wavelet_forward(u, levels):
-    """c = W u (pat_wavelet_forward): u a CUDA float tensor [ny][nx]; c [4 nx ny]."""
+def wavelet_work(nx, ny, dtype):
+    """A work buffer for the wavelet transform calls (pat_wavelet_work_elems)."""
+    return torch.empty(L.load().pat_wavelet_work_elems(nx, ny), dtype=dtype, device="cuda")
+
+
+def wavelet_forward(u, levels, out=None, work=None):
+    """c = W u (pat_wavelet_forward): u a CUDA float tensor [ny][nx]; c [4 nx ny].
+    work: optional buffer from wavelet_work (else the call allocates and waits)."""
     ny, nx = u.shape
     _need(u, u.dtype, nx * ny, "u")
-    c = torch.empty(4 * nx * ny, dtype=u.dtype, device=u.device)
-    L.check(L.load().pat_wavelet_forward(_DT[u.dtype], nx, ny, levels, _ptr(u), _ptr(c), _stream()))
+    c = torch.empty(4 * nx * ny, dtype=u.dtype, device=u.device) if out is None else out
+    _need(c, u.dtype, 4 * nx * ny, "out")
+    if work is not None:
+        _need(work, u.dtype, L.load().pat_wavelet_work_elems(nx, ny), "work")
+    L.check(L.load().pat_wavelet_forward(_DT[u.dtype], nx, ny, levels, _ptr(u), _ptr(c), _ptr(work),
+                                         _stream()))
     return c
 
 
-def wavelet_adjoint(c, nx, ny, levels):
+def wavelet_adjoint(c, nx, ny, levels, out=None, work=None):
     """u = W^T c (pat_wavelet_adjoint): c a CUDA float tensor [4 nx ny]; u [ny][nx]."""
     _need(c, c.dtype, 4 * nx * ny, "c")
-    u = torch.empty((ny, nx), dtype=c.dtype, device=c.device)
-    L.check(L.load().pat_wavelet_adjoint(_DT[c.dtype], nx, ny, levels, _ptr(c), _ptr(u), _stream()))
+    u = torch.empty((ny, nx), dtype=c.dtype, device=c.device) if out is None else out
+    _need(u, c.dtype, nx * ny, "out")
+    if work is not None:
+        _need(work, c.dtype, L.load().pat_wavelet_work_elems(nx, ny), "work")
+    L.check(L.load().pat_wavelet_adjoint(_DT[c.dtype], nx, ny, levels, _ptr(c), _ptr(u), _ptr(work),
+                                         _stream()))
     return u
 
 

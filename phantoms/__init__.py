@@ -65,10 +65,11 @@ class Workload:
     n_t: int               # time samples; radii 0 .. 2.4 inclusive
     family: str            # phantom family
     noise: float           # relative L2 noise level
-    reg: str               # "tv" | "tgv" | "dtv"
-    lam: float             # TV / dTV weight, TGV first-order weight alpha1
+    reg: str               # "tv" | "tgv" | "dtv" | "wav"
+    lam: float             # TV / dTV / wavelet weight, TGV first-order weight alpha1
     alpha0: float = 0.0    # TGV second-order weight
     eta: float = 1.0       # dTV anisotropy
+    levels: int = 3        # wavelet decomposition levels
     iters: int = 0         # fixed iteration count (0: run to gap_tol)
     gap_tol: float = 1e-4
     max_iter: int = 2000
@@ -88,6 +89,10 @@ WORKLOADS = {
     "dtv512": Workload("dtv512", 512, 128, 0.5 * math.pi, 1024, "segment", 0.05,
                        "dtv", 0.02, eta=0.1, gap_tol=1e-4, max_iter=2000,
                        seeds=tuple(range(200, 210))),
+    # 256^2 dual-tree wavelet l1 (3 levels), geometry of tgv256, vascular
+    # phantom (the paper's wavelet experiment reconstructs a vascular image).
+    "wav256": Workload("wav256", 256, 256, 2 * math.pi, 512, "vessel", 0.05, "wav", 0.003,
+                       gap_tol=1e-4, max_iter=2000, dtype="f64", seeds=tuple(range(300, 310))),
     # 256^2 TV, geometry of tgv256: the warm-start workload.
     "tv256": Workload("tv256", 256, 256, 2 * math.pi, 512, "mixed", 0.05, "tv", 0.02,
                       gap_tol=1e-4, max_iter=2000, seeds=tuple(range(50000, 50512))),

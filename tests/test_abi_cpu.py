@@ -85,8 +85,11 @@ def test_wavelet_transform_validation():
            (2, 8, 8, 1, x, x), (1, 8, 8, 1, None, x), (1, 8, 8, 1, x, None), (0, 8, 6, 2, x, x)]
     for args in bad:
         for fn in (lib.pat_wavelet_forward, lib.pat_wavelet_adjoint):
-            assert fn(*args, None) == L.PAT_ERR_INVALID_ARG, args
+            assert fn(*args, x, None) == L.PAT_ERR_INVALID_ARG, args
             assert b"invalid argument" in lib.pat_last_error()
+    assert lib.pat_wavelet_work_elems(8, 8) == 64 + 16
+    assert lib.pat_wavelet_work_elems(6, 2) == 12 + 3
+    assert lib.pat_wavelet_work_elems(0, 8) == 0
 
 
 STRUCTS = {

@@ -50,6 +50,13 @@ def test_transform_and_adjoint_match_the_oracle(shape, dt):
     cin = rng.standard_normal(4 * nx * ny)
     v = pat.wavelet_adjoint(to_dev(cin, DT[dt]), nx, ny, J)
     _check(host(v), W.T @ cin, dt)
+    # with a caller's work buffer (stream-ordered, nothing allocated): the
+    # same bits, twice in a row through the same buffer
+    work = pat.wavelet_work(nx, ny, DT[dt])
+    for _ in range(2):
+        c2 = pat.wavelet_forward(to_dev(u, DT[dt]), J, work=work)
+        v2 = pat.wavelet_adjoint(to_dev(cin, DT[dt]), nx, ny, J, work=work)
+        assert np.array_equal(host(c2), host(c)) and np.array_equal(host(v2), host(v))
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
@@ -169,6 +176,25 @@ def test_fixed_iterations_full_state(name, J, dt):
     assert np.abs(got["r"]).max() <= lam * (1 + 1e-6)
     assert np.abs(got["r"]).max() >= 0.999 * lam
     _gap_terms_agree(info, p, ref, dt)
+
+
+def test_block_steps_fixed_iterations():
+    """The two-block scalar steps (L2 = ||W|| by power iteration, sigma2 for
+    every coefficient) for 60 iterations against the oracle's."""
+    og, g = _geoms("rect48", "f64")
+    A, f = _data(og, 10)
+    p = oracle_problem(A, f, og.nx, "wav", 0.01, ny=og.ny, levels=3)
+    pcr = OP.precond_block(p)
+    assert pcr["L2"] == pytest.approx(1.05, rel=1e-9)  # ||W|| = 1 times the safety factor
+    ref = OP.pdhg_solve(p, pcr, iters=60)
+    reg = pat.Reg("wav", 0.01, levels=3)
+    pc = pat.Precond(g, reg, "block")
+    st = torch.zeros(g.state_elems("wav"), dtype=torch.float64, device="cuda")
+    _, info, _ = pat.solve(g, to_dev(f, torch.float64), reg, max_iter=60, gap_tol=0.0, gap_every=10,
+                           graph_block=20, state_out=st, precond=pc)
+    got = split_state(host(st), "wav", og.n_pix, og.n_bins)
+    for key in ("u", "ubar", "q", "r"):
+        assert rel(got[key], ref[key]) <= 1e-8, key
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
