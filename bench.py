@@ -107,8 +107,9 @@ def parse():
     p.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     p.add_argument("--no-batched", action="store_true", help="skip the batched leg")
     p.add_argument("--no-plain", action="store_true", help="skip the constant-step (plain PDHGM) leg")
-    p.add_argument("--accel-gamma", type=float, default=1.0,
-                   help="the timed solve's accelerated schedule: gamma (0: constant steps)")
+    p.add_argument("--accel-gamma", type=float, default=None,
+                   help="the timed solve's accelerated schedule: gamma (0: constant steps); default 1 on "
+                        "tgv256, where it is faster, and constant steps on dtv512 and wav256, where it is not")
     p.add_argument("--accel-step-max", type=float, default=8.0,
                    help="the timed solve's accelerated schedule: bound on the growth of the dual steps")
     p.add_argument("--no-fused", action="store_true",
@@ -124,7 +125,10 @@ def parse():
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="after the JSON line, stream MIB MiB through a plain elementwise copy "
                         "(3 launches) as the reference for hardware byte counters")
-    return p.parse_args()
+    a = p.parse_args()
+    if a.accel_gamma is None:
+        a.accel_gamma = 1.0 if a.workload == "tgv256" else 0.0
+    return a
 
 
 def log(msg):
