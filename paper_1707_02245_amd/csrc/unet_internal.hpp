@@ -1,6 +1,7 @@
 // Internal definitions of the warm-start network kernels.
 #pragma once
 
+#include "fastdiv.hpp"
 #include "pat_internal.hpp"
 
 namespace pat {
@@ -11,6 +12,15 @@ struct View {
   const uint16_t* p = nullptr;
   uint16_t* p16 = nullptr;
   int H = 0, W = 0, C = 0, pitch = 0, off = 0;
+  // divisions by C, W, H, W/2 and H/2 in the kernels (set by prep_div)
+  FastDiv dC, dW, dH, dW2, dH2;
+  void prep_div() {
+    dC = make_fastdiv((uint32_t)C);
+    dW = make_fastdiv((uint32_t)W);
+    dH = make_fastdiv((uint32_t)H);
+    dW2 = make_fastdiv((uint32_t)(W / 2));
+    dH2 = make_fastdiv((uint32_t)(H / 2));
+  }
 };
 
 inline View view(uint16_t* base, int H, int W, int C, int pitch, int off) {

@@ -10,8 +10,10 @@
 // The GEMM computes C[m][n] = sum_k A(m,k) B(n,k). A and B are fetched
 // element-wise through index maps (direct, 3x3 im2col with +/- tap offsets,
 // 2x2 sub-pixel gathers, transposed views), staged through LDS in 32-wide k
-// chunks and multiplied with __builtin_amdgcn_mfma_f32_16x16x16bf16_1k: lane
-// l supplies A[l%16][4(l/16)+r] and B[4(l/16)+r][l%16] and receives
+// chunks and multiplied with the gfx950 instruction
+// __builtin_amdgcn_mfma_f32_16x16x32_bf16: lane l supplies A[l%16][8(l/16)+j]
+// and B[8(l/16)+j][l%16], j = 0..7 (one 16-byte LDS read per operand; any
+// grouping of k that A and B share gives the same product), and receives
 // D[4(l/16)+r][l%16], r = 0..3.
 
 #include <climits>
@@ -21,7 +23,7 @@
 namespace pat {
 namespace nn {
 
-typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
@@ -29,6 +31,23 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
   uint32_t u = __float_as_uint(f);
   u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
   return (uint16_t)(u >> 16);
+}
+
+// Pixel index -> (batch, row, column) of a view, and a 3x3 tap index -> offsets.
+__device__ __forceinline__ void pix_split(int m, const FastDiv& dw, const FastDiv& dh, int& b, int& y, int& x) {
+  uint32_t t, r;
+  fast_divmod((uint32_t)m, dw, t, r);
+  x = (int)r;
+  uint32_t bb, yy;
+  fast_divmod(t, dh, bb, yy);
+  y = (int)yy;
+  b = (int)bb;
+}
+__device__ __forceinline__ void chan_split(int k, const FastDiv& dc, int& tap, int& c) {
+  uint32_t q, r;
+  fast_divmod((uint32_t)k, dc, q, r);
+  tap = (int)q;
+  c = (int)r;
 }
 
 // ------------------------------------------------------------------ operand fetch
@@ -40,26 +59,27 @@ __device__ __forceinline__ uint16_t fetch_a(const GemmDesc& d, int m, int k) {
     case A_DIRECT:
       return v.p[(int64_t)m * v.pitch + v.off + k];
     case A_CONV: {
-      const int tap = k / v.C, c = k - tap * v.C;
+      int tap, c, b, y, x;
+      chan_split(k, v.dC, tap, c);
       const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-      const int x = m % v.W, t = m / v.W, y = t % v.H, b = t / v.H;
+      pix_split(m, v.dW, v.dH, b, y, x);
       const int yy = y + d.a_sign * dy, xx = x + d.a_sign * dx;
       if (yy < 0 || yy >= v.H || xx < 0 || xx >= v.W) return 0;
       return v.p[((int64_t)(b * v.H + yy) * v.W + xx) * v.pitch + v.off + c];
     }
     case A_G22: {  // m: low-res pixel on (H/2, W/2); k = sub * C + c; source at full res
-      const int sub = k / v.C, c = k - sub * v.C;
-      const int w2 = v.W >> 1, h2 = v.H >> 1;
-      const int x = m % w2, t = m / w2, y = t % h2, b = t / h2;
+      int sub, c, b, y, x;
+      chan_split(k, v.dC, sub, c);
+      pix_split(m, v.dW2, v.dH2, b, y, x);
       const int yy = 2 * y + (sub >> 1), xx = 2 * x + (sub & 1);
       return v.p[((int64_t)(b * v.H + yy) * v.W + xx) * v.pitch + v.off + c];
     }
     case A_T:  // m = channel, k = pixel
       return v.p[(int64_t)k * v.pitch + v.off + m];
     case A_TG22: {  // m = sub * C + c, k = low-res pixel; source at full res
-      const int sub = m / v.C, c = m - sub * v.C;
-      const int w2 = v.W >> 1, h2 = v.H >> 1;
-      const int x = k % w2, t = k / w2, y = t % h2, b = t / h2;
+      int sub, c, b, y, x;
+      chan_split(m, v.dC, sub, c);
+      pix_split(k, v.dW2, v.dH2, b, y, x);
       const int yy = 2 * y + (sub >> 1), xx = 2 * x + (sub & 1);
       return v.p[((int64_t)(b * v.H + yy) * v.W + xx) * v.pitch + v.off + c];
     }
@@ -74,9 +94,10 @@ __device__ __forceinline__ uint16_t fetch_b(const GemmDesc& d, int n, int k) {
     case B_W:
       return d.w[(int64_t)n * d.K + k];
     case B_IM2COL: {  // n = tap * C + c, k = pixel
-      const int tap = n / v.C, c = n - tap * v.C;
+      int tap, c, b, y, x;
+      chan_split(n, v.dC, tap, c);
       const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-      const int x = k % v.W, t = k / v.W, y = t % v.H, b = t / v.H;
+      pix_split(k, v.dW, v.dH, b, y, x);
       const int yy = y + dy, xx = x + dx;
       if (yy < 0 || yy >= v.H || xx < 0 || xx >= v.W) return 0;
       return v.p[((int64_t)(b * v.H + yy) * v.W + xx) * v.pitch + v.off + c];
@@ -96,26 +117,27 @@ __device__ __forceinline__ const uint16_t* addr8_a(const GemmDesc& d, int m, int
     case A_DIRECT:
       return v.p + (int64_t)m * v.pitch + v.off + k;
     case A_CONV: {
-      const int tap = k / v.C, c = k - tap * v.C;
+      int tap, c, b, y, x;
+      chan_split(k, v.dC, tap, c);
       const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-      const int x = m % v.W, t = m / v.W, y = t % v.H, b = t / v.H;
+      pix_split(m, v.dW, v.dH, b, y, x);
       const int yy = y + d.a_sign * dy, xx = x + d.a_sign * dx;
       if (yy < 0 || yy >= v.H || xx < 0 || xx >= v.W) return nullptr;
       return v.p + ((int64_t)(b * v.H + yy) * v.W + xx) * v.pitch + v.off + c;
     }
     case A_G22: {
-      const int sub = k / v.C, c = k - sub * v.C;
-      const int w2 = v.W >> 1, h2 = v.H >> 1;
-      const int x = m % w2, t = m / w2, y = t % h2, b = t / h2;
+      int sub, c, b, y, x;
+      chan_split(k, v.dC, sub, c);
+      pix_split(m, v.dW2, v.dH2, b, y, x);
       const int yy = 2 * y + (sub >> 1), xx = 2 * x + (sub & 1);
       return v.p + ((int64_t)(b * v.H + yy) * v.W + xx) * v.pitch + v.off + c;
     }
     case A_T:
       return v.p + (int64_t)k * v.pitch + v.off + m;
     case A_TG22: {
-      const int sub = m / v.C, c = m - sub * v.C;
-      const int w2 = v.W >> 1, h2 = v.H >> 1;
-      const int x = k % w2, t = k / w2, y = t % h2, b = t / h2;
+      int sub, c, b, y, x;
+      chan_split(m, v.dC, sub, c);
+      pix_split(k, v.dW2, v.dH2, b, y, x);
       const int yy = 2 * y + (sub >> 1), xx = 2 * x + (sub & 1);
       return v.p + ((int64_t)(b * v.H + yy) * v.W + xx) * v.pitch + v.off + c;
     }
@@ -129,9 +151,10 @@ __device__ __forceinline__ const uint16_t* addr8_b(const GemmDesc& d, int n, int
     case B_W:
       return d.w + (int64_t)n * d.K + k;
     case B_IM2COL: {
-      const int tap = n / v.C, c = n - tap * v.C;
+      int tap, c, b, y, x;
+      chan_split(n, v.dC, tap, c);
       const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-      const int x = k % v.W, t = k / v.W, y = t % v.H, b = t / v.H;
+      pix_split(k, v.dW, v.dH, b, y, x);
       const int yy = y + dy, xx = x + dx;
       if (yy < 0 || yy >= v.H || xx < 0 || xx >= v.W) return nullptr;
       return v.p + ((int64_t)(b * v.H + yy) * v.W + xx) * v.pitch + v.off + c;
@@ -143,9 +166,11 @@ __device__ __forceinline__ const uint16_t* addr8_b(const GemmDesc& d, int n, int
 }
 
 // Stage a ROWS x KC chunk of one operand into LDS (row-major, leading dim LD).
-template <bool IS_A, int ROWS, int KC, int LD>
+// VEC >= 0: the vector mode fixed at compile time (the other paths compiled
+// out); -1: read from the descriptor.
+template <bool IS_A, int ROWS, int KC, int LD, int VEC>
 __device__ __forceinline__ void stage(const GemmDesc& d, uint16_t* S, int row0, int k0, int ke, int t) {
-  const int vec = IS_A ? d.a_vec : d.b_vec;
+  const int vec = VEC >= 0 ? VEC : (IS_A ? d.a_vec : d.b_vec);
   const int nrows = IS_A ? d.M : d.N;
   if (vec == 1) {  // 8 consecutive k of one row: one 16-byte load, one 16-byte LDS store
     for (int e = t; e < ROWS * KC / 8; e += 256) {
@@ -167,29 +192,25 @@ __device__ __forceinline__ void stage(const GemmDesc& d, uint16_t* S, int row0, 
       }
       *reinterpret_cast<uint4*>(S + r * LD + kv) = w;
     }
-  } else if (vec == 2) {  // 8 consecutive rows at one k: one 16-byte load, 8 LDS stores
+  } else if (vec == 2) {
+    // 8 consecutive rows at one k: one 16-byte load, 8 LDS stores; launch_gemm
+    // takes this path only when the row count is a multiple of 8, so a group
+    // of 8 rows is wholly inside or wholly outside
+#pragma unroll 1
     for (int e = t; e < ROWS / 8 * KC; e += 256) {
       const int rv = (e / KC) * 8, kk = e % KC;
       const int row = row0 + rv, k = k0 + kk;
-      uint16_t h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      if (k < ke) {
-        if (row + 8 <= nrows) {
-          const uint16_t* p = IS_A ? addr8_a(d, row, k) : addr8_b(d, row, k);
-          if (p) {
-            const uint4 w = *reinterpret_cast<const uint4*>(p);
-            h[0] = w.x & 0xFFFF; h[1] = w.x >> 16; h[2] = w.y & 0xFFFF; h[3] = w.y >> 16;
-            h[4] = w.z & 0xFFFF; h[5] = w.z >> 16; h[6] = w.w & 0xFFFF; h[7] = w.w >> 16;
-          }
-        } else {
-#pragma unroll
-          for (int i = 0; i < 8; ++i)
-            h[i] = (row + i < nrows) ? (IS_A ? fetch_a(d, row + i, k) : fetch_b(d, row + i, k)) : (uint16_t)0;
-        }
+      uint4 w = make_uint4(0, 0, 0, 0);
+      if (k < ke && row < nrows) {
+        const uint16_t* p = IS_A ? addr8_a(d, row, k) : addr8_b(d, row, k);
+        if (p) w = *reinterpret_cast<const uint4*>(p);
       }
+      const uint32_t dw[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-      for (int i = 0; i < 8; ++i) S[(rv + i) * LD + kk] = h[i];
+      for (int i = 0; i < 8; ++i) S[(rv + i) * LD + kk] = (uint16_t)(dw[i >> 1] >> (16 * (i & 1)));
     }
   } else {
+#pragma unroll 1
     for (int e = t; e < ROWS * KC; e += 256) {
       const int r = e / KC, kk = e % KC;
       S[r * LD + kk] = (k0 + kk < ke) ? (IS_A ? fetch_a(d, row0 + r, k0 + kk) : fetch_b(d, row0 + r, k0 + kk))
@@ -201,8 +222,9 @@ __device__ __forceinline__ void stage(const GemmDesc& d, uint16_t* S, int row0, 
 // ------------------------------------------------------------------ the GEMM
 
 // WM x WN waves, each computing FM x FN 16x16 fragments: a TM x TN tile with
-// TM = 16 WM FM, TN = 16 WN FN.
-template <int WM, int WN, int FM, int FN>
+// TM = 16 WM FM, TN = 16 WN FN. AV, BV: the operands' vector modes when fixed
+// at compile time (-1: from the descriptor).
+template <int WM, int WN, int FM, int FN, int AV, int BV>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmDesc d) {
   constexpr int TM = 16 * WM * FM, TN = 16 * WN * FN, KC = 32, LD = KC + 8;
   __shared__ __align__(16) uint16_t As[TM * LD];
@@ -219,29 +241,23 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmDesc d) {
     for (int j = 0; j < FN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
   for (int k0 = kb; k0 < ke; k0 += KC) {
     // stage A (TM x KC) and B (TN x KC); element (row, kk) -> row * LD + kk
-    stage<true, TM, KC, LD>(d, As, m0, k0, ke, t);
-    stage<false, TN, KC, LD>(d, Bs, n0, k0, ke, t);
+    stage<true, TM, KC, LD, AV>(d, As, m0, k0, ke, t);
+    stage<false, TN, KC, LD, BV>(d, Bs, n0, k0, ke, t);
     __syncthreads();
 #pragma unroll
-    for (int ks = 0; ks < KC; ks += 16) {
-      v4s a[FM], b[FN];
+    for (int ks = 0; ks < KC; ks += 32) {
+      v8bf a[FM], b[FN];
 #pragma unroll
-      for (int i = 0; i < FM; ++i) {
-        const uint16_t* pa = As + (wm * 16 * FM + i * 16 + lane % 16) * LD + ks + 4 * (lane / 16);
+      for (int i = 0; i < FM; ++i)
+        a[i] = *reinterpret_cast<const v8bf*>(As + (wm * 16 * FM + i * 16 + lane % 16) * LD + ks + 8 * (lane / 16));
 #pragma unroll
-        for (int r = 0; r < 4; ++r) a[i][r] = (short)pa[r];
-      }
-#pragma unroll
-      for (int j = 0; j < FN; ++j) {
-        const uint16_t* pb = Bs + (wn * 16 * FN + j * 16 + lane % 16) * LD + ks + 4 * (lane / 16);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) b[j][r] = (short)pb[r];
-      }
+      for (int j = 0; j < FN; ++j)
+        b[j] = *reinterpret_cast<const v8bf*>(Bs + (wn * 16 * FN + j * 16 + lane % 16) * LD + ks + 8 * (lane / 16));
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
@@ -267,11 +283,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmDesc d) {
           if (d.mask.p && !(bf2f(d.mask.p[(int64_t)m * d.mask.pitch + d.mask.off + n]) > 0.f)) h = 0;
           d.out.p16[(int64_t)m * d.out.pitch + d.out.off + n] = h;
         } else if (d.out_mode == E_SHUF) {  // m: low-res pixel, n = sub * C + c
-          const int C = d.out.C;
-          const int sub = n / C, c = n - sub * C;
+          int sub, c, b, y, x;
+          chan_split(n, d.out.dC, sub, c);
           if (d.bias) v += d.bias[c];
-          const int w2 = d.out.W >> 1, h2 = d.out.H >> 1;
-          const int x = m % w2, tt = m / w2, y = tt % h2, b = tt / h2;
+          pix_split(m, d.out.dW2, d.out.dH2, b, y, x);
           const int yy = 2 * y + (sub >> 1), xx = 2 * x + (sub & 1);
           d.out.p16[((int64_t)(b * d.out.H + yy) * d.out.W + xx) * d.out.pitch + d.out.off + c] = f2bf(v);
         }
@@ -291,19 +306,20 @@ static void choose_vec(GemmDesc& d) {
   if (d.ksplit % 8 != 0) return;
   const View& a = d.a;
   const bool a_rows = a.p && al16(a.p) && a.pitch % 8 == 0 && a.off % 8 == 0;
+  // along rows (mode 2): also whole groups of 8 rows
   switch (d.a_mode) {
     case A_DIRECT: if (a_rows) d.a_vec = 1; break;
     case A_CONV:
     case A_G22: if (a_rows && a.C % 8 == 0) d.a_vec = 1; break;
-    case A_T: if (a_rows) d.a_vec = 2; break;
-    case A_TG22: if (a_rows && a.C % 8 == 0) d.a_vec = 2; break;
+    case A_T: if (a_rows && d.M % 8 == 0) d.a_vec = 2; break;
+    case A_TG22: if (a_rows && a.C % 8 == 0 && d.M % 8 == 0) d.a_vec = 2; break;
   }
   const View& b = d.b;
   const bool b_rows = b.p && al16(b.p) && b.pitch % 8 == 0 && b.off % 8 == 0;
   switch (d.b_mode) {
     case B_W: if (d.w && al16(d.w) && d.K % 8 == 0) d.b_vec = 1; break;
-    case B_IM2COL: if (b_rows && b.C % 8 == 0) d.b_vec = 2; break;
-    case B_T: if (b_rows) d.b_vec = 2; break;
+    case B_IM2COL: if (b_rows && b.C % 8 == 0 && d.N % 8 == 0) d.b_vec = 2; break;
+    case B_T: if (b_rows && d.N % 8 == 0) d.b_vec = 2; break;
   }
 }
 
@@ -313,38 +329,59 @@ static void choose_vec(GemmDesc& d) {
 static int g_gemm_tiles = 0;
 void set_gemm_tiles(int mode) { g_gemm_tiles = mode; }
 
+// Launch one tile shape with the operands' vector modes as template arguments
+// where they are the common pairs (both along k, both along rows).
+template <int WM, int WN, int FM, int FN>
+static void launch_tile(const GemmDesc& d, dim3 grid, hipStream_t s) {
+  if (d.a_vec == 1 && d.b_vec == 1)
+    hipLaunchKernelGGL((gemm_kernel<WM, WN, FM, FN, 1, 1>), grid, dim3(256), 0, s, d);
+  else if (d.a_vec == 2 && d.b_vec == 2)
+    hipLaunchKernelGGL((gemm_kernel<WM, WN, FM, FN, 2, 2>), grid, dim3(256), 0, s, d);
+  else
+    hipLaunchKernelGGL((gemm_kernel<WM, WN, FM, FN, -1, -1>), grid, dim3(256), 0, s, d);
+}
+
 void launch_gemm(const GemmDesc& d_in, hipStream_t s) {
   GemmDesc d = d_in;
+  d.a.prep_div();
+  d.b.prep_div();
+  d.out.prep_div();
   choose_vec(d);
   const int nsplit = (d.K + d.ksplit - 1) / d.ksplit;
   // the largest tile that still gives every CU a few workgroups
   const int64_t min_blocks = g_gemm_tiles == 1 ? 0 : (g_gemm_tiles >= 2 ? INT64_MAX : 1024);
   auto blocks = [&](int tm, int tn) { return (int64_t)((d.M + tm - 1) / tm) * ((d.N + tn - 1) / tn) * nsplit; };
   if (d.N <= 32) {
-    dim3 grid((d.M + 127) / 128, (d.N + 31) / 32, nsplit);
-    hipLaunchKernelGGL((gemm_kernel<4, 1, 2, 2>), grid, dim3(256), 0, s, d);
+    launch_tile<4, 1, 2, 2>(d, dim3((d.M + 127) / 128, (d.N + 31) / 32, nsplit), s);
   } else if (d.N >= 128 && blocks(128, 128) >= min_blocks) {
-    dim3 grid((d.M + 127) / 128, (d.N + 127) / 128, nsplit);
-    hipLaunchKernelGGL((gemm_kernel<2, 2, 4, 4>), grid, dim3(256), 0, s, d);
+    launch_tile<2, 2, 4, 4>(d, dim3((d.M + 127) / 128, (d.N + 127) / 128, nsplit), s);
   } else if (g_gemm_tiles == 2 || blocks(128, 64) >= min_blocks) {
-    dim3 grid((d.M + 127) / 128, (d.N + 63) / 64, nsplit);
-    hipLaunchKernelGGL((gemm_kernel<2, 2, 4, 2>), grid, dim3(256), 0, s, d);
+    launch_tile<2, 2, 4, 2>(d, dim3((d.M + 127) / 128, (d.N + 63) / 64, nsplit), s);
   } else {
-    dim3 grid((d.M + 63) / 64, (d.N + 63) / 64, nsplit);
-    hipLaunchKernelGGL((gemm_kernel<2, 2, 2, 2>), grid, dim3(256), 0, s, d);
+    launch_tile<2, 2, 2, 2>(d, dim3((d.M + 63) / 64, (d.N + 63) / 64, nsplit), s);
   }
   PAT_HIP(hipGetLastError());
 }
 
 // out[m][n] (with optional [ci][co] <- [(a,e,co)][ci] permutation) = sum_z part[z][m][n]
+// A workgroup takes 32 elements; its 8 lanes per element add the partials
+// z = lane, lane + 8, ... and then the 8 lane sums in lane order.
+constexpr int kSplitEl = 32, kSplitLanes = 8;
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(const float* __restrict__ part, int nsplit,
                                                             int M, int N, float* __restrict__ out,
                                                             int permute_cout) {
   const int64_t total = (int64_t)M * N;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    float s = 0.f;
-    for (int z = 0; z < nsplit; ++z) s += part[(int64_t)z * total + i];
+  const int el = threadIdx.x % kSplitEl, zl = threadIdx.x / kSplitEl;
+  const int64_t i = (int64_t)blockIdx.x * kSplitEl + el;
+  float s = 0.f;
+  if (i < total)
+    for (int z = zl; z < nsplit; z += kSplitLanes) s += part[(int64_t)z * total + i];
+  __shared__ float lds[256];
+  lds[threadIdx.x] = s;
+  __syncthreads();
+  if (zl == 0 && i < total) {
+#pragma unroll
+    for (int l = 1; l < kSplitLanes; ++l) s += lds[l * kSplitEl + el];
     if (permute_cout > 0) {
       // row m = sub * Cout + co, column n = ci -> [sub][ci][co]
       const int m = (int)(i / N), n = (int)(i % N);
@@ -359,7 +396,7 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const float* __restr
 void launch_splitk_reduce(const float* part, int nsplit, int M, int N, float* out, int permute_cout,
                           hipStream_t s) {
   const int64_t total = (int64_t)M * N;
-  const int blocks = (int)std::min<int64_t>((total + 255) / 256, 8192);
+  const int blocks = (int)((total + kSplitEl - 1) / kSplitEl);
   hipLaunchKernelGGL(splitk_reduce_kernel, dim3(blocks), dim3(256), 0, s, part, nsplit, M, N, out,
                      permute_cout);
   PAT_HIP(hipGetLastError());
@@ -486,19 +523,72 @@ void launch_mse(const float* y, const float* t, float* gy, double* part, double*
 __global__ __launch_bounds__(256) void head_back_kernel(View h, const float* __restrict__ w,
                                                         const float* __restrict__ gy, View gh,
                                                         float* __restrict__ part, int64_t P, int K,
-                                                        int64_t hw, int rows_per_block) {
+                                                        int64_t hw, int rows_per_block, FastDiv dhw) {
   const int C = h.C;
   const int64_t p0 = (int64_t)blockIdx.x * rows_per_block;
   const int64_t p1 = min(P, p0 + rows_per_block);
-  for (int e = threadIdx.x; e < K * (C + 1); e += blockDim.x) {
-    const int k = e < K * C ? e / C : e - K * C;
-    const int c = e < K * C ? e % C : -1;
-    float s = 0.f;
-    for (int64_t p = p0; p < p1; ++p) {
-      const float g = gy[((p / hw) * K + k) * hw + p % hw];
-      s += (c >= 0) ? g * bf2f(h.p[p * h.pitch + h.off + c]) : g;
+  if (C <= 256 && 256 % C == 0 && K <= 4) {
+    // thread t: channel t % C over every (256 / C)-th pixel from the (t / C)-th;
+    // lane sums added in lane order
+    // with the data gradient of the same pixels and channel
+    const int lanes = 256 / C, c = threadIdx.x % C, r = threadIdx.x / C;
+    float sw[4] = {0.f, 0.f, 0.f, 0.f}, sb[4] = {0.f, 0.f, 0.f, 0.f}, wq[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) wq[k] = k < K ? bf2f(f2bf(w[k * C + c])) : 0.f;
+    for (int64_t p = p0 + r; p < p1; p += lanes) {
+      const float hv = bf2f(h.p[p * h.pitch + h.off + c]);
+      uint32_t img, pix;
+      fast_divmod((uint32_t)p, dhw, img, pix);
+      const int64_t g0 = (int64_t)img * K * hw + pix;
+      float acc = 0.f;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (k < K) {
+          const float g = gy[g0 + k * hw];
+          sw[k] += g * hv;
+          sb[k] += g;
+          acc += g * wq[k];
+        }
+      }
+      uint16_t v = f2bf(acc);
+      if (!(hv > 0.f)) v = 0;
+      gh.p16[p * gh.pitch + gh.off + c] = v;
     }
-    part[(int64_t)blockIdx.x * K * (C + 1) + e] = s;
+    __shared__ float lw[4][256];
+    __shared__ float lb[4][256];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      lw[k][threadIdx.x] = sw[k];
+      lb[k][threadIdx.x] = sb[k];
+    }
+    __syncthreads();
+    float* out = part + (int64_t)blockIdx.x * K * (C + 1);
+    if (r == 0) {
+      for (int k = 0; k < K; ++k) {
+        float s = lw[k][c];
+        for (int l = 1; l < lanes; ++l) s += lw[k][l * C + c];
+        out[k * C + c] = s;
+      }
+    }
+    // the bias sums: the lanes of channel 0 saw every pixel once
+    if (threadIdx.x < K) {
+      const int k = threadIdx.x;
+      float s = lb[k][0];
+      for (int l = 1; l < lanes; ++l) s += lb[k][l * C];
+      out[K * C + k] = s;
+    }
+    return;
+  } else {
+    for (int e = threadIdx.x; e < K * (C + 1); e += blockDim.x) {
+      const int k = e < K * C ? e / C : e - K * C;
+      const int c = e < K * C ? e % C : -1;
+      float s = 0.f;
+      for (int64_t p = p0; p < p1; ++p) {
+        const float g = gy[((p / hw) * K + k) * hw + p % hw];
+        s += (c >= 0) ? g * bf2f(h.p[p * h.pitch + h.off + c]) : g;
+      }
+      part[(int64_t)blockIdx.x * K * (C + 1) + e] = s;
+    }
   }
   for (int64_t e = p0 * C + threadIdx.x; e < p1 * C; e += blockDim.x) {
     const int64_t p = e / C;
@@ -516,19 +606,36 @@ void launch_head_back(const View& h, const float* w, const float* gy, const View
                       int64_t P, int K, int64_t hw, int rows_per_block, hipStream_t s) {
   const int blocks = (int)((P + rows_per_block - 1) / rows_per_block);
   hipLaunchKernelGGL(head_back_kernel, dim3(blocks), dim3(256), 0, s, h, w, gy, gh, part, P, K, hw,
-                     rows_per_block);
+                     rows_per_block, make_fastdiv((uint32_t)hw));
   PAT_HIP(hipGetLastError());
 }
 
 // column sums of a bf16 NHWC gradient view: part[block][c] over a pixel range
+// When C divides 256, thread t adds channel t % C over every (256 / C)-th
+// pixel of the range from the (t / C)-th, and the 256 / C lane sums of a
+// channel are added in lane order; else one thread per channel.
 __global__ __launch_bounds__(256) void colsum_kernel(View g, float* __restrict__ part, int64_t P,
                                                      int rows_per_block) {
   const int64_t p0 = (int64_t)blockIdx.x * rows_per_block;
   const int64_t p1 = min(P, p0 + rows_per_block);
-  for (int c = threadIdx.x; c < g.C; c += blockDim.x) {
+  const int C = g.C;
+  if (C <= 256 && 256 % C == 0) {
+    const int lanes = 256 / C, c = threadIdx.x % C, r = threadIdx.x / C;
+    float s = 0.f;
+    for (int64_t p = p0 + r; p < p1; p += lanes) s += bf2f(g.p[p * g.pitch + g.off + c]);
+    __shared__ float lds[256];
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    if (r == 0) {
+      for (int l = 1; l < lanes; ++l) s += lds[l * C + c];
+      part[(int64_t)blockIdx.x * C + c] = s;
+    }
+    return;
+  }
+  for (int c = threadIdx.x; c < C; c += blockDim.x) {
     float s = 0.f;
     for (int64_t p = p0; p < p1; ++p) s += bf2f(g.p[p * g.pitch + g.off + c]);
-    part[(int64_t)blockIdx.x * g.C + c] = s;
+    part[(int64_t)blockIdx.x * C + c] = s;
   }
 }
 
