@@ -219,6 +219,51 @@ __device__ __forceinline__ void stage(const GemmDesc& d, uint16_t* S, int row0, 
   }
 }
 
+// One operand chunk (ROWS x KC) of a fixed vector mode held in registers
+// between its global loads and its LDS stores, so that the loads of the next
+// chunk are in flight while the current one is multiplied. VEC 1: 8
+// consecutive k of one row per 16-byte vector; 2: 8 consecutive rows at one k
+// (launch_gemm guarantees K, the split-K chunks and, for 2, the row count to
+// be multiples of 8, so a vector is wholly inside or outside the operand).
+template <bool IS_A, int ROWS, int KC, int LD, int VEC>
+struct ChunkRegs {
+  static constexpr int NV = VEC == 1 ? ROWS * KC / 8 : ROWS / 8 * KC;
+  static constexpr int SLOTS = (NV + 255) / 256;
+  uint4 r[SLOTS];
+
+  __device__ __forceinline__ void load(const GemmDesc& d, int row0, int k0, int ke, int t) {
+    const int nrows = IS_A ? d.M : d.N;
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      const int e = t + 256 * s;
+      r[s] = make_uint4(0, 0, 0, 0);
+      if (e >= NV) continue;
+      const int row = row0 + (VEC == 1 ? e / (KC / 8) : (e / KC) * 8);
+      const int k = k0 + (VEC == 1 ? (e % (KC / 8)) * 8 : e % KC);
+      if (row < nrows && k < ke) {
+        const uint16_t* p = IS_A ? addr8_a(d, row, k) : addr8_b(d, row, k);
+        if (p) r[s] = *reinterpret_cast<const uint4*>(p);
+      }
+    }
+  }
+
+  __device__ __forceinline__ void store(uint16_t* S, int t) const {
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      const int e = t + 256 * s;
+      if (e >= NV) continue;
+      if (VEC == 1) {
+        *reinterpret_cast<uint4*>(S + (e / (KC / 8)) * LD + (e % (KC / 8)) * 8) = r[s];
+      } else {
+        const int rv = (e / KC) * 8, kk = e % KC;
+        const uint32_t dw[4] = {r[s].x, r[s].y, r[s].z, r[s].w};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) S[(rv + i) * LD + kk] = (uint16_t)(dw[i >> 1] >> (16 * (i & 1)));
+      }
+    }
+  }
+};
+
 // ------------------------------------------------------------------ the GEMM
 
 // WM x WN waves, each computing FM x FN 16x16 fragments: a TM x TN tile with
@@ -239,11 +284,29 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmDesc d) {
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  // fixed vector modes: chunk n + 1 is loaded into registers while chunk n is
+  // multiplied
+  constexpr bool PIPE = AV > 0 && BV > 0;
+  ChunkRegs<true, TM, KC, LD, PIPE ? AV : 1> ca;
+  ChunkRegs<false, TN, KC, LD, PIPE ? BV : 1> cb;
+  if (PIPE) {
+    ca.load(d, m0, kb, ke, t);
+    cb.load(d, n0, kb, ke, t);
+  }
   for (int k0 = kb; k0 < ke; k0 += KC) {
     // stage A (TM x KC) and B (TN x KC); element (row, kk) -> row * LD + kk
-    stage<true, TM, KC, LD, AV>(d, As, m0, k0, ke, t);
-    stage<false, TN, KC, LD, BV>(d, Bs, n0, k0, ke, t);
+    if (PIPE) {
+      ca.store(As, t);
+      cb.store(Bs, t);
+    } else {
+      stage<true, TM, KC, LD, AV>(d, As, m0, k0, ke, t);
+      stage<false, TN, KC, LD, BV>(d, Bs, n0, k0, ke, t);
+    }
     __syncthreads();
+    if (PIPE && k0 + KC < ke) {
+      ca.load(d, m0, k0 + KC, ke, t);
+      cb.load(d, n0, k0 + KC, ke, t);
+    }
 #pragma unroll
     for (int ks = 0; ks < KC; ks += 32) {
       v8bf a[FM], b[FN];
@@ -305,6 +368,7 @@ static void choose_vec(GemmDesc& d) {
   d.a_vec = d.b_vec = 0;
   if (d.ksplit % 8 != 0) return;
   const View& a = d.a;
+  if (d.K % 8 != 0) return;
   const bool a_rows = a.p && al16(a.p) && a.pitch % 8 == 0 && a.off % 8 == 0;
   // along rows (mode 2): also whole groups of 8 rows
   switch (d.a_mode) {
