@@ -535,9 +535,28 @@ __global__ __launch_bounds__(256) void head_kernel(View h, const float* __restri
   const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= P) return;
   const int64_t base = (p / hw) * K * hw + p % hw;
+  const uint16_t* row = h.p + p * h.pitch + h.off;
+  if (h.C % 8 == 0 && h.pitch % 8 == 0 && h.off % 8 == 0 && K <= 4 &&
+      (reinterpret_cast<uintptr_t>(h.p) & 15) == 0) {
+    // the pixel's channels in 16-byte loads; each output adds over c in order
+    float s[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int c0 = 0; c0 < h.C; c0 += 8) {
+      const uint4 v = *reinterpret_cast<const uint4*>(row + c0);
+      const uint32_t dw[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const float x = bf2f((uint16_t)(dw[i >> 1] >> (16 * (i & 1))));
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (k < K) s[k] += x * bf2f(f2bf(w[k * h.C + c0 + i]));
+      }
+    }
+    for (int k = 0; k < K; ++k) y[base + k * hw] = s[k] + b[k];
+    return;
+  }
   for (int k = 0; k < K; ++k) {
     float s = 0.f;
-    for (int c = 0; c < h.C; ++c) s += bf2f(h.p[p * h.pitch + h.off + c]) * bf2f(f2bf(w[k * h.C + c]));
+    for (int c = 0; c < h.C; ++c) s += bf2f(row[c]) * bf2f(f2bf(w[k * h.C + c]));
     y[base + k * hw] = s + b[k];
   }
 }
@@ -683,6 +702,30 @@ __global__ __launch_bounds__(256) void colsum_kernel(View g, float* __restrict__
   const int64_t p0 = (int64_t)blockIdx.x * rows_per_block;
   const int64_t p1 = min(P, p0 + rows_per_block);
   const int C = g.C;
+  if (C % 8 == 0 && C <= 256 && 256 % (C / 8) == 0 && g.pitch % 8 == 0 && g.off % 8 == 0 &&
+      (reinterpret_cast<uintptr_t>(g.p) & 15) == 0) {
+    // 16-byte loads: thread t adds channels 8 (t % (C/8)) .. + 7 over every
+    // (256 / (C/8))-th pixel from the (t / (C/8))-th; lane sums in lane order
+    const int groups = C / 8, lanes = 256 / groups, cg = threadIdx.x % groups, r = threadIdx.x / groups;
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int64_t p = p0 + r; p < p1; p += lanes) {
+      const uint4 v = *reinterpret_cast<const uint4*>(g.p + p * g.pitch + g.off + 8 * cg);
+      const uint32_t dw[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int i = 0; i < 8; ++i) s[i] += bf2f((uint16_t)(dw[i >> 1] >> (16 * (i & 1))));
+    }
+    __shared__ float lds8[8][256];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) lds8[i][threadIdx.x] = s[i];
+    __syncthreads();
+    if (threadIdx.x < C) {
+      const int c = threadIdx.x, g8 = c / 8, i = c % 8;
+      float acc = 0.f;
+      for (int l = 0; l < lanes; ++l) acc += lds8[i][l * groups + g8];
+      part[(int64_t)blockIdx.x * C + c] = acc;
+    }
+    return;
+  }
   if (C <= 256 && 256 % C == 0) {
     const int lanes = 256 / C, c = threadIdx.x % C, r = threadIdx.x / C;
     float s = 0.f;
