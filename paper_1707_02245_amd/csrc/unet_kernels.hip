@@ -271,7 +271,9 @@ struct ChunkRegs {
 // at compile time (-1: from the descriptor).
 template <int WM, int WN, int FM, int FN, int AV, int BV>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmDesc d) {
-  constexpr int TM = 16 * WM * FM, TN = 16 * WN * FN, KC = 32, LD = KC + 8;
+  // 64-wide k chunks for the row-major operands of the weight gradients (long k,
+  // split across workgroups), 32 elsewhere (fewer registers, more workgroups per CU)
+  constexpr int TM = 16 * WM * FM, TN = 16 * WN * FN, KC = (AV == 2 && BV == 2) ? 64 : 32, LD = KC + 8;
   __shared__ __align__(16) uint16_t As[TM * LD];
   __shared__ __align__(16) uint16_t Bs[TN * LD];
   const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
