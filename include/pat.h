@@ -466,7 +466,8 @@ pat_status pat_warmstart_num_params(pat_unet n, int64_t* out);
  * test hook): 0 automatic (128x128 or 128x64 tiles only where the launch has
  * at least 1024 workgroups, else 64x64), 1 the largest tile the column count
  * allows, 2 128x64, 3 64x64; layers with at most 32 output columns always
- * take 128x32. The tiles differ only in how output elements are grouped into
+ * take 128x32, and products of at most 32 rows (the weight gradients of
+ * 32-channel layers) 32x64. The tiles differ only in how output elements are grouped into
  * workgroups; each element accumulates along k in the same chunks. Invalid
  * mode: PAT_ERR_INVALID_ARG. */
 pat_status pat_warmstart_set_gemm_tiles(int32_t mode);

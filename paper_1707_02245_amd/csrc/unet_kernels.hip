@@ -390,8 +390,9 @@ static void choose_vec(GemmDesc& d) {
 }
 
 // Tile rule of launch_gemm (process-wide): 0 automatic, 1 the largest tile
-// the column count allows, 2 128x64, 3 64x64 (for N > 32; N <= 32 always
-// takes 128x32). Each output element accumulates along k in the same chunks.
+// the column count allows, 2 128x64, 3 64x64 (for N > 32 and M > 32; N <= 32
+// always takes 128x32, M <= 32 32x64). Each output element accumulates along
+// k in the same chunks.
 static int g_gemm_tiles = 0;
 void set_gemm_tiles(int mode) { g_gemm_tiles = mode; }
 
@@ -419,6 +420,9 @@ void launch_gemm(const GemmDesc& d_in, hipStream_t s) {
   auto blocks = [&](int tm, int tn) { return (int64_t)((d.M + tm - 1) / tm) * ((d.N + tn - 1) / tn) * nsplit; };
   if (d.N <= 32) {
     launch_tile<4, 1, 2, 2>(d, dim3((d.M + 127) / 128, (d.N + 31) / 32, nsplit), s);
+  } else if (d.M <= 32) {
+    // the weight gradients of 32-channel layers: 32 x 64 tiles
+    launch_tile<2, 2, 1, 2>(d, dim3((d.M + 31) / 32, (d.N + 63) / 64, nsplit), s);
   } else if (d.N >= 128 && blocks(128, 128) >= min_blocks) {
     launch_tile<2, 2, 4, 4>(d, dim3((d.M + 127) / 128, (d.N + 127) / 128, nsplit), s);
   } else if (g_gemm_tiles == 2 || blocks(128, 64) >= min_blocks) {
