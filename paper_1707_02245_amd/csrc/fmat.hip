@@ -42,7 +42,6 @@ namespace pat {
 namespace {
 
 constexpr int kFmLocalMax = 12288;  // local bins per tile (LDS counters, 48 KB)
-constexpr int kLps = 4;  // lanes per segment
 constexpr int64_t kFmSlack = 64;    // zero entries past the end
 
 __device__ __forceinline__ int find_blk(const int* __restrict__ starts, int n, int blk) {
@@ -138,74 +137,76 @@ __global__ __launch_bounds__(256) void fmat_kernel(FwdArgs<T> a0, const FwdArgs<
     img[kPix * r + t] = v;
   }
   __syncthreads();
-  const int quad = threadIdx.x / kLps, ql = threadIdx.x % kLps;
   const gptr<const uint32_t> off4 = as_global(reinterpret_cast<const uint32_t*>(g.fm_off));
   const gptr<const T> wt = as_global(static_cast<const T*>(g.fm_w));
   typedef T T2 __attribute__((ext_vector_type(2)));
   typedef T T4 __attribute__((ext_vector_type(4)));
-  // a lane's 4-entry group: offsets (4 bytes) and weights (16 or 32 bytes)
-  auto load = [&](int e, uint32_t& o4, T* w) {
-    o4 = __builtin_nontemporal_load(off4 + (e >> 2));
-    if constexpr (sizeof(T) == 8) {
-      const gptr<const T2> w2 = (gptr<const T2>)(wt + e);
-      const T2 wa = __builtin_nontemporal_load(w2), wb = __builtin_nontemporal_load(w2 + 1);
-      w[0] = wa.x;
-      w[1] = wa.y;
-      w[2] = wb.x;
-      w[3] = wb.y;
-    } else {
-      const T4 wa = __builtin_nontemporal_load((gptr<const T4>)(wt + e));
-      w[0] = wa.x;
-      w[1] = wa.y;
-      w[2] = wa.z;
-      w[3] = wa.w;
-    }
-  };
-  for (int s = ch.y + quad; s < ch.z; s += 256 / kLps) {
-    const int4 sd = g.fm_seg[s];  // first entry and count are multiples of 4
-    T acc0 = T(0), acc1 = T(0), acc2 = T(0), acc3 = T(0);
-    const int e1 = sd.x + sd.y;
-    // two groups per lane and step, both loaded before either is used; a
-    // second group past the segment's end reloads the first with zero weight
-    for (int e = sd.x + 4 * ql; e < e1; e += 8 * kLps) {
-      const bool two = e + 4 * kLps < e1;
-      uint32_t oa, ob;
-      T wa[4], wb[4];
-      load(e, oa, wa);
-      load(two ? e + 4 * kLps : e, ob, wb);
-      auto pixel = [&](int o) -> T4 { return *reinterpret_cast<const T4*>(img + kPix * o); };
+  // The chunk's segments are contiguous: its entries, in groups of four (no
+  // group straddles two segments), run from the first segment's first entry.
+  // Thread t takes groups t, t + 256, ... (consecutive lanes on consecutive
+  // groups, so a wave's loads are contiguous), all loaded before any is used,
+  // and leaves each group's four turn sums in LDS; then a thread per segment
+  // adds its groups' sums in order.
+  __shared__ __align__(16) T4 gsum[kFmChunkEntries / 4];
+  const int e0 = g.fm_seg[ch.y].x;
+  const int4 last = g.fm_seg[ch.z - 1];
+  const int ng = (last.x + last.y - e0) >> 2;  // at most kFmChunkEntries / 4
+  constexpr int kPer = kFmChunkEntries / 4 / 256;
+  uint32_t o4[kPer];
+  T w[kPer][4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const T4 px = pixel((oa >> (8 * k)) & 0xFF);
-        acc0 = fma(wa[k], px.x, acc0);
-        acc1 = fma(wa[k], px.y, acc1);
-        acc2 = fma(wa[k], px.z, acc2);
-        acc3 = fma(wa[k], px.w, acc3);
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const T wk = two ? wb[k] : T(0);
-        const T4 px = pixel((ob >> (8 * k)) & 0xFF);
-        acc0 = fma(wk, px.x, acc0);
-        acc1 = fma(wk, px.y, acc1);
-        acc2 = fma(wk, px.z, acc2);
-        acc3 = fma(wk, px.w, acc3);
+  for (int i = 0; i < kPer; ++i) {
+    const int q = threadIdx.x + 256 * i;
+    o4[i] = 0;
+    w[i][0] = w[i][1] = w[i][2] = w[i][3] = T(0);
+    if (q < ng) {
+      const int e = e0 + 4 * q;
+      o4[i] = __builtin_nontemporal_load(off4 + (e >> 2));
+      if constexpr (sizeof(T) == 8) {
+        const gptr<const T2> w2 = (gptr<const T2>)(wt + e);
+        const T2 wa = __builtin_nontemporal_load(w2), wb = __builtin_nontemporal_load(w2 + 1);
+        w[i][0] = wa.x;
+        w[i][1] = wa.y;
+        w[i][2] = wb.x;
+        w[i][3] = wb.y;
+      } else {
+        const T4 wa = __builtin_nontemporal_load((gptr<const T4>)(wt + e));
+        w[i][0] = wa.x;
+        w[i][1] = wa.y;
+        w[i][2] = wa.z;
+        w[i][3] = wa.w;
       }
     }
-    acc0 = quad_sum(acc0);
-    acc1 = quad_sum(acc1);
-    acc2 = quad_sum(acc2);
-    acc3 = quad_sum(acc3);
-    if (ql == 0) {
-      // a segment's four partials side by side, segments in tile order: a
-      // workgroup writes one contiguous run
-      T4 pv;
-      pv.x = acc0;
-      pv.y = acc1;
-      pv.z = acc2;
-      pv.w = acc3;
-      *reinterpret_cast<T4*>(a.part + 4 * (int64_t)s) = pv;
+  }
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int q = threadIdx.x + 256 * i;
+    if (q < ng) {
+      T acc0 = T(0), acc1 = T(0), acc2 = T(0), acc3 = T(0);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const T4 px = *reinterpret_cast<const T4*>(img + kPix * ((o4[i] >> (8 * k)) & 0xFF));
+        acc0 = fma(w[i][k], px.x, acc0);
+        acc1 = fma(w[i][k], px.y, acc1);
+        acc2 = fma(w[i][k], px.z, acc2);
+        acc3 = fma(w[i][k], px.w, acc3);
+      }
+      T4 v;
+      v.x = acc0;
+      v.y = acc1;
+      v.z = acc2;
+      v.w = acc3;
+      gsum[q] = v;
     }
+  }
+  __syncthreads();
+  // a segment's four partials side by side, segments in tile order: a
+  // workgroup writes one contiguous run
+  for (int s = ch.y + threadIdx.x; s < ch.z; s += 256) {
+    const int4 sd = g.fm_seg[s];
+    T4 acc = gsum[(sd.x - e0) >> 2];
+    for (int q = ((sd.x - e0) >> 2) + 1, qe = (sd.x + sd.y - e0) >> 2; q < qe; ++q) acc += gsum[q];
+    *reinterpret_cast<T4*>(a.part + 4 * (int64_t)s) = acc;
   }
 }
 
