@@ -37,35 +37,23 @@ HBM_PEAK_GBS = 8000.0
 # rocprofv3 counter passes, scaled by what the counters read for a plain copy of known
 # size (FETCH x 2, WRITE x 1); profiles/*_hbm_traffic.md. An entry is reported only
 # while the kernel's sources are the ones measured.
-_SRC_FWD = {"paper_1707_02245_amd/csrc/projector.hip":
-            "dac4e7ecd78374581f9fb3bdaa72fe62eb5e9dd1e8eb9456f69948380b789b12",
-            "paper_1707_02245_amd/csrc/pat_common.hpp":
-            "cfcbba40b7f22a819d8564e336b95b702bef06d20d034345790c0ca8412ea1d2"}
-_SRC_ADJ = {"paper_1707_02245_amd/csrc/csr.hip":
-            "3040aa591c28c22f8e93010f102c44657b3b859840285bf95ee966a505330612",
-            "paper_1707_02245_amd/csrc/pat_common.hpp":
-            "cfcbba40b7f22a819d8564e336b95b702bef06d20d034345790c0ca8412ea1d2"}
-_SRC_FMAT = {"paper_1707_02245_amd/csrc/fmat.hip":
-             "81021914c1473d70865fe97420dfc4684d62ffc8032a989d2a95d173ab7e602a",
-             "paper_1707_02245_amd/csrc/fwd_epilogue.hpp":
-             "e8308bc255c13bd6e6b36f8e6a7bb41666da4a8efe5470fdf8b3331cc7a56af9",
-             "paper_1707_02245_amd/csrc/pat_common.hpp":
-             "cfcbba40b7f22a819d8564e336b95b702bef06d20d034345790c0ca8412ea1d2"}
+_COMMON = ("paper_1707_02245_amd/csrc/pat_common.hpp",
+           "5f0da6402d67b625b9057508ce3782ad94166fd9d927e84a9818a87119a309c4")
+_SRC_FWD = dict([("paper_1707_02245_amd/csrc/projector.hip",
+                  "dac4e7ecd78374581f9fb3bdaa72fe62eb5e9dd1e8eb9456f69948380b789b12"), _COMMON])
+_SRC_ADJ = dict([("paper_1707_02245_amd/csrc/csr.hip",
+                  "3040aa591c28c22f8e93010f102c44657b3b859840285bf95ee966a505330612"), _COMMON])
+_SRC_FMAT = dict([("paper_1707_02245_amd/csrc/fmat.hip",
+                   "a422703fa2ce9934c68b8f4bc7ef1abf1d14a55c33b70a7d92cce0d8c8b68e23"),
+                  ("paper_1707_02245_amd/csrc/fwd_epilogue.hpp",
+                   "e8308bc255c13bd6e6b36f8e6a7bb41666da4a8efe5470fdf8b3331cc7a56af9"), _COMMON])
 MEASURED_TRAFFIC = [
-    # profiles/fwd_gather_tgv256_f64_hbm_traffic.md
-    {"kernel": "fwd_kernel<double, 0, 16, false, 1, false>", "bytes_per_launch": 34.45e6, "sources": _SRC_FWD},
-    {"kernel": "fwd_kernel<double, 0, 32, false, 1, false>", "bytes_per_launch": 39.38e6, "sources": _SRC_FWD},
-    {"kernel": "fwd_kernel<double, 0, 64, false, 1, false>", "bytes_per_launch": 42.56e6, "sources": _SRC_FWD},
-    # both passes of the stored A (path 3): 238.33 + 27.44 MB
-    {"kernel": "fmat_kernel<double, false> + fmat_reduce_kernel<double, 0>", "bytes_per_launch": 265.77e6,
+    # profiles/fwd_paths_tgv256_f64_counters.md (one counter run of the forward-path sequence)
+    {"kernel": "fwd_kernel<double, 0, 16, false, 1, false>", "bytes_per_launch": 46.11e6, "sources": _SRC_FWD},
+    # both passes of the stored A (path 3): 163.49 + 18.43 MB and 26.39 + 1.05 MB
+    {"kernel": "fmat_kernel<double, false> + fmat_reduce_kernel<double, 0>", "bytes_per_launch": 209.36e6,
      "sources": _SRC_FMAT},
-    # profiles/csr_tiled_tgv256_f64_hbm_traffic.md
-    {"kernel": "csr_tiled_kernel<double, false, 4, 256, 16>", "bytes_per_launch": 187.77e6, "sources": _SRC_ADJ},
-    {"kernel": "csr_tiled_kernel<double, false, 4, 512, 16>", "bytes_per_launch": 189.63e6, "sources": _SRC_ADJ},
-    {"kernel": "csr_tiled_kernel<double, false, 4, 1024, 16>", "bytes_per_launch": 193.50e6, "sources": _SRC_ADJ},
-    {"kernel": "csr_tiled_kernel<double, false, 4, 256, 64>", "bytes_per_launch": 181.09e6, "sources": _SRC_ADJ},
-    {"kernel": "csr_tiled_kernel<double, false, 4, 512, 64>", "bytes_per_launch": 180.97e6, "sources": _SRC_ADJ},
-    {"kernel": "csr_tiled_kernel<double, false, 4, 1024, 64>", "bytes_per_launch": 182.29e6, "sources": _SRC_ADJ},
+    {"kernel": "csr_tiled_kernel<double, false, 4, 256, 16>", "bytes_per_launch": 187.84e6, "sources": _SRC_ADJ},
 ]
 
 
