@@ -63,6 +63,17 @@ WavFilters wav_filters(int level) {
 
 enum { WAV_PLAIN = 0, WAV_DUAL = 1, WAV_GAP = 2 };
 
+// Workgroups go to the 8 XCDs in turn (block b to XCD b mod 8). Numbering the
+// position ranges so that each XCD takes one contiguous run keeps the rows a
+// position row shares with its neighbours (the filters' overlapping taps) in
+// that XCD's L2. Measured at 4096^2 it helps the levels from 2 on (synthesis
+// 91 -> 76 and 25 -> 21 us); the level-1 analysis, which reads the image, was
+// no faster with it and keeps launch order.
+__device__ __forceinline__ int64_t xcd_block() {
+  const unsigned nb = gridDim.x, b = blockIdx.x;
+  return nb % 8 == 0 ? (int64_t)(b % 8) * (nb / 8) + b / 8 : (int64_t)b;
+}
+
 // One analysis level. Input grid cy x cx (the image at level 1, else the
 // previous level's four lowpass bands); output grid (cy/2) x (cx/2).
 template <class T, class A>
@@ -87,7 +98,7 @@ template <class T, class A, int MODE, bool FIRST>
 __global__ __launch_bounds__(256) void wav_analysis_kernel(WavAnaArgs<T, A> a) {
   const int hx = a.cx >> 1, hy = a.cy >> 1;
   const int64_t S = (int64_t)hx * hy;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t e = (FIRST ? (int64_t)blockIdx.x : xcd_block()) * 256 + threadIdx.x;
   double gap = 0.0;
   if (e < S) {
     const int ix = (int)(e % hx), iy = (int)(e / hx);
@@ -235,7 +246,7 @@ template <class T, class A, bool FIRST>
 __global__ __launch_bounds__(256) void wav_synthesis_kernel(WavSynArgs<T, A> a) {
   const int hx = a.cx >> 1, hy = a.cy >> 1;
   const int64_t S = (int64_t)hx * hy;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t e = xcd_block() * 256 + threadIdx.x;
   if (e >= S) return;
   const int X = (int)(e % hx), Y = (int)(e / hx);
   const A kc = (A)a.f.kc;
