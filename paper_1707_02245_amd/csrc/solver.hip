@@ -3,11 +3,15 @@
 // Sec. 3.3.3, for one instance or many instances sharing every launch.
 //
 // One iteration is three launches over all active instances:
-//   1. forward gather of ubar with the dual data step fused (q update), and in
-//      the same launch the regulariser's dual step (r, and s for TGV)
+//   1. the forward of ubar with the dual data step fused (q update), and in
+//      the same launch the regulariser's dual step (r, and s for TGV); with
+//      the stored A by pixel tiles (forward path 3) its tile pass carries the
+//      regulariser's step and a per-bin pass the dual data step
 //   2. A^T q into one partial image per quarter turn (stored CSR) or per
 //      detector group (matrix-free scatter)
 //   3. primal step (sums the partials, u and v updates, extrapolation)
+// The wavelet model adds one analysis launch per level with its dual step
+// after 1 and one synthesis launch per level (W^T r) before 3.
 // The last iteration of a block adds the gap: forward gather of u+ with the
 // data and F* terms reduced, the regulariser value reduced, and an ordered
 // final sum per instance. Blocks of iterations are captured once as a HIP
