@@ -231,6 +231,19 @@ __global__ __launch_bounds__(256) void fmat_reduce_kernel(FwdArgs<T> a0, const F
   const int gl = threadIdx.x & 15;
   const int64_t b = (int64_t)blk * 16 + (threadIdx.x >> 4);
   const bool valid = b < nb;
+  // the dual data step's operands of the four turns, loaded before the
+  // partials so that both round trips overlap (the same arithmetic as the
+  // forward's epilogue)
+  T dq[4], df[4], ds[4];
+  if (MODE == FWD_DUAL && valid && gl == 0) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t bt = b + t * a.slot_bins;
+      dq[t] = a.out[bt];
+      df[t] = a.f[bt];
+      ds[t] = a.sigma[bt];
+    }
+  }
   T v[4] = {T(0), T(0), T(0), T(0)};
   if (valid) {
     typedef T T4 __attribute__((ext_vector_type(4)));
@@ -245,6 +258,18 @@ __global__ __launch_bounds__(256) void fmat_reduce_kernel(FwdArgs<T> a0, const F
   }
 #pragma unroll
   for (int t = 0; t < 4; ++t) v[t] = row16_sum(v[t]);
+  if (MODE == FWD_DUAL) {
+    if (valid && gl == 0) {
+      const T dm = a.mult ? (T)a.mult[0] : T(1);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        // q <- (q + sigma (A ubar - f)) / (1 + sigma), as fwd_epilogue
+        const T sg = a.mult ? ds[t] * dm : ds[t];
+        a.out[b + t * a.slot_bins] = (dq[t] + sg * (v[t] - df[t])) / (T(1) + sg);
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     FwdArgs<T> at = a;
