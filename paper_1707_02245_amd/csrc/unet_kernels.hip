@@ -264,6 +264,108 @@ struct ChunkRegs {
   }
 };
 
+// ------------------------------------------------------------------ direct 3x3 convolution
+
+// The 3x3 convolutions with 32 outputs (the 32-channel top level: M = every
+// pixel of the batch, N = 32, K = 9 C) as a direct convolution: a workgroup
+// takes an 8 x 16 pixel tile of one image, stages the tile's input with its
+// one-pixel halo (10 x 18 pixels, 32 channels at a time) and the weights of
+// those channels for the nine taps in LDS once, and multiplies each tap's
+// shifted view of the halo with the 16x16x32 MFMA, so a pixel's input is read
+// from memory once per channel chunk instead of once per tap. Channels and
+// weight rows are padded to 40 elements in LDS (an 80-byte stride puts the 16
+// rows a fragment reads in distinct banks). a_sign = -1 (the data gradient)
+// reads the taps mirrored, as the GEMM's index map does. Accumulation: per
+// chunk of 32 channels, taps in order.
+constexpr int kCvTH = 8, kCvTW = 16, kCvHH = kCvTH + 2, kCvHW = kCvTW + 2, kCvLD = 40;
+
+__global__ __launch_bounds__(256) void conv3_kernel(GemmDesc d) {
+  __shared__ __align__(16) uint16_t halo[kCvHH * kCvHW * kCvLD];
+  __shared__ __align__(16) uint16_t wts[9 * 32 * kCvLD];
+  const View& v = d.a;
+  const int H = v.H, W = v.W, C = v.C;
+  const int tiles_x = W / kCvTW, tiles_y = H / kCvTH;
+  int blk = blockIdx.x;
+  const int tx = blk % tiles_x;
+  blk /= tiles_x;
+  const int ty = blk % tiles_y, b = blk / tiles_y;
+  const int x0 = tx * kCvTW, y0 = ty * kCvTH;
+  const int t = threadIdx.x, wave = t / 64, lane = t % 64;
+  v4f acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int c0 = 0; c0 < C; c0 += 32) {
+    // halo: 10 x 18 pixels x 32 channels as 16-byte vectors of 8 channels
+    for (int e = t; e < kCvHH * kCvHW * 4; e += 256) {
+      const int cv = e % 4, px = e / 4;
+      const int hx = px % kCvHW, hy = px / kCvHW;
+      const int yy = y0 + hy - 1, xx = x0 + hx - 1;
+      uint4 w = make_uint4(0, 0, 0, 0);
+      if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+        w = *reinterpret_cast<const uint4*>(v.p + ((int64_t)(b * H + yy) * W + xx) * v.pitch + v.off + c0 + 8 * cv);
+      *reinterpret_cast<uint4*>(halo + px * kCvLD + 8 * cv) = w;
+    }
+    // weights of the chunk: w[n][tap C + c0 + c] for 32 n, 9 taps, 32 c
+    for (int e = t; e < 9 * 32 * 4; e += 256) {
+      const int cv = e % 4, row = e / 4;  // row = tap * 32 + n
+      const int tap = row / 32, n = row % 32;
+      const uint4 w = *reinterpret_cast<const uint4*>(d.w + (int64_t)n * d.K + tap * C + c0 + 8 * cv);
+      *reinterpret_cast<uint4*>(wts + row * kCvLD + 8 * cv) = w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int dy = d.a_sign * (tap / 3 - 1), dx = d.a_sign * (tap % 3 - 1);
+      v8bf a[2], bw[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int hy = wave * 2 + i + 1 + dy, hx = lane % 16 + 1 + dx;
+        a[i] = *reinterpret_cast<const v8bf*>(halo + (hy * kCvHW + hx) * kCvLD + 8 * (lane / 16));
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        bw[j] = *reinterpret_cast<const v8bf*>(wts + (tap * 32 + j * 16 + lane % 16) * kCvLD + 8 * (lane / 16));
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bw[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // epilogue as the GEMM's E_ACT: fragment i covers tile row wave * 2 + i,
+  // D[4(l/16)+r][l%16] -> pixel column 4(l/16)+r, output channel j * 16 + l % 16
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int y = y0 + wave * 2 + i;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int n = j * 16 + lane % 16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int x = x0 + 4 * (lane / 16) + r;
+        const int64_t m = (int64_t)(b * H + y) * W + x;
+        float val = acc[i][j][r];
+        if (d.bias) val += d.bias[n];
+        if (d.relu) val = fmaxf(val, 0.f);
+        uint16_t h = f2bf(val);
+        if (d.mask.p && !(bf2f(d.mask.p[m * d.mask.pitch + d.mask.off + n]) > 0.f)) h = 0;
+        d.out.p16[m * d.out.pitch + d.out.off + n] = h;
+      }
+    }
+  }
+}
+
+// Whether conv3_kernel serves this product (else the generic GEMM).
+static bool conv3_applies(const GemmDesc& d) {
+  const View& v = d.a;
+  return d.a_mode == A_CONV && d.b_mode == B_W && d.out_mode == E_ACT && d.a_vec == 1 && d.b_vec == 1 &&
+         d.N == 32 && d.ksplit >= d.K && v.C % 32 == 0 && d.K == 9 * v.C && v.H % kCvTH == 0 &&
+         v.W % kCvTW == 0 && v.H > 0 && v.W > 0 && d.M % (v.H * v.W) == 0;
+}
+
 // ------------------------------------------------------------------ the GEMM
 
 // WM x WN waves, each computing FM x FN 16x16 fragments: a TM x TN tile with
@@ -418,7 +520,10 @@ void launch_gemm(const GemmDesc& d_in, hipStream_t s) {
   // the largest tile that still gives every CU a few workgroups
   const int64_t min_blocks = g_gemm_tiles == 1 ? 0 : (g_gemm_tiles >= 2 ? INT64_MAX : 1024);
   auto blocks = [&](int tm, int tn) { return (int64_t)((d.M + tm - 1) / tm) * ((d.N + tn - 1) / tn) * nsplit; };
-  if (d.N <= 32) {
+  if (conv3_applies(d)) {
+    const int64_t n_blk = (int64_t)(d.M / (d.a.H * d.a.W)) * (d.a.H / kCvTH) * (d.a.W / kCvTW);
+    hipLaunchKernelGGL(conv3_kernel, dim3((unsigned)n_blk), dim3(256), 0, s, d);
+  } else if (d.N <= 32) {
     launch_tile<4, 1, 2, 2>(d, dim3((d.M + 127) / 128, (d.N + 31) / 32, nsplit), s);
   } else if (d.M <= 32) {
     // the weight gradients of 32-channel layers: 32 x 64 tiles
