@@ -266,9 +266,10 @@ struct ChunkRegs {
 
 // ------------------------------------------------------------------ direct 3x3 convolution
 
-// The 3x3 convolutions with 32 outputs (the 32-channel top level: M = every
-// pixel of the batch, N = 32, K = 9 C) as a direct convolution: a workgroup
-// takes an 8 x 16 pixel tile of one image, stages the tile's input with its
+// The 3x3 convolutions (M = every pixel of the batch, N = output channels, a
+// multiple of 32, K = 9 C) as a direct convolution: a workgroup takes an
+// 8 x 16 pixel tile of one image and 32 of the output channels (blockIdx.y),
+// stages the tile's input with its
 // one-pixel halo (10 x 18 pixels, 32 channels at a time) and the weights of
 // those channels for the nine taps in LDS once, and multiplies each tap's
 // shifted view of the halo with the 16x16x32 MFMA, so a pixel's input is read
@@ -290,6 +291,7 @@ __global__ __launch_bounds__(256) void conv3_kernel(GemmDesc d) {
   blk /= tiles_x;
   const int ty = blk % tiles_y, b = blk / tiles_y;
   const int x0 = tx * kCvTW, y0 = ty * kCvTH;
+  const int n0 = 32 * blockIdx.y;  // the workgroup's output channels n0 .. n0 + 31
   const int t = threadIdx.x, wave = t / 64, lane = t % 64;
   v4f acc[2][2];
 #pragma unroll
@@ -307,11 +309,11 @@ __global__ __launch_bounds__(256) void conv3_kernel(GemmDesc d) {
         w = *reinterpret_cast<const uint4*>(v.p + ((int64_t)(b * H + yy) * W + xx) * v.pitch + v.off + c0 + 8 * cv);
       *reinterpret_cast<uint4*>(halo + px * kCvLD + 8 * cv) = w;
     }
-    // weights of the chunk: w[n][tap C + c0 + c] for 32 n, 9 taps, 32 c
+    // weights of the chunk: w[n0 + n][tap C + c0 + c] for 32 n, 9 taps, 32 c
     for (int e = t; e < 9 * 32 * 4; e += 256) {
       const int cv = e % 4, row = e / 4;  // row = tap * 32 + n
       const int tap = row / 32, n = row % 32;
-      const uint4 w = *reinterpret_cast<const uint4*>(d.w + (int64_t)n * d.K + tap * C + c0 + 8 * cv);
+      const uint4 w = *reinterpret_cast<const uint4*>(d.w + (int64_t)(n0 + n) * d.K + tap * C + c0 + 8 * cv);
       *reinterpret_cast<uint4*>(wts + row * kCvLD + 8 * cv) = w;
     }
     __syncthreads();
@@ -342,7 +344,7 @@ __global__ __launch_bounds__(256) void conv3_kernel(GemmDesc d) {
     const int y = y0 + wave * 2 + i;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      const int n = j * 16 + lane % 16;
+      const int n = n0 + j * 16 + lane % 16;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int x = x0 + 4 * (lane / 16) + r;
@@ -362,7 +364,7 @@ __global__ __launch_bounds__(256) void conv3_kernel(GemmDesc d) {
 static bool conv3_applies(const GemmDesc& d) {
   const View& v = d.a;
   return d.a_mode == A_CONV && d.b_mode == B_W && d.out_mode == E_ACT && d.a_vec == 1 && d.b_vec == 1 &&
-         d.N == 32 && d.ksplit >= d.K && v.C % 32 == 0 && d.K == 9 * v.C && v.H % kCvTH == 0 &&
+         d.N % 32 == 0 && d.ksplit >= d.K && v.C % 32 == 0 && d.K == 9 * v.C && v.H % kCvTH == 0 &&
          v.W % kCvTW == 0 && v.H > 0 && v.W > 0 && d.M % (v.H * v.W) == 0;
 }
 
@@ -522,7 +524,7 @@ void launch_gemm(const GemmDesc& d_in, hipStream_t s) {
   auto blocks = [&](int tm, int tn) { return (int64_t)((d.M + tm - 1) / tm) * ((d.N + tn - 1) / tn) * nsplit; };
   if (conv3_applies(d)) {
     const int64_t n_blk = (int64_t)(d.M / (d.a.H * d.a.W)) * (d.a.H / kCvTH) * (d.a.W / kCvTW);
-    hipLaunchKernelGGL(conv3_kernel, dim3((unsigned)n_blk), dim3(256), 0, s, d);
+    hipLaunchKernelGGL(conv3_kernel, dim3((unsigned)n_blk, (unsigned)(d.N / 32)), dim3(256), 0, s, d);
   } else if (d.N <= 32) {
     launch_tile<4, 1, 2, 2>(d, dim3((d.M + 127) / 128, (d.N + 31) / 32, nsplit), s);
   } else if (d.M <= 32) {

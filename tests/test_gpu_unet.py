@@ -74,8 +74,10 @@ def test_parameter_count_matches_oracle(cout):
     lib.pat_warmstart_destroy(h)
 
 
+# (4, 32, 1, 128, 128, 3): every level's 3x3 convolutions take the direct
+# convolution kernel (sides multiples of 8 x 16 down to the 16 x 16 bottom)
 @pytest.mark.parametrize("shape", [(4, 8, 2, 16, 24, 1), (3, 4, 1, 8, 8, 1), (4, 32, 1, 32, 32, 1),
-                                   (4, 8, 2, 16, 24, 3)])
+                                   (4, 8, 2, 16, 24, 3), (4, 32, 1, 128, 128, 3)])
 def test_forward_matches_oracle(shape):
     levels, base, B, H, W, cout = shape
     lib, h, n, p, x, t = _setup(levels, base, B, H, W, cout=cout)
@@ -116,7 +118,8 @@ def _check_gradients(lib, h, n, p, x, t, levels, base, B, H, W, cout):
 TOL_GRAD_TENSOR = 5e-2
 
 
-@pytest.mark.parametrize("shape", [(4, 8, 2, 16, 24, 1), (3, 4, 1, 8, 8, 1), (4, 8, 2, 16, 24, 3)])
+@pytest.mark.parametrize("shape", [(4, 8, 2, 16, 24, 1), (3, 4, 1, 8, 8, 1), (4, 8, 2, 16, 24, 3),
+                                   (4, 32, 1, 128, 128, 3)])
 def test_gradients_match_oracle(shape):
     levels, base, B, H, W, cout = shape
     lib, h, n, p, x, t = _setup(levels, base, B, H, W, cout=cout)
