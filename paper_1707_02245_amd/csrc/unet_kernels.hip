@@ -267,20 +267,22 @@ struct ChunkRegs {
 // ------------------------------------------------------------------ direct 3x3 convolution
 
 // The 3x3 convolutions (M = every pixel of the batch, N = output channels, a
-// multiple of 32, K = 9 C) as a direct convolution: a workgroup takes an
-// 8 x 16 pixel tile of one image and 32 of the output channels (blockIdx.y),
-// stages the tile's input with its
-// one-pixel halo (10 x 18 pixels, 32 channels at a time) and the weights of
-// those channels for the nine taps in LDS once, and multiplies each tap's
+// multiple of 32, K = 9 C) as a direct convolution: a workgroup of 8 waves
+// takes a 16 x 16 pixel tile of one image (two rows per wave) and 32 of the
+// output channels (blockIdx.y), stages the tile's input with its one-pixel
+// halo (18 x 18 pixels, 32 channels at a time) and the weights of those
+// channels for the nine taps in LDS once, and multiplies each tap's
 // shifted view of the halo with the 16x16x32 MFMA, so a pixel's input is read
 // from memory once per channel chunk instead of once per tap. Channels and
 // weight rows are padded to 40 elements in LDS (an 80-byte stride puts the 16
 // rows a fragment reads in distinct banks). a_sign = -1 (the data gradient)
 // reads the taps mirrored, as the GEMM's index map does. Accumulation: per
-// chunk of 32 channels, taps in order.
-constexpr int kCvTH = 8, kCvTW = 16, kCvHH = kCvTH + 2, kCvHW = kCvTW + 2, kCvLD = 40;
+// chunk of 32 channels, taps in order. (16 x 16 tiles took the training step
+// 2.64 -> 2.51 ms against 8 x 16 tiles of 4 waves: the weights are staged for
+// twice as many pixels.)
+constexpr int kCvTH = 16, kCvTW = 16, kCvHH = kCvTH + 2, kCvHW = kCvTW + 2, kCvLD = 40, kCvThreads = 512;
 
-__global__ __launch_bounds__(256) void conv3_kernel(GemmDesc d) {
+__global__ __launch_bounds__(kCvThreads) void conv3_kernel(GemmDesc d) {
   __shared__ __align__(16) uint16_t halo[kCvHH * kCvHW * kCvLD];
   __shared__ __align__(16) uint16_t wts[9 * 32 * kCvLD];
   const View& v = d.a;
@@ -300,7 +302,7 @@ __global__ __launch_bounds__(256) void conv3_kernel(GemmDesc d) {
     for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
   for (int c0 = 0; c0 < C; c0 += 32) {
     // halo: 10 x 18 pixels x 32 channels as 16-byte vectors of 8 channels
-    for (int e = t; e < kCvHH * kCvHW * 4; e += 256) {
+    for (int e = t; e < kCvHH * kCvHW * 4; e += kCvThreads) {
       const int cv = e % 4, px = e / 4;
       const int hx = px % kCvHW, hy = px / kCvHW;
       const int yy = y0 + hy - 1, xx = x0 + hx - 1;
@@ -310,7 +312,7 @@ __global__ __launch_bounds__(256) void conv3_kernel(GemmDesc d) {
       *reinterpret_cast<uint4*>(halo + px * kCvLD + 8 * cv) = w;
     }
     // weights of the chunk: w[n0 + n][tap C + c0 + c] for 32 n, 9 taps, 32 c
-    for (int e = t; e < 9 * 32 * 4; e += 256) {
+    for (int e = t; e < 9 * 32 * 4; e += kCvThreads) {
       const int cv = e % 4, row = e / 4;  // row = tap * 32 + n
       const int tap = row / 32, n = row % 32;
       const uint4 w = *reinterpret_cast<const uint4*>(d.w + (int64_t)(n0 + n) * d.K + tap * C + c0 + 8 * cv);
@@ -524,7 +526,7 @@ void launch_gemm(const GemmDesc& d_in, hipStream_t s) {
   auto blocks = [&](int tm, int tn) { return (int64_t)((d.M + tm - 1) / tm) * ((d.N + tn - 1) / tn) * nsplit; };
   if (conv3_applies(d)) {
     const int64_t n_blk = (int64_t)(d.M / (d.a.H * d.a.W)) * (d.a.H / kCvTH) * (d.a.W / kCvTW);
-    hipLaunchKernelGGL(conv3_kernel, dim3((unsigned)n_blk, (unsigned)(d.N / 32)), dim3(256), 0, s, d);
+    hipLaunchKernelGGL(conv3_kernel, dim3((unsigned)n_blk, (unsigned)(d.N / 32)), dim3(kCvThreads), 0, s, d);
   } else if (d.N <= 32) {
     launch_tile<4, 1, 2, 2>(d, dim3((d.M + 127) / 128, (d.N + 31) / 32, nsplit), s);
   } else if (d.M <= 32) {
