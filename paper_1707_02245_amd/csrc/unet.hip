@@ -146,8 +146,8 @@ static void ensure_act(pat_unet_s* n, int B, int H, int W) {
   a.g_s3.alloc(h * px(L3) * n->ch(L3));
   a.ws.alloc(kWorkspace);
   // per-block partial sums: bias gradients (256 pixels per block, up to 2 C
-  // channels) and the head (1024 pixels per block, cout (C0 + 1) sums)
-  int64_t part = (px(0) + 1023) / 1024 * n->cout * (n->ch(0) + 1);
+  // channels) and the head (256 pixels per block, cout (C0 + 1) sums)
+  int64_t part = (px(0) + 255) / 256 * n->cout * (n->ch(0) + 1);
   for (int l = 0; l < n->levels; ++l) part = std::max<int64_t>(part, (px(l) + 255) / 256 * 2 * n->ch(l));
   a.part.alloc(sizeof(float) * part);
   a.loss_part.alloc(sizeof(double) * ((px(0) * n->cout + 255) / 256 + 1));
@@ -342,7 +342,7 @@ static void backward(pat_unet_s* n, hipStream_t s) {
   // head: gh = bf16(sum_k gy_k w_k) * (ub0 > 0)
   const int C0 = n->ch(0);
   View g = gview(a.g_ub[0], 0, C0, C0, 0);
-  const int rows = 1024;
+  const int rows = 256;
   const int nblk = (int)((P0 + rows - 1) / rows);
   launch_head_back(v.ub[0], ptr<float>(n->params) + n->head_w, ptr<float>(a.gy), g, ptr<float>(a.part), P0,
                    n->cout, (int64_t)a.H * a.W, rows, s);

@@ -625,18 +625,116 @@ __global__ __launch_bounds__(256) void maxpool_back_kernel(View gout, const uint
   }
 }
 
+// The same two operations on 8 channels per thread (16-byte loads and stores of
+// the activations, 8-byte ones of the window indices), element by element the
+// same arithmetic; taken when every view's channels, pitch and offset are
+// multiples of 8 and the pointers 16-byte aligned. Index e runs over
+// (pixel, channel group) pairs; the divisions by C / 8, the width and the
+// height take their host-computed multiply-high constants.
+__device__ __forceinline__ uint16_t half16(const uint32_t (&w)[4], int i) {
+  return (uint16_t)(w[i >> 1] >> (16 * (i & 1)));
+}
+
+__global__ __launch_bounds__(256) void maxpool8_kernel(View in, View out, uint8_t* __restrict__ idx,
+                                                       uint32_t total, FastDiv dG, FastDiv dW2, FastDiv dH2) {
+  const int C = in.C;
+  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    uint32_t p, cg, t, x, b, y;
+    fast_divmod(e, dG, p, cg);
+    fast_divmod(p, dW2, t, x);
+    fast_divmod(t, dH2, b, y);
+    const int c = 8 * (int)cg;
+    uint32_t w[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t src = (int64_t)(b * in.H + 2 * y + (q >> 1)) * in.W + 2 * x + (q & 1);
+      const uint4 v = *reinterpret_cast<const uint4*>(in.p + src * in.pitch + in.off + c);
+      w[q][0] = v.x; w[q][1] = v.y; w[q][2] = v.z; w[q][3] = v.w;
+    }
+    uint32_t o[4] = {0u, 0u, 0u, 0u}, ix[2] = {0u, 0u};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      float best = -INFINITY;
+      int bi = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float v = bf2f(half16(w[q], i));
+        if (v > best) { best = v; bi = q; }
+      }
+      o[i >> 1] |= (uint32_t)f2bf(best) << (16 * (i & 1));
+      ix[i >> 2] |= (uint32_t)bi << (8 * (i & 3));
+    }
+    *reinterpret_cast<uint4*>(out.p16 + (int64_t)p * out.pitch + out.off + c) = make_uint4(o[0], o[1], o[2], o[3]);
+    *reinterpret_cast<uint2*>(idx + (int64_t)p * C + c) = make_uint2(ix[0], ix[1]);
+  }
+}
+
+__global__ __launch_bounds__(256) void maxpool_back8_kernel(View gout, const uint8_t* __restrict__ idx,
+                                                            View gskip, View act, View gin, uint32_t total,
+                                                            FastDiv dG, FastDiv dW, FastDiv dH) {
+  const int C = gin.C, W2 = gin.W / 2, H2 = gin.H / 2;
+  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    uint32_t p, cg, t, x, b, y;
+    fast_divmod(e, dG, p, cg);
+    fast_divmod(p, dW, t, x);
+    fast_divmod(t, dH, b, y);
+    const int c = 8 * (int)cg;
+    const int64_t q = (int64_t)(b * H2 + y / 2) * W2 + x / 2;
+    const uint32_t pos = ((y & 1) << 1) | (x & 1);
+    const uint2 iv = *reinterpret_cast<const uint2*>(idx + q * C + c);
+    const uint4 go = *reinterpret_cast<const uint4*>(gout.p + q * gout.pitch + gout.off + c);
+    const uint4 gs = *reinterpret_cast<const uint4*>(gskip.p + (int64_t)p * gskip.pitch + gskip.off + c);
+    const uint4 av = *reinterpret_cast<const uint4*>(act.p + (int64_t)p * act.pitch + act.off + c);
+    const uint32_t wo[4] = {go.x, go.y, go.z, go.w}, ws[4] = {gs.x, gs.y, gs.z, gs.w},
+                   wa[4] = {av.x, av.y, av.z, av.w}, wi[2] = {iv.x, iv.y};
+    uint32_t o[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const uint32_t sel = (wi[i >> 2] >> (8 * (i & 3))) & 0xffu;
+      float v = (sel == pos) ? bf2f(half16(wo, i)) : 0.f;
+      v += bf2f(half16(ws, i));
+      uint16_t h = f2bf(v);
+      if (!(bf2f(half16(wa, i)) > 0.f)) h = 0;
+      o[i >> 1] |= (uint32_t)h << (16 * (i & 1));
+    }
+    *reinterpret_cast<uint4*>(gin.p16 + (int64_t)p * gin.pitch + gin.off + c) = make_uint4(o[0], o[1], o[2], o[3]);
+  }
+}
+
+static bool vec8_view(const View& v) {
+  return v.C % 8 == 0 && v.pitch % 8 == 0 && v.off % 8 == 0 &&
+         (reinterpret_cast<uintptr_t>(v.p) & 15) == 0;
+}
+
 void launch_maxpool(const View& in, const View& out, uint8_t* idx, int B, hipStream_t s) {
   const int64_t total = (int64_t)B * (in.H / 2) * (in.W / 2) * in.C;
-  const int blocks = (int)std::min<int64_t>((total + 255) / 256, 16384);
-  hipLaunchKernelGGL(maxpool_kernel, dim3(blocks), dim3(256), 0, s, in, out, idx, B);
+  if (vec8_view(in) && vec8_view(out) && (reinterpret_cast<uintptr_t>(idx) & 7) == 0 && total / 8 < (1ll << 31)) {
+    const int64_t groups = total / 8;
+    const int blocks = (int)std::min<int64_t>((groups + 255) / 256, 16384);
+    hipLaunchKernelGGL(maxpool8_kernel, dim3(blocks), dim3(256), 0, s, in, out, idx, (uint32_t)groups,
+                       make_fastdiv((uint32_t)(in.C / 8)), make_fastdiv((uint32_t)(in.W / 2)),
+                       make_fastdiv((uint32_t)(in.H / 2)));
+  } else {
+    const int blocks = (int)std::min<int64_t>((total + 255) / 256, 16384);
+    hipLaunchKernelGGL(maxpool_kernel, dim3(blocks), dim3(256), 0, s, in, out, idx, B);
+  }
   PAT_HIP(hipGetLastError());
 }
 
 void launch_maxpool_back(const View& gout, const uint8_t* idx, const View& gskip, const View& act,
                          const View& gin, int B, hipStream_t s) {
   const int64_t total = (int64_t)B * gin.H * gin.W * gin.C;
-  const int blocks = (int)std::min<int64_t>((total + 255) / 256, 16384);
-  hipLaunchKernelGGL(maxpool_back_kernel, dim3(blocks), dim3(256), 0, s, gout, idx, gskip, act, gin, B);
+  if (vec8_view(gout) && vec8_view(gskip) && vec8_view(act) && vec8_view(gin) &&
+      (reinterpret_cast<uintptr_t>(idx) & 7) == 0 && total / 8 < (1ll << 31)) {
+    const int64_t groups = total / 8;
+    const int blocks = (int)std::min<int64_t>((groups + 255) / 256, 16384);
+    hipLaunchKernelGGL(maxpool_back8_kernel, dim3(blocks), dim3(256), 0, s, gout, idx, gskip, act, gin,
+                       (uint32_t)groups, make_fastdiv((uint32_t)(gin.C / 8)), make_fastdiv((uint32_t)gin.W),
+                       make_fastdiv((uint32_t)gin.H));
+  } else {
+    const int blocks = (int)std::min<int64_t>((total + 255) / 256, 16384);
+    hipLaunchKernelGGL(maxpool_back_kernel, dim3(blocks), dim3(256), 0, s, gout, idx, gskip, act, gin, B);
+  }
   PAT_HIP(hipGetLastError());
 }
 
@@ -725,7 +823,79 @@ __global__ __launch_bounds__(256) void head_back_kernel(View h, const float* __r
   const int C = h.C;
   const int64_t p0 = (int64_t)blockIdx.x * rows_per_block;
   const int64_t p1 = min(P, p0 + rows_per_block);
-  if (C <= 256 && 256 % C == 0 && K <= 4) {
+  if (C % 8 == 0 && C <= 256 && 256 % (C / 8) == 0 && K <= 4 && h.pitch % 8 == 0 && h.off % 8 == 0 &&
+      gh.pitch % 8 == 0 && gh.off % 8 == 0 && (reinterpret_cast<uintptr_t>(h.p) & 15) == 0 &&
+      (reinterpret_cast<uintptr_t>(gh.p16) & 15) == 0) {
+    // thread t: channels 8 (t % (C/8)) .. + 7 of every (256 / (C/8))-th pixel
+    // from the (t / (C/8))-th, by 16-byte loads and stores; lane sums added
+    // in lane order
+    const int groups = C / 8, lanes = 256 / groups, cg = threadIdx.x % groups, r = threadIdx.x / groups;
+    float sw[4][8], sb[4] = {0.f, 0.f, 0.f, 0.f}, wq[4][8];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        sw[k][i] = 0.f;
+        wq[k][i] = k < K ? bf2f(f2bf(w[k * C + 8 * cg + i])) : 0.f;
+      }
+    }
+    for (int64_t p = p0 + r; p < p1; p += lanes) {
+      const uint4 hv4 = *reinterpret_cast<const uint4*>(h.p + p * h.pitch + h.off + 8 * cg);
+      const uint32_t hw32[4] = {hv4.x, hv4.y, hv4.z, hv4.w};
+      uint32_t img, pix;
+      fast_divmod((uint32_t)p, dhw, img, pix);
+      const int64_t g0 = (int64_t)img * K * hw + pix;
+      float g[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        g[k] = k < K ? gy[g0 + k * hw] : 0.f;
+        sb[k] += g[k];
+      }
+      uint32_t o[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const float hv = bf2f((uint16_t)(hw32[i >> 1] >> (16 * (i & 1))));
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (k < K) {
+            sw[k][i] += g[k] * hv;
+            acc += g[k] * wq[k][i];
+          }
+        }
+        uint16_t v = f2bf(acc);
+        if (!(hv > 0.f)) v = 0;
+        o[i >> 1] |= (uint32_t)v << (16 * (i & 1));
+      }
+      *reinterpret_cast<uint4*>(gh.p16 + p * gh.pitch + gh.off + 8 * cg) = make_uint4(o[0], o[1], o[2], o[3]);
+    }
+    // one output k at a time through 8 KB of LDS
+    __shared__ float l8[8][256];
+    float* out = part + (int64_t)blockIdx.x * K * (C + 1);
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) l8[i][threadIdx.x] = sw[k][i];
+      __syncthreads();
+      if (threadIdx.x < C) {
+        const int c = threadIdx.x, g8 = c / 8, i = c % 8;
+        float s = l8[i][g8];
+        for (int l = 1; l < lanes; ++l) s += l8[i][l * groups + g8];
+        out[k * C + c] = s;
+      }
+      __syncthreads();
+    }
+    // the bias sums: the lanes of channel group 0 saw every pixel once
+#pragma unroll
+    for (int k = 0; k < 4; ++k) l8[k][threadIdx.x] = sb[k];
+    __syncthreads();
+    if (threadIdx.x < K) {
+      const int k = threadIdx.x;
+      float s = l8[k][0];
+      for (int l = 1; l < lanes; ++l) s += l8[k][l * groups];
+      out[K * C + k] = s;
+    }
+    return;
+  } else if (C <= 256 && 256 % C == 0 && K <= 4) {
     // thread t: channel t % C over every (256 / C)-th pixel from the (t / C)-th;
     // lane sums added in lane order
     // with the data gradient of the same pixels and channel
