@@ -44,16 +44,16 @@ _SRC_FWD = dict([("paper_1707_02245_amd/csrc/projector.hip",
 _SRC_ADJ = dict([("paper_1707_02245_amd/csrc/csr.hip",
                   "3040aa591c28c22f8e93010f102c44657b3b859840285bf95ee966a505330612"), _COMMON])
 _SRC_FMAT = dict([("paper_1707_02245_amd/csrc/fmat.hip",
-                   "a422703fa2ce9934c68b8f4bc7ef1abf1d14a55c33b70a7d92cce0d8c8b68e23"),
+                   "2cb2ab07444bdd58359cc4649efe70fcdc0d230c960337e2738ea982f588734a"),
                   ("paper_1707_02245_amd/csrc/fwd_epilogue.hpp",
                    "e8308bc255c13bd6e6b36f8e6a7bb41666da4a8efe5470fdf8b3331cc7a56af9"), _COMMON])
 MEASURED_TRAFFIC = [
     # profiles/fwd_paths_tgv256_f64_counters.md (one counter run of the forward-path sequence)
     {"kernel": "fwd_kernel<double, 0, 16, false, 1, false>", "bytes_per_launch": 46.11e6, "sources": _SRC_FWD},
-    # both passes of the stored A (path 3): 163.49 + 18.43 MB and 26.39 + 1.05 MB
-    {"kernel": "fmat_kernel<double, false> + fmat_reduce_kernel<double, 0>", "bytes_per_launch": 209.36e6,
+    # both passes of the stored A (path 3): 163.54 + 18.43 MB and 26.39 + 1.05 MB
+    {"kernel": "fmat_kernel<double, false> + fmat_reduce_kernel<double, 0>", "bytes_per_launch": 209.41e6,
      "sources": _SRC_FMAT},
-    {"kernel": "csr_tiled_kernel<double, false, 4, 256, 16>", "bytes_per_launch": 187.84e6, "sources": _SRC_ADJ},
+    {"kernel": "csr_tiled_kernel<double, false, 4, 256, 16>", "bytes_per_launch": 187.80e6, "sources": _SRC_ADJ},
 ]
 
 
