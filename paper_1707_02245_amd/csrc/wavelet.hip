@@ -240,9 +240,11 @@ struct WavSynArgs {
 // k = 2 a + dy - shift from position Y - a (mod cy/2), for a = 0, 1 (and 2
 // when the shift is 1, at level 1), each valid k once: the positions of
 // offsets a, b in {0, 1, 2} hold every term. Their 16 values (12 oriented
-// detail bands, 4 lowpass) are read once per thread and turned back into the
-// trees' subbands (the transposed band combination).
-template <class T, class A, bool FIRST>
+// detail bands, 4 lowpass) are turned back into the trees' subbands (the
+// transposed band combination). This kernel serves the levels from 2 on
+// (no shifts: offsets 0 and 1), reading each position's values once per
+// thread; level 1 is wav_synthesis1_kernel below.
+template <class T, class A>
 __global__ __launch_bounds__(256) void wav_synthesis_kernel(WavSynArgs<T, A> a) {
   const int hx = a.cx >> 1, hy = a.cy >> 1;
   const int64_t S = (int64_t)hx * hy;
@@ -250,7 +252,7 @@ __global__ __launch_bounds__(256) void wav_synthesis_kernel(WavSynArgs<T, A> a) 
   if (e >= S) return;
   const int X = (int)(e % hx), Y = (int)(e / hx);
   const A kc = (A)a.f.kc;
-  constexpr int NA = FIRST ? 3 : 2;
+  constexpr int NA = 2;
   A acc[4][2][2];  // [tree][dy][dx]
 #pragma unroll
   for (int t = 0; t < 4; ++t)
@@ -281,16 +283,13 @@ __global__ __launch_bounds__(256) void wav_synthesis_kernel(WavSynArgs<T, A> a) 
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int ty = t >> 1, tx = t & 1;
-        const int sy = FIRST ? ty : 0, sx = FIRST ? tx : 0;
 #pragma unroll
         for (int dy = 0; dy < 2; ++dy) {
-          const int ky = 2 * ay + dy - sy;
-          if (ky < 0 || ky > 3) continue;
+          const int ky = 2 * ay + dy;
           const A ly = (A)a.f.lo[ty][ky], gy = (A)a.f.hi[ty][ky];
 #pragma unroll
           for (int dx = 0; dx < 2; ++dx) {
-            const int kx = 2 * ax + dx - sx;
-            if (kx < 0 || kx > 3) continue;
+            const int kx = 2 * ax + dx;
             const A lx = (A)a.f.lo[tx][kx], gx = (A)a.f.hi[tx][kx];
             acc[t][dy][dx] += ly * (lx * sub[t][0] + gx * sub[t][1]) + gy * (lx * sub[t][2] + gx * sub[t][3]);
           }
@@ -304,13 +303,89 @@ __global__ __launch_bounds__(256) void wav_synthesis_kernel(WavSynArgs<T, A> a) 
     const int64_t row = (int64_t)(2 * Y + dy) * a.cx + 2 * X;
 #pragma unroll
     for (int dx = 0; dx < 2; ++dx) {
-      if (FIRST) {
-        a.out[row + dx] = (acc[0][dy][dx] + acc[1][dy][dx]) + (acc[2][dy][dx] + acc[3][dy][dx]);
-      } else {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) a.ll_out[t * n + row + dx] = acc[t][dy][dx];
+      for (int t = 0; t < 4; ++t) a.ll_out[t * n + row + dx] = acc[t][dy][dx];
+    }
+  }
+}
+
+// Level 1 by tiles of 16 x 16 positions. The positions a tile's threads
+// reach (the tile and the two position rows and columns before it, periodic)
+// are turned into the trees' subbands once and kept in LDS, band-major, so
+// that every coefficient is read from memory about 1.27 times instead of
+// once per neighbour that uses it (nine times); each thread then sums its
+// 3 x 3 neighbourhood in the same order and with the same values as
+// wav_synthesis_kernel at level 1.
+constexpr int kWsT = 16, kWsH = kWsT + 2, kWsP = kWsH * kWsH;
+
+template <class T, class A>
+__global__ __launch_bounds__(256) void wav_synthesis1_kernel(WavSynArgs<T, A> a) {
+  __shared__ A sl[16][kWsP];  // [tree * 4 + band][position in the haloed tile]
+  const int hx = a.cx >> 1, hy = a.cy >> 1;
+  const int64_t S = (int64_t)hx * hy;
+  const int tiles_x = (hx + kWsT - 1) / kWsT;
+  const int64_t tile = xcd_block();
+  const int X0 = (int)(tile % tiles_x) * kWsT, Y0 = (int)(tile / tiles_x) * kWsT;
+  const A kc = (A)a.f.kc;
+  for (int q = threadIdx.x; q < kWsP; q += 256) {
+    const int ly = q / kWsH, lx = q - ly * kWsH;
+    const int iy = ((Y0 - 2 + ly) % hy + hy) % hy, ix = ((X0 - 2 + lx) % hx + hx) % hx;
+    const int64_t pos = (int64_t)iy * hx + ix;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      sl[4 * t][q] = a.ll_off >= 0 ? A(0.5) * (A)a.coef[a.ll_off + t * S + pos] : a.ll_in[t * S + pos];
+#pragma unroll
+    for (int o = 0; o < 3; ++o) {
+      const T* c = a.coef + a.band_off + (int64_t)(4 * o) * S + pos;
+      const A p = (A)c[0], r = (A)c[S], s = (A)c[2 * S], u = (A)c[3 * S];
+      sl[o + 1][q] = kc * (p + r);       // aa
+      sl[4 + o + 1][q] = kc * (s + u);   // ab
+      sl[8 + o + 1][q] = kc * (s - u);   // ba
+      sl[12 + o + 1][q] = kc * (r - p);  // bb
+    }
+  }
+  __syncthreads();
+  const int tx = threadIdx.x % kWsT, ty = threadIdx.x / kWsT;
+  const int X = X0 + tx, Y = Y0 + ty;
+  if (X >= hx || Y >= hy) return;
+  A acc[4][2][2];  // [tree][dy][dx]
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 2; ++dx) acc[t][dy][dx] = A(0);
+#pragma unroll
+  for (int ay = 0; ay < 3; ++ay) {
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const int q = (ty + 2 - ay) * kWsH + (tx + 2 - ax);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int fy = t >> 1, fx = t & 1;
+        const A s0 = sl[4 * t][q], s1 = sl[4 * t + 1][q], s2 = sl[4 * t + 2][q], s3 = sl[4 * t + 3][q];
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+          const int ky = 2 * ay + dy - fy;
+          if (ky < 0 || ky > 3) continue;
+          const A ly = (A)a.f.lo[fy][ky], gy = (A)a.f.hi[fy][ky];
+#pragma unroll
+          for (int dx = 0; dx < 2; ++dx) {
+            const int kx = 2 * ax + dx - fx;
+            if (kx < 0 || kx > 3) continue;
+            const A lx = (A)a.f.lo[fx][kx], gx = (A)a.f.hi[fx][kx];
+            acc[t][dy][dx] += ly * (lx * s0 + gx * s1) + gy * (lx * s2 + gx * s3);
+          }
+        }
       }
     }
+  }
+#pragma unroll
+  for (int dy = 0; dy < 2; ++dy) {
+    const int64_t row = (int64_t)(2 * Y + dy) * a.cx + 2 * X;
+#pragma unroll
+    for (int dx = 0; dx < 2; ++dx)
+      a.out[row + dx] = (acc[0][dy][dx] + acc[1][dy][dx]) + (acc[2][dy][dx] + acc[3][dy][dx]);
   }
 }
 
@@ -388,8 +463,13 @@ static void synthesis(int nx, int ny, int J, const T* coef, A* out, A* work, hip
     a.out = j == 1 ? out : nullptr;
     a.f = wav_filters(j);
     const unsigned grid = blocks_for(band_size(nx, ny, j));
-    if (j == 1) hipLaunchKernelGGL((wav_synthesis_kernel<T, A, true>), dim3(grid), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((wav_synthesis_kernel<T, A, false>), dim3(grid), dim3(256), 0, s, a);
+    if (j == 1) {
+      const int hx = a.cx >> 1, hy = a.cy >> 1;
+      const unsigned tiles = (unsigned)(((hx + kWsT - 1) / kWsT) * ((hy + kWsT - 1) / kWsT));
+      hipLaunchKernelGGL((wav_synthesis1_kernel<T, A>), dim3(tiles), dim3(256), 0, s, a);
+    } else {
+      hipLaunchKernelGGL((wav_synthesis_kernel<T, A>), dim3(grid), dim3(256), 0, s, a);
+    }
     PAT_HIP(hipGetLastError());
   }
 }
