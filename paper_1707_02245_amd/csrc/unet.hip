@@ -215,10 +215,11 @@ static void conv_wgrad(pat_unet_s* n, const Layer& L, const View& x, const View&
   d.b = x;
   d.out_mode = E_SPLIT;
   d.out_f32 = ptr<float>(n->act.ws);
+  const int bnblk = launch_colsum_partials(g, ptr<float>(n->act.part), d.K, 256, s);
   launch_gemm(d, s);
   const int nsplit = (d.K + d.ksplit - 1) / d.ksplit;
-  launch_splitk_reduce(d.out_f32, nsplit, d.M, d.N, ptr<float>(n->grads) + L.w, 0, s);
-  launch_colsum(g, ptr<float>(n->act.part), ptr<float>(n->grads) + L.b, d.K, 256, s);
+  launch_wgrad_reduce(d.out_f32, nsplit, d.M, d.N, ptr<float>(n->grads) + L.w, 0, ptr<float>(n->act.part),
+                      bnblk, g.C, ptr<float>(n->grads) + L.b, s);
 }
 
 // input gradient of a 3x3 convolution (flipped taps), rounded to bf16 and masked
@@ -254,11 +255,12 @@ static void convt_wgrad(pat_unet_s* n, const Layer& L, const View& x, const View
   d.b = x;
   d.out_mode = E_SPLIT;
   d.out_f32 = ptr<float>(n->act.ws);
+  const int bnblk =
+      launch_colsum_partials(g, ptr<float>(n->act.part), (int64_t)n->act.B * g.H * g.W, 256, s);
   launch_gemm(d, s);
   const int nsplit = (d.K + d.ksplit - 1) / d.ksplit;
-  launch_splitk_reduce(d.out_f32, nsplit, d.M, d.N, ptr<float>(n->grads) + L.w, L.cout, s);
-  launch_colsum(g, ptr<float>(n->act.part), ptr<float>(n->grads) + L.b, (int64_t)n->act.B * g.H * g.W,
-                256, s);
+  launch_wgrad_reduce(d.out_f32, nsplit, d.M, d.N, ptr<float>(n->grads) + L.w, L.cout,
+                      ptr<float>(n->act.part), bnblk, g.C, ptr<float>(n->grads) + L.b, s);
 }
 
 static void convt_dgrad(pat_unet_s* n, const Layer& L, const View& g, const View& out, const View& mask,

@@ -59,8 +59,8 @@ struct GemmDesc {
 
 void launch_gemm(const GemmDesc& d, hipStream_t s);
 void set_gemm_tiles(int mode);
-void launch_splitk_reduce(const float* part, int nsplit, int M, int N, float* out, int permute_cout,
-                          hipStream_t s);
+void launch_wgrad_reduce(const float* part, int nsplit, int M, int N, float* out, int permute_cout,
+                         const float* bpart, int bnblk, int bC, float* bout, hipStream_t s);
 void launch_maxpool(const View& in, const View& out, uint8_t* idx, int B, hipStream_t s);
 void launch_maxpool_back(const View& gout, const uint8_t* idx, const View& gskip, const View& act,
                          const View& gin, int B, hipStream_t s);
@@ -70,7 +70,7 @@ void launch_mse(const float* y, const float* t, float* gy, double* part, double*
                 hipStream_t s);
 void launch_head_back(const View& h, const float* w, const float* gy, const View& gh, float* part,
                       int64_t P, int K, int64_t hw, int rows_per_block, hipStream_t s);
-void launch_colsum(const View& g, float* part, float* out, int64_t P, int rows_per_block, hipStream_t s);
+int launch_colsum_partials(const View& g, float* part, int64_t P, int rows_per_block, hipStream_t s);
 void launch_part_reduce(const float* part, int nblk, int C, int ld, float* out, hipStream_t s);
 void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                  float eps, float bc1, float bc2, hipStream_t s);

@@ -543,24 +543,24 @@ void launch_gemm(const GemmDesc& d_in, hipStream_t s) {
 }
 
 // out[m][n] (with optional [ci][co] <- [(a,e,co)][ci] permutation) = sum_z part[z][m][n]
-// A workgroup takes 32 elements; its 8 lanes per element add the partials
-// z = lane, lane + 8, ... and then the 8 lane sums in lane order.
-constexpr int kSplitEl = 32, kSplitLanes = 8;
-__global__ __launch_bounds__(256) void splitk_reduce_kernel(const float* __restrict__ part, int nsplit,
-                                                            int M, int N, float* __restrict__ out,
-                                                            int permute_cout) {
+// A workgroup takes 256 / lanes elements; the lanes of an element add the
+// partials z = lane, lane + lanes, ... and then the lane sums in lane order.
+// lanes (8, 32 or 128) follows from the shape alone: more lanes when the
+// partials are many and the elements too few to fill the device.
+__device__ __forceinline__ void splitk_reduce_block(const float* __restrict__ part, int nsplit, int M, int N,
+                                                    float* __restrict__ out, int permute_cout, int lanes,
+                                                    int blk, float* lds) {
+  const int els = 256 / lanes;
   const int64_t total = (int64_t)M * N;
-  const int el = threadIdx.x % kSplitEl, zl = threadIdx.x / kSplitEl;
-  const int64_t i = (int64_t)blockIdx.x * kSplitEl + el;
+  const int el = threadIdx.x % els, zl = threadIdx.x / els;
+  const int64_t i = (int64_t)blk * els + el;
   float s = 0.f;
   if (i < total)
-    for (int z = zl; z < nsplit; z += kSplitLanes) s += part[(int64_t)z * total + i];
-  __shared__ float lds[256];
+    for (int z = zl; z < nsplit; z += lanes) s += part[(int64_t)z * total + i];
   lds[threadIdx.x] = s;
   __syncthreads();
   if (zl == 0 && i < total) {
-#pragma unroll
-    for (int l = 1; l < kSplitLanes; ++l) s += lds[l * kSplitEl + el];
+    for (int l = 1; l < lanes; ++l) s += lds[l * els + el];
     if (permute_cout > 0) {
       // row m = sub * Cout + co, column n = ci -> [sub][ci][co]
       const int m = (int)(i / N), n = (int)(i % N);
@@ -572,12 +572,46 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const float* __restr
   }
 }
 
-void launch_splitk_reduce(const float* part, int nsplit, int M, int N, float* out, int permute_cout,
-                          hipStream_t s) {
+static int splitk_lanes(int nsplit, int64_t total) {
+  int lanes = 8;
+  while (lanes < 128 && 4 * lanes <= nsplit && (total * lanes + 255) / 256 < 1024) lanes *= 4;
+  return lanes;
+}
+
+// out[c] = sum over the nblk rows of part[.][c] (ld floats per row), one
+// workgroup per column
+__device__ __forceinline__ void part_reduce_block(const float* __restrict__ part, int nblk, int ld,
+                                                  float* __restrict__ out, int c) {
+  float s = 0.f;
+  for (int b = threadIdx.x; b < nblk; b += 256) s += part[(int64_t)b * ld + c];
+  __shared__ float lds[8];
+  s = block_sum<256>(s, lds);
+  if (threadIdx.x == 0) out[c] = s;
+}
+
+// A weight gradient's two reductions in one launch: workgroups [0, nb_split)
+// sum its split-K partials, the next bC workgroups the bias column sums'
+// per-workgroup partials (bnblk rows of bC).
+__global__ __launch_bounds__(256) void wgrad_reduce_kernel(const float* __restrict__ part, int nsplit, int M,
+                                                           int N, float* __restrict__ out, int permute_cout,
+                                                           int lanes, int nb_split,
+                                                           const float* __restrict__ bpart, int bnblk, int bC,
+                                                           float* __restrict__ bout) {
+  __shared__ float lds[256];
+  if ((int)blockIdx.x < nb_split)
+    splitk_reduce_block(part, nsplit, M, N, out, permute_cout, lanes, blockIdx.x, lds);
+  else
+    part_reduce_block(bpart, bnblk, bC, bout, (int)blockIdx.x - nb_split);
+}
+
+void launch_wgrad_reduce(const float* part, int nsplit, int M, int N, float* out, int permute_cout,
+                         const float* bpart, int bnblk, int bC, float* bout, hipStream_t s) {
   const int64_t total = (int64_t)M * N;
-  const int blocks = (int)((total + kSplitEl - 1) / kSplitEl);
-  hipLaunchKernelGGL(splitk_reduce_kernel, dim3(blocks), dim3(256), 0, s, part, nsplit, M, N, out,
-                     permute_cout);
+  const int lanes = splitk_lanes(nsplit, total);
+  const int els = 256 / lanes;
+  const int nb_split = (int)((total + els - 1) / els);
+  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(nb_split + bC), dim3(256), 0, s, part, nsplit, M, N, out,
+                     permute_cout, lanes, nb_split, bpart, bnblk, bC, bout);
   PAT_HIP(hipGetLastError());
 }
 
@@ -1035,20 +1069,17 @@ __global__ __launch_bounds__(256) void colsum_kernel(View g, float* __restrict__
 // threads stride the blocks, then a fixed reduction tree (deterministic)
 __global__ __launch_bounds__(256) void part_reduce_kernel(const float* __restrict__ part, int nblk,
                                                           int C, int ld, float* __restrict__ out) {
-  const int c = blockIdx.x;
-  if (c >= C) return;
-  float s = 0.f;
-  for (int b = threadIdx.x; b < nblk; b += 256) s += part[(int64_t)b * ld + c];
-  __shared__ float lds[8];
-  s = block_sum<256>(s, lds);
-  if (threadIdx.x == 0) out[c] = s;
+  if ((int)blockIdx.x >= C) return;
+  part_reduce_block(part, nblk, ld, out, blockIdx.x);
 }
 
-void launch_colsum(const View& g, float* part, float* out, int64_t P, int rows_per_block, hipStream_t s) {
+// the bias column sums' per-workgroup partials (rows_per_block pixels each);
+// returns the number of partial rows
+int launch_colsum_partials(const View& g, float* part, int64_t P, int rows_per_block, hipStream_t s) {
   const int nblk = (int)((P + rows_per_block - 1) / rows_per_block);
   hipLaunchKernelGGL(colsum_kernel, dim3(nblk), dim3(256), 0, s, g, part, P, rows_per_block);
-  hipLaunchKernelGGL(part_reduce_kernel, dim3(g.C), dim3(256), 0, s, part, nblk, g.C, g.C, out);
   PAT_HIP(hipGetLastError());
+  return nblk;
 }
 
 void launch_part_reduce(const float* part, int nblk, int C, int ld, float* out, hipStream_t s) {
