@@ -101,13 +101,22 @@ static int dec(const pat_unet_s* n, int l, int j) {                     // j = 0
 }
 
 static void prep_weights(pat_unet_s* n, hipStream_t s) {
-  const float* P = ptr<float>(n->params);
+  PAT_CHECK_ARG(n->layers.size() <= (size_t)kMaxPrepLayers, "too many layers for the weight table");
+  PrepTable t{};
+  int blocks = 0;
   for (const Layer& L : n->layers) {
-    uint16_t* wf = ptr<uint16_t>(n->wf) + L.wf;
-    uint16_t* wd = ptr<uint16_t>(n->wd) + L.wd;
-    if (L.kind == 0) launch_prep_conv(P + L.w, L.cout, L.cin, wf, wd, s);
-    else launch_prep_convt(P + L.w, L.cin, L.cout, wf, wd, s);
+    PrepLayer& e = t.L[t.count++];
+    e.w = L.w;
+    e.wf = L.wf;
+    e.wd = L.wd;
+    e.kind = L.kind;
+    e.cout = L.cout;
+    e.cin = L.cin;
+    e.first_block = blocks;
+    const int64_t elems = (int64_t)(L.kind == 0 ? 9 : 4) * L.cin * L.cout;
+    blocks += (int)((elems + 255) / 256);
   }
+  launch_prep_all(ptr<float>(n->params), ptr<uint16_t>(n->wf), ptr<uint16_t>(n->wd), t, blocks, s);
 }
 
 static void ensure_act(pat_unet_s* n, int B, int H, int W) {
@@ -665,18 +674,17 @@ extern "C" pat_status pat_warmstart_train(pat_unet n, int32_t count, int32_t h, 
     const int per_epoch = count / B;
     std::vector<double> losses;
     pat::DevBuf loss_hist(sizeof(double) * (size_t)per_epoch);
+    pat::DevBuf order_d(sizeof(int) * (size_t)count);
     double last = 0.0;
     for (int ep = 0; ep < opts->epochs; ++ep) {
       std::shuffle(order.begin(), order.end(), rng);
+      // the epoch's order on the device (the copy has read the host vector when
+      // it returns; the vector is reshuffled only after the epoch's synchronisation)
+      PAT_HIP(hipMemcpyAsync(order_d.p, order.data(), sizeof(int) * (size_t)count, hipMemcpyHostToDevice, s));
       for (int bi = 0; bi < per_epoch; ++bi) {
-        for (int j = 0; j < B; ++j) {
-          const int idx = order[(size_t)bi * B + j];
-          PAT_HIP(hipMemcpyAsync(pat::ptr<float>(n->act.t) + j * timg, d_targets + idx * timg,
-                                 sizeof(float) * timg, hipMemcpyDeviceToDevice, s));
-          PAT_HIP(hipMemcpyAsync(pat::ptr<float>(n->act.gy) + j * img, d_inputs + idx * img, sizeof(float) * img,
-                                 hipMemcpyDeviceToDevice, s));
-        }
         // the input batch is staged in gy (overwritten by the loss gradient after the forward)
+        pat::nn::launch_batch_gather(d_inputs, d_targets, pat::ptr<int>(order_d), bi * B, B, img, timg,
+                                     pat::ptr<float>(n->act.gy), pat::ptr<float>(n->act.t), s);
         pat::nn::forward(n, pat::ptr<float>(n->act.gy), s);
         pat::nn::launch_mse(pat::ptr<float>(n->act.y), pat::ptr<float>(n->act.t), pat::ptr<float>(n->act.gy),
                             pat::ptr<double>(n->act.loss_part), pat::ptr<double>(loss_hist) + bi,

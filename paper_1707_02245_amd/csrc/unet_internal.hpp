@@ -74,9 +74,23 @@ int launch_colsum_partials(const View& g, float* part, int64_t P, int rows_per_b
 void launch_part_reduce(const float* part, int nblk, int C, int ld, float* out, hipStream_t s);
 void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                  float eps, float bc1, float bc2, hipStream_t s);
-void launch_prep_conv(const float* w, int Cout, int Cin, uint16_t* wf, uint16_t* wd, hipStream_t s);
-void launch_prep_convt(const float* w, int Cin, int Cout, uint16_t* wf, uint16_t* wd, hipStream_t s);
+// one layer of launch_prep_all: offsets in the FP32 parameters and in the two
+// bf16 weight buffers, its kind (0 3x3, 1 transposed 2x2), channels, and its
+// first workgroup in the launch
+struct PrepLayer {
+  int64_t w, wf, wd;
+  int kind, cout, cin, first_block;
+};
+constexpr int kMaxPrepLayers = 32;
+struct PrepTable {
+  PrepLayer L[kMaxPrepLayers];
+  int count;
+};
+void launch_prep_all(const float* params, uint16_t* wf, uint16_t* wd, const PrepTable& t, int blocks,
+                     hipStream_t s);
 void launch_to_bf16(const float* x, const View& out, int64_t P, hipStream_t s);
+void launch_batch_gather(const float* inputs, const float* targets, const int* order, int base, int B,
+                         int64_t img, int64_t timg, float* x, float* t, hipStream_t s);
 
 }  // namespace nn
 }  // namespace pat

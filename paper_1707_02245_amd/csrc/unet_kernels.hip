@@ -1115,45 +1115,75 @@ void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float 
 // bf16 weight layouts from the FP32 master:
 //  conv3x3 [Cout][9][Cin]: forward B = same layout; dgrad B[ci][tap*Cout+co]
 //  convT  [2][2][Cin][Cout]: forward B[(sub*Cout+co)][ci]; dgrad B[ci][sub*Cout+co]
-__global__ __launch_bounds__(256) void prep_conv_kernel(const float* __restrict__ w, int Cout, int Cin,
-                                                        uint16_t* __restrict__ wf, uint16_t* __restrict__ wd) {
-  const int64_t n = (int64_t)Cout * 9 * Cin;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int ci = (int)(i % Cin);
-    const int64_t r = i / Cin;
+// Every layer's bf16 weight copies in one launch: workgroup b serves the
+// layer whose range of workgroups holds b, one weight per thread. A 3x3
+// layer's weights [co][tap][ci] go to wf as they are and to wd as
+// [ci][tap][co]; a transposed layer's [sub][ci][co] go to wf as
+// [sub][co][ci] and to wd as [ci][sub][co].
+__global__ __launch_bounds__(256) void prep_all_kernel(const float* __restrict__ params, uint16_t* __restrict__ wf,
+                                                       uint16_t* __restrict__ wd, PrepTable t) {
+  int li = 0;
+  for (int k = 1; k < t.count; ++k)
+    if ((int)blockIdx.x >= t.L[k].first_block) li = k;
+  const PrepLayer L = t.L[li];
+  const int64_t i = (int64_t)((int)blockIdx.x - L.first_block) * 256 + threadIdx.x;
+  if (L.kind == 0) {
+    if (i >= (int64_t)L.cout * 9 * L.cin) return;
+    const int ci = (int)(i % L.cin);
+    const int64_t r = i / L.cin;
     const int tap = (int)(r % 9), co = (int)(r / 9);
-    const uint16_t h = f2bf(w[i]);
-    wf[i] = h;
-    wd[((int64_t)ci * 9 + tap) * Cout + co] = h;
+    const uint16_t h = f2bf(params[L.w + i]);
+    wf[L.wf + i] = h;
+    wd[L.wd + ((int64_t)ci * 9 + tap) * L.cout + co] = h;
+  } else {
+    if (i >= (int64_t)4 * L.cin * L.cout) return;
+    const int co = (int)(i % L.cout);
+    const int64_t r = i / L.cout;
+    const int ci = (int)(r % L.cin), sub = (int)(r / L.cin);
+    const uint16_t h = f2bf(params[L.w + i]);
+    wf[L.wf + ((int64_t)sub * L.cout + co) * L.cin + ci] = h;
+    wd[L.wd + (int64_t)ci * 4 * L.cout + sub * L.cout + co] = h;
   }
 }
 
-__global__ __launch_bounds__(256) void prep_convt_kernel(const float* __restrict__ w, int Cin, int Cout,
-                                                         uint16_t* __restrict__ wf, uint16_t* __restrict__ wd) {
-  const int64_t n = (int64_t)4 * Cin * Cout;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int co = (int)(i % Cout);
-    const int64_t r = i / Cout;
-    const int ci = (int)(r % Cin), sub = (int)(r / Cin);
-    const uint16_t h = f2bf(w[i]);
-    wf[((int64_t)sub * Cout + co) * Cin + ci] = h;
-    wd[(int64_t)ci * 4 * Cout + sub * Cout + co] = h;
-  }
-}
-
-void launch_prep_conv(const float* w, int Cout, int Cin, uint16_t* wf, uint16_t* wd, hipStream_t s) {
-  const int64_t n = (int64_t)Cout * 9 * Cin;
-  hipLaunchKernelGGL(prep_conv_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256),
-                     0, s, w, Cout, Cin, wf, wd);
+void launch_prep_all(const float* params, uint16_t* wf, uint16_t* wd, const PrepTable& t, int blocks,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(prep_all_kernel, dim3((unsigned)blocks), dim3(256), 0, s, params, wf, wd, t);
   PAT_HIP(hipGetLastError());
 }
 
-void launch_prep_convt(const float* w, int Cin, int Cout, uint16_t* wf, uint16_t* wd, hipStream_t s) {
-  const int64_t n = (int64_t)4 * Cin * Cout;
-  hipLaunchKernelGGL(prep_convt_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256),
-                     0, s, w, Cin, Cout, wf, wd);
+// A training batch gathered by the epoch's order: batch image j is sample
+// order[base + j], its input (img floats) to x and its target (timg floats)
+// to t; workgroup row j serves image j, 4 floats per thread when VEC.
+template <bool VEC>
+__global__ __launch_bounds__(256) void batch_gather_kernel(const float* __restrict__ inputs,
+                                                           const float* __restrict__ targets,
+                                                           const int* __restrict__ order, int base, int64_t img,
+                                                           int64_t timg, float* __restrict__ x,
+                                                           float* __restrict__ t) {
+  const int j = blockIdx.y;
+  const int64_t src = order[base + j];
+  const int64_t w = VEC ? 4 : 1, n_in = img / w, n = (img + timg) / w;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const bool in = e < n_in;
+    const float* from = in ? inputs + src * img + e * w : targets + src * timg + (e - n_in) * w;
+    float* to = in ? x + j * img + e * w : t + j * timg + (e - n_in) * w;
+    if (VEC) *reinterpret_cast<float4*>(to) = *reinterpret_cast<const float4*>(from);
+    else *to = *from;
+  }
+}
+
+void launch_batch_gather(const float* inputs, const float* targets, const int* order, int base, int B,
+                         int64_t img, int64_t timg, float* x, float* t, hipStream_t s) {
+  const bool vec = img % 4 == 0 && timg % 4 == 0 && (reinterpret_cast<uintptr_t>(inputs) & 15) == 0 &&
+                   (reinterpret_cast<uintptr_t>(targets) & 15) == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0 &&
+                   (reinterpret_cast<uintptr_t>(t) & 15) == 0;
+  const int64_t n = (img + timg) / (vec ? 4 : 1);
+  const dim3 grid((unsigned)std::min<int64_t>((n + 255) / 256, 1024), (unsigned)B);
+  if (vec)
+    hipLaunchKernelGGL(batch_gather_kernel<true>, grid, dim3(256), 0, s, inputs, targets, order, base, img, timg, x, t);
+  else
+    hipLaunchKernelGGL(batch_gather_kernel<false>, grid, dim3(256), 0, s, inputs, targets, order, base, img, timg, x, t);
   PAT_HIP(hipGetLastError());
 }
 
