@@ -212,23 +212,30 @@ static int choose_ksplit(int64_t M, int64_t N, int64_t K) {
 }
 
 // weight gradient of a 3x3 convolution: dW[co][tap*Cin+ci] = sum_p g[p][co] X[p+tap][ci]
+// (by pixel tiles where the shapes allow, else the implicit GEMM split over k)
 static void conv_wgrad(pat_unet_s* n, const Layer& L, const View& x, const View& g, hipStream_t s) {
-  GemmDesc d;
-  d.M = L.cout;
-  d.N = 9 * L.cin;
-  d.K = n->act.B * x.H * x.W;
-  d.ksplit = choose_ksplit(d.M, d.N, d.K);
-  d.a_mode = A_T;
-  d.a = g;
-  d.b_mode = B_IM2COL;
-  d.b = x;
-  d.out_mode = E_SPLIT;
-  d.out_f32 = ptr<float>(n->act.ws);
-  const int bnblk = launch_colsum_partials(g, ptr<float>(n->act.part), d.K, 256, s);
-  launch_gemm(d, s);
-  const int nsplit = (d.K + d.ksplit - 1) / d.ksplit;
-  launch_wgrad_reduce(d.out_f32, nsplit, d.M, d.N, ptr<float>(n->grads) + L.w, 0, ptr<float>(n->act.part),
-                      bnblk, g.C, ptr<float>(n->grads) + L.b, s);
+  const int64_t P = (int64_t)n->act.B * x.H * x.W;
+  const int bnblk = launch_colsum_partials(g, ptr<float>(n->act.part), P, 256, s);
+  int nsplit;
+  if (wgrad3_applies(x, g, L.cin, L.cout)) {
+    nsplit = launch_wgrad3(x, g, n->act.B, L.cin, L.cout, ptr<float>(n->act.ws), (int64_t)kWorkspace, s);
+  } else {
+    GemmDesc d;
+    d.M = L.cout;
+    d.N = 9 * L.cin;
+    d.K = (int)P;
+    d.ksplit = choose_ksplit(d.M, d.N, d.K);
+    d.a_mode = A_T;
+    d.a = g;
+    d.b_mode = B_IM2COL;
+    d.b = x;
+    d.out_mode = E_SPLIT;
+    d.out_f32 = ptr<float>(n->act.ws);
+    launch_gemm(d, s);
+    nsplit = (d.K + d.ksplit - 1) / d.ksplit;
+  }
+  launch_wgrad_reduce(ptr<float>(n->act.ws), nsplit, L.cout, 9 * L.cin, ptr<float>(n->grads) + L.w, 0,
+                      ptr<float>(n->act.part), bnblk, g.C, ptr<float>(n->grads) + L.b, s);
 }
 
 // input gradient of a 3x3 convolution (flipped taps), rounded to bf16 and masked

@@ -370,6 +370,119 @@ static bool conv3_applies(const GemmDesc& d) {
          v.W % kCvTW == 0 && v.H > 0 && v.W > 0 && d.M % (v.H * v.W) == 0;
 }
 
+// The weight gradient of a 3x3 convolution as a direct product over pixel
+// tiles: dW[co][tap C + ci] = sum_p g[p][co] x[p + off(tap)][ci], off(tap) =
+// (tap / 3 - 1, tap % 3 - 1), zero outside the image (the product the GEMM
+// takes with B = im2col(x)). A workgroup of 4 waves takes 32 output channels
+// (blockIdx.y), 32 input channels (blockIdx.z) and the 16 x 16-pixel tiles
+// blockIdx.x, blockIdx.x + gridDim.x, ... For each tile it stages the
+// gradient transposed, gT[co][pixel], and the input's 18 x 18 halo transposed
+// in three copies shifted by 0, 1 and 2 columns, xs[dx][ci][row][col], so that
+// every MFMA operand is one aligned 16-byte LDS read of 8 consecutive pixels
+// (the halo is read from memory once instead of once per tap). k = pixels, 32
+// per MFMA: tile rows 2s and 2s + 1, lane group q = l / 16 holding row
+// 2s + q / 2, columns 8 (q % 2) .. + 7, in both operands. Wave w accumulates
+// output channels 16 (w / 2) .. + 15 against input channels 16 (w % 2) .. + 15
+// for the nine taps, over its tiles in order, and writes the sums to the
+// split-K partials [blockIdx.x][co][tap C + ci]. Rows are padded by 8
+// elements in LDS against bank conflicts.
+constexpr int kWgT = 16, kWgGLD = kWgT * kWgT + 8, kWgXLD = (kWgT + 2) * kWgT + 8;
+constexpr int kWgTargetBlocks = 512;
+
+__global__ __launch_bounds__(256) void wgrad3_kernel(View x, View g, float* __restrict__ part, int cout, int cin,
+                                                     int n_tiles) {
+  __shared__ __align__(16) uint16_t gT[32 * kWgGLD];
+  __shared__ __align__(16) uint16_t xs[3 * 32 * kWgXLD];
+  const int H = x.H, W = x.W;
+  const int tiles_x = W / kWgT, tiles_y = H / kWgT;
+  const int co0 = 32 * blockIdx.y, ci0 = 32 * blockIdx.z;
+  const int t = threadIdx.x, wave = t / 64, lane = t % 64;
+  const int cf = wave >> 1, nf = wave & 1, q = lane / 16, r16 = lane % 16;
+  v4f acc[9];
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap) acc[tap] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    int tt = tile;
+    const int tx = tt % tiles_x;
+    tt /= tiles_x;
+    const int ty = tt % tiles_y, b = tt / tiles_y;
+    const int x0 = tx * kWgT, y0 = ty * kWgT;
+    // the gradient's 256 pixels x 32 channels, 8 channels per 16-byte load,
+    // consecutive lanes on consecutive pixels
+    for (int e = t; e < kWgT * kWgT * 4; e += 256) {
+      const int px = e % (kWgT * kWgT), cv = e / (kWgT * kWgT);
+      const int yy = y0 + px / kWgT, xx = x0 + px % kWgT;
+      const uint4 v =
+          *reinterpret_cast<const uint4*>(g.p + ((int64_t)(b * H + yy) * W + xx) * g.pitch + g.off + co0 + 8 * cv);
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int i = 0; i < 8; ++i) gT[(8 * cv + i) * kWgGLD + px] = (uint16_t)(w[i >> 1] >> (16 * (i & 1)));
+    }
+    // the input's halo pixel (hy, hx) lands in copy dx at column hx - dx
+    for (int e = t; e < (kWgT + 2) * (kWgT + 2) * 4; e += 256) {
+      const int px = e % ((kWgT + 2) * (kWgT + 2)), cv = e / ((kWgT + 2) * (kWgT + 2));
+      const int hy = px / (kWgT + 2), hx = px % (kWgT + 2);
+      const int yy = y0 + hy - 1, xx = x0 + hx - 1;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+        v = *reinterpret_cast<const uint4*>(x.p + ((int64_t)(b * H + yy) * W + xx) * x.pitch + x.off + ci0 + 8 * cv);
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const int col = hx - dx;
+        if (col < 0 || col >= kWgT) continue;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          xs[(dx * 32 + 8 * cv + i) * kWgXLD + hy * kWgT + col] = (uint16_t)(w[i >> 1] >> (16 * (i & 1)));
+      }
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int st = 0; st < kWgT / 2; ++st) {
+      const int row = 2 * st + (q >> 1), col = 8 * (q & 1);
+      const v8bf a = *reinterpret_cast<const v8bf*>(gT + (16 * cf + r16) * kWgGLD + row * kWgT + col);
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) {
+        const int dy = tap / 3, dx = tap % 3;
+        const v8bf bx =
+            *reinterpret_cast<const v8bf*>(xs + (dx * 32 + 16 * nf + r16) * kWgXLD + (row + dy) * kWgT + col);
+        acc[tap] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bx, acc[tap], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // D[4 q + r][r16]: output channel co0 + 16 cf + 4 q + r, input channel ci0 + 16 nf + r16
+  const int64_t N = 9 * (int64_t)cin;
+  float* out = part + (int64_t)blockIdx.x * cout * N;
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      out[(int64_t)(co0 + 16 * cf + 4 * q + r) * N + tap * cin + ci0 + 16 * nf + r16] = acc[tap][r];
+}
+
+bool wgrad3_applies(const View& x, const View& g, int cin, int cout) {
+  auto vec_ok = [](const View& v) {
+    return v.pitch % 8 == 0 && v.off % 8 == 0 && (reinterpret_cast<uintptr_t>(v.p) & 15) == 0;
+  };
+  return cin % 32 == 0 && cout % 32 == 0 && x.C == cin && g.C == cout && x.H == g.H && x.W == g.W &&
+         x.H > 0 && x.W > 0 && x.H % kWgT == 0 && x.W % kWgT == 0 && vec_ok(x) && vec_ok(g);
+}
+
+int launch_wgrad3(const View& x, const View& g, int B, int cin, int cout, float* part, int64_t part_bytes,
+                  hipStream_t s) {
+  const int n_tiles = B * (x.H / kWgT) * (x.W / kWgT);
+  const int slices = (cout / 32) * (cin / 32);
+  int nsplit = std::max(1, std::min(n_tiles, kWgTargetBlocks / slices));
+  const int64_t per_split = (int64_t)cout * 9 * cin * (int64_t)sizeof(float);
+  nsplit = (int)std::min<int64_t>(nsplit, std::max<int64_t>(1, part_bytes / per_split));
+  PAT_CHECK_ARG(per_split <= part_bytes, "weight gradient partials exceed the workspace");
+  hipLaunchKernelGGL(wgrad3_kernel, dim3((unsigned)nsplit, (unsigned)(cout / 32), (unsigned)(cin / 32)),
+                     dim3(256), 0, s, x, g, part, cout, cin, n_tiles);
+  PAT_HIP(hipGetLastError());
+  return nsplit;
+}
+
 // ------------------------------------------------------------------ the GEMM
 
 // WM x WN waves, each computing FM x FN 16x16 fragments: a TM x TN tile with
