@@ -215,11 +215,14 @@ static int choose_ksplit(int64_t M, int64_t N, int64_t K) {
 // (by pixel tiles where the shapes allow, else the implicit GEMM split over k)
 static void conv_wgrad(pat_unet_s* n, const Layer& L, const View& x, const View& g, hipStream_t s) {
   const int64_t P = (int64_t)n->act.B * x.H * x.W;
-  const int bnblk = launch_colsum_partials(g, ptr<float>(n->act.part), P, 256, s);
-  int nsplit;
+  int nsplit, bnblk;
   if (wgrad3_applies(x, g, L.cin, L.cout)) {
-    nsplit = launch_wgrad3(x, g, n->act.B, L.cin, L.cout, ptr<float>(n->act.ws), (int64_t)kWorkspace, s);
+    // the bias partials come from the same launch, one row per split
+    nsplit = launch_wgrad3(x, g, n->act.B, L.cin, L.cout, ptr<float>(n->act.ws), (int64_t)kWorkspace,
+                           ptr<float>(n->act.part), (int64_t)n->act.part.bytes, s);
+    bnblk = nsplit;
   } else {
+    bnblk = launch_colsum_partials(g, ptr<float>(n->act.part), P, 256, s);
     GemmDesc d;
     d.M = L.cout;
     d.N = 9 * L.cin;

@@ -59,10 +59,11 @@ struct GemmDesc {
 
 void launch_gemm(const GemmDesc& d, hipStream_t s);
 // weight gradient of a 3x3 convolution by pixel tiles (when wgrad3_applies):
-// writes nsplit partials [split][cout][9 cin] to part and returns nsplit
+// writes nsplit partials [split][cout][9 cin] to part and the bias column
+// sums' partials [split][cout] to bpart, and returns nsplit
 bool wgrad3_applies(const View& x, const View& g, int cin, int cout);
 int launch_wgrad3(const View& x, const View& g, int B, int cin, int cout, float* part, int64_t part_bytes,
-                  hipStream_t s);
+                  float* bpart, int64_t bpart_bytes, hipStream_t s);
 void set_gemm_tiles(int mode);
 void launch_wgrad_reduce(const float* part, int nsplit, int M, int N, float* out, int permute_cout,
                          const float* bpart, int bnblk, int bC, float* bout, hipStream_t s);

@@ -384,13 +384,17 @@ static bool conv3_applies(const GemmDesc& d) {
 // 2s + q / 2, columns 8 (q % 2) .. + 7, in both operands. Wave w accumulates
 // output channels 16 (w / 2) .. + 15 against input channels 16 (w % 2) .. + 15
 // for the nine taps, over its tiles in order, and writes the sums to the
-// split-K partials [blockIdx.x][co][tap C + ci]. Rows are padded by 8
-// elements in LDS against bank conflicts.
+// split-K partials [blockIdx.x][co][tap C + ci]. The bias gradient's column
+// sums sum_p g[p][co] come from the same staged gradient: the workgroups of
+// the first input-channel chunk multiply it by a ones operand in a tenth
+// accumulator (waves of input-channel fragment 0) and write
+// bpart[blockIdx.x][co]. Rows are padded by 8 elements in LDS against bank
+// conflicts.
 constexpr int kWgT = 16, kWgGLD = kWgT * kWgT + 8, kWgXLD = (kWgT + 2) * kWgT + 8;
 constexpr int kWgTargetBlocks = 512;
 
-__global__ __launch_bounds__(256) void wgrad3_kernel(View x, View g, float* __restrict__ part, int cout, int cin,
-                                                     int n_tiles) {
+__global__ __launch_bounds__(256) void wgrad3_kernel(View x, View g, float* __restrict__ part,
+                                                     float* __restrict__ bpart, int cout, int cin, int n_tiles) {
   __shared__ __align__(16) uint16_t gT[32 * kWgGLD];
   __shared__ __align__(16) uint16_t xs[3 * 32 * kWgXLD];
   const int H = x.H, W = x.W;
@@ -398,7 +402,11 @@ __global__ __launch_bounds__(256) void wgrad3_kernel(View x, View g, float* __re
   const int co0 = 32 * blockIdx.y, ci0 = 32 * blockIdx.z;
   const int t = threadIdx.x, wave = t / 64, lane = t % 64;
   const int cf = wave >> 1, nf = wave & 1, q = lane / 16, r16 = lane % 16;
-  v4f acc[9];
+  const bool bias = blockIdx.z == 0 && nf == 0;
+  v8bf ones;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) ones[j] = (__bf16)1.0f;
+  v4f acc[9], accb = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int tap = 0; tap < 9; ++tap) acc[tap] = v4f{0.f, 0.f, 0.f, 0.f};
   for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
@@ -448,6 +456,7 @@ __global__ __launch_bounds__(256) void wgrad3_kernel(View x, View g, float* __re
             *reinterpret_cast<const v8bf*>(xs + (dx * 32 + 16 * nf + r16) * kWgXLD + (row + dy) * kWgT + col);
         acc[tap] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bx, acc[tap], 0, 0, 0);
       }
+      if (bias) accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, ones, accb, 0, 0, 0);
     }
     __syncthreads();
   }
@@ -459,6 +468,10 @@ __global__ __launch_bounds__(256) void wgrad3_kernel(View x, View g, float* __re
 #pragma unroll
     for (int r = 0; r < 4; ++r)
       out[(int64_t)(co0 + 16 * cf + 4 * q + r) * N + tap * cin + ci0 + 16 * nf + r16] = acc[tap][r];
+  // every column of the ones product holds the sum; column 0 is written
+  if (bias && r16 == 0)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bpart[(int64_t)blockIdx.x * cout + co0 + 16 * cf + 4 * q + r] = accb[r];
 }
 
 bool wgrad3_applies(const View& x, const View& g, int cin, int cout) {
@@ -470,15 +483,17 @@ bool wgrad3_applies(const View& x, const View& g, int cin, int cout) {
 }
 
 int launch_wgrad3(const View& x, const View& g, int B, int cin, int cout, float* part, int64_t part_bytes,
-                  hipStream_t s) {
+                  float* bpart, int64_t bpart_bytes, hipStream_t s) {
   const int n_tiles = B * (x.H / kWgT) * (x.W / kWgT);
   const int slices = (cout / 32) * (cin / 32);
   int nsplit = std::max(1, std::min(n_tiles, kWgTargetBlocks / slices));
   const int64_t per_split = (int64_t)cout * 9 * cin * (int64_t)sizeof(float);
   nsplit = (int)std::min<int64_t>(nsplit, std::max<int64_t>(1, part_bytes / per_split));
-  PAT_CHECK_ARG(per_split <= part_bytes, "weight gradient partials exceed the workspace");
+  nsplit = (int)std::min<int64_t>(nsplit, std::max<int64_t>(1, bpart_bytes / (cout * (int64_t)sizeof(float))));
+  PAT_CHECK_ARG(per_split <= part_bytes && cout * (int64_t)sizeof(float) <= bpart_bytes,
+                "weight gradient partials exceed the workspace");
   hipLaunchKernelGGL(wgrad3_kernel, dim3((unsigned)nsplit, (unsigned)(cout / 32), (unsigned)(cin / 32)),
-                     dim3(256), 0, s, x, g, part, cout, cin, n_tiles);
+                     dim3(256), 0, s, x, g, part, bpart, cout, cin, n_tiles);
   PAT_HIP(hipGetLastError());
   return nsplit;
 }
