@@ -671,38 +671,60 @@ void launch_gemm(const GemmDesc& d_in, hipStream_t s) {
 }
 
 // out[m][n] (with optional [ci][co] <- [(a,e,co)][ci] permutation) = sum_z part[z][m][n]
-// A workgroup takes 256 / lanes elements; the lanes of an element add the
-// partials z = lane, lane + lanes, ... and then the lane sums in lane order.
-// lanes (8, 32 or 128) follows from the shape alone: more lanes when the
-// partials are many and the elements too few to fill the device.
+// A thread takes V consecutive elements (V = 4: 16-byte loads, when M N is a
+// multiple of 4) and a workgroup 256 V / lanes of them; the lanes of an
+// element group add the partials z = lane, lane + lanes, ... and then the
+// lane sums in lane order. lanes (8 or 32) follows from the shape alone: more
+// lanes when the partials are many and the elements too few to fill the
+// device.
+template <int V>
 __device__ __forceinline__ void splitk_reduce_block(const float* __restrict__ part, int nsplit, int M, int N,
                                                     float* __restrict__ out, int permute_cout, int lanes,
                                                     int blk, float* lds) {
   const int els = 256 / lanes;
   const int64_t total = (int64_t)M * N;
   const int el = threadIdx.x % els, zl = threadIdx.x / els;
-  const int64_t i = (int64_t)blk * els + el;
-  float s = 0.f;
-  if (i < total)
-    for (int z = zl; z < nsplit; z += lanes) s += part[(int64_t)z * total + i];
-  lds[threadIdx.x] = s;
+  const int64_t i = ((int64_t)blk * els + el) * V;
+  float s[V];
+#pragma unroll
+  for (int j = 0; j < V; ++j) s[j] = 0.f;
+  if (i < total) {
+    for (int z = zl; z < nsplit; z += lanes) {
+      if constexpr (V == 4) {
+        const float4 v = *reinterpret_cast<const float4*>(part + (int64_t)z * total + i);
+        s[0] += v.x;
+        s[1] += v.y;
+        s[2] += v.z;
+        s[3] += v.w;
+      } else {
+        s[0] += part[(int64_t)z * total + i];
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < V; ++j) lds[j * 256 + threadIdx.x] = s[j];
   __syncthreads();
   if (zl == 0 && i < total) {
-    for (int l = 1; l < lanes; ++l) s += lds[l * els + el];
-    if (permute_cout > 0) {
-      // row m = sub * Cout + co, column n = ci -> [sub][ci][co]
-      const int m = (int)(i / N), n = (int)(i % N);
-      const int sub = m / permute_cout, co = m % permute_cout;
-      out[((int64_t)sub * N + n) * permute_cout + co] = s;
-    } else {
-      out[i] = s;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      float sj = s[j];
+      for (int l = 1; l < lanes; ++l) sj += lds[j * 256 + l * els + el];
+      const int64_t ij = i + j;
+      if (permute_cout > 0) {
+        // row m = sub * Cout + co, column n = ci -> [sub][ci][co]
+        const int m = (int)(ij / N), n = (int)(ij % N);
+        const int sub = m / permute_cout, co = m % permute_cout;
+        out[((int64_t)sub * N + n) * permute_cout + co] = sj;
+      } else {
+        out[ij] = sj;
+      }
     }
   }
 }
 
-static int splitk_lanes(int nsplit, int64_t total) {
+static int splitk_lanes(int nsplit, int64_t groups) {
   int lanes = 8;
-  while (lanes < 128 && 4 * lanes <= nsplit && (total * lanes + 255) / 256 < 1024) lanes *= 4;
+  if (4 * lanes <= nsplit && (groups * lanes + 255) / 256 < 1024) lanes *= 4;
   return lanes;
 }
 
@@ -720,14 +742,15 @@ __device__ __forceinline__ void part_reduce_block(const float* __restrict__ part
 // A weight gradient's two reductions in one launch: workgroups [0, nb_split)
 // sum its split-K partials, the next bC workgroups the bias column sums'
 // per-workgroup partials (bnblk rows of bC).
+template <int V>
 __global__ __launch_bounds__(256) void wgrad_reduce_kernel(const float* __restrict__ part, int nsplit, int M,
                                                            int N, float* __restrict__ out, int permute_cout,
                                                            int lanes, int nb_split,
                                                            const float* __restrict__ bpart, int bnblk, int bC,
                                                            float* __restrict__ bout) {
-  __shared__ float lds[256];
+  __shared__ float lds[256 * V];
   if ((int)blockIdx.x < nb_split)
-    splitk_reduce_block(part, nsplit, M, N, out, permute_cout, lanes, blockIdx.x, lds);
+    splitk_reduce_block<V>(part, nsplit, M, N, out, permute_cout, lanes, blockIdx.x, lds);
   else
     part_reduce_block(bpart, bnblk, bC, bout, (int)blockIdx.x - nb_split);
 }
@@ -735,11 +758,17 @@ __global__ __launch_bounds__(256) void wgrad_reduce_kernel(const float* __restri
 void launch_wgrad_reduce(const float* part, int nsplit, int M, int N, float* out, int permute_cout,
                          const float* bpart, int bnblk, int bC, float* bout, hipStream_t s) {
   const int64_t total = (int64_t)M * N;
-  const int lanes = splitk_lanes(nsplit, total);
+  const bool vec = total % 4 == 0 && (reinterpret_cast<uintptr_t>(part) & 15) == 0;
+  const int64_t groups = vec ? total / 4 : total;
+  const int lanes = splitk_lanes(nsplit, groups);
   const int els = 256 / lanes;
-  const int nb_split = (int)((total + els - 1) / els);
-  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(nb_split + bC), dim3(256), 0, s, part, nsplit, M, N, out,
-                     permute_cout, lanes, nb_split, bpart, bnblk, bC, bout);
+  const int nb_split = (int)((groups + els - 1) / els);
+  if (vec)
+    hipLaunchKernelGGL(wgrad_reduce_kernel<4>, dim3(nb_split + bC), dim3(256), 0, s, part, nsplit, M, N, out,
+                       permute_cout, lanes, nb_split, bpart, bnblk, bC, bout);
+  else
+    hipLaunchKernelGGL(wgrad_reduce_kernel<1>, dim3(nb_split + bC), dim3(256), 0, s, part, nsplit, M, N, out,
+                       permute_cout, lanes, nb_split, bpart, bnblk, bC, bout);
   PAT_HIP(hipGetLastError());
 }
 
