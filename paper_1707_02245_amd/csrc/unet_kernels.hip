@@ -561,6 +561,44 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmDesc d) {
     __syncthreads();
   }
   // epilogue
+  if (d.out_mode == E_SHUF) {
+    // m: low-res pixel (b, y, x), n = sub * C + c -> output pixel
+    // (2y + sub / 2, 2x + sub % 2), channel c: each row's pixel and each
+    // column's sub-pixel offset split once
+    const View& o = d.out;
+    int64_t base[FM][4];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * 16 * FM + i * 16 + 4 * (lane / 16) + r;
+        base[i][r] = -1;
+        if (m < d.M) {
+          int b, y, x;
+          pix_split(m, o.dW2, o.dH2, b, y, x);
+          base[i][r] = ((int64_t)(b * o.H + 2 * y) * o.W + 2 * x) * o.pitch + o.off;
+        }
+      }
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int n = n0 + wn * 16 * FN + j * 16 + lane % 16;
+      if (n >= d.N) continue;
+      int sub, c;
+      chan_split(n, o.dC, sub, c);
+      const int64_t so = ((int64_t)(sub >> 1) * o.W + (sub & 1)) * o.pitch + c;
+      const float bc = d.bias ? d.bias[c] : 0.f;
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (base[i][r] < 0) continue;
+          float v = acc[i][j][r];
+          if (d.bias) v += bc;
+          o.p16[base[i][r] + so] = f2bf(v);
+        }
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < FM; ++i) {
 #pragma unroll
@@ -581,13 +619,6 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmDesc d) {
           uint16_t h = f2bf(v);
           if (d.mask.p && !(bf2f(d.mask.p[(int64_t)m * d.mask.pitch + d.mask.off + n]) > 0.f)) h = 0;
           d.out.p16[(int64_t)m * d.out.pitch + d.out.off + n] = h;
-        } else if (d.out_mode == E_SHUF) {  // m: low-res pixel, n = sub * C + c
-          int sub, c, b, y, x;
-          chan_split(n, d.out.dC, sub, c);
-          if (d.bias) v += d.bias[c];
-          pix_split(m, d.out.dW2, d.out.dH2, b, y, x);
-          const int yy = 2 * y + (sub >> 1), xx = 2 * x + (sub & 1);
-          d.out.p16[((int64_t)(b * d.out.H + yy) * d.out.W + xx) * d.out.pitch + d.out.off + c] = f2bf(v);
         }
       }
     }
