@@ -370,6 +370,60 @@ static bool conv3_applies(const GemmDesc& d) {
          v.W % kCvTW == 0 && v.H > 0 && v.W > 0 && d.M % (v.H * v.W) == 0;
 }
 
+// A 3x3 convolution of a one-channel input (the network's first layer,
+// K = 9): one thread per pixel reads its nine taps once and writes its N
+// outputs (N a multiple of 8, at most 64) as 16-byte vectors, each output the
+// FP32 sum of the nine products in tap order, then bias, ReLU, bf16 and the
+// mask as the GEMM's E_ACT epilogue. The bf16 weights sit in LDS as floats
+// (every thread reads the same weight: broadcast). a_sign = -1 mirrors the
+// taps, as the GEMM's index map does.
+constexpr int kCiMaxN = 64;
+
+__global__ __launch_bounds__(256) void conv_in_kernel(GemmDesc d) {
+  __shared__ float wl[kCiMaxN * 9];
+  __shared__ float bl[kCiMaxN];
+  for (int e = threadIdx.x; e < d.N * 9; e += blockDim.x) wl[e] = bf2f(d.w[e]);
+  for (int e = threadIdx.x; e < d.N; e += blockDim.x) bl[e] = d.bias ? d.bias[e] : 0.f;
+  __syncthreads();
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= d.M) return;
+  const View& v = d.a;
+  int b, y, x;
+  pix_split(m, v.dW, v.dH, b, y, x);
+  float xv[9];
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap) {
+    const int yy = y + d.a_sign * (tap / 3 - 1), xx = x + d.a_sign * (tap % 3 - 1);
+    xv[tap] = (yy >= 0 && yy < v.H && xx >= 0 && xx < v.W)
+                  ? bf2f(v.p[((int64_t)(b * v.H + yy) * v.W + xx) * v.pitch + v.off])
+                  : 0.f;
+  }
+  for (int c0 = 0; c0 < d.N; c0 += 8) {
+    uint32_t o[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int n = c0 + i;
+      float acc = 0.f;
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) acc = fmaf(xv[tap], wl[n * 9 + tap], acc);
+      if (d.bias) acc += bl[n];
+      if (d.relu) acc = fmaxf(acc, 0.f);
+      uint16_t h = f2bf(acc);
+      if (d.mask.p && !(bf2f(d.mask.p[(int64_t)m * d.mask.pitch + d.mask.off + n]) > 0.f)) h = 0;
+      o[i >> 1] |= (uint32_t)h << (16 * (i & 1));
+    }
+    *reinterpret_cast<uint4*>(d.out.p16 + (int64_t)m * d.out.pitch + d.out.off + c0) =
+        make_uint4(o[0], o[1], o[2], o[3]);
+  }
+}
+
+static bool conv_in_applies(const GemmDesc& d) {
+  const View& v = d.a;
+  return d.a_mode == A_CONV && d.b_mode == B_W && d.out_mode == E_ACT && v.C == 1 && d.K == 9 &&
+         d.ksplit >= d.K && d.N % 8 == 0 && d.N <= kCiMaxN && d.out.pitch % 8 == 0 && d.out.off % 8 == 0 &&
+         (reinterpret_cast<uintptr_t>(d.out.p16) & 15) == 0 && v.H > 0 && v.W > 0 && d.M % (v.H * v.W) == 0;
+}
+
 // The weight gradient of a 3x3 convolution as a direct product over pixel
 // tiles: dW[co][tap C + ci] = sum_p g[p][co] x[p + off(tap)][ci], off(tap) =
 // (tap / 3 - 1, tap % 3 - 1), zero outside the image (the product the GEMM
@@ -686,6 +740,8 @@ void launch_gemm(const GemmDesc& d_in, hipStream_t s) {
   if (conv3_applies(d)) {
     const int64_t n_blk = (int64_t)(d.M / (d.a.H * d.a.W)) * (d.a.H / kCvTH) * (d.a.W / kCvTW);
     hipLaunchKernelGGL(conv3_kernel, dim3((unsigned)n_blk, (unsigned)(d.N / 32)), dim3(kCvThreads), 0, s, d);
+  } else if (conv_in_applies(d)) {
+    hipLaunchKernelGGL(conv_in_kernel, dim3((unsigned)((d.M + 255) / 256)), dim3(256), 0, s, d);
   } else if (d.N <= 32) {
     launch_tile<4, 1, 2, 2>(d, dim3((d.M + 127) / 128, (d.N + 31) / 32, nsplit), s);
   } else if (d.M <= 32) {
