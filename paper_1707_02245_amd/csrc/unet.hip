@@ -221,6 +221,10 @@ static void conv_wgrad(pat_unet_s* n, const Layer& L, const View& x, const View&
     nsplit = launch_wgrad3(x, g, n->act.B, L.cin, L.cout, ptr<float>(n->act.ws), (int64_t)kWorkspace,
                            ptr<float>(n->act.part), (int64_t)n->act.part.bytes, s);
     bnblk = nsplit;
+  } else if (wgrad1_applies(x, g, L.cin, L.cout)) {
+    nsplit = launch_wgrad1(x, g, n->act.B, L.cout, ptr<float>(n->act.ws), (int64_t)kWorkspace,
+                           ptr<float>(n->act.part), (int64_t)n->act.part.bytes, s);
+    bnblk = nsplit;
   } else {
     bnblk = launch_colsum_partials(g, ptr<float>(n->act.part), P, 256, s);
     GemmDesc d;

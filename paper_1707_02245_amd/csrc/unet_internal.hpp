@@ -64,6 +64,10 @@ void launch_gemm(const GemmDesc& d, hipStream_t s);
 bool wgrad3_applies(const View& x, const View& g, int cin, int cout);
 int launch_wgrad3(const View& x, const View& g, int B, int cin, int cout, float* part, int64_t part_bytes,
                   float* bpart, int64_t bpart_bytes, hipStream_t s);
+// the same for a one-channel input (partials [split][cout][9] and [split][cout])
+bool wgrad1_applies(const View& x, const View& g, int cin, int cout);
+int launch_wgrad1(const View& x, const View& g, int B, int cout, float* part, int64_t part_bytes, float* bpart,
+                  int64_t bpart_bytes, hipStream_t s);
 void set_gemm_tiles(int mode);
 void launch_wgrad_reduce(const float* part, int nsplit, int M, int N, float* out, int permute_cout,
                          const float* bpart, int bnblk, int bC, float* bout, hipStream_t s);

@@ -552,6 +552,99 @@ int launch_wgrad3(const View& x, const View& g, int B, int cin, int cout, float*
   return nsplit;
 }
 
+// The weight and bias gradients of a 3x3 convolution of a one-channel input
+// (the first layer): dW[co][tap] = sum_p g[p][co] x[p + off(tap)] and
+// db[co] = sum_p g[p][co] in one MFMA per output-channel fragment and k step,
+// the 16 columns of B being the nine taps' shifted views of the input, a
+// ones column (the bias) and zeros. Per 16 x 16-pixel tile the gradient is
+// staged transposed as in wgrad3_kernel and the input's one-channel halo in
+// three column-shifted copies; wave w takes output channels 16 w .. + 15
+// (cout / 16 waves). Partials: part[blockIdx.x][co][tap], bpart[blockIdx.x][co].
+constexpr int kW1MaxC = 64;
+
+__global__ __launch_bounds__(256) void wgrad1_kernel(View x, View g, float* __restrict__ part,
+                                                     float* __restrict__ bpart, int cout, int n_tiles) {
+  __shared__ __align__(16) uint16_t gT[kW1MaxC * kWgGLD];
+  __shared__ __align__(16) uint16_t xs[3 * kWgXLD];
+  const int H = x.H, W = x.W;
+  const int tiles_x = W / kWgT, tiles_y = H / kWgT;
+  const int t = threadIdx.x, nt = blockDim.x, cf = t / 64, lane = t % 64, q = lane / 16, r16 = lane % 16;
+  const int gv = cout / 8;  // 16-byte vectors per gradient pixel
+  v8bf ones, zeros;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    ones[j] = (__bf16)1.0f;
+    zeros[j] = (__bf16)0.0f;
+  }
+  v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    int tt = tile;
+    const int tx = tt % tiles_x;
+    tt /= tiles_x;
+    const int ty = tt % tiles_y, b = tt / tiles_y;
+    const int x0 = tx * kWgT, y0 = ty * kWgT;
+    for (int e = t; e < kWgT * kWgT * gv; e += nt) {
+      const int px = e % (kWgT * kWgT), cv = e / (kWgT * kWgT);
+      const int yy = y0 + px / kWgT, xx = x0 + px % kWgT;
+      const uint4 v = *reinterpret_cast<const uint4*>(g.p + ((int64_t)(b * H + yy) * W + xx) * g.pitch + g.off + 8 * cv);
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int i = 0; i < 8; ++i) gT[(8 * cv + i) * kWgGLD + px] = (uint16_t)(w[i >> 1] >> (16 * (i & 1)));
+    }
+    for (int px = t; px < (kWgT + 2) * (kWgT + 2); px += nt) {
+      const int hy = px / (kWgT + 2), hx = px % (kWgT + 2);
+      const int yy = y0 + hy - 1, xx = x0 + hx - 1;
+      const uint16_t v = (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                             ? x.p[((int64_t)(b * H + yy) * W + xx) * x.pitch + x.off]
+                             : (uint16_t)0;
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const int col = hx - dx;
+        if (col >= 0 && col < kWgT) xs[dx * kWgXLD + hy * kWgT + col] = v;
+      }
+    }
+    __syncthreads();
+    for (int st = 0; st < kWgT / 2; ++st) {
+      const int row = 2 * st + (q >> 1), col = 8 * (q & 1);
+      const v8bf a = *reinterpret_cast<const v8bf*>(gT + (16 * cf + r16) * kWgGLD + row * kWgT + col);
+      v8bf bx = zeros;
+      if (r16 < 9)
+        bx = *reinterpret_cast<const v8bf*>(xs + (r16 % 3) * kWgXLD + (row + r16 / 3) * kWgT + col);
+      else if (r16 == 9)
+        bx = ones;
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bx, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // D[4 q + r][r16]: output channel 16 cf + 4 q + r; column r16 a tap (< 9) or the bias (9)
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int co = 16 * cf + 4 * q + r;
+    if (r16 < 9) part[((int64_t)blockIdx.x * cout + co) * 9 + r16] = acc[r];
+    else if (r16 == 9) bpart[(int64_t)blockIdx.x * cout + co] = acc[r];
+  }
+}
+
+bool wgrad1_applies(const View& x, const View& g, int cin, int cout) {
+  return cin == 1 && x.C == 1 && g.C == cout && cout % 16 == 0 && cout <= kW1MaxC && x.H == g.H &&
+         x.W == g.W && x.H > 0 && x.W > 0 && x.H % kWgT == 0 && x.W % kWgT == 0 && g.pitch % 8 == 0 &&
+         g.off % 8 == 0 && (reinterpret_cast<uintptr_t>(g.p) & 15) == 0;
+}
+
+int launch_wgrad1(const View& x, const View& g, int B, int cout, float* part, int64_t part_bytes, float* bpart,
+                  int64_t bpart_bytes, hipStream_t s) {
+  const int n_tiles = B * (x.H / kWgT) * (x.W / kWgT);
+  int nsplit = std::max(1, std::min(n_tiles, kWgTargetBlocks));
+  nsplit = (int)std::min<int64_t>(nsplit, std::max<int64_t>(1, part_bytes / (cout * 9 * (int64_t)sizeof(float))));
+  nsplit = (int)std::min<int64_t>(nsplit, std::max<int64_t>(1, bpart_bytes / (cout * (int64_t)sizeof(float))));
+  PAT_CHECK_ARG(cout * 9 * (int64_t)sizeof(float) <= part_bytes && cout * (int64_t)sizeof(float) <= bpart_bytes,
+                "weight gradient partials exceed the workspace");
+  hipLaunchKernelGGL(wgrad1_kernel, dim3((unsigned)nsplit), dim3(64 * (cout / 16)), 0, s, x, g, part, bpart, cout,
+                     n_tiles);
+  PAT_HIP(hipGetLastError());
+  return nsplit;
+}
+
 // ------------------------------------------------------------------ the GEMM
 
 // WM x WN waves, each computing FM x FN 16x16 fragments: a TM x TN tile with
