@@ -1,7 +1,10 @@
 // Kernels of the warm-start network: a generic implicit-GEMM on the bf16 matrix
-// cores (FP32 accumulation) that serves every convolution of the network in
-// the forward pass and both backward passes, plus pooling, the 1x1 head, the
-// loss, bias gradients, split-K reduction, Adam and weight re-layout.
+// cores (FP32 accumulation) that can serve every convolution of the network in
+// the forward pass and both backward passes; direct kernels on staged pixel
+// tiles for the 3x3 convolutions whose shapes allow them (forward and data
+// gradient, weight and bias gradients, the one-channel first layer); plus
+// pooling, the 1x1 head, the loss, bias gradients, split-K reduction, Adam and
+// weight re-layout.
 //
 // Tensors are NHWC. Every activation view carries a channel pitch and offset,
 // so a transposed convolution writes the first half and an encoder
