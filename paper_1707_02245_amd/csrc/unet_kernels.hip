@@ -343,34 +343,54 @@ __global__ __launch_bounds__(kCvThreads) void conv3_kernel(GemmDesc d) {
     __syncthreads();
   }
   // epilogue as the GEMM's E_ACT: fragment i covers tile row wave * 2 + i,
-  // D[4(l/16)+r][l%16] -> pixel column 4(l/16)+r, output channel j * 16 + l % 16
+  // D[4(l/16)+r][l%16] -> pixel column 4(l/16)+r, output channel j * 16 + l % 16.
+  // Bias, ReLU and bf16 per element into LDS (the halo's space: the last
+  // chunk's barrier has passed), then each pixel's 32 channels leave as four
+  // 16-byte stores, with the mask applied per element.
+  uint16_t* ost = halo;  // [256 pixels][kCvLD]
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int y = y0 + wave * 2 + i;
+  for (int j = 0; j < 2; ++j) {
+    const int nl = j * 16 + lane % 16;
+    const float bn = d.bias ? d.bias[n0 + nl] : 0.f;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int n = n0 + j * 16 + lane % 16;
+    for (int i = 0; i < 2; ++i) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int x = x0 + 4 * (lane / 16) + r;
-        const int64_t m = (int64_t)(b * H + y) * W + x;
         float val = acc[i][j][r];
-        if (d.bias) val += d.bias[n];
+        if (d.bias) val += bn;
         if (d.relu) val = fmaxf(val, 0.f);
-        uint16_t h = f2bf(val);
-        if (d.mask.p && !(bf2f(d.mask.p[m * d.mask.pitch + d.mask.off + n]) > 0.f)) h = 0;
-        d.out.p16[m * d.out.pitch + d.out.off + n] = h;
+        ost[((wave * 2 + i) * kCvTW + 4 * (lane / 16) + r) * kCvLD + nl] = f2bf(val);
       }
     }
+  }
+  __syncthreads();
+  for (int e = t; e < kCvTH * kCvTW * 4; e += kCvThreads) {
+    const int px = e / 4, cv = e % 4;
+    const int64_t m = (int64_t)(b * H + y0 + px / kCvTW) * W + x0 + px % kCvTW;
+    uint4 o = *reinterpret_cast<const uint4*>(ost + px * kCvLD + 8 * cv);
+    if (d.mask.p) {
+      const uint4 mk = *reinterpret_cast<const uint4*>(d.mask.p + m * d.mask.pitch + d.mask.off + n0 + 8 * cv);
+      uint32_t ow[4] = {o.x, o.y, o.z, o.w};
+      const uint32_t mw[4] = {mk.x, mk.y, mk.z, mk.w};
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (!(bf2f((uint16_t)(mw[k >> 1] >> (16 * (k & 1)))) > 0.f)) ow[k >> 1] &= ~(0xFFFFu << (16 * (k & 1)));
+      o = make_uint4(ow[0], ow[1], ow[2], ow[3]);
+    }
+    *reinterpret_cast<uint4*>(d.out.p16 + m * d.out.pitch + d.out.off + n0 + 8 * cv) = o;
   }
 }
 
 // Whether conv3_kernel serves this product (else the generic GEMM).
 static bool conv3_applies(const GemmDesc& d) {
   const View& v = d.a;
+  auto vec_out = [](const View& o, const void* p) {
+    return o.pitch % 8 == 0 && o.off % 8 == 0 && (reinterpret_cast<uintptr_t>(p) & 15) == 0;
+  };
   return d.a_mode == A_CONV && d.b_mode == B_W && d.out_mode == E_ACT && d.a_vec == 1 && d.b_vec == 1 &&
          d.N % 32 == 0 && d.ksplit >= d.K && v.C % 32 == 0 && d.K == 9 * v.C && v.H % kCvTH == 0 &&
-         v.W % kCvTW == 0 && v.H > 0 && v.W > 0 && d.M % (v.H * v.W) == 0;
+         v.W % kCvTW == 0 && v.H > 0 && v.W > 0 && d.M % (v.H * v.W) == 0 && vec_out(d.out, d.out.p16) &&
+         (!d.mask.p || vec_out(d.mask, d.mask.p));
 }
 
 // A 3x3 convolution of a one-channel input (the network's first layer,
