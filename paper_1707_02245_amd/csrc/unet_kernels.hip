@@ -461,12 +461,29 @@ static bool conv_in_applies(const GemmDesc& d) {
 // 2s + q / 2, columns 8 (q % 2) .. + 7, in both operands. Wave w accumulates
 // output channels 16 (w / 2) .. + 15 against input channels 16 (w % 2) .. + 15
 // for the nine taps, over its tiles in order, and writes the sums to the
-// split-K partials [blockIdx.x][co][tap C + ci]. The bias gradient's column
+// split-K partials [blockIdx.x][co][tap C + ci]. Both stagings move blocks of
+// 8 pixels x 8 channels (eight 16-byte loads, a transpose in registers, eight
+// 16-byte LDS stores). The bias gradient's column
 // sums sum_p g[p][co] come from the same staged gradient: the workgroups of
 // the first input-channel chunk multiply it by a ones operand in a tenth
 // accumulator (waves of input-channel fragment 0) and write
 // bpart[blockIdx.x][co]. Rows are padded by 8 elements in LDS against bank
 // conflicts.
+// v[p] holds 8 bf16 channels of pixel p (p = 0..7); store channel c's 8
+// pixels as one 16-byte row at dst + c * ld (16-byte aligned).
+__device__ __forceinline__ void transpose8_store(const uint4 (&v)[8], uint16_t* dst, int ld) {
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    uint32_t o[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t w0 = (&v[2 * k].x)[c >> 1], w1 = (&v[2 * k + 1].x)[c >> 1];
+      o[k] = (c & 1) ? ((w0 >> 16) | (w1 & 0xFFFF0000u)) : ((w0 & 0xFFFFu) | (w1 << 16));
+    }
+    *reinterpret_cast<uint4*>(dst + c * ld) = make_uint4(o[0], o[1], o[2], o[3]);
+  }
+}
+
 constexpr int kWgT = 16, kWgGLD = kWgT * kWgT + 8, kWgXLD = (kWgT + 2) * kWgT + 8;
 constexpr int kWgTargetBlocks = 512;
 
@@ -492,34 +509,34 @@ __global__ __launch_bounds__(256) void wgrad3_kernel(View x, View g, float* __re
     tt /= tiles_x;
     const int ty = tt % tiles_y, b = tt / tiles_y;
     const int x0 = tx * kWgT, y0 = ty * kWgT;
-    // the gradient's 256 pixels x 32 channels, 8 channels per 16-byte load,
-    // consecutive lanes on consecutive pixels
-    for (int e = t; e < kWgT * kWgT * 4; e += 256) {
-      const int px = e % (kWgT * kWgT), cv = e / (kWgT * kWgT);
-      const int yy = y0 + px / kWgT, xx = x0 + px % kWgT;
-      const uint4 v =
-          *reinterpret_cast<const uint4*>(g.p + ((int64_t)(b * H + yy) * W + xx) * g.pitch + g.off + co0 + 8 * cv);
-      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    // the gradient's 256 pixels x 32 channels by blocks of 8 pixels (a row
+    // run) x 8 channels: eight 16-byte loads, a transpose in registers, eight
+    // 16-byte LDS stores of 8 pixels of one channel
+    if (t < 128) {
+      const int pg = t % 32, cg = t / 32;
+      const int row = pg / 2, col0 = 8 * (pg % 2);
+      uint4 v[8];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) gT[(8 * cv + i) * kWgGLD + px] = (uint16_t)(w[i >> 1] >> (16 * (i & 1)));
+      for (int p = 0; p < 8; ++p)
+        v[p] = *reinterpret_cast<const uint4*>(g.p + ((int64_t)(b * H + y0 + row) * W + x0 + col0 + p) * g.pitch +
+                                               g.off + co0 + 8 * cg);
+      transpose8_store(v, gT + (8 * cg) * kWgGLD + row * kWgT + col0, kWgGLD);
     }
-    // the input's halo pixel (hy, hx) lands in copy dx at column hx - dx
-    for (int e = t; e < (kWgT + 2) * (kWgT + 2) * 4; e += 256) {
-      const int px = e % ((kWgT + 2) * (kWgT + 2)), cv = e / ((kWgT + 2) * (kWgT + 2));
-      const int hy = px / (kWgT + 2), hx = px % (kWgT + 2);
-      const int yy = y0 + hy - 1, xx = x0 + hx - 1;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-        v = *reinterpret_cast<const uint4*>(x.p + ((int64_t)(b * H + yy) * W + xx) * x.pitch + x.off + ci0 + 8 * cv);
-      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    // the input's halo: copy dx, row hy, columns 8 h .. 8 h + 7 hold the
+    // pixels hx = dx + 8 h .. (image column x0 + hx - 1), zero outside
+    for (int e = t; e < 3 * (kWgT + 2) * 2 * 4; e += 256) {
+      const int cg = e % 4, h = (e / 4) % 2, hy = (e / 8) % (kWgT + 2), dx = e / (8 * (kWgT + 2));
+      const int yy = y0 + hy - 1;
+      uint4 v[8];
 #pragma unroll
-      for (int dx = 0; dx < 3; ++dx) {
-        const int col = hx - dx;
-        if (col < 0 || col >= kWgT) continue;
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-          xs[(dx * 32 + 8 * cv + i) * kWgXLD + hy * kWgT + col] = (uint16_t)(w[i >> 1] >> (16 * (i & 1)));
+      for (int p = 0; p < 8; ++p) {
+        const int xx = x0 + dx + 8 * h + p - 1;
+        v[p] = make_uint4(0, 0, 0, 0);
+        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+          v[p] = *reinterpret_cast<const uint4*>(x.p + ((int64_t)(b * H + yy) * W + xx) * x.pitch + x.off + ci0 +
+                                                 8 * cg);
       }
+      transpose8_store(v, xs + (dx * 32 + 8 * cg) * kWgXLD + hy * kWgT + 8 * h, kWgXLD);
     }
     __syncthreads();
 #pragma unroll 2
