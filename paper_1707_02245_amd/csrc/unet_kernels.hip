@@ -458,16 +458,16 @@ static bool conv_in_applies(const GemmDesc& d) {
 // every MFMA operand is one aligned 16-byte LDS read of 8 consecutive pixels
 // (the halo is read from memory once instead of once per tap). k = pixels, 32
 // per MFMA: tile rows 2s and 2s + 1, lane group q = l / 16 holding row
-// 2s + q / 2, columns 8 (q % 2) .. + 7, in both operands. Wave w accumulates
-// output channels 16 (w / 2) .. + 15 against input channels 16 (w % 2) .. + 15
-// for the nine taps, over its tiles in order, and writes the sums to the
-// split-K partials [blockIdx.x][co][tap C + ci]. Both stagings move blocks of
+// 2s + q / 2, columns 8 (q % 2) .. + 7, in both operands. Wave w takes the k
+// steps s = w and w + 4 of every tile for all 2 x 2 channel fragments and nine
+// taps (two A and eighteen B reads per 36 products); the four waves' sums are
+// added in wave order at the end and written to the split-K partials
+// [blockIdx.x][co][tap C + ci]. Both stagings move blocks of
 // 8 pixels x 8 channels (eight 16-byte loads, a transpose in registers, eight
 // 16-byte LDS stores). The bias gradient's column
 // sums sum_p g[p][co] come from the same staged gradient: the workgroups of
-// the first input-channel chunk multiply it by a ones operand in a tenth
-// accumulator (waves of input-channel fragment 0) and write
-// bpart[blockIdx.x][co]. Rows are padded by 8 elements in LDS against bank
+// the first input-channel chunk multiply it by a ones operand in one more
+// accumulator per output-channel fragment and write bpart[blockIdx.x][co]. Rows are padded by 8 elements in LDS against bank
 // conflicts.
 // v[p] holds 8 bf16 channels of pixel p (p = 0..7); store channel c's 8
 // pixels as one 16-byte row at dst + c * ld (16-byte aligned).
@@ -487,7 +487,7 @@ __device__ __forceinline__ void transpose8_store(const uint4 (&v)[8], uint16_t* 
 constexpr int kWgT = 16, kWgGLD = kWgT * kWgT + 8, kWgXLD = (kWgT + 2) * kWgT + 8;
 constexpr int kWgTargetBlocks = 512;
 
-__global__ __launch_bounds__(256) void wgrad3_kernel(View x, View g, float* __restrict__ part,
+__global__ __launch_bounds__(256, 2) void wgrad3_kernel(View x, View g, float* __restrict__ part,
                                                      float* __restrict__ bpart, int cout, int cin, int n_tiles) {
   __shared__ __align__(16) uint16_t gT[32 * kWgGLD];
   __shared__ __align__(16) uint16_t xs[3 * 32 * kWgXLD];
@@ -495,14 +495,22 @@ __global__ __launch_bounds__(256) void wgrad3_kernel(View x, View g, float* __re
   const int tiles_x = W / kWgT, tiles_y = H / kWgT;
   const int co0 = 32 * blockIdx.y, ci0 = 32 * blockIdx.z;
   const int t = threadIdx.x, wave = t / 64, lane = t % 64;
-  const int cf = wave >> 1, nf = wave & 1, q = lane / 16, r16 = lane % 16;
-  const bool bias = blockIdx.z == 0 && nf == 0;
+  const int q = lane / 16, r16 = lane % 16;
+  const bool bias = blockIdx.z == 0;
   v8bf ones;
 #pragma unroll
   for (int j = 0; j < 8; ++j) ones[j] = (__bf16)1.0f;
-  v4f acc[9], accb = v4f{0.f, 0.f, 0.f, 0.f};
+  // [output-channel fragment][input-channel fragment][tap], and the bias
+  // column per output-channel fragment
+  v4f acc[2][2][9], accb[2];
 #pragma unroll
-  for (int tap = 0; tap < 9; ++tap) acc[tap] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int cf = 0; cf < 2; ++cf) {
+    accb[cf] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int nf = 0; nf < 2; ++nf)
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) acc[cf][nf][tap] = v4f{0.f, 0.f, 0.f, 0.f};
+  }
   for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     int tt = tile;
     const int tx = tt % tiles_x;
@@ -539,33 +547,69 @@ __global__ __launch_bounds__(256) void wgrad3_kernel(View x, View g, float* __re
       transpose8_store(v, xs + (dx * 32 + 8 * cg) * kWgXLD + hy * kWgT + 8 * h, kWgXLD);
     }
     __syncthreads();
-#pragma unroll 2
-    for (int st = 0; st < kWgT / 2; ++st) {
+    // wave w: k steps w and w + 4 (tile rows 2 st, 2 st + 1), all four fragments
+#pragma unroll
+    for (int sw = 0; sw < kWgT / 8; ++sw) {
+      const int st = wave + 4 * sw;
       const int row = 2 * st + (q >> 1), col = 8 * (q & 1);
-      const v8bf a = *reinterpret_cast<const v8bf*>(gT + (16 * cf + r16) * kWgGLD + row * kWgT + col);
+      v8bf a[2];
+#pragma unroll
+      for (int cf = 0; cf < 2; ++cf)
+        a[cf] = *reinterpret_cast<const v8bf*>(gT + (16 * cf + r16) * kWgGLD + row * kWgT + col);
 #pragma unroll
       for (int tap = 0; tap < 9; ++tap) {
         const int dy = tap / 3, dx = tap % 3;
-        const v8bf bx =
-            *reinterpret_cast<const v8bf*>(xs + (dx * 32 + 16 * nf + r16) * kWgXLD + (row + dy) * kWgT + col);
-        acc[tap] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bx, acc[tap], 0, 0, 0);
+#pragma unroll
+        for (int nf = 0; nf < 2; ++nf) {
+          const v8bf bx =
+              *reinterpret_cast<const v8bf*>(xs + (dx * 32 + 16 * nf + r16) * kWgXLD + (row + dy) * kWgT + col);
+#pragma unroll
+          for (int cf = 0; cf < 2; ++cf)
+            acc[cf][nf][tap] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[cf], bx, acc[cf][nf][tap], 0, 0, 0);
+        }
       }
-      if (bias) accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, ones, accb, 0, 0, 0);
+      if (bias)
+#pragma unroll
+        for (int cf = 0; cf < 2; ++cf) accb[cf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[cf], ones, accb[cf], 0, 0, 0);
     }
     __syncthreads();
   }
-  // D[4 q + r][r16]: output channel co0 + 16 cf + 4 q + r, input channel ci0 + 16 nf + r16
+  // the four waves' sums, added in wave order through LDS (the staging space:
+  // the last tile's barrier has passed), one fragment pair (cf, nf) at a time;
+  // D[4 q + r][r16]: output channel co0 + 16 cf + 4 q + r, input channel
+  // ci0 + 16 nf + r16
+  float* red = reinterpret_cast<float*>(xs);  // [wave][tap][r][lane]: 4 x 2304 floats
   const int64_t N = 9 * (int64_t)cin;
   float* out = part + (int64_t)blockIdx.x * cout * N;
 #pragma unroll
-  for (int tap = 0; tap < 9; ++tap)
+  for (int pr = 0; pr < 4; ++pr) {
+    const int cf = pr >> 1, nf = pr & 1;
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      out[(int64_t)(co0 + 16 * cf + 4 * q + r) * N + tap * cin + ci0 + 16 * nf + r16] = acc[tap][r];
-  // every column of the ones product holds the sum; column 0 is written
-  if (bias && r16 == 0)
+    for (int tap = 0; tap < 9; ++tap)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) bpart[(int64_t)blockIdx.x * cout + co0 + 16 * cf + 4 * q + r] = accb[r];
+      for (int r = 0; r < 4; ++r) red[((wave * 9 + tap) * 4 + r) * 64 + lane] = acc[cf][nf][tap][r];
+    __syncthreads();
+    for (int e = t; e < 9 * 4 * 64; e += 256) {
+      const float v = ((red[e] + red[2304 + e]) + red[2 * 2304 + e]) + red[3 * 2304 + e];
+      const int tap = e / 256, r = (e / 64) % 4, l = e % 64;
+      out[(int64_t)(co0 + 16 * cf + 4 * (l / 16) + r) * N + tap * cin + ci0 + 16 * nf + l % 16] = v;
+    }
+    __syncthreads();
+  }
+  if (bias) {
+    // every column of the ones product holds the sum; column 0 is used
+#pragma unroll
+    for (int cf = 0; cf < 2; ++cf)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[((wave * 2 + cf) * 4 + r) * 64 + lane] = accb[cf][r];
+    __syncthreads();
+    if (t < 2 * 4 * 4) {
+      const int cf = t / 16, r = (t / 4) % 4, qq = t % 4;
+      const int e = (cf * 4 + r) * 64 + 16 * qq;
+      const float v = ((red[e] + red[512 + e]) + red[2 * 512 + e]) + red[3 * 512 + e];
+      bpart[(int64_t)blockIdx.x * cout + co0 + 16 * cf + 4 * qq + r] = v;
+    }
+  }
 }
 
 bool wgrad3_applies(const View& x, const View& g, int cin, int cout) {
