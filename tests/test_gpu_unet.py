@@ -74,10 +74,18 @@ def test_parameter_count_matches_oracle(cout):
     lib.pat_warmstart_destroy(h)
 
 
-# (4, 32, 1, 128, 128, 3): every level's 3x3 convolutions take the direct
-# convolution kernel (sides multiples of 8 x 16 down to the 16 x 16 bottom)
+# Which kernels the shapes take: (4, 32, 1, 128, 128, 3) the direct 3x3
+# convolution and weight-gradient kernels at every level (sides multiples of
+# 16 down to the 16 x 16 bottom) and the one-channel first layer's kernels;
+# (3, 16, 2, 32, 32, 1) the first layer's kernels with 16 outputs (one wave)
+# and the GEMM elsewhere (16 channels); (3, 64, 2, 32, 32, 3) two 32-channel
+# chunks per tile in the direct kernels, the first layer's with 64 outputs;
+# base 4 and 8 the GEMM for everything.
+SHAPES_DIRECT = [(4, 32, 1, 128, 128, 3), (3, 16, 2, 32, 32, 1), (3, 64, 2, 32, 32, 3)]
+
+
 @pytest.mark.parametrize("shape", [(4, 8, 2, 16, 24, 1), (3, 4, 1, 8, 8, 1), (4, 32, 1, 32, 32, 1),
-                                   (4, 8, 2, 16, 24, 3), (4, 32, 1, 128, 128, 3)])
+                                   (4, 8, 2, 16, 24, 3)] + SHAPES_DIRECT)
 def test_forward_matches_oracle(shape):
     levels, base, B, H, W, cout = shape
     lib, h, n, p, x, t = _setup(levels, base, B, H, W, cout=cout)
@@ -118,8 +126,8 @@ def _check_gradients(lib, h, n, p, x, t, levels, base, B, H, W, cout):
 TOL_GRAD_TENSOR = 5e-2
 
 
-@pytest.mark.parametrize("shape", [(4, 8, 2, 16, 24, 1), (3, 4, 1, 8, 8, 1), (4, 8, 2, 16, 24, 3),
-                                   (4, 32, 1, 128, 128, 3)])
+@pytest.mark.parametrize("shape", [(4, 8, 2, 16, 24, 1), (3, 4, 1, 8, 8, 1), (4, 8, 2, 16, 24, 3)] +
+                         SHAPES_DIRECT)
 def test_gradients_match_oracle(shape):
     levels, base, B, H, W, cout = shape
     lib, h, n, p, x, t = _setup(levels, base, B, H, W, cout=cout)
