@@ -1199,14 +1199,20 @@ void launch_maxpool_back(const View& gout, const uint8_t* idx, const View& gskip
 // pixel). Outputs are channel planes: y[((p / hw) K + k) hw + p % hw].
 __global__ __launch_bounds__(256) void head_kernel(View h, const float* __restrict__ w,
                                                    const float* __restrict__ b, float* __restrict__ y,
-                                                   int64_t P, int K, int64_t hw) {
+                                                   int64_t P, int K, int64_t hw, FastDiv dhw) {
   const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (p >= P) return;
-  const int64_t base = (p / hw) * K * hw + p % hw;
-  const uint16_t* row = h.p + p * h.pitch + h.off;
-  if (h.C % 8 == 0 && h.pitch % 8 == 0 && h.off % 8 == 0 && K <= 4 &&
-      (reinterpret_cast<uintptr_t>(h.p) & 15) == 0) {
-    // the pixel's channels in 16-byte loads; each output adds over c in order
+  if (h.C % 8 == 0 && h.C <= 256 && h.pitch % 8 == 0 && h.off % 8 == 0 && K <= 4 &&
+      (reinterpret_cast<uintptr_t>(h.p) & 15) == 0 && P < (int64_t)UINT32_MAX) {
+    // the bf16-rounded weights in LDS; the pixel's channels in 16-byte loads;
+    // each output adds over c in order
+    __shared__ float wl[4 * 256];
+    for (int e = threadIdx.x; e < K * h.C; e += blockDim.x) wl[e] = bf2f(f2bf(w[e]));
+    __syncthreads();
+    if (p >= P) return;
+    uint32_t img, pix;
+    fast_divmod((uint32_t)p, dhw, img, pix);
+    const int64_t base = (int64_t)img * K * hw + pix;
+    const uint16_t* row = h.p + p * h.pitch + h.off;
     float s[4] = {0.f, 0.f, 0.f, 0.f};
     for (int c0 = 0; c0 < h.C; c0 += 8) {
       const uint4 v = *reinterpret_cast<const uint4*>(row + c0);
@@ -1216,12 +1222,15 @@ __global__ __launch_bounds__(256) void head_kernel(View h, const float* __restri
         const float x = bf2f((uint16_t)(dw[i >> 1] >> (16 * (i & 1))));
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-          if (k < K) s[k] += x * bf2f(f2bf(w[k * h.C + c0 + i]));
+          if (k < K) s[k] += x * wl[k * h.C + c0 + i];
       }
     }
     for (int k = 0; k < K; ++k) y[base + k * hw] = s[k] + b[k];
     return;
   }
+  if (p >= P) return;
+  const int64_t base = (p / hw) * K * hw + p % hw;
+  const uint16_t* row = h.p + p * h.pitch + h.off;
   for (int k = 0; k < K; ++k) {
     float s = 0.f;
     for (int c = 0; c < h.C; ++c) s += bf2f(row[c]) * bf2f(f2bf(w[k * h.C + c]));
@@ -1231,7 +1240,8 @@ __global__ __launch_bounds__(256) void head_kernel(View h, const float* __restri
 
 void launch_head(const View& h, const float* w, const float* b, float* y, int64_t P, int K, int64_t hw,
                  hipStream_t s) {
-  hipLaunchKernelGGL(head_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, h, w, b, y, P, K, hw);
+  hipLaunchKernelGGL(head_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, h, w, b, y, P, K, hw,
+                     make_fastdiv((uint32_t)hw));
   PAT_HIP(hipGetLastError());
 }
 
