@@ -792,10 +792,58 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmDesc d) {
     __syncthreads();
   }
   // epilogue
-  if (d.out_mode == E_SHUF) {
+  if (d.out_mode == E_SHUF && d.out.C % 8 == 0 && d.out.pitch % 8 == 0 && d.out.off % 8 == 0 &&
+      (reinterpret_cast<uintptr_t>(d.out.p16) & 15) == 0) {
     // m: low-res pixel (b, y, x), n = sub * C + c -> output pixel
-    // (2y + sub / 2, 2x + sub % 2), channel c: each row's pixel and each
-    // column's sub-pixel offset split once
+    // (2y + sub / 2, 2x + sub % 2), channel c. The tile leaves through LDS (the
+    // A staging space, free after the last chunk's barrier) in passes of 32
+    // columns: bias and bf16 per element, then 16-byte stores of 8 columns
+    // (8 consecutive channels of one output pixel, C being a multiple of 8)
+    const View& o = d.out;
+    constexpr int SLD = 40;
+    static_assert(SLD <= LD, "a staged pass must fit the A staging space");
+#pragma unroll
+    for (int pass = 0; pass < TN / 32; ++pass) {
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int cl = wn * 16 * FN + j * 16;  // the fragment's first column in the tile
+        if (cl / 32 != pass) continue;
+        const int n = n0 + cl + lane % 16;
+        float bc = 0.f;
+        if (d.bias && n < d.N) {
+          int sub, c;
+          chan_split(n, o.dC, sub, c);
+          bc = d.bias[c];
+        }
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            float v = acc[i][j][r];
+            if (d.bias) v += bc;
+            As[(wm * 16 * FM + i * 16 + 4 * (lane / 16) + r) * SLD + cl % 32 + lane % 16] = f2bf(v);
+          }
+      }
+      __syncthreads();
+      for (int e = t; e < TM * 4; e += 256) {
+        const int row = e / 4, cv = e % 4;
+        const int m = m0 + row, n = n0 + 32 * pass + 8 * cv;
+        if (m < d.M && n < d.N) {
+          int b, y, x, sub, c;
+          pix_split(m, o.dW2, o.dH2, b, y, x);
+          chan_split(n, o.dC, sub, c);
+          const int yy = 2 * y + (sub >> 1), xx = 2 * x + (sub & 1);
+          *reinterpret_cast<uint4*>(o.p16 + ((int64_t)(b * o.H + yy) * o.W + xx) * o.pitch + o.off + c) =
+              *reinterpret_cast<const uint4*>(As + row * SLD + 8 * cv);
+        }
+      }
+      __syncthreads();
+    }
+    return;
+  }
+  if (d.out_mode == E_SHUF) {
+    // the same element by element (channel counts that are not multiples
+    // of 8): each row's pixel and each column's sub-pixel offset split once
     const View& o = d.out;
     int64_t base[FM][4];
 #pragma unroll
