@@ -37,7 +37,11 @@ struct Act {
   DevBuf x0, y, gy, t, idx[5];
   DevBuf a[6], cat[5], s3, p[5], ua[5], ub[5];
   DevBuf g_ub[5], g_ua[5], g_cat[5], g_s3, g_a[6], g_p[5], g_s[5];
-  DevBuf ws, part, loss_part, loss;
+  DevBuf part, loss_part, loss;
+  // per layer: its weight gradient's split partials and bias partials, kept
+  // until the backward pass's one reduction launch (wred)
+  DevBuf lws[kMaxWgReduce], lbp[kMaxWgReduce];
+  WgReduceTable wred{};
 };
 
 }  // namespace nn
@@ -56,7 +60,7 @@ struct pat_unet_s {
 namespace pat {
 namespace nn {
 
-constexpr size_t kWorkspace = 64ull << 20;  // split-K partials (bytes)
+constexpr size_t kWorkspace = 64ull << 20;  // bound on one layer's split-K partials (bytes)
 
 static void build_layers(pat_unet_s* n) {
   int64_t off = 0, woff = 0;
@@ -153,7 +157,6 @@ static void ensure_act(pat_unet_s* n, int B, int H, int W) {
   const int L3 = n->levels - 1;
   a.s3.alloc(h * px(L3) * n->ch(L3));
   a.g_s3.alloc(h * px(L3) * n->ch(L3));
-  a.ws.alloc(kWorkspace);
   // per-block partial sums: bias gradients (256 pixels per block, up to 2 C
   // channels) and the head (256 pixels per block, cout (C0 + 1) sums)
   int64_t part = (px(0) + 255) / 256 * n->cout * (n->ch(0) + 1);
@@ -212,37 +215,49 @@ static int choose_ksplit(int64_t M, int64_t N, int64_t K) {
 }
 
 // weight gradient of a 3x3 convolution: dW[co][tap*Cin+ci] = sum_p g[p][co] X[p+tap][ci]
-// (by pixel tiles where the shapes allow, else the implicit GEMM split over k)
+// (by pixel tiles where the shapes allow, else the implicit GEMM split over k);
+// the partials go to the layer's own buffers and their reduction joins the
+// backward pass's table
 static void conv_wgrad(pat_unet_s* n, const Layer& L, const View& x, const View& g, hipStream_t s) {
-  const int64_t P = (int64_t)n->act.B * x.H * x.W;
+  Act& a = n->act;
+  const int li = (int)(&L - n->layers.data());
+  const int64_t P = (int64_t)a.B * x.H * x.W;
+  const size_t f = sizeof(float);
   int nsplit, bnblk;
   if (wgrad3_applies(x, g, L.cin, L.cout)) {
     // the bias partials come from the same launch, one row per split
-    nsplit = launch_wgrad3(x, g, n->act.B, L.cin, L.cout, ptr<float>(n->act.ws), (int64_t)kWorkspace,
-                           ptr<float>(n->act.part), (int64_t)n->act.part.bytes, s);
+    nsplit = wgrad3_splits(x, a.B, L.cin, L.cout);
+    a.lws[li].ensure(f * nsplit * L.cout * 9 * L.cin);
+    a.lbp[li].ensure(f * nsplit * L.cout);
+    launch_wgrad3(x, g, a.B, L.cin, L.cout, nsplit, ptr<float>(a.lws[li]), ptr<float>(a.lbp[li]), s);
     bnblk = nsplit;
   } else if (wgrad1_applies(x, g, L.cin, L.cout)) {
-    nsplit = launch_wgrad1(x, g, n->act.B, L.cout, ptr<float>(n->act.ws), (int64_t)kWorkspace,
-                           ptr<float>(n->act.part), (int64_t)n->act.part.bytes, s);
+    nsplit = wgrad1_splits(x, a.B);
+    a.lws[li].ensure(f * nsplit * L.cout * 9);
+    a.lbp[li].ensure(f * nsplit * L.cout);
+    launch_wgrad1(x, g, a.B, L.cout, nsplit, ptr<float>(a.lws[li]), ptr<float>(a.lbp[li]), s);
     bnblk = nsplit;
   } else {
-    bnblk = launch_colsum_partials(g, ptr<float>(n->act.part), P, 256, s);
+    bnblk = (int)((P + 255) / 256);
+    a.lbp[li].ensure(f * bnblk * g.C);
+    launch_colsum_partials(g, ptr<float>(a.lbp[li]), P, 256, s);
     GemmDesc d;
     d.M = L.cout;
     d.N = 9 * L.cin;
     d.K = (int)P;
     d.ksplit = choose_ksplit(d.M, d.N, d.K);
+    nsplit = (d.K + d.ksplit - 1) / d.ksplit;
+    a.lws[li].ensure(f * nsplit * d.M * d.N);
     d.a_mode = A_T;
     d.a = g;
     d.b_mode = B_IM2COL;
     d.b = x;
     d.out_mode = E_SPLIT;
-    d.out_f32 = ptr<float>(n->act.ws);
+    d.out_f32 = ptr<float>(a.lws[li]);
     launch_gemm(d, s);
-    nsplit = (d.K + d.ksplit - 1) / d.ksplit;
   }
-  launch_wgrad_reduce(ptr<float>(n->act.ws), nsplit, L.cout, 9 * L.cin, ptr<float>(n->grads) + L.w, 0,
-                      ptr<float>(n->act.part), bnblk, g.C, ptr<float>(n->grads) + L.b, s);
+  wgrad_reduce_add(a.wred, ptr<float>(a.lws[li]), nsplit, L.cout, 9 * L.cin, ptr<float>(n->grads) + L.w, 0,
+                   ptr<float>(a.lbp[li]), bnblk, g.C, ptr<float>(n->grads) + L.b);
 }
 
 // input gradient of a 3x3 convolution (flipped taps), rounded to bf16 and masked
@@ -267,23 +282,29 @@ static void conv_dgrad(pat_unet_s* n, const Layer& L, const View& g, const View&
 // transposed convolution: x is the low-resolution input, g the full-resolution
 // output gradient
 static void convt_wgrad(pat_unet_s* n, const Layer& L, const View& x, const View& g, hipStream_t s) {
+  Act& a = n->act;
+  const int li = (int)(&L - n->layers.data());
+  const size_t f = sizeof(float);
   GemmDesc d;
   d.M = 4 * L.cout;
   d.N = L.cin;
-  d.K = n->act.B * x.H * x.W;
+  d.K = a.B * x.H * x.W;
   d.ksplit = choose_ksplit(d.M, d.N, d.K);
+  const int nsplit = (d.K + d.ksplit - 1) / d.ksplit;
+  a.lws[li].ensure(f * nsplit * d.M * d.N);
   d.a_mode = A_TG22;
   d.a = g;
   d.b_mode = B_T;
   d.b = x;
   d.out_mode = E_SPLIT;
-  d.out_f32 = ptr<float>(n->act.ws);
-  const int bnblk =
-      launch_colsum_partials(g, ptr<float>(n->act.part), (int64_t)n->act.B * g.H * g.W, 256, s);
+  d.out_f32 = ptr<float>(a.lws[li]);
+  const int64_t P = (int64_t)a.B * g.H * g.W;
+  const int bnblk = (int)((P + 255) / 256);
+  a.lbp[li].ensure(f * bnblk * g.C);
+  launch_colsum_partials(g, ptr<float>(a.lbp[li]), P, 256, s);
   launch_gemm(d, s);
-  const int nsplit = (d.K + d.ksplit - 1) / d.ksplit;
-  launch_wgrad_reduce(d.out_f32, nsplit, d.M, d.N, ptr<float>(n->grads) + L.w, L.cout,
-                      ptr<float>(n->act.part), bnblk, g.C, ptr<float>(n->grads) + L.b, s);
+  wgrad_reduce_add(a.wred, d.out_f32, nsplit, d.M, d.N, ptr<float>(n->grads) + L.w, L.cout, ptr<float>(a.lbp[li]),
+                   bnblk, g.C, ptr<float>(n->grads) + L.b);
 }
 
 static void convt_dgrad(pat_unet_s* n, const Layer& L, const View& g, const View& out, const View& mask,
@@ -359,6 +380,7 @@ static void forward(pat_unet_s* n, const float* x, hipStream_t s) {
 static void backward(pat_unet_s* n, hipStream_t s) {
   Act& a = n->act;
   const Views v = views(n);
+  a.wred.count = 0;
   const int64_t P0 = (int64_t)a.B * a.H * a.W;
   auto gview = [&](DevBuf& b, int l, int C, int pitch, int off) {
     return view(ptr<uint16_t>(b), a.H >> l, a.W >> l, C, pitch, off);
@@ -423,6 +445,7 @@ static void backward(pat_unet_s* n, hipStream_t s) {
       g = gp;
     }
   }
+  launch_wgrad_reduce(a.wred, s);
 }
 
 static void init_params(pat_unet_s* n, uint64_t seed, hipStream_t s) {

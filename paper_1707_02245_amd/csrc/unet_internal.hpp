@@ -59,18 +59,36 @@ struct GemmDesc {
 
 void launch_gemm(const GemmDesc& d, hipStream_t s);
 // weight gradient of a 3x3 convolution by pixel tiles (when wgrad3_applies):
-// writes nsplit partials [split][cout][9 cin] to part and the bias column
-// sums' partials [split][cout] to bpart, and returns nsplit
+// writes nsplit (wgrad3_splits) partials [split][cout][9 cin] to part and the
+// bias column sums' partials [split][cout] to bpart
 bool wgrad3_applies(const View& x, const View& g, int cin, int cout);
-int launch_wgrad3(const View& x, const View& g, int B, int cin, int cout, float* part, int64_t part_bytes,
-                  float* bpart, int64_t bpart_bytes, hipStream_t s);
+int wgrad3_splits(const View& x, int B, int cin, int cout);
+void launch_wgrad3(const View& x, const View& g, int B, int cin, int cout, int nsplit, float* part, float* bpart,
+                   hipStream_t s);
 // the same for a one-channel input (partials [split][cout][9] and [split][cout])
 bool wgrad1_applies(const View& x, const View& g, int cin, int cout);
-int launch_wgrad1(const View& x, const View& g, int B, int cout, float* part, int64_t part_bytes, float* bpart,
-                  int64_t bpart_bytes, hipStream_t s);
+int wgrad1_splits(const View& x, int B);
+void launch_wgrad1(const View& x, const View& g, int B, int cout, int nsplit, float* part, float* bpart,
+                   hipStream_t s);
 void set_gemm_tiles(int mode);
-void launch_wgrad_reduce(const float* part, int nsplit, int M, int N, float* out, int permute_cout,
-                         const float* bpart, int bnblk, int bC, float* bout, hipStream_t s);
+// the reductions of a backward pass's weight gradients, gathered and then
+// launched together (each entry: nsplit partials of M x N, the result in out,
+// permuted [sub][ci][co] when permute_cout > 0; bnblk bias partial rows of bC)
+struct WgReduce {
+  const float* part;
+  float* out;
+  const float* bpart;
+  float* bout;
+  int nsplit, M, N, permute_cout, bnblk, bC, lanes, vec, nb_split, first_block;
+};
+constexpr int kMaxWgReduce = 32;
+struct WgReduceTable {
+  WgReduce e[kMaxWgReduce];
+  int count;
+};
+void wgrad_reduce_add(WgReduceTable& tb, const float* part, int nsplit, int M, int N, float* out, int permute_cout,
+                      const float* bpart, int bnblk, int bC, float* bout);
+void launch_wgrad_reduce(const WgReduceTable& tb, hipStream_t s);
 void launch_maxpool(const View& in, const View& out, uint8_t* idx, int B, hipStream_t s);
 void launch_maxpool_back(const View& gout, const uint8_t* idx, const View& gskip, const View& act,
                          const View& gin, int B, hipStream_t s);

@@ -620,20 +620,18 @@ bool wgrad3_applies(const View& x, const View& g, int cin, int cout) {
          x.H > 0 && x.W > 0 && x.H % kWgT == 0 && x.W % kWgT == 0 && vec_ok(x) && vec_ok(g);
 }
 
-int launch_wgrad3(const View& x, const View& g, int B, int cin, int cout, float* part, int64_t part_bytes,
-                  float* bpart, int64_t bpart_bytes, hipStream_t s) {
+int wgrad3_splits(const View& x, int B, int cin, int cout) {
   const int n_tiles = B * (x.H / kWgT) * (x.W / kWgT);
   const int slices = (cout / 32) * (cin / 32);
-  int nsplit = std::max(1, std::min(n_tiles, kWgTargetBlocks / slices));
-  const int64_t per_split = (int64_t)cout * 9 * cin * (int64_t)sizeof(float);
-  nsplit = (int)std::min<int64_t>(nsplit, std::max<int64_t>(1, part_bytes / per_split));
-  nsplit = (int)std::min<int64_t>(nsplit, std::max<int64_t>(1, bpart_bytes / (cout * (int64_t)sizeof(float))));
-  PAT_CHECK_ARG(per_split <= part_bytes && cout * (int64_t)sizeof(float) <= bpart_bytes,
-                "weight gradient partials exceed the workspace");
+  return std::max(1, std::min(n_tiles, kWgTargetBlocks / slices));
+}
+
+void launch_wgrad3(const View& x, const View& g, int B, int cin, int cout, int nsplit, float* part, float* bpart,
+                   hipStream_t s) {
+  const int n_tiles = B * (x.H / kWgT) * (x.W / kWgT);
   hipLaunchKernelGGL(wgrad3_kernel, dim3((unsigned)nsplit, (unsigned)(cout / 32), (unsigned)(cin / 32)),
                      dim3(256), 0, s, x, g, part, bpart, cout, cin, n_tiles);
   PAT_HIP(hipGetLastError());
-  return nsplit;
 }
 
 // The weight and bias gradients of a 3x3 convolution of a one-channel input
@@ -715,18 +713,17 @@ bool wgrad1_applies(const View& x, const View& g, int cin, int cout) {
          g.off % 8 == 0 && (reinterpret_cast<uintptr_t>(g.p) & 15) == 0;
 }
 
-int launch_wgrad1(const View& x, const View& g, int B, int cout, float* part, int64_t part_bytes, float* bpart,
-                  int64_t bpart_bytes, hipStream_t s) {
+int wgrad1_splits(const View& x, int B) {
   const int n_tiles = B * (x.H / kWgT) * (x.W / kWgT);
-  int nsplit = std::max(1, std::min(n_tiles, kWgTargetBlocks));
-  nsplit = (int)std::min<int64_t>(nsplit, std::max<int64_t>(1, part_bytes / (cout * 9 * (int64_t)sizeof(float))));
-  nsplit = (int)std::min<int64_t>(nsplit, std::max<int64_t>(1, bpart_bytes / (cout * (int64_t)sizeof(float))));
-  PAT_CHECK_ARG(cout * 9 * (int64_t)sizeof(float) <= part_bytes && cout * (int64_t)sizeof(float) <= bpart_bytes,
-                "weight gradient partials exceed the workspace");
+  return std::max(1, std::min(n_tiles, kWgTargetBlocks));
+}
+
+void launch_wgrad1(const View& x, const View& g, int B, int cout, int nsplit, float* part, float* bpart,
+                   hipStream_t s) {
+  const int n_tiles = B * (x.H / kWgT) * (x.W / kWgT);
   hipLaunchKernelGGL(wgrad1_kernel, dim3((unsigned)nsplit), dim3(64 * (cout / 16)), 0, s, x, g, part, bpart, cout,
                      n_tiles);
   PAT_HIP(hipGetLastError());
-  return nsplit;
 }
 
 // ------------------------------------------------------------------ the GEMM
@@ -1051,36 +1048,56 @@ __device__ __forceinline__ void part_reduce_block(const float* __restrict__ part
   if (threadIdx.x == 0) out[c] = s;
 }
 
-// A weight gradient's two reductions in one launch: workgroups [0, nb_split)
-// sum its split-K partials, the next bC workgroups the bias column sums'
-// per-workgroup partials (bnblk rows of bC).
-template <int V>
-__global__ __launch_bounds__(256) void wgrad_reduce_kernel(const float* __restrict__ part, int nsplit, int M,
-                                                           int N, float* __restrict__ out, int permute_cout,
-                                                           int lanes, int nb_split,
-                                                           const float* __restrict__ bpart, int bnblk, int bC,
-                                                           float* __restrict__ bout) {
-  __shared__ float lds[256 * V];
-  if ((int)blockIdx.x < nb_split)
-    splitk_reduce_block<V>(part, nsplit, M, N, out, permute_cout, lanes, blockIdx.x, lds);
-  else
-    part_reduce_block(bpart, bnblk, bC, bout, (int)blockIdx.x - nb_split);
+// Every weight gradient's two reductions of a backward pass in one launch:
+// entry k of the table owns workgroups [first_block, next entry's): the first
+// nb_split sum its split-K partials, the next bC the bias column sums'
+// per-workgroup partials (bnblk rows of bC). Each entry's partials have their
+// own buffers, so the reductions wait only for the end of the backward pass.
+__global__ __launch_bounds__(256) void wgrad_reduce_kernel(WgReduceTable tb) {
+  __shared__ float lds[256 * 4];
+  int li = 0;
+  for (int k = 1; k < tb.count; ++k)
+    if ((int)blockIdx.x >= tb.e[k].first_block) li = k;
+  const WgReduce r = tb.e[li];
+  const int blk = (int)blockIdx.x - r.first_block;
+  if (blk < r.nb_split) {
+    if (r.vec)
+      splitk_reduce_block<4>(r.part, r.nsplit, r.M, r.N, r.out, r.permute_cout, r.lanes, blk, lds);
+    else
+      splitk_reduce_block<1>(r.part, r.nsplit, r.M, r.N, r.out, r.permute_cout, r.lanes, blk, lds);
+  } else {
+    part_reduce_block(r.bpart, r.bnblk, r.bC, r.bout, blk - r.nb_split);
+  }
 }
 
-void launch_wgrad_reduce(const float* part, int nsplit, int M, int N, float* out, int permute_cout,
-                         const float* bpart, int bnblk, int bC, float* bout, hipStream_t s) {
+void wgrad_reduce_add(WgReduceTable& tb, const float* part, int nsplit, int M, int N, float* out, int permute_cout,
+                      const float* bpart, int bnblk, int bC, float* bout) {
+  PAT_CHECK_ARG(tb.count < kMaxWgReduce, "too many weight gradients for one reduction launch");
   const int64_t total = (int64_t)M * N;
-  const bool vec = total % 4 == 0 && (reinterpret_cast<uintptr_t>(part) & 15) == 0;
-  const int64_t groups = vec ? total / 4 : total;
-  const int lanes = splitk_lanes(nsplit, groups);
-  const int els = 256 / lanes;
-  const int nb_split = (int)((groups + els - 1) / els);
-  if (vec)
-    hipLaunchKernelGGL(wgrad_reduce_kernel<4>, dim3(nb_split + bC), dim3(256), 0, s, part, nsplit, M, N, out,
-                       permute_cout, lanes, nb_split, bpart, bnblk, bC, bout);
-  else
-    hipLaunchKernelGGL(wgrad_reduce_kernel<1>, dim3(nb_split + bC), dim3(256), 0, s, part, nsplit, M, N, out,
-                       permute_cout, lanes, nb_split, bpart, bnblk, bC, bout);
+  WgReduce& r = tb.e[tb.count];
+  r.part = part;
+  r.out = out;
+  r.bpart = bpart;
+  r.bout = bout;
+  r.nsplit = nsplit;
+  r.M = M;
+  r.N = N;
+  r.permute_cout = permute_cout;
+  r.bnblk = bnblk;
+  r.bC = bC;
+  r.vec = total % 4 == 0 && (reinterpret_cast<uintptr_t>(part) & 15) == 0;
+  const int64_t groups = r.vec ? total / 4 : total;
+  r.lanes = splitk_lanes(nsplit, groups);
+  r.nb_split = (int)((groups + 256 / r.lanes - 1) / (256 / r.lanes));
+  r.first_block = tb.count == 0 ? 0 : tb.e[tb.count - 1].first_block + tb.e[tb.count - 1].nb_split + tb.e[tb.count - 1].bC;
+  ++tb.count;
+}
+
+void launch_wgrad_reduce(const WgReduceTable& tb, hipStream_t s) {
+  if (tb.count == 0) return;
+  const WgReduce& last = tb.e[tb.count - 1];
+  const int blocks = last.first_block + last.nb_split + last.bC;
+  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, tb);
   PAT_HIP(hipGetLastError());
 }
 
