@@ -394,9 +394,11 @@ static void backward(pat_unet_s* n, hipStream_t s) {
   launch_head_back(v.ub[0], ptr<float>(n->params) + n->head_w, ptr<float>(a.gy), g, ptr<float>(a.part), P0,
                    n->cout, (int64_t)a.H * a.W, rows, s);
   // part rows are [cout][C0] weight sums then cout bias sums: the head's
-  // parameter layout, so one reduction fills both
+  // parameter layout, so one column reduction (an entry without split
+  // partials in the backward pass's reduction launch) fills both
   const int hk = n->cout * (C0 + 1);
-  launch_part_reduce(ptr<float>(a.part), nblk, hk, hk, ptr<float>(n->grads) + n->head_w, s);
+  wgrad_reduce_add(a.wred, nullptr, 0, 0, 0, nullptr, 0, ptr<float>(a.part), nblk, hk,
+                   ptr<float>(n->grads) + n->head_w);
   // decoder, level 0 up to levels-2
   for (int l = 0; l < n->levels - 1; ++l) {
     const int C = n->ch(l);

@@ -99,7 +99,6 @@ void launch_mse(const float* y, const float* t, float* gy, double* part, double*
 void launch_head_back(const View& h, const float* w, const float* gy, const View& gh, float* part,
                       int64_t P, int K, int64_t hw, int rows_per_block, hipStream_t s);
 int launch_colsum_partials(const View& g, float* part, int64_t P, int rows_per_block, hipStream_t s);
-void launch_part_reduce(const float* part, int nblk, int C, int ld, float* out, hipStream_t s);
 void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                  float eps, float bc1, float bc2, hipStream_t s);
 // one layer of launch_prep_all: offsets in the FP32 parameters and in the two

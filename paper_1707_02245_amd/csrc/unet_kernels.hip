@@ -1561,14 +1561,6 @@ __global__ __launch_bounds__(256) void colsum_kernel(View g, float* __restrict__
   }
 }
 
-// out[c] = sum over blocks of part[block][c]: one workgroup per column,
-// threads stride the blocks, then a fixed reduction tree (deterministic)
-__global__ __launch_bounds__(256) void part_reduce_kernel(const float* __restrict__ part, int nblk,
-                                                          int C, int ld, float* __restrict__ out) {
-  if ((int)blockIdx.x >= C) return;
-  part_reduce_block(part, nblk, ld, out, blockIdx.x);
-}
-
 // the bias column sums' per-workgroup partials (rows_per_block pixels each);
 // returns the number of partial rows
 int launch_colsum_partials(const View& g, float* part, int64_t P, int rows_per_block, hipStream_t s) {
@@ -1576,11 +1568,6 @@ int launch_colsum_partials(const View& g, float* part, int64_t P, int rows_per_b
   hipLaunchKernelGGL(colsum_kernel, dim3(nblk), dim3(256), 0, s, g, part, P, rows_per_block);
   PAT_HIP(hipGetLastError());
   return nblk;
-}
-
-void launch_part_reduce(const float* part, int nblk, int C, int ld, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(part_reduce_kernel, dim3(C), dim3(256), 0, s, part, nblk, C, ld, out);
-  PAT_HIP(hipGetLastError());
 }
 
 // ------------------------------------------------------------------ parameters
