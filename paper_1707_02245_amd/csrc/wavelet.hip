@@ -243,7 +243,7 @@ struct WavSynArgs {
 // detail bands, 4 lowpass) are turned back into the trees' subbands (the
 // transposed band combination). This kernel serves the levels from 2 on
 // (no shifts: offsets 0 and 1), reading each position's values once per
-// thread; level 1 is wav_synthesis1_kernel below.
+// thread; level 1, and levels of many positions, take the tiled kernel below.
 template <class T, class A>
 __global__ __launch_bounds__(256) void wav_synthesis_kernel(WavSynArgs<T, A> a) {
   const int hx = a.cx >> 1, hy = a.cy >> 1;
@@ -309,27 +309,34 @@ __global__ __launch_bounds__(256) void wav_synthesis_kernel(WavSynArgs<T, A> a) 
   }
 }
 
-// Level 1 by tiles of 16 x 16 positions. The positions a tile's threads
-// reach (the tile and the two position rows and columns before it, periodic)
-// are turned into the trees' subbands once and kept in LDS, band-major, so
-// that every coefficient is read from memory about 1.27 times instead of
-// once per neighbour that uses it (nine times); each thread then sums its
-// 3 x 3 neighbourhood in the same order and with the same values as
-// wav_synthesis_kernel at level 1.
-constexpr int kWsT = 16, kWsH = kWsT + 2, kWsP = kWsH * kWsH;
+// The same by tiles of 16 x 16 positions: the positions a tile's threads
+// reach (the tile and the NA - 1 position rows and columns before it,
+// periodic; NA = 3 at level 1, else 2) are turned into the trees' subbands
+// once and kept in LDS, band-major (conflict-free 8-byte reads), so that every
+// coefficient is read from memory (1 + (NA - 1) / 16)^2 times instead of once
+// per neighbour that uses it (NA^2 times); each thread then sums its
+// neighbourhood in the same order and with the same values as the
+// per-position kernel. Level 1 (FIRST: the tree shifts) writes the image
+// summed over the trees, the other levels each tree's lowpass band. Used at
+// level 1 and wherever a level has many tiles (at 4096^2 the levels 2 and 3
+// went 78 -> 67 and 22 -> 20 us); a level of a few tiles is latency-bound and
+// keeps one thread per position (at 256^2 the tiles' extra barrier and LDS
+// round trip cost 4.9 -> 6.8 us at level 2).
+constexpr int kWsT = 16, kWsTiledMin = 256;
 
-template <class T, class A>
-__global__ __launch_bounds__(256) void wav_synthesis1_kernel(WavSynArgs<T, A> a) {
-  __shared__ A sl[16][kWsP];  // [tree * 4 + band][position in the haloed tile]
+template <class T, class A, bool FIRST>
+__global__ __launch_bounds__(256) void wav_synthesis_tiled_kernel(WavSynArgs<T, A> a) {
+  constexpr int NA = FIRST ? 3 : 2, HALO = NA - 1, TH = kWsT + HALO, TP = TH * TH;
+  __shared__ A sl[16][TP];  // [tree * 4 + band][position in the haloed tile]
   const int hx = a.cx >> 1, hy = a.cy >> 1;
   const int64_t S = (int64_t)hx * hy;
   const int tiles_x = (hx + kWsT - 1) / kWsT;
   const int64_t tile = xcd_block();
   const int X0 = (int)(tile % tiles_x) * kWsT, Y0 = (int)(tile / tiles_x) * kWsT;
   const A kc = (A)a.f.kc;
-  for (int q = threadIdx.x; q < kWsP; q += 256) {
-    const int ly = q / kWsH, lx = q - ly * kWsH;
-    const int iy = ((Y0 - 2 + ly) % hy + hy) % hy, ix = ((X0 - 2 + lx) % hx + hx) % hx;
+  for (int q = threadIdx.x; q < TP; q += 256) {
+    const int ly = q / TH, lx = q - ly * TH;
+    const int iy = ((Y0 - HALO + ly) % hy + hy) % hy, ix = ((X0 - HALO + lx) % hx + hx) % hx;
     const int64_t pos = (int64_t)iy * hx + ix;
 #pragma unroll
     for (int t = 0; t < 4; ++t)
@@ -356,22 +363,23 @@ __global__ __launch_bounds__(256) void wav_synthesis1_kernel(WavSynArgs<T, A> a)
 #pragma unroll
       for (int dx = 0; dx < 2; ++dx) acc[t][dy][dx] = A(0);
 #pragma unroll
-  for (int ay = 0; ay < 3; ++ay) {
+  for (int ay = 0; ay < NA; ++ay) {
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      const int q = (ty + 2 - ay) * kWsH + (tx + 2 - ax);
+    for (int ax = 0; ax < NA; ++ax) {
+      const int q = (ty + HALO - ay) * TH + (tx + HALO - ax);
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int fy = t >> 1, fx = t & 1;
+        const int sy = FIRST ? fy : 0, sx = FIRST ? fx : 0;
         const A s0 = sl[4 * t][q], s1 = sl[4 * t + 1][q], s2 = sl[4 * t + 2][q], s3 = sl[4 * t + 3][q];
 #pragma unroll
         for (int dy = 0; dy < 2; ++dy) {
-          const int ky = 2 * ay + dy - fy;
+          const int ky = 2 * ay + dy - sy;
           if (ky < 0 || ky > 3) continue;
           const A ly = (A)a.f.lo[fy][ky], gy = (A)a.f.hi[fy][ky];
 #pragma unroll
           for (int dx = 0; dx < 2; ++dx) {
-            const int kx = 2 * ax + dx - fx;
+            const int kx = 2 * ax + dx - sx;
             if (kx < 0 || kx > 3) continue;
             const A lx = (A)a.f.lo[fx][kx], gx = (A)a.f.hi[fx][kx];
             acc[t][dy][dx] += ly * (lx * s0 + gx * s1) + gy * (lx * s2 + gx * s3);
@@ -380,12 +388,19 @@ __global__ __launch_bounds__(256) void wav_synthesis1_kernel(WavSynArgs<T, A> a)
       }
     }
   }
+  const int64_t n = (int64_t)a.cx * a.cy;
 #pragma unroll
   for (int dy = 0; dy < 2; ++dy) {
     const int64_t row = (int64_t)(2 * Y + dy) * a.cx + 2 * X;
 #pragma unroll
-    for (int dx = 0; dx < 2; ++dx)
-      a.out[row + dx] = (acc[0][dy][dx] + acc[1][dy][dx]) + (acc[2][dy][dx] + acc[3][dy][dx]);
+    for (int dx = 0; dx < 2; ++dx) {
+      if (FIRST) {
+        a.out[row + dx] = (acc[0][dy][dx] + acc[1][dy][dx]) + (acc[2][dy][dx] + acc[3][dy][dx]);
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) a.ll_out[t * n + row + dx] = acc[t][dy][dx];
+      }
+    }
   }
 }
 
@@ -463,13 +478,14 @@ static void synthesis(int nx, int ny, int J, const T* coef, A* out, A* work, hip
     a.out = j == 1 ? out : nullptr;
     a.f = wav_filters(j);
     const unsigned grid = blocks_for(band_size(nx, ny, j));
-    if (j == 1) {
-      const int hx = a.cx >> 1, hy = a.cy >> 1;
-      const unsigned tiles = (unsigned)(((hx + kWsT - 1) / kWsT) * ((hy + kWsT - 1) / kWsT));
-      hipLaunchKernelGGL((wav_synthesis1_kernel<T, A>), dim3(tiles), dim3(256), 0, s, a);
-    } else {
+    const int hx = a.cx >> 1, hy = a.cy >> 1;
+    const unsigned tiles = (unsigned)(((hx + kWsT - 1) / kWsT) * ((hy + kWsT - 1) / kWsT));
+    if (j == 1)
+      hipLaunchKernelGGL((wav_synthesis_tiled_kernel<T, A, true>), dim3(tiles), dim3(256), 0, s, a);
+    else if (tiles >= (unsigned)kWsTiledMin)
+      hipLaunchKernelGGL((wav_synthesis_tiled_kernel<T, A, false>), dim3(tiles), dim3(256), 0, s, a);
+    else
       hipLaunchKernelGGL((wav_synthesis_kernel<T, A>), dim3(grid), dim3(256), 0, s, a);
-    }
     PAT_HIP(hipGetLastError());
   }
 }

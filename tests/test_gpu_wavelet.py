@@ -81,6 +81,23 @@ def test_full_size_parseval_inverse_and_constant(J, dt):
     assert np.allclose(cc[ll:], 3.0 * 2 ** J / 2, rtol=1e-12 if dt == "f64" else 1e-6)
 
 
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_large_levels_inverse_and_parseval(dt):
+    """1024 x 1024, 3 levels: the synthesis takes its LDS-tiled kernel at
+    levels 1 and 2 (256 tiles of 16 x 16 positions at level 2) and one thread
+    per position at level 3. W^T W u = u and ||W u|| = ||u|| hold at any size,
+    with W pinned to the oracle's matrix on the small shapes above."""
+    n, J = 1024, 3
+    rng = np.random.default_rng(7)
+    u = rng.uniform(-1, 1, (n, n))
+    print(f"wavelet {n}x{n} J={J} {dt}", flush=True)
+    c = pat.wavelet_forward(to_dev(u, DT[dt]), J)
+    back = pat.wavelet_adjoint(c, n, n, J)
+    tol = 1e-12 if dt == "f64" else 2e-6
+    assert abs(np.linalg.norm(host(c)) / np.linalg.norm(u) - 1.0) <= tol
+    assert rel(host(back), u) <= tol * 10
+
+
 def test_transform_rejects_bad_shapes():
     u = torch.zeros((12, 8), dtype=torch.float64, device="cuda")
     with pytest.raises(Exception):
